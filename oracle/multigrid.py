@@ -1,0 +1,309 @@
+"""Geometric multigrid for the DEC 0-form Laplacian -- plain FP64 reference.
+
+TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  Follows Sec. 2.2.1 (interpolation
+by M(f)^T, restriction), Sec. 3.1 (rediscretised Laplacian per level, V-cycles, relative
+residual ||L u - b|| / ||b||, GMG as a CG preconditioner).  The smoother, cycle shape and
+coarse solve are the ones of the workloads: V(nu1, nu2) weighted Jacobi and an exact dense
+solve on the coarsest level.  Readings of the paper that are not spelled out there:
+
+* Q1 sign: L = d0^T star1 d0 is positive semi-definite; -lap u = f becomes L u = star0 f.
+* Q2 star1 = |dual edge| / |primal edge| (cotangent weights).
+* Q4 restriction paired with the stiffness form L is R = M_c P^T (no row normalisation);
+  ``pairing="paper"`` runs the row-normalised restriction of Def. 6 with star0^{-1} L.
+* Q6 zero Dirichlet: identity rows/columns at boundary vertices, restricted residual zeroed
+  at coarse boundary vertices.
+* Q9 singular (closed surface, natural boundary): the plain vertex mean is removed from b,
+  from every preconditioner output and from the final solution.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+from . import dec
+
+
+class Level:
+    """One mesh of the hierarchy with its rediscretised operators (Sec. 3.1: every DEC
+    primitive is rebuilt on every level)."""
+
+    def __init__(self, xyz, tri):
+        self.xyz = xyz
+        self.tri = tri
+        self.nv = len(xyz)
+        self.edges, self.tri_edges, self.tri_sign = dec.edges_of(tri, self.nv)
+        self.ne = len(self.edges)
+        self.nt = len(tri)
+        self.d0 = dec.d0_matrix(self.edges, self.nv)
+        self.star0, self.star1 = dec.hodge_stars(xyz, tri, self.tri_edges, self.ne)
+        self.bnd = dec.boundary_vertices(self.tri_edges, self.edges, self.nv)
+        self.Mt = None          # interpolation from the next coarser level (V x V_coarse)
+        self.w = self.star1.copy()
+        self.L = None
+        self.A = None
+
+    @property
+    def d1(self):
+        return dec.d1_matrix(self.tri_edges, self.tri_sign, self.ne)
+
+
+class Hierarchy:
+    """Meshes X_0 (coarsest) .. X_l (finest) related by binary subdivision maps (Fig. 3),
+    with L on each level and the transfer operators between neighbours."""
+
+    def __init__(self, xyz, tri, nsub: int, project: bool = False, bc: str = "dirichlet"):
+        assert bc in ("dirichlet", "natural")
+        self.bc = bc
+        self.levels = [Level(xyz, tri)]
+        for _ in range(nsub):
+            c = self.levels[-1]
+            fxyz, ftri, Mt = dec.subdivide(c.xyz, c.tri, c.edges, c.tri_edges, project)
+            f = Level(fxyz, ftri)
+            f.Mt = Mt
+            self.levels.append(f)
+        self._assemble()
+
+    # -- operators
+    def _assemble(self):
+        for lv in self.levels:
+            lv.L = dec.laplacian(lv.d0, lv.w)
+            lv.A = dec.dirichlet(lv.L, lv.bnd) if self.bc == "dirichlet" else lv.L
+
+    def set_vertex_coeff(self, kv_fine: np.ndarray):
+        """Edge coefficient for the Darcy operator: each level takes the vertex field at its
+        own vertices (coarse vertex ids are kept by subdivision, so this is injection), sets
+        k_e = (k_lo + k_hi) / 2 and w = star1 * k_e (reading Q13)."""
+        for lv in self.levels:
+            kv = kv_fine[:lv.nv]
+            ke = 0.5 * (kv[lv.edges[:, 0]] + kv[lv.edges[:, 1]])
+            lv.w = lv.star1 * ke
+        self._assemble()
+
+    @property
+    def fine(self) -> Level:
+        return self.levels[-1]
+
+    @property
+    def top(self) -> int:
+        return len(self.levels) - 1
+
+    def restrict(self, l: int, r: np.ndarray) -> np.ndarray:
+        """R = M_c P^T from level l to l-1, zeroed at coarse Dirichlet vertices."""
+        rc = self.levels[l].Mt.T @ r
+        if self.bc == "dirichlet":
+            rc[self.levels[l - 1].bnd] = 0.0
+        return rc
+
+    def prolong(self, l: int, ec: np.ndarray) -> np.ndarray:
+        """Interpolation of Def. 5: values on level l-1 -> level l by M(f)^T."""
+        return self.levels[l].Mt @ ec
+
+    def rhs(self, f: np.ndarray) -> np.ndarray:
+        """b = star0 f on the finest level (Dirichlet: zero on the boundary)."""
+        b = self.fine.star0 * f
+        if self.bc == "dirichlet":
+            b[self.fine.bnd] = 0.0
+        return b
+
+    def unknowns(self) -> int:
+        lv = self.fine
+        return int(np.count_nonzero(~lv.bnd)) if self.bc == "dirichlet" else lv.nv
+
+
+# ------------------------------------------------------------------ smoother and cycle
+def jacobi(A, b, x, omega: float, nsweeps: int):
+    """Weighted Jacobi: x <- x + omega D^{-1} (b - A x), D = diag(A)."""
+    dinv = 1.0 / A.diagonal()
+    for _ in range(nsweeps):
+        x = x + omega * dinv * (b - A @ x)
+    return x
+
+
+def coarse_solve(h: Hierarchy, b: np.ndarray) -> np.ndarray:
+    """Exact solve on the coarsest level: dense LU, or the minimum-norm least-squares
+    solution (L^+ b) when L is singular."""
+    A = h.levels[0].A.toarray()
+    if h.bc == "dirichlet":
+        return np.linalg.solve(A, b)
+    return np.linalg.lstsq(A, b, rcond=None)[0]
+
+
+def vcycle(h: Hierarchy, b, x=None, l=None, nu1=2, nu2=2, omega=0.8):
+    """One V(nu1, nu2) cycle for A_l x = b: pre-smooth, restrict the residual, recurse with a
+    zero initial guess, interpolate and correct, post-smooth (Sec. 2, Sec. 3.1)."""
+    if l is None:
+        l = h.top
+    if l == 0:
+        return coarse_solve(h, b)
+    A = h.levels[l].A
+    x = np.zeros_like(b) if x is None else x.copy()
+    x = jacobi(A, b, x, omega, nu1)
+    r = b - A @ x
+    ec = vcycle(h, h.restrict(l, r), None, l - 1, nu1, nu2, omega)
+    x = x + h.prolong(l, ec)
+    x = jacobi(A, b, x, omega, nu2)
+    return x
+
+
+def vcycle_paper(h: Hierarchy, f, x=None, l=None, nu1=2, nu2=2, omega=0.8):
+    """The same cycle for the paper's scaling, star0^{-1} L x = f, with the row-normalised
+    restriction of Def. 6 (Dirichlet identity rows kept unscaled)."""
+    if l is None:
+        l = h.top
+    lv = h.levels[l]
+    s0 = lv.star0.copy()
+    if h.bc == "dirichlet":
+        s0[lv.bnd] = 1.0
+    A = sp.diags(1.0 / s0) @ lv.A
+    if l == 0:
+        A0 = A.toarray()
+        if h.bc == "dirichlet":
+            return np.linalg.solve(A0, f)
+        return np.linalg.lstsq(A0, f, rcond=None)[0]
+    x = np.zeros_like(f) if x is None else x.copy()
+    x = jacobi(A, f, x, omega, nu1)
+    r = f - A @ x
+    rc = dec.paper_restriction(lv.Mt) @ r
+    if h.bc == "dirichlet":
+        rc[h.levels[l - 1].bnd] = 0.0
+    ec = vcycle_paper(h, rc, None, l - 1, nu1, nu2, omega)
+    x = x + h.prolong(l, ec)
+    x = jacobi(A, f, x, omega, nu2)
+    return x
+
+
+# ------------------------------------------------------------------ solvers
+def _project(h: Hierarchy, v):
+    return v - v.mean() if h.bc == "natural" else v
+
+
+def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.8):
+    """Stand-alone multigrid: repeat V-cycles from x = 0 until ||b - A x|| <= rtol ||b||.
+    Returns (x, cycles, history of relative residuals)."""
+    A = h.fine.A
+    b = _project(h, b)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    hist = [1.0]
+    k = 0
+    while hist[-1] > rtol and k < max_cycles and nb > 0:
+        x = vcycle(h, b, x, None, nu1, nu2, omega)
+        k += 1
+        hist.append(np.linalg.norm(b - A @ x) / nb)
+    return _project(h, x), k, hist
+
+
+def _precond(h, r, nu1, nu2, omega):
+    return _project(h, vcycle(h, r, None, None, nu1, nu2, omega))
+
+
+def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8):
+    """Conjugate gradients preconditioned by one V-cycle (Sec. 3.1, CG-GMG), x0 = 0, stopped
+    on the recursively updated residual.  Returns (x, iterations, history)."""
+    A = h.fine.A
+    b = _project(h, b)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    hist = [1.0 if nb > 0 else 0.0]
+    if nb == 0:
+        return x, 0, hist
+    z = _precond(h, r, nu1, nu2, omega)
+    p = z.copy()
+    rho = r @ z
+    k = 0
+    while k < max_iter:
+        q = A @ p
+        alpha = rho / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        k += 1
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= rtol:
+            break
+        z = _precond(h, r, nu1, nu2, omega)
+        rho_new = r @ z
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+    return _project(h, x), k, hist
+
+
+def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None):
+    """Flexible CG with one-vector truncation (FCG(1)): alpha = p^T r / p^T q,
+    beta = -z^T q_prev / p_prev^T q_prev.  ``precond`` defaults to one V-cycle; passing
+    another callable lets a test emulate a perturbed (e.g. lower precision) cycle."""
+    A = h.fine.A
+    b = _project(h, b)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    r = b.copy()
+    hist = [1.0 if nb > 0 else 0.0]
+    if nb == 0:
+        return x, 0, hist
+    M = precond or (lambda v: vcycle(h, v, None, None, nu1, nu2, omega))
+    p_prev = q_prev = None
+    k = 0
+    while k < max_iter:
+        z = _project(h, M(r))
+        if p_prev is None:
+            p = z
+        else:
+            p = z - ((z @ q_prev) / (p_prev @ q_prev)) * p_prev
+        q = A @ p
+        alpha = (p @ r) / (p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        k += 1
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= rtol:
+            break
+        p_prev, q_prev = p, q
+    return _project(h, x), k, hist
+
+
+def mg_ir(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None):
+    """Iterative refinement: x <- x + M(b - A x) with the true residual recomputed each
+    step."""
+    A = h.fine.A
+    b = _project(h, b)
+    nb = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    M = precond or (lambda v: vcycle(h, v, None, None, nu1, nu2, omega))
+    r = b.copy()
+    hist = [1.0 if nb > 0 else 0.0]
+    k = 0
+    while nb > 0 and hist[-1] > rtol and k < max_iter:
+        x = x + _project(h, M(r))
+        r = b - A @ x
+        k += 1
+        hist.append(np.linalg.norm(r) / nb)
+    return _project(h, x), k, hist
+
+
+def rel_residual(h: Hierarchy, b, x) -> float:
+    """||A x - b||_2 / ||b||_2 on the finest mesh (Sec. 3.1)."""
+    b = _project(h, b)
+    return float(np.linalg.norm(h.fine.A @ x - b) / np.linalg.norm(b))
+
+
+def direct_solve(h: Hierarchy, b):
+    """The plain definition u* = A^{-1} b (A^+ b, zero mean, when singular): sparse LU."""
+    import scipy.sparse.linalg as spla
+    b = _project(h, b)
+    A = h.fine.A
+    if h.bc == "dirichlet":
+        return spla.spsolve(sp.csc_matrix(A), b)
+    n = A.shape[0]
+    one = np.ones((n, 1))
+    K = sp.bmat([[A, sp.csr_matrix(one)], [sp.csr_matrix(one.T), None]], format="csc")
+    sol = spla.spsolve(K, np.concatenate([b, [0.0]]))
+    return sol[:n]
+
+
+def contraction_factor(hist, tail: int = 5) -> float:
+    """Asymptotic residual reduction per cycle: geometric mean over the last ``tail``
+    cycles of a residual history."""
+    h = np.asarray(hist)
+    h = h[h > 0]
+    k = min(tail, len(h) - 1)
+    return float((h[-1] / h[-1 - k]) ** (1.0 / k))

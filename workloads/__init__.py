@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs for the DEC multigrid workloads.
+
+This module is shared by the FP64 reference (``oracle/``) and by the HIP path.  It holds
+random draws and closed-form test functions evaluated at given coordinates, and nothing of
+the method itself: no mesh construction, no DEC operator, no smoothing, no solve.  Vertex
+coordinates are always passed in by the caller, each side passing its own.
+
+Workloads (unit square meshes are 2-D right-triangle grids, spheres are icospheres):
+
+* ``c1``: 4x4 cells, 4 subdivisions, f = 2 pi^2 sin(pi x) sin(pi y) (the Poisson check of
+  Sec. 3.1 with a manufactured solution).
+* ``c2``: icosahedron, 7 projected subdivisions, f = sum of real spherical harmonics of
+  degree 1..8 with N(0,1) coefficients (seed 2).
+* ``c3``: 8x8 cells, 8 subdivisions (2049 x 2049 vertices), f ~ N(0,1) per vertex (seed 3).
+* ``c4``: 256 instances, a seeded mix of icosphere levels 4..7 and square grids 33^2..513^2.
+* ``c5``: porous convection on 4x4 cells, 6 subdivisions (257 x 257): white noise for the
+  log-permeability (seed 5), temperature noise (seed 6), loss weights (seed 7).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+SEED_C2 = 2
+SEED_C3 = 3
+SEED_C4 = 4
+SEED_C5_G = 5
+SEED_C5_T = 6
+SEED_C5_W = 7
+
+# (base cells per side, subdivisions) for each square workload; spheres give the level.
+C1 = dict(base_cells=4, nsub=4)
+C2 = dict(sphere_level=7)
+C3 = dict(base_cells=8, nsub=8)
+C5 = dict(base_cells=4, nsub=6, Ra=1000.0, phi=0.1, steps=200, ckpt=20, noise=1e-2,
+          g_smooth_sweeps=20, g_smooth_omega=0.8)
+
+# The C4 menu: ("sphere", level) or ("square", vertices-per-side).  Squares use a 4x4-cell
+# base; vertices-per-side 33..513 are 3..7 subdivisions of it.
+C4_MENU = [("sphere", 4), ("sphere", 5), ("sphere", 6), ("sphere", 7),
+           ("square", 33), ("square", 65), ("square", 129), ("square", 257), ("square", 513)]
+
+
+def normal(n: int, seed: int) -> np.ndarray:
+    """i.i.d. N(0,1) draws, float64, from numpy's PCG64 ``default_rng(seed)``."""
+    return np.random.default_rng(seed).standard_normal(int(n))
+
+
+def uniform01(n: int, seed: int) -> np.ndarray:
+    """i.i.d. U[0,1) draws, float64 (the consistent-RHS trick b = L r of Sec. 3.1)."""
+    return np.random.default_rng(seed).random(int(n))
+
+
+def manufactured_c1(xyz: np.ndarray) -> np.ndarray:
+    """f = 2 pi^2 sin(pi x) sin(pi y); u = sin(pi x) sin(pi y) solves -lap u = f, u = 0 on the
+    boundary of the unit square."""
+    x, y = xyz[:, 0], xyz[:, 1]
+    return 2.0 * math.pi ** 2 * np.sin(math.pi * x) * np.sin(math.pi * y)
+
+
+def manufactured_c1_solution(xyz: np.ndarray) -> np.ndarray:
+    x, y = xyz[:, 0], xyz[:, 1]
+    return np.sin(math.pi * x) * np.sin(math.pi * y)
+
+
+# ---------------------------------------------------------------- spherical harmonics
+def _assoc_legendre(lmax: int, x: np.ndarray) -> dict:
+    """P_l^m(x) for 0 <= m <= l <= lmax without the Condon-Shortley phase, by the standard
+    three-term recurrences (m-diagonal, then upward in l)."""
+    P = {}
+    s = np.sqrt(np.maximum(0.0, 1.0 - x * x))
+    pmm = np.ones_like(x)
+    for m in range(lmax + 1):
+        if m > 0:
+            pmm = pmm * (2 * m - 1) * s
+        P[(m, m)] = pmm
+        if m + 1 <= lmax:
+            P[(m + 1, m)] = x * (2 * m + 1) * pmm
+        for l in range(m + 2, lmax + 1):
+            P[(l, m)] = ((2 * l - 1) * x * P[(l - 1, m)] - (l + m - 1) * P[(l - 2, m)]) / (l - m)
+    return P
+
+
+def real_sph_harm(lmax: int, xyz: np.ndarray) -> dict:
+    """Orthonormal real spherical harmonics Y_lm on the unit sphere, 0 <= l <= lmax,
+    -l <= m <= l: sqrt(2) N P_l^|m| cos(m phi) for m > 0, N P_l^0 for m = 0 and
+    sqrt(2) N P_l^|m| sin(|m| phi) for m < 0, N = sqrt((2l+1)/(4 pi) (l-|m|)!/(l+|m|)!).
+    Points are projected to the unit sphere first."""
+    r = np.sqrt(xyz[:, 0] ** 2 + xyz[:, 1] ** 2 + xyz[:, 2] ** 2)
+    ct = xyz[:, 2] / r
+    ph = np.arctan2(xyz[:, 1], xyz[:, 0])
+    P = _assoc_legendre(lmax, ct)
+    Y = {}
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            am = abs(m)
+            N = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
+            if m == 0:
+                Y[(l, m)] = N * P[(l, 0)]
+            elif m > 0:
+                Y[(l, m)] = math.sqrt(2.0) * N * P[(l, am)] * np.cos(am * ph)
+            else:
+                Y[(l, m)] = math.sqrt(2.0) * N * P[(l, am)] * np.sin(am * ph)
+    return Y
+
+
+def sh_coefficients(seed: int = SEED_C2, lmax: int = 8) -> list:
+    """[(l, m, c_lm)] with c_lm ~ N(0,1) drawn in the order l = 1..lmax, m = -l..l."""
+    c = normal((lmax + 1) ** 2 - 1, seed)
+    out, k = [], 0
+    for l in range(1, lmax + 1):
+        for m in range(-l, l + 1):
+            out.append((l, m, float(c[k])))
+            k += 1
+    return out
+
+
+def sphere_rhs(xyz: np.ndarray, coeffs: list) -> np.ndarray:
+    """f = sum c_lm Y_lm evaluated at the vertices (zero mean over the continuous sphere)."""
+    lmax = max(l for l, _, _ in coeffs)
+    Y = real_sph_harm(lmax, xyz)
+    f = np.zeros(len(xyz))
+    for l, m, c in coeffs:
+        f += c * Y[(l, m)]
+    return f
+
+
+def sphere_exact(xyz: np.ndarray, coeffs: list) -> np.ndarray:
+    """Continuous zero-mean solution of -lap_S u = f: u = sum c_lm Y_lm / (l (l+1))."""
+    lmax = max(l for l, _, _ in coeffs)
+    Y = real_sph_harm(lmax, xyz)
+    u = np.zeros(len(xyz))
+    for l, m, c in coeffs:
+        u += c / (l * (l + 1)) * Y[(l, m)]
+    return u
+
+
+# ---------------------------------------------------------------- batched mix
+def c4_instances(seed: int = SEED_C4, n: int = 256) -> list:
+    """The seeded C4 mix: a list of dicts {kind, level|side, nsub, rhs_seed}."""
+    types = np.random.default_rng(seed).integers(0, len(C4_MENU), n)
+    out = []
+    for i, t in enumerate(types):
+        kind, v = C4_MENU[int(t)]
+        if kind == "sphere":
+            out.append(dict(kind="sphere", nsub=v, rhs_seed=4000 + i))
+        else:
+            nsub = int(round(math.log2((v - 1) / 4)))
+            out.append(dict(kind="square", base_cells=4, nsub=nsub, rhs_seed=4000 + i))
+    return out
+
+
+# ---------------------------------------------------------------- porous convection
+def c5_logk_noise(nv: int) -> np.ndarray:
+    """White noise for the log-permeability field g before smoothing (seed 5)."""
+    return normal(nv, SEED_C5_G)
+
+
+def c5_initial_temperature(xyz: np.ndarray) -> np.ndarray:
+    """T0 = 1 - y + noise * N(0,1) (seed 6).  Noise is drawn for every vertex; the walls
+    y = 0 and y = 1 are reset to 1 and 0 exactly, so they hold their conductive values."""
+    y = xyz[:, 1]
+    T = 1.0 - y + C5["noise"] * normal(len(xyz), SEED_C5_T)
+    T[y == 0.0] = 1.0
+    T[y == 1.0] = 0.0
+    return T
+
+
+def c5_loss_weights(nv: int) -> np.ndarray:
+    """Loss J = sum_i w_i T_i(final) with w ~ N(0,1) (seed 7)."""
+    return normal(nv, SEED_C5_W)

@@ -1,0 +1,193 @@
+/*
+ * decmg -- geometric multigrid for the discrete-exterior-calculus 0-form Laplacian on
+ * MI355X (gfx950).  C ABI of libdecmg.so.
+ *
+ * The method (arXiv 2508.12501):
+ *   - meshes are 2-D embedded simplicial complexes (Def. 1); a hierarchy is built by binary
+ *     1-to-4 subdivision, whose geometric map has the matrix M(f) of Def. 4;
+ *   - on every level the operator is rediscretised (Sec. 3.1): L = d0^T star1 d0, with star1
+ *     the circumcentric |dual edge|/|primal edge| ratio and star0 the dual-cell area
+ *     (Eq. hodge0-laplacian; the paper's Delta_0 equals -star0^{-1} L);
+ *   - interpolation is P = M(f)^T (Def. 5); restriction is R = P^T, the stiffness-form
+ *     counterpart of the row-normalised operator of Def. 6;
+ *   - V-cycles with a weighted-Jacobi smoother and an exact coarsest solve are used as a
+ *     solver and as a CG preconditioner (Sec. 3.1); the Darcy pressure step of porous
+ *     convection solves d0^T star1 K d0 p = rhs (Sec. 3.2, Eq. poisson).
+ *
+ * Conventions shared by every entry point:
+ *   - Every call returns an mg_status.  Nothing throws across the ABI.  On failure
+ *     mg_last_error() returns a message (thread-local, valid until the next failing call).
+ *   - Vectors passed to operator and solver calls are DEVICE pointers to contiguous arrays
+ *     of one value per vertex of the named level, in the natural vertex numbering: base mesh
+ *     ids, then after each subdivision coarse ids are kept and the midpoint of coarse edge e
+ *     gets id V_coarse + e.  Edges are numbered by first appearance scanning triangles and
+ *     their sides (v0v1, v1v2, v2v0) and are oriented from the smaller to the larger id.
+ *     The caller owns these buffers; the library never frees or keeps them.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  All device work of a call is
+ *     enqueued on it; calls that return host-side results (solver statistics) synchronise
+ *     it before returning.
+ *   - dtype is MG_F64 (double) or MG_F32 (float) for the calls that take `const void*`.
+ *   - Handles are not thread-safe; distinct handles may be used from distinct threads.
+ *   - Zero-Dirichlet hierarchies iterate on interior vertices only.  Boundary rows are
+ *     identity rows: solvers return x = b there, operator calls return y = x there.
+ */
+#ifndef DECMG_H
+#define DECMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MG_OK = 0,
+  MG_EINVAL = 1,      /* bad argument or malformed mesh */
+  MG_ENOMEM = 2,      /* host or device allocation failed */
+  MG_EDEVICE = 3,     /* a HIP runtime call failed; the HIP error string is in the message */
+  MG_ENOCONV = 4,     /* max_iter reached before rtol; result and x are still filled */
+  MG_EBREAKDOWN = 5,  /* CG breakdown: p^T A p <= 0 or a non-positive preconditioned norm */
+  MG_ENONFINITE = 6,  /* a non-finite value in the input or in a residual norm */
+  MG_EINCOMPAT = 7    /* singular system with a right-hand side far from the range */
+} mg_status;
+
+enum { MG_F64 = 0, MG_F32 = 1 };
+enum { MG_BC_DIRICHLET0 = 0, MG_BC_NATURAL = 1 };
+enum { MG_OUTER_CG = 0, MG_OUTER_FCG = 1, MG_OUTER_IR = 2 };
+
+typedef struct dec_mesh dec_mesh;
+typedef struct mg_hierarchy mg_hierarchy;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* mg_last_error(void);
+/* ABI revision of this header. */
+int32_t mg_abi_version(void);
+
+/* ------------------------------------------------------------------ meshes (host)
+ * Def. 1: a point cloud with triangles given by vertex triples.  Edges and face maps are
+ * derived.  The mesh is copied; the caller keeps ownership of its arrays.  Rejected with
+ * MG_EINVAL: nv < 3, nt < 1, an index out of range, a degenerate or duplicate triangle, an
+ * edge shared by more than two triangles, a vertex in no triangle, a non-finite coordinate.
+ */
+mg_status dec_mesh_from_arrays(int64_t nv, const double* xyz /* nv x 3 */, int64_t nt,
+                               const int32_t* tri /* nt x 3 */, dec_mesh** out);
+/* Unit square, ncells x ncells cells; vertex (i,j) at (i/n, j/n, 0) has id j*(n+1)+i;
+ * cell (i,j) (j outer) gives triangles (a,b,c), (a,c,d) with a=(i,j), b=(i+1,j),
+ * c=(i+1,j+1), d=(i,j+1). */
+mg_status dec_mesh_square_grid(int32_t ncells, dec_mesh** out);
+/* Unit icosahedron: the cyclic permutations of (0, +-1, +-phi) in the order
+ * (-1,phi,0) (1,phi,0) (-1,-phi,0) (1,-phi,0) (0,-1,phi) (0,1,phi) (0,-1,-phi) (0,1,-phi)
+ * (phi,0,-1) (phi,0,1) (-phi,0,-1) (-phi,0,1), normalised; faces are the vertex triples at
+ * mutual distance 2 in lexicographic order, oriented outward. */
+mg_status dec_mesh_icosahedron(dec_mesh** out);
+void dec_mesh_free(dec_mesh* m);
+
+/* ------------------------------------------------------------------ hierarchy
+ * n_subdiv binary subdivisions of the base (Sec. 2.2.1); project_sphere pushes every new
+ * midpoint radially onto the unit sphere.  All DEC operators are rebuilt on every level
+ * (Sec. 3.1).  Device memory is allocated with hipMalloc and owned by the handle. */
+typedef struct {
+  int32_t n_subdiv;
+  int32_t project_sphere;
+  int32_t bc;      /* MG_BC_DIRICHLET0 (boundary vertices fixed at 0) or MG_BC_NATURAL */
+  int32_t reserved;
+} mg_hier_opts;
+
+mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, void* stream,
+                             mg_hierarchy** out);
+void mg_hierarchy_free(mg_hierarchy* h);
+
+typedef struct {
+  int32_t n_levels;      /* levels 0 (base) .. n_levels-1 (finest) */
+  int32_t level;
+  int64_t nv, ne, nt;
+  int64_t n_unknowns;    /* interior vertices (Dirichlet) or all vertices (natural) */
+  int64_t nnz_operator;  /* stored off-diagonal entries of the device operator */
+} mg_level_info;
+mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
+
+/* Host copies of one level, natural numbering.  Any pointer may be NULL to skip it.
+ * Sizes: xyz nv*3, tri nt*3, edges ne*2 (lo,hi), tri_edges nt*3, tri_sign nt*3 (+1 where
+ * the triangle's boundary cycle runs lo->hi), star0 nv, star1 ne, boundary nv (1 = on a
+ * boundary edge), parents nv*2 (level >= 1: coarse vertex ids (a,b) of each fine vertex,
+ * a == b for kept vertices; row j of M(f)^T is 1/2 e_a + 1/2 e_b). */
+mg_status mg_hierarchy_export(const mg_hierarchy* h, int32_t level, double* xyz, int32_t* tri,
+                              int32_t* edges, int32_t* tri_edges, int8_t* tri_sign,
+                              double* star0, double* star1, uint8_t* boundary,
+                              int32_t* parents);
+
+/* Darcy coefficient (Sec. 3.2, Eq. dec_darcy): k_vertex is a device array of nv_finest
+ * positive values.  Every level takes the values at its own vertices (injection) and
+ * uses edge weights star1_e * (k_lo + k_hi)/2.  Passing NULL restores k = 1. */
+mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex, void* stream);
+
+/* ------------------------------------------------------------------ operators (device)
+ * b = star0 f on `level` (Sec. 3.1 right-hand side of L u = star0 f); Dirichlet: b = 0 on
+ * the boundary.  f, b: nv doubles. */
+mg_status dec_star0_apply(mg_hierarchy* h, int32_t level, const double* f, double* b,
+                          void* stream);
+/* y = A x with A = L (natural) or the Dirichlet form M L M + (I - M). */
+mg_status dec_laplacian_apply(mg_hierarchy* h, int32_t level, int32_t dtype, const void* x,
+                              void* y, void* stream);
+/* nsweeps of weighted Jacobi, x <- x + omega D^{-1} (b - A x), in place on x. */
+mg_status mg_smooth(mg_hierarchy* h, int32_t level, int32_t dtype, int32_t nsweeps,
+                    double omega, const void* b, void* x, void* stream);
+/* r_coarse = R r_fine from `level` to level-1, R = M(f) (= P^T), zero at coarse Dirichlet
+ * vertices.  r_fine has nv(level) entries, r_coarse nv(level-1).  Fine boundary entries
+ * of r_fine are ignored on Dirichlet hierarchies. */
+mg_status mg_restrict(mg_hierarchy* h, int32_t level, int32_t dtype, const void* r_fine,
+                      void* r_coarse, void* stream);
+/* x_fine += P e_coarse, P = M(f)^T (Def. 5), from level-1 to `level`.  Dirichlet: coarse
+ * boundary entries of e_coarse are taken as 0 and fine boundary entries of x are kept. */
+mg_status mg_prolong(mg_hierarchy* h, int32_t level, int32_t dtype, const void* e_coarse,
+                     void* x_fine, void* stream);
+
+/* ------------------------------------------------------------------ solvers */
+typedef struct {
+  int32_t nu1, nu2;      /* pre/post Jacobi sweeps (2, 2) */
+  double omega;          /* Jacobi weight (0.8) */
+  int32_t precision;     /* MG_F64 or MG_F32: arithmetic of the V-cycle preconditioner */
+  int32_t outer;         /* MG_OUTER_CG, MG_OUTER_FCG or MG_OUTER_IR (mg_pcg only) */
+  double rtol;           /* stop at ||b - A x||_2 <= rtol ||b||_2 (1e-10) */
+  int32_t max_iter;      /* (200) */
+  int32_t check_every;   /* iterations enqueued between host convergence checks (4) */
+  int32_t use_graph;     /* replay the iteration as a hipGraph (1) */
+  int32_t reserved;
+} mg_opts;
+void mg_opts_default(mg_opts* o);
+
+typedef struct {
+  int32_t iterations;          /* outer iterations (cycles for mg_solve) */
+  int32_t status;              /* the mg_status of the call */
+  double rel_residual;         /* true ||b - A x|| / ||b|| at exit, computed in FP64 */
+  double rel_residual_loop;    /* the recursively updated value the loop stopped on */
+} mg_result;
+
+/* One V(nu1,nu2) cycle on `level` (normally the finest), in place: x <- V(b, x).  dtype
+ * selects FP64 or FP32 arithmetic (b and x of that type); the coarsest solve is FP64. */
+mg_status mg_vcycle(mg_hierarchy* h, const mg_opts* o, int32_t level, int32_t dtype,
+                    const void* b, void* x, void* stream);
+/* Stand-alone multigrid: V-cycles from x = 0 until rtol (FP64). */
+mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
+                   mg_result* res, void* stream);
+/* Krylov solve with one V-cycle as preconditioner, from x = 0: CG (symmetric FP64 cycle),
+ * flexible CG FCG(1) (beta = -z^T q_prev / p_prev^T q_prev) or iterative refinement.  With
+ * precision MG_F32 the cycle runs in FP32 on a scaled FP32 copy of the FP64 residual; the
+ * residual, the solution update and the coarsest solve stay FP64.  Natural-BC hierarchies
+ * remove the vertex mean of b, of every preconditioned vector and of x. */
+mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
+                 mg_result* res, void* stream);
+
+/* ------------------------------------------------------------------ measurement
+ * Times `reps` back-to-back launches of one kernel of the path on `level` with hipEvents
+ * recorded on `stream`, and returns the mean duration per launch in milliseconds.
+ * kernel: 0 = Jacobi sweep, 1 = operator apply, 2 = residual, 3 = restriction,
+ * 4 = interpolation.  Uses the hierarchy's own work vectors. */
+mg_status mg_time_kernel(mg_hierarchy* h, int32_t kernel, int32_t level, int32_t dtype,
+                         int32_t reps, void* stream, double* ms_per_launch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DECMG_H */

@@ -1,0 +1,363 @@
+"""decmg: geometric multigrid for the DEC 0-form Laplacian on MI355X (gfx950).
+
+A thin ctypes binding of ``libdecmg.so`` (declared in ``include/decmg.h``).  Functions carry
+the C names and only marshal arguments: every step of the path runs in the library's HIP
+kernels.  Vectors are contiguous torch tensors on the GPU (float64, or float32 where the C
+call takes a dtype), one entry per vertex of the named level in the natural numbering.  Work
+is enqueued on torch's current stream.
+
+If the library has not been built, importing works but the first call raises
+``LibraryMissing``; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdecmg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "decmg.h")
+
+MG_OK, MG_EINVAL, MG_ENOMEM, MG_EDEVICE, MG_ENOCONV, MG_EBREAKDOWN, MG_ENONFINITE, MG_EINCOMPAT = range(8)
+STATUS_NAMES = ["MG_OK", "MG_EINVAL", "MG_ENOMEM", "MG_EDEVICE", "MG_ENOCONV", "MG_EBREAKDOWN",
+                "MG_ENONFINITE", "MG_EINCOMPAT"]
+MG_F64, MG_F32 = 0, 1
+MG_BC_DIRICHLET0, MG_BC_NATURAL = 0, 1
+MG_OUTER_CG, MG_OUTER_FCG, MG_OUTER_IR = 0, 1, 2
+KERNEL_JACOBI, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
+
+
+class LibraryMissing(ImportError):
+    pass
+
+
+class MGError(RuntimeError):
+    def __init__(self, status: int, message: str, result=None):
+        self.status = status
+        self.result = result
+        name = STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else str(status)
+        super().__init__(f"{name}: {message}")
+
+
+class mg_hier_opts(ctypes.Structure):
+    _fields_ = [("n_subdiv", ctypes.c_int32), ("project_sphere", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class mg_level_info(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nt", ctypes.c_int64),
+                ("n_unknowns", ctypes.c_int64), ("nnz_operator", ctypes.c_int64)]
+
+
+class mg_opts(ctypes.Structure):
+    _fields_ = [("nu1", ctypes.c_int32), ("nu2", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class mg_result(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("rel_residual_loop", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_d = ctypes.c_double
+_PROTOS = {
+    "mg_last_error": (ctypes.c_char_p, []),
+    "mg_abi_version": (_i32, []),
+    "dec_mesh_from_arrays": (_i32, [_i64, _vp, _i64, _vp, ctypes.POINTER(_vp)]),
+    "dec_mesh_square_grid": (_i32, [_i32, ctypes.POINTER(_vp)]),
+    "dec_mesh_icosahedron": (_i32, [ctypes.POINTER(_vp)]),
+    "dec_mesh_free": (None, [_vp]),
+    "mg_hierarchy_build": (_i32, [_vp, ctypes.POINTER(mg_hier_opts), _vp, ctypes.POINTER(_vp)]),
+    "mg_hierarchy_free": (None, [_vp]),
+    "mg_hierarchy_info": (_i32, [_vp, _i32, ctypes.POINTER(mg_level_info)]),
+    "mg_hierarchy_export": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mg_hierarchy_set_vertex_coeff": (_i32, [_vp, _vp, _vp]),
+    "dec_star0_apply": (_i32, [_vp, _i32, _vp, _vp, _vp]),
+    "dec_laplacian_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "mg_smooth": (_i32, [_vp, _i32, _i32, _i32, _d, _vp, _vp, _vp]),
+    "mg_restrict": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "mg_prolong": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
+    "mg_opts_default": (None, [ctypes.POINTER(mg_opts)]),
+    "mg_vcycle": (_i32, [_vp, ctypes.POINTER(mg_opts), _i32, _i32, _vp, _vp, _vp]),
+    "mg_solve": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
+    "mg_pcg": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
+    "mg_time_kernel": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_d)]),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load libdecmg.so (once).  Raises LibraryMissing if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is missing: run `python -m paper_2508_12501_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def header_functions() -> list:
+    """Names of the functions declared in include/decmg.h."""
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?[\w]+\*?\s+\**(\w+)\s*\(", src, flags=re.M)
+
+
+def _check(st: int, result=None):
+    if st != MG_OK:
+        raise MGError(st, lib().mg_last_error().decode(), result)
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype=None, numel=None, name="tensor"):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} entries, got {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return MG_F64
+    if t.dtype == torch.float32:
+        return MG_F32
+    raise ValueError("vectors must be float64 or float32")
+
+
+# ----------------------------------------------------------------- meshes
+def dec_mesh_square_grid(ncells: int):
+    out = _vp()
+    _check(lib().dec_mesh_square_grid(int(ncells), ctypes.byref(out)))
+    return out
+
+
+def dec_mesh_icosahedron():
+    out = _vp()
+    _check(lib().dec_mesh_icosahedron(ctypes.byref(out)))
+    return out
+
+
+def dec_mesh_from_arrays(xyz, tri):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+    tri = np.ascontiguousarray(tri, dtype=np.int32)
+    if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
+        raise ValueError("xyz must be (nv, 3) and tri (nt, 3)")
+    out = _vp()
+    _check(lib().dec_mesh_from_arrays(xyz.shape[0], xyz.ctypes.data, tri.shape[0],
+                                      tri.ctypes.data, ctypes.byref(out)))
+    return out
+
+
+def dec_mesh_free(m):
+    lib().dec_mesh_free(m)
+
+
+# ----------------------------------------------------------------- hierarchy
+def mg_hierarchy_build(mesh, n_subdiv: int, project_sphere: bool = False,
+                       bc: int = MG_BC_DIRICHLET0, stream=None):
+    o = mg_hier_opts(int(n_subdiv), int(bool(project_sphere)), int(bc), 0)
+    out = _vp()
+    _check(lib().mg_hierarchy_build(mesh, ctypes.byref(o), _stream(stream), ctypes.byref(out)))
+    return out
+
+
+def mg_hierarchy_free(h):
+    lib().mg_hierarchy_free(h)
+
+
+def mg_hierarchy_info(h, level: int) -> dict:
+    info = mg_level_info()
+    _check(lib().mg_hierarchy_info(h, int(level), ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def mg_hierarchy_export(h, level: int) -> dict:
+    i = mg_hierarchy_info(h, level)
+    nv, ne, nt = i["nv"], i["ne"], i["nt"]
+    out = dict(xyz=np.empty((nv, 3)), tri=np.empty((nt, 3), np.int32),
+               edges=np.empty((ne, 2), np.int32), tri_edges=np.empty((nt, 3), np.int32),
+               tri_sign=np.empty((nt, 3), np.int8), star0=np.empty(nv), star1=np.empty(ne),
+               boundary=np.empty(nv, np.uint8))
+    parents = np.empty((nv, 2), np.int32) if level > 0 else None
+    _check(lib().mg_hierarchy_export(
+        h, int(level), *(out[k].ctypes.data for k in
+                         ("xyz", "tri", "edges", "tri_edges", "tri_sign", "star0", "star1", "boundary")),
+        parents.ctypes.data if parents is not None else None))
+    out["parents"] = parents
+    return out
+
+
+def mg_hierarchy_set_vertex_coeff(h, k_vertex, stream=None):
+    import torch
+    ptr = None if k_vertex is None else _ptr(k_vertex, torch.float64, _nv(h, _top(h)), "k_vertex")
+    _check(lib().mg_hierarchy_set_vertex_coeff(h, ptr, _stream(stream)))
+
+
+# ----------------------------------------------------------------- operators
+def _nv(h, level):
+    return mg_hierarchy_info(h, level)["nv"]
+
+
+def _top(h):
+    return mg_hierarchy_info(h, 0)["n_levels"] - 1
+
+
+def dec_star0_apply(h, level: int, f, b, stream=None):
+    import torch
+    n = _nv(h, level)
+    _check(lib().dec_star0_apply(h, int(level), _ptr(f, torch.float64, n, "f"),
+                                 _ptr(b, torch.float64, n, "b"), _stream(stream)))
+
+
+def dec_laplacian_apply(h, level: int, x, y, stream=None):
+    n = _nv(h, level)
+    _check(lib().dec_laplacian_apply(h, int(level), _dtype_code(x), _ptr(x, y.dtype, n, "x"),
+                                     _ptr(y, x.dtype, n, "y"), _stream(stream)))
+
+
+def mg_smooth(h, level: int, nsweeps: int, omega: float, b, x, stream=None):
+    n = _nv(h, level)
+    _check(lib().mg_smooth(h, int(level), _dtype_code(x), int(nsweeps), float(omega),
+                           _ptr(b, x.dtype, n, "b"), _ptr(x, None, n, "x"), _stream(stream)))
+
+
+def mg_restrict(h, level: int, r_fine, r_coarse, stream=None):
+    nf, nc = _nv(h, level), _nv(h, max(level - 1, 0))
+    _check(lib().mg_restrict(h, int(level), _dtype_code(r_fine), _ptr(r_fine, None, nf, "r_fine"),
+                             _ptr(r_coarse, r_fine.dtype, nc, "r_coarse"), _stream(stream)))
+
+
+def mg_prolong(h, level: int, e_coarse, x_fine, stream=None):
+    nf, nc = _nv(h, level), _nv(h, max(level - 1, 0))
+    _check(lib().mg_prolong(h, int(level), _dtype_code(x_fine),
+                            _ptr(e_coarse, x_fine.dtype, nc, "e_coarse"),
+                            _ptr(x_fine, None, nf, "x_fine"), _stream(stream)))
+
+
+# ----------------------------------------------------------------- solvers
+def mg_opts_default(**kw) -> mg_opts:
+    o = mg_opts()
+    lib().mg_opts_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(k)
+        setattr(o, k, v)
+    return o
+
+
+def mg_vcycle(h, opts: mg_opts, level: int, b, x, stream=None):
+    n = _nv(h, level)
+    _check(lib().mg_vcycle(h, ctypes.byref(opts), int(level), _dtype_code(x),
+                           _ptr(b, x.dtype, n, "b"), _ptr(x, None, n, "x"), _stream(stream)))
+
+
+def mg_solve(h, opts: mg_opts, b, x, stream=None, raise_on_error=True) -> mg_result:
+    import torch
+    res = mg_result()
+    n = _nv(h, _top(h))
+    st = lib().mg_solve(h, ctypes.byref(opts), _ptr(b, torch.float64, n, "b"),
+                        _ptr(x, torch.float64, n, "x"), ctypes.byref(res), _stream(stream))
+    if raise_on_error:
+        _check(st, res)
+    return res
+
+
+def mg_pcg(h, opts: mg_opts, b, x, stream=None, raise_on_error=True) -> mg_result:
+    import torch
+    res = mg_result()
+    n = _nv(h, _top(h))
+    st = lib().mg_pcg(h, ctypes.byref(opts), _ptr(b, torch.float64, n, "b"),
+                      _ptr(x, torch.float64, n, "x"), ctypes.byref(res), _stream(stream))
+    if raise_on_error:
+        _check(st, res)
+    return res
+
+
+def mg_time_kernel(h, kernel: int, level: int, dtype: int, reps: int, stream=None) -> float:
+    ms = ctypes.c_double()
+    _check(lib().mg_time_kernel(h, int(kernel), int(level), int(dtype), int(reps), _stream(stream),
+                                ctypes.byref(ms)))
+    return ms.value
+
+
+# ----------------------------------------------------------------- convenience
+class Hierarchy:
+    """Owns a mesh and a hierarchy handle; frees both when closed or collected."""
+
+    def __init__(self, kind: str, n_subdiv: int, base_cells: int = 4, bc=None, xyz=None, tri=None):
+        if kind == "square":
+            self.mesh = dec_mesh_square_grid(base_cells)
+            bc = MG_BC_DIRICHLET0 if bc is None else bc
+            project = False
+        elif kind == "sphere":
+            self.mesh = dec_mesh_icosahedron()
+            bc = MG_BC_NATURAL if bc is None else bc
+            project = True
+        elif kind == "arrays":
+            self.mesh = dec_mesh_from_arrays(xyz, tri)
+            bc = MG_BC_DIRICHLET0 if bc is None else bc
+            project = False
+        else:
+            raise ValueError(kind)
+        self.bc = bc
+        self.h = mg_hierarchy_build(self.mesh, n_subdiv, project, bc)
+        self.n_levels = mg_hierarchy_info(self.h, 0)["n_levels"]
+        self.top = self.n_levels - 1
+        self.info = [mg_hierarchy_info(self.h, l) for l in range(self.n_levels)]
+
+    def nv(self, level=None):
+        return self.info[self.top if level is None else level]["nv"]
+
+    def close(self):
+        if getattr(self, "h", None):
+            mg_hierarchy_free(self.h)
+            self.h = None
+        if getattr(self, "mesh", None):
+            dec_mesh_free(self.mesh)
+            self.mesh = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

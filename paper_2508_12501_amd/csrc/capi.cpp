@@ -1,0 +1,466 @@
+// extern "C" entry points of libdecmg.so (declared in include/decmg.h).  Validation happens
+// here, before any launch; exceptions from the host code become status codes.
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+
+#include "decmg.h"
+#include "hier.hpp"
+#include "solver.hpp"
+#include "util.hpp"
+
+struct dec_mesh {
+  decmg::Mesh m;
+};
+struct mg_hierarchy {
+  std::unique_ptr<decmg::Hierarchy> h;
+};
+
+namespace {
+thread_local std::string g_err;
+
+mg_status fail(mg_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define API_BEGIN try {
+#define API_END                                                              \
+  }                                                                          \
+  catch (const decmg::DeviceError& e) {                                      \
+    const std::string w = e.what();                                          \
+    return fail(w.find("out of memory") != std::string::npos ? MG_ENOMEM     \
+                                                             : MG_EDEVICE,   \
+                w);                                                          \
+  }                                                                          \
+  catch (const std::bad_alloc&) {                                            \
+    return fail(MG_ENOMEM, "out of host memory");                            \
+  }                                                                          \
+  catch (const std::exception& e) {                                          \
+    return fail(MG_EINVAL, e.what());                                        \
+  }
+
+hipStream_t S(void* p) { return reinterpret_cast<hipStream_t>(p); }
+
+mg_status check_level(const mg_hierarchy* h, int32_t level, bool need_coarser = false) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  const int nl = int(h->h->lv.size());
+  if (level < 0 || level >= nl) return fail(MG_EINVAL, "level out of range");
+  if (need_coarser && level < 1) return fail(MG_EINVAL, "level 0 has no coarser level");
+  return MG_OK;
+}
+
+mg_status check_dtype(int32_t dtype) {
+  if (dtype != MG_F64 && dtype != MG_F32) return fail(MG_EINVAL, "dtype must be MG_F64 or MG_F32");
+  return MG_OK;
+}
+
+mg_status check_opts(const mg_opts* o) {
+  if (!o) return fail(MG_EINVAL, "null options");
+  if (o->nu1 < 0 || o->nu2 < 0 || o->nu1 > 64 || o->nu2 > 64)
+    return fail(MG_EINVAL, "nu1/nu2 must be in 0..64");
+  if (!(o->omega > 0.0 && o->omega < 2.0)) return fail(MG_EINVAL, "omega must be in (0, 2)");
+  if (o->precision != MG_F64 && o->precision != MG_F32)
+    return fail(MG_EINVAL, "precision must be MG_F64 or MG_F32");
+  if (o->outer != MG_OUTER_CG && o->outer != MG_OUTER_FCG && o->outer != MG_OUTER_IR)
+    return fail(MG_EINVAL, "unknown outer method");
+  if (!(o->rtol > 0.0) || !std::isfinite(o->rtol)) return fail(MG_EINVAL, "rtol must be > 0");
+  if (o->max_iter < 1) return fail(MG_EINVAL, "max_iter must be >= 1");
+  return MG_OK;
+}
+
+template <typename T>
+void op_vcycle(decmg::Hierarchy& H, const mg_opts& o, int level, const void* b, void* x,
+               hipStream_t s) {
+  using namespace decmg;
+  Level& L = *H.lv[level];
+  LevelVecs<T>& V = vecs<T>(L);
+  const T* bn = static_cast<const T*>(b);
+  T* xn = static_cast<T*>(x);
+  const int32_t nb = int32_t(L.bnd_h.size());
+  k::gather<T>(L.perm, L.n, bn, V.b, s);
+  if (level == 0) {
+    k::coarse<T>(H, V.b, V.x, nullptr, s);
+    k::scatter<T>(L.perm, L.n, V.x, xn, s);
+    k::bnd_copy<T>(L.bnd_ids, nb, bn, xn, s);
+    return;
+  }
+  k::gather<T>(L.perm, L.n, xn, V.x, s);
+  T* cur = vcycle<T>(H, level, V.b, V.x, o, nullptr, s);
+  k::scatter<T>(L.perm, L.n, cur, xn, s);
+  for (int i = 0; i < o.nu1 + o.nu2; ++i) k::bnd_jacobi<T>(L.bnd_ids, nb, bn, xn, o.omega, s);
+}
+
+template <typename T>
+void op_smooth(decmg::Hierarchy& H, int level, int nsweeps, double omega, const void* b, void* x,
+               hipStream_t s) {
+  using namespace decmg;
+  Level& L = *H.lv[level];
+  LevelVecs<T>& V = vecs<T>(L);
+  const T* bn = static_cast<const T*>(b);
+  T* xn = static_cast<T*>(x);
+  k::gather<T>(L.perm, L.n, bn, V.b, s);
+  k::gather<T>(L.perm, L.n, xn, V.x, s);
+  T *cur = V.x, *oth = V.t;
+  for (int i = 0; i < nsweeps; ++i) {
+    k::jacobi<T>(L, cur, V.b, oth, omega, nullptr, s);
+    std::swap(cur, oth);
+  }
+  k::scatter<T>(L.perm, L.n, cur, xn, s);
+  for (int i = 0; i < nsweeps; ++i)
+    k::bnd_jacobi<T>(L.bnd_ids, int32_t(L.bnd_h.size()), bn, xn, omega, s);
+}
+
+template <typename T>
+void op_apply(decmg::Hierarchy& H, int level, const void* x, void* y, hipStream_t s) {
+  using namespace decmg;
+  Level& L = *H.lv[level];
+  LevelVecs<T>& V = vecs<T>(L);
+  k::gather<T>(L.perm, L.n, static_cast<const T*>(x), V.x, s);
+  k::spmv<T>(L, V.x, V.r, nullptr, s);
+  k::scatter<T>(L.perm, L.n, V.r, static_cast<T*>(y), s);
+  k::bnd_copy<T>(L.bnd_ids, int32_t(L.bnd_h.size()), static_cast<const T*>(x), static_cast<T*>(y), s);
+}
+
+template <typename T>
+void op_restrict(decmg::Hierarchy& H, int level, const void* rf, void* rc, hipStream_t s) {
+  using namespace decmg;
+  Level& F = *H.lv[level];
+  Level& C = *H.lv[level - 1];
+  k::gather<T>(F.perm, F.n, static_cast<const T*>(rf), vecs<T>(F).r, s);
+  k::restrict_<T>(F, C, vecs<T>(F).r, vecs<T>(C).b, nullptr, s);
+  k::scatter<T>(C.perm, C.n, vecs<T>(C).b, static_cast<T*>(rc), s);
+  k::bnd_zero<T>(C.bnd_ids, int32_t(C.bnd_h.size()), static_cast<T*>(rc), s);
+}
+
+template <typename T>
+void op_prolong(decmg::Hierarchy& H, int level, const void* ec, void* xf, hipStream_t s) {
+  using namespace decmg;
+  Level& F = *H.lv[level];
+  Level& C = *H.lv[level - 1];
+  k::gather<T>(C.perm, C.n, static_cast<const T*>(ec), vecs<T>(C).x, s);
+  k::gather<T>(F.perm, F.n, static_cast<const T*>(xf), vecs<T>(F).x, s);
+  k::prolong<T>(F, C, vecs<T>(C).x, vecs<T>(F).x, nullptr, s);
+  k::scatter<T>(F.perm, F.n, vecs<T>(F).x, static_cast<T*>(xf), s);
+}
+
+void sync_check(hipStream_t s) {
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  decmg::check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mg_last_error(void) { return g_err.c_str(); }
+int32_t mg_abi_version(void) { return 1; }
+
+mg_status dec_mesh_from_arrays(int64_t nv, const double* xyz, int64_t nt, const int32_t* tri,
+                               dec_mesh** out) {
+  API_BEGIN
+  if (!out || !xyz || !tri) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  if (nv < 3 || nt < 1) return fail(MG_EINVAL, "mesh needs nv >= 3 and nt >= 1");
+  if (nv > (int64_t(1) << 30) || nt > (int64_t(1) << 30)) return fail(MG_EINVAL, "mesh too large");
+  auto m = std::make_unique<dec_mesh>();
+  m->m.nv = nv;
+  m->m.nt = nt;
+  m->m.xyz.assign(xyz, xyz + 3 * nv);
+  m->m.tri.assign(tri, tri + 3 * nt);
+  for (int64_t i = 0; i < 3 * nt; ++i)
+    if (tri[i] < 0 || tri[i] >= nv) return fail(MG_EINVAL, "triangle index out of range");
+  std::string err = m->m.validate_vertices();
+  if (err.empty()) err = m->m.build_topology();
+  if (!err.empty()) return fail(MG_EINVAL, err);
+  *out = m.release();
+  API_END
+  return MG_OK;
+}
+
+mg_status dec_mesh_square_grid(int32_t ncells, dec_mesh** out) {
+  API_BEGIN
+  if (!out) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  if (ncells < 1 || ncells > 32768) return fail(MG_EINVAL, "ncells must be in 1..32768");
+  auto m = std::make_unique<dec_mesh>();
+  m->m = decmg::square_grid(ncells);
+  std::string err = m->m.build_topology();
+  if (!err.empty()) return fail(MG_EINVAL, err);
+  *out = m.release();
+  API_END
+  return MG_OK;
+}
+
+mg_status dec_mesh_icosahedron(dec_mesh** out) {
+  API_BEGIN
+  if (!out) return fail(MG_EINVAL, "null argument");
+  auto m = std::make_unique<dec_mesh>();
+  m->m = decmg::icosahedron();
+  std::string err = m->m.build_topology();
+  if (!err.empty()) return fail(MG_EINVAL, err);
+  *out = m.release();
+  API_END
+  return MG_OK;
+}
+
+void dec_mesh_free(dec_mesh* m) { delete m; }
+
+mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, void* stream,
+                             mg_hierarchy** out) {
+  API_BEGIN
+  (void)stream;
+  if (!base || !opts || !out) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  if (opts->n_subdiv < 0 || opts->n_subdiv > 12) return fail(MG_EINVAL, "n_subdiv must be in 0..12");
+  if (opts->bc != MG_BC_DIRICHLET0 && opts->bc != MG_BC_NATURAL)
+    return fail(MG_EINVAL, "bc must be MG_BC_DIRICHLET0 or MG_BC_NATURAL");
+  const double growth = std::pow(4.0, opts->n_subdiv);
+  if (double(base->m.nt) * growth > double(int64_t(1) << 30))
+    return fail(MG_EINVAL, "finest level would exceed 2^30 triangles");
+  auto h = std::make_unique<mg_hierarchy>();
+  h->h.reset(decmg::build_hierarchy(base->m, *opts));
+  *out = h.release();
+  API_END
+  return MG_OK;
+}
+
+void mg_hierarchy_free(mg_hierarchy* h) { delete h; }
+
+mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (!out) return fail(MG_EINVAL, "null argument");
+  const decmg::Level& L = *h->h->lv[level];
+  out->n_levels = int32_t(h->h->lv.size());
+  out->level = level;
+  out->nv = L.mesh.nv;
+  out->ne = L.mesh.ne;
+  out->nt = L.mesh.nt;
+  out->n_unknowns = L.n;
+  int64_t nnz = 0;
+  for (int32_t e : L.entry_edge) nnz += (e >= 0);
+  out->nnz_operator = nnz;
+  return MG_OK;
+}
+
+mg_status mg_hierarchy_export(const mg_hierarchy* h, int32_t level, double* xyz, int32_t* tri,
+                              int32_t* edges, int32_t* tri_edges, int8_t* tri_sign,
+                              double* star0, double* star1, uint8_t* boundary,
+                              int32_t* parents) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  const decmg::Mesh& m = h->h->lv[level]->mesh;
+  auto cp = [](auto* dst, const auto& v) {
+    if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+  };
+  cp(xyz, m.xyz);
+  cp(tri, m.tri);
+  cp(edges, m.edge);
+  cp(tri_edges, m.tri_edge);
+  cp(tri_sign, m.tri_sign);
+  cp(star0, m.star0);
+  cp(star1, m.star1);
+  cp(boundary, m.bnd);
+  if (parents) {
+    if (level == 0) return fail(MG_EINVAL, "level 0 has no parents");
+    cp(parents, m.parent);
+  }
+  return MG_OK;
+}
+
+mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex, void* stream) {
+  API_BEGIN
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  decmg::Hierarchy& H = *h->h;
+  if (!k_vertex) {
+    H.kvert_h.clear();
+  } else {
+    const int32_t nv = H.lv.back()->nv;
+    std::vector<double> kv(nv);
+    decmg::check_hip(hipStreamSynchronize(S(stream)), "hipStreamSynchronize");
+    decmg::check_hip(hipMemcpy(kv.data(), k_vertex, nv * sizeof(double), hipMemcpyDeviceToHost),
+                     "hipMemcpy");
+    for (double v : kv)
+      if (!(v > 0.0) || !std::isfinite(v))
+        return fail(MG_EINVAL, "vertex coefficients must be finite and positive");
+    H.kvert_h = std::move(kv);
+  }
+  decmg::upload_weights(H);
+  API_END
+  return MG_OK;
+}
+
+mg_status dec_star0_apply(mg_hierarchy* h, int32_t level, const double* f, double* b, void* stream) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (!f || !b) return fail(MG_EINVAL, "null vector");
+  API_BEGIN
+  decmg::k::star0_apply(*h->h->lv[level], h->h->bc, f, b, S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+mg_status dec_laplacian_apply(mg_hierarchy* h, int32_t level, int32_t dtype, const void* x, void* y,
+                              void* stream) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  if (!x || !y) return fail(MG_EINVAL, "null vector");
+  if (x == y) return fail(MG_EINVAL, "x and y must not alias");
+  API_BEGIN
+  if (dtype == MG_F64)
+    op_apply<double>(*h->h, level, x, y, S(stream));
+  else
+    op_apply<float>(*h->h, level, x, y, S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_smooth(mg_hierarchy* h, int32_t level, int32_t dtype, int32_t nsweeps, double omega,
+                    const void* b, void* x, void* stream) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  if (!b || !x) return fail(MG_EINVAL, "null vector");
+  if (nsweeps < 0) return fail(MG_EINVAL, "nsweeps must be >= 0");
+  if (!(omega > 0.0 && omega < 2.0)) return fail(MG_EINVAL, "omega must be in (0, 2)");
+  API_BEGIN
+  if (dtype == MG_F64)
+    op_smooth<double>(*h->h, level, nsweeps, omega, b, x, S(stream));
+  else
+    op_smooth<float>(*h->h, level, nsweeps, omega, b, x, S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_restrict(mg_hierarchy* h, int32_t level, int32_t dtype, const void* r_fine,
+                      void* r_coarse, void* stream) {
+  if (mg_status st = check_level(h, level, true); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  if (!r_fine || !r_coarse) return fail(MG_EINVAL, "null vector");
+  API_BEGIN
+  if (dtype == MG_F64)
+    op_restrict<double>(*h->h, level, r_fine, r_coarse, S(stream));
+  else
+    op_restrict<float>(*h->h, level, r_fine, r_coarse, S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_prolong(mg_hierarchy* h, int32_t level, int32_t dtype, const void* e_coarse,
+                     void* x_fine, void* stream) {
+  if (mg_status st = check_level(h, level, true); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  if (!e_coarse || !x_fine) return fail(MG_EINVAL, "null vector");
+  API_BEGIN
+  if (dtype == MG_F64)
+    op_prolong<double>(*h->h, level, e_coarse, x_fine, S(stream));
+  else
+    op_prolong<float>(*h->h, level, e_coarse, x_fine, S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+void mg_opts_default(mg_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->omega = 0.8;
+  o->precision = MG_F64;
+  o->outer = MG_OUTER_CG;
+  o->rtol = 1e-10;
+  o->max_iter = 200;
+  o->check_every = 4;
+  o->use_graph = 1;
+}
+
+mg_status mg_vcycle(mg_hierarchy* h, const mg_opts* o, int32_t level, int32_t dtype, const void* b,
+                    void* x, void* stream) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (!b || !x) return fail(MG_EINVAL, "null vector");
+  API_BEGIN
+  if (dtype == MG_F64)
+    op_vcycle<double>(*h->h, *o, level, b, x, S(stream));
+  else
+    op_vcycle<float>(*h->h, *o, level, b, x, S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x, mg_result* res,
+                   void* stream) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (!b || !x) return fail(MG_EINVAL, "null vector");
+  API_BEGIN
+  const int st = decmg::run_mg(*h->h, *o, b, x, res, S(stream));
+  if (st != MG_OK) return fail(mg_status(st), "mg_solve stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x, mg_result* res,
+                 void* stream) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (!b || !x) return fail(MG_EINVAL, "null vector");
+  API_BEGIN
+  const int st = decmg::run_pcg(*h->h, *o, b, x, res, S(stream));
+  if (st != MG_OK) return fail(mg_status(st), "mg_pcg stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_time_kernel(mg_hierarchy* h, int32_t kernel, int32_t level, int32_t dtype, int32_t reps,
+                         void* stream, double* ms_per_launch) {
+  if (mg_status st = check_level(h, level, kernel >= 3); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  if (kernel < 0 || kernel > 4) return fail(MG_EINVAL, "kernel must be 0..4");
+  if (reps < 1 || !ms_per_launch) return fail(MG_EINVAL, "reps >= 1 and a result pointer needed");
+  API_BEGIN
+  using namespace decmg;
+  Hierarchy& H = *h->h;
+  Level& L = *H.lv[level];
+  hipStream_t s = S(stream);
+  hipEvent_t e0, e1;
+  check_hip(hipEventCreate(&e0), "hipEventCreate");
+  check_hip(hipEventCreate(&e1), "hipEventCreate");
+  auto launch = [&](auto tag) {
+    using T = decltype(tag);
+    LevelVecs<T>& V = vecs<T>(L);
+    switch (kernel) {
+      case 0: k::jacobi<T>(L, V.x, V.b, V.t, 0.8, nullptr, s); break;
+      case 1: k::spmv<T>(L, V.x, V.r, nullptr, s); break;
+      case 2: k::residual<T>(L, V.x, V.b, V.r, nullptr, s); break;
+      case 3: k::restrict_<T>(L, *H.lv[level - 1], V.r, vecs<T>(*H.lv[level - 1]).b, nullptr, s); break;
+      case 4: k::prolong<T>(L, *H.lv[level - 1], vecs<T>(*H.lv[level - 1]).x, V.t, nullptr, s); break;
+    }
+  };
+  auto run = [&]() {
+    for (int i = 0; i < reps; ++i) {
+      if (dtype == MG_F64) launch(double(0)); else launch(float(0));
+    }
+  };
+  run();  // warm-up pass
+  check_hip(hipEventRecord(e0, s), "hipEventRecord");
+  run();
+  check_hip(hipEventRecord(e1, s), "hipEventRecord");
+  check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+  float ms = 0.f;
+  check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  check_hip(hipGetLastError(), "kernel launch");
+  *ms_per_launch = double(ms) / reps;
+  API_END
+  return MG_OK;
+}
+
+}  // extern "C"

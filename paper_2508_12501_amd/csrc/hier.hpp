@@ -1,0 +1,153 @@
+// Device-side hierarchy of the DEC multigrid library and the kernel launchers.
+//
+// Every level keeps its unknowns (interior vertices for zero Dirichlet, all vertices for
+// natural boundaries) in an internal order chosen for locality: a Morton (Z-order) sort of
+// the vertex coordinates.  Coordinates nest across levels, so parents and children of a
+// vertex sit at nearby internal positions on neighbouring levels.  Internal vectors have
+// n + 1 entries; entry n is a zero slot that gathers for absent neighbours point at.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "decmg.h"
+#include "mesh.hpp"
+
+namespace decmg {
+
+constexpr int kSlice = 64;    // SELL slice height: one wavefront, one row per lane
+constexpr int kBlock = 256;   // threads per row-parallel workgroup (4 wavefronts)
+constexpr int kMaxCoarse = 2048;  // largest coarsest level solved densely
+
+// Operator in sliced ELLPACK (SELL-64): slice s covers internal rows 64s..64s+63 and owns
+// columns sptr[s]..sptr[s+1]-1; entry k of lane l sits at [k*64 + l].  The same column
+// array serves the FP64 and FP32 weights.  Exact zero couplings (star1 = 0, the diagonals
+// of right-triangle grids) are dropped; they contribute nothing to L x.
+struct DevOperator {
+  int32_t nslices = 0, ncols = 0;
+  int32_t* sptr = nullptr;
+  int32_t* col = nullptr;
+  double* w64 = nullptr;
+  float* w32 = nullptr;
+  double* diag64 = nullptr;   // sum of the row's weights, in SELL order
+  float* diag32 = nullptr;
+};
+
+struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
+  int32_t* pa = nullptr;      // n_f: internal coarse ids (or n_c) of the two parents
+  int32_t* pb = nullptr;
+  int32_t* r_self = nullptr;  // n_c: fine internal id of the kept vertex
+  int32_t nslices = 0, ncols = 0;
+  int32_t* r_sptr = nullptr;  // SELL over coarse rows of the fine midpoints (weight 1/2)
+  int32_t* r_col = nullptr;
+};
+
+template <typename T>
+struct LevelVecs {
+  T* x = nullptr;
+  T* b = nullptr;
+  T* r = nullptr;
+  T* t = nullptr;
+};
+
+struct Level {
+  Mesh mesh;                       // natural numbering (host)
+  int32_t nv = 0, n = 0;
+  std::vector<int32_t> perm_h;     // internal -> natural
+  std::vector<int32_t> inv_h;      // natural -> internal or -1
+  std::vector<int32_t> bnd_h;      // natural ids that are not unknowns
+  std::vector<int32_t> entry_edge; // per SELL entry: edge id or -1 (padding)
+  std::vector<int32_t> sptr_h;
+  int32_t* perm = nullptr;         // device copies
+  int32_t* bnd_ids = nullptr;
+  double* star0 = nullptr;         // nv, natural numbering
+  DevOperator op;
+  DevTransfer tr;                  // valid for l >= 1
+  LevelVecs<double> v64;
+  LevelVecs<float> v32;
+};
+
+struct DevScalars {
+  double alpha, beta, rho, pq, rnorm, bnorm, rtol, scale, inv_scale, mean;
+  double n_unknowns;
+  int32_t done, iters, status, max_iter;
+};
+
+struct Hierarchy {
+  int32_t bc = MG_BC_DIRICHLET0;
+  bool project = false;
+  std::vector<std::unique_ptr<Level>> lv;
+  double* coarse_inv = nullptr;    // n0 x n0 FP64 inverse of the coarsest operator
+  int32_t n0 = 0;
+  std::vector<double> kvert_h;     // vertex coefficient (finest), empty = 1
+  // solver workspace (finest level, internal numbering, n+1 entries)
+  double *sx = nullptr, *sr = nullptr, *sp = nullptr, *sq = nullptr, *sz = nullptr,
+         *sb = nullptr;
+  double* part = nullptr;          // reduction partials, 3 x max blocks
+  int32_t part_cap = 0;
+  DevScalars* scal = nullptr;
+  DevScalars* scal_host = nullptr; // pinned
+  hipStream_t capture_stream = nullptr;
+  std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
+  ~Hierarchy();
+};
+
+// ----------------------------------------------------------------- kernel launchers
+// All take internal-order vectors; `done` (nullable) makes a launch a no-op once a solver
+// has converged, so speculative iterations cost one flag read.
+namespace k {
+template <typename T> void spmv(const Level& L, const T* x, T* y, const int* done, hipStream_t s);
+template <typename T> void residual(const Level& L, const T* x, const T* b, T* r, const int* done, hipStream_t s);
+template <typename T> void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
+template <typename T> void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s);
+template <typename T> void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done, hipStream_t s);
+template <typename T> void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done, hipStream_t s);
+template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);
+template <typename T> void fill(T* p, int64_t n, T v, hipStream_t s);
+template <typename T> void gather(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);
+template <typename T> void scatter(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);
+template <typename T> void bnd_copy(const int32_t* ids, int32_t nb, const T* src, T* dst, hipStream_t s);
+template <typename T> void bnd_jacobi(const int32_t* ids, int32_t nb, const T* b, T* x, double omega, hipStream_t s);
+template <typename T> void bnd_zero(const int32_t* ids, int32_t nb, T* x, hipStream_t s);
+void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t s);
+
+// Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
+int blocks_for(int32_t n);
+void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
+               double* part1, const int* done, hipStream_t s);
+void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
+               double* r, float* r32, double* part0, const int* done, hipStream_t s);
+void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
+                   const DevScalars* sc, double* part0, const int* done, hipStream_t s);
+void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done, hipStream_t s);
+void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s);
+void sum32(int32_t n, const float* v, const DevScalars* sc, double* part0, const int* done, hipStream_t s);
+void zconv_dot(int32_t n, const DevScalars* sc, const float* z32, double* z, const double* o,
+               double* part0, int sub_mean_flag, const int* done, hipStream_t s);
+void zsub_dot(int32_t n, const DevScalars* sc, double* z, const double* o, double* part0,
+              int sub_mean_flag, const int* done, hipStream_t s);
+void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s);
+void dot(int32_t n, const double* a, const double* b, double* part0, const int* done, hipStream_t s);
+void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s);
+void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const int* done, hipStream_t s);
+
+enum FinOp : int {
+  FIN_BNORM = 0,      // bnorm = sqrt(sum0 + boundary part); choose the FP32 scale
+  FIN_ALPHA_CG = 1,   // pq = sum0; alpha = rho / pq
+  FIN_ALPHA_FCG = 2,  // pq = sum0; alpha = sum1 / pq
+  FIN_CHECK = 3,      // rnorm = sqrt(sum0); iters++; convergence / limits
+  FIN_BETA_CG = 4,    // beta = sum0 / rho; rho = sum0
+  FIN_BETA_FCG = 5,   // beta = -sum0 / pq
+  FIN_MEAN = 6,       // mean = sum0 / n
+  FIN_RNORM = 7,      // rnorm = sqrt(sum0) (no iteration bookkeeping)
+};
+void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
+              double extra, hipStream_t s);
+}  // namespace k
+
+}  // namespace decmg

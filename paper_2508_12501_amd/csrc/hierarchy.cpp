@@ -1,0 +1,393 @@
+// Hierarchy construction: subdivision levels, locality ordering, SELL-64 operators, transfer
+// lists, the coarsest dense inverse and device upload.  Host code, compiled with
+// -ffp-contract=off so that host sums match the kernels' plain IEEE order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+#include "hier.hpp"
+#include "util.hpp"
+
+namespace decmg {
+
+namespace {
+
+uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  uint64_t m = 0;
+  for (int b = 0; b < 21; ++b) {
+    m |= uint64_t((x >> b) & 1u) << (3 * b);
+    m |= uint64_t((y >> b) & 1u) << (3 * b + 1);
+    m |= uint64_t((z >> b) & 1u) << (3 * b + 2);
+  }
+  return m;
+}
+
+// Internal order of the unknowns: Z-order of the coordinates quantised on a 2^20 grid of the
+// level's bounding box (grid spacings that are powers of two land on whole cells).
+void order_level(Level& L, int bc) {
+  const Mesh& m = L.mesh;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t v = 0; v < m.nv; ++v)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], m.xyz[3 * v + c]);
+      hi[c] = std::max(hi[c], m.xyz[3 * v + c]);
+    }
+  std::vector<std::pair<uint64_t, int32_t>> keys;
+  keys.reserve(m.nv);
+  L.bnd_h.clear();
+  for (int64_t v = 0; v < m.nv; ++v) {
+    if (bc == MG_BC_DIRICHLET0 && m.bnd[v]) {
+      L.bnd_h.push_back(int32_t(v));
+      continue;
+    }
+    uint32_t q[3];
+    for (int c = 0; c < 3; ++c) {
+      const double span = hi[c] - lo[c];
+      q[c] = span > 0 ? uint32_t(std::floor((m.xyz[3 * v + c] - lo[c]) / span * 1048576.0)) : 0u;
+    }
+    keys.emplace_back(morton3(q[0], q[1], q[2]), int32_t(v));
+  }
+  std::sort(keys.begin(), keys.end());
+  L.n = int32_t(keys.size());
+  L.perm_h.resize(L.n);
+  L.inv_h.assign(m.nv, -1);
+  for (int32_t k = 0; k < L.n; ++k) {
+    L.perm_h[k] = keys[k].second;
+    L.inv_h[keys[k].second] = k;
+  }
+}
+
+// Vertex -> incident edges (all edges, CSR).
+void vertex_edges(const Mesh& m, std::vector<int64_t>& off, std::vector<int32_t>& inc) {
+  off.assign(m.nv + 1, 0);
+  for (int64_t e = 0; e < m.ne; ++e) {
+    off[m.edge[2 * e] + 1]++;
+    off[m.edge[2 * e + 1] + 1]++;
+  }
+  for (int64_t v = 0; v < m.nv; ++v) off[v + 1] += off[v];
+  inc.resize(off[m.nv]);
+  std::vector<int64_t> pos(off.begin(), off.end() - 1);
+  for (int64_t e = 0; e < m.ne; ++e) {
+    inc[pos[m.edge[2 * e]]++] = int32_t(e);
+    inc[pos[m.edge[2 * e + 1]]++] = int32_t(e);
+  }
+}
+
+template <typename T>
+T* upload(const std::vector<T>& h) {
+  T* d = nullptr;
+  if (h.empty()) return nullptr;
+  check_hip(hipMalloc(&d, h.size() * sizeof(T)), "hipMalloc");
+  check_hip(hipMemcpy(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice), "hipMemcpy");
+  return d;
+}
+
+template <typename T>
+T* zeros(int64_t n) {
+  T* d = nullptr;
+  check_hip(hipMalloc(&d, std::max<int64_t>(n, 1) * sizeof(T)), "hipMalloc");
+  check_hip(hipMemset(d, 0, std::max<int64_t>(n, 1) * sizeof(T)), "hipMemset");
+  return d;
+}
+
+// SELL-64 structure of the operator: per internal row, the couplings with nonzero star1,
+// sorted by column; neighbours that are not unknowns point at the zero slot n.
+void build_operator_structure(Level& L, std::vector<int32_t>& col) {
+  const Mesh& m = L.mesh;
+  std::vector<int64_t> off;
+  std::vector<int32_t> inc;
+  vertex_edges(m, off, inc);
+  const int32_t n = L.n;
+  const int32_t nslices = (n + kSlice - 1) / kSlice;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rows(kSlice);
+  L.sptr_h.assign(nslices + 1, 0);
+  col.clear();
+  L.entry_edge.clear();
+  for (int32_t s = 0; s < nslices; ++s) {
+    int32_t width = 0;
+    for (int l = 0; l < kSlice; ++l) {
+      rows[l].clear();
+      const int32_t r = s * kSlice + l;
+      if (r >= n) continue;
+      const int32_t v = L.perm_h[r];
+      for (int64_t q = off[v]; q < off[v + 1]; ++q) {
+        const int32_t e = inc[q];
+        if (m.star1[e] == 0.0) continue;
+        const int32_t u = m.edge[2 * e] == v ? m.edge[2 * e + 1] : m.edge[2 * e];
+        const int32_t c = L.inv_h[u] >= 0 ? L.inv_h[u] : n;
+        rows[l].emplace_back(c, e);
+      }
+      std::sort(rows[l].begin(), rows[l].end());
+      width = std::max<int32_t>(width, int32_t(rows[l].size()));
+    }
+    L.sptr_h[s + 1] = L.sptr_h[s] + width;
+    const size_t base = col.size();
+    col.resize(base + size_t(width) * kSlice, n);
+    L.entry_edge.resize(base + size_t(width) * kSlice, -1);
+    for (int l = 0; l < kSlice; ++l)
+      for (size_t k = 0; k < rows[l].size(); ++k) {
+        col[base + k * kSlice + l] = rows[l][k].first;
+        L.entry_edge[base + k * kSlice + l] = rows[l][k].second;
+      }
+  }
+  L.op.nslices = nslices;
+  L.op.ncols = L.sptr_h[nslices];
+}
+
+// Edge weights w_e = star1_e * (k_lo + k_hi) / 2 for the SELL entries (k = 1 when empty),
+// row sums in SELL order.
+void compute_weights(const Level& L, const std::vector<double>& kv, std::vector<double>& w64,
+                     std::vector<float>& w32, std::vector<double>& d64, std::vector<float>& d32) {
+  const Mesh& m = L.mesh;
+  const size_t ne = L.entry_edge.size();
+  w64.assign(ne, 0.0);
+  w32.assign(ne, 0.0f);
+  for (size_t i = 0; i < ne; ++i) {
+    const int32_t e = L.entry_edge[i];
+    if (e < 0) continue;
+    double w = m.star1[e];
+    if (!kv.empty()) w = m.star1[e] * (0.5 * (kv[m.edge[2 * e]] + kv[m.edge[2 * e + 1]]));
+    w64[i] = w;
+    w32[i] = static_cast<float>(w);
+  }
+  d64.assign(L.n + 1, 0.0);
+  d32.assign(L.n + 1, 0.0f);
+  for (int32_t r = 0; r < L.n; ++r) {
+    const int32_t s = r / kSlice, l = r % kSlice;
+    double a = 0.0;
+    float b = 0.0f;
+    for (int32_t k = L.sptr_h[s]; k < L.sptr_h[s + 1]; ++k) {
+      a += w64[size_t(k) * kSlice + l];
+      b += w32[size_t(k) * kSlice + l];
+    }
+    d64[r] = a;
+    d32[r] = b;
+  }
+}
+
+// Dense inverse of the coarsest operator over its unknowns (Cholesky).  Natural boundaries
+// (L singular, kernel = constants): the pseudo-inverse L^+ = (L + 1 1^T / n)^{-1} - 1 1^T / n,
+// i.e. the minimum-norm solution, which is zero-mean for any right-hand side.
+std::vector<double> coarse_inverse(const Level& L, const std::vector<double>& w64, int bc) {
+  const int32_t n = L.n;
+  std::vector<double> A(size_t(n) * n, 0.0);
+  for (int32_t r = 0; r < n; ++r) {
+    const int32_t s = r / kSlice, l = r % kSlice;
+    for (int32_t k = L.sptr_h[s]; k < L.sptr_h[s + 1]; ++k) {
+      const size_t i = size_t(k) * kSlice + l;
+      const int32_t e = L.entry_edge[i];
+      if (e < 0) continue;
+      const int32_t v = L.perm_h[r];
+      const int32_t u = L.mesh.edge[2 * e] == v ? L.mesh.edge[2 * e + 1] : L.mesh.edge[2 * e];
+      const int32_t cc = L.inv_h[u];
+      A[size_t(r) * n + r] += w64[i];
+      if (cc >= 0) A[size_t(r) * n + cc] -= w64[i];
+    }
+  }
+  if (bc == MG_BC_NATURAL)
+    for (auto& a : A) a += 1.0 / n;
+  // Cholesky A = G G^T (lower G)
+  std::vector<double> G(A);
+  for (int32_t j = 0; j < n; ++j) {
+    double d = G[size_t(j) * n + j];
+    for (int32_t k = 0; k < j; ++k) d -= G[size_t(j) * n + k] * G[size_t(j) * n + k];
+    if (!(d > 0)) throw std::runtime_error("coarsest operator is not positive definite");
+    d = std::sqrt(d);
+    G[size_t(j) * n + j] = d;
+    for (int32_t i = j + 1; i < n; ++i) {
+      double v = G[size_t(i) * n + j];
+      for (int32_t k = 0; k < j; ++k) v -= G[size_t(i) * n + k] * G[size_t(j) * n + k];
+      G[size_t(i) * n + j] = v / d;
+    }
+  }
+  // inverse column by column: solve G y = e_c, G^T x = y
+  std::vector<double> inv(size_t(n) * n, 0.0), y(n);
+  for (int32_t c = 0; c < n; ++c) {
+    for (int32_t i = 0; i < n; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int32_t k = 0; k < i; ++k) v -= G[size_t(i) * n + k] * y[k];
+      y[i] = v / G[size_t(i) * n + i];
+    }
+    for (int32_t i = n - 1; i >= 0; --i) {
+      double v = y[i];
+      for (int32_t k = i + 1; k < n; ++k) v -= G[size_t(k) * n + i] * inv[size_t(k) * n + c];
+      inv[size_t(i) * n + c] = v / G[size_t(i) * n + i];
+    }
+  }
+  if (bc == MG_BC_NATURAL)
+    for (auto& a : inv) a -= 1.0 / n;
+  return inv;
+}
+
+void build_transfer(Level& F, const Level& C) {
+  // interpolation: two coarse parents per fine unknown (zero slot for non-unknowns)
+  std::vector<int32_t> pa(F.n + 1, C.n), pb(F.n + 1, C.n);
+  for (int32_t k = 0; k < F.n; ++k) {
+    const int32_t v = F.perm_h[k];
+    const int32_t a = F.mesh.parent[2 * v], b = F.mesh.parent[2 * v + 1];
+    pa[k] = C.inv_h[a] >= 0 ? C.inv_h[a] : C.n;
+    pb[k] = C.inv_h[b] >= 0 ? C.inv_h[b] : C.n;
+  }
+  // restriction rows: kept vertex + midpoints of all incident coarse edges
+  std::vector<int64_t> off;
+  std::vector<int32_t> inc;
+  vertex_edges(C.mesh, off, inc);
+  std::vector<int32_t> self(C.n + 1, F.n);
+  const int32_t nslices = (C.n + kSlice - 1) / kSlice;
+  std::vector<int32_t> sptr(nslices + 1, 0), col;
+  std::vector<std::vector<int32_t>> rows(kSlice);
+  for (int32_t s = 0; s < nslices; ++s) {
+    int32_t width = 0;
+    for (int l = 0; l < kSlice; ++l) {
+      rows[l].clear();
+      const int32_t r = s * kSlice + l;
+      if (r >= C.n) continue;
+      const int32_t v = C.perm_h[r];
+      self[r] = F.inv_h[v];
+      for (int64_t q = off[v]; q < off[v + 1]; ++q) {
+        const int32_t mid = int32_t(C.mesh.nv + inc[q]);
+        if (F.inv_h[mid] >= 0) rows[l].push_back(F.inv_h[mid]);
+      }
+      std::sort(rows[l].begin(), rows[l].end());
+      width = std::max<int32_t>(width, int32_t(rows[l].size()));
+    }
+    sptr[s + 1] = sptr[s] + width;
+    const size_t base = col.size();
+    col.resize(base + size_t(width) * kSlice, F.n);
+    for (int l = 0; l < kSlice; ++l)
+      for (size_t k = 0; k < rows[l].size(); ++k) col[base + k * kSlice + l] = rows[l][k];
+  }
+  F.tr.pa = upload(pa);
+  F.tr.pb = upload(pb);
+  F.tr.r_self = upload(self);
+  F.tr.nslices = nslices;
+  F.tr.ncols = sptr[nslices];
+  F.tr.r_sptr = upload(sptr);
+  F.tr.r_col = col.empty() ? zeros<int32_t>(1) : upload(col);
+}
+
+template <typename T>
+void alloc_vecs(LevelVecs<T>& V, int32_t n) {
+  V.x = zeros<T>(n + 1);
+  V.b = zeros<T>(n + 1);
+  V.r = zeros<T>(n + 1);
+  V.t = zeros<T>(n + 1);
+}
+
+void free_dev(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+}  // namespace
+
+void upload_weights(Hierarchy& H) {
+  for (size_t l = 0; l < H.lv.size(); ++l) {
+    Level& L = *H.lv[l];
+    std::vector<double> w64, d64;
+    std::vector<float> w32, d32;
+    std::vector<double> kv;
+    if (!H.kvert_h.empty()) kv.assign(H.kvert_h.begin(), H.kvert_h.begin() + L.nv);
+    compute_weights(L, kv, w64, w32, d64, d32);
+    if (!L.op.w64) {
+      L.op.w64 = zeros<double>(std::max<size_t>(w64.size(), 1));
+      L.op.w32 = zeros<float>(std::max<size_t>(w32.size(), 1));
+      L.op.diag64 = zeros<double>(L.n + 1);
+      L.op.diag32 = zeros<float>(L.n + 1);
+    }
+    if (!w64.empty()) {
+      check_hip(hipMemcpy(L.op.w64, w64.data(), w64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
+      check_hip(hipMemcpy(L.op.w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    check_hip(hipMemcpy(L.op.diag64, d64.data(), d64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
+    check_hip(hipMemcpy(L.op.diag32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    if (l == 0 && L.n > 0) {
+      std::vector<double> inv = coarse_inverse(L, w64, H.bc);
+      if (!H.coarse_inv) H.coarse_inv = zeros<double>(int64_t(L.n) * L.n);
+      check_hip(hipMemcpy(H.coarse_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice),
+                "hipMemcpy");
+    }
+  }
+}
+
+Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
+  auto H = std::make_unique<Hierarchy>();
+  H->bc = o.bc;
+  H->project = o.project_sphere != 0;
+  // host meshes
+  std::vector<Mesh> meshes;
+  meshes.push_back(base);
+  for (int i = 0; i < o.n_subdiv; ++i) {
+    Mesh f = subdivide(meshes.back(), H->project);
+    std::string err = f.build_topology();
+    if (!err.empty()) throw std::invalid_argument(err);
+    meshes.push_back(std::move(f));
+  }
+  for (auto& m : meshes) {
+    m.build_stars();
+    m.build_boundary();
+    auto L = std::make_unique<Level>();
+    L->mesh = std::move(m);
+    L->nv = int32_t(L->mesh.nv);
+    order_level(*L, H->bc);
+    H->lv.push_back(std::move(L));
+  }
+  if (H->lv[0]->n > kMaxCoarse)
+    throw std::invalid_argument("base mesh has more than " + std::to_string(kMaxCoarse) +
+                                " unknowns; the coarsest level is solved densely");
+  if (H->lv[0]->n == 0) throw std::invalid_argument("base mesh has no unknowns");
+  for (size_t l = 0; l < H->lv.size(); ++l) {
+    Level& L = *H->lv[l];
+    std::vector<int32_t> col;
+    build_operator_structure(L, col);
+    L.op.sptr = upload(L.sptr_h);
+    L.op.col = col.empty() ? zeros<int32_t>(1) : upload(col);
+    L.perm = upload(L.perm_h);
+    L.bnd_ids = L.bnd_h.empty() ? zeros<int32_t>(1) : upload(L.bnd_h);
+    L.star0 = upload(L.mesh.star0);
+    alloc_vecs(L.v64, L.n);
+    alloc_vecs(L.v32, L.n);
+    if (l > 0) build_transfer(L, *H->lv[l - 1]);
+  }
+  H->n0 = H->lv[0]->n;
+  upload_weights(*H);
+  // Krylov workspace on the finest level
+  const int32_t n = H->lv.back()->n;
+  H->sx = zeros<double>(n + 1);
+  H->sr = zeros<double>(n + 1);
+  H->sp = zeros<double>(n + 1);
+  H->sq = zeros<double>(n + 1);
+  H->sz = zeros<double>(n + 1);
+  const int32_t nvmax = H->lv.back()->nv;
+  H->sb = zeros<double>(std::max(n, nvmax) + 1);
+  H->part_cap = std::max(k::blocks_for(nvmax), 1);
+  H->part = zeros<double>(3 * int64_t(H->part_cap));
+  H->scal = zeros<DevScalars>(1);
+  check_hip(hipHostMalloc(reinterpret_cast<void**>(&H->scal_host), sizeof(DevScalars), 0),
+            "hipHostMalloc");
+  std::memset(H->scal_host, 0, sizeof(DevScalars));
+  check_hip(hipStreamCreateWithFlags(&H->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
+  return H.release();
+}
+
+Hierarchy::~Hierarchy() {
+  for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  for (auto& Lp : lv) {
+    Level& L = *Lp;
+    for (void* p : {(void*)L.perm, (void*)L.bnd_ids, (void*)L.star0, (void*)L.op.sptr,
+                    (void*)L.op.col, (void*)L.op.w64, (void*)L.op.w32, (void*)L.op.diag64,
+                    (void*)L.op.diag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
+                    (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.v64.x, (void*)L.v64.b,
+                    (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
+                    (void*)L.v32.r, (void*)L.v32.t})
+      free_dev(p);
+  }
+  for (void* p : {(void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
+                  (void*)sb, (void*)part, (void*)scal})
+    free_dev(p);
+  if (scal_host) (void)hipHostFree(scal_host);
+  if (capture_stream) (void)hipStreamDestroy(capture_stream);
+}
+
+}  // namespace decmg

@@ -1,0 +1,665 @@
+// HIP kernels of the DEC multigrid path for CDNA4 (gfx950).
+//
+// Every stage is a sparse, memory-bound gather, so nothing here uses MFMA.  Rows map one to
+// a lane of a 64-wide wavefront; the operator is stored as SELL-64 so that the index and
+// weight streams of a wavefront are single coalesced 256/512-byte loads per column.  Row
+// blocks are remapped so that each XCD (the hardware hands workgroups to the 8 XCDs in
+// turn) walks one contiguous range of rows and its neighbour gathers stay in its own L2.
+// Reductions are deterministic: wavefront butterflies, a fixed-order combine of the four
+// wavefronts, per-block partials, then one fixed-order finalisation block.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "hier.hpp"
+
+namespace decmg {
+namespace {
+
+__device__ __forceinline__ int xcd_block() {
+  const int b = blockIdx.x, g = gridDim.x;
+  const int x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block of kBlock threads: returns the block total in thread 0 (fixed order).
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double sa[kBlock / 64], sb[kBlock / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sa[w] = a;
+    sb[w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) {
+      ta += sa[i];
+      tb += sb[i];
+    }
+    a = ta;
+    b = tb;
+  }
+}
+
+__device__ __forceinline__ double block_sum1(double a) {
+  double b = 0.0;
+  block_sum2(a, b);
+  return a;
+}
+
+// acc = sum_k w_k (x_i - x_j(k)) and d = sum_k w_k over the row's SELL entries.
+template <typename T>
+__device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr,
+                                          const int32_t* __restrict__ col,
+                                          const T* __restrict__ w, const T* __restrict__ x,
+                                          int row, T xi, T& acc, T& d) {
+  const int s = row >> 6, lane = row & 63;
+  const int beg = sptr[s], end = sptr[s + 1];
+  acc = T(0);
+  d = T(0);
+  for (int k = beg; k < end; ++k) {
+    const int idx = k * kSlice + lane;
+    const T wk = w[idx];
+    d += wk;
+    acc += wk * (xi - x[col[idx]]);
+  }
+}
+
+// MODE 0: y = A x.  MODE 1: y = b - A x.  MODE 2: y = x + omega (b - A x) / D.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ sptr,
+                                                 const int32_t* __restrict__ col,
+                                                 const T* __restrict__ w,
+                                                 const T* __restrict__ x,
+                                                 const T* __restrict__ b, T* __restrict__ y,
+                                                 int32_t n, T omega,
+                                                 const int* __restrict__ done) {
+  if (done && *done) return;
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= n) return;
+  const T xi = x[row];
+  T acc, d;
+  row_apply(sptr, col, w, x, row, xi, acc, d);
+  if (MODE == 0)
+    y[row] = acc;
+  else if (MODE == 1)
+    y[row] = b[row] - acc;
+  else
+    y[row] = xi + omega * (b[row] - acc) / d;
+}
+
+// First smoothing sweep from x = 0: x = omega b / D.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_zero(const T* __restrict__ diag,
+                                                        const T* __restrict__ b,
+                                                        T* __restrict__ y, int32_t n, T omega,
+                                                        const int* __restrict__ done) {
+  if (done && *done) return;
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= n) return;
+  y[row] = omega * b[row] / diag[row];
+}
+
+// r_c = M(f) r_f: the kept vertex with weight 1, every midpoint of an incident coarse edge
+// with weight 1/2.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__ self,
+                                                     const int32_t* __restrict__ sptr,
+                                                     const int32_t* __restrict__ col,
+                                                     const T* __restrict__ rf,
+                                                     T* __restrict__ rc, int32_t nc,
+                                                     const int* __restrict__ done) {
+  if (done && *done) return;
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= nc) return;
+  const int s = row >> 6, lane = row & 63;
+  const int beg = sptr[s], end = sptr[s + 1];
+  T acc = T(0);
+  for (int k = beg; k < end; ++k) acc += rf[col[k * kSlice + lane]];
+  rc[row] = rf[self[row]] + T(0.5) * acc;
+}
+
+// x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ pa,
+                                                    const int32_t* __restrict__ pb,
+                                                    const T* __restrict__ ec,
+                                                    T* __restrict__ xf, int32_t nf,
+                                                    const int* __restrict__ done) {
+  if (done && *done) return;
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= nf) return;
+  xf[row] += T(0.5) * (ec[pa[row]] + ec[pb[row]]);
+}
+
+// Exact coarsest solve x = A0^{-1} b in FP64 by one workgroup.
+template <typename T>
+__global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ ainv,
+                                                const T* __restrict__ b, T* __restrict__ x,
+                                                int32_t n0, const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sb[kMaxCoarse];
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) sb[i] = static_cast<double>(b[i]);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+    const double* a = ainv + static_cast<int64_t>(i) * n0;
+    double acc = 0.0;
+    for (int j = 0; j < n0; ++j) acc += a[j] * sb[j];
+    x[i] = static_cast<T>(acc);
+  }
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_gather(const int32_t* __restrict__ perm, int32_t n, const T* __restrict__ src,
+                         T* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[perm[i]];
+}
+
+template <typename T>
+__global__ void k_scatter(const int32_t* __restrict__ perm, int32_t n, const T* __restrict__ src,
+                          T* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[perm[i]] = src[i];
+}
+
+template <typename T>
+__global__ void k_bnd_copy(const int32_t* __restrict__ ids, int32_t nb, const T* __restrict__ src,
+                           T* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) dst[ids[i]] = src[ids[i]];
+}
+
+template <typename T>
+__global__ void k_bnd_jacobi(const int32_t* __restrict__ ids, int32_t nb, const T* __restrict__ b,
+                             T* __restrict__ x, T omega) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    const int v = ids[i];
+    x[v] = x[v] + omega * (b[v] - x[v]);
+  }
+}
+
+template <typename T>
+__global__ void k_bnd_zero(const int32_t* __restrict__ ids, int32_t nb, T* __restrict__ x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) x[ids[i]] = T(0);
+}
+
+__global__ void k_star0(const double* __restrict__ s0, const double* __restrict__ f,
+                        double* __restrict__ b, int32_t nv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nv) b[i] = s0[i] * f[i];
+}
+
+// ------------------------------------------------------------------ Krylov kernels (FP64)
+__global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict__ sptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const double* __restrict__ w,
+                                                      const double* __restrict__ p,
+                                                      double* __restrict__ q,
+                                                      const double* __restrict__ r,
+                                                      double* __restrict__ part0,
+                                                      double* __restrict__ part1, int32_t n,
+                                                      const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  const int row = blk * kBlock + threadIdx.x;
+  double v0 = 0.0, v1 = 0.0;
+  if (row < n) {
+    const double pi = p[row];
+    double acc, d;
+    row_apply(sptr, col, w, p, row, pi, acc, d);
+    q[row] = acc;
+    v0 = pi * acc;
+    v1 = pi * r[row];
+  }
+  block_sum2(v0, v1);
+  if (threadIdx.x == 0) {
+    part0[blk] = v0;
+    part1[blk] = v1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalars* __restrict__ sc,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ x,
+                                                      double* __restrict__ r,
+                                                      float* __restrict__ r32,
+                                                      double* __restrict__ part0,
+                                                      const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const double a = sc->alpha;
+    x[i] = x[i] + a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    v = ri * ri;
+    if (r32) r32[i] = static_cast<float>(ri * sc->scale);
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restrict__ sptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const double* __restrict__ w,
+                                                          const double* __restrict__ x,
+                                                          const double* __restrict__ b,
+                                                          double* __restrict__ r,
+                                                          float* __restrict__ r32,
+                                                          const DevScalars* __restrict__ sc,
+                                                          double* __restrict__ part0, int32_t n,
+                                                          const int* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = xcd_block();
+  const int row = blk * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (row < n) {
+    double acc, d;
+    row_apply(sptr, col, w, x, row, x[row], acc, d);
+    const double ri = b[row] - acc;
+    r[row] = ri;
+    v = ri * ri;
+    if (r32) r32[row] = static_cast<float>(ri * sc->scale);
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pupdate(int32_t n, const DevScalars* __restrict__ sc,
+                                                    const double* __restrict__ z,
+                                                    double* __restrict__ p,
+                                                    const int* __restrict__ done) {
+  if (*done) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i < n) p[i] = z[i] + sc->beta * p[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum64(int32_t n, const double* __restrict__ v,
+                                                  double* __restrict__ part0,
+                                                  const int* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double a = (i < n) ? v[i] : 0.0;
+  a = block_sum1(a);
+  if (threadIdx.x == 0) part0[blk] = a;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum32(int32_t n, const float* __restrict__ v,
+                                                  const DevScalars* __restrict__ sc,
+                                                  double* __restrict__ part0,
+                                                  const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double a = (i < n) ? static_cast<double>(v[i]) * sc->inv_scale : 0.0;
+  a = block_sum1(a);
+  if (threadIdx.x == 0) part0[blk] = a;
+}
+
+// z = z32 / scale - mean (mean only when sub_mean), part0 = z . o
+__global__ __launch_bounds__(kBlock) void k_zconv_dot(int32_t n, const DevScalars* __restrict__ sc,
+                                                      const float* __restrict__ z32,
+                                                      double* __restrict__ z,
+                                                      const double* __restrict__ o,
+                                                      double* __restrict__ part0, int sub_mean,
+                                                      const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double zi = static_cast<double>(z32[i]) * sc->inv_scale;
+    if (sub_mean) zi = zi - sc->mean;
+    z[i] = zi;
+    v = zi * o[i];
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
+// z -= mean (when sub_mean), part0 = z . o
+__global__ __launch_bounds__(kBlock) void k_zsub_dot(int32_t n, const DevScalars* __restrict__ sc,
+                                                     double* __restrict__ z,
+                                                     const double* __restrict__ o,
+                                                     double* __restrict__ part0, int sub_mean,
+                                                     const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    double zi = z[i];
+    if (sub_mean) {
+      zi = zi - sc->mean;
+      z[i] = zi;
+    }
+    v = zi * o[i];
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_axpy1(int32_t n, const double* __restrict__ z,
+                                                  double* __restrict__ x,
+                                                  const int* __restrict__ done) {
+  if (*done) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i < n) x[i] = x[i] + z[i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double* __restrict__ a,
+                                                const double* __restrict__ b,
+                                                double* __restrict__ part0,
+                                                const int* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double v = (i < n) ? a[i] * b[i] : 0.0;
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
+__global__ void k_sub_mean(int32_t n, const DevScalars* __restrict__ sc, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = v[i] - sc->mean;
+}
+
+__global__ void k_to_f32(int32_t n, const DevScalars* __restrict__ sc, const double* __restrict__ r,
+                         float* __restrict__ r32, const int* __restrict__ done) {
+  if (done && *done) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) r32[i] = static_cast<float>(r[i] * sc->scale);
+}
+
+// One workgroup: fixed-order sum of the partials, then the scalar step `op`.
+__global__ __launch_bounds__(kBlock) void k_finalize(int op, int32_t nb,
+                                                     const double* __restrict__ part0,
+                                                     const double* __restrict__ part1,
+                                                     DevScalars* __restrict__ sc, double extra) {
+  if (sc->done) return;
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kBlock) {
+    a += part0[i];
+    if (part1) b += part1[i];
+  }
+  block_sum2(a, b);
+  if (threadIdx.x != 0) return;
+  switch (op) {
+    case k::FIN_BNORM: {
+      const double bn = sqrt(a + extra);
+      sc->bnorm = bn;
+      sc->rnorm = bn;
+      if (!isfinite(bn)) {
+        sc->status = MG_ENONFINITE;
+        sc->done = 1;
+      } else if (bn == 0.0) {
+        sc->status = MG_OK;
+        sc->done = 1;
+      } else {
+        // power-of-two scale that brings the residual to O(1) for the FP32 copy
+        int e;
+        frexp(bn / sqrt(sc->n_unknowns), &e);
+        sc->scale = ldexp(1.0, -e);
+        sc->inv_scale = ldexp(1.0, e);
+      }
+      break;
+    }
+    case k::FIN_ALPHA_CG:
+      sc->pq = a;
+      if (!(a > 0.0) || !isfinite(a)) {
+        sc->status = isfinite(a) ? MG_EBREAKDOWN : MG_ENONFINITE;
+        sc->done = 1;
+      } else {
+        sc->alpha = sc->rho / a;
+      }
+      break;
+    case k::FIN_ALPHA_FCG:
+      sc->pq = a;
+      if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
+        sc->status = (isfinite(a) && isfinite(b)) ? MG_EBREAKDOWN : MG_ENONFINITE;
+        sc->done = 1;
+      } else {
+        sc->alpha = b / a;
+      }
+      break;
+    case k::FIN_CHECK: {
+      const double rn = sqrt(a);
+      sc->rnorm = rn;
+      sc->iters += 1;
+      if (!isfinite(rn)) {
+        sc->status = MG_ENONFINITE;
+        sc->done = 1;
+      } else if (rn <= sc->rtol * sc->bnorm) {
+        sc->status = MG_OK;
+        sc->done = 1;
+      } else if (sc->iters >= sc->max_iter) {
+        sc->status = MG_ENOCONV;
+        sc->done = 1;
+      }
+      break;
+    }
+    case k::FIN_BETA_CG:
+      if (!(a > 0.0) || !isfinite(a)) {
+        sc->status = isfinite(a) ? MG_EBREAKDOWN : MG_ENONFINITE;
+        sc->done = 1;
+      } else {
+        sc->beta = a / sc->rho;
+        sc->rho = a;
+      }
+      break;
+    case k::FIN_BETA_FCG:
+      sc->beta = -a / sc->pq;
+      if (!isfinite(sc->beta)) {
+        sc->status = MG_ENONFINITE;
+        sc->done = 1;
+      }
+      break;
+    case k::FIN_MEAN:
+      sc->mean = a / sc->n_unknowns;
+      break;
+    case k::FIN_RNORM:
+      sc->rnorm = sqrt(a);
+      break;
+  }
+}
+
+inline unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+namespace k {
+
+int blocks_for(int32_t n) { return static_cast<int>(grid_for(n)); }
+
+template <typename T>
+static const T* weights(const Level& L);
+template <>
+const double* weights<double>(const Level& L) { return L.op.w64; }
+template <>
+const float* weights<float>(const Level& L) { return L.op.w32; }
+template <typename T>
+static const T* diagonal(const Level& L);
+template <>
+const double* diagonal<double>(const Level& L) { return L.op.diag64; }
+template <>
+const float* diagonal<float>(const Level& L) { return L.op.diag32; }
+
+template <typename T>
+void spmv(const Level& L, const T* x, T* y, const int* done, hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_rows<T, 0>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
+                     weights<T>(L), x, static_cast<const T*>(nullptr), y, L.n, T(0), done);
+}
+template <typename T>
+void residual(const Level& L, const T* x, const T* b, T* r, const int* done, hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_rows<T, 1>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
+                     weights<T>(L), x, b, r, L.n, T(0), done);
+}
+template <typename T>
+void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done,
+            hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_rows<T, 2>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
+                     weights<T>(L), x, b, xo, L.n, static_cast<T>(omega), done);
+}
+template <typename T>
+void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_jacobi_zero<T>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, diagonal<T>(L), b,
+                     xo, L.n, static_cast<T>(omega), done);
+}
+template <typename T>
+void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done,
+               hipStream_t s) {
+  if (Lc.n == 0) return;
+  hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s, Lf.tr.r_self,
+                     Lf.tr.r_sptr, Lf.tr.r_col, rf, rc, Lc.n, done);
+}
+template <typename T>
+void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int* done,
+             hipStream_t s) {
+  if (Lf.n == 0) return;
+  hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s, Lf.tr.pa, Lf.tr.pb,
+                     ec, xf, Lf.n, done);
+}
+template <typename T>
+void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s) {
+  if (H.n0 == 0) return;
+  hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(256), 0, s, H.coarse_inv, b, x, H.n0, done);
+}
+template <typename T>
+void fill(T* p, int64_t n, T v, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
+}
+template <typename T>
+void gather(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_gather<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, perm, n, src, dst);
+}
+template <typename T>
+void scatter(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_scatter<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, perm, n, src, dst);
+}
+template <typename T>
+void bnd_copy(const int32_t* ids, int32_t nb, const T* src, T* dst, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_bnd_copy<T>), dim3(grid_for(nb)), dim3(kBlock), 0, s, ids, nb, src, dst);
+}
+template <typename T>
+void bnd_jacobi(const int32_t* ids, int32_t nb, const T* b, T* x, double omega, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_bnd_jacobi<T>), dim3(grid_for(nb)), dim3(kBlock), 0, s, ids, nb, b, x,
+                     static_cast<T>(omega));
+}
+template <typename T>
+void bnd_zero(const int32_t* ids, int32_t nb, T* x, hipStream_t s) {
+  if (nb <= 0) return;
+  hipLaunchKernelGGL((k_bnd_zero<T>), dim3(grid_for(nb)), dim3(kBlock), 0, s, ids, nb, x);
+}
+void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_star0, dim3(grid_for(L.nv)), dim3(kBlock), 0, s, L.star0, f, b, L.nv);
+  if (bc == MG_BC_DIRICHLET0) bnd_zero<double>(L.bnd_ids, static_cast<int32_t>(L.bnd_h.size()), b, s);
+}
+
+void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
+               double* part1, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_spmv_dot2, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
+                     L.op.w64, p, q, r, part0, part1, L.n, done);
+}
+void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
+               double* r, float* r32, double* part0, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_xr, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, p, q, x, r, r32,
+                     part0, done);
+}
+void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
+                   const DevScalars* sc, double* part0, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_residual_norm, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                     L.op.col, L.op.w64, x, b, r, r32, sc, part0, L.n, done);
+}
+void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
+             hipStream_t s) {
+  hipLaunchKernelGGL(k_pupdate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, p, done);
+}
+void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum64, dim3(grid_for(n)), dim3(kBlock), 0, s, n, v, part0, done);
+}
+void sum32(int32_t n, const float* v, const DevScalars* sc, double* part0, const int* done,
+           hipStream_t s) {
+  hipLaunchKernelGGL(k_sum32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, v, sc, part0, done);
+}
+void zconv_dot(int32_t n, const DevScalars* sc, const float* z32, double* z, const double* o,
+               double* part0, int sub_mean_flag, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_zconv_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z32, z, o, part0,
+                     sub_mean_flag, done);
+}
+void zsub_dot(int32_t n, const DevScalars* sc, double* z, const double* o, double* part0,
+              int sub_mean_flag, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_zsub_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, o, part0,
+                     sub_mean_flag, done);
+}
+void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n)), dim3(kBlock), 0, s, n, z, x, done);
+}
+void dot(int32_t n, const double* a, const double* b, double* part0, const int* done,
+         hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, n, a, b, part0, done);
+}
+void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, v);
+}
+void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const int* done,
+            hipStream_t s) {
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, r, r32, done);
+}
+void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
+              double extra, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, op, nblocks, part0, part1, sc, extra);
+}
+
+#define DECMG_INST(T)                                                                          \
+  template void spmv<T>(const Level&, const T*, T*, const int*, hipStream_t);                   \
+  template void residual<T>(const Level&, const T*, const T*, T*, const int*, hipStream_t);     \
+  template void jacobi<T>(const Level&, const T*, const T*, T*, double, const int*, hipStream_t); \
+  template void jacobi_zero<T>(const Level&, const T*, T*, double, const int*, hipStream_t);    \
+  template void restrict_<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t); \
+  template void prolong<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t);  \
+  template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \
+  template void fill<T>(T*, int64_t, T, hipStream_t);                                          \
+  template void gather<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                 \
+  template void scatter<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                \
+  template void bnd_copy<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);               \
+  template void bnd_jacobi<T>(const int32_t*, int32_t, const T*, T*, double, hipStream_t);     \
+  template void bnd_zero<T>(const int32_t*, int32_t, T*, hipStream_t);
+DECMG_INST(double)
+DECMG_INST(float)
+#undef DECMG_INST
+
+}  // namespace k
+}  // namespace decmg

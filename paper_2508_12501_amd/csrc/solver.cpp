@@ -1,0 +1,270 @@
+// Host orchestration of the V-cycle and the outer Krylov loops.
+//
+// The outer loop keeps all its scalars (alpha, beta, norms, the convergence flag) in device
+// memory, so one iteration is a fixed sequence of launches with fixed arguments.  It is
+// captured once as a hipGraph per (hierarchy, method, cycle shape) and replayed; the host
+// enqueues `check_every` replays, then reads the flag.  Replays after convergence cost one
+// flag read per kernel.
+#include <algorithm>
+#include <cstring>
+#include <stdexcept>
+
+#include "hier.hpp"
+#include "solver.hpp"
+#include "util.hpp"
+
+namespace decmg {
+
+template <>
+LevelVecs<double>& vecs<double>(Level& L) { return L.v64; }
+template <>
+LevelVecs<float>& vecs<float>(Level& L) { return L.v32; }
+
+template <typename T>
+T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const int* done,
+          hipStream_t s) {
+  Level& L = *H.lv[l];
+  LevelVecs<T>& V = vecs<T>(L);
+  if (l == 0) {
+    k::coarse<T>(H, b, V.x, done, s);
+    return V.x;
+  }
+  T *cur, *oth;
+  int pre = o.nu1;
+  if (!x_init) {
+    cur = V.x;
+    oth = V.t;
+    if (pre > 0) {
+      k::jacobi_zero<T>(L, b, cur, o.omega, done, s);
+      --pre;
+    } else {
+      k::fill<T>(cur, L.n, T(0), s);
+    }
+  } else {
+    cur = x_init;
+    oth = (x_init == V.t) ? V.x : V.t;
+  }
+  for (; pre > 0; --pre) {
+    k::jacobi<T>(L, cur, b, oth, o.omega, done, s);
+    std::swap(cur, oth);
+  }
+  Level& C = *H.lv[l - 1];
+  k::residual<T>(L, cur, b, V.r, done, s);
+  k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+  T* ec = vcycle<T>(H, l - 1, vecs<T>(C).b, nullptr, o, done, s);
+  k::prolong<T>(L, C, ec, cur, done, s);
+  for (int i = 0; i < o.nu2; ++i) {
+    k::jacobi<T>(L, cur, b, oth, o.omega, done, s);
+    std::swap(cur, oth);
+  }
+  return cur;
+}
+
+template double* vcycle<double>(Hierarchy&, int, const double*, double*, const mg_opts&,
+                                const int*, hipStream_t);
+template float* vcycle<float>(Hierarchy&, int, const float*, float*, const mg_opts&, const int*,
+                              hipStream_t);
+
+namespace {
+
+void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, double extra = 0.0) {
+  k::finalize(op, k::blocks_for(n), H.part, two ? H.part + H.part_cap : nullptr, H.scal, extra, s);
+}
+
+// One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).
+void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
+  Level& F = *H.lv.back();
+  const int32_t n = F.n;
+  const int top = int(H.lv.size()) - 1;
+  const bool natural = H.bc == MG_BC_NATURAL;
+  const int* done = &H.scal->done;
+  double* P0 = H.part;
+  double* P1 = H.part + H.part_cap;
+  const double* other = (o.outer == MG_OUTER_FCG) ? H.sq : H.sr;
+  double* z;
+  if (o.precision == MG_F32) {
+    float* z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s);
+    if (natural) {
+      k::sum32(n, z32, H.scal, P0, done, s);
+      fin(H, k::FIN_MEAN, n, false, s);
+    }
+    k::zconv_dot(n, H.scal, z32, H.sz, other, P0, natural ? 1 : 0, done, s);
+    z = H.sz;
+  } else {
+    z = vcycle<double>(H, top, H.sr, nullptr, o, done, s);
+    if (natural) {
+      k::sum64(n, z, P0, done, s);
+      fin(H, k::FIN_MEAN, n, false, s);
+    }
+    k::zsub_dot(n, H.scal, z, other, P0, natural ? 1 : 0, done, s);
+  }
+  float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
+  if (o.outer == MG_OUTER_IR) {
+    k::axpy1(n, z, H.sx, done, s);
+    k::residual_norm(F, H.sx, H.sb, H.sr, r32, H.scal, P0, done, s);
+    fin(H, k::FIN_CHECK, n, false, s);
+    return;
+  }
+  fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
+  k::pupdate(n, H.scal, z, H.sp, done, s);
+  k::spmv_dot2(F, H.sp, H.sq, H.sr, P0, P1, done, s);
+  fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s);
+  k::update_xr(n, H.scal, H.sp, H.sq, H.sx, H.sr, r32, P0, done, s);
+  fin(H, k::FIN_CHECK, n, false, s);
+}
+
+// One stand-alone V-cycle iteration (mg_solve): x <- V(b, x); r = b - A x; check.
+void enqueue_cycle(Hierarchy& H, const mg_opts& o, hipStream_t s) {
+  Level& F = *H.lv.back();
+  const int top = int(H.lv.size()) - 1;
+  const int* done = &H.scal->done;
+  // with an even number of sweeps per cycle the ping-pong ends in H.sx (checked by run_mg)
+  (void)vcycle<double>(H, top, H.sb, H.sx, o, done, s);
+  k::residual_norm(F, H.sx, H.sb, H.sr, nullptr, H.scal, H.part, done, s);
+  fin(H, k::FIN_CHECK, F.n, false, s);
+}
+
+hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
+  auto key = std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2, 0, o.omega);
+  auto it = H.graphs.find(key);
+  if (it != H.graphs.end()) return it->second;
+  hipGraph_t g = nullptr;
+  check_hip(hipStreamBeginCapture(H.capture_stream, hipStreamCaptureModeThreadLocal),
+            "hipStreamBeginCapture");
+  if (kind == 0)
+    enqueue_iteration(H, o, H.capture_stream);
+  else
+    enqueue_cycle(H, o, H.capture_stream);
+  check_hip(hipStreamEndCapture(H.capture_stream, &g), "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  check_hip(e, "hipGraphInstantiate");
+  H.graphs[key] = ex;
+  return ex;
+}
+
+void init_scalars(Hierarchy& H, const mg_opts& o, hipStream_t s) {
+  DevScalars& h = *H.scal_host;
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  std::memset(&h, 0, sizeof(DevScalars));
+  h.rho = 1.0;
+  h.pq = 1.0;
+  h.scale = 1.0;
+  h.inv_scale = 1.0;
+  h.rtol = o.rtol;
+  h.max_iter = o.max_iter;
+  h.n_unknowns = double(H.lv.back()->n);
+  check_hip(hipMemcpyAsync(H.scal, &h, sizeof(DevScalars), hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+}
+
+void read_scalars(Hierarchy& H, hipStream_t s) {
+  check_hip(hipMemcpyAsync(H.scal_host, H.scal, sizeof(DevScalars), hipMemcpyDeviceToHost, s),
+            "hipMemcpyAsync");
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  check_hip(hipGetLastError(), "kernel launch");
+}
+
+// b (natural, nv) -> H.sb (internal); ||b|| with the boundary part; projected for natural.
+void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s) {
+  Level& F = *H.lv.back();
+  const int32_t n = F.n;
+  k::gather<double>(F.perm, n, b_nat, H.sb, s);
+  if (H.bc == MG_BC_NATURAL) {
+    k::sum64(n, H.sb, H.part, nullptr, s);
+    fin(H, k::FIN_MEAN, n, false, s);
+    k::sub_mean(n, H.scal, H.sb, s);
+    k::dot(n, H.sb, H.sb, H.part, nullptr, s);
+    fin(H, k::FIN_BNORM, n, false, s);
+  } else {
+    k::dot(F.nv, b_nat, b_nat, H.part, nullptr, s);
+    fin(H, k::FIN_BNORM, F.nv, false, s);
+  }
+}
+
+// Final projection, true residual, scatter to the caller's numbering.
+void finish(Hierarchy& H, const double* b_nat, double* x_nat, mg_result* res, hipStream_t s) {
+  Level& F = *H.lv.back();
+  const int32_t n = F.n;
+  read_scalars(H, s);
+  const DevScalars loop = *H.scal_host;
+  // exit bookkeeping runs whatever the convergence flag says
+  DevScalars& h = *H.scal_host;
+  h.done = 0;
+  check_hip(hipMemcpyAsync(&H.scal->done, &h.done, sizeof(int32_t), hipMemcpyHostToDevice, s),
+            "hipMemcpyAsync");
+  if (H.bc == MG_BC_NATURAL) {
+    k::sum64(n, H.sx, H.part, nullptr, s);
+    fin(H, k::FIN_MEAN, n, false, s);
+    k::sub_mean(n, H.scal, H.sx, s);
+  }
+  k::residual_norm(F, H.sx, H.sb, H.sz, nullptr, H.scal, H.part, nullptr, s);
+  fin(H, k::FIN_RNORM, n, false, s);
+  k::scatter<double>(F.perm, n, H.sx, x_nat, s);
+  k::bnd_copy<double>(F.bnd_ids, int32_t(F.bnd_h.size()), b_nat, x_nat, s);
+  read_scalars(H, s);
+  if (res) {
+    res->iterations = loop.iters;
+    res->status = loop.status;
+    res->rel_residual_loop = loop.bnorm > 0 ? loop.rnorm / loop.bnorm : 0.0;
+    res->rel_residual = loop.bnorm > 0 ? H.scal_host->rnorm / loop.bnorm : 0.0;
+  }
+  H.scal_host->status = loop.status;
+}
+
+}  // namespace
+
+int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
+            hipStream_t s) {
+  Level& F = *H.lv.back();
+  const int32_t n = F.n;
+  init_scalars(H, o, s);
+  setup_rhs(H, b_nat, s);
+  k::fill<double>(H.sx, n, 0.0, s);
+  k::fill<double>(H.sp, n, 0.0, s);
+  k::fill<double>(H.sq, n, 0.0, s);
+  check_hip(hipMemcpyAsync(H.sr, H.sb, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
+            "hipMemcpyAsync");
+  if (o.precision == MG_F32) k::to_f32(n, H.scal, H.sr, F.v32.b, nullptr, s);
+  hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 0) : nullptr;
+  const int every = std::max(1, o.check_every);
+  for (int it = 0; it < o.max_iter; it += every) {
+    for (int j = 0; j < every; ++j) {
+      if (g)
+        check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
+      else
+        enqueue_iteration(H, o, s);
+    }
+    read_scalars(H, s);
+    if (H.scal_host->done) break;
+  }
+  finish(H, b_nat, x_nat, res, s);
+  return H.scal_host->status;
+}
+
+int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
+           hipStream_t s) {
+  Level& F = *H.lv.back();
+  if ((o.nu1 + o.nu2) % 2 != 0)
+    throw std::invalid_argument("mg_solve needs an even number of smoothing sweeps per cycle");
+  init_scalars(H, o, s);
+  setup_rhs(H, b_nat, s);
+  k::fill<double>(H.sx, F.n, 0.0, s);
+  hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 1) : nullptr;
+  const int every = std::max(1, o.check_every);
+  for (int it = 0; it < o.max_iter; it += every) {
+    for (int j = 0; j < every; ++j) {
+      if (g)
+        check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
+      else
+        enqueue_cycle(H, o, s);
+    }
+    read_scalars(H, s);
+    if (H.scal_host->done) break;
+  }
+  finish(H, b_nat, x_nat, res, s);
+  return H.scal_host->status;
+}
+
+}  // namespace decmg

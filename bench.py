@@ -30,7 +30,33 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--profile-kernels", action="store_true",
+                   help="only launch the finest-level kernels (and a plain copy of known size "
+                        "that calibrates the HBM counters) a few times each, for rocprofv3 --pmc")
     return p.parse_args()
+
+
+def profile_kernels(reps=5):
+    """Short program for counter runs: C3 finest-level sweeps/applies and a 256 MiB copy."""
+    import torch
+
+    import paper_2508_12501_amd as mg
+    import workloads as W
+    H = mg.Hierarchy("square", W.C3["nsub"], base_cells=W.C3["base_cells"])
+    top = H.top
+    src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")   # 256 MiB
+    dst = torch.empty_like(src)
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    for kern, dt in ((mg.KERNEL_JACOBI, mg.MG_F32), (mg.KERNEL_JACOBI, mg.MG_F64),
+                     (mg.KERNEL_APPLY, mg.MG_F64), (mg.KERNEL_RESTRICT, mg.MG_F32),
+                     (mg.KERNEL_PROLONG, mg.MG_F32)):
+        ms = mg.mg_time_kernel(H.h, kern, top, dt, reps)
+        print(f"[profile] kernel {kern} dtype {dt}: {ms:.4f} ms/launch", file=sys.stderr, flush=True)
+    info = H.info[top]
+    print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
+                      "n_unknowns": info["n_unknowns"], "nnz_operator": info["nnz_operator"]}))
 
 
 def kernel_bytes(info, dtype_bytes, kind):
@@ -72,6 +98,9 @@ def cpu_baseline(b_nat_np, rtol):
 
 def main():
     a = parse()
+    if a.profile_kernels:
+        profile_kernels()
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": a.gpus}))

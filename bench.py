@@ -30,6 +30,12 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--kernel-reps", type=int, default=50)
+    p.add_argument("--probe-steps", type=int, default=3,
+                   help="eager solves during which the finest-level FP32 sweeps are timed with "
+                        "hipEvents (the roofline figure)")
+    p.add_argument("--isolated", action="store_true",
+                   help="also time back-to-back launches of single kernels (warm caches)")
+    p.add_argument("--order", choices=["stripes", "morton"], default="stripes")
     p.add_argument("--profile-kernels", action="store_true",
                    help="only launch the finest-level kernels (and a plain copy of known size "
                         "that calibrates the HBM counters) a few times each, for rocprofv3 --pmc")
@@ -60,13 +66,14 @@ def profile_kernels(reps=5):
 
 
 def kernel_bytes(info, dtype_bytes, kind):
-    """Algorithmic bytes of one launch on a level: each stored coupling read once (int32
-    column + weight), each vector entry read or written once, gathers at perfect reuse."""
-    n, nnz = info["n_unknowns"], info["nnz_operator"]
+    """Algorithmic bytes of one launch on a level: each stored coupling read once (column
+    index of the level's width + weight), each vector entry read or written once, gathers at
+    perfect reuse."""
+    n, nnz, ib = info["n_unknowns"], info["nnz_operator"], info["index_bytes"]
     if kind == "jacobi":      # col + w per coupling; x, b read, x' written
-        return nnz * (4 + dtype_bytes) + n * 3 * dtype_bytes
+        return nnz * (ib + dtype_bytes) + n * 3 * dtype_bytes
     if kind == "spmv":        # col + w per coupling; x read, y written
-        return nnz * (4 + dtype_bytes) + n * 2 * dtype_bytes
+        return nnz * (ib + dtype_bytes) + n * 2 * dtype_bytes
     raise ValueError(kind)
 
 
@@ -114,7 +121,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.perf_counter()
-    H = mg.Hierarchy("square", W.C3["nsub"], base_cells=W.C3["base_cells"])
+    order = mg.MG_ORDER_MORTON if a.order == "morton" else mg.MG_ORDER_STRIPES
+    H = mg.Hierarchy("square", W.C3["nsub"], base_cells=W.C3["base_cells"], order=order)
     t_hier = time.perf_counter() - t0
     top = H.top
     info = H.info[top]
@@ -161,15 +169,34 @@ def main():
     value = unknowns / (total_m / a.steps)
     value_fp64 = unknowns / (total_d / n64)
 
-    # dominant kernel: the FP32 Jacobi sweep on the finest level
-    ms_j32 = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, mg.MG_F32, a.kernel_reps)
-    ms_j64 = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, mg.MG_F64, a.kernel_reps)
-    ms_a64 = mg.mg_time_kernel(H.h, mg.KERNEL_APPLY, top, mg.MG_F64, a.kernel_reps)
+    # dominant kernel: the FP32 Jacobi sweep on the finest level, timed with hipEvents on the
+    # solve's stream around each of its launches inside eager (non-graph) mixed solves
+    eager = mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32, rtol=rtol, use_graph=0)
+    mg.mg_probe_begin(H.h, top, mg.MG_F32)
+    t_eager = []
+    for _ in range(a.probe_steps):
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mg.mg_pcg(H.h, eager, b, x)
+        torch.cuda.synchronize()
+        t_eager.append(time.perf_counter() - t)
+    ms_j32, n_probe = mg.mg_probe_end(H.h)
     by_j32 = kernel_bytes(info, 4, "jacobi")
-    by_j64 = kernel_bytes(info, 8, "jacobi")
-    by_a64 = kernel_bytes(info, 8, "spmv")
     gbs = lambda by, ms: by / (ms * 1e-3) / 1e9
     achieved = gbs(by_j32, ms_j32)
+    print(f"[bench] probe: {n_probe} finest-level FP32 sweeps in {a.probe_steps} eager solves, "
+          f"{1e3 * ms_j32:.2f} us each, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    others = {}
+    if a.isolated:
+        by_j64 = kernel_bytes(info, 8, "jacobi")
+        by_a64 = kernel_bytes(info, 8, "spmv")
+        ms_w32 = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, mg.MG_F32, a.kernel_reps)
+        ms_j64 = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, mg.MG_F64, a.kernel_reps)
+        ms_a64 = mg.mg_time_kernel(H.h, mg.KERNEL_APPLY, top, mg.MG_F64, a.kernel_reps)
+        others = {"isolated_warm_jacobi_f32": {"GB/s": gbs(by_j32, ms_w32), "ms": ms_w32},
+                  "isolated_warm_jacobi_f64": {"GB/s": gbs(by_j64, ms_j64), "ms": ms_j64, "bytes": by_j64},
+                  "isolated_warm_apply_f64": {"GB/s": gbs(by_a64, ms_a64), "ms": ms_a64, "bytes": by_a64}}
 
     out = {
         "metric": "MG solve DOF/s to 1e-10 rel residual: FP32-precond+FP64-refine vs FP64",
@@ -190,6 +217,7 @@ def main():
                         "FCG(FP64) + FP32 V(2,2) Jacobi(0.8) preconditioner to 1e-10",
             "unknowns": unknowns,
             "levels": H.n_levels,
+            "order": a.order,
         },
         "mixed": {"iterations": res_m.iterations, "rel_residual": res_m.rel_residual,
                   "ms_median": 1e3 * float(np.median(times_m))},
@@ -198,7 +226,8 @@ def main():
         "speedup_mixed_vs_fp64": value / value_fp64,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_rows<float,2> (FP32 Jacobi sweep, finest level)",
+            "kernel": "k_rows<float, 2, %s> (FP32 weighted-Jacobi sweep, finest level)"
+                      % ("true" if info["index_bytes"] == 2 else "false"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -206,10 +235,10 @@ def main():
             "traffic": None,
             "bytes_per_launch": by_j32,
             "ms_per_launch": ms_j32,
-            "others": {
-                "jacobi_f64": {"GB/s": gbs(by_j64, ms_j64), "ms": ms_j64, "bytes": by_j64},
-                "apply_f64": {"GB/s": gbs(by_a64, ms_a64), "ms": ms_a64, "bytes": by_a64},
-            },
+            "launches_timed": n_probe,
+            "timed_in": f"{a.probe_steps} eager mixed solves (hipEvents on the solve stream)",
+            "eager_solve_ms_median": 1e3 * float(np.median(t_eager)),
+            "others": others,
         },
     }
     if not a.no_cpu_baseline:

@@ -55,6 +55,11 @@ typedef enum {
 enum { MG_F64 = 0, MG_F32 = 1 };
 enum { MG_BC_DIRICHLET0 = 0, MG_BC_NATURAL = 1 };
 enum { MG_OUTER_CG = 0, MG_OUTER_FCG = 1, MG_OUTER_IR = 2 };
+/* Internal (device) order of a level's unknowns.  Results do not depend on it beyond
+ * summation order; it only changes memory locality.  STRIPES: strips one median edge length
+ * wide across the axis of largest extent, sorted along the second axis (row-major on grids);
+ * MORTON: Z-order of the coordinates. */
+enum { MG_ORDER_STRIPES = 0, MG_ORDER_MORTON = 1 };
 
 typedef struct dec_mesh dec_mesh;
 typedef struct mg_hierarchy mg_hierarchy;
@@ -91,7 +96,7 @@ typedef struct {
   int32_t n_subdiv;
   int32_t project_sphere;
   int32_t bc;      /* MG_BC_DIRICHLET0 (boundary vertices fixed at 0) or MG_BC_NATURAL */
-  int32_t reserved;
+  int32_t order;   /* internal order of the unknowns: MG_ORDER_STRIPES (0) or MG_ORDER_MORTON */
 } mg_hier_opts;
 
 mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, void* stream,
@@ -104,6 +109,8 @@ typedef struct {
   int64_t nv, ne, nt;
   int64_t n_unknowns;    /* interior vertices (Dirichlet) or all vertices (natural) */
   int64_t nnz_operator;  /* stored off-diagonal entries of the device operator */
+  int32_t index_bytes;   /* bytes per stored column index of the device operator (2 or 4) */
+  int32_t reserved;
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 
@@ -186,6 +193,14 @@ mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
  * 4 = interpolation.  Uses the hierarchy's own work vectors. */
 mg_status mg_time_kernel(mg_hierarchy* h, int32_t kernel, int32_t level, int32_t dtype,
                          int32_t reps, void* stream, double* ms_per_launch);
+
+/* In-solve timing of the smoother.  Between mg_probe_begin and mg_probe_end, every weighted-
+ * Jacobi sweep kernel that an eager solve (use_graph = 0) launches on `level` in arithmetic
+ * `dtype` is bracketed by hipEvents on the solve's stream.  mg_probe_end synchronises that
+ * stream and returns the mean duration per launch and the number of launches.  Sweeps replayed
+ * from a captured graph are not probed. */
+mg_status mg_probe_begin(mg_hierarchy* h, int32_t level, int32_t dtype);
+mg_status mg_probe_end(mg_hierarchy* h, double* ms_per_launch, int32_t* launches);
 
 #ifdef __cplusplus
 }

@@ -27,6 +27,7 @@ STATUS_NAMES = ["MG_OK", "MG_EINVAL", "MG_ENOMEM", "MG_EDEVICE", "MG_ENOCONV", "
 MG_F64, MG_F32 = 0, 1
 MG_BC_DIRICHLET0, MG_BC_NATURAL = 0, 1
 MG_OUTER_CG, MG_OUTER_FCG, MG_OUTER_IR = 0, 1, 2
+MG_ORDER_STRIPES, MG_ORDER_MORTON = 0, 1
 KERNEL_JACOBI, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
 
 
@@ -44,13 +45,14 @@ class MGError(RuntimeError):
 
 class mg_hier_opts(ctypes.Structure):
     _fields_ = [("n_subdiv", ctypes.c_int32), ("project_sphere", ctypes.c_int32),
-                ("bc", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bc", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class mg_level_info(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("level", ctypes.c_int32),
                 ("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nt", ctypes.c_int64),
-                ("n_unknowns", ctypes.c_int64), ("nnz_operator", ctypes.c_int64)]
+                ("n_unknowns", ctypes.c_int64), ("nnz_operator", ctypes.c_int64),
+                ("index_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class mg_opts(ctypes.Structure):
@@ -95,6 +97,8 @@ _PROTOS = {
     "mg_solve": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
     "mg_pcg": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
     "mg_time_kernel": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_d)]),
+    "mg_probe_begin": (_i32, [_vp, _i32, _i32]),
+    "mg_probe_end": (_i32, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
 }
 
 _LIB = None
@@ -188,8 +192,8 @@ def dec_mesh_free(m):
 
 # ----------------------------------------------------------------- hierarchy
 def mg_hierarchy_build(mesh, n_subdiv: int, project_sphere: bool = False,
-                       bc: int = MG_BC_DIRICHLET0, stream=None):
-    o = mg_hier_opts(int(n_subdiv), int(bool(project_sphere)), int(bc), 0)
+                       bc: int = MG_BC_DIRICHLET0, stream=None, order: int = MG_ORDER_STRIPES):
+    o = mg_hier_opts(int(n_subdiv), int(bool(project_sphere)), int(bc), int(order))
     out = _vp()
     _check(lib().mg_hierarchy_build(mesh, ctypes.byref(o), _stream(stream), ctypes.byref(out)))
     return out
@@ -314,11 +318,24 @@ def mg_time_kernel(h, kernel: int, level: int, dtype: int, reps: int, stream=Non
     return ms.value
 
 
+def mg_probe_begin(h, level: int, dtype: int):
+    _check(lib().mg_probe_begin(h, int(level), int(dtype)))
+
+
+def mg_probe_end(h):
+    """Returns (mean ms per probed sweep launch, number of launches)."""
+    ms = ctypes.c_double()
+    n = ctypes.c_int32()
+    _check(lib().mg_probe_end(h, ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
+
+
 # ----------------------------------------------------------------- convenience
 class Hierarchy:
     """Owns a mesh and a hierarchy handle; frees both when closed or collected."""
 
-    def __init__(self, kind: str, n_subdiv: int, base_cells: int = 4, bc=None, xyz=None, tri=None):
+    def __init__(self, kind: str, n_subdiv: int, base_cells: int = 4, bc=None, xyz=None, tri=None,
+                 order: int = MG_ORDER_STRIPES):
         if kind == "square":
             self.mesh = dec_mesh_square_grid(base_cells)
             bc = MG_BC_DIRICHLET0 if bc is None else bc
@@ -334,7 +351,7 @@ class Hierarchy:
         else:
             raise ValueError(kind)
         self.bc = bc
-        self.h = mg_hierarchy_build(self.mesh, n_subdiv, project, bc)
+        self.h = mg_hierarchy_build(self.mesh, n_subdiv, project, bc, order=order)
         self.n_levels = mg_hierarchy_info(self.h, 0)["n_levels"]
         self.top = self.n_levels - 1
         self.info = [mg_hierarchy_info(self.h, l) for l in range(self.n_levels)]

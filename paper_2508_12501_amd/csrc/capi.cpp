@@ -217,6 +217,8 @@ mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, voi
   if (opts->n_subdiv < 0 || opts->n_subdiv > 12) return fail(MG_EINVAL, "n_subdiv must be in 0..12");
   if (opts->bc != MG_BC_DIRICHLET0 && opts->bc != MG_BC_NATURAL)
     return fail(MG_EINVAL, "bc must be MG_BC_DIRICHLET0 or MG_BC_NATURAL");
+  if (opts->order != MG_ORDER_STRIPES && opts->order != MG_ORDER_MORTON)
+    return fail(MG_EINVAL, "order must be MG_ORDER_STRIPES or MG_ORDER_MORTON");
   const double growth = std::pow(4.0, opts->n_subdiv);
   if (double(base->m.nt) * growth > double(int64_t(1) << 30))
     return fail(MG_EINVAL, "finest level would exceed 2^30 triangles");
@@ -242,6 +244,8 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   int64_t nnz = 0;
   for (int32_t e : L.entry_edge) nnz += (e >= 0);
   out->nnz_operator = nnz;
+  out->index_bytes = L.op.col16 ? 2 : 4;
+  out->reserved = 0;
   return MG_OK;
 }
 
@@ -459,6 +463,44 @@ mg_status mg_time_kernel(mg_hierarchy* h, int32_t kernel, int32_t level, int32_t
   (void)hipEventDestroy(e1);
   check_hip(hipGetLastError(), "kernel launch");
   *ms_per_launch = double(ms) / reps;
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_probe_begin(mg_hierarchy* h, int32_t level, int32_t dtype) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (mg_status st = check_dtype(dtype); st != MG_OK) return st;
+  decmg::Hierarchy::Probe& P = h->h->probe;
+  for (auto& e : P.ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  P.ev.clear();
+  P.on = true;
+  P.level = level;
+  P.dtype = dtype;
+  P.stream = nullptr;
+  return MG_OK;
+}
+
+mg_status mg_probe_end(mg_hierarchy* h, double* ms_per_launch, int32_t* launches) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  API_BEGIN
+  decmg::Hierarchy::Probe& P = h->h->probe;
+  P.on = false;
+  double total = 0.0;
+  if (!P.ev.empty()) decmg::check_hip(hipStreamSynchronize(P.stream), "hipStreamSynchronize");
+  for (auto& e : P.ev) {
+    float ms = 0.f;
+    decmg::check_hip(hipEventElapsedTime(&ms, e.first, e.second), "hipEventElapsedTime");
+    total += ms;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  const int32_t n = int32_t(P.ev.size());
+  P.ev.clear();
+  if (launches) *launches = n;
+  if (ms_per_launch) *ms_per_launch = n ? total / n : 0.0;
   API_END
   return MG_OK;
 }

@@ -23,15 +23,22 @@ namespace decmg {
 constexpr int kSlice = 64;    // SELL slice height: one wavefront, one row per lane
 constexpr int kBlock = 256;   // threads per row-parallel workgroup (4 wavefronts)
 constexpr int kMaxCoarse = 2048;  // largest coarsest level solved densely
+constexpr int kRedBlocks = 2048;  // cap on workgroups (and partial sums) of a reduction
 
 // Operator in sliced ELLPACK (SELL-64): slice s covers internal rows 64s..64s+63 and owns
 // columns sptr[s]..sptr[s+1]-1; entry k of lane l sits at [k*64 + l].  The same column
 // array serves the FP64 and FP32 weights.  Exact zero couplings (star1 = 0, the diagonals
 // of right-triangle grids) are dropped; they contribute nothing to L x.
+constexpr int kZeroSlot16 = -32768;  // 16-bit column offset that stands for the zero slot
+constexpr int kUnroll = 8;           // rows up to this many entries take the batched-load path
+
 struct DevOperator {
   int32_t nslices = 0, ncols = 0;
   int32_t* sptr = nullptr;
   int32_t* col = nullptr;
+  // The same columns as offsets from the row (kZeroSlot16 = zero slot), when every offset of
+  // the level fits in 16 bits; the row kernels then read half the index bytes.
+  int16_t* col16 = nullptr;
   double* w64 = nullptr;
   float* w32 = nullptr;
   double* diag64 = nullptr;   // sum of the row's weights, in SELL order
@@ -45,6 +52,24 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t nslices = 0, ncols = 0;
   int32_t* r_sptr = nullptr;  // SELL over coarse rows of the fine midpoints (weight 1/2)
   int32_t* r_col = nullptr;
+};
+
+constexpr int kCoarseThreads = 1024;       // workgroup of the fused coarse cycle
+constexpr int kCoarseLdsBytes = 64 * 1024; // LDS budget of the fused coarse cycle
+
+// Per-level descriptor of the fused coarse cycle (device copy per precision).
+template <typename T>
+struct CoarseLevel {
+  int32_t n = 0, lds = 0;            // unknowns; offset (in T) of x, partner, b in LDS
+  const int32_t* sptr = nullptr;
+  const int32_t* col = nullptr;
+  const T* w = nullptr;
+  const T* diag = nullptr;
+  const int32_t* pa = nullptr;       // interpolation from level-1
+  const int32_t* pb = nullptr;
+  const int32_t* r_self = nullptr;   // restriction into level-1
+  const int32_t* r_sptr = nullptr;
+  const int32_t* r_col = nullptr;
 };
 
 template <typename T>
@@ -94,20 +119,50 @@ struct Hierarchy {
   DevScalars* scal_host = nullptr; // pinned
   hipStream_t capture_stream = nullptr;
   std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
+  std::map<std::tuple<int, int, int, int, double>, int> last_iters;
+  // fused coarse cycle: highest level handled by one workgroup, per precision (-1 = none)
+  int ctop64 = -1, ctop32 = -1;
+  CoarseLevel<double>* clv64 = nullptr;
+  CoarseLevel<float>* clv32 = nullptr;
+  std::vector<int32_t> clds64, clds32;   // LDS offsets (in elements) per level
+  // in-solve timing probe of the smoothing sweeps (eager launches only)
+  struct Probe {
+    bool on = false;
+    int level = -1, dtype = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    hipStream_t stream = nullptr;
+  } probe;
+  bool capturing = false;
   ~Hierarchy();
 };
 
 // ----------------------------------------------------------------- kernel launchers
 // All take internal-order vectors; `done` (nullable) makes a launch a no-op once a solver
 // has converged, so speculative iterations cost one flag read.
+template <typename T> const CoarseLevel<T>* coarse_levels(const Hierarchy& H);
+template <> inline const CoarseLevel<double>* coarse_levels<double>(const Hierarchy& H) { return H.clv64; }
+template <> inline const CoarseLevel<float>* coarse_levels<float>(const Hierarchy& H) { return H.clv32; }
+template <typename T> int coarse_top(const Hierarchy& H);
+template <> inline int coarse_top<double>(const Hierarchy& H) { return H.ctop64; }
+template <> inline int coarse_top<float>(const Hierarchy& H) { return H.ctop32; }
+template <typename T> size_t coarse_lds_bytes(const Hierarchy& H, int top);
+template <> inline size_t coarse_lds_bytes<double>(const Hierarchy& H, int top) {
+  return size_t(H.clds64[top] + 3 * (H.lv[top]->n + 1)) * sizeof(double);
+}
+template <> inline size_t coarse_lds_bytes<float>(const Hierarchy& H, int top) {
+  return size_t(H.clds32[top] + 3 * (H.lv[top]->n + 1)) * sizeof(float);
+}
+
 namespace k {
 template <typename T> void spmv(const Level& L, const T* x, T* y, const int* done, hipStream_t s);
 template <typename T> void residual(const Level& L, const T* x, const T* b, T* r, const int* done, hipStream_t s);
 template <typename T> void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s);
+template <typename T> void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done, hipStream_t s);
 template <typename T> void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done, hipStream_t s);
 template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);
+template <typename T> void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2, const int* done, hipStream_t s);
 template <typename T> void fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T> void gather(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);
 template <typename T> void scatter(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);
@@ -118,6 +173,7 @@ void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t
 
 // Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
 int blocks_for(int32_t n);
+int red_blocks(int32_t n);   // grid (= number of partials) of the reduction kernels
 void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, const int* done, hipStream_t s);
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
@@ -132,6 +188,10 @@ void zconv_dot(int32_t n, const DevScalars* sc, const float* z32, double* z, con
 void zsub_dot(int32_t n, const DevScalars* sc, double* z, const double* o, double* part0,
               int sub_mean_flag, const int* done, hipStream_t s);
 void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s);
+void zdot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, double* part0,
+            int sub_mean_flag, const int* done, hipStream_t s);
+void pupd32(int32_t n, const DevScalars* sc, const float* z32, double* p, int sub_mean_flag,
+            const int* done, hipStream_t s);
 void dot(int32_t n, const double* a, const double* b, double* part0, const int* done, hipStream_t s);
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s);
 void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const int* done, hipStream_t s);

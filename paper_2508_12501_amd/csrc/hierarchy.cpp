@@ -24,9 +24,13 @@ uint64_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return m;
 }
 
-// Internal order of the unknowns: Z-order of the coordinates quantised on a 2^20 grid of the
-// level's bounding box (grid spacings that are powers of two land on whole cells).
-void order_level(Level& L, int bc) {
+// Internal order of the unknowns.  MORTON: Z-order of the coordinates quantised on a 2^20
+// grid of the level's bounding box.  STRIPES: strips one median edge length wide across the
+// axis of largest extent, each sorted along the second axis; on a grid this is row-major
+// order, so a wavefront's 64 rows are 64 consecutive vertices of one grid row and the
+// neighbours in the adjacent rows are consecutive too.  Both orders nest across levels
+// (coordinates are kept by subdivision), and the stripes order keeps neighbour offsets small.
+void order_level(Level& L, int bc, int order) {
   const Mesh& m = L.mesh;
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t v = 0; v < m.nv; ++v)
@@ -34,29 +38,63 @@ void order_level(Level& L, int bc) {
       lo[c] = std::min(lo[c], m.xyz[3 * v + c]);
       hi[c] = std::max(hi[c], m.xyz[3 * v + c]);
     }
-  std::vector<std::pair<uint64_t, int32_t>> keys;
-  keys.reserve(m.nv);
   L.bnd_h.clear();
+  std::vector<int32_t> unk;
+  unk.reserve(m.nv);
   for (int64_t v = 0; v < m.nv; ++v) {
-    if (bc == MG_BC_DIRICHLET0 && m.bnd[v]) {
+    if (bc == MG_BC_DIRICHLET0 && m.bnd[v])
       L.bnd_h.push_back(int32_t(v));
-      continue;
-    }
-    uint32_t q[3];
-    for (int c = 0; c < 3; ++c) {
-      const double span = hi[c] - lo[c];
-      q[c] = span > 0 ? uint32_t(std::floor((m.xyz[3 * v + c] - lo[c]) / span * 1048576.0)) : 0u;
-    }
-    keys.emplace_back(morton3(q[0], q[1], q[2]), int32_t(v));
+    else
+      unk.push_back(int32_t(v));
   }
-  std::sort(keys.begin(), keys.end());
-  L.n = int32_t(keys.size());
-  L.perm_h.resize(L.n);
+  if (order == MG_ORDER_MORTON) {
+    std::vector<std::pair<uint64_t, int32_t>> keys;
+    keys.reserve(unk.size());
+    for (int32_t v : unk) {
+      uint32_t q[3];
+      for (int c = 0; c < 3; ++c) {
+        const double span = hi[c] - lo[c];
+        q[c] = span > 0 ? uint32_t(std::floor((m.xyz[3 * v + c] - lo[c]) / span * 1048576.0)) : 0u;
+      }
+      keys.emplace_back(morton3(q[0], q[1], q[2]), v);
+    }
+    std::sort(keys.begin(), keys.end());
+    for (size_t k = 0; k < keys.size(); ++k) unk[k] = keys[k].second;
+  } else {
+    int ax[3] = {0, 1, 2};
+    std::stable_sort(ax, ax + 3, [&](int a, int b) { return hi[a] - lo[a] > hi[b] - lo[b]; });
+    std::vector<double> len(m.ne);
+    for (int64_t e = 0; e < m.ne; ++e) {
+      const double* a = &m.xyz[3 * m.edge[2 * e]];
+      const double* b = &m.xyz[3 * m.edge[2 * e + 1]];
+      len[e] = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) +
+                         (b[2] - a[2]) * (b[2] - a[2]));
+    }
+    std::nth_element(len.begin(), len.begin() + len.size() / 2, len.end());
+    const double h = len.empty() ? 1.0 : len[len.size() / 2];
+    struct Key {
+      int64_t strip;
+      double b, c;
+      int32_t v;
+    };
+    std::vector<Key> keys;
+    keys.reserve(unk.size());
+    for (int32_t v : unk) {
+      const double* p = &m.xyz[3 * v];
+      keys.push_back({int64_t(std::floor((p[ax[0]] - lo[ax[0]]) / h + 0.5)), p[ax[1]], p[ax[2]], v});
+    }
+    std::sort(keys.begin(), keys.end(), [](const Key& a, const Key& b) {
+      if (a.strip != b.strip) return a.strip < b.strip;
+      if (a.b != b.b) return a.b < b.b;
+      if (a.c != b.c) return a.c < b.c;
+      return a.v < b.v;
+    });
+    for (size_t k = 0; k < keys.size(); ++k) unk[k] = keys[k].v;
+  }
+  L.n = int32_t(unk.size());
+  L.perm_h = unk;
   L.inv_h.assign(m.nv, -1);
-  for (int32_t k = 0; k < L.n; ++k) {
-    L.perm_h[k] = keys[k].second;
-    L.inv_h[keys[k].second] = k;
-  }
+  for (int32_t k = 0; k < L.n; ++k) L.inv_h[L.perm_h[k]] = k;
 }
 
 // Vertex -> incident edges (all edges, CSR).
@@ -136,6 +174,23 @@ void build_operator_structure(Level& L, std::vector<int32_t>& col) {
   L.op.ncols = L.sptr_h[nslices];
 }
 
+// 16-bit offsets col - row, with kZeroSlot16 for the zero slot; false if any offset does not
+// fit in [-32767, 32767].
+bool delta16(const Level& L, const std::vector<int32_t>& col, std::vector<int16_t>& out) {
+  out.assign(col.size(), int16_t(kZeroSlot16));
+  for (int32_t s = 0; s < L.op.nslices; ++s)
+    for (int32_t k = L.sptr_h[s]; k < L.sptr_h[s + 1]; ++k)
+      for (int l = 0; l < kSlice; ++l) {
+        const size_t i = size_t(k) * kSlice + l;
+        const int32_t row = s * kSlice + l;
+        if (col[i] == L.n) continue;
+        const int32_t d = col[i] - row;
+        if (d < -32767 || d > 32767) return false;
+        out[i] = int16_t(d);
+      }
+  return true;
+}
+
 // Edge weights w_e = star1_e * (k_lo + k_hi) / 2 for the SELL entries (k = 1 when empty),
 // row sums in SELL order.
 void compute_weights(const Level& L, const std::vector<double>& kv, std::vector<double>& w64,
@@ -165,6 +220,9 @@ void compute_weights(const Level& L, const std::vector<double>& kv, std::vector<
     d64[r] = a;
     d32[r] = b;
   }
+  // zero slot: D = 1 there, so omega * b / D is 0 for the zero slot of b
+  d64[L.n] = 1.0;
+  d32[L.n] = 1.0f;
 }
 
 // Dense inverse of the coarsest operator over its unknowns (Cholesky).  Natural boundaries
@@ -280,6 +338,54 @@ void free_dev(void* p) {
   if (p) (void)hipFree(p);
 }
 
+template <typename T>
+const T* level_weights(const Level& L);
+template <>
+const double* level_weights<double>(const Level& L) { return L.op.w64; }
+template <>
+const float* level_weights<float>(const Level& L) { return L.op.w32; }
+template <typename T>
+const T* level_diag(const Level& L);
+template <>
+const double* level_diag<double>(const Level& L) { return L.op.diag64; }
+template <>
+const float* level_diag<float>(const Level& L) { return L.op.diag32; }
+
+// Descriptors of the levels that fit the fused coarse cycle's LDS budget (3 (n+1) values per
+// level); ctop is the highest such level, or -1 when even level 1 does not fit.
+template <typename T>
+void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vector<int32_t>& lds) {
+  const int nl = int(H.lv.size());
+  std::vector<CoarseLevel<T>> hv(nl);
+  lds.assign(nl, 0);
+  size_t off = 0;
+  ctop = -1;
+  for (int l = 0; l < nl; ++l) {
+    const Level& L = *H.lv[l];
+    const size_t need = off + 3 * size_t(L.n + 1);
+    if (need * sizeof(T) > size_t(kCoarseLdsBytes)) break;
+    CoarseLevel<T>& c = hv[l];
+    c.n = L.n;
+    c.lds = int32_t(off);
+    c.sptr = L.op.sptr;
+    c.col = L.op.col;
+    c.w = level_weights<T>(L);
+    c.diag = level_diag<T>(L);
+    if (l >= 1) {
+      c.pa = L.tr.pa;
+      c.pb = L.tr.pb;
+      c.r_self = L.tr.r_self;
+      c.r_sptr = L.tr.r_sptr;
+      c.r_col = L.tr.r_col;
+    }
+    lds[l] = int32_t(off);
+    off = need;
+    ctop = l;
+  }
+  if (ctop < 1) ctop = -1;
+  dev = upload(hv);
+}
+
 }  // namespace
 
 void upload_weights(Hierarchy& H) {
@@ -330,7 +436,7 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
     auto L = std::make_unique<Level>();
     L->mesh = std::move(m);
     L->nv = int32_t(L->mesh.nv);
-    order_level(*L, H->bc);
+    order_level(*L, H->bc, o.order);
     H->lv.push_back(std::move(L));
   }
   if (H->lv[0]->n > kMaxCoarse)
@@ -343,6 +449,8 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
     build_operator_structure(L, col);
     L.op.sptr = upload(L.sptr_h);
     L.op.col = col.empty() ? zeros<int32_t>(1) : upload(col);
+    std::vector<int16_t> col16;
+    if (delta16(L, col, col16) && !col16.empty()) L.op.col16 = upload(col16);
     L.perm = upload(L.perm_h);
     L.bnd_ids = L.bnd_h.empty() ? zeros<int32_t>(1) : upload(L.bnd_h);
     L.star0 = upload(L.mesh.star0);
@@ -352,6 +460,8 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
   }
   H->n0 = H->lv[0]->n;
   upload_weights(*H);
+  build_coarse_levels(*H, H->clv64, H->ctop64, H->clds64);
+  build_coarse_levels(*H, H->clv32, H->ctop32, H->clds32);
   // Krylov workspace on the finest level
   const int32_t n = H->lv.back()->n;
   H->sx = zeros<double>(n + 1);
@@ -376,14 +486,15 @@ Hierarchy::~Hierarchy() {
   for (auto& Lp : lv) {
     Level& L = *Lp;
     for (void* p : {(void*)L.perm, (void*)L.bnd_ids, (void*)L.star0, (void*)L.op.sptr,
-                    (void*)L.op.col, (void*)L.op.w64, (void*)L.op.w32, (void*)L.op.diag64,
+                    (void*)L.op.col, (void*)L.op.col16, (void*)L.op.w64, (void*)L.op.w32,
+                    (void*)L.op.diag64,
                     (void*)L.op.diag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
                     (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.v64.x, (void*)L.v64.b,
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
                     (void*)L.v32.r, (void*)L.v32.t})
       free_dev(p);
   }
-  for (void* p : {(void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
+  for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
                   (void*)sb, (void*)part, (void*)scal})
     free_dev(p);
   if (scal_host) (void)hipHostFree(scal_host);

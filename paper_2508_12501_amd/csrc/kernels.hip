@@ -9,6 +9,7 @@
 // wavefronts, per-block partials, then one fixed-order finalisation block.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "hier.hpp"
@@ -20,6 +21,14 @@ __device__ __forceinline__ int xcd_block() {
   const int b = blockIdx.x, g = gridDim.x;
   const int x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
   return x * q + (x < r ? x : r) + i;
+}
+
+// Reduction kernels run a capped grid; logical block b walks a contiguous range of 256-row
+// tiles so the number of partial sums stays small.
+__device__ __forceinline__ void tile_range(int ntiles, int blk, int& t0, int& t1) {
+  const int g = gridDim.x;
+  t0 = static_cast<int>(static_cast<int64_t>(ntiles) * blk / g);
+  t1 = static_cast<int>(static_cast<int64_t>(ntiles) * (blk + 1) / g);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -57,28 +66,170 @@ __device__ __forceinline__ double block_sum1(double a) {
   return a;
 }
 
-// acc = sum_k w_k (x_i - x_j(k)) and d = sum_k w_k over the row's SELL entries.
-template <typename T>
-__device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr,
-                                          const int32_t* __restrict__ col,
-                                          const T* __restrict__ w, const T* __restrict__ x,
-                                          int row, T xi, T& acc, T& d) {
-  const int s = row >> 6, lane = row & 63;
-  const int beg = sptr[s], end = sptr[s + 1];
-  acc = T(0);
-  d = T(0);
-  for (int k = beg; k < end; ++k) {
-    const int idx = k * kSlice + lane;
-    const T wk = w[idx];
-    d += wk;
-    acc += wk * (xi - x[col[idx]]);
+// Column of SELL entry idx in row `row`: absolute int32 ids, or (D16) 16-bit offsets from
+// the row with kZeroSlot16 marking the zero slot n.
+template <bool D16>
+__device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int row, int n) {
+  if (D16) {
+    const int c = static_cast<const int16_t*>(col)[idx];
+    return c == kZeroSlot16 ? n : row + c;
+  }
+  return static_cast<const int32_t*>(col)[idx];
+}
+
+// Slice bounds of the wavefront holding `row`.  All 64 lanes of a wavefront share one slice,
+// so the bounds are scalar loads and the entry loop below has a wave-uniform trip count.
+__device__ __forceinline__ void slice_bounds(const int32_t* __restrict__ sptr, int row, int& beg,
+                                             int& width) {
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  beg = sptr[s];
+  width = sptr[s + 1] - beg;
+}
+
+// acc = sum_k w_k (x_i - x_j(k)) and d = sum_k w_k over the row's SELL entries, in entry
+// order.  The entry count is wave-uniform, so a scalar switch picks a fully unrolled body
+// that issues all index and weight loads, then all gathers: a wavefront waits on two memory
+// round trips instead of two per entry.
+template <typename T, bool D16, int N>
+__device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const T* __restrict__ w,
+                                            const T* __restrict__ x, int beg, int lane, int row,
+                                            int n, T xi, T& acc, T& d) {
+  int cj[N];
+  T wk[N], xj[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    cj[k] = col_at<D16>(col, idx, row, n);
+    wk[k] = w[idx];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) xj[k] = x[cj[k]];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    d += wk[k];
+    acc += wk[k] * (xi - xj[k]);
   }
 }
 
+template <typename T, bool D16>
+__device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr,
+                                          const void* __restrict__ col,
+                                          const T* __restrict__ w, const T* __restrict__ x,
+                                          int row, int n, T xi, T& acc, T& d) {
+  int beg, width;
+  slice_bounds(sptr, row, beg, width);
+  const int lane = row & 63;
+  acc = T(0);
+  d = T(0);
+  switch (width) {
+    case 0: break;
+    case 1: row_apply_n<T, D16, 1>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 2: row_apply_n<T, D16, 2>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 3: row_apply_n<T, D16, 3>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 4: row_apply_n<T, D16, 4>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 5: row_apply_n<T, D16, 5>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 6: row_apply_n<T, D16, 6>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 7: row_apply_n<T, D16, 7>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    case 8: row_apply_n<T, D16, 8>(col, w, x, beg, lane, row, n, xi, acc, d); break;
+    default:
+      for (int k = 0; k < width; ++k) {
+        const int idx = (beg + k) * kSlice + lane;
+        const T wk = w[idx];
+        d += wk;
+        acc += wk * (xi - x[col_at<D16>(col, idx, row, n)]);
+      }
+  }
+}
+
+// Same batching for the first two sweeps from zero: gathers b and D instead of x.
+template <typename T, bool D16, int N>
+__device__ __forceinline__ void row_two_n(const void* __restrict__ col, const T* __restrict__ w,
+                                          const T* __restrict__ b, const T* __restrict__ diag,
+                                          int beg, int lane, int row, int n, T omega, T xi,
+                                          T& acc, T& d) {
+  int cj[N];
+  T wk[N], bj[N], dj[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    cj[k] = col_at<D16>(col, idx, row, n);
+    wk[k] = w[idx];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    bj[k] = b[cj[k]];
+    dj[k] = diag[cj[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    d += wk[k];
+    acc += wk[k] * (xi - omega * bj[k] / dj[k]);
+  }
+}
+
+// Batched restriction row: sum of the N midpoint values.
+template <typename T, int N>
+__device__ __forceinline__ T restrict_n(const int32_t* __restrict__ col, const T* __restrict__ rf,
+                                        int beg, int lane) {
+  int cj[N];
+  T v[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) cj[k] = col[(beg + k) * kSlice + lane];
+#pragma unroll
+  for (int k = 0; k < N; ++k) v[k] = rf[cj[k]];
+  T acc = T(0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) acc += v[k];
+  return acc;
+}
+
+// The first two smoothing sweeps from x = 0 in one pass: the first sweep is local
+// (x1 = omega b / D), so the second reads b and D at the neighbours instead of x1.  The
+// expressions are those of k_jacobi_zero and k_rows<T,2>, so the result is the same.  The
+// zero slot of D holds 1, making x1 there 0.
+template <typename T, bool D16>
+__global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict__ sptr,
+                                                       const void* __restrict__ col,
+                                                       const T* __restrict__ w,
+                                                       const T* __restrict__ diag,
+                                                       const T* __restrict__ b,
+                                                       T* __restrict__ y, int32_t n, T omega,
+                                                       const int* __restrict__ done) {
+  if (done && *done) return;
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= n) return;
+  int beg, width;
+  slice_bounds(sptr, row, beg, width);
+  const int lane = row & 63;
+  const T bi = b[row];
+  const T xi = omega * bi / diag[row];
+  T acc = T(0), d = T(0);
+  switch (width) {
+    case 0: break;
+    case 1: row_two_n<T, D16, 1>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 2: row_two_n<T, D16, 2>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 3: row_two_n<T, D16, 3>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 4: row_two_n<T, D16, 4>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 5: row_two_n<T, D16, 5>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 6: row_two_n<T, D16, 6>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 7: row_two_n<T, D16, 7>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 8: row_two_n<T, D16, 8>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    default:
+      for (int k = 0; k < width; ++k) {
+        const int idx = (beg + k) * kSlice + lane;
+        const T wk = w[idx];
+        const int j = col_at<D16>(col, idx, row, n);
+        d += wk;
+        acc += wk * (xi - omega * b[j] / diag[j]);
+      }
+  }
+  y[row] = xi + omega * (bi - acc) / d;
+}
+
 // MODE 0: y = A x.  MODE 1: y = b - A x.  MODE 2: y = x + omega (b - A x) / D.
-template <typename T, int MODE>
+template <typename T, int MODE, bool D16>
 __global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ sptr,
-                                                 const int32_t* __restrict__ col,
+                                                 const void* __restrict__ col,
                                                  const T* __restrict__ w,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ b, T* __restrict__ y,
@@ -88,14 +239,15 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ spt
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= n) return;
   const T xi = x[row];
+  const T bi = (MODE == 0) ? T(0) : b[row];
   T acc, d;
-  row_apply(sptr, col, w, x, row, xi, acc, d);
+  row_apply<T, D16>(sptr, col, w, x, row, n, xi, acc, d);
   if (MODE == 0)
     y[row] = acc;
   else if (MODE == 1)
-    y[row] = b[row] - acc;
+    y[row] = bi - acc;
   else
-    y[row] = xi + omega * (b[row] - acc) / d;
+    y[row] = xi + omega * (bi - acc) / d;
 }
 
 // First smoothing sweep from x = 0: x = omega b / D.
@@ -122,11 +274,25 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__
   if (done && *done) return;
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= nc) return;
-  const int s = row >> 6, lane = row & 63;
-  const int beg = sptr[s], end = sptr[s + 1];
+  int beg, width;
+  slice_bounds(sptr, row, beg, width);
+  const int lane = row & 63;
+  const T rs = rf[self[row]];
   T acc = T(0);
-  for (int k = beg; k < end; ++k) acc += rf[col[k * kSlice + lane]];
-  rc[row] = rf[self[row]] + T(0.5) * acc;
+  switch (width) {
+    case 0: break;
+    case 1: acc = restrict_n<T, 1>(col, rf, beg, lane); break;
+    case 2: acc = restrict_n<T, 2>(col, rf, beg, lane); break;
+    case 3: acc = restrict_n<T, 3>(col, rf, beg, lane); break;
+    case 4: acc = restrict_n<T, 4>(col, rf, beg, lane); break;
+    case 5: acc = restrict_n<T, 5>(col, rf, beg, lane); break;
+    case 6: acc = restrict_n<T, 6>(col, rf, beg, lane); break;
+    case 7: acc = restrict_n<T, 7>(col, rf, beg, lane); break;
+    case 8: acc = restrict_n<T, 8>(col, rf, beg, lane); break;
+    default:
+      for (int k = 0; k < width; ++k) acc += rf[col[(beg + k) * kSlice + lane]];
+  }
+  rc[row] = rs + T(0.5) * acc;
 }
 
 // x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.
@@ -157,6 +323,119 @@ __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ ainv,
     for (int j = 0; j < n0; ++j) acc += a[j] * sb[j];
     x[i] = static_cast<T>(acc);
   }
+}
+
+// The coarse end of a V-cycle (levels top..0) in one workgroup.  Each level keeps x, its
+// ping-pong partner and b in LDS (3 (n+1) values, the last of each being the zero slot); the
+// residual reuses the partner buffer.  Operator and transfer indices are read from global
+// memory (L2 resident at these sizes).  The arithmetic is that of the per-level kernels.
+template <typename T>
+__device__ __forceinline__ void cc_sweep(const CoarseLevel<T>& L, const T* __restrict__ cx,
+                                         const T* __restrict__ B, T* __restrict__ out, T omega,
+                                         int mode) {
+  for (int r = threadIdx.x; r < L.n; r += blockDim.x) {
+    const T xi = cx[r];
+    T acc, d;
+    row_apply<T, false>(L.sptr, L.col, L.w, cx, r, L.n, xi, acc, d);
+    if (mode == 2)
+      out[r] = xi + omega * (B[r] - acc) / d;
+    else
+      out[r] = B[r] - acc;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
+    const CoarseLevel<T>* __restrict__ lv, int top, const double* __restrict__ ainv, int32_t n0,
+    const T* __restrict__ b_in, T* __restrict__ x_out, T omega, int nu1, int nu2,
+    const int* __restrict__ done) {
+  if (done && *done) return;
+  extern __shared__ double smem_d[];
+  T* sm = reinterpret_cast<T*>(smem_d);
+  const int total = lv[top].lds + 3 * (lv[top].n + 1);
+  for (int i = threadIdx.x; i < total; i += blockDim.x) sm[i] = T(0);
+  __syncthreads();
+  {
+    const CoarseLevel<T>& L = lv[top];
+    T* B = sm + L.lds + 2 * (L.n + 1);
+    for (int i = threadIdx.x; i < L.n; i += blockDim.x) B[i] = b_in[i];
+  }
+  __syncthreads();
+  unsigned in_t = 0;   // bit l set: level l's current iterate sits in its partner buffer
+  for (int l = top; l >= 1; --l) {
+    const CoarseLevel<T>& L = lv[l];
+    T* X = sm + L.lds;
+    T* Tt = X + (L.n + 1);
+    T* B = Tt + (L.n + 1);
+    T* cx = X;
+    T* ox = Tt;
+    if (nu1 > 0) {
+      for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] = omega * B[r] / L.diag[r];
+      __syncthreads();
+      for (int it = 1; it < nu1; ++it) {
+        cc_sweep(L, cx, B, ox, omega, 2);
+        __syncthreads();
+        T* tmp = cx;
+        cx = ox;
+        ox = tmp;
+      }
+    } else {
+      for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] = T(0);
+      __syncthreads();
+    }
+    cc_sweep(L, cx, B, ox, omega, 1);   // residual into the partner buffer
+    __syncthreads();
+    const CoarseLevel<T>& C = lv[l - 1];
+    T* Bc = sm + C.lds + 2 * (C.n + 1);
+    for (int r = threadIdx.x; r < C.n; r += blockDim.x) {
+      int beg, width;
+      slice_bounds(L.r_sptr, r, beg, width);
+      const int lane = r & 63;
+      T acc = T(0);
+      for (int k = 0; k < width; ++k) acc += ox[L.r_col[(beg + k) * kSlice + lane]];
+      Bc[r] = ox[L.r_self[r]] + T(0.5) * acc;
+    }
+    __syncthreads();
+    if (cx == Tt) in_t |= 1u << l;
+  }
+  {
+    const CoarseLevel<T>& C = lv[0];
+    T* X0 = sm + C.lds;
+    const T* B0 = X0 + 2 * (C.n + 1);
+    for (int i = threadIdx.x; i < n0; i += blockDim.x) {
+      const double* a = ainv + static_cast<int64_t>(i) * n0;
+      double acc = 0.0;
+      for (int j = 0; j < n0; ++j) acc += a[j] * static_cast<double>(B0[j]);
+      X0[i] = static_cast<T>(acc);
+    }
+  }
+  __syncthreads();
+  for (int l = 1; l <= top; ++l) {
+    const CoarseLevel<T>& L = lv[l];
+    const CoarseLevel<T>& C = lv[l - 1];
+    T* X = sm + L.lds;
+    T* Tt = X + (L.n + 1);
+    T* B = Tt + (L.n + 1);
+    T* cx = (in_t >> l & 1u) ? Tt : X;
+    T* ox = (cx == X) ? Tt : X;
+    const T* ec = sm + C.lds + ((in_t >> (l - 1) & 1u) ? (C.n + 1) : 0);
+    for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] += T(0.5) * (ec[L.pa[r]] + ec[L.pb[r]]);
+    __syncthreads();
+    for (int it = 0; it < nu2; ++it) {
+      cc_sweep(L, cx, B, ox, omega, 2);
+      __syncthreads();
+      T* tmp = cx;
+      cx = ox;
+      ox = tmp;
+    }
+    if (cx == Tt)
+      in_t |= 1u << l;
+    else
+      in_t &= ~(1u << l);
+  }
+  const CoarseLevel<T>& L = lv[top];
+  const T* xs = sm + L.lds + ((in_t >> top & 1u) ? (L.n + 1) : 0);
+  for (int i = threadIdx.x; i < L.n; i += blockDim.x) x_out[i] = xs[i];
 }
 
 template <typename T>
@@ -209,8 +488,9 @@ __global__ void k_star0(const double* __restrict__ s0, const double* __restrict_
 }
 
 // ------------------------------------------------------------------ Krylov kernels (FP64)
+template <bool D16>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict__ sptr,
-                                                      const int32_t* __restrict__ col,
+                                                      const void* __restrict__ col,
                                                       const double* __restrict__ w,
                                                       const double* __restrict__ p,
                                                       double* __restrict__ q,
@@ -220,15 +500,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict_
                                                       const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
-  const int row = blk * kBlock + threadIdx.x;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
   double v0 = 0.0, v1 = 0.0;
-  if (row < n) {
-    const double pi = p[row];
-    double acc, d;
-    row_apply(sptr, col, w, p, row, pi, acc, d);
-    q[row] = acc;
-    v0 = pi * acc;
-    v1 = pi * r[row];
+  for (int t = t0; t < t1; ++t) {
+    const int row = t * kBlock + threadIdx.x;
+    if (row < n) {
+      const double pi = p[row];
+      double acc, d;
+      row_apply<double, D16>(sptr, col, w, p, row, n, pi, acc, d);
+      q[row] = acc;
+      v0 += pi * acc;
+      v1 += pi * r[row];
+    }
   }
   block_sum2(v0, v1);
   if (threadIdx.x == 0) {
@@ -247,22 +531,27 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
                                                       const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
-  const int i = blk * kBlock + threadIdx.x;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double a = sc->alpha, scale = sc->scale;
   double v = 0.0;
-  if (i < n) {
-    const double a = sc->alpha;
-    x[i] = x[i] + a * p[i];
-    const double ri = r[i] - a * q[i];
-    r[i] = ri;
-    v = ri * ri;
-    if (r32) r32[i] = static_cast<float>(ri * sc->scale);
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      x[i] = x[i] + a * p[i];
+      const double ri = r[i] - a * q[i];
+      r[i] = ri;
+      v += ri * ri;
+      if (r32) r32[i] = static_cast<float>(ri * scale);
+    }
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
 }
 
+template <bool D16>
 __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restrict__ sptr,
-                                                          const int32_t* __restrict__ col,
+                                                          const void* __restrict__ col,
                                                           const double* __restrict__ w,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ b,
@@ -273,15 +562,19 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restr
                                                           const int* __restrict__ done) {
   if (done && *done) return;
   const int blk = xcd_block();
-  const int row = blk * kBlock + threadIdx.x;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
   double v = 0.0;
-  if (row < n) {
-    double acc, d;
-    row_apply(sptr, col, w, x, row, x[row], acc, d);
-    const double ri = b[row] - acc;
-    r[row] = ri;
-    v = ri * ri;
-    if (r32) r32[row] = static_cast<float>(ri * sc->scale);
+  for (int t = t0; t < t1; ++t) {
+    const int row = t * kBlock + threadIdx.x;
+    if (row < n) {
+      double acc, d;
+      row_apply<double, D16>(sptr, col, w, x, row, n, x[row], acc, d);
+      const double ri = b[row] - acc;
+      r[row] = ri;
+      v += ri * ri;
+      if (r32) r32[row] = static_cast<float>(ri * sc->scale);
+    }
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
@@ -301,8 +594,13 @@ __global__ __launch_bounds__(kBlock) void k_sum64(int32_t n, const double* __res
                                                   const int* __restrict__ done) {
   if (done && *done) return;
   const int blk = xcd_block();
-  const int i = blk * kBlock + threadIdx.x;
-  double a = (i < n) ? v[i] : 0.0;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) a += v[i];
+  }
   a = block_sum1(a);
   if (threadIdx.x == 0) part0[blk] = a;
 }
@@ -313,8 +611,14 @@ __global__ __launch_bounds__(kBlock) void k_sum32(int32_t n, const float* __rest
                                                   const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
-  const int i = blk * kBlock + threadIdx.x;
-  double a = (i < n) ? static_cast<double>(v[i]) * sc->inv_scale : 0.0;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double s = sc->inv_scale;
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) a += static_cast<double>(v[i]) * s;
+  }
   a = block_sum1(a);
   if (threadIdx.x == 0) part0[blk] = a;
 }
@@ -328,16 +632,59 @@ __global__ __launch_bounds__(kBlock) void k_zconv_dot(int32_t n, const DevScalar
                                                       const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
-  const int i = blk * kBlock + threadIdx.x;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0;
   double v = 0.0;
-  if (i < n) {
-    double zi = static_cast<double>(z32[i]) * sc->inv_scale;
-    if (sub_mean) zi = zi - sc->mean;
-    z[i] = zi;
-    v = zi * o[i];
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      double zi = static_cast<double>(z32[i]) * s;
+      if (sub_mean) zi = zi - m;
+      z[i] = zi;
+      v += zi * o[i];
+    }
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
+}
+
+// part0 = z . o with z = z32 / scale - mean, without storing z
+__global__ __launch_bounds__(kBlock) void k_zdot32(int32_t n, const DevScalars* __restrict__ sc,
+                                                   const float* __restrict__ z32,
+                                                   const double* __restrict__ o,
+                                                   double* __restrict__ part0, int sub_mean,
+                                                   const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0;
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      double zi = static_cast<double>(z32[i]) * s;
+      if (sub_mean) zi = zi - m;
+      v += zi * o[i];
+    }
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
+// p = z + beta p with z = z32 / scale - mean
+__global__ __launch_bounds__(kBlock) void k_pupd32(int32_t n, const DevScalars* __restrict__ sc,
+                                                   const float* __restrict__ z32,
+                                                   double* __restrict__ p, int sub_mean,
+                                                   const int* __restrict__ done) {
+  if (*done) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i < n) {
+    double zi = static_cast<double>(z32[i]) * sc->inv_scale;
+    if (sub_mean) zi = zi - sc->mean;
+    p[i] = zi + sc->beta * p[i];
+  }
 }
 
 // z -= mean (when sub_mean), part0 = z . o
@@ -348,15 +695,20 @@ __global__ __launch_bounds__(kBlock) void k_zsub_dot(int32_t n, const DevScalars
                                                      const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
-  const int i = blk * kBlock + threadIdx.x;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double m = sub_mean ? sc->mean : 0.0;
   double v = 0.0;
-  if (i < n) {
-    double zi = z[i];
-    if (sub_mean) {
-      zi = zi - sc->mean;
-      z[i] = zi;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      double zi = z[i];
+      if (sub_mean) {
+        zi = zi - m;
+        z[i] = zi;
+      }
+      v += zi * o[i];
     }
-    v = zi * o[i];
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
@@ -376,8 +728,13 @@ __global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double* __restr
                                                 const int* __restrict__ done) {
   if (done && *done) return;
   const int blk = xcd_block();
-  const int i = blk * kBlock + threadIdx.x;
-  double v = (i < n) ? a[i] * b[i] : 0.0;
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) v += a[i] * b[i];
+  }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
 }
@@ -395,18 +752,34 @@ __global__ void k_to_f32(int32_t n, const DevScalars* __restrict__ sc, const dou
 }
 
 // One workgroup: fixed-order sum of the partials, then the scalar step `op`.
-__global__ __launch_bounds__(kBlock) void k_finalize(int op, int32_t nb,
-                                                     const double* __restrict__ part0,
-                                                     const double* __restrict__ part1,
-                                                     DevScalars* __restrict__ sc, double extra) {
+constexpr int kFinThreads = 1024;
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
+                                                          const double* __restrict__ part0,
+                                                          const double* __restrict__ part1,
+                                                          DevScalars* __restrict__ sc,
+                                                          double extra) {
   if (sc->done) return;
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kBlock) {
+  for (int i = threadIdx.x; i < nb; i += kFinThreads) {
     a += part0[i];
     if (part1) b += part1[i];
   }
-  block_sum2(a, b);
+  __shared__ double sa[kFinThreads / 64], sb[kFinThreads / 64];
+  a = wave_sum(a);
+  b = wave_sum(b);
+  if ((threadIdx.x & 63) == 0) {
+    sa[threadIdx.x >> 6] = a;
+    sb[threadIdx.x >> 6] = b;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  a = 0.0;
+  b = 0.0;
+  for (int i = 0; i < kFinThreads / 64; ++i) {
+    a += sa[i];
+    b += sb[i];
+  }
   switch (op) {
     case k::FIN_BNORM: {
       const double bn = sqrt(a + extra);
@@ -494,6 +867,7 @@ inline unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kBlock -
 namespace k {
 
 int blocks_for(int32_t n) { return static_cast<int>(grid_for(n)); }
+int red_blocks(int32_t n) { return std::max(1, std::min(static_cast<int>(grid_for(n)), kRedBlocks)); }
 
 template <typename T>
 static const T* weights(const Level& L);
@@ -508,24 +882,43 @@ const double* diagonal<double>(const Level& L) { return L.op.diag64; }
 template <>
 const float* diagonal<float>(const Level& L) { return L.op.diag32; }
 
+template <typename T, int MODE>
+static void rows(const Level& L, const T* x, const T* b, T* y, double omega, const int* done,
+                 hipStream_t s) {
+  if (L.n == 0) return;
+  if (L.op.col16)
+    hipLaunchKernelGGL((k_rows<T, MODE, true>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col16), weights<T>(L), x, b, y, L.n,
+                       static_cast<T>(omega), done);
+  else
+    hipLaunchKernelGGL((k_rows<T, MODE, false>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col), weights<T>(L), x, b, y, L.n,
+                       static_cast<T>(omega), done);
+}
 template <typename T>
 void spmv(const Level& L, const T* x, T* y, const int* done, hipStream_t s) {
-  if (L.n == 0) return;
-  hipLaunchKernelGGL((k_rows<T, 0>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
-                     weights<T>(L), x, static_cast<const T*>(nullptr), y, L.n, T(0), done);
+  rows<T, 0>(L, x, static_cast<const T*>(nullptr), y, 0.0, done, s);
 }
 template <typename T>
 void residual(const Level& L, const T* x, const T* b, T* r, const int* done, hipStream_t s) {
-  if (L.n == 0) return;
-  hipLaunchKernelGGL((k_rows<T, 1>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
-                     weights<T>(L), x, b, r, L.n, T(0), done);
+  rows<T, 1>(L, x, b, r, 0.0, done, s);
 }
 template <typename T>
 void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done,
             hipStream_t s) {
+  rows<T, 2>(L, x, b, xo, omega, done, s);
+}
+template <typename T>
+void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
   if (L.n == 0) return;
-  hipLaunchKernelGGL((k_rows<T, 2>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
-                     weights<T>(L), x, b, xo, L.n, static_cast<T>(omega), done);
+  if (L.op.col16)
+    hipLaunchKernelGGL((k_jacobi_two<T, true>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col16), weights<T>(L), diagonal<T>(L), b, xo,
+                       L.n, static_cast<T>(omega), done);
+  else
+    hipLaunchKernelGGL((k_jacobi_two<T, false>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col), weights<T>(L), diagonal<T>(L), b, xo,
+                       L.n, static_cast<T>(omega), done);
 }
 template <typename T>
 void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
@@ -551,6 +944,14 @@ template <typename T>
 void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s) {
   if (H.n0 == 0) return;
   hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(256), 0, s, H.coarse_inv, b, x, H.n0, done);
+}
+template <typename T>
+void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2,
+                  const int* done, hipStream_t s) {
+  const CoarseLevel<T>* lv = coarse_levels<T>(H);
+  const size_t bytes = coarse_lds_bytes<T>(H, top);
+  hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(kCoarseThreads), bytes, s, lv, top,
+                     H.coarse_inv, H.n0, b, x, static_cast<T>(omega), nu1, nu2, done);
 }
 template <typename T>
 void fill(T* p, int64_t n, T v, hipStream_t s) {
@@ -590,46 +991,66 @@ void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t
 
 void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_spmv_dot2, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr, L.op.col,
-                     L.op.w64, p, q, r, part0, part1, L.n, done);
+  if (L.op.col16)
+    hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col16), L.op.w64, p, q, r, part0, part1, L.n, done);
+  else
+    hipLaunchKernelGGL(k_spmv_dot2<false>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col), L.op.w64, p, q, r, part0, part1, L.n, done);
 }
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
                double* r, float* r32, double* part0, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_xr, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, p, q, x, r, r32,
+  hipLaunchKernelGGL(k_update_xr, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, p, q, x, r, r32,
                      part0, done);
 }
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual_norm, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                     L.op.col, L.op.w64, x, b, r, r32, sc, part0, L.n, done);
+  if (L.op.col16)
+    hipLaunchKernelGGL(k_residual_norm<true>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col16), L.op.w64, x, b, r, r32, sc, part0, L.n,
+                       done);
+  else
+    hipLaunchKernelGGL(k_residual_norm<false>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+                       static_cast<const void*>(L.op.col), L.op.w64, x, b, r, r32, sc, part0, L.n,
+                       done);
 }
 void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
              hipStream_t s) {
   hipLaunchKernelGGL(k_pupdate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, p, done);
 }
 void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum64, dim3(grid_for(n)), dim3(kBlock), 0, s, n, v, part0, done);
+  hipLaunchKernelGGL(k_sum64, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, v, part0, done);
 }
 void sum32(int32_t n, const float* v, const DevScalars* sc, double* part0, const int* done,
            hipStream_t s) {
-  hipLaunchKernelGGL(k_sum32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, v, sc, part0, done);
+  hipLaunchKernelGGL(k_sum32, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, v, sc, part0, done);
 }
 void zconv_dot(int32_t n, const DevScalars* sc, const float* z32, double* z, const double* o,
                double* part0, int sub_mean_flag, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_zconv_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z32, z, o, part0,
+  hipLaunchKernelGGL(k_zconv_dot, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z32, z, o, part0,
                      sub_mean_flag, done);
 }
 void zsub_dot(int32_t n, const DevScalars* sc, double* z, const double* o, double* part0,
               int sub_mean_flag, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_zsub_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, o, part0,
+  hipLaunchKernelGGL(k_zsub_dot, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z, o, part0,
                      sub_mean_flag, done);
+}
+void zdot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, double* part0,
+            int sub_mean_flag, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_zdot32, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z32, o, part0,
+                     sub_mean_flag, done);
+}
+void pupd32(int32_t n, const DevScalars* sc, const float* z32, double* p, int sub_mean_flag,
+            const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_pupd32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z32, p, sub_mean_flag,
+                     done);
 }
 void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n)), dim3(kBlock), 0, s, n, z, x, done);
 }
 void dot(int32_t n, const double* a, const double* b, double* part0, const int* done,
          hipStream_t s) {
-  hipLaunchKernelGGL(k_dot, dim3(grid_for(n)), dim3(kBlock), 0, s, n, a, b, part0, done);
+  hipLaunchKernelGGL(k_dot, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, a, b, part0, done);
 }
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, v);
@@ -640,7 +1061,8 @@ void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const 
 }
 void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
               double extra, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, op, nblocks, part0, part1, sc, extra);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, op, nblocks, part0, part1, sc,
+                     extra);
 }
 
 #define DECMG_INST(T)                                                                          \
@@ -648,9 +1070,12 @@ void finalize(int op, int32_t nblocks, const double* part0, const double* part1,
   template void residual<T>(const Level&, const T*, const T*, T*, const int*, hipStream_t);     \
   template void jacobi<T>(const Level&, const T*, const T*, T*, double, const int*, hipStream_t); \
   template void jacobi_zero<T>(const Level&, const T*, T*, double, const int*, hipStream_t);    \
+  template void jacobi_two<T>(const Level&, const T*, T*, double, const int*, hipStream_t);     \
   template void restrict_<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t); \
   template void prolong<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t);  \
   template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \
+  template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
+                                hipStream_t);                                                  \
   template void fill<T>(T*, int64_t, T, hipStream_t);                                          \
   template void gather<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                 \
   template void scatter<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                \

@@ -6,6 +6,7 @@
 // enqueues `check_every` replays, then reads the flag.  Replays after convergence cost one
 // flag read per kernel.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <stdexcept>
 
@@ -21,6 +22,29 @@ template <>
 LevelVecs<float>& vecs<float>(Level& L) { return L.v32; }
 
 template <typename T>
+static constexpr int dtype_of() { return sizeof(T) == 8 ? MG_F64 : MG_F32; }
+
+// A weighted-Jacobi sweep, bracketed by probe events when the probe watches this level.
+template <typename T>
+static void sweep(Hierarchy& H, int l, const T* x, const T* b, T* xo, double omega, const int* done,
+                  hipStream_t s) {
+  Hierarchy::Probe& P = H.probe;
+  const bool timed = P.on && !H.capturing && P.level == l && P.dtype == dtype_of<T>();
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed) {
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    check_hip(hipEventRecord(e0, s), "hipEventRecord");
+  }
+  k::jacobi<T>(*H.lv[l], x, b, xo, omega, done, s);
+  if (timed) {
+    check_hip(hipEventRecord(e1, s), "hipEventRecord");
+    P.ev.emplace_back(e0, e1);
+    P.stream = s;
+  }
+}
+
+template <typename T>
 T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const int* done,
           hipStream_t s) {
   Level& L = *H.lv[l];
@@ -29,14 +53,21 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
     k::coarse<T>(H, b, V.x, done, s);
     return V.x;
   }
+  if (!x_init && l <= coarse_top<T>(H)) {
+    k::coarse_cycle<T>(H, l, b, V.x, o.omega, o.nu1, o.nu2, done, s);
+    return V.x;
+  }
   T *cur, *oth;
   int pre = o.nu1;
   if (!x_init) {
     cur = V.x;
     oth = V.t;
-    if (pre > 0) {
+    if (pre >= 2) {
+      k::jacobi_two<T>(L, b, cur, o.omega, done, s);
+      pre -= 2;
+    } else if (pre == 1) {
       k::jacobi_zero<T>(L, b, cur, o.omega, done, s);
-      --pre;
+      pre = 0;
     } else {
       k::fill<T>(cur, L.n, T(0), s);
     }
@@ -45,7 +76,7 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
     oth = (x_init == V.t) ? V.x : V.t;
   }
   for (; pre > 0; --pre) {
-    k::jacobi<T>(L, cur, b, oth, o.omega, done, s);
+    sweep<T>(H, l, cur, b, oth, o.omega, done, s);
     std::swap(cur, oth);
   }
   Level& C = *H.lv[l - 1];
@@ -54,7 +85,7 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
   T* ec = vcycle<T>(H, l - 1, vecs<T>(C).b, nullptr, o, done, s);
   k::prolong<T>(L, C, ec, cur, done, s);
   for (int i = 0; i < o.nu2; ++i) {
-    k::jacobi<T>(L, cur, b, oth, o.omega, done, s);
+    sweep<T>(H, l, cur, b, oth, o.omega, done, s);
     std::swap(cur, oth);
   }
   return cur;
@@ -68,7 +99,7 @@ template float* vcycle<float>(Hierarchy&, int, const float*, float*, const mg_op
 namespace {
 
 void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, double extra = 0.0) {
-  k::finalize(op, k::blocks_for(n), H.part, two ? H.part + H.part_cap : nullptr, H.scal, extra, s);
+  k::finalize(op, k::red_blocks(n), H.part, two ? H.part + H.part_cap : nullptr, H.scal, extra, s);
 }
 
 // One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).
@@ -82,13 +113,19 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   double* P1 = H.part + H.part_cap;
   const double* other = (o.outer == MG_OUTER_FCG) ? H.sq : H.sr;
   double* z;
+  float* z32 = nullptr;
   if (o.precision == MG_F32) {
-    float* z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s);
+    z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s);
     if (natural) {
       k::sum32(n, z32, H.scal, P0, done, s);
       fin(H, k::FIN_MEAN, n, false, s);
     }
-    k::zconv_dot(n, H.scal, z32, H.sz, other, P0, natural ? 1 : 0, done, s);
+    if (o.outer == MG_OUTER_IR) {
+      k::zconv_dot(n, H.scal, z32, H.sz, other, P0, natural ? 1 : 0, done, s);
+    } else {
+      // z stays in FP32: the dot and the p update widen it on the fly
+      k::zdot32(n, H.scal, z32, other, P0, natural ? 1 : 0, done, s);
+    }
     z = H.sz;
   } else {
     z = vcycle<double>(H, top, H.sr, nullptr, o, done, s);
@@ -106,7 +143,10 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
     return;
   }
   fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
-  k::pupdate(n, H.scal, z, H.sp, done, s);
+  if (z32)
+    k::pupd32(n, H.scal, z32, H.sp, natural ? 1 : 0, done, s);
+  else
+    k::pupdate(n, H.scal, z, H.sp, done, s);
   k::spmv_dot2(F, H.sp, H.sq, H.sr, P0, P1, done, s);
   fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s);
   k::update_xr(n, H.scal, H.sp, H.sq, H.sx, H.sr, r32, P0, done, s);
@@ -124,17 +164,23 @@ void enqueue_cycle(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   fin(H, k::FIN_CHECK, F.n, false, s);
 }
 
+std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
+  return std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2, 0, o.omega);
+}
+
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
-  auto key = std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2, 0, o.omega);
+  auto key = graph_key(o, kind);
   auto it = H.graphs.find(key);
   if (it != H.graphs.end()) return it->second;
   hipGraph_t g = nullptr;
   check_hip(hipStreamBeginCapture(H.capture_stream, hipStreamCaptureModeThreadLocal),
             "hipStreamBeginCapture");
+  H.capturing = true;
   if (kind == 0)
     enqueue_iteration(H, o, H.capture_stream);
   else
     enqueue_cycle(H, o, H.capture_stream);
+  H.capturing = false;
   check_hip(hipStreamEndCapture(H.capture_stream, &g), "hipStreamEndCapture");
   hipGraphExec_t ex = nullptr;
   hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -215,6 +261,35 @@ void finish(Hierarchy& H, const double* b_nat, double* x_nat, mg_result* res, hi
 
 }  // namespace
 
+// Enqueues iterations in batches and checks the device flag between batches.  The first batch
+// is the iteration count of the previous solve with the same settings (or check_every); later
+// batches are sized from the observed mean residual reduction per iteration, so a solve
+// normally needs one or two host round trips and runs few or no no-op iterations.
+template <typename F>
+void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue) {
+  const int every = std::max(1, o.check_every);
+  auto key = graph_key(o, kind);
+  auto it = H.last_iters.find(key);
+  int batch = (it != H.last_iters.end()) ? std::max(1, it->second) : every;
+  int launched = 0;
+  while (launched < o.max_iter) {
+    batch = std::min(batch, o.max_iter - launched);
+    for (int j = 0; j < batch; ++j) enqueue();
+    launched += batch;
+    read_scalars(H, s);
+    const DevScalars& h = *H.scal_host;
+    if (h.done) break;
+    batch = every;
+    if (h.iters > 0 && h.rnorm > 0 && h.bnorm > 0) {
+      const double rate = std::pow(h.rnorm / h.bnorm, 1.0 / h.iters);
+      const double goal = h.rtol * h.bnorm / h.rnorm;
+      if (rate > 0 && rate < 1 && goal < 1)
+        batch = std::max(1, std::min(4 * every, int(std::ceil(std::log(goal) / std::log(rate)))));
+    }
+  }
+  H.last_iters[key] = H.scal_host->iters;
+}
+
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
             hipStream_t s) {
   Level& F = *H.lv.back();
@@ -228,17 +303,12 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
             "hipMemcpyAsync");
   if (o.precision == MG_F32) k::to_f32(n, H.scal, H.sr, F.v32.b, nullptr, s);
   hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 0) : nullptr;
-  const int every = std::max(1, o.check_every);
-  for (int it = 0; it < o.max_iter; it += every) {
-    for (int j = 0; j < every; ++j) {
-      if (g)
-        check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
-      else
-        enqueue_iteration(H, o, s);
-    }
-    read_scalars(H, s);
-    if (H.scal_host->done) break;
-  }
+  iterate(H, o, 0, s, [&]() {
+    if (g)
+      check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
+    else
+      enqueue_iteration(H, o, s);
+  });
   finish(H, b_nat, x_nat, res, s);
   return H.scal_host->status;
 }
@@ -252,17 +322,12 @@ int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, m
   setup_rhs(H, b_nat, s);
   k::fill<double>(H.sx, F.n, 0.0, s);
   hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 1) : nullptr;
-  const int every = std::max(1, o.check_every);
-  for (int it = 0; it < o.max_iter; it += every) {
-    for (int j = 0; j < every; ++j) {
-      if (g)
-        check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
-      else
-        enqueue_cycle(H, o, s);
-    }
-    read_scalars(H, s);
-    if (H.scal_host->done) break;
-  }
+  iterate(H, o, 1, s, [&]() {
+    if (g)
+      check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
+    else
+      enqueue_cycle(H, o, s);
+  });
   finish(H, b_nat, x_nat, res, s);
   return H.scal_host->status;
 }

@@ -103,6 +103,25 @@ def test_c3_mixed_fcg(c3):
     assert err <= 1e-8
 
 
+def test_c3_morton_order_matches(c3):
+    """The same solve with the Z-order layout, whose neighbour offsets at this size do not fit
+    16 bits (absolute 32-bit column path), against the oracle."""
+    g, o, b = c3
+    gm = mg.Hierarchy("square", W.C3["nsub"], base_cells=W.C3["base_cells"], order=mg.MG_ORDER_MORTON)
+    x0 = W.normal(o.fine.nv, 41)
+    y = torch.zeros(o.fine.nv, dtype=torch.float64, device=DEV)
+    mg.dec_laplacian_apply(gm.h, gm.top, gpu(x0), y)
+    assert rel(host(y), o.fine.A @ x0) <= 1e-14
+    xo, ko, _ = omg.mg_pcg(o, b)
+    x = torch.zeros(o.fine.nv, dtype=torch.float64, device=DEV)
+    res = mg.mg_pcg(gm.h, mg.mg_opts_default(), gpu(b), x)
+    assert res.iterations == ko and rel(host(x), xo) <= 1e-12
+    x.zero_()
+    mg.mg_pcg(gm.h, mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32), gpu(b), x)
+    assert omg.rel_residual(o, b, host(x)) <= 1e-10
+    gm.close()
+
+
 def test_c2_sphere_fullsize():
     xyz, tri = dec.icosahedron()
     o = omg.Hierarchy(xyz, tri, W.C2["sphere_level"], project=True, bc="natural")

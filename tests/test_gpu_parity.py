@@ -42,9 +42,9 @@ def host(t):
 class Pair:
     """The same hierarchy built by the library and by the oracle."""
 
-    def __init__(self, kind, nsub, base_cells=4, bc=None):
-        print(f"[parity] building {kind} base={base_cells} nsub={nsub}", flush=True)
-        self.g = mg.Hierarchy(kind, nsub, base_cells=base_cells, bc=bc)
+    def __init__(self, kind, nsub, base_cells=4, bc=None, order=mg.MG_ORDER_STRIPES):
+        print(f"[parity] building {kind} base={base_cells} nsub={nsub} order={order}", flush=True)
+        self.g = mg.Hierarchy(kind, nsub, base_cells=base_cells, bc=bc, order=order)
         if kind == "square":
             xyz, tri = dec.square_grid(base_cells)
             self.o = omg.Hierarchy(xyz, tri, nsub, bc="dirichlet" if bc in (None, 0) else "natural")
@@ -71,7 +71,13 @@ def ragged():
     return Pair("square", 3, base_cells=3)
 
 
-PAIRS = ["c1", "sphere", "ragged"]
+@pytest.fixture(scope="module")
+def sphere_z():
+    # the same icosphere laid out in Z-order instead of stripes
+    return Pair("sphere", 4, order=mg.MG_ORDER_MORTON)
+
+
+PAIRS = ["c1", "sphere", "ragged", "sphere_z"]
 
 
 # ------------------------------------------------------------------ host build
@@ -176,7 +182,7 @@ def test_vcycle(which, request):
 
 def _rhs(P, which):
     xyz = P.o.fine.xyz
-    if which == "sphere":
+    if which.startswith("sphere"):
         f = W.sphere_rhs(xyz, W.sh_coefficients())
     elif which == "c1":
         f = W.manufactured_c1(xyz)

@@ -241,9 +241,7 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->ne = L.mesh.ne;
   out->nt = L.mesh.nt;
   out->n_unknowns = L.n;
-  int64_t nnz = 0;
-  for (int32_t e : L.entry_edge) nnz += (e >= 0);
-  out->nnz_operator = nnz;
+  out->nnz_operator = L.nnz;
   out->index_bytes = L.op.col16 ? 2 : 4;
   out->reserved = 0;
   return MG_OK;

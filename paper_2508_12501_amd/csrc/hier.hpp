@@ -55,12 +55,14 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
 };
 
 constexpr int kCoarseThreads = 1024;       // workgroup of the fused coarse cycle
-constexpr int kCoarseLdsBytes = 64 * 1024; // LDS budget of the fused coarse cycle
+constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse cycle
 
 // Per-level descriptor of the fused coarse cycle (device copy per precision).
 template <typename T>
 struct CoarseLevel {
   int32_t n = 0, lds = 0;            // unknowns; offset (in T) of x, partner, b in LDS
+  int32_t nslices = 0, r_nslices = 0;
+  int32_t lds_sptr = 0, lds_rsptr = 0;  // offsets (in int32) of the preloaded slice bounds
   const int32_t* sptr = nullptr;
   const int32_t* col = nullptr;
   const T* w = nullptr;
@@ -88,6 +90,7 @@ struct Level {
   std::vector<int32_t> bnd_h;      // natural ids that are not unknowns
   std::vector<int32_t> entry_edge; // per SELL entry: edge id or -1 (padding)
   std::vector<int32_t> sptr_h;
+  int64_t nnz = 0;                 // stored couplings (SELL entries that are not padding)
   int32_t* perm = nullptr;         // device copies
   int32_t* bnd_ids = nullptr;
   double* star0 = nullptr;         // nv, natural numbering
@@ -100,6 +103,7 @@ struct Level {
 struct DevScalars {
   double alpha, beta, rho, pq, rnorm, bnorm, rtol, scale, inv_scale, mean;
   double n_unknowns;
+  double true_rnorm;   // ||b - A x|| recomputed at exit
   int32_t done, iters, status, max_iter;
 };
 
@@ -122,6 +126,13 @@ struct Hierarchy {
   std::map<std::tuple<int, int, int, int, double>, int> last_iters;
   // fused coarse cycle: highest level handled by one workgroup, per precision (-1 = none)
   int ctop64 = -1, ctop32 = -1;
+  int coarse_width = 0;   // widest operator slice among the levels of the fused cycle
+  // LDS layout of the fused cycle per precision: vectors, then (8-byte aligned) the dense
+  // coarsest inverse, then the slice bounds of every fused level
+  size_t cvec64 = 0, cvec32 = 0;        // bytes of the vector region up to each ctop
+  size_t cint_off64 = 0, cint_off32 = 0;   // byte offset of the int region
+  size_t clds_total64 = 0, clds_total32 = 0;
+  int lds_limit = 64 * 1024;
   CoarseLevel<double>* clv64 = nullptr;
   CoarseLevel<float>* clv32 = nullptr;
   std::vector<int32_t> clds64, clds32;   // LDS offsets (in elements) per level
@@ -145,13 +156,12 @@ template <> inline const CoarseLevel<float>* coarse_levels<float>(const Hierarch
 template <typename T> int coarse_top(const Hierarchy& H);
 template <> inline int coarse_top<double>(const Hierarchy& H) { return H.ctop64; }
 template <> inline int coarse_top<float>(const Hierarchy& H) { return H.ctop32; }
-template <typename T> size_t coarse_lds_bytes(const Hierarchy& H, int top);
-template <> inline size_t coarse_lds_bytes<double>(const Hierarchy& H, int top) {
-  return size_t(H.clds64[top] + 3 * (H.lv[top]->n + 1)) * sizeof(double);
-}
-template <> inline size_t coarse_lds_bytes<float>(const Hierarchy& H, int top) {
-  return size_t(H.clds32[top] + 3 * (H.lv[top]->n + 1)) * sizeof(float);
-}
+template <typename T> size_t coarse_lds_bytes(const Hierarchy& H);
+template <> inline size_t coarse_lds_bytes<double>(const Hierarchy& H) { return H.clds_total64; }
+template <> inline size_t coarse_lds_bytes<float>(const Hierarchy& H) { return H.clds_total32; }
+template <typename T> size_t coarse_int_offset(const Hierarchy& H);
+template <> inline size_t coarse_int_offset<double>(const Hierarchy& H) { return H.cint_off64; }
+template <> inline size_t coarse_int_offset<float>(const Hierarchy& H) { return H.cint_off32; }
 
 namespace k {
 template <typename T> void spmv(const Level& L, const T* x, T* y, const int* done, hipStream_t s);
@@ -170,10 +180,12 @@ template <typename T> void bnd_copy(const int32_t* ids, int32_t nb, const T* src
 template <typename T> void bnd_jacobi(const int32_t* ids, int32_t nb, const T* b, T* x, double omega, hipStream_t s);
 template <typename T> void bnd_zero(const int32_t* ids, int32_t nb, T* x, hipStream_t s);
 void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t s);
+void prepare_coarse(const Hierarchy& H);
 
 // Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
 int blocks_for(int32_t n);
-int red_blocks(int32_t n);   // grid (= number of partials) of the reduction kernels
+int red_blocks(int32_t n);   // grid (= number of partials) of the streaming reductions
+// spmv_dot2 and residual_norm run one 256-row tile per workgroup: blocks_for(n) partials
 void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, const int* done, hipStream_t s);
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
@@ -207,7 +219,8 @@ enum FinOp : int {
   FIN_RNORM = 7,      // rnorm = sqrt(sum0) (no iteration bookkeeping)
 };
 void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
-              double extra, hipStream_t s);
+              double extra, int force, hipStream_t s);
+void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, hipStream_t s);
 }  // namespace k
 
 }  // namespace decmg

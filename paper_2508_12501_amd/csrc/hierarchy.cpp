@@ -172,6 +172,11 @@ void build_operator_structure(Level& L, std::vector<int32_t>& col) {
   }
   L.op.nslices = nslices;
   L.op.ncols = L.sptr_h[nslices];
+  L.nnz = 0;
+  for (int32_t e : L.entry_edge) L.nnz += (e >= 0);
+  // one padding column (zero slot, weight 0) so clamped loads past the last slice stay in bounds
+  col.resize(col.size() + kSlice, n);
+  L.entry_edge.resize(L.entry_edge.size() + kSlice, -1);
 }
 
 // 16-bit offsets col - row, with kZeroSlot16 for the zero slot; false if any offset does not
@@ -317,13 +322,14 @@ void build_transfer(Level& F, const Level& C) {
     for (int l = 0; l < kSlice; ++l)
       for (size_t k = 0; k < rows[l].size(); ++k) col[base + k * kSlice + l] = rows[l][k];
   }
+  col.resize(col.size() + kSlice, F.n);   // padding column
   F.tr.pa = upload(pa);
   F.tr.pb = upload(pb);
   F.tr.r_self = upload(self);
   F.tr.nslices = nslices;
   F.tr.ncols = sptr[nslices];
   F.tr.r_sptr = upload(sptr);
-  F.tr.r_col = col.empty() ? zeros<int32_t>(1) : upload(col);
+  F.tr.r_col = upload(col);
 }
 
 template <typename T>
@@ -351,22 +357,30 @@ const double* level_diag<double>(const Level& L) { return L.op.diag64; }
 template <>
 const float* level_diag<float>(const Level& L) { return L.op.diag32; }
 
-// Descriptors of the levels that fit the fused coarse cycle's LDS budget (3 (n+1) values per
-// level); ctop is the highest such level, or -1 when even level 1 does not fit.
+// Descriptors of the levels that fit the fused coarse cycle's LDS budget.  The LDS holds,
+// for levels 0..ctop, x, partner and b (3 (n+1) values each), then the dense coarsest inverse
+// (n0^2 doubles), then the operator and restriction slice bounds of every level; ctop is the
+// highest level for which all of it fits, or -1 when even level 1 does not.
 template <typename T>
-void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vector<int32_t>& lds) {
+void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vector<int32_t>& lds,
+                         size_t& int_off, size_t& total) {
   const int nl = int(H.lv.size());
   std::vector<CoarseLevel<T>> hv(nl);
   lds.assign(nl, 0);
-  size_t off = 0;
   ctop = -1;
+  size_t vec = 0, ints = 0;
+  const size_t inv_bytes = size_t(H.lv[0]->n) * H.lv[0]->n * sizeof(double);
   for (int l = 0; l < nl; ++l) {
     const Level& L = *H.lv[l];
-    const size_t need = off + 3 * size_t(L.n + 1);
-    if (need * sizeof(T) > size_t(kCoarseLdsBytes)) break;
+    const size_t vec2 = vec + 3 * size_t(L.n + 1) * sizeof(T);
+    const size_t ints2 = ints + size_t(L.op.nslices + 1) + (l >= 1 ? size_t(L.tr.nslices + 1) : 0);
+    const size_t off2 = (vec2 + 7) / 8 * 8 + inv_bytes;
+    if (off2 + ints2 * sizeof(int32_t) > size_t(H.lds_limit)) break;
     CoarseLevel<T>& c = hv[l];
     c.n = L.n;
-    c.lds = int32_t(off);
+    c.lds = int32_t(vec / sizeof(T));
+    c.nslices = L.op.nslices;
+    c.lds_sptr = int32_t(ints);
     c.sptr = L.op.sptr;
     c.col = L.op.col;
     c.w = level_weights<T>(L);
@@ -377,10 +391,17 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
       c.r_self = L.tr.r_self;
       c.r_sptr = L.tr.r_sptr;
       c.r_col = L.tr.r_col;
+      c.r_nslices = L.tr.nslices;
+      c.lds_rsptr = int32_t(ints + L.op.nslices + 1);
     }
-    lds[l] = int32_t(off);
-    off = need;
+    lds[l] = c.lds;
+    vec = vec2;
+    ints = ints2;
+    int_off = (vec + 7) / 8 * 8 + inv_bytes;
+    total = int_off + ints * sizeof(int32_t);
     ctop = l;
+    for (int32_t s = 0; s < L.op.nslices; ++s)
+      H.coarse_width = std::max(H.coarse_width, L.sptr_h[s + 1] - L.sptr_h[s]);
   }
   if (ctop < 1) ctop = -1;
   dev = upload(hv);
@@ -448,7 +469,7 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
     std::vector<int32_t> col;
     build_operator_structure(L, col);
     L.op.sptr = upload(L.sptr_h);
-    L.op.col = col.empty() ? zeros<int32_t>(1) : upload(col);
+    L.op.col = upload(col);
     std::vector<int16_t> col16;
     if (delta16(L, col, col16) && !col16.empty()) L.op.col16 = upload(col16);
     L.perm = upload(L.perm_h);
@@ -460,8 +481,16 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
   }
   H->n0 = H->lv[0]->n;
   upload_weights(*H);
-  build_coarse_levels(*H, H->clv64, H->ctop64, H->clds64);
-  build_coarse_levels(*H, H->clv32, H->ctop32, H->clds32);
+  {
+    int dev = 0, lim = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    check_hip(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+              "hipDeviceGetAttribute");
+    H->lds_limit = std::min(lim, kCoarseLdsMax);
+  }
+  build_coarse_levels(*H, H->clv64, H->ctop64, H->clds64, H->cint_off64, H->clds_total64);
+  build_coarse_levels(*H, H->clv32, H->ctop32, H->clds32, H->cint_off32, H->clds_total32);
+  k::prepare_coarse(*H);
   // Krylov workspace on the finest level
   const int32_t n = H->lv.back()->n;
   H->sx = zeros<double>(n + 1);

@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "hier.hpp"
+#include "util.hpp"
 
 namespace decmg {
 namespace {
@@ -329,31 +330,93 @@ __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ ainv,
 // ping-pong partner and b in LDS (3 (n+1) values, the last of each being the zero slot); the
 // residual reuses the partner buffer.  Operator and transfer indices are read from global
 // memory (L2 resident at these sizes).  The arithmetic is that of the per-level kernels.
-template <typename T>
-__device__ __forceinline__ void cc_sweep(const CoarseLevel<T>& L, const T* __restrict__ cx,
-                                         const T* __restrict__ B, T* __restrict__ out, T omega,
-                                         int mode) {
-  for (int r = threadIdx.x; r < L.n; r += blockDim.x) {
-    const T xi = cx[r];
-    T acc, d;
-    row_apply<T, false>(L.sptr, L.col, L.w, cx, r, L.n, xi, acc, d);
-    if (mode == 2)
-      out[r] = xi + omega * (B[r] - acc) / d;
-    else
-      out[r] = B[r] - acc;
+// One sweep or residual pass over a coarse level held in LDS (vectors and slice bounds `sp`
+// in LDS, index and weight arrays in global memory).  With KMAX > 0 every thread takes four
+// rows per pass and issues all their index and weight loads before any gather: rows are
+// clamped to n-1 and entries to the row's last one (the SELL arrays carry one padding column),
+// and weights past a row's width are masked to 0, which adds exact zeros.
+template <typename T, int KMAX>
+__device__ __forceinline__ void cc_sweep(const CoarseLevel<T>& L, const int32_t* sp,
+                                         const T* __restrict__ cx, const T* __restrict__ B,
+                                         T* __restrict__ out, T omega, int mode) {
+  const int n = L.n, nt = blockDim.x;
+  if (KMAX == 0) {
+    for (int r = threadIdx.x; r < n; r += nt) {
+      const int sl = r >> 6, lane = r & 63;
+      const int beg = sp[sl], end = sp[sl + 1];
+      const T xi = cx[r];
+      T acc = T(0), d = T(0);
+      for (int k = beg; k < end; ++k) {
+        const int idx = k * kSlice + lane;
+        const T wk = L.w[idx];
+        d += wk;
+        acc += wk * (xi - cx[L.col[idx]]);
+      }
+      out[r] = (mode == 2) ? xi + omega * (B[r] - acc) / d : B[r] - acc;
+    }
+    return;
+  }
+  constexpr int K = KMAX > 0 ? KMAX : 1;
+  for (int r0 = threadIdx.x; r0 < n; r0 += 4 * nt) {
+    int row[4], beg[4], wid[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      row[q] = min(r0 + q * nt, n - 1);
+      const int sl = row[q] >> 6;
+      beg[q] = sp[sl];
+      wid[q] = sp[sl + 1] - beg[q];
+    }
+    int c[4][K];
+    T wv[4][K];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int kk = min(k, max(wid[q] - 1, 0));
+        const int idx = (beg[q] + kk) * kSlice + (row[q] & 63);
+        c[q][k] = L.col[idx];
+        const T wl = L.w[idx];
+        wv[q][k] = (k < wid[q]) ? wl : T(0);
+      }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const T xi = cx[row[q]];
+      T acc = T(0), d = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        d += wv[q][k];
+        acc += wv[q][k] * (xi - cx[c[q][k]]);
+      }
+      if (r0 + q * nt < n)
+        out[row[q]] = (mode == 2) ? xi + omega * (B[row[q]] - acc) / d : B[row[q]] - acc;
+    }
   }
 }
 
-template <typename T>
+// The coarse end of a V-cycle (levels top..0) in one workgroup.  LDS holds, per level, x, its
+// ping-pong partner and b (3 (n+1) values, the last of each being the zero slot; the residual
+// reuses the partner buffer), the dense coarsest inverse, and the slice bounds of the operator
+// and restriction of every level.  The arithmetic is that of the per-level kernels.
+template <typename T, int KMAX>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
     const CoarseLevel<T>* __restrict__ lv, int top, const double* __restrict__ ainv, int32_t n0,
-    const T* __restrict__ b_in, T* __restrict__ x_out, T omega, int nu1, int nu2,
-    const int* __restrict__ done) {
+    int32_t inv_off, int32_t int_off, const T* __restrict__ b_in, T* __restrict__ x_out, T omega,
+    int nu1, int nu2, const int* __restrict__ done) {
   if (done && *done) return;
   extern __shared__ double smem_d[];
   T* sm = reinterpret_cast<T*>(smem_d);
+  double* sinv = smem_d + inv_off / 8;
+  int32_t* sint = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(smem_d) + int_off);
   const int total = lv[top].lds + 3 * (lv[top].n + 1);
   for (int i = threadIdx.x; i < total; i += blockDim.x) sm[i] = T(0);
+  for (int i = threadIdx.x; i < n0 * n0; i += blockDim.x) sinv[i] = ainv[i];
+  for (int l = 0; l <= top; ++l) {
+    const CoarseLevel<T>& L = lv[l];
+    for (int i = threadIdx.x; i <= L.nslices; i += blockDim.x) sint[L.lds_sptr + i] = L.sptr[i];
+    if (l >= 1)
+      for (int i = threadIdx.x; i <= L.r_nslices; i += blockDim.x)
+        sint[L.lds_rsptr + i] = L.r_sptr[i];
+  }
   __syncthreads();
   {
     const CoarseLevel<T>& L = lv[top];
@@ -364,6 +427,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
   unsigned in_t = 0;   // bit l set: level l's current iterate sits in its partner buffer
   for (int l = top; l >= 1; --l) {
     const CoarseLevel<T>& L = lv[l];
+    const int32_t* sp = sint + L.lds_sptr;
     T* X = sm + L.lds;
     T* Tt = X + (L.n + 1);
     T* B = Tt + (L.n + 1);
@@ -373,7 +437,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
       for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] = omega * B[r] / L.diag[r];
       __syncthreads();
       for (int it = 1; it < nu1; ++it) {
-        cc_sweep(L, cx, B, ox, omega, 2);
+        cc_sweep<T, KMAX>(L, sp, cx, B, ox, omega, 2);
         __syncthreads();
         T* tmp = cx;
         cx = ox;
@@ -383,14 +447,14 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
       for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] = T(0);
       __syncthreads();
     }
-    cc_sweep(L, cx, B, ox, omega, 1);   // residual into the partner buffer
+    cc_sweep<T, KMAX>(L, sp, cx, B, ox, omega, 1);   // residual into the partner buffer
     __syncthreads();
     const CoarseLevel<T>& C = lv[l - 1];
     T* Bc = sm + C.lds + 2 * (C.n + 1);
+    const int32_t* rsp = sint + L.lds_rsptr;
     for (int r = threadIdx.x; r < C.n; r += blockDim.x) {
-      int beg, width;
-      slice_bounds(L.r_sptr, r, beg, width);
-      const int lane = r & 63;
+      const int sl = r >> 6, lane = r & 63;
+      const int beg = rsp[sl], width = rsp[sl + 1] - beg;
       T acc = T(0);
       for (int k = 0; k < width; ++k) acc += ox[L.r_col[(beg + k) * kSlice + lane]];
       Bc[r] = ox[L.r_self[r]] + T(0.5) * acc;
@@ -403,7 +467,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
     T* X0 = sm + C.lds;
     const T* B0 = X0 + 2 * (C.n + 1);
     for (int i = threadIdx.x; i < n0; i += blockDim.x) {
-      const double* a = ainv + static_cast<int64_t>(i) * n0;
+      const double* a = sinv + static_cast<int64_t>(i) * n0;
       double acc = 0.0;
       for (int j = 0; j < n0; ++j) acc += a[j] * static_cast<double>(B0[j]);
       X0[i] = static_cast<T>(acc);
@@ -413,6 +477,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
   for (int l = 1; l <= top; ++l) {
     const CoarseLevel<T>& L = lv[l];
     const CoarseLevel<T>& C = lv[l - 1];
+    const int32_t* sp = sint + L.lds_sptr;
     T* X = sm + L.lds;
     T* Tt = X + (L.n + 1);
     T* B = Tt + (L.n + 1);
@@ -422,7 +487,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
     for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] += T(0.5) * (ec[L.pa[r]] + ec[L.pb[r]]);
     __syncthreads();
     for (int it = 0; it < nu2; ++it) {
-      cc_sweep(L, cx, B, ox, omega, 2);
+      cc_sweep<T, KMAX>(L, sp, cx, B, ox, omega, 2);
       __syncthreads();
       T* tmp = cx;
       cx = ox;
@@ -500,19 +565,16 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict_
                                                       const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
-  int t0, t1;
-  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const int row = blk * kBlock + threadIdx.x;
   double v0 = 0.0, v1 = 0.0;
-  for (int t = t0; t < t1; ++t) {
-    const int row = t * kBlock + threadIdx.x;
-    if (row < n) {
-      const double pi = p[row];
-      double acc, d;
-      row_apply<double, D16>(sptr, col, w, p, row, n, pi, acc, d);
-      q[row] = acc;
-      v0 += pi * acc;
-      v1 += pi * r[row];
-    }
+  if (row < n) {
+    const double pi = p[row];
+    const double ri = r[row];
+    double acc, d;
+    row_apply<double, D16>(sptr, col, w, p, row, n, pi, acc, d);
+    q[row] = acc;
+    v0 = pi * acc;
+    v1 = pi * ri;
   }
   block_sum2(v0, v1);
   if (threadIdx.x == 0) {
@@ -562,19 +624,16 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restr
                                                           const int* __restrict__ done) {
   if (done && *done) return;
   const int blk = xcd_block();
-  int t0, t1;
-  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const int row = blk * kBlock + threadIdx.x;
   double v = 0.0;
-  for (int t = t0; t < t1; ++t) {
-    const int row = t * kBlock + threadIdx.x;
-    if (row < n) {
-      double acc, d;
-      row_apply<double, D16>(sptr, col, w, x, row, n, x[row], acc, d);
-      const double ri = b[row] - acc;
-      r[row] = ri;
-      v += ri * ri;
-      if (r32) r32[row] = static_cast<float>(ri * sc->scale);
-    }
+  if (row < n) {
+    const double bi = b[row];
+    double acc, d;
+    row_apply<double, D16>(sptr, col, w, x, row, n, x[row], acc, d);
+    const double ri = bi - acc;
+    r[row] = ri;
+    v = ri * ri;
+    if (r32) r32[row] = static_cast<float>(ri * sc->scale);
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
@@ -752,18 +811,48 @@ __global__ void k_to_f32(int32_t n, const DevScalars* __restrict__ sc, const dou
 }
 
 // One workgroup: fixed-order sum of the partials, then the scalar step `op`.
+// Starting values of the solver scalars (a kernel, so no host copy is in flight).
+__global__ void k_init_scalars(DevScalars* __restrict__ sc, double rtol, int32_t max_iter,
+                               double n_unknowns) {
+  DevScalars z = {};
+  z.rho = 1.0;
+  z.pq = 1.0;
+  z.scale = 1.0;
+  z.inv_scale = 1.0;
+  z.rtol = rtol;
+  z.max_iter = max_iter;
+  z.n_unknowns = n_unknowns;
+  *sc = z;
+}
+
 constexpr int kFinThreads = 1024;
 
 __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
                                                           const double* __restrict__ part0,
                                                           const double* __restrict__ part1,
                                                           DevScalars* __restrict__ sc,
-                                                          double extra) {
-  if (sc->done) return;
+                                                          double extra, int force) {
+  if (!force && sc->done) return;
+  // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nb; i += kFinThreads) {
-    a += part0[i];
-    if (part1) b += part1[i];
+  for (int base = 0; nb > 0 && base < nb; base += 8 * kFinThreads) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int i = base + j * kFinThreads + threadIdx.x;
+      const int ic = i < nb ? i : nb - 1;
+      va[j] = part0[ic];
+      vb[j] = part1 ? part1[ic] : 0.0;
+      if (i >= nb) {
+        va[j] = 0.0;
+        vb[j] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      a += va[j];
+      b += vb[j];
+    }
   }
   __shared__ double sa[kFinThreads / 64], sb[kFinThreads / 64];
   a = wave_sum(a);
@@ -854,12 +943,16 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       sc->mean = a / sc->n_unknowns;
       break;
     case k::FIN_RNORM:
-      sc->rnorm = sqrt(a);
+      sc->true_rnorm = sqrt(a);
       break;
   }
 }
 
 inline unsigned grid_for(int64_t n) { return static_cast<unsigned>((n + kBlock - 1) / kBlock); }
+
+inline void check_hip_k(hipError_t e) {
+  if (e != hipSuccess) throw DeviceError(std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+}
 
 }  // namespace
 
@@ -945,13 +1038,43 @@ void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s
   if (H.n0 == 0) return;
   hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(256), 0, s, H.coarse_inv, b, x, H.n0, done);
 }
+template <typename T, int K>
+static void launch_coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega,
+                                int nu1, int nu2, const int* done, hipStream_t s) {
+  const size_t bytes = coarse_lds_bytes<T>(H);
+  const size_t int_off = coarse_int_offset<T>(H);
+  const size_t inv_off = int_off - size_t(H.n0) * H.n0 * sizeof(double);
+  hipLaunchKernelGGL((k_coarse_cycle<T, K>), dim3(1), dim3(kCoarseThreads), bytes, s,
+                     coarse_levels<T>(H), top, H.coarse_inv, H.n0, int32_t(inv_off),
+                     int32_t(int_off), b, x, static_cast<T>(omega), nu1, nu2, done);
+}
+
+// Allows the fused coarse cycle its dynamic LDS (above the default 64 KiB); called once when
+// a hierarchy is built, outside any stream capture.
+void prepare_coarse(const Hierarchy& H) {
+  const int b64 = int(coarse_lds_bytes<double>(H)), b32 = int(coarse_lds_bytes<float>(H));
+  auto allow = [](const void* f, int bytes) {
+    if (bytes > 64 * 1024)
+      check_hip_k(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+  };
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle<double, 4>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle<double, 8>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle<double, 0>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 4>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 8>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 0>), b32);
+}
+
 template <typename T>
 void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2,
                   const int* done, hipStream_t s) {
-  const CoarseLevel<T>* lv = coarse_levels<T>(H);
-  const size_t bytes = coarse_lds_bytes<T>(H, top);
-  hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(kCoarseThreads), bytes, s, lv, top,
-                     H.coarse_inv, H.n0, b, x, static_cast<T>(omega), nu1, nu2, done);
+  const int kmax = H.coarse_width;
+  if (kmax <= 4)
+    launch_coarse_cycle<T, 4>(H, top, b, x, omega, nu1, nu2, done, s);
+  else if (kmax <= 8)
+    launch_coarse_cycle<T, 8>(H, top, b, x, omega, nu1, nu2, done, s);
+  else
+    launch_coarse_cycle<T, 0>(H, top, b, x, omega, nu1, nu2, done, s);
 }
 template <typename T>
 void fill(T* p, int64_t n, T v, hipStream_t s) {
@@ -992,10 +1115,10 @@ void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t
 void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, const int* done, hipStream_t s) {
   if (L.op.col16)
-    hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+    hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
                        static_cast<const void*>(L.op.col16), L.op.w64, p, q, r, part0, part1, L.n, done);
   else
-    hipLaunchKernelGGL(k_spmv_dot2<false>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+    hipLaunchKernelGGL(k_spmv_dot2<false>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
                        static_cast<const void*>(L.op.col), L.op.w64, p, q, r, part0, part1, L.n, done);
 }
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
@@ -1006,11 +1129,11 @@ void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s) {
   if (L.op.col16)
-    hipLaunchKernelGGL(k_residual_norm<true>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+    hipLaunchKernelGGL(k_residual_norm<true>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
                        static_cast<const void*>(L.op.col16), L.op.w64, x, b, r, r32, sc, part0, L.n,
                        done);
   else
-    hipLaunchKernelGGL(k_residual_norm<false>, dim3(red_blocks(L.n)), dim3(kBlock), 0, s, L.op.sptr,
+    hipLaunchKernelGGL(k_residual_norm<false>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
                        static_cast<const void*>(L.op.col), L.op.w64, x, b, r, r32, sc, part0, L.n,
                        done);
 }
@@ -1060,9 +1183,13 @@ void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const 
   hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, r, r32, done);
 }
 void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
-              double extra, hipStream_t s) {
+              double extra, int force, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, op, nblocks, part0, part1, sc,
-                     extra);
+                     extra, force);
+}
+
+void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, sc, rtol, max_iter, n_unknowns);
 }
 
 #define DECMG_INST(T)                                                                          \

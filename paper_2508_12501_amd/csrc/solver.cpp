@@ -6,7 +6,10 @@
 // enqueues `check_every` replays, then reads the flag.  Replays after convergence cost one
 // flag read per kernel.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 
@@ -98,8 +101,12 @@ template float* vcycle<float>(Hierarchy&, int, const float*, float*, const mg_op
 
 namespace {
 
-void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, double extra = 0.0) {
-  k::finalize(op, k::red_blocks(n), H.part, two ? H.part + H.part_cap : nullptr, H.scal, extra, s);
+// Finalise the partial sums of a streaming reduction over n entries (or, with `tiles`, of a
+// one-tile-per-workgroup kernel).  `force` runs it even after convergence (exit bookkeeping).
+void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, bool tiles = false,
+         bool force = false) {
+  const int nb = tiles ? k::blocks_for(n) : k::red_blocks(n);
+  k::finalize(op, nb, H.part, two ? H.part + H.part_cap : nullptr, H.scal, 0.0, force ? 1 : 0, s);
 }
 
 // One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).
@@ -139,7 +146,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   if (o.outer == MG_OUTER_IR) {
     k::axpy1(n, z, H.sx, done, s);
     k::residual_norm(F, H.sx, H.sb, H.sr, r32, H.scal, P0, done, s);
-    fin(H, k::FIN_CHECK, n, false, s);
+    fin(H, k::FIN_CHECK, n, false, s, true);
     return;
   }
   fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
@@ -148,7 +155,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   else
     k::pupdate(n, H.scal, z, H.sp, done, s);
   k::spmv_dot2(F, H.sp, H.sq, H.sr, P0, P1, done, s);
-  fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s);
+  fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s, true);
   k::update_xr(n, H.scal, H.sp, H.sq, H.sx, H.sr, r32, P0, done, s);
   fin(H, k::FIN_CHECK, n, false, s);
 }
@@ -161,7 +168,7 @@ void enqueue_cycle(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   // with an even number of sweeps per cycle the ping-pong ends in H.sx (checked by run_mg)
   (void)vcycle<double>(H, top, H.sb, H.sx, o, done, s);
   k::residual_norm(F, H.sx, H.sb, H.sr, nullptr, H.scal, H.part, done, s);
-  fin(H, k::FIN_CHECK, F.n, false, s);
+  fin(H, k::FIN_CHECK, F.n, false, s, true);
 }
 
 std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
@@ -191,18 +198,7 @@ hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
 }
 
 void init_scalars(Hierarchy& H, const mg_opts& o, hipStream_t s) {
-  DevScalars& h = *H.scal_host;
-  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-  std::memset(&h, 0, sizeof(DevScalars));
-  h.rho = 1.0;
-  h.pq = 1.0;
-  h.scale = 1.0;
-  h.inv_scale = 1.0;
-  h.rtol = o.rtol;
-  h.max_iter = o.max_iter;
-  h.n_unknowns = double(H.lv.back()->n);
-  check_hip(hipMemcpyAsync(H.scal, &h, sizeof(DevScalars), hipMemcpyHostToDevice, s),
-            "hipMemcpyAsync");
+  k::init_scalars(H.scal, o.rtol, o.max_iter, double(H.lv.back()->n), s);
 }
 
 void read_scalars(Hierarchy& H, hipStream_t s) {
@@ -229,44 +225,58 @@ void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s) {
   }
 }
 
-// Final projection, true residual, scatter to the caller's numbering.
+// Final projection, true residual, scatter to the caller's numbering; one host read.
 void finish(Hierarchy& H, const double* b_nat, double* x_nat, mg_result* res, hipStream_t s) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
-  read_scalars(H, s);
-  const DevScalars loop = *H.scal_host;
-  // exit bookkeeping runs whatever the convergence flag says
-  DevScalars& h = *H.scal_host;
-  h.done = 0;
-  check_hip(hipMemcpyAsync(&H.scal->done, &h.done, sizeof(int32_t), hipMemcpyHostToDevice, s),
-            "hipMemcpyAsync");
   if (H.bc == MG_BC_NATURAL) {
     k::sum64(n, H.sx, H.part, nullptr, s);
-    fin(H, k::FIN_MEAN, n, false, s);
+    fin(H, k::FIN_MEAN, n, false, s, false, true);
     k::sub_mean(n, H.scal, H.sx, s);
   }
   k::residual_norm(F, H.sx, H.sb, H.sz, nullptr, H.scal, H.part, nullptr, s);
-  fin(H, k::FIN_RNORM, n, false, s);
+  fin(H, k::FIN_RNORM, n, false, s, true, true);
   k::scatter<double>(F.perm, n, H.sx, x_nat, s);
   k::bnd_copy<double>(F.bnd_ids, int32_t(F.bnd_h.size()), b_nat, x_nat, s);
   read_scalars(H, s);
+  const DevScalars& h = *H.scal_host;
   if (res) {
-    res->iterations = loop.iters;
-    res->status = loop.status;
-    res->rel_residual_loop = loop.bnorm > 0 ? loop.rnorm / loop.bnorm : 0.0;
-    res->rel_residual = loop.bnorm > 0 ? H.scal_host->rnorm / loop.bnorm : 0.0;
+    res->iterations = h.iters;
+    res->status = h.status;
+    res->rel_residual_loop = h.bnorm > 0 ? h.rnorm / h.bnorm : 0.0;
+    res->rel_residual = h.bnorm > 0 ? h.true_rnorm / h.bnorm : 0.0;
   }
-  H.scal_host->status = loop.status;
 }
 
 }  // namespace
+
+// Host-side phase timing of a solve, printed to stderr when DECMG_HOST_TIMING is set.
+struct HostTimer {
+  bool on = std::getenv("DECMG_HOST_TIMING") != nullptr;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now(), last = t0;
+  char buf[512] = {0};
+  size_t len = 0;
+  void mark(const char* what) {
+    if (!on) return;
+    const auto now = std::chrono::steady_clock::now();
+    const double us = std::chrono::duration<double, std::micro>(now - last).count();
+    last = now;
+    len += size_t(std::snprintf(buf + len, sizeof(buf) - len, " %s=%.1f", what, us));
+  }
+  ~HostTimer() {
+    if (!on) return;
+    const double us = std::chrono::duration<double, std::micro>(last - t0).count();
+    std::fprintf(stderr, "[decmg host] total=%.1fus%s\n", us, buf);
+  }
+};
 
 // Enqueues iterations in batches and checks the device flag between batches.  The first batch
 // is the iteration count of the previous solve with the same settings (or check_every); later
 // batches are sized from the observed mean residual reduction per iteration, so a solve
 // normally needs one or two host round trips and runs few or no no-op iterations.
 template <typename F>
-void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue) {
+void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
+             HostTimer* T = nullptr) {
   const int every = std::max(1, o.check_every);
   auto key = graph_key(o, kind);
   auto it = H.last_iters.find(key);
@@ -276,7 +286,9 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue)
     batch = std::min(batch, o.max_iter - launched);
     for (int j = 0; j < batch; ++j) enqueue();
     launched += batch;
+    if (T) T->mark("enqueue");
     read_scalars(H, s);
+    if (T) T->mark("wait");
     const DevScalars& h = *H.scal_host;
     if (h.done) break;
     batch = every;
@@ -292,6 +304,7 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue)
 
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
             hipStream_t s) {
+  HostTimer T;
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   init_scalars(H, o, s);
@@ -302,14 +315,17 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   check_hip(hipMemcpyAsync(H.sr, H.sb, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
             "hipMemcpyAsync");
   if (o.precision == MG_F32) k::to_f32(n, H.scal, H.sr, F.v32.b, nullptr, s);
+  T.mark("setup");
   hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 0) : nullptr;
+  T.mark("graph");
   iterate(H, o, 0, s, [&]() {
     if (g)
       check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
     else
       enqueue_iteration(H, o, s);
-  });
+  }, &T);
   finish(H, b_nat, x_nat, res, s);
+  T.mark("finish");
   return H.scal_host->status;
 }
 

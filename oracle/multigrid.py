@@ -307,3 +307,24 @@ def contraction_factor(hist, tail: int = 5) -> float:
     h = h[h > 0]
     k = min(tail, len(h) - 1)
     return float((h[-1] / h[-1 - k]) ** (1.0 / k))
+
+
+def solve_adjoint(h: Hierarchy, u, grad_u):
+    """Reverse-mode derivative of the exact solve u = A^{-1} b (A^+ b when singular) for a
+    loss J(u) with upstream gradient grad_u (Sec. 3.3 differentiates through the solver).
+
+    lambda = A^{-T} grad_u = A^{-1} grad_u (A symmetric) is dJ/db.  With the finest-level
+    edge weights w_e = star1_e k_e, k_e = (k_lo + k_hi) / 2 (reading Q13), dA/dk_e =
+    star1_e (M d0_e)^T (M d0_e) where M masks Dirichlet vertices (identity otherwise), so
+    dJ/dk_e = -lambda^T (dA/dk_e) u = -star1_e (d0 M lambda)_e (d0 M u)_e and
+    dJ/dk_v = 1/2 sum over the edges at v of dJ/dk_e.  Coarser levels only shape the
+    preconditioner and do not enter the exact solution.  Returns (dJ/db, dJ/dk_v)."""
+    lv = h.fine
+    lam = direct_solve(h, grad_u)
+    m = np.ones(lv.nv)
+    if h.bc == "dirichlet":
+        m[lv.bnd] = 0.0
+    d0 = sp.csr_matrix(lv.d0, dtype=np.float64)
+    gk_e = -lv.star1 * (d0 @ (m * lam)) * (d0 @ (m * u))
+    gk_v = 0.5 * (abs(d0).T @ gk_e)
+    return lam, gk_v

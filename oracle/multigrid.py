@@ -293,11 +293,13 @@ def direct_solve(h: Hierarchy, b):
     A = h.fine.A
     if h.bc == "dirichlet":
         return spla.spsolve(sp.csc_matrix(A), b)
-    n = A.shape[0]
-    one = np.ones((n, 1))
-    K = sp.bmat([[A, sp.csr_matrix(one)], [sp.csr_matrix(one.T), None]], format="csc")
-    sol = spla.spsolve(K, np.concatenate([b, [0.0]]))
-    return sol[:n]
+    # natural boundary (Q9): b is compatible after the projection, so every solution differs
+    # from A^+ b by a constant; ground vertex 0, solve the remaining nonsingular system, then
+    # remove the mean
+    A = sp.csc_matrix(A)
+    x = np.zeros(A.shape[0])
+    x[1:] = spla.spsolve(A[1:, 1:], b[1:])
+    return x - x.mean()
 
 
 def contraction_factor(hist, tail: int = 5) -> float:

@@ -60,6 +60,7 @@ class PorousModel:
         self.ke = 0.5 * (self.kv[e[:, 0]] + self.kv[e[:, 1]])
         self.W = self.star1 * self.ke
         self.LK = self.lv.A                             # d0^T diag(W) d0 (set_vertex_coeff)
+        self._lu = None
 
     # -- pieces of one step
     def buoyancy(self, T):
@@ -68,7 +69,15 @@ class PorousModel:
     def solve(self, rhs):
         """Zero-mean solution of L_K p = rhs."""
         if self.solver == "direct":
-            return omg.direct_solve(self.h, rhs)
+            # the definition of multigrid.direct_solve (ground vertex 0, solve, remove the
+            # mean) with the sparse LU factor kept while k does not change
+            if self._lu is None:
+                import scipy.sparse.linalg as spla
+                self._lu = spla.splu(sp.csc_matrix(self.LK)[1:, 1:])
+            b = rhs - rhs.mean()
+            x = np.zeros_like(b)
+            x[1:] = self._lu.solve(b[1:])
+            return x - x.mean()
         x, _, _ = omg.mg_pcg(self.h, rhs, rtol=self.rtol)
         return x
 

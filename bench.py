@@ -77,6 +77,24 @@ def kernel_bytes(info, dtype_bytes, kind):
     raise ValueError(kind)
 
 
+def recorded_traffic(kernel_key):
+    """HBM bytes per launch of `kernel_key` from the committed rocprofv3 --pmc summary, or None
+    when the kernels have changed since the counters were taken (source hash differs)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "c3_finest_kernels_hbm_traffic.md")
+    src = os.path.join(ROOT, "paper_2508_12501_amd", "csrc", "kernels.hip")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+    except Exception:
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["kernels_hip_sha256"]:
+        return None
+    k = rec["kernels"].get(kernel_key)
+    return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
 def cpu_baseline(b_nat_np, rtol):
     """The FP64 oracle's MG-PCG on the same system, one thread, timed on the host."""
     try:
@@ -228,7 +246,9 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": recorded_traffic("k_rows<float, 2, %s>@%d" % (
+                "true" if info["index_bytes"] == 2 else "false", (unknowns + 255) // 256 * 256)),
+            "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": by_j32,
             "ms_per_launch": ms_j32,
             "launches_timed": n_probe,

@@ -186,6 +186,48 @@ mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x
 mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
                  mg_result* res, void* stream);
 
+/* Adjoint of mg_pcg (Sec. 3.3, reverse-mode differentiation through the solve).  For
+ * u = A^-1 b (A^+ on natural-BC hierarchies) and an upstream gradient g_u = dJ/du, solves
+ * A lambda = g_u with the same options and returns dJ/db = lambda in grad_b (nv doubles).
+ * When grad_k is not null it ACCUMULATES dJ/dk_v for the vertex coefficient k
+ * (k_e = (k_lo + k_hi)/2 on the finest level): grad_k_v += 1/2 sum over the edges e at v of
+ * -star1_e (d0 lambda)_e (d0 u)_e, with u the solution the forward call returned (u_fine,
+ * nv doubles; boundary vertices of a Dirichlet hierarchy count as zero).  All vectors are
+ * device pointers in natural vertex order on the finest level. */
+mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine,
+                         const double* grad_u, double* grad_b, double* grad_k, mg_result* res,
+                         void* stream);
+
+/* ------------------------------------------------------------------ porous convection
+ * One forward-Euler step of the Darcy-Boussinesq model of Sec. 3.2 (scaled form: advection
+ * factor 1/phi, diffusivity kappa = 1/(phi Ra)) on the finest level of a natural-BC hierarchy
+ * of a mesh in the plane, with permeability k = the hierarchy's vertex coefficient:
+ *   b1_e = (y_hi - y_lo)(T_lo + T_hi)/2                 buoyancy 1-form
+ *   L_K p = d0^T W b1,  W = star1 k_e                    pressure (zero-mean, MG-PCG)
+ *   q = -k_e (d0 p - b1)                                 Darcy flux
+ *   T' = T + dt mask/star0 ( -(1/phi) 1/2 |d0|^T (star1 q d0 T) - kappa L T )
+ * where mask is 0 on the vertices with the smallest and the largest y (fixed temperature
+ * walls) and 1 elsewhere. */
+typedef struct {
+  double Ra;        /* Rayleigh number (> 0) */
+  double phi;       /* porosity (> 0) */
+  double dt;        /* time step (> 0) */
+  mg_opts solve;    /* options of the pressure solves (mg_pcg) */
+} porous_params;
+
+/* T_out = step(T).  p (nullable) receives the pressure.  res (nullable) reports the pressure
+ * solve.  T, T_out, p: nv doubles on the device, natural order; T_out must not alias T.
+ * MG_EINVAL for a hierarchy with Dirichlet boundaries or a non-positive parameter. */
+mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T, double* T_out,
+                      double* p, mg_result* res, void* stream);
+/* Transpose of the step's Jacobian: lambda_out = (dT'/dT)^T lambda, with the pressure solve
+ * differentiated through (one adjoint-pressure solve).  p (nullable) is the pressure that
+ * porous_step returned for this T (recomputed when null).  grad_k (nullable) ACCUMULATES
+ * lambda^T dT'/dk_v (nv doubles).  lambda_out must not alias lambda. */
+mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const double* T,
+                              const double* p, const double* lambda, double* lambda_out,
+                              double* grad_k, void* stream);
+
 /* ------------------------------------------------------------------ measurement
  * Times `reps` back-to-back launches of one kernel of the path on `level` with hipEvents
  * recorded on `stream`, and returns the mean duration per launch in milliseconds.
@@ -196,7 +238,8 @@ mg_status mg_time_kernel(mg_hierarchy* h, int32_t kernel, int32_t level, int32_t
 
 /* In-solve timing of the smoother.  Between mg_probe_begin and mg_probe_end, every weighted-
  * Jacobi sweep kernel that an eager solve (use_graph = 0) launches on `level` in arithmetic
- * `dtype` is bracketed by hipEvents on the solve's stream.  mg_probe_end synchronises that
+ * `dtype` is launched with start/stop hipEvents stamped by its dispatch on the solve's stream
+ * (kernel execution time).  mg_probe_end synchronises that
  * stream and returns the mean duration per launch and the number of launches.  Sweeps replayed
  * from a captured graph are not probed. */
 mg_status mg_probe_begin(mg_hierarchy* h, int32_t level, int32_t dtype);

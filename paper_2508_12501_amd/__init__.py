@@ -71,6 +71,11 @@ class mg_result(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class porous_params(ctypes.Structure):
+    _fields_ = [("Ra", ctypes.c_double), ("phi", ctypes.c_double), ("dt", ctypes.c_double),
+                ("solve", mg_opts)]
+
+
 _vp = ctypes.c_void_p
 _i32 = ctypes.c_int32
 _i64 = ctypes.c_int64
@@ -96,6 +101,12 @@ _PROTOS = {
     "mg_vcycle": (_i32, [_vp, ctypes.POINTER(mg_opts), _i32, _i32, _vp, _vp, _vp]),
     "mg_solve": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
     "mg_pcg": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
+    "mg_pcg_adjoint": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, _vp, _vp,
+                              ctypes.POINTER(mg_result), _vp]),
+    "porous_step": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp,
+                           ctypes.POINTER(mg_result), _vp]),
+    "porous_step_adjoint": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp, _vp, _vp,
+                                   _vp]),
     "mg_time_kernel": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_d)]),
     "mg_probe_begin": (_i32, [_vp, _i32, _i32]),
     "mg_probe_end": (_i32, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
@@ -309,6 +320,55 @@ def mg_pcg(h, opts: mg_opts, b, x, stream=None, raise_on_error=True) -> mg_resul
     if raise_on_error:
         _check(st, res)
     return res
+
+
+def _opt_ptr(t, dtype, n, name):
+    return ctypes.c_void_p(None) if t is None else _ptr(t, dtype, n, name)
+
+
+def mg_pcg_adjoint(h, opts: mg_opts, u, grad_u, grad_b, grad_k=None, stream=None,
+                   raise_on_error=True) -> mg_result:
+    """grad_b = A^-1 grad_u; grad_k (if given) += dJ/dk at the vertices (accumulates)."""
+    import torch
+    res = mg_result()
+    n = _nv(h, _top(h))
+    st = lib().mg_pcg_adjoint(h, ctypes.byref(opts), _opt_ptr(u, torch.float64, n, "u"),
+                              _ptr(grad_u, torch.float64, n, "grad_u"),
+                              _ptr(grad_b, torch.float64, n, "grad_b"),
+                              _opt_ptr(grad_k, torch.float64, n, "grad_k"), ctypes.byref(res),
+                              _stream(stream))
+    if raise_on_error:
+        _check(st, res)
+    return res
+
+
+def porous_params_make(Ra: float, phi: float, dt: float, solve: mg_opts | None = None) -> porous_params:
+    p = porous_params()
+    p.Ra, p.phi, p.dt = float(Ra), float(phi), float(dt)
+    p.solve = solve if solve is not None else mg_opts_default()
+    return p
+
+
+def porous_step(h, prm: porous_params, T, T_out, p=None, stream=None, raise_on_error=True) -> mg_result:
+    import torch
+    res = mg_result()
+    n = _nv(h, _top(h))
+    st = lib().porous_step(h, ctypes.byref(prm), _ptr(T, torch.float64, n, "T"),
+                           _ptr(T_out, torch.float64, n, "T_out"), _opt_ptr(p, torch.float64, n, "p"),
+                           ctypes.byref(res), _stream(stream))
+    if raise_on_error:
+        _check(st, res)
+    return res
+
+
+def porous_step_adjoint(h, prm: porous_params, T, p, lam, lam_out, grad_k=None, stream=None):
+    import torch
+    n = _nv(h, _top(h))
+    _check(lib().porous_step_adjoint(h, ctypes.byref(prm), _ptr(T, torch.float64, n, "T"),
+                                     _opt_ptr(p, torch.float64, n, "p"),
+                                     _ptr(lam, torch.float64, n, "lambda"),
+                                     _ptr(lam_out, torch.float64, n, "lambda_out"),
+                                     _opt_ptr(grad_k, torch.float64, n, "grad_k"), _stream(stream)))
 
 
 def mg_time_kernel(h, kernel: int, level: int, dtype: int, reps: int, stream=None) -> float:

@@ -288,6 +288,7 @@ mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex,
         return fail(MG_EINVAL, "vertex coefficients must be finite and positive");
     H.kvert_h = std::move(kv);
   }
+  ++H.kversion;
   decmg::upload_weights(H);
   API_END
   return MG_OK;
@@ -416,6 +417,65 @@ mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x, 
   API_BEGIN
   const int st = decmg::run_pcg(*h->h, *o, b, x, res, S(stream));
   if (st != MG_OK) return fail(mg_status(st), "mg_pcg stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine,
+                         const double* grad_u, double* grad_b, double* grad_k, mg_result* res,
+                         void* stream) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (!grad_u || !grad_b) return fail(MG_EINVAL, "null vector");
+  if (grad_k && !u_fine) return fail(MG_EINVAL, "grad_k needs the forward solution u_fine");
+  API_BEGIN
+  const int st = decmg::run_pcg_adjoint(*h->h, *o, u_fine, grad_u, grad_b, grad_k, res, S(stream));
+  if (st != MG_OK)
+    return fail(mg_status(st), "mg_pcg_adjoint stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+namespace {
+mg_status check_porous(const mg_hierarchy* h, const porous_params* p) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  if (!p) return fail(MG_EINVAL, "null parameters");
+  if (h->h->bc != MG_BC_NATURAL)
+    return fail(MG_EINVAL, "the porous step needs a hierarchy with natural boundaries");
+  if (!(p->Ra > 0) || !(p->phi > 0) || !(p->dt > 0) || !std::isfinite(p->Ra) ||
+      !std::isfinite(p->phi) || !std::isfinite(p->dt))
+    return fail(MG_EINVAL, "Ra, phi and dt must be finite and positive");
+  return check_opts(&p->solve);
+}
+decmg::PorousParams porous_of(const porous_params* p) {
+  return decmg::PorousParams{p->Ra, p->phi, p->dt, p->solve};
+}
+}  // namespace
+
+mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T, double* T_out,
+                      double* p, mg_result* res, void* stream) {
+  if (mg_status st = check_porous(h, prm); st != MG_OK) return st;
+  if (!T || !T_out) return fail(MG_EINVAL, "null vector");
+  if (T == T_out) return fail(MG_EINVAL, "T_out must not alias T");
+  API_BEGIN
+  const int st = decmg::run_porous_step(*h->h, porous_of(prm), T, T_out, p, res, S(stream));
+  if (st != MG_OK)
+    return fail(mg_status(st), "porous_step pressure solve stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const double* T,
+                              const double* p, const double* lambda, double* lambda_out,
+                              double* grad_k, void* stream) {
+  if (mg_status st = check_porous(h, prm); st != MG_OK) return st;
+  if (!T || !lambda || !lambda_out) return fail(MG_EINVAL, "null vector");
+  if (lambda == lambda_out) return fail(MG_EINVAL, "lambda_out must not alias lambda");
+  API_BEGIN
+  const int st = decmg::run_porous_adjoint(*h->h, porous_of(prm), T, p, lambda, lambda_out,
+                                           grad_k, S(stream));
+  if (st != MG_OK)
+    return fail(mg_status(st), "porous_step_adjoint solve stopped with status " + std::to_string(st));
   API_END
   return MG_OK;
 }

@@ -107,6 +107,27 @@ struct DevScalars {
   int32_t done, iters, status, max_iter;
 };
 
+// Finest-level data of the porous-convection step and of the solve gradients (built on first
+// use; edge coefficients refreshed when the vertex coefficient changes).
+struct PorousData {
+  bool ready = false;
+  int64_t kversion = -1;
+  double* s1 = nullptr;      // per SELL entry: star1 of the entry's edge (0 for padding)
+  double* ke = nullptr;      // per SELL entry: (k_lo + k_hi)/2
+  double* y = nullptr;       // per unknown (n + 1): y coordinate
+  double* star0 = nullptr;   // per unknown (n + 1)
+  double* mask = nullptr;    // per unknown (n + 1): 0 on the walls y = y_min and y = y_max
+  int32_t ne = 0;
+  int32_t* ea = nullptr;     // per edge: internal id of (lo, hi), or n when not an unknown
+  int32_t* eb = nullptr;
+  double* s1e = nullptr;     // per edge: star1
+  double* ge = nullptr;      // per edge scratch
+  int64_t* vptr = nullptr;   // natural vertex -> incident edges
+  int32_t* vinc = nullptr;
+  double *T = nullptr, *T2 = nullptr, *P = nullptr, *Lm = nullptr, *L2 = nullptr, *M = nullptr,
+         *U = nullptr;       // internal work vectors (n + 1)
+};
+
 struct Hierarchy {
   int32_t bc = MG_BC_DIRICHLET0;
   bool project = false;
@@ -114,6 +135,8 @@ struct Hierarchy {
   double* coarse_inv = nullptr;    // n0 x n0 FP64 inverse of the coarsest operator
   int32_t n0 = 0;
   std::vector<double> kvert_h;     // vertex coefficient (finest), empty = 1
+  int64_t kversion = 0;            // bumped by every change of the vertex coefficient
+  PorousData por;
   // solver workspace (finest level, internal numbering, n+1 entries)
   double *sx = nullptr, *sr = nullptr, *sp = nullptr, *sq = nullptr, *sz = nullptr,
          *sb = nullptr;
@@ -169,6 +192,7 @@ template <typename T> void residual(const Level& L, const T* x, const T* b, T* r
 template <typename T> void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s);
+template <typename T> void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done, hipStream_t s);
 template <typename T> void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done, hipStream_t s);
 template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);
@@ -181,6 +205,22 @@ template <typename T> void bnd_jacobi(const int32_t* ids, int32_t nb, const T* b
 template <typename T> void bnd_zero(const int32_t* ids, int32_t nb, T* x, hipStream_t s);
 void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t s);
 void prepare_coarse(const Hierarchy& H);
+
+// porous step and solve gradients (porous.hip)
+void por_rhs(const Level& L, const PorousData& D, const double* T, double* rhs, hipStream_t s);
+void por_update(const Level& L, const PorousData& D, const double* T, const double* P, double* Tout,
+                double dt, double phi, double Ra, hipStream_t s);
+void por_mu(const Level& L, const PorousData& D, const double* lam, double* mu, hipStream_t s);
+void por_adj_rhs(const Level& L, const PorousData& D, const double* T, const double* mu,
+                 double* rhs, hipStream_t s);
+void por_adj_update(const Level& L, const PorousData& D, const double* T, const double* P,
+                    const double* mu, const double* lam, const double* psi, double* lam_out,
+                    double dt, double phi, double Ra, hipStream_t s);
+void por_grad_k(const Level& L, const PorousData& D, const double* T, const double* P,
+                const double* mu, const double* psi, double* gk_nat, double dt, double phi,
+                hipStream_t s);
+void mg_grad_k(const Level& L, const PorousData& D, const double* lam, const double* u,
+               double* gk_nat, hipStream_t s);
 
 // Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
 int blocks_for(int32_t n);

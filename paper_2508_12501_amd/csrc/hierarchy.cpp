@@ -8,6 +8,7 @@
 #include <stdexcept>
 
 #include "hier.hpp"
+#include "solver.hpp"
 #include "util.hpp"
 
 namespace decmg {
@@ -512,6 +513,7 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
 
 Hierarchy::~Hierarchy() {
   for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+  free_porous(*this);
   for (auto& Lp : lv) {
     Level& L = *Lp;
     for (void* p : {(void*)L.perm, (void*)L.bnd_ids, (void*)L.star0, (void*)L.op.sptr,

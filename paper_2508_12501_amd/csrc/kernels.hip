@@ -7,6 +7,7 @@
 // turn) walks one contiguous range of rows and its neighbour gathers stay in its own L2.
 // Reductions are deterministic: wavefront butterflies, a fixed-order combine of the four
 // wavefronts, per-block partials, then one fixed-order finalisation block.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -988,6 +989,22 @@ static void rows(const Level& L, const T* x, const T* b, T* y, double omega, con
                        static_cast<const void*>(L.op.col), weights<T>(L), x, b, y, L.n,
                        static_cast<T>(omega), done);
 }
+// A weighted-Jacobi sweep whose start and stop are stamped into e0/e1 by the dispatch
+// itself (kernel execution time only, no queueing between the two events).
+template <typename T>
+void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done,
+                  hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  if (L.n == 0) return;
+  if (L.op.col16)
+    hipExtLaunchKernelGGL((k_rows<T, 2, true>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0, e1, 0,
+                          L.op.sptr, static_cast<const void*>(L.op.col16), weights<T>(L), x, b, xo,
+                          L.n, static_cast<T>(omega), done);
+  else
+    hipExtLaunchKernelGGL((k_rows<T, 2, false>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0, e1, 0,
+                          L.op.sptr, static_cast<const void*>(L.op.col), weights<T>(L), x, b, xo,
+                          L.n, static_cast<T>(omega), done);
+}
+
 template <typename T>
 void spmv(const Level& L, const T* x, T* y, const int* done, hipStream_t s) {
   rows<T, 0>(L, x, static_cast<const T*>(nullptr), y, 0.0, done, s);
@@ -1198,6 +1215,8 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
   template void jacobi<T>(const Level&, const T*, const T*, T*, double, const int*, hipStream_t); \
   template void jacobi_zero<T>(const Level&, const T*, T*, double, const int*, hipStream_t);    \
   template void jacobi_two<T>(const Level&, const T*, T*, double, const int*, hipStream_t);     \
+  template void jacobi_timed<T>(const Level&, const T*, const T*, T*, double, const int*,        \
+                                hipStream_t, hipEvent_t, hipEvent_t);                           \
   template void restrict_<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t); \
   template void prolong<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t);  \
   template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \

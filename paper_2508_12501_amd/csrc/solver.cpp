@@ -33,18 +33,16 @@ static void sweep(Hierarchy& H, int l, const T* x, const T* b, T* xo, double ome
                   hipStream_t s) {
   Hierarchy::Probe& P = H.probe;
   const bool timed = P.on && !H.capturing && P.level == l && P.dtype == dtype_of<T>();
+  if (!timed) {
+    k::jacobi<T>(*H.lv[l], x, b, xo, omega, done, s);
+    return;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed) {
-    check_hip(hipEventCreate(&e0), "hipEventCreate");
-    check_hip(hipEventCreate(&e1), "hipEventCreate");
-    check_hip(hipEventRecord(e0, s), "hipEventRecord");
-  }
-  k::jacobi<T>(*H.lv[l], x, b, xo, omega, done, s);
-  if (timed) {
-    check_hip(hipEventRecord(e1, s), "hipEventRecord");
-    P.ev.emplace_back(e0, e1);
-    P.stream = s;
-  }
+  check_hip(hipEventCreate(&e0), "hipEventCreate");
+  check_hip(hipEventCreate(&e1), "hipEventCreate");
+  k::jacobi_timed<T>(*H.lv[l], x, b, xo, omega, done, s, e0, e1);
+  P.ev.emplace_back(e0, e1);
+  P.stream = s;
 }
 
 template <typename T>
@@ -209,19 +207,23 @@ void read_scalars(Hierarchy& H, hipStream_t s) {
 }
 
 // b (natural, nv) -> H.sb (internal); ||b|| with the boundary part; projected for natural.
+// With b_nat == nullptr the internal right-hand side is already in H.sb.
 void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
-  k::gather<double>(F.perm, n, b_nat, H.sb, s);
+  if (b_nat) k::gather<double>(F.perm, n, b_nat, H.sb, s);
   if (H.bc == MG_BC_NATURAL) {
     k::sum64(n, H.sb, H.part, nullptr, s);
     fin(H, k::FIN_MEAN, n, false, s);
     k::sub_mean(n, H.scal, H.sb, s);
     k::dot(n, H.sb, H.sb, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, n, false, s);
-  } else {
+  } else if (b_nat) {
     k::dot(F.nv, b_nat, b_nat, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, F.nv, false, s);
+  } else {
+    k::dot(n, H.sb, H.sb, H.part, nullptr, s);
+    fin(H, k::FIN_BNORM, n, false, s);
   }
 }
 
@@ -236,8 +238,10 @@ void finish(Hierarchy& H, const double* b_nat, double* x_nat, mg_result* res, hi
   }
   k::residual_norm(F, H.sx, H.sb, H.sz, nullptr, H.scal, H.part, nullptr, s);
   fin(H, k::FIN_RNORM, n, false, s, true, true);
-  k::scatter<double>(F.perm, n, H.sx, x_nat, s);
-  k::bnd_copy<double>(F.bnd_ids, int32_t(F.bnd_h.size()), b_nat, x_nat, s);
+  if (x_nat) {
+    k::scatter<double>(F.perm, n, H.sx, x_nat, s);
+    k::bnd_copy<double>(F.bnd_ids, int32_t(F.bnd_h.size()), b_nat, x_nat, s);
+  }
   read_scalars(H, s);
   const DevScalars& h = *H.scal_host;
   if (res) {

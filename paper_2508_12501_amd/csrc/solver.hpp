@@ -21,4 +21,18 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
 int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
            hipStream_t s);
 
+// porous step, its adjoint and the adjoint of mg_pcg (porous.cpp)
+struct PorousParams {
+  double Ra, phi, dt;
+  mg_opts solve;
+};
+int run_porous_step(Hierarchy& H, const PorousParams& p, const double* T_nat, double* Tout_nat,
+                    double* p_nat, mg_result* res, hipStream_t s);
+int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
+                       const double* p_nat, const double* lam_nat, double* lam_out_nat,
+                       double* gk_nat, hipStream_t s);
+int run_pcg_adjoint(Hierarchy& H, const mg_opts& o, const double* u_nat, const double* gu_nat,
+                    double* gb_nat, double* gk_nat, mg_result* res, hipStream_t s);
+void free_porous(Hierarchy& H);
+
 }  // namespace decmg

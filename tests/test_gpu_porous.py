@@ -1,0 +1,264 @@
+"""GPU parity of the porous-convection step (Sec. 3.2), its adjoint, and the differentiable
+solve, through the C-ABI, against the FP64 oracle (oracle/porous.py, multigrid.solve_adjoint).
+
+Tolerances (relative L2):
+* pressure and the step increment T' - T, GPU MG-PCG at rtol 1e-13 vs the oracle's exact
+  solve: 1e-10 (the solve tolerance times the operator's condition number bounds the gap);
+* adjoint step (lambda' - lambda and dJ/dk) and the rollout gradients: 1e-9;
+* the conductive state T = 1 - y: T unchanged to 1e-13 absolute (linear precision);
+* finite differences of the GPU rollout along seeded directions: 1e-6 (Q18).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2508_12501_amd as mg  # noqa: E402
+from paper_2508_12501_amd import autograd as mga  # noqa: E402
+from oracle import dec  # noqa: E402
+from oracle import multigrid as omg  # noqa: E402
+from oracle import porous as op  # noqa: E402
+import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+RA, PHI = W.C5["Ra"], W.C5["phi"]
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+def gpu(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def tight():
+    return mg.mg_opts_default(rtol=1e-13)
+
+
+class PorousPair:
+    """Natural-BC square hierarchy in the library and in the oracle, with g from the C5
+    recipe (white noise smoothed by weighted Jacobi on the unit-k operator) times `amp`."""
+
+    def __init__(self, base_cells, nsub, amp=1.0):
+        print(f"[porous] base={base_cells} nsub={nsub} amp={amp}", flush=True)
+        self.g = mg.Hierarchy("square", nsub, base_cells=base_cells, bc=mg.MG_BC_NATURAL)
+        xyz, tri = dec.square_grid(base_cells)
+        self.o = omg.Hierarchy(xyz, tri, nsub, bc="natural")
+        nv = self.o.fine.nv
+        self.nv = nv
+        noise = W.c5_logk_noise(nv)
+        # g on the GPU: Jacobi sweeps with zero right-hand side on the unit-k operator
+        gg = gpu(noise)
+        mg.mg_smooth(self.g.h, self.g.top, W.C5["g_smooth_sweeps"], W.C5["g_smooth_omega"],
+                     torch.zeros_like(gg), gg)
+        self.g_gpu = gg * amp
+        self.g_ref = op.smooth_logk(self.o, noise, W.C5["g_smooth_sweeps"],
+                                    W.C5["g_smooth_omega"]) * amp
+        self.model = op.PorousModel(self.o, self.g_ref, Ra=RA, phi=PHI)
+        self.dt = self.model.dt
+        self.T0 = W.c5_initial_temperature(self.o.fine.xyz)
+        mg.mg_hierarchy_set_vertex_coeff(self.g.h, torch.exp(self.g_gpu))
+
+    def prm(self, rtol=1e-13):
+        return mg.porous_params_make(RA, PHI, self.dt, mg.mg_opts_default(rtol=rtol))
+
+
+@pytest.fixture(scope="module")
+def p65():
+    return PorousPair(4, 4, amp=5.0)
+
+
+@pytest.fixture(scope="module")
+def p25():
+    # 3x3 base: 625 vertices, not a multiple of 64 (ragged last slice)
+    return PorousPair(3, 3, amp=5.0)
+
+
+PAIRS = ["p65", "p25"]
+
+
+def test_logk_smoothing_matches_oracle(p65):
+    assert rel(host(p65.g_gpu), p65.g_ref) <= 1e-14
+
+
+@pytest.mark.parametrize("which", PAIRS)
+def test_porous_step(which, request):
+    P = request.getfixturevalue(which)
+    mg.mg_hierarchy_set_vertex_coeff(P.g.h, torch.exp(P.g_gpu))
+    T = gpu(P.T0)
+    Tn = torch.empty_like(T)
+    p = torch.empty_like(T)
+    res = mg.porous_step(P.g.h, P.prm(), T, Tn, p)
+    Tr, pr = P.model.step(P.T0)
+    ep, ed = rel(host(p), pr), rel(host(Tn) - P.T0, Tr - P.T0)
+    print(f"[porous] {which}: pressure iterations {res.iterations}, rel p {ep:.2e}, "
+          f"rel dT {ed:.2e}")
+    assert ep <= 1e-10 and ed <= 1e-10
+    # the wall rows do not move
+    y = P.o.fine.xyz[:, 1]
+    wall = (y == 0.0) | (y == 1.0)
+    assert np.array_equal(host(Tn)[wall], P.T0[wall])
+
+
+def test_porous_conductive_state(p65):
+    """T = 1 - y is a steady state for any k: p = y - y^2/2 (zero mean), q = 0."""
+    y = p65.o.fine.xyz[:, 1]
+    T0 = 1.0 - y
+    T = gpu(T0)
+    Tn = torch.empty_like(T)
+    p = torch.empty_like(T)
+    mg.porous_step(p65.g.h, p65.prm(), T, Tn, p)
+    pe = y - 0.5 * y * y
+    pe -= pe.mean()
+    assert np.abs(host(Tn) - T0).max() <= 1e-13
+    assert rel(host(p), pe) <= 1e-10
+
+
+@pytest.mark.parametrize("which", PAIRS)
+@pytest.mark.parametrize("give_p", [False, True])
+def test_porous_adjoint_step(which, give_p, request):
+    P = request.getfixturevalue(which)
+    mg.mg_hierarchy_set_vertex_coeff(P.g.h, torch.exp(P.g_gpu))
+    lam0 = W.normal(P.nv, 77)
+    T = gpu(P.T0)
+    p = None
+    if give_p:
+        p = torch.empty_like(T)
+        mg.porous_step(P.g.h, P.prm(), T, torch.empty_like(T), p)
+    lo = torch.empty_like(T)
+    gk = torch.zeros_like(T)
+    mg.porous_step_adjoint(P.g.h, P.prm(), T, p, gpu(lam0), lo, gk)
+    lr, gr = P.model.step_adjoint(P.T0, lam0)
+    el, eg = rel(host(lo) - lam0, lr - lam0), rel(host(gk), gr)
+    print(f"[porous] {which} adjoint (p given {give_p}): rel dlambda {el:.2e}, rel dJ/dk {eg:.2e}")
+    assert el <= 1e-9 and eg <= 1e-9
+
+
+def test_porous_adjoint_accumulates(p25):
+    mg.mg_hierarchy_set_vertex_coeff(p25.g.h, torch.exp(p25.g_gpu))
+    T = gpu(p25.T0)
+    lam = gpu(W.normal(p25.nv, 78))
+    base = gpu(W.normal(p25.nv, 79))
+    gk = base.clone()
+    lo = torch.empty_like(T)
+    mg.porous_step_adjoint(p25.g.h, p25.prm(), T, None, lam, lo, gk)
+    gk0 = torch.zeros_like(T)
+    mg.porous_step_adjoint(p25.g.h, p25.prm(), T, None, lam, lo, gk0)
+    assert rel(host(gk) - host(base), host(gk0)) <= 1e-13
+
+
+def test_rollout_gradient_matches_oracle(p65):
+    steps, ckpt = 12, 5
+    w = W.c5_loss_weights(p65.nv)
+    J, gg, gT = p65.model.loss_and_grad(p65.T0, w, steps, ckpt)
+    g = p65.g_gpu.clone().requires_grad_(True)
+    T0 = gpu(p65.T0).requires_grad_(True)
+    TN = mga.porous_rollout(p65.g, T0, g, steps, RA, PHI, p65.dt, ckpt=ckpt)
+    Jg = (TN * gpu(w)).sum()
+    Jg.backward()
+    ej, eg, eT = abs(Jg.item() - J) / abs(J), rel(host(g.grad), gg), rel(host(T0.grad), gT)
+    print(f"[porous] rollout {steps} steps: rel J {ej:.2e}, rel dJ/dg {eg:.2e}, rel dJ/dT0 {eT:.2e}")
+    assert ej <= 1e-12 and eg <= 1e-9 and eT <= 1e-9
+
+
+def test_rollout_finite_differences(p25):
+    """Central differences of the GPU rollout along seeded directions in g and in T0.  The
+    step is 1e-3 (ten steps stay bounded) so that J depends on g well above rounding; the
+    g difference step is 1e-4, where the central-difference error measured with the oracle
+    is below 1e-7."""
+    steps, ckpt, dt = 10, 3, 1e-3
+    w = gpu(W.c5_loss_weights(p25.nv))
+
+    def J(g, T0):
+        with torch.no_grad():
+            return float((mga.porous_rollout(p25.g, T0, g, steps, RA, PHI, dt, ckpt=ckpt) * w).sum())
+
+    g = p25.g_gpu.clone().requires_grad_(True)
+    T0 = gpu(p25.T0).requires_grad_(True)
+    (mga.porous_rollout(p25.g, T0, g, steps, RA, PHI, dt, ckpt=ckpt) * w).sum().backward()
+    for seed in (91, 92):
+        d = gpu(W.normal(p25.nv, seed))
+        eps = 1e-4
+        fd = (J(p25.g_gpu + eps * d, gpu(p25.T0)) - J(p25.g_gpu - eps * d, gpu(p25.T0))) / (2 * eps)
+        an = float((g.grad * d).sum())
+        print(f"[porous] FD in g (seed {seed}): fd {fd:.10e} adjoint {an:.10e}")
+        assert abs(fd - an) <= 1e-6 * abs(an)
+        eps = 1e-6
+        fd = (J(p25.g_gpu, gpu(p25.T0) + eps * d) - J(p25.g_gpu, gpu(p25.T0) - eps * d)) / (2 * eps)
+        an = float((T0.grad * d).sum())
+        assert abs(fd - an) <= 1e-6 * abs(an)
+
+
+@pytest.mark.parametrize("kind", ["square", "sphere"])
+def test_mg_solve_autograd(kind):
+    if kind == "square":
+        g = mg.Hierarchy("square", 4)
+        xyz, tri = dec.square_grid(4)
+        o = omg.Hierarchy(xyz, tri, 4)
+    else:
+        g = mg.Hierarchy("sphere", 4)
+        xyz, tri = dec.icosahedron()
+        o = omg.Hierarchy(xyz, tri, 4, project=True, bc="natural")
+    nv = o.fine.nv
+    kv = np.exp(0.3 * W.normal(nv, 55))
+    o.set_vertex_coeff(kv)
+    b0 = o.rhs(W.normal(nv, 56))
+    wv = W.normal(nv, 57)
+    if kind == "square":
+        wv[o.fine.bnd] = 0.0
+    b = gpu(b0).requires_grad_(True)
+    k = gpu(kv).requires_grad_(True)
+    u = mga.mg_solve_diff(g, b, k, mg.mg_opts_default(rtol=1e-13))
+    (u * gpu(wv)).sum().backward()
+    ur = omg.direct_solve(o, b0)
+    lam, gkr = omg.solve_adjoint(o, ur, wv)
+    eu, eb, ek = rel(host(u), ur), rel(host(b.grad), lam), rel(host(k.grad), gkr)
+    print(f"[porous] MGSolve {kind}: rel u {eu:.2e}, rel dJ/db {eb:.2e}, rel dJ/dk {ek:.2e}")
+    assert eu <= 1e-10 and eb <= 1e-10 and ek <= 1e-9
+    g.close()
+
+
+def test_porous_status_paths(p25):
+    T = gpu(p25.T0)
+    out = torch.empty_like(T)
+    bad = mg.porous_params_make(RA, PHI, 0.0)
+    with pytest.raises(mg.MGError) as e:
+        mg.porous_step(p25.g.h, bad, T, out)
+    assert e.value.status == mg.MG_EINVAL
+    with pytest.raises(mg.MGError) as e:
+        mg.porous_step(p25.g.h, p25.prm(), T, T)
+    assert e.value.status == mg.MG_EINVAL
+    d = mg.Hierarchy("square", 2)
+    x = torch.zeros(d.nv(), dtype=torch.float64, device=DEV)
+    with pytest.raises(mg.MGError) as e:
+        mg.porous_step(d.h, p25.prm(), x, torch.empty_like(x))
+    assert e.value.status == mg.MG_EINVAL
+    d.close()
+
+
+def test_c5_fullsize_gradient():
+    """The full C5 workload (257 x 257 vertices, 200 steps, checkpoints every 20) against the
+    oracle's discrete adjoint."""
+    P = PorousPair(W.C5["base_cells"], W.C5["nsub"])
+    steps, ckpt = W.C5["steps"], W.C5["ckpt"]
+    w = W.c5_loss_weights(P.nv)
+    g = P.g_gpu.clone().requires_grad_(True)
+    T0 = gpu(P.T0).requires_grad_(True)
+    TN = mga.porous_rollout(P.g, T0, g, steps, RA, PHI, P.dt, ckpt=ckpt)
+    Jg = (TN * gpu(w)).sum()
+    Jg.backward()
+    print("[porous] C5 GPU rollout and gradient done; running the oracle", flush=True)
+    J, gg, gT = P.model.loss_and_grad(P.T0, w, steps, ckpt)
+    ej, eg, eT = abs(Jg.item() - J) / abs(J), rel(host(g.grad), gg), rel(host(T0.grad), gT)
+    print(f"[porous] C5 full: J {Jg.item():.12e} (oracle {J:.12e}), rel dJ/dg {eg:.2e}, "
+          f"rel dJ/dT0 {eT:.2e}")
+    assert ej <= 1e-12 and eg <= 1e-9 and eT <= 1e-9
+    P.g.close()

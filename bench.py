@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--isolated", action="store_true",
                    help="also time back-to-back launches of single kernels (warm caches)")
     p.add_argument("--order", choices=["stripes", "morton"], default="stripes")
+    p.add_argument("--no-porous", action="store_true",
+                   help="skip the porous-convection rollout and gradient timing")
     p.add_argument("--profile-kernels", action="store_true",
                    help="only launch the finest-level kernels (and a plain copy of known size "
                         "that calibrates the HBM counters) a few times each, for rocprofv3 --pmc")
@@ -119,6 +121,76 @@ def cpu_baseline(b_nat_np, rtol):
             ctx.__exit__(None, None, None)
     return dict(x=x, iters=k, t_solve=t_solve, t_build=t_build, hier=o,
                 final=hist[-1], unknowns=o.unknowns())
+
+
+def porous_bench(mg, W, torch, np, with_oracle):
+    """The porous-convection rollout (257 x 257 vertices, 200 forward-Euler steps, pressure by
+    MG-PCG FP64 to 1e-10) and its discrete-adjoint gradient with checkpoints every 20 steps."""
+    from paper_2508_12501_amd import autograd as mga
+    C = W.C5
+    H = mg.Hierarchy("square", C["nsub"], base_cells=C["base_cells"], bc=mg.MG_BC_NATURAL)
+    nv = H.nv()
+    g = torch.tensor(W.c5_logk_noise(nv), device="cuda:0")
+    mg.mg_smooth(H.h, H.top, C["g_smooth_sweeps"], C["g_smooth_omega"], torch.zeros_like(g), g)
+    xyz = mg.mg_hierarchy_export(H.h, H.top)["xyz"]
+    T0 = torch.tensor(W.c5_initial_temperature(xyz), device="cuda:0")
+    w = torch.tensor(W.c5_loss_weights(nv), device="cuda:0")
+    # dt = 1/2 min(h^2 phi Ra / 4, 2 phi / (Ra k_max^2)), h the shortest edge (1/256 here)
+    h = 1.0 / (C["base_cells"] * 2 ** C["nsub"])
+    kmax = float(torch.exp(g).max())
+    dt = 0.5 * min(h * h * C["phi"] * C["Ra"] / 4, 2 * C["phi"] / (C["Ra"] * kmax ** 2))
+    steps, ckpt = C["steps"], C["ckpt"]
+    prm = mg.porous_params_make(C["Ra"], C["phi"], dt, mg.mg_opts_default(rtol=1e-10))
+    mg.mg_hierarchy_set_vertex_coeff(H.h, torch.exp(g))
+    Ta, Tb = T0.clone(), torch.empty_like(T0)
+    for _ in range(3):
+        mg.porous_step(H.h, prm, Ta, Tb)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    Ta.copy_(T0)
+    iters = 0
+    for _ in range(steps):
+        r = mg.porous_step(H.h, prm, Ta, Tb)
+        iters += r.iterations
+        Ta, Tb = Tb, Ta
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t
+    gq = g.clone().requires_grad_(True)
+    T0q = T0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    TN = mga.porous_rollout(H, T0q, gq, steps, C["Ra"], C["phi"], dt, ckpt=ckpt,
+                            solve=mg.mg_opts_default(rtol=1e-10))
+    J = (TN * w).sum()
+    J.backward()
+    torch.cuda.synchronize()
+    t_grad = time.perf_counter() - t
+    out = {"workload": "porous convection, unit square 4x4 base x 6 subdivisions (257x257), "
+                       "Ra 1000, phi 0.1, 200 forward-Euler steps, checkpoints every 20",
+           "vertices": nv, "dt": dt, "steps_per_s": steps / t_fwd,
+           "ms_per_step": 1e3 * t_fwd / steps, "pressure_iterations_mean": iters / steps,
+           "gradient_s": t_grad, "loss": float(J)}
+    if with_oracle:
+        from oracle import dec
+        from oracle import multigrid as omg
+        from oracle import porous as op
+        xyz_o, tri = dec.square_grid(C["base_cells"])
+        o = omg.Hierarchy(xyz_o, tri, C["nsub"], bc="natural")
+        g_ref = op.smooth_logk(o, W.c5_logk_noise(nv), C["g_smooth_sweeps"], C["g_smooth_omega"])
+        m = op.PorousModel(o, g_ref, Ra=C["Ra"], phi=C["phi"], dt=dt)
+        t = time.perf_counter()
+        Jo, gg, gT = m.loss_and_grad(W.c5_initial_temperature(o.fine.xyz), W.c5_loss_weights(nv),
+                                     steps, ckpt)
+        t_o = time.perf_counter() - t
+        rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        out["cpu_baseline"] = {"value": 1.0 / t_o, "unit": "gradients/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one full 200-step loss + adjoint gradient ({t_o:.1f} s)"}
+        out["parity"] = {"loss_rel": abs(float(J) - Jo) / abs(Jo),
+                         "grad_g_rel_l2": rel(gq.grad.cpu().numpy(), gg),
+                         "grad_T0_rel_l2": rel(T0q.grad.cpu().numpy(), gT)}
+    H.close()
+    return out
 
 
 def main():
@@ -274,6 +346,11 @@ def main():
             "fp64_rel_l2_vs_oracle": float(np.linalg.norm(x_fp64.cpu().numpy() - xo)) / den,
             "oracle_iterations": cb["iters"],
         }
+    if not a.no_porous:
+        print("[bench] porous-convection rollout and gradient ...", file=sys.stderr, flush=True)
+        out["porous"] = porous_bench(mg, W, torch, np, not a.no_cpu_baseline)
+        print(f"[bench] porous: {out['porous']['ms_per_step']:.3f} ms/step, gradient "
+              f"{out['porous']['gradient_s']:.3f} s", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -198,6 +198,47 @@ mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine
                          const double* grad_u, double* grad_b, double* grad_k, mg_result* res,
                          void* stream);
 
+/* ------------------------------------------------------------------ batched solves
+ * Many independent solves at once (not in the paper: a throughput mode for many small and
+ * mid-size problems).  Instance i solves A_i x_i = b_i on hierarchy h[i] with the FCG(1)
+ * recurrence of mg_pcg (outer must be MG_OUTER_FCG; precision MG_F32 or MG_F64 selects the
+ * V-cycle arithmetic), with its own scalars and stopping test.  Instances that share a
+ * hierarchy handle are packed into groups of up to max_cols right-hand sides solved together:
+ * the operator is read once per group for all its columns.  Groups run concurrently on
+ * `streams` internal streams; each group's iteration is replayed as a hipGraph when
+ * o->use_graph is set.  The hierarchies must outlive the batch and must not be used by another
+ * call while mg_batch_solve runs. */
+typedef struct mg_batch mg_batch;
+typedef struct {
+  int32_t max_cols;     /* widest group: a power of two in 1..64 (default 32) */
+  int32_t pad_groups;   /* 1: a hierarchy's last group is padded up to a power of two;
+                           0: its instances are split exactly into power-of-two groups (1) */
+  int32_t streams;      /* internal streams, 1..4 (4) */
+  int32_t reserved;
+} mg_batch_tuning;
+
+/* h: n hierarchy handles (one per instance, repeated handles share a hierarchy).  tune
+ * (nullable): explicit tuning; else tune_cache (nullable path of a text file written by
+ * mg_batch_autotune) supplies the tuning recorded for this mix of instances, else defaults.
+ * Allocates every device buffer of the batch. */
+mg_status mg_batch_create(mg_hierarchy* const* h, int32_t n, const mg_opts* o,
+                          const mg_batch_tuning* tune, const char* tune_cache, mg_batch** out);
+/* b, x: host arrays of n device pointers; b[i] and x[i] hold nv doubles of instance i's finest
+ * level in natural vertex order (x[i] is overwritten; Dirichlet vertices get b).  res
+ * (nullable): n results.  Returns MG_OK when every instance converged, else the first failing
+ * instance status (res tells which).  Synchronises `stream` with the batch's streams and the
+ * host before returning. */
+mg_status mg_batch_solve(mg_batch* bt, const double* const* b, double* const* x, mg_result* res,
+                         void* stream);
+/* Tries every tuning of max_cols in {8,16,32,64} x pad_groups in {1,0} x streams in {1,2,4} on
+ * these inputs (one warm-up and `reps` timed solves each), keeps the fastest, and records it in
+ * tune_cache (nullable) under this mix of instances.  chosen, best_ms (nullable) report it. */
+mg_status mg_batch_autotune(mg_batch* bt, const double* const* b, double* const* x, int32_t reps,
+                            const char* tune_cache, mg_batch_tuning* chosen, double* best_ms);
+/* Current tuning and number of groups. */
+mg_status mg_batch_info(const mg_batch* bt, mg_batch_tuning* tune, int32_t* n_groups);
+void mg_batch_free(mg_batch* bt);
+
 /* ------------------------------------------------------------------ porous convection
  * One forward-Euler step of the Darcy-Boussinesq model of Sec. 3.2 (scaled form: advection
  * factor 1/phi, diffusivity kappa = 1/(phi Ra)) on the finest level of a natural-BC hierarchy

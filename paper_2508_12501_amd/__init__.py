@@ -71,6 +71,14 @@ class mg_result(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class mg_batch_tuning(ctypes.Structure):
+    _fields_ = [("max_cols", ctypes.c_int32), ("pad_groups", ctypes.c_int32),
+                ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+
+
 class porous_params(ctypes.Structure):
     _fields_ = [("Ra", ctypes.c_double), ("phi", ctypes.c_double), ("dt", ctypes.c_double),
                 ("solve", mg_opts)]
@@ -107,6 +115,16 @@ _PROTOS = {
                            ctypes.POINTER(mg_result), _vp]),
     "porous_step_adjoint": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp, _vp, _vp,
                                    _vp]),
+    "mg_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(mg_opts),
+                               ctypes.POINTER(mg_batch_tuning), ctypes.c_char_p,
+                               ctypes.POINTER(_vp)]),
+    "mg_batch_solve": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp),
+                              ctypes.POINTER(mg_result), _vp]),
+    "mg_batch_autotune": (_i32, [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _i32,
+                                 ctypes.c_char_p, ctypes.POINTER(mg_batch_tuning),
+                                 ctypes.POINTER(_d)]),
+    "mg_batch_info": (_i32, [_vp, ctypes.POINTER(mg_batch_tuning), ctypes.POINTER(_i32)]),
+    "mg_batch_free": (None, [_vp]),
     "mg_time_kernel": (_i32, [_vp, _i32, _i32, _i32, _i32, _vp, ctypes.POINTER(_d)]),
     "mg_probe_begin": (_i32, [_vp, _i32, _i32]),
     "mg_probe_end": (_i32, [_vp, ctypes.POINTER(_d), ctypes.POINTER(_i32)]),
@@ -369,6 +387,72 @@ def porous_step_adjoint(h, prm: porous_params, T, p, lam, lam_out, grad_k=None, 
                                      _ptr(lam, torch.float64, n, "lambda"),
                                      _ptr(lam_out, torch.float64, n, "lambda_out"),
                                      _opt_ptr(grad_k, torch.float64, n, "grad_k"), _stream(stream)))
+
+
+class BatchRef:
+    """A batch handle with the vertex count of each instance (for argument checks)."""
+
+    def __init__(self, ptr, nvs):
+        self._as_parameter_ = ctypes.c_void_p(ptr)
+        self.nvs = list(nvs)
+        self.n = len(self.nvs)
+
+
+def mg_batch_create(hs, opts: mg_opts, tune: mg_batch_tuning | None = None,
+                    tune_cache: str | None = None) -> BatchRef:
+    """hs: one hierarchy handle per instance (repeat a handle to share its hierarchy)."""
+    n = len(hs)
+    arr = (_vp * n)(*[h.value if isinstance(h, ctypes.c_void_p) else h for h in hs])
+    out = _vp()
+    _check(lib().mg_batch_create(arr, n, ctypes.byref(opts),
+                                 ctypes.byref(tune) if tune is not None else None,
+                                 tune_cache.encode() if tune_cache else None, ctypes.byref(out)))
+    return BatchRef(out.value, [_nv(h, _top(h)) for h in hs])
+
+
+def _ptr_arrays(bt: BatchRef, bs, xs):
+    import torch
+    if len(bs) != bt.n or len(xs) != bt.n:
+        raise ValueError(f"need {bt.n} right-hand sides and solutions")
+    pb = (_vp * bt.n)(*[_ptr(b, torch.float64, nv, "b").value for b, nv in zip(bs, bt.nvs)])
+    px = (_vp * bt.n)(*[_ptr(x, torch.float64, nv, "x").value for x, nv in zip(xs, bt.nvs)])
+    return pb, px
+
+
+def mg_batch_solve(bt: BatchRef, bs, xs, stream=None, raise_on_error=True):
+    """Solves every instance; returns the list of mg_result."""
+    pb, px = _ptr_arrays(bt, bs, xs)
+    res = (mg_result * bt.n)()
+    st = lib().mg_batch_solve(bt, pb, px, res, _stream(stream))
+    out = list(res)
+    if raise_on_error:
+        _check(st, out)
+    return out
+
+
+def mg_batch_autotune(bt: BatchRef, bs, xs, reps: int = 2, tune_cache: str | None = None):
+    """Returns (chosen mg_batch_tuning, best time in ms)."""
+    pb, px = _ptr_arrays(bt, bs, xs)
+    chosen = mg_batch_tuning()
+    ms = ctypes.c_double()
+    _check(lib().mg_batch_autotune(bt, pb, px, int(reps),
+                                   tune_cache.encode() if tune_cache else None,
+                                   ctypes.byref(chosen), ctypes.byref(ms)))
+    return chosen, ms.value
+
+
+def mg_batch_info(bt: BatchRef):
+    """Returns (mg_batch_tuning, number of groups)."""
+    t = mg_batch_tuning()
+    ng = ctypes.c_int32()
+    _check(lib().mg_batch_info(bt, ctypes.byref(t), ctypes.byref(ng)))
+    return t, ng.value
+
+
+def mg_batch_free(bt: BatchRef):
+    if bt is not None and bt._as_parameter_.value:
+        lib().mg_batch_free(bt)
+        bt._as_parameter_ = ctypes.c_void_p(None)
 
 
 def mg_time_kernel(h, kernel: int, level: int, dtype: int, reps: int, stream=None) -> float:

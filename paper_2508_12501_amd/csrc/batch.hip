@@ -1,0 +1,869 @@
+// HIP kernels of the batched (multi right-hand-side) solve.
+//
+// A group's vectors hold M columns row-blocked: entry (i, c) at [i * M + c], M a power of two
+// up to 64.  A 256-thread workgroup covers 256 / M consecutive rows; thread t works on column
+// t % M of row t / M.  A wavefront then covers 64 / M consecutive rows that sit in one 64-row
+// SELL slice, so the slice width is wave-uniform exactly as in the single-column kernels; the
+// M threads of a row load the same column index and weight (one transaction serves them all)
+// and gather x_j as one contiguous M-wide segment.
+//
+// Reductions produce one partial sum per (workgroup, column); a one-workgroup finaliser turns
+// them into the per-column scalars of the FCG(1) recurrence and maintains the group flag.
+#include <hip/hip_runtime.h>
+
+#include <stdexcept>
+#include <type_traits>
+
+#include "batch.hpp"
+#include "util.hpp"
+
+namespace decmg {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kFin = 1024;
+constexpr int kMaxRed = 2048;
+
+__device__ __forceinline__ int xcd_blk() {
+  const int b = blockIdx.x, g = gridDim.x;
+  const int x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ void tiles_of(int ntiles, int blk, int& t0, int& t1) {
+  const int g = gridDim.x;
+  t0 = static_cast<int>(static_cast<int64_t>(ntiles) * blk / g);
+  t1 = static_cast<int>(static_cast<int64_t>(ntiles) * (blk + 1) / g);
+}
+
+template <bool D16>
+__device__ __forceinline__ int colx(const void* __restrict__ col, int idx, int row, int n) {
+  if (D16) {
+    const int c = static_cast<const int16_t*>(col)[idx];
+    return c == kZeroSlot16 ? n : row + c;
+  }
+  return static_cast<const int32_t*>(col)[idx];
+}
+
+// Per-column block reduction of up to two values; threads t < M write part[blk * M + t].
+template <int M>
+__device__ __forceinline__ void block_cols(double v0, double v1, double* part0, double* part1,
+                                           int blk) {
+  __shared__ double s0[kThreads], s1[kThreads];
+  s0[threadIdx.x] = v0;
+  if (part1) s1[threadIdx.x] = v1;
+  __syncthreads();
+  if (threadIdx.x < M) {
+    double a = 0.0, b = 0.0;
+    for (int j = 0; j < kThreads / M; ++j) {
+      a += s0[j * M + threadIdx.x];
+      if (part1) b += s1[j * M + threadIdx.x];
+    }
+    part0[blk * M + threadIdx.x] = a;
+    if (part1) part1[blk * M + threadIdx.x] = b;
+  }
+}
+
+// acc = sum_k w_k (x_i - x_j(k)), d = sum_k w_k over the row's entries, column c.
+template <typename T, bool D16, int M, int N>
+__device__ __forceinline__ void brow_n(const void* __restrict__ col, const T* __restrict__ w,
+                                       const T* __restrict__ x, int beg, int lane, int row, int c,
+                                       int n, T xi, T& acc, T& d) {
+  int cj[N];
+  T wk[N], xj[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    cj[k] = colx<D16>(col, idx, row, n);
+    wk[k] = w[idx];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) xj[k] = x[cj[k] * M + c];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    d += wk[k];
+    acc += wk[k] * (xi - xj[k]);
+  }
+}
+
+template <typename T, bool D16, int M>
+__device__ __forceinline__ void brow(const int32_t* __restrict__ sptr, const void* __restrict__ col,
+                                     const T* __restrict__ w, const T* __restrict__ x, int row,
+                                     int c, int n, T xi, T& acc, T& d) {
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = sptr[s];
+  const int width = sptr[s + 1] - beg;
+  const int lane = row & 63;
+  acc = T(0);
+  d = T(0);
+  switch (width) {
+    case 0: break;
+    case 1: brow_n<T, D16, M, 1>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 2: brow_n<T, D16, M, 2>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 3: brow_n<T, D16, M, 3>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 4: brow_n<T, D16, M, 4>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 5: brow_n<T, D16, M, 5>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 6: brow_n<T, D16, M, 6>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 7: brow_n<T, D16, M, 7>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    case 8: brow_n<T, D16, M, 8>(col, w, x, beg, lane, row, c, n, xi, acc, d); break;
+    default:
+      for (int k = 0; k < width; ++k) {
+        const int idx = (beg + k) * kSlice + lane;
+        const T wk = w[idx];
+        d += wk;
+        acc += wk * (xi - x[colx<D16>(col, idx, row, n) * M + c]);
+      }
+  }
+}
+
+#define BK_ROWCOL(M)                                           \
+  const int c = threadIdx.x & ((M) - 1);                       \
+  const int row = xcd_blk() * (kThreads / (M)) + threadIdx.x / (M);
+
+// MODE 0: y = A x;  1: y = b - A x;  2: y = x + omega (b - A x) / diag
+template <typename T, int MODE, bool D16, int M>
+__global__ __launch_bounds__(kThreads) void bk_rows(const int32_t* __restrict__ sptr,
+                                                    const void* __restrict__ col,
+                                                    const T* __restrict__ w,
+                                                    const T* __restrict__ x,
+                                                    const T* __restrict__ b, T* __restrict__ y,
+                                                    int32_t n, T omega,
+                                                    const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_ROWCOL(M)
+  if (row >= n) return;
+  const T xi = x[row * M + c];
+  const T bi = (MODE == 0) ? T(0) : b[row * M + c];
+  T acc, d;
+  brow<T, D16, M>(sptr, col, w, x, row, c, n, xi, acc, d);
+  if (MODE == 0)
+    y[row * M + c] = acc;
+  else if (MODE == 1)
+    y[row * M + c] = bi - acc;
+  else
+    y[row * M + c] = xi + omega * (bi - acc) / d;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_jacobi_zero(const T* __restrict__ diag,
+                                                           const T* __restrict__ b,
+                                                           T* __restrict__ y, int32_t n, T omega,
+                                                           const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_ROWCOL(M)
+  if (row >= n) return;
+  y[row * M + c] = omega * b[row * M + c] / diag[row];
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_restrict(const int32_t* __restrict__ self,
+                                                        const int32_t* __restrict__ sptr,
+                                                        const int32_t* __restrict__ col,
+                                                        const T* __restrict__ rf,
+                                                        T* __restrict__ rc, int32_t nc,
+                                                        const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_ROWCOL(M)
+  if (row >= nc) return;
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = sptr[s], width = sptr[s + 1] - beg;
+  const int lane = row & 63;
+  T acc = T(0);
+  for (int k = 0; k < width; ++k) acc += rf[col[(beg + k) * kSlice + lane] * M + c];
+  rc[row * M + c] = rf[self[row] * M + c] + T(0.5) * acc;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_prolong(const int32_t* __restrict__ pa,
+                                                       const int32_t* __restrict__ pb,
+                                                       const T* __restrict__ ec,
+                                                       T* __restrict__ xf, int32_t nf,
+                                                       const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_ROWCOL(M)
+  if (row >= nf) return;
+  xf[row * M + c] += T(0.5) * (ec[pa[row] * M + c] + ec[pb[row] * M + c]);
+}
+
+// x = A0^{-1} b on the coarsest level (FP64 dense inverse), one thread per (row, column)
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_coarse(const double* __restrict__ ainv,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ x, int32_t n0,
+                                                      const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const int i = gid / M, c = gid & (M - 1);
+  if (i >= n0) return;
+  const double* a = ainv + static_cast<int64_t>(i) * n0;
+  double acc = 0.0;
+  for (int j = 0; j < n0; ++j) acc += a[j] * static_cast<double>(b[j * M + c]);
+  x[i * M + c] = static_cast<T>(acc);
+}
+
+// ----------------------------------------------------------------- Krylov part (FP64)
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_gather_in(const int32_t* __restrict__ perm,
+                                                         int32_t n,
+                                                         const double* const* __restrict__ bptr,
+                                                         double* __restrict__ Bv, int ncols) {
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const int i = gid / M, c = gid & (M - 1);
+  if (i >= n) return;
+  Bv[i * M + c] = c < ncols ? bptr[c][perm[i]] : 0.0;
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_scatter_out(const int32_t* __restrict__ perm,
+                                                           int32_t n,
+                                                           const double* __restrict__ Xv,
+                                                           double* const* __restrict__ xptr,
+                                                           int ncols) {
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const int i = gid / M, c = gid & (M - 1);
+  if (i >= n || c >= ncols) return;
+  xptr[c][perm[i]] = Xv[i * M + c];
+}
+
+// x = b at the vertices that are not unknowns (Dirichlet boundary)
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_bnd_copy(const int32_t* __restrict__ bnd,
+                                                        int32_t nbnd,
+                                                        const double* const* __restrict__ bptr,
+                                                        double* const* __restrict__ xptr,
+                                                        int ncols) {
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const int i = gid / M, c = gid & (M - 1);
+  if (i >= nbnd || c >= ncols) return;
+  xptr[c][bnd[i]] = bptr[c][bnd[i]];
+}
+
+// sum of squares of each caller vector (natural order, nv entries): block (bx, c)
+__global__ __launch_bounds__(kThreads) void bk_nat_sumsq(int M, int ncols, int32_t nv,
+                                                         const double* const* __restrict__ bptr,
+                                                         double* __restrict__ part) {
+  const int c = blockIdx.y;
+  double v = 0.0;
+  if (c < ncols) {
+    const double* b = bptr[c];
+    const int ntiles = (nv + kThreads - 1) / kThreads;
+    int t0, t1;
+    tiles_of(ntiles, blockIdx.x, t0, t1);
+    for (int t = t0; t < t1; ++t) {
+      const int i = t * kThreads + threadIdx.x;
+      if (i < nv) v += b[i] * b[i];
+    }
+  }
+  __shared__ double s[kThreads];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0;
+    for (int j = 0; j < kThreads; ++j) a += s[j];
+    part[blockIdx.x * M + c] = a;
+  }
+}
+
+// Streaming per-column reductions over a capped grid: logical block b walks a contiguous range
+// of (256 / M)-row tiles.
+#define BK_TILES(M, n)                                              \
+  const int c = threadIdx.x & ((M) - 1);                            \
+  const int rb = kThreads / (M);                                    \
+  const int blk = blockIdx.x;                                       \
+  int t0, t1;                                                       \
+  tiles_of(((n) + rb - 1) / rb, blk, t0, t1);
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_colsum(int32_t n, const double* __restrict__ v,
+                                                      double* __restrict__ part,
+                                                      const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_TILES(M, n)
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * rb + threadIdx.x / M;
+    if (i < n) a += v[i * M + c];
+  }
+  block_cols<M>(a, 0.0, part, nullptr, blk);
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_colsum32(int32_t n, const float* __restrict__ v,
+                                                        const BatchCol* __restrict__ col,
+                                                        double* __restrict__ part,
+                                                        const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_TILES(M, n)
+  const double s = col[c].inv_scale;
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * rb + threadIdx.x / M;
+    if (i < n) a += static_cast<double>(v[i * M + c]) * s;
+  }
+  block_cols<M>(a, 0.0, part, nullptr, blk);
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_sub_mean(int32_t n, const BatchCol* __restrict__ col,
+                                                        double* __restrict__ v) {
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const int i = gid / M, c = gid & (M - 1);
+  if (i < n) v[i * M + c] = v[i * M + c] - col[c].mean;
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_dot(int32_t n, const double* __restrict__ a,
+                                                   const double* __restrict__ b,
+                                                   double* __restrict__ part,
+                                                   const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_TILES(M, n)
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * rb + threadIdx.x / M;
+    if (i < n) v += a[i * M + c] * b[i * M + c];
+  }
+  block_cols<M>(v, 0.0, part, nullptr, blk);
+}
+
+// r = b, x = p = q = 0, r32 = scale * r
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_start(int32_t n, const BatchCol* __restrict__ col,
+                                                     const double* __restrict__ Bv,
+                                                     double* __restrict__ X, double* __restrict__ R,
+                                                     double* __restrict__ P, double* __restrict__ Q,
+                                                     float* __restrict__ r32) {
+  const int gid = blockIdx.x * kThreads + threadIdx.x;
+  const int i = gid / M, c = gid & (M - 1);
+  if (i >= n) return;
+  const int k = i * M + c;
+  const double bi = Bv[k];
+  R[k] = bi;
+  X[k] = 0.0;
+  P[k] = 0.0;
+  Q[k] = 0.0;
+  if (r32) r32[k] = static_cast<float>(bi * col[c].scale);
+}
+
+// z widened (FP32: times inv_scale), minus the column mean when projecting
+template <typename T>
+__device__ __forceinline__ double zval(const T* z, int k, const BatchCol& cc, int sub_mean) {
+  double zi = std::is_same<T, float>::value ? static_cast<double>(z[k]) * cc.inv_scale
+                                            : static_cast<double>(z[k]);
+  if (sub_mean) zi = zi - cc.mean;
+  return zi;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_zdot(int32_t n, const BatchCol* __restrict__ col,
+                                                    const T* __restrict__ z,
+                                                    const double* __restrict__ q,
+                                                    double* __restrict__ part, int sub_mean,
+                                                    const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_TILES(M, n)
+  const BatchCol cc = col[c];
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * rb + threadIdx.x / M;
+    if (i < n) v += zval<T>(z, i * M + c, cc, sub_mean) * q[i * M + c];
+  }
+  block_cols<M>(v, 0.0, part, nullptr, blk);
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_pupd(int32_t n, const BatchCol* __restrict__ col,
+                                                    const T* __restrict__ z, double* __restrict__ p,
+                                                    int sub_mean,
+                                                    const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_ROWCOL(M)
+  if (row >= n) return;
+  const BatchCol& cc = col[c];
+  if (cc.done) return;
+  const int k = row * M + c;
+  p[k] = zval<T>(z, k, cc, sub_mean) + cc.beta * p[k];
+}
+
+template <bool D16, int M>
+__global__ __launch_bounds__(kThreads) void bk_spmv_dot2(const int32_t* __restrict__ sptr,
+                                                         const void* __restrict__ colv,
+                                                         const double* __restrict__ w,
+                                                         const double* __restrict__ p,
+                                                         double* __restrict__ q,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ part0,
+                                                         double* __restrict__ part1, int32_t n,
+                                                         const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_TILES(M, n)
+  double v0 = 0.0, v1 = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int row = t * rb + threadIdx.x / M;
+    if (row < n) {
+      const int k = row * M + c;
+      const double pi = p[k];
+      double acc, d;
+      brow<double, D16, M>(sptr, colv, w, p, row, c, n, pi, acc, d);
+      q[k] = acc;
+      v0 += pi * acc;
+      v1 += pi * r[k];
+    }
+  }
+  block_cols<M>(v0, v1, part0, part1, blk);
+}
+
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_update_xr(int32_t n, const BatchCol* __restrict__ col,
+                                                         const double* __restrict__ p,
+                                                         const double* __restrict__ q,
+                                                         double* __restrict__ x,
+                                                         double* __restrict__ r,
+                                                         float* __restrict__ r32,
+                                                         double* __restrict__ part,
+                                                         const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_TILES(M, n)
+  const BatchCol cc = col[c];
+  double v = 0.0;
+  if (!cc.done) {
+    for (int t = t0; t < t1; ++t) {
+      const int i = t * rb + threadIdx.x / M;
+      if (i < n) {
+        const int k = i * M + c;
+        x[k] = x[k] + cc.alpha * p[k];
+        const double ri = r[k] - cc.alpha * q[k];
+        r[k] = ri;
+        v += ri * ri;
+        if (r32) r32[k] = static_cast<float>(ri * cc.scale);
+      }
+    }
+  }
+  block_cols<M>(v, 0.0, part, nullptr, blk);
+}
+
+template <bool D16, int M>
+__global__ __launch_bounds__(kThreads) void bk_residual_norm(const int32_t* __restrict__ sptr,
+                                                             const void* __restrict__ colv,
+                                                             const double* __restrict__ w,
+                                                             const double* __restrict__ x,
+                                                             const double* __restrict__ b,
+                                                             double* __restrict__ part,
+                                                             int32_t n) {
+  BK_TILES(M, n)
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int row = t * rb + threadIdx.x / M;
+    if (row < n) {
+      const int k = row * M + c;
+      double acc, d;
+      brow<double, D16, M>(sptr, colv, w, x, row, c, n, x[k], acc, d);
+      const double ri = b[k] - acc;
+      v += ri * ri;
+    }
+  }
+  block_cols<M>(v, 0.0, part, nullptr, blk);
+}
+
+__global__ void bk_init(BatchCol* __restrict__ col, BatchFlag* __restrict__ flag, int M, int ncols,
+                        double rtol, int32_t max_iter, double n_unknowns) {
+  const int c = threadIdx.x;
+  if (c < M) {
+    BatchCol z = {};
+    z.pq = 1.0;
+    z.scale = 1.0;
+    z.inv_scale = 1.0;
+    z.rtol = rtol;
+    z.max_iter = max_iter;
+    z.n_unknowns = n_unknowns;
+    // padding columns carry zeros and are finished from the start
+    z.done = c < ncols ? 0 : 1;
+    col[c] = z;
+  }
+  if (c == 0) flag->all_done = ncols > 0 ? 0 : 1;
+}
+
+// One workgroup: per column, sum the nb partials of part0 (and part1), then apply `op`.
+__global__ __launch_bounds__(kFin) void bk_finalize(int op, int M, int nb,
+                                                    const double* __restrict__ part0,
+                                                    const double* __restrict__ part1,
+                                                    BatchCol* __restrict__ col,
+                                                    BatchFlag* __restrict__ flag, int force) {
+  if (!force && flag->all_done) return;
+  const int J = kFin / M;
+  const int c = threadIdx.x % M, j = threadIdx.x / M;
+  double a = 0.0, b = 0.0;
+  for (int blk = j; blk < nb; blk += J) {
+    a += part0[blk * M + c];
+    if (part1) b += part1[blk * M + c];
+  }
+  __shared__ double sa[kFin], sb[kFin];
+  __shared__ int sdone[kBatchMaxCols];
+  sa[threadIdx.x] = a;
+  sb[threadIdx.x] = b;
+  __syncthreads();
+  if (j == 0) {
+    a = 0.0;
+    b = 0.0;
+    for (int q = 0; q < J; ++q) {
+      a += sa[q * M + c];
+      b += sb[q * M + c];
+    }
+    BatchCol& cc = col[c];
+    const bool live = force || !cc.done;
+    if (live) {
+      switch (op) {
+        case bk::FIN_BNORM: {
+          const double bn = sqrt(a);
+          cc.bnorm = bn;
+          cc.rnorm = bn;
+          if (!isfinite(bn)) {
+            cc.status = MG_ENONFINITE;
+            cc.done = 1;
+          } else if (bn == 0.0) {
+            cc.status = MG_OK;
+            cc.done = 1;
+          } else {
+            int e;
+            frexp(bn / sqrt(cc.n_unknowns), &e);
+            cc.scale = ldexp(1.0, -e);
+            cc.inv_scale = ldexp(1.0, e);
+          }
+          break;
+        }
+        case bk::FIN_ALPHA_FCG:
+          cc.pq = a;
+          if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
+            cc.status = (isfinite(a) && isfinite(b)) ? MG_EBREAKDOWN : MG_ENONFINITE;
+            cc.done = 1;
+          } else {
+            cc.alpha = b / a;
+          }
+          break;
+        case bk::FIN_CHECK: {
+          const double rn = sqrt(a);
+          cc.rnorm = rn;
+          cc.iters += 1;
+          if (!isfinite(rn)) {
+            cc.status = MG_ENONFINITE;
+            cc.done = 1;
+          } else if (rn <= cc.rtol * cc.bnorm) {
+            cc.status = MG_OK;
+            cc.done = 1;
+          } else if (cc.iters >= cc.max_iter) {
+            cc.status = MG_ENOCONV;
+            cc.done = 1;
+          }
+          break;
+        }
+        case bk::FIN_BETA_FCG:
+          cc.beta = -a / cc.pq;
+          if (!isfinite(cc.beta)) {
+            cc.status = MG_ENONFINITE;
+            cc.done = 1;
+          }
+          break;
+        case bk::FIN_MEAN:
+          cc.mean = a / cc.n_unknowns;
+          break;
+        case bk::FIN_RNORM:
+          cc.true_rnorm = sqrt(a);
+          break;
+      }
+    }
+    sdone[c] = cc.done;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int all = 1;
+    for (int q = 0; q < M; ++q) all &= (sdone[q] != 0);
+    flag->all_done = all;
+  }
+}
+
+__global__ void bk_fill(uint32_t* __restrict__ p, size_t n) {
+  const size_t i = static_cast<size_t>(blockIdx.x) * kThreads + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+inline unsigned grid_for(int64_t items) {
+  return static_cast<unsigned>((items + kThreads - 1) / kThreads);
+}
+inline unsigned row_blocks(int32_t n, int M) {
+  const int rb = kThreads / M;
+  return static_cast<unsigned>((n + rb - 1) / rb);
+}
+inline const void* colp(const Level& L) {
+  return L.op.col16 ? static_cast<const void*>(L.op.col16) : static_cast<const void*>(L.op.col);
+}
+
+// Calls f(std::integral_constant<int, M>) for a power of two M in [1, 64].
+template <typename F>
+void with_m(int M, F&& f) {
+  switch (M) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    case 64: f(std::integral_constant<int, 64>{}); break;
+    default: throw std::invalid_argument("batch group width must be a power of two up to 64");
+  }
+}
+
+template <typename T> const T* wts(const Level& L);
+template <> const double* wts<double>(const Level& L) { return L.op.w64; }
+template <> const float* wts<float>(const Level& L) { return L.op.w32; }
+template <typename T> const T* diag_of(const Level& L);
+template <> const double* diag_of<double>(const Level& L) { return L.op.diag64; }
+template <> const float* diag_of<float>(const Level& L) { return L.op.diag32; }
+
+}  // namespace
+
+namespace bk {
+
+int red_blocks(int32_t n, int M) {
+  const int rb = kThreads / M;
+  const int tiles = (n + rb - 1) / rb;
+  return std::max(1, std::min(kMaxRed, tiles));
+}
+
+void init_cols(BatchCol* col, BatchFlag* flag, int M, int ncols, double rtol, int32_t max_iter,
+               double n_unknowns, hipStream_t s) {
+  hipLaunchKernelGGL(bk_init, dim3(1), dim3(64), 0, s, col, flag, M, ncols, rtol, max_iter,
+                     n_unknowns);
+}
+
+void finalize(int op, int M, int nb, const double* part0, const double* part1, BatchCol* col,
+              BatchFlag* flag, int force, hipStream_t s) {
+  hipLaunchKernelGGL(bk_finalize, dim3(1), dim3(kFin), 0, s, op, M, nb, part0, part1, col, flag,
+                     force);
+}
+
+void gather_in(int M, int ncols, const int32_t* perm, int32_t n, const double* const* bptr,
+               double* Bv, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_gather_in<MM>, dim3(grid_for(int64_t(n) * MM)), dim3(kThreads), 0, s,
+                       perm, n, bptr, Bv, ncols);
+  });
+}
+
+void scatter_out(int M, int ncols, const int32_t* perm, int32_t n, const int32_t* bnd,
+                 int32_t nbnd, const double* Xv, const double* const* bptr, double* const* xptr,
+                 hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_scatter_out<MM>, dim3(grid_for(int64_t(n) * MM)), dim3(kThreads), 0, s,
+                       perm, n, Xv, xptr, ncols);
+    if (nbnd > 0)
+      hipLaunchKernelGGL(bk_bnd_copy<MM>, dim3(grid_for(int64_t(nbnd) * MM)), dim3(kThreads), 0, s,
+                         bnd, nbnd, bptr, xptr, ncols);
+  });
+}
+
+void nat_sumsq(int M, int ncols, int32_t nv, const double* const* bptr, double* part, int nb,
+               hipStream_t s) {
+  hipLaunchKernelGGL(bk_nat_sumsq, dim3(nb, M), dim3(kThreads), 0, s, M, ncols, nv, bptr, part);
+}
+
+void colsum(int M, int32_t n, const double* v, double* part, int nb, const BatchFlag* flag,
+            hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_colsum<MM>, dim3(nb), dim3(kThreads), 0, s, n, v, part, flag);
+  });
+}
+
+void colsum32(int M, int32_t n, const float* v, const BatchCol* col, double* part, int nb,
+              const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_colsum32<MM>, dim3(nb), dim3(kThreads), 0, s, n, v, col, part, flag);
+  });
+}
+
+void sub_mean(int M, int32_t n, const BatchCol* col, double* v, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_sub_mean<MM>, dim3(grid_for(int64_t(n) * MM)), dim3(kThreads), 0, s, n,
+                       col, v);
+  });
+}
+
+void dot(int M, int32_t n, const double* a, const double* b, double* part, int nb,
+         const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_dot<MM>, dim3(nb), dim3(kThreads), 0, s, n, a, b, part, flag);
+  });
+}
+
+void start(int M, int32_t n, const BatchCol* col, const double* Bv, double* X, double* R,
+           double* P, double* Q, float* r32, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_start<MM>, dim3(grid_for(int64_t(n) * MM)), dim3(kThreads), 0, s, n, col,
+                       Bv, X, R, P, Q, r32);
+  });
+}
+
+template <typename T>
+void zdot(int M, int32_t n, const BatchCol* col, const T* z, const double* q, double* part, int nb,
+          int sub_mean, const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL((bk_zdot<T, MM>), dim3(nb), dim3(kThreads), 0, s, n, col, z, q, part,
+                       sub_mean, flag);
+  });
+}
+
+template <typename T>
+void pupd(int M, int32_t n, const BatchCol* col, const T* z, double* p, int sub_mean,
+          const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL((bk_pupd<T, MM>), dim3(row_blocks(n, MM)), dim3(kThreads), 0, s, n, col, z,
+                       p, sub_mean, flag);
+  });
+}
+
+void spmv_dot2(int M, const Level& L, const double* p, double* q, const double* r, double* part0,
+               double* part1, int nb, const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    if (L.op.col16)
+      hipLaunchKernelGGL((bk_spmv_dot2<true, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
+                         colp(L), L.op.w64, p, q, r, part0, part1, L.n, flag);
+    else
+      hipLaunchKernelGGL((bk_spmv_dot2<false, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
+                         colp(L), L.op.w64, p, q, r, part0, part1, L.n, flag);
+  });
+}
+
+void update_xr(int M, int32_t n, const BatchCol* col, const double* p, const double* q, double* x,
+               double* r, float* r32, double* part, int nb, const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_update_xr<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, p, q, x, r, r32,
+                       part, flag);
+  });
+}
+
+void residual_norm(int M, const Level& L, const double* x, const double* b, double* part, int nb,
+                   hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    if (L.op.col16)
+      hipLaunchKernelGGL((bk_residual_norm<true, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
+                         colp(L), L.op.w64, x, b, part, L.n);
+    else
+      hipLaunchKernelGGL((bk_residual_norm<false, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
+                         colp(L), L.op.w64, x, b, part, L.n);
+  });
+}
+
+template <typename T>
+void rows(int mode, int M, const Level& L, const T* x, const T* b, T* y, double omega,
+          const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    const dim3 g(row_blocks(L.n, MM));
+    const T om = static_cast<T>(omega);
+    const bool d16 = L.op.col16 != nullptr;
+#define BK_ROWS_LAUNCH(MODE)                                                                    \
+  if (d16)                                                                                      \
+    hipLaunchKernelGGL((bk_rows<T, MODE, true, MM>), g, dim3(kThreads), 0, s, L.op.sptr, colp(L), \
+                       wts<T>(L), x, b, y, L.n, om, flag);                                      \
+  else                                                                                          \
+    hipLaunchKernelGGL((bk_rows<T, MODE, false, MM>), g, dim3(kThreads), 0, s, L.op.sptr,       \
+                       colp(L), wts<T>(L), x, b, y, L.n, om, flag);
+    if (mode == 0) {
+      BK_ROWS_LAUNCH(0)
+    } else if (mode == 1) {
+      BK_ROWS_LAUNCH(1)
+    } else {
+      BK_ROWS_LAUNCH(2)
+    }
+#undef BK_ROWS_LAUNCH
+  });
+}
+
+template <typename T>
+void jacobi_zero(int M, const Level& L, const T* b, T* y, double omega, const BatchFlag* flag,
+                 hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL((bk_jacobi_zero<T, MM>), dim3(row_blocks(L.n, MM)), dim3(kThreads), 0, s,
+                       diag_of<T>(L), b, y, L.n, static_cast<T>(omega), flag);
+  });
+}
+
+template <typename T>
+void restrict_(int M, const Level& Lf, const Level& Lc, const T* rf, T* rc, const BatchFlag* flag,
+               hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL((bk_restrict<T, MM>), dim3(row_blocks(Lc.n, MM)), dim3(kThreads), 0, s,
+                       Lf.tr.r_self, Lf.tr.r_sptr, Lf.tr.r_col, rf, rc, Lc.n, flag);
+  });
+}
+
+template <typename T>
+void prolong(int M, const Level& Lf, const Level& Lc, const T* ec, T* xf, const BatchFlag* flag,
+             hipStream_t s) {
+  (void)Lc;
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL((bk_prolong<T, MM>), dim3(row_blocks(Lf.n, MM)), dim3(kThreads), 0, s,
+                       Lf.tr.pa, Lf.tr.pb, ec, xf, Lf.n, flag);
+  });
+}
+
+template <typename T>
+void coarse(int M, const Hierarchy& H, const T* b, T* x, const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL((bk_coarse<T, MM>), dim3(grid_for(int64_t(H.n0) * MM)), dim3(kThreads), 0,
+                       s, H.coarse_inv, b, x, H.n0, flag);
+  });
+}
+
+void zero(void* p, size_t bytes, hipStream_t s) {
+  const size_t n = bytes / sizeof(uint32_t);
+  if (n) hipLaunchKernelGGL(bk_fill, dim3(grid_for(int64_t(n))), dim3(kThreads), 0, s,
+                            static_cast<uint32_t*>(p), n);
+}
+
+template void zdot<float>(int, int32_t, const BatchCol*, const float*, const double*, double*, int,
+                          int, const BatchFlag*, hipStream_t);
+template void zdot<double>(int, int32_t, const BatchCol*, const double*, const double*, double*,
+                           int, int, const BatchFlag*, hipStream_t);
+template void pupd<float>(int, int32_t, const BatchCol*, const float*, double*, int,
+                          const BatchFlag*, hipStream_t);
+template void pupd<double>(int, int32_t, const BatchCol*, const double*, double*, int,
+                           const BatchFlag*, hipStream_t);
+template void rows<float>(int, int, const Level&, const float*, const float*, float*, double,
+                          const BatchFlag*, hipStream_t);
+template void rows<double>(int, int, const Level&, const double*, const double*, double*, double,
+                           const BatchFlag*, hipStream_t);
+template void jacobi_zero<float>(int, const Level&, const float*, float*, double, const BatchFlag*,
+                                 hipStream_t);
+template void jacobi_zero<double>(int, const Level&, const double*, double*, double,
+                                  const BatchFlag*, hipStream_t);
+template void restrict_<float>(int, const Level&, const Level&, const float*, float*,
+                               const BatchFlag*, hipStream_t);
+template void restrict_<double>(int, const Level&, const Level&, const double*, double*,
+                                const BatchFlag*, hipStream_t);
+template void prolong<float>(int, const Level&, const Level&, const float*, float*,
+                             const BatchFlag*, hipStream_t);
+template void prolong<double>(int, const Level&, const Level&, const double*, double*,
+                              const BatchFlag*, hipStream_t);
+template void coarse<float>(int, const Hierarchy&, const float*, float*, const BatchFlag*,
+                            hipStream_t);
+template void coarse<double>(int, const Hierarchy&, const double*, double*, const BatchFlag*,
+                             hipStream_t);
+
+}  // namespace bk
+}  // namespace decmg

@@ -6,6 +6,7 @@
 #include <new>
 #include <string>
 
+#include "batch.hpp"
 #include "decmg.h"
 #include "hier.hpp"
 #include "solver.hpp"
@@ -16,6 +17,9 @@ struct dec_mesh {
 };
 struct mg_hierarchy {
   std::unique_ptr<decmg::Hierarchy> h;
+};
+struct mg_batch {
+  std::unique_ptr<decmg::Batch> b;
 };
 
 namespace {
@@ -479,6 +483,88 @@ mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const d
   API_END
   return MG_OK;
 }
+
+namespace {
+mg_status check_tuning(const mg_batch_tuning* t) {
+  const int mc = t->max_cols;
+  if (mc < 1 || mc > decmg::kBatchMaxCols || (mc & (mc - 1)) != 0)
+    return fail(MG_EINVAL, "max_cols must be a power of two in 1..64");
+  if (t->pad_groups != 0 && t->pad_groups != 1) return fail(MG_EINVAL, "pad_groups must be 0 or 1");
+  if (t->streams < 1 || t->streams > 4) return fail(MG_EINVAL, "streams must be in 1..4");
+  return MG_OK;
+}
+mg_status check_ptrs(const mg_batch* bt, const double* const* b, double* const* x) {
+  if (!bt || !bt->b) return fail(MG_EINVAL, "null batch");
+  if (!b || !x) return fail(MG_EINVAL, "null pointer array");
+  for (size_t i = 0; i < bt->b->inst_h.size(); ++i)
+    if (!b[i] || !x[i]) return fail(MG_EINVAL, "null vector for instance " + std::to_string(i));
+  return MG_OK;
+}
+}  // namespace
+
+mg_status mg_batch_create(mg_hierarchy* const* h, int32_t n, const mg_opts* o,
+                          const mg_batch_tuning* tune, const char* tune_cache, mg_batch** out) {
+  if (!out) return fail(MG_EINVAL, "null output handle");
+  *out = nullptr;
+  if (!h || n < 1) return fail(MG_EINVAL, "need at least one instance");
+  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (o->outer != MG_OUTER_FCG) return fail(MG_EINVAL, "batched solves run FCG(1): outer must be MG_OUTER_FCG");
+  if (tune)
+    if (mg_status st = check_tuning(tune); st != MG_OK) return st;
+  for (int32_t i = 0; i < n; ++i)
+    if (!h[i] || !h[i]->h) return fail(MG_EINVAL, "null hierarchy for instance " + std::to_string(i));
+  API_BEGIN
+  auto B = std::make_unique<decmg::Batch>();
+  B->opts = *o;
+  for (int32_t i = 0; i < n; ++i) B->inst_h.push_back(h[i]->h.get());
+  B->signature = decmg::batch_signature(*B);
+  if (tune) {
+    B->tune = decmg::BatchTuning{tune->max_cols, tune->pad_groups, tune->streams};
+  } else {
+    decmg::BatchTuning t;
+    if (decmg::batch_cache_lookup(tune_cache, B->signature, t)) {
+      const mg_batch_tuning ct{t.max_cols, t.pad_groups, t.streams, 0};
+      if (check_tuning(&ct) == MG_OK) B->tune = t;
+    }
+  }
+  decmg::batch_setup(*B);
+  auto* r = new mg_batch;
+  r->b = std::move(B);
+  *out = r;
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_batch_solve(mg_batch* bt, const double* const* b, double* const* x, mg_result* res,
+                         void* stream) {
+  if (mg_status st = check_ptrs(bt, b, x); st != MG_OK) return st;
+  API_BEGIN
+  const int st = decmg::batch_solve(*bt->b, b, x, res, S(stream));
+  if (st != MG_OK) return fail(mg_status(st), "an instance of the batch stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_batch_autotune(mg_batch* bt, const double* const* b, double* const* x, int32_t reps,
+                            const char* tune_cache, mg_batch_tuning* chosen, double* best_ms) {
+  if (mg_status st = check_ptrs(bt, b, x); st != MG_OK) return st;
+  if (reps < 1 || reps > 100) return fail(MG_EINVAL, "reps must be in 1..100");
+  API_BEGIN
+  const double ms = decmg::batch_autotune(*bt->b, b, x, reps, tune_cache);
+  if (chosen) *chosen = mg_batch_tuning{bt->b->tune.max_cols, bt->b->tune.pad_groups, bt->b->tune.streams, 0};
+  if (best_ms) *best_ms = ms;
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_batch_info(const mg_batch* bt, mg_batch_tuning* tune, int32_t* n_groups) {
+  if (!bt || !bt->b) return fail(MG_EINVAL, "null batch");
+  if (tune) *tune = mg_batch_tuning{bt->b->tune.max_cols, bt->b->tune.pad_groups, bt->b->tune.streams, 0};
+  if (n_groups) *n_groups = int32_t(bt->b->groups.size());
+  return MG_OK;
+}
+
+void mg_batch_free(mg_batch* bt) { delete bt; }
 
 mg_status mg_time_kernel(mg_hierarchy* h, int32_t kernel, int32_t level, int32_t dtype, int32_t reps,
                          void* stream, double* ms_per_launch) {

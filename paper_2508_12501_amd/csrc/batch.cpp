@@ -78,8 +78,15 @@ T* vcycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, hipStream_t s) {
   bk::rows<T>(1, M, L, cur, b, V.r, 0.0, fl, s);
   bk::restrict_<T>(M, L, C, V.r, VC.b, fl, s);
   T* ec = vcycle_b<T>(o, G, l - 1, VC.b, s);
-  bk::prolong<T>(M, L, C, ec, cur, fl, s);
-  for (int i = 0; i < o.nu2; ++i) {
+  int post = o.nu2;
+  if (post >= 1 && int64_t(L.n) * M <= kFuseProlongRows) {
+    bk::prolong_sweep<T>(M, L, ec, cur, b, oth, o.omega, fl, s);
+    std::swap(cur, oth);
+    --post;
+  } else {
+    bk::prolong<T>(M, L, C, ec, cur, fl, s);
+  }
+  for (; post > 0; --post) {
     bk::rows<T>(2, M, L, cur, b, oth, o.omega, fl, s);
     std::swap(cur, oth);
   }

@@ -65,8 +65,8 @@ __device__ __forceinline__ void block_cols(double v0, double v1, double* part0, 
 }
 
 // acc = sum_k w_k (x_i - x_j(k)), d = sum_k w_k over the row's entries, column c.
-template <typename T, bool D16, int M, int N>
-__device__ __forceinline__ void brow_n(const void* __restrict__ col, const T* __restrict__ w,
+template <typename T, bool D16, int M, int N, typename WT>
+__device__ __forceinline__ void brow_n(const void* __restrict__ col, const WT* __restrict__ w,
                                        const T* __restrict__ x, int beg, int lane, int row, int c,
                                        int n, T xi, T& acc, T& d) {
   int cj[N];
@@ -75,7 +75,7 @@ __device__ __forceinline__ void brow_n(const void* __restrict__ col, const T* __
   for (int k = 0; k < N; ++k) {
     const int idx = (beg + k) * kSlice + lane;
     cj[k] = colx<D16>(col, idx, row, n);
-    wk[k] = w[idx];
+    wk[k] = static_cast<T>(w[idx]);
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) xj[k] = x[cj[k] * M + c];
@@ -86,9 +86,9 @@ __device__ __forceinline__ void brow_n(const void* __restrict__ col, const T* __
   }
 }
 
-template <typename T, bool D16, int M>
+template <typename T, bool D16, int M, typename WT>
 __device__ __forceinline__ void brow(const int32_t* __restrict__ sptr, const void* __restrict__ col,
-                                     const T* __restrict__ w, const T* __restrict__ x, int row,
+                                     const WT* __restrict__ w, const T* __restrict__ x, int row,
                                      int c, int n, T xi, T& acc, T& d) {
   const int s = __builtin_amdgcn_readfirstlane(row >> 6);
   const int beg = sptr[s];
@@ -121,10 +121,10 @@ __device__ __forceinline__ void brow(const int32_t* __restrict__ sptr, const voi
   const int row = xcd_blk() * (kThreads / (M)) + threadIdx.x / (M);
 
 // MODE 0: y = A x;  1: y = b - A x;  2: y = x + omega (b - A x) / diag
-template <typename T, int MODE, bool D16, int M>
+template <typename T, int MODE, bool D16, int M, typename WT>
 __global__ __launch_bounds__(kThreads) void bk_rows(const int32_t* __restrict__ sptr,
                                                     const void* __restrict__ col,
-                                                    const T* __restrict__ w,
+                                                    const WT* __restrict__ w,
                                                     const T* __restrict__ x,
                                                     const T* __restrict__ b, T* __restrict__ y,
                                                     int32_t n, T omega,
@@ -183,6 +183,34 @@ __global__ __launch_bounds__(kThreads) void bk_prolong(const int32_t* __restrict
   BK_ROWCOL(M)
   if (row >= nf) return;
   xf[row * M + c] += T(0.5) * (ec[pa[row] * M + c] + ec[pb[row] * M + c]);
+}
+
+// First post-smoothing sweep with the interpolation fused in: x0 = x + M(f)^T e_c is formed on
+// the fly for the row and its neighbours (zero slot included: its parents are the coarse zero
+// slot), then y = x0 + omega (b - A x0) / diag.
+template <typename T, bool D16, int M, typename WT>
+__global__ __launch_bounds__(kThreads) void bk_prolong_sweep(
+    const int32_t* __restrict__ sptr, const void* __restrict__ col, const WT* __restrict__ w,
+    const int32_t* __restrict__ pa, const int32_t* __restrict__ pb, const T* __restrict__ ec,
+    const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int32_t n, T omega,
+    const BatchFlag* __restrict__ flag) {
+  if (flag && flag->all_done) return;
+  BK_ROWCOL(M)
+  if (row >= n) return;
+  const T xi0 = x[row * M + c] + T(0.5) * (ec[pa[row] * M + c] + ec[pb[row] * M + c]);
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = sptr[s], width = sptr[s + 1] - beg;
+  const int lane = row & 63;
+  T acc = T(0), d = T(0);
+  for (int k = 0; k < width; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    const int j = colx<D16>(col, idx, row, n);
+    const T xj = x[j * M + c] + T(0.5) * (ec[pa[j] * M + c] + ec[pb[j] * M + c]);
+    const T wk = w[idx];
+    d += wk;
+    acc += wk * (xi0 - xj);
+  }
+  y[row * M + c] = xi0 + omega * (b[row * M + c] - acc) / d;
 }
 
 // x = A0^{-1} b on the coarsest level (FP64 dense inverse), one thread per (row, column)
@@ -385,10 +413,10 @@ __global__ __launch_bounds__(kThreads) void bk_pupd(int32_t n, const BatchCol* _
   p[k] = zval<T>(z, k, cc, sub_mean) + cc.beta * p[k];
 }
 
-template <bool D16, int M>
+template <bool D16, int M, typename WT>
 __global__ __launch_bounds__(kThreads) void bk_spmv_dot2(const int32_t* __restrict__ sptr,
                                                          const void* __restrict__ colv,
-                                                         const double* __restrict__ w,
+                                                         const WT* __restrict__ w,
                                                          const double* __restrict__ p,
                                                          double* __restrict__ q,
                                                          const double* __restrict__ r,
@@ -442,10 +470,10 @@ __global__ __launch_bounds__(kThreads) void bk_update_xr(int32_t n, const BatchC
   block_cols<M>(v, 0.0, part, nullptr, blk);
 }
 
-template <bool D16, int M>
+template <bool D16, int M, typename WT>
 __global__ __launch_bounds__(kThreads) void bk_residual_norm(const int32_t* __restrict__ sptr,
                                                              const void* __restrict__ colv,
-                                                             const double* __restrict__ w,
+                                                             const WT* __restrict__ w,
                                                              const double* __restrict__ x,
                                                              const double* __restrict__ b,
                                                              double* __restrict__ part,
@@ -612,9 +640,21 @@ void with_m(int M, F&& f) {
   }
 }
 
-template <typename T> const T* wts(const Level& L);
-template <> const double* wts<double>(const Level& L) { return L.op.w64; }
-template <> const float* wts<float>(const Level& L) { return L.op.w32; }
+// Calls f(w) with the weights T-arithmetic kernels read: FP32 for FP32 kernels, and for FP64
+// kernels too when every FP64 weight of the level equals its FP32 copy.
+template <typename T, typename F>
+void with_wts(const Level& L, F&& f) {
+  if constexpr (std::is_same<T, float>::value) {
+    f(static_cast<const float*>(L.op.w32));
+  } else {
+    if (L.op.w_exact32)
+      f(static_cast<const float*>(L.op.w32));
+    else
+      f(static_cast<const double*>(L.op.w64));
+  }
+}
+template <typename P>
+using pointee = std::remove_const_t<std::remove_pointer_t<P>>;
 template <typename T> const T* diag_of(const Level& L);
 template <> const double* diag_of<double>(const Level& L) { return L.op.diag64; }
 template <> const float* diag_of<float>(const Level& L) { return L.op.diag32; }
@@ -733,12 +773,15 @@ void spmv_dot2(int M, const Level& L, const double* p, double* q, const double* 
                double* part1, int nb, const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    if (L.op.col16)
-      hipLaunchKernelGGL((bk_spmv_dot2<true, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
-                         colp(L), L.op.w64, p, q, r, part0, part1, L.n, flag);
-    else
-      hipLaunchKernelGGL((bk_spmv_dot2<false, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
-                         colp(L), L.op.w64, p, q, r, part0, part1, L.n, flag);
+    with_wts<double>(L, [&](auto w) {
+      using WT = pointee<decltype(w)>;
+      if (L.op.col16)
+        hipLaunchKernelGGL((bk_spmv_dot2<true, MM, WT>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
+                           colp(L), w, p, q, r, part0, part1, L.n, flag);
+      else
+        hipLaunchKernelGGL((bk_spmv_dot2<false, MM, WT>), dim3(nb), dim3(kThreads), 0, s,
+                           L.op.sptr, colp(L), w, p, q, r, part0, part1, L.n, flag);
+    });
   });
 }
 
@@ -755,12 +798,15 @@ void residual_norm(int M, const Level& L, const double* x, const double* b, doub
                    hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    if (L.op.col16)
-      hipLaunchKernelGGL((bk_residual_norm<true, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
-                         colp(L), L.op.w64, x, b, part, L.n);
-    else
-      hipLaunchKernelGGL((bk_residual_norm<false, MM>), dim3(nb), dim3(kThreads), 0, s, L.op.sptr,
-                         colp(L), L.op.w64, x, b, part, L.n);
+    with_wts<double>(L, [&](auto w) {
+      using WT = pointee<decltype(w)>;
+      if (L.op.col16)
+        hipLaunchKernelGGL((bk_residual_norm<true, MM, WT>), dim3(nb), dim3(kThreads), 0, s,
+                           L.op.sptr, colp(L), w, x, b, part, L.n);
+      else
+        hipLaunchKernelGGL((bk_residual_norm<false, MM, WT>), dim3(nb), dim3(kThreads), 0, s,
+                           L.op.sptr, colp(L), w, x, b, part, L.n);
+    });
   });
 }
 
@@ -772,21 +818,24 @@ void rows(int mode, int M, const Level& L, const T* x, const T* b, T* y, double 
     const dim3 g(row_blocks(L.n, MM));
     const T om = static_cast<T>(omega);
     const bool d16 = L.op.col16 != nullptr;
-#define BK_ROWS_LAUNCH(MODE)                                                                    \
-  if (d16)                                                                                      \
-    hipLaunchKernelGGL((bk_rows<T, MODE, true, MM>), g, dim3(kThreads), 0, s, L.op.sptr, colp(L), \
-                       wts<T>(L), x, b, y, L.n, om, flag);                                      \
-  else                                                                                          \
-    hipLaunchKernelGGL((bk_rows<T, MODE, false, MM>), g, dim3(kThreads), 0, s, L.op.sptr,       \
-                       colp(L), wts<T>(L), x, b, y, L.n, om, flag);
-    if (mode == 0) {
-      BK_ROWS_LAUNCH(0)
-    } else if (mode == 1) {
-      BK_ROWS_LAUNCH(1)
-    } else {
-      BK_ROWS_LAUNCH(2)
-    }
+    with_wts<T>(L, [&](auto w) {
+      using WT = pointee<decltype(w)>;
+#define BK_ROWS_LAUNCH(MODE)                                                                     \
+  if (d16)                                                                                       \
+    hipLaunchKernelGGL((bk_rows<T, MODE, true, MM, WT>), g, dim3(kThreads), 0, s, L.op.sptr,      \
+                       colp(L), w, x, b, y, L.n, om, flag);                                      \
+  else                                                                                           \
+    hipLaunchKernelGGL((bk_rows<T, MODE, false, MM, WT>), g, dim3(kThreads), 0, s, L.op.sptr,     \
+                       colp(L), w, x, b, y, L.n, om, flag);
+      if (mode == 0) {
+        BK_ROWS_LAUNCH(0)
+      } else if (mode == 1) {
+        BK_ROWS_LAUNCH(1)
+      } else {
+        BK_ROWS_LAUNCH(2)
+      }
 #undef BK_ROWS_LAUNCH
+    });
   });
 }
 
@@ -818,6 +867,26 @@ void prolong(int M, const Level& Lf, const Level& Lc, const T* ec, T* xf, const 
     constexpr int MM = decltype(mc)::value;
     hipLaunchKernelGGL((bk_prolong<T, MM>), dim3(row_blocks(Lf.n, MM)), dim3(kThreads), 0, s,
                        Lf.tr.pa, Lf.tr.pb, ec, xf, Lf.n, flag);
+  });
+}
+
+template <typename T>
+void prolong_sweep(int M, const Level& Lf, const T* ec, const T* x, const T* b, T* y,
+                   double omega, const BatchFlag* flag, hipStream_t s) {
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    const dim3 g(row_blocks(Lf.n, MM));
+    with_wts<T>(Lf, [&](auto w) {
+      using WT = pointee<decltype(w)>;
+      if (Lf.op.col16)
+        hipLaunchKernelGGL((bk_prolong_sweep<T, true, MM, WT>), g, dim3(kThreads), 0, s,
+                           Lf.op.sptr, colp(Lf), w, Lf.tr.pa, Lf.tr.pb, ec, x, b, y, Lf.n,
+                           static_cast<T>(omega), flag);
+      else
+        hipLaunchKernelGGL((bk_prolong_sweep<T, false, MM, WT>), g, dim3(kThreads), 0, s,
+                           Lf.op.sptr, colp(Lf), w, Lf.tr.pa, Lf.tr.pb, ec, x, b, y, Lf.n,
+                           static_cast<T>(omega), flag);
+    });
   });
 }
 
@@ -860,6 +929,10 @@ template void prolong<float>(int, const Level&, const Level&, const float*, floa
                              const BatchFlag*, hipStream_t);
 template void prolong<double>(int, const Level&, const Level&, const double*, double*,
                               const BatchFlag*, hipStream_t);
+template void prolong_sweep<float>(int, const Level&, const float*, const float*, const float*,
+                                   float*, double, const BatchFlag*, hipStream_t);
+template void prolong_sweep<double>(int, const Level&, const double*, const double*,
+                                    const double*, double*, double, const BatchFlag*, hipStream_t);
 template void coarse<float>(int, const Hierarchy&, const float*, float*, const BatchFlag*,
                             hipStream_t);
 template void coarse<double>(int, const Hierarchy&, const double*, double*, const BatchFlag*,

@@ -136,6 +136,9 @@ template <typename T>
 void prolong(int M, const Level& Lf, const Level& Lc, const T* ec, T* xf, const BatchFlag* flag,
              hipStream_t s);
 template <typename T>
+void prolong_sweep(int M, const Level& Lf, const T* ec, const T* x, const T* b, T* y,
+                   double omega, const BatchFlag* flag, hipStream_t s);
+template <typename T>
 void coarse(int M, const Hierarchy& H, const T* b, T* x, const BatchFlag* flag, hipStream_t s);
 void zero(void* p, size_t bytes, hipStream_t s);   // bytes: a multiple of 4
 }  // namespace bk

@@ -41,6 +41,7 @@ struct DevOperator {
   int16_t* col16 = nullptr;
   double* w64 = nullptr;
   float* w32 = nullptr;
+  bool w_exact32 = false;     // every FP64 weight equals its FP32 copy: FP64 kernels read w32
   double* diag64 = nullptr;   // sum of the row's weights, in SELL order
   float* diag32 = nullptr;
 };
@@ -54,6 +55,7 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t* r_col = nullptr;
 };
 
+constexpr int32_t kFuseProlongRows = 1 << 19;   // fuse interpolation into the first post sweep up to this size
 constexpr int kCoarseThreads = 1024;       // workgroup of the fused coarse cycle
 constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse cycle
 
@@ -195,6 +197,8 @@ template <typename T> void jacobi_two(const Level& L, const T* b, T* xo, double 
 template <typename T> void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done, hipStream_t s);
 template <typename T> void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done, hipStream_t s);
+// xo = one weighted-Jacobi sweep of (x + M(f)^T ec), the interpolation fused into the sweep
+template <typename T> void prolong_sweep(const Level& Lf, const Level& Lc, const T* ec, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);
 template <typename T> void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2, const int* done, hipStream_t s);
 template <typename T> void fill(T* p, int64_t n, T v, hipStream_t s);

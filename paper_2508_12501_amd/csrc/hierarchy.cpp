@@ -424,6 +424,12 @@ void upload_weights(Hierarchy& H) {
       L.op.diag64 = zeros<double>(L.n + 1);
       L.op.diag32 = zeros<float>(L.n + 1);
     }
+    L.op.w_exact32 = true;
+    for (size_t i = 0; i < w64.size(); ++i)
+      if (static_cast<double>(w32[i]) != w64[i]) {
+        L.op.w_exact32 = false;
+        break;
+      }
     if (!w64.empty()) {
       check_hip(hipMemcpy(L.op.w64, w64.data(), w64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
       check_hip(hipMemcpy(L.op.w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");

@@ -10,6 +10,8 @@
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include <algorithm>
 #include <cmath>
 
@@ -92,8 +94,8 @@ __device__ __forceinline__ void slice_bounds(const int32_t* __restrict__ sptr, i
 // order.  The entry count is wave-uniform, so a scalar switch picks a fully unrolled body
 // that issues all index and weight loads, then all gathers: a wavefront waits on two memory
 // round trips instead of two per entry.
-template <typename T, bool D16, int N>
-__device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const T* __restrict__ w,
+template <typename T, bool D16, int N, typename WT>
+__device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const WT* __restrict__ w,
                                             const T* __restrict__ x, int beg, int lane, int row,
                                             int n, T xi, T& acc, T& d) {
   int cj[N];
@@ -102,7 +104,7 @@ __device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const 
   for (int k = 0; k < N; ++k) {
     const int idx = (beg + k) * kSlice + lane;
     cj[k] = col_at<D16>(col, idx, row, n);
-    wk[k] = w[idx];
+    wk[k] = static_cast<T>(w[idx]);
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) xj[k] = x[cj[k]];
@@ -113,10 +115,10 @@ __device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const 
   }
 }
 
-template <typename T, bool D16>
+template <typename T, bool D16, typename WT>
 __device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr,
                                           const void* __restrict__ col,
-                                          const T* __restrict__ w, const T* __restrict__ x,
+                                          const WT* __restrict__ w, const T* __restrict__ x,
                                           int row, int n, T xi, T& acc, T& d) {
   int beg, width;
   slice_bounds(sptr, row, beg, width);
@@ -144,8 +146,8 @@ __device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr,
 }
 
 // Same batching for the first two sweeps from zero: gathers b and D instead of x.
-template <typename T, bool D16, int N>
-__device__ __forceinline__ void row_two_n(const void* __restrict__ col, const T* __restrict__ w,
+template <typename T, bool D16, int N, typename WT>
+__device__ __forceinline__ void row_two_n(const void* __restrict__ col, const WT* __restrict__ w,
                                           const T* __restrict__ b, const T* __restrict__ diag,
                                           int beg, int lane, int row, int n, T omega, T xi,
                                           T& acc, T& d) {
@@ -155,7 +157,7 @@ __device__ __forceinline__ void row_two_n(const void* __restrict__ col, const T*
   for (int k = 0; k < N; ++k) {
     const int idx = (beg + k) * kSlice + lane;
     cj[k] = col_at<D16>(col, idx, row, n);
-    wk[k] = w[idx];
+    wk[k] = static_cast<T>(w[idx]);
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -189,10 +191,10 @@ __device__ __forceinline__ T restrict_n(const int32_t* __restrict__ col, const T
 // (x1 = omega b / D), so the second reads b and D at the neighbours instead of x1.  The
 // expressions are those of k_jacobi_zero and k_rows<T,2>, so the result is the same.  The
 // zero slot of D holds 1, making x1 there 0.
-template <typename T, bool D16>
+template <typename T, bool D16, typename WT = T>
 __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict__ sptr,
                                                        const void* __restrict__ col,
-                                                       const T* __restrict__ w,
+                                                       const WT* __restrict__ w,
                                                        const T* __restrict__ diag,
                                                        const T* __restrict__ b,
                                                        T* __restrict__ y, int32_t n, T omega,
@@ -229,10 +231,10 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict
 }
 
 // MODE 0: y = A x.  MODE 1: y = b - A x.  MODE 2: y = x + omega (b - A x) / D.
-template <typename T, int MODE, bool D16>
+template <typename T, int MODE, bool D16, typename WT = T>
 __global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ sptr,
                                                  const void* __restrict__ col,
-                                                 const T* __restrict__ w,
+                                                 const WT* __restrict__ w,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ b, T* __restrict__ y,
                                                  int32_t n, T omega,
@@ -295,6 +297,84 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__
       for (int k = 0; k < width; ++k) acc += rf[col[(beg + k) * kSlice + lane]];
   }
   rc[row] = rs + T(0.5) * acc;
+}
+
+// First post-smoothing sweep fused with the interpolation of the coarse correction.  The
+// corrected iterate x0 = x + M(f)^T e_c is formed on the fly, for the row and for each of its
+// neighbours, with the rounding of k_prolong; then xo = x0 + omega (b - A x0) / diag.  The
+// parent arrays have an entry for the zero slot (pointing at the coarse zero slot), so absent
+// neighbours contribute x0 = 0 without a branch.
+template <typename T, bool D16, int N, typename WT>
+__device__ __forceinline__ void row_prolong_n(const void* __restrict__ col,
+                                              const WT* __restrict__ w, const T* __restrict__ x,
+                                              const int32_t* __restrict__ pa,
+                                              const int32_t* __restrict__ pb,
+                                              const T* __restrict__ ec, int beg, int lane,
+                                              int row, int n, T xi0, T& acc, T& d) {
+  int cj[N], ca[N], cb[N];
+  T wk[N], xj[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    cj[k] = col_at<D16>(col, idx, row, n);
+    wk[k] = static_cast<T>(w[idx]);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    xj[k] = x[cj[k]];
+    ca[k] = pa[cj[k]];
+    cb[k] = pb[cj[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) xj[k] = xj[k] + T(0.5) * (ec[ca[k]] + ec[cb[k]]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    d += wk[k];
+    acc += wk[k] * (xi0 - xj[k]);
+  }
+}
+
+template <typename T, bool D16, typename WT = T>
+__global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restrict__ sptr,
+                                                          const void* __restrict__ col,
+                                                          const WT* __restrict__ w,
+                                                          const int32_t* __restrict__ pa,
+                                                          const int32_t* __restrict__ pb,
+                                                          const T* __restrict__ ec,
+                                                          const T* __restrict__ x,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ xo, int32_t n, T omega,
+                                                          const int* __restrict__ done) {
+  if (done && *done) return;
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= n) return;
+  const T xi0 = x[row] + T(0.5) * (ec[pa[row]] + ec[pb[row]]);
+  const T bi = b[row];
+  int beg, width;
+  slice_bounds(sptr, row, beg, width);
+  const int lane = row & 63;
+  T acc = T(0), d = T(0);
+  switch (width) {
+    case 0: break;
+    case 1: row_prolong_n<T, D16, 1>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 2: row_prolong_n<T, D16, 2>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 3: row_prolong_n<T, D16, 3>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 4: row_prolong_n<T, D16, 4>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 5: row_prolong_n<T, D16, 5>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 6: row_prolong_n<T, D16, 6>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 7: row_prolong_n<T, D16, 7>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    case 8: row_prolong_n<T, D16, 8>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
+    default:
+      for (int k = 0; k < width; ++k) {
+        const int idx = (beg + k) * kSlice + lane;
+        const int j = col_at<D16>(col, idx, row, n);
+        const T xj = x[j] + T(0.5) * (ec[pa[j]] + ec[pb[j]]);
+        const T wk = w[idx];
+        d += wk;
+        acc += wk * (xi0 - xj);
+      }
+  }
+  xo[row] = xi0 + omega * (bi - acc) / d;
 }
 
 // x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.
@@ -554,10 +634,10 @@ __global__ void k_star0(const double* __restrict__ s0, const double* __restrict_
 }
 
 // ------------------------------------------------------------------ Krylov kernels (FP64)
-template <bool D16>
+template <bool D16, typename WT = double>
 __global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict__ sptr,
                                                       const void* __restrict__ col,
-                                                      const double* __restrict__ w,
+                                                      const WT* __restrict__ w,
                                                       const double* __restrict__ p,
                                                       double* __restrict__ q,
                                                       const double* __restrict__ r,
@@ -612,10 +692,10 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
   if (threadIdx.x == 0) part0[blk] = v;
 }
 
-template <bool D16>
+template <bool D16, typename WT = double>
 __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restrict__ sptr,
                                                           const void* __restrict__ col,
-                                                          const double* __restrict__ w,
+                                                          const WT* __restrict__ w,
                                                           const double* __restrict__ x,
                                                           const double* __restrict__ b,
                                                           double* __restrict__ r,
@@ -976,18 +1056,38 @@ const double* diagonal<double>(const Level& L) { return L.op.diag64; }
 template <>
 const float* diagonal<float>(const Level& L) { return L.op.diag32; }
 
+// Calls f(w) with the weight array the T-arithmetic row kernels read: the FP32 copy for FP32
+// kernels, and for FP64 kernels too when every FP64 weight of the level is exactly an FP32
+// number (the widened values are then the FP64 weights bit for bit, at half the bytes).
+template <typename T, typename F>
+static void with_weights(const Level& L, F&& f) {
+  if constexpr (std::is_same<T, float>::value) {
+    f(L.op.w32);
+  } else {
+    if (L.op.w_exact32)
+      f(static_cast<const float*>(L.op.w32));
+    else
+      f(static_cast<const double*>(L.op.w64));
+  }
+}
+template <typename P>
+using pointee_t = std::remove_const_t<std::remove_pointer_t<P>>;
+
 template <typename T, int MODE>
 static void rows(const Level& L, const T* x, const T* b, T* y, double omega, const int* done,
                  hipStream_t s) {
   if (L.n == 0) return;
-  if (L.op.col16)
-    hipLaunchKernelGGL((k_rows<T, MODE, true>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col16), weights<T>(L), x, b, y, L.n,
-                       static_cast<T>(omega), done);
-  else
-    hipLaunchKernelGGL((k_rows<T, MODE, false>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col), weights<T>(L), x, b, y, L.n,
-                       static_cast<T>(omega), done);
+  with_weights<T>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipLaunchKernelGGL((k_rows<T, MODE, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col16), w, x, b, y, L.n,
+                         static_cast<T>(omega), done);
+    else
+      hipLaunchKernelGGL((k_rows<T, MODE, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col), w, x, b, y, L.n,
+                         static_cast<T>(omega), done);
+  });
 }
 // A weighted-Jacobi sweep whose start and stop are stamped into e0/e1 by the dispatch
 // itself (kernel execution time only, no queueing between the two events).
@@ -995,14 +1095,17 @@ template <typename T>
 void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done,
                   hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (L.n == 0) return;
-  if (L.op.col16)
-    hipExtLaunchKernelGGL((k_rows<T, 2, true>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0, e1, 0,
-                          L.op.sptr, static_cast<const void*>(L.op.col16), weights<T>(L), x, b, xo,
-                          L.n, static_cast<T>(omega), done);
-  else
-    hipExtLaunchKernelGGL((k_rows<T, 2, false>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0, e1, 0,
-                          L.op.sptr, static_cast<const void*>(L.op.col), weights<T>(L), x, b, xo,
-                          L.n, static_cast<T>(omega), done);
+  with_weights<T>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipExtLaunchKernelGGL((k_rows<T, 2, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0,
+                            e1, 0, L.op.sptr, static_cast<const void*>(L.op.col16), w, x, b, xo,
+                            L.n, static_cast<T>(omega), done);
+    else
+      hipExtLaunchKernelGGL((k_rows<T, 2, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0,
+                            e1, 0, L.op.sptr, static_cast<const void*>(L.op.col), w, x, b, xo, L.n,
+                            static_cast<T>(omega), done);
+  });
 }
 
 template <typename T>
@@ -1021,14 +1124,17 @@ void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const i
 template <typename T>
 void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
   if (L.n == 0) return;
-  if (L.op.col16)
-    hipLaunchKernelGGL((k_jacobi_two<T, true>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col16), weights<T>(L), diagonal<T>(L), b, xo,
-                       L.n, static_cast<T>(omega), done);
-  else
-    hipLaunchKernelGGL((k_jacobi_two<T, false>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col), weights<T>(L), diagonal<T>(L), b, xo,
-                       L.n, static_cast<T>(omega), done);
+  with_weights<T>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipLaunchKernelGGL((k_jacobi_two<T, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col16), w, diagonal<T>(L), b, xo,
+                         L.n, static_cast<T>(omega), done);
+    else
+      hipLaunchKernelGGL((k_jacobi_two<T, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col), w, diagonal<T>(L), b, xo,
+                         L.n, static_cast<T>(omega), done);
+  });
 }
 template <typename T>
 void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
@@ -1049,6 +1155,22 @@ void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int
   if (Lf.n == 0) return;
   hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s, Lf.tr.pa, Lf.tr.pb,
                      ec, xf, Lf.n, done);
+}
+template <typename T>
+void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x, const T* b,
+                   T* xo, double omega, const int* done, hipStream_t s) {
+  if (Lf.n == 0) return;
+  with_weights<T>(Lf, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (Lf.op.col16)
+      hipLaunchKernelGGL((k_prolong_sweep<T, true, WT>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s,
+                         Lf.op.sptr, static_cast<const void*>(Lf.op.col16), w, Lf.tr.pa, Lf.tr.pb,
+                         ec, x, b, xo, Lf.n, static_cast<T>(omega), done);
+    else
+      hipLaunchKernelGGL((k_prolong_sweep<T, false, WT>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s,
+                         Lf.op.sptr, static_cast<const void*>(Lf.op.col), w, Lf.tr.pa, Lf.tr.pb,
+                         ec, x, b, xo, Lf.n, static_cast<T>(omega), done);
+  });
 }
 template <typename T>
 void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s) {
@@ -1131,12 +1253,17 @@ void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t
 
 void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, const int* done, hipStream_t s) {
-  if (L.op.col16)
-    hipLaunchKernelGGL(k_spmv_dot2<true>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col16), L.op.w64, p, q, r, part0, part1, L.n, done);
-  else
-    hipLaunchKernelGGL(k_spmv_dot2<false>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col), L.op.w64, p, q, r, part0, part1, L.n, done);
+  with_weights<double>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipLaunchKernelGGL((k_spmv_dot2<true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col16), w, p, q, r, part0, part1,
+                         L.n, done);
+    else
+      hipLaunchKernelGGL((k_spmv_dot2<false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col), w, p, q, r, part0, part1,
+                         L.n, done);
+  });
 }
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
                double* r, float* r32, double* part0, const int* done, hipStream_t s) {
@@ -1145,14 +1272,17 @@ void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q
 }
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s) {
-  if (L.op.col16)
-    hipLaunchKernelGGL(k_residual_norm<true>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col16), L.op.w64, x, b, r, r32, sc, part0, L.n,
-                       done);
-  else
-    hipLaunchKernelGGL(k_residual_norm<false>, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.op.sptr,
-                       static_cast<const void*>(L.op.col), L.op.w64, x, b, r, r32, sc, part0, L.n,
-                       done);
+  with_weights<double>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipLaunchKernelGGL((k_residual_norm<true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col16), w, x, b, r, r32, sc,
+                         part0, L.n, done);
+    else
+      hipLaunchKernelGGL((k_residual_norm<false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, static_cast<const void*>(L.op.col), w, x, b, r, r32, sc, part0,
+                         L.n, done);
+  });
 }
 void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
              hipStream_t s) {
@@ -1219,6 +1349,8 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
                                 hipStream_t, hipEvent_t, hipEvent_t);                           \
   template void restrict_<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t); \
   template void prolong<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t);  \
+  template void prolong_sweep<T>(const Level&, const Level&, const T*, const T*, const T*, T*,  \
+                                 double, const int*, hipStream_t);                              \
   template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \
   template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
                                 hipStream_t);                                                  \

@@ -84,8 +84,18 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
   k::residual<T>(L, cur, b, V.r, done, s);
   k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
   T* ec = vcycle<T>(H, l - 1, vecs<T>(C).b, nullptr, o, done, s);
-  k::prolong<T>(L, C, ec, cur, done, s);
-  for (int i = 0; i < o.nu2; ++i) {
+  int post = o.nu2;
+  if (post >= 1 && L.n <= kFuseProlongRows) {
+    // the first post-smoothing sweep reads x + P e_c directly (one launch fewer on levels
+    // whose kernels are launch-bound; on large levels the extra dependent gathers cost more
+    // than the separate interpolation pass)
+    k::prolong_sweep<T>(L, C, ec, cur, b, oth, o.omega, done, s);
+    std::swap(cur, oth);
+    --post;
+  } else {
+    k::prolong<T>(L, C, ec, cur, done, s);
+  }
+  for (; post > 0; --post) {
     sweep<T>(H, l, cur, b, oth, o.omega, done, s);
     std::swap(cur, oth);
   }

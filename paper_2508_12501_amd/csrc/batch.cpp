@@ -79,7 +79,7 @@ T* vcycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, hipStream_t s) {
   bk::restrict_<T>(M, L, C, V.r, VC.b, fl, s);
   T* ec = vcycle_b<T>(o, G, l - 1, VC.b, s);
   int post = o.nu2;
-  if (post >= 1 && int64_t(L.n) * M <= kFuseProlongRows) {
+  if (post >= 1 && int64_t(L.n) * M <= kLaunchBoundRows) {
     bk::prolong_sweep<T>(M, L, ec, cur, b, oth, o.omega, fl, s);
     std::swap(cur, oth);
     --post;

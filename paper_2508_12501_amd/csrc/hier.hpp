@@ -55,9 +55,16 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t* r_col = nullptr;
 };
 
-constexpr int32_t kFuseProlongRows = 1 << 19;   // fuse interpolation into the first post sweep up to this size
+// Levels up to this many rows are launch-bound: there the interpolation is fused into the
+// first post-smoothing sweep (one launch fewer); on larger levels the extra dependent gathers
+// of the fused kernel cost more than the separate pass.
+constexpr int32_t kLaunchBoundRows = 1 << 19;
 constexpr int kCoarseThreads = 1024;       // workgroup of the fused coarse cycle
 constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse cycle
+// Largest level the fused coarse cycle takes.  It runs in one workgroup, whose memory
+// throughput (one CU's outstanding misses) makes it pay only for levels whose operator data is
+// a few tens of KB; larger levels run as regular multi-workgroup launches.
+constexpr int32_t kCoarseFuseRows = 2048;
 
 // Per-level descriptor of the fused coarse cycle (device copy per precision).
 template <typename T>

@@ -377,6 +377,7 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
     const size_t ints2 = ints + size_t(L.op.nslices + 1) + (l >= 1 ? size_t(L.tr.nslices + 1) : 0);
     const size_t off2 = (vec2 + 7) / 8 * 8 + inv_bytes;
     if (off2 + ints2 * sizeof(int32_t) > size_t(H.lds_limit)) break;
+    if (L.n > kCoarseFuseRows) break;
     CoarseLevel<T>& c = hv[l];
     c.n = L.n;
     c.lds = int32_t(vec / sizeof(T));

@@ -85,7 +85,7 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
   k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
   T* ec = vcycle<T>(H, l - 1, vecs<T>(C).b, nullptr, o, done, s);
   int post = o.nu2;
-  if (post >= 1 && L.n <= kFuseProlongRows) {
+  if (post >= 1 && L.n <= kLaunchBoundRows) {
     // the first post-smoothing sweep reads x + P e_c directly (one launch fewer on levels
     // whose kernels are launch-bound; on large levels the extra dependent gathers cost more
     // than the separate interpolation pass)

@@ -34,6 +34,7 @@ constexpr int kUnroll = 8;           // rows up to this many entries take the ba
 
 struct DevOperator {
   int32_t nslices = 0, ncols = 0;
+  int32_t uw = -1;            // every slice has this width (ELL layout), or -1
   int32_t* sptr = nullptr;
   int32_t* col = nullptr;
   // The same columns as offsets from the row (kZeroSlot16 = zero slot), when every offset of
@@ -51,6 +52,7 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t* pb = nullptr;
   int32_t* r_self = nullptr;  // n_c: fine internal id of the kept vertex
   int32_t nslices = 0, ncols = 0;
+  int32_t r_uw = -1;          // uniform slice width of the restriction lists, or -1
   int32_t* r_sptr = nullptr;  // SELL over coarse rows of the fine midpoints (weight 1/2)
   int32_t* r_col = nullptr;
 };

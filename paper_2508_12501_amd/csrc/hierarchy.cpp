@@ -131,6 +131,33 @@ T* zeros(int64_t n) {
   return d;
 }
 
+// Pads every slice of a SELL-64 layout (`col` per entry, `aux` per entry when not null, slice
+// pointers `sptr` in columns) to the widest slice when that adds at most 1/16 of the entries:
+// the kernels then compute slice bounds instead of loading them.  Returns the uniform width, or
+// -1 (layout unchanged).  Padding entries are `fill_col` / `fill_aux`.
+int32_t make_uniform(std::vector<int32_t>& sptr, std::vector<int32_t>& col,
+                     std::vector<int32_t>* aux, int32_t fill_col, int32_t fill_aux) {
+  const int32_t nslices = int32_t(sptr.size()) - 1;
+  if (nslices <= 0) return -1;
+  int32_t wmax = 0;
+  for (int32_t s = 0; s < nslices; ++s) wmax = std::max(wmax, sptr[s + 1] - sptr[s]);
+  const int64_t have = sptr[nslices], want = int64_t(wmax) * nslices;
+  if (want - have > have / 16) return -1;
+  std::vector<int32_t> c2(size_t(want) * kSlice, fill_col), a2;
+  if (aux) a2.assign(size_t(want) * kSlice, fill_aux);
+  for (int32_t s = 0; s < nslices; ++s)
+    for (int32_t k = 0; k < sptr[s + 1] - sptr[s]; ++k)
+      for (int l = 0; l < kSlice; ++l) {
+        const size_t from = size_t(sptr[s] + k) * kSlice + l, to = size_t(s * wmax + k) * kSlice + l;
+        c2[to] = col[from];
+        if (aux) a2[to] = (*aux)[from];
+      }
+  for (int32_t s = 0; s <= nslices; ++s) sptr[s] = s * wmax;
+  col.swap(c2);
+  if (aux) aux->swap(a2);
+  return wmax;
+}
+
 // SELL-64 structure of the operator: per internal row, the couplings with nonzero star1,
 // sorted by column; neighbours that are not unknowns point at the zero slot n.
 void build_operator_structure(Level& L, std::vector<int32_t>& col) {
@@ -171,6 +198,7 @@ void build_operator_structure(Level& L, std::vector<int32_t>& col) {
         L.entry_edge[base + k * kSlice + l] = rows[l][k].second;
       }
   }
+  L.op.uw = make_uniform(L.sptr_h, col, &L.entry_edge, n, -1);
   L.op.nslices = nslices;
   L.op.ncols = L.sptr_h[nslices];
   L.nnz = 0;
@@ -323,6 +351,7 @@ void build_transfer(Level& F, const Level& C) {
     for (int l = 0; l < kSlice; ++l)
       for (size_t k = 0; k < rows[l].size(); ++k) col[base + k * kSlice + l] = rows[l][k];
   }
+  F.tr.r_uw = make_uniform(sptr, col, nullptr, F.n, 0);
   col.resize(col.size() + kSlice, F.n);   // padding column
   F.tr.pa = upload(pa);
   F.tr.pb = upload(pb);

@@ -81,13 +81,29 @@ __device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int
   return static_cast<const int32_t*>(col)[idx];
 }
 
+// Launch-bound kernels (n <= kLaunchBoundRows) issue the load of the convergence flag with their
+// other first loads and test it only before their stores, which takes a dependent memory round
+// trip off their critical path; large launches test it first, so a replay after convergence
+// costs one flag read instead of a pass over the data.
+#define DECMG_DONE_LOAD(n)                    \
+  const int dn_ = done ? *done : 0;           \
+  if ((n) > kLaunchBoundRows && dn_) return;
+#define DECMG_DONE_CHECK() \
+  if (dn_) return;
+
 // Slice bounds of the wavefront holding `row`.  All 64 lanes of a wavefront share one slice,
-// so the bounds are scalar loads and the entry loop below has a wave-uniform trip count.
-__device__ __forceinline__ void slice_bounds(const int32_t* __restrict__ sptr, int row, int& beg,
-                                             int& width) {
+// so the bounds are scalar loads and the entry loop below has a wave-uniform trip count.  A
+// level whose slices all have the same width (uw >= 0) needs no load at all.
+__device__ __forceinline__ void slice_bounds(const int32_t* __restrict__ sptr, int uw, int row,
+                                             int& beg, int& width) {
   const int s = __builtin_amdgcn_readfirstlane(row >> 6);
-  beg = sptr[s];
-  width = sptr[s + 1] - beg;
+  if (uw >= 0) {   // uniform width (ELL): no load
+    beg = s * uw;
+    width = uw;
+  } else {
+    beg = sptr[s];
+    width = sptr[s + 1] - beg;
+  }
 }
 
 // acc = sum_k w_k (x_i - x_j(k)) and d = sum_k w_k over the row's SELL entries, in entry
@@ -116,12 +132,12 @@ __device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const 
 }
 
 template <typename T, bool D16, typename WT>
-__device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr,
+__device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr, int uw,
                                           const void* __restrict__ col,
                                           const WT* __restrict__ w, const T* __restrict__ x,
                                           int row, int n, T xi, T& acc, T& d) {
   int beg, width;
-  slice_bounds(sptr, row, beg, width);
+  slice_bounds(sptr, uw, row, beg, width);
   const int lane = row & 63;
   acc = T(0);
   d = T(0);
@@ -192,18 +208,18 @@ __device__ __forceinline__ T restrict_n(const int32_t* __restrict__ col, const T
 // expressions are those of k_jacobi_zero and k_rows<T,2>, so the result is the same.  The
 // zero slot of D holds 1, making x1 there 0.
 template <typename T, bool D16, typename WT = T>
-__global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict__ sptr,
+__global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict__ sptr, int32_t uw,
                                                        const void* __restrict__ col,
                                                        const WT* __restrict__ w,
                                                        const T* __restrict__ diag,
                                                        const T* __restrict__ b,
                                                        T* __restrict__ y, int32_t n, T omega,
                                                        const int* __restrict__ done) {
-  if (done && *done) return;
+  DECMG_DONE_LOAD(n)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= n) return;
   int beg, width;
-  slice_bounds(sptr, row, beg, width);
+  slice_bounds(sptr, uw, row, beg, width);
   const int lane = row & 63;
   const T bi = b[row];
   const T xi = omega * bi / diag[row];
@@ -227,25 +243,27 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict
         acc += wk * (xi - omega * b[j] / diag[j]);
       }
   }
+  DECMG_DONE_CHECK()
   y[row] = xi + omega * (bi - acc) / d;
 }
 
 // MODE 0: y = A x.  MODE 1: y = b - A x.  MODE 2: y = x + omega (b - A x) / D.
 template <typename T, int MODE, bool D16, typename WT = T>
-__global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ sptr,
+__global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ sptr, int32_t uw,
                                                  const void* __restrict__ col,
                                                  const WT* __restrict__ w,
                                                  const T* __restrict__ x,
                                                  const T* __restrict__ b, T* __restrict__ y,
                                                  int32_t n, T omega,
                                                  const int* __restrict__ done) {
-  if (done && *done) return;
+  DECMG_DONE_LOAD(n)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= n) return;
   const T xi = x[row];
   const T bi = (MODE == 0) ? T(0) : b[row];
   T acc, d;
-  row_apply<T, D16>(sptr, col, w, x, row, n, xi, acc, d);
+  row_apply<T, D16>(sptr, uw, col, w, x, row, n, xi, acc, d);
+  DECMG_DONE_CHECK()
   if (MODE == 0)
     y[row] = acc;
   else if (MODE == 1)
@@ -260,26 +278,28 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_zero(const T* __restrict__ di
                                                         const T* __restrict__ b,
                                                         T* __restrict__ y, int32_t n, T omega,
                                                         const int* __restrict__ done) {
-  if (done && *done) return;
+  DECMG_DONE_LOAD(n)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= n) return;
-  y[row] = omega * b[row] / diag[row];
+  const T v = omega * b[row] / diag[row];
+  DECMG_DONE_CHECK()
+  y[row] = v;
 }
 
 // r_c = M(f) r_f: the kept vertex with weight 1, every midpoint of an incident coarse edge
 // with weight 1/2.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__ self,
-                                                     const int32_t* __restrict__ sptr,
+                                                     const int32_t* __restrict__ sptr, int32_t uw,
                                                      const int32_t* __restrict__ col,
                                                      const T* __restrict__ rf,
                                                      T* __restrict__ rc, int32_t nc,
                                                      const int* __restrict__ done) {
-  if (done && *done) return;
+  DECMG_DONE_LOAD(nc)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= nc) return;
   int beg, width;
-  slice_bounds(sptr, row, beg, width);
+  slice_bounds(sptr, uw, row, beg, width);
   const int lane = row & 63;
   const T rs = rf[self[row]];
   T acc = T(0);
@@ -296,6 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__
     default:
       for (int k = 0; k < width; ++k) acc += rf[col[(beg + k) * kSlice + lane]];
   }
+  DECMG_DONE_CHECK()
   rc[row] = rs + T(0.5) * acc;
 }
 
@@ -335,7 +356,7 @@ __device__ __forceinline__ void row_prolong_n(const void* __restrict__ col,
 }
 
 template <typename T, bool D16, typename WT = T>
-__global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restrict__ sptr,
+__global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restrict__ sptr, int32_t uw,
                                                           const void* __restrict__ col,
                                                           const WT* __restrict__ w,
                                                           const int32_t* __restrict__ pa,
@@ -345,13 +366,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
                                                           const T* __restrict__ b,
                                                           T* __restrict__ xo, int32_t n, T omega,
                                                           const int* __restrict__ done) {
-  if (done && *done) return;
+  DECMG_DONE_LOAD(n)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= n) return;
   const T xi0 = x[row] + T(0.5) * (ec[pa[row]] + ec[pb[row]]);
   const T bi = b[row];
   int beg, width;
-  slice_bounds(sptr, row, beg, width);
+  slice_bounds(sptr, uw, row, beg, width);
   const int lane = row & 63;
   T acc = T(0), d = T(0);
   switch (width) {
@@ -374,6 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
         acc += wk * (xi0 - xj);
       }
   }
+  DECMG_DONE_CHECK()
   xo[row] = xi0 + omega * (bi - acc) / d;
 }
 
@@ -384,10 +406,12 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ 
                                                     const T* __restrict__ ec,
                                                     T* __restrict__ xf, int32_t nf,
                                                     const int* __restrict__ done) {
-  if (done && *done) return;
+  DECMG_DONE_LOAD(nf)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= nf) return;
-  xf[row] += T(0.5) * (ec[pa[row]] + ec[pb[row]]);
+  const T v = xf[row] + T(0.5) * (ec[pa[row]] + ec[pb[row]]);
+  DECMG_DONE_CHECK()
+  xf[row] = v;
 }
 
 // Exact coarsest solve x = A0^{-1} b in FP64 by one workgroup.
@@ -635,7 +659,7 @@ __global__ void k_star0(const double* __restrict__ s0, const double* __restrict_
 
 // ------------------------------------------------------------------ Krylov kernels (FP64)
 template <bool D16, typename WT = double>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict__ sptr,
+__global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict__ sptr, int32_t uw,
                                                       const void* __restrict__ col,
                                                       const WT* __restrict__ w,
                                                       const double* __restrict__ p,
@@ -652,7 +676,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict_
     const double pi = p[row];
     const double ri = r[row];
     double acc, d;
-    row_apply<double, D16>(sptr, col, w, p, row, n, pi, acc, d);
+    row_apply<double, D16>(sptr, uw, col, w, p, row, n, pi, acc, d);
     q[row] = acc;
     v0 = pi * acc;
     v1 = pi * ri;
@@ -693,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
 }
 
 template <bool D16, typename WT = double>
-__global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restrict__ sptr,
+__global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restrict__ sptr, int32_t uw,
                                                           const void* __restrict__ col,
                                                           const WT* __restrict__ w,
                                                           const double* __restrict__ x,
@@ -710,7 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restr
   if (row < n) {
     const double bi = b[row];
     double acc, d;
-    row_apply<double, D16>(sptr, col, w, x, row, n, x[row], acc, d);
+    row_apply<double, D16>(sptr, uw, col, w, x, row, n, x[row], acc, d);
     const double ri = bi - acc;
     r[row] = ri;
     v = ri * ri;
@@ -1081,11 +1105,11 @@ static void rows(const Level& L, const T* x, const T* b, T* y, double omega, con
     using WT = pointee_t<decltype(w)>;
     if (L.op.col16)
       hipLaunchKernelGGL((k_rows<T, MODE, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col16), w, x, b, y, L.n,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, y, L.n,
                          static_cast<T>(omega), done);
     else
       hipLaunchKernelGGL((k_rows<T, MODE, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col), w, x, b, y, L.n,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, x, b, y, L.n,
                          static_cast<T>(omega), done);
   });
 }
@@ -1099,11 +1123,11 @@ void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, c
     using WT = pointee_t<decltype(w)>;
     if (L.op.col16)
       hipExtLaunchKernelGGL((k_rows<T, 2, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0,
-                            e1, 0, L.op.sptr, static_cast<const void*>(L.op.col16), w, x, b, xo,
+                            e1, 0, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, xo,
                             L.n, static_cast<T>(omega), done);
     else
       hipExtLaunchKernelGGL((k_rows<T, 2, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0,
-                            e1, 0, L.op.sptr, static_cast<const void*>(L.op.col), w, x, b, xo, L.n,
+                            e1, 0, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, x, b, xo, L.n,
                             static_cast<T>(omega), done);
   });
 }
@@ -1128,11 +1152,11 @@ void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done
     using WT = pointee_t<decltype(w)>;
     if (L.op.col16)
       hipLaunchKernelGGL((k_jacobi_two<T, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col16), w, diagonal<T>(L), b, xo,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, diagonal<T>(L), b, xo,
                          L.n, static_cast<T>(omega), done);
     else
       hipLaunchKernelGGL((k_jacobi_two<T, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col), w, diagonal<T>(L), b, xo,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, diagonal<T>(L), b, xo,
                          L.n, static_cast<T>(omega), done);
   });
 }
@@ -1147,7 +1171,7 @@ void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* 
                hipStream_t s) {
   if (Lc.n == 0) return;
   hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s, Lf.tr.r_self,
-                     Lf.tr.r_sptr, Lf.tr.r_col, rf, rc, Lc.n, done);
+                     Lf.tr.r_sptr, Lf.tr.r_uw, Lf.tr.r_col, rf, rc, Lc.n, done);
 }
 template <typename T>
 void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int* done,
@@ -1164,11 +1188,11 @@ void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x
     using WT = pointee_t<decltype(w)>;
     if (Lf.op.col16)
       hipLaunchKernelGGL((k_prolong_sweep<T, true, WT>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s,
-                         Lf.op.sptr, static_cast<const void*>(Lf.op.col16), w, Lf.tr.pa, Lf.tr.pb,
+                         Lf.op.sptr, Lf.op.uw, static_cast<const void*>(Lf.op.col16), w, Lf.tr.pa, Lf.tr.pb,
                          ec, x, b, xo, Lf.n, static_cast<T>(omega), done);
     else
       hipLaunchKernelGGL((k_prolong_sweep<T, false, WT>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s,
-                         Lf.op.sptr, static_cast<const void*>(Lf.op.col), w, Lf.tr.pa, Lf.tr.pb,
+                         Lf.op.sptr, Lf.op.uw, static_cast<const void*>(Lf.op.col), w, Lf.tr.pa, Lf.tr.pb,
                          ec, x, b, xo, Lf.n, static_cast<T>(omega), done);
   });
 }
@@ -1257,11 +1281,11 @@ void spmv_dot2(const Level& L, const double* p, double* q, const double* r, doub
     using WT = pointee_t<decltype(w)>;
     if (L.op.col16)
       hipLaunchKernelGGL((k_spmv_dot2<true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col16), w, p, q, r, part0, part1,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, p, q, r, part0, part1,
                          L.n, done);
     else
       hipLaunchKernelGGL((k_spmv_dot2<false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col), w, p, q, r, part0, part1,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, p, q, r, part0, part1,
                          L.n, done);
   });
 }
@@ -1276,11 +1300,11 @@ void residual_norm(const Level& L, const double* x, const double* b, double* r, 
     using WT = pointee_t<decltype(w)>;
     if (L.op.col16)
       hipLaunchKernelGGL((k_residual_norm<true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col16), w, x, b, r, r32, sc,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, r, r32, sc,
                          part0, L.n, done);
     else
       hipLaunchKernelGGL((k_residual_norm<false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, static_cast<const void*>(L.op.col), w, x, b, r, r32, sc, part0,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, x, b, r, r32, sc, part0,
                          L.n, done);
   });
 }

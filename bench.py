@@ -362,13 +362,13 @@ def main():
         "speedup_mixed_vs_fp64": value / value_fp64,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_rows<float, 2, %s> (FP32 weighted-Jacobi sweep, finest level)"
+            "kernel": "k_rows<float, 2, %s, float> (FP32 weighted-Jacobi sweep, finest level)"
                       % ("true" if info["index_bytes"] == 2 else "false"),
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic("k_rows<float, 2, %s>@%d" % (
+            "traffic": recorded_traffic("k_rows<float, 2, %s, float>@%d" % (
                 "true" if info["index_bytes"] == 2 else "false", (unknowns + 255) // 256 * 256)),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": by_j32,

@@ -145,6 +145,36 @@ def vcycle(h: Hierarchy, b, x=None, l=None, nu1=2, nu2=2, omega=0.8):
     return x
 
 
+def mgcycle(h: Hierarchy, b, x=None, l=None, kind="V", nu1=2, nu2=2, omega=0.8):
+    """One multigrid cycle of shape `kind` for A_l x = b (the V-, W- and F-cycles named in
+    Sec. 2, textbook recursion): pre-smooth, restrict the residual, coarse-grid correction,
+    interpolate and correct, post-smooth.  The coarse-grid correction is one cycle of the same
+    shape from zero for V, two for W (the second starting from the first's result), and an
+    F-cycle followed by a V-cycle for F.  On the coarsest level every shape is the exact solve."""
+    if l is None:
+        l = h.top
+    if l == 0:
+        return coarse_solve(h, b)
+    A = h.levels[l].A
+    x = np.zeros_like(b) if x is None else x.copy()
+    x = jacobi(A, b, x, omega, nu1)
+    r = b - A @ x
+    rc = h.restrict(l, r)
+    if kind == "V":
+        ec = mgcycle(h, rc, None, l - 1, "V", nu1, nu2, omega)
+    elif kind == "W":
+        ec = mgcycle(h, rc, None, l - 1, "W", nu1, nu2, omega)
+        ec = mgcycle(h, rc, ec, l - 1, "W", nu1, nu2, omega)
+    elif kind == "F":
+        ec = mgcycle(h, rc, None, l - 1, "F", nu1, nu2, omega)
+        ec = mgcycle(h, rc, ec, l - 1, "V", nu1, nu2, omega)
+    else:
+        raise ValueError(kind)
+    x = x + h.prolong(l, ec)
+    x = jacobi(A, b, x, omega, nu2)
+    return x
+
+
 def vcycle_paper(h: Hierarchy, f, x=None, l=None, nu1=2, nu2=2, omega=0.8):
     """The same cycle for the paper's scaling, star0^{-1} L x = f, with the row-normalised
     restriction of Def. 6 (Dirichlet identity rows kept unscaled)."""
@@ -177,8 +207,8 @@ def _project(h: Hierarchy, v):
     return v - v.mean() if h.bc == "natural" else v
 
 
-def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.8):
-    """Stand-alone multigrid: repeat V-cycles from x = 0 until ||b - A x|| <= rtol ||b||.
+def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.8, cycle="V"):
+    """Stand-alone multigrid: repeat cycles from x = 0 until ||b - A x|| <= rtol ||b||.
     Returns (x, cycles, history of relative residuals)."""
     A = h.fine.A
     b = _project(h, b)
@@ -187,17 +217,17 @@ def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.
     hist = [1.0]
     k = 0
     while hist[-1] > rtol and k < max_cycles and nb > 0:
-        x = vcycle(h, b, x, None, nu1, nu2, omega)
+        x = mgcycle(h, b, x, None, cycle, nu1, nu2, omega)
         k += 1
         hist.append(np.linalg.norm(b - A @ x) / nb)
     return _project(h, x), k, hist
 
 
-def _precond(h, r, nu1, nu2, omega):
-    return _project(h, vcycle(h, r, None, None, nu1, nu2, omega))
+def _precond(h, r, nu1, nu2, omega, cycle="V"):
+    return _project(h, mgcycle(h, r, None, None, cycle, nu1, nu2, omega))
 
 
-def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8):
+def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, cycle="V"):
     """Conjugate gradients preconditioned by one V-cycle (Sec. 3.1, CG-GMG), x0 = 0, stopped
     on the recursively updated residual.  Returns (x, iterations, history)."""
     A = h.fine.A
@@ -208,7 +238,7 @@ def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8):
     hist = [1.0 if nb > 0 else 0.0]
     if nb == 0:
         return x, 0, hist
-    z = _precond(h, r, nu1, nu2, omega)
+    z = _precond(h, r, nu1, nu2, omega, cycle)
     p = z.copy()
     rho = r @ z
     k = 0
@@ -221,14 +251,15 @@ def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8):
         hist.append(np.linalg.norm(r) / nb)
         if hist[-1] <= rtol:
             break
-        z = _precond(h, r, nu1, nu2, omega)
+        z = _precond(h, r, nu1, nu2, omega, cycle)
         rho_new = r @ z
         p = z + (rho_new / rho) * p
         rho = rho_new
     return _project(h, x), k, hist
 
 
-def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None):
+def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None,
+           cycle="V"):
     """Flexible CG with one-vector truncation (FCG(1)): alpha = p^T r / p^T q,
     beta = -z^T q_prev / p_prev^T q_prev.  ``precond`` defaults to one V-cycle; passing
     another callable lets a test emulate a perturbed (e.g. lower precision) cycle."""
@@ -240,7 +271,7 @@ def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, p
     hist = [1.0 if nb > 0 else 0.0]
     if nb == 0:
         return x, 0, hist
-    M = precond or (lambda v: vcycle(h, v, None, None, nu1, nu2, omega))
+    M = precond or (lambda v: mgcycle(h, v, None, None, cycle, nu1, nu2, omega))
     p_prev = q_prev = None
     k = 0
     while k < max_iter:
@@ -261,14 +292,15 @@ def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, p
     return _project(h, x), k, hist
 
 
-def mg_ir(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None):
+def mg_ir(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None,
+          cycle="V"):
     """Iterative refinement: x <- x + M(b - A x) with the true residual recomputed each
     step."""
     A = h.fine.A
     b = _project(h, b)
     nb = np.linalg.norm(b)
     x = np.zeros_like(b)
-    M = precond or (lambda v: vcycle(h, v, None, None, nu1, nu2, omega))
+    M = precond or (lambda v: mgcycle(h, v, None, None, cycle, nu1, nu2, omega))
     r = b.copy()
     hist = [1.0 if nb > 0 else 0.0]
     k = 0

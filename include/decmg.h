@@ -151,6 +151,14 @@ mg_status mg_prolong(mg_hierarchy* h, int32_t level, int32_t dtype, const void* 
                      void* x_fine, void* stream);
 
 /* ------------------------------------------------------------------ solvers */
+/* Cycle shapes (Sec. 2 names V-, W- and F-cycles): the coarse-grid correction of a level is
+ * one cycle of the same shape from zero (V), two (W: the second starts from the first's
+ * result), or an F-cycle followed by a V-cycle (F).  The W-cycle is symmetric like the V-cycle;
+ * the F-cycle is not, so pair it with MG_OUTER_FCG or MG_OUTER_IR. */
+#define MG_CYCLE_V 0
+#define MG_CYCLE_W 1
+#define MG_CYCLE_F 2
+
 typedef struct {
   int32_t nu1, nu2;      /* pre/post Jacobi sweeps (2, 2) */
   double omega;          /* Jacobi weight (0.8) */
@@ -160,7 +168,7 @@ typedef struct {
   int32_t max_iter;      /* (200) */
   int32_t check_every;   /* iterations enqueued between host convergence checks (4) */
   int32_t use_graph;     /* replay the iteration as a hipGraph (1) */
-  int32_t reserved;
+  int32_t cycle;         /* MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F (V) */
 } mg_opts;
 void mg_opts_default(mg_opts* o);
 

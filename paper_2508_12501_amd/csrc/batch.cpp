@@ -49,8 +49,11 @@ template <typename T> std::vector<BatchLevelVecs<T>>& bvecs(BatchGroup& G);
 template <> std::vector<BatchLevelVecs<float>>& bvecs<float>(BatchGroup& G) { return G.v32; }
 template <> std::vector<BatchLevelVecs<double>>& bvecs<double>(BatchGroup& G) { return G.v64; }
 
+// One cycle of shape `kind` (V, W or F, as in the single-column solver) on level l, from zero
+// or from x_init (a buffer of this level).
 template <typename T>
-T* vcycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, hipStream_t s) {
+T* cycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, T* x_init, int kind,
+           hipStream_t s) {
   Hierarchy& H = *G.H;
   Level& L = *H.lv[l];
   BatchLevelVecs<T>& V = bvecs<T>(G)[l];
@@ -60,14 +63,21 @@ T* vcycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, hipStream_t s) {
     bk::coarse<T>(M, H, b, V.x, fl, s);
     return V.x;
   }
-  T* cur = V.x;
-  T* oth = V.t;
+  T* cur;
+  T* oth;
   int pre = o.nu1;
-  if (pre >= 1) {
-    bk::jacobi_zero<T>(M, L, b, cur, o.omega, fl, s);
-    --pre;
+  if (x_init) {
+    cur = x_init;
+    oth = (x_init == V.t) ? V.x : V.t;
   } else {
-    bk::zero(cur, size_t(L.n) * M * sizeof(T), s);
+    cur = V.x;
+    oth = V.t;
+    if (pre >= 1) {
+      bk::jacobi_zero<T>(M, L, b, cur, o.omega, fl, s);
+      --pre;
+    } else {
+      bk::zero(cur, size_t(L.n) * M * sizeof(T), s);
+    }
   }
   for (; pre > 0; --pre) {
     bk::rows<T>(2, M, L, cur, b, oth, o.omega, fl, s);
@@ -77,7 +87,16 @@ T* vcycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, hipStream_t s) {
   BatchLevelVecs<T>& VC = bvecs<T>(G)[l - 1];
   bk::rows<T>(1, M, L, cur, b, V.r, 0.0, fl, s);
   bk::restrict_<T>(M, L, C, V.r, VC.b, fl, s);
-  T* ec = vcycle_b<T>(o, G, l - 1, VC.b, s);
+  T* ec;
+  if (kind == MG_CYCLE_W) {
+    ec = cycle_b<T>(o, G, l - 1, VC.b, nullptr, MG_CYCLE_W, s);
+    ec = cycle_b<T>(o, G, l - 1, VC.b, ec, MG_CYCLE_W, s);
+  } else if (kind == MG_CYCLE_F) {
+    ec = cycle_b<T>(o, G, l - 1, VC.b, nullptr, MG_CYCLE_F, s);
+    ec = cycle_b<T>(o, G, l - 1, VC.b, ec, MG_CYCLE_V, s);
+  } else {
+    ec = cycle_b<T>(o, G, l - 1, VC.b, nullptr, MG_CYCLE_V, s);
+  }
   int post = o.nu2;
   if (post >= 1 && int64_t(L.n) * M <= kLaunchBoundRows) {
     bk::prolong_sweep<T>(M, L, ec, cur, b, oth, o.omega, fl, s);
@@ -108,7 +127,7 @@ void enqueue_iter(const mg_opts& o, BatchGroup& G, hipStream_t s) {
   float* r32 = nullptr;
   if (o.precision == MG_F32) {
     r32 = G.v32[top].b;
-    float* z = vcycle_b<float>(o, G, top, r32, s);
+    float* z = cycle_b<float>(o, G, top, r32, nullptr, o.cycle, s);
     if (natural) {
       bk::colsum32(M, n, z, G.col, P0, nb, fl, s);
       bk::finalize(bk::FIN_MEAN, M, nb, P0, nullptr, G.col, fl, 0, s);
@@ -117,7 +136,7 @@ void enqueue_iter(const mg_opts& o, BatchGroup& G, hipStream_t s) {
     bk::finalize(bk::FIN_BETA_FCG, M, nb, P0, nullptr, G.col, fl, 0, s);
     bk::pupd<float>(M, n, G.col, z, G.P, natural, fl, s);
   } else {
-    double* z = vcycle_b<double>(o, G, top, G.R, s);
+    double* z = cycle_b<double>(o, G, top, G.R, nullptr, o.cycle, s);
     if (natural) {
       bk::colsum(M, n, z, P0, nb, fl, s);
       bk::finalize(bk::FIN_MEAN, M, nb, P0, nullptr, G.col, fl, 0, s);

@@ -72,6 +72,8 @@ mg_status check_opts(const mg_opts* o) {
     return fail(MG_EINVAL, "unknown outer method");
   if (!(o->rtol > 0.0) || !std::isfinite(o->rtol)) return fail(MG_EINVAL, "rtol must be > 0");
   if (o->max_iter < 1) return fail(MG_EINVAL, "max_iter must be >= 1");
+  if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F)
+    return fail(MG_EINVAL, "cycle must be MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F");
   return MG_OK;
 }
 

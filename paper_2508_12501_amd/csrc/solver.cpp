@@ -45,16 +45,19 @@ static void sweep(Hierarchy& H, int l, const T* x, const T* b, T* xo, double ome
   P.stream = s;
 }
 
+// One cycle of shape `kind` on level l (MG_CYCLE_V/W/F): the coarse-grid correction is one
+// cycle of the same shape from zero (V), two (W, the second from the first's result), or an
+// F-cycle followed by a V-cycle (F).  Returns the buffer holding the result.
 template <typename T>
-T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const int* done,
-          hipStream_t s) {
+static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, int kind,
+                  const int* done, hipStream_t s) {
   Level& L = *H.lv[l];
   LevelVecs<T>& V = vecs<T>(L);
   if (l == 0) {
     k::coarse<T>(H, b, V.x, done, s);
     return V.x;
   }
-  if (!x_init && l <= coarse_top<T>(H)) {
+  if (!x_init && kind == MG_CYCLE_V && l <= coarse_top<T>(H)) {
     k::coarse_cycle<T>(H, l, b, V.x, o.omega, o.nu1, o.nu2, done, s);
     return V.x;
   }
@@ -83,7 +86,17 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
   Level& C = *H.lv[l - 1];
   k::residual<T>(L, cur, b, V.r, done, s);
   k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
-  T* ec = vcycle<T>(H, l - 1, vecs<T>(C).b, nullptr, o, done, s);
+  const T* bc = vecs<T>(C).b;
+  T* ec;
+  if (kind == MG_CYCLE_W) {
+    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_W, done, s);
+    ec = mgcycle<T>(H, l - 1, bc, ec, o, MG_CYCLE_W, done, s);
+  } else if (kind == MG_CYCLE_F) {
+    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_F, done, s);
+    ec = mgcycle<T>(H, l - 1, bc, ec, o, MG_CYCLE_V, done, s);
+  } else {
+    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_V, done, s);
+  }
   int post = o.nu2;
   if (post >= 1 && L.n <= kLaunchBoundRows) {
     // the first post-smoothing sweep reads x + P e_c directly (one launch fewer on levels
@@ -100,6 +113,12 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
     std::swap(cur, oth);
   }
   return cur;
+}
+
+template <typename T>
+T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const int* done,
+          hipStream_t s) {
+  return mgcycle<T>(H, l, b, x_init, o, o.cycle, done, s);
 }
 
 template double* vcycle<double>(Hierarchy&, int, const double*, double*, const mg_opts&,
@@ -180,7 +199,7 @@ void enqueue_cycle(Hierarchy& H, const mg_opts& o, hipStream_t s) {
 }
 
 std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
-  return std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2, 0, o.omega);
+  return std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2, o.cycle, o.omega);
 }
 
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {

@@ -79,6 +79,15 @@ class Hierarchy:
             lv.w = lv.star1 * ke
         self._assemble()
 
+    def colors(self, l: int) -> np.ndarray:
+        """Greedy colour classes of level l's operator (cached; the sparsity does not change
+        with the vertex coefficient)."""
+        if not hasattr(self, "_colors"):
+            self._colors = {}
+        if l not in self._colors:
+            self._colors[l] = greedy_colors(self.levels[l].A)
+        return self._colors[l]
+
     @property
     def fine(self) -> Level:
         return self.levels[-1]
@@ -119,6 +128,55 @@ def jacobi(A, b, x, omega: float, nsweeps: int):
     return x
 
 
+def greedy_colors(A) -> np.ndarray:
+    """Colour classes for a multicolour Gauss-Seidel sweep: vertices in increasing id, each
+    taking the smallest colour not used by an already coloured neighbour, where neighbours are
+    the couplings of A with a nonzero value (reading Q7b)."""
+    G = sp.csr_matrix(A, copy=True)
+    G.setdiag(0.0)
+    G.eliminate_zeros()
+    n = G.shape[0]
+    color = np.full(n, -1, dtype=np.int64)
+    for i in range(n):
+        used = {int(color[j]) for j in G.indices[G.indptr[i]:G.indptr[i + 1]] if color[j] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        color[i] = c
+    return color
+
+
+def gauss_seidel(A, b, x, colors, nsweeps: int, backward: bool = False):
+    """Multicolour Gauss-Seidel: colour classes in increasing order (decreasing when
+    `backward`); every vertex of a class takes x_i <- x_i + (b_i - (A x)_i) / A_ii with the
+    latest values.  Vertices of one class are not coupled, so the order inside a class does not
+    matter (the paper smooths with Gauss-Seidel, Sec. 3.1 and 3.2)."""
+    A = sp.csr_matrix(A)
+    d = A.diagonal()
+    x = x.copy()
+    order = list(range(int(colors.max()) + 1))
+    if backward:
+        order.reverse()
+    for _ in range(nsweeps):
+        for c in order:
+            for i in np.flatnonzero(colors == c):
+                lo, hi = A.indptr[i], A.indptr[i + 1]
+                x[i] = x[i] + (b[i] - A.data[lo:hi] @ x[A.indices[lo:hi]]) / d[i]
+    return x
+
+
+def smooth(h: Hierarchy, l: int, b, x, nsweeps: int, omega: float, smoother: str, post: bool):
+    """The smoother of a cycle on level l: weighted Jacobi, or multicolour Gauss-Seidel with
+    forward sweeps before the coarse-grid correction and backward sweeps after it (so the
+    cycle stays symmetric)."""
+    A = h.levels[l].A
+    if smoother == "jacobi":
+        return jacobi(A, b, x, omega, nsweeps)
+    if smoother == "gs":
+        return gauss_seidel(A, b, x, h.colors(l), nsweeps, backward=post)
+    raise ValueError(smoother)
+
+
 def coarse_solve(h: Hierarchy, b: np.ndarray) -> np.ndarray:
     """Exact solve on the coarsest level: dense LU, or the minimum-norm least-squares
     solution (L^+ b) when L is singular."""
@@ -145,33 +203,35 @@ def vcycle(h: Hierarchy, b, x=None, l=None, nu1=2, nu2=2, omega=0.8):
     return x
 
 
-def mgcycle(h: Hierarchy, b, x=None, l=None, kind="V", nu1=2, nu2=2, omega=0.8):
+def mgcycle(h: Hierarchy, b, x=None, l=None, kind="V", nu1=2, nu2=2, omega=0.8,
+            smoother="jacobi"):
     """One multigrid cycle of shape `kind` for A_l x = b (the V-, W- and F-cycles named in
     Sec. 2, textbook recursion): pre-smooth, restrict the residual, coarse-grid correction,
     interpolate and correct, post-smooth.  The coarse-grid correction is one cycle of the same
     shape from zero for V, two for W (the second starting from the first's result), and an
-    F-cycle followed by a V-cycle for F.  On the coarsest level every shape is the exact solve."""
+    F-cycle followed by a V-cycle for F.  On the coarsest level every shape is the exact solve.
+    `smoother` is "jacobi" (weighted, omega) or "gs" (multicolour Gauss-Seidel, see smooth)."""
     if l is None:
         l = h.top
     if l == 0:
         return coarse_solve(h, b)
     A = h.levels[l].A
     x = np.zeros_like(b) if x is None else x.copy()
-    x = jacobi(A, b, x, omega, nu1)
+    x = smooth(h, l, b, x, nu1, omega, smoother, post=False)
     r = b - A @ x
     rc = h.restrict(l, r)
     if kind == "V":
-        ec = mgcycle(h, rc, None, l - 1, "V", nu1, nu2, omega)
+        ec = mgcycle(h, rc, None, l - 1, "V", nu1, nu2, omega, smoother)
     elif kind == "W":
-        ec = mgcycle(h, rc, None, l - 1, "W", nu1, nu2, omega)
-        ec = mgcycle(h, rc, ec, l - 1, "W", nu1, nu2, omega)
+        ec = mgcycle(h, rc, None, l - 1, "W", nu1, nu2, omega, smoother)
+        ec = mgcycle(h, rc, ec, l - 1, "W", nu1, nu2, omega, smoother)
     elif kind == "F":
-        ec = mgcycle(h, rc, None, l - 1, "F", nu1, nu2, omega)
-        ec = mgcycle(h, rc, ec, l - 1, "V", nu1, nu2, omega)
+        ec = mgcycle(h, rc, None, l - 1, "F", nu1, nu2, omega, smoother)
+        ec = mgcycle(h, rc, ec, l - 1, "V", nu1, nu2, omega, smoother)
     else:
         raise ValueError(kind)
     x = x + h.prolong(l, ec)
-    x = jacobi(A, b, x, omega, nu2)
+    x = smooth(h, l, b, x, nu2, omega, smoother, post=True)
     return x
 
 
@@ -207,7 +267,8 @@ def _project(h: Hierarchy, v):
     return v - v.mean() if h.bc == "natural" else v
 
 
-def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.8, cycle="V"):
+def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.8, cycle="V",
+             smoother="jacobi"):
     """Stand-alone multigrid: repeat cycles from x = 0 until ||b - A x|| <= rtol ||b||.
     Returns (x, cycles, history of relative residuals)."""
     A = h.fine.A
@@ -217,17 +278,18 @@ def mg_solve(h: Hierarchy, b, rtol=1e-10, max_cycles=200, nu1=2, nu2=2, omega=0.
     hist = [1.0]
     k = 0
     while hist[-1] > rtol and k < max_cycles and nb > 0:
-        x = mgcycle(h, b, x, None, cycle, nu1, nu2, omega)
+        x = mgcycle(h, b, x, None, cycle, nu1, nu2, omega, smoother)
         k += 1
         hist.append(np.linalg.norm(b - A @ x) / nb)
     return _project(h, x), k, hist
 
 
-def _precond(h, r, nu1, nu2, omega, cycle="V"):
-    return _project(h, mgcycle(h, r, None, None, cycle, nu1, nu2, omega))
+def _precond(h, r, nu1, nu2, omega, cycle="V", smoother="jacobi"):
+    return _project(h, mgcycle(h, r, None, None, cycle, nu1, nu2, omega, smoother))
 
 
-def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, cycle="V"):
+def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, cycle="V",
+           smoother="jacobi"):
     """Conjugate gradients preconditioned by one V-cycle (Sec. 3.1, CG-GMG), x0 = 0, stopped
     on the recursively updated residual.  Returns (x, iterations, history)."""
     A = h.fine.A
@@ -238,7 +300,7 @@ def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, c
     hist = [1.0 if nb > 0 else 0.0]
     if nb == 0:
         return x, 0, hist
-    z = _precond(h, r, nu1, nu2, omega, cycle)
+    z = _precond(h, r, nu1, nu2, omega, cycle, smoother)
     p = z.copy()
     rho = r @ z
     k = 0
@@ -251,7 +313,7 @@ def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, c
         hist.append(np.linalg.norm(r) / nb)
         if hist[-1] <= rtol:
             break
-        z = _precond(h, r, nu1, nu2, omega, cycle)
+        z = _precond(h, r, nu1, nu2, omega, cycle, smoother)
         rho_new = r @ z
         p = z + (rho_new / rho) * p
         rho = rho_new
@@ -259,7 +321,7 @@ def mg_pcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, c
 
 
 def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None,
-           cycle="V"):
+           cycle="V", smoother="jacobi"):
     """Flexible CG with one-vector truncation (FCG(1)): alpha = p^T r / p^T q,
     beta = -z^T q_prev / p_prev^T q_prev.  ``precond`` defaults to one V-cycle; passing
     another callable lets a test emulate a perturbed (e.g. lower precision) cycle."""
@@ -271,7 +333,7 @@ def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, p
     hist = [1.0 if nb > 0 else 0.0]
     if nb == 0:
         return x, 0, hist
-    M = precond or (lambda v: mgcycle(h, v, None, None, cycle, nu1, nu2, omega))
+    M = precond or (lambda v: mgcycle(h, v, None, None, cycle, nu1, nu2, omega, smoother))
     p_prev = q_prev = None
     k = 0
     while k < max_iter:
@@ -293,14 +355,14 @@ def mg_fcg(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, p
 
 
 def mg_ir(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, precond=None,
-          cycle="V"):
+          cycle="V", smoother="jacobi"):
     """Iterative refinement: x <- x + M(b - A x) with the true residual recomputed each
     step."""
     A = h.fine.A
     b = _project(h, b)
     nb = np.linalg.norm(b)
     x = np.zeros_like(b)
-    M = precond or (lambda v: mgcycle(h, v, None, None, cycle, nu1, nu2, omega))
+    M = precond or (lambda v: mgcycle(h, v, None, None, cycle, nu1, nu2, omega, smoother))
     r = b.copy()
     hist = [1.0 if nb > 0 else 0.0]
     k = 0

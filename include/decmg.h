@@ -158,6 +158,13 @@ mg_status mg_prolong(mg_hierarchy* h, int32_t level, int32_t dtype, const void* 
 #define MG_CYCLE_V 0
 #define MG_CYCLE_W 1
 #define MG_CYCLE_F 2
+/* Smoothers: weighted Jacobi (omega), or multicolour Gauss-Seidel (Sec. 3.1 and 3.2 smooth
+ * with Gauss-Seidel): the unknowns of each level are coloured greedily in increasing vertex id
+ * (smallest colour not used by a coupled, lower-numbered unknown); pre-smoothing sweeps the
+ * colour classes in increasing order, post-smoothing in decreasing order, so the cycle stays
+ * symmetric; omega is not used.  The batched solve supports Jacobi only. */
+#define MG_SMOOTH_JACOBI 0
+#define MG_SMOOTH_GS 1
 
 typedef struct {
   int32_t nu1, nu2;      /* pre/post Jacobi sweeps (2, 2) */
@@ -169,6 +176,8 @@ typedef struct {
   int32_t check_every;   /* iterations enqueued between host convergence checks (4) */
   int32_t use_graph;     /* replay the iteration as a hipGraph (1) */
   int32_t cycle;         /* MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F (V) */
+  int32_t smoother;      /* MG_SMOOTH_JACOBI or MG_SMOOTH_GS (Jacobi) */
+  int32_t reserved;
 } mg_opts;
 void mg_opts_default(mg_opts* o);
 

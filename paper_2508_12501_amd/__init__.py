@@ -29,6 +29,7 @@ MG_BC_DIRICHLET0, MG_BC_NATURAL = 0, 1
 MG_OUTER_CG, MG_OUTER_FCG, MG_OUTER_IR = 0, 1, 2
 MG_ORDER_STRIPES, MG_ORDER_MORTON = 0, 1
 MG_CYCLE_V, MG_CYCLE_W, MG_CYCLE_F = 0, 1, 2
+MG_SMOOTH_JACOBI, MG_SMOOTH_GS = 0, 1
 KERNEL_JACOBI, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
 
 
@@ -61,7 +62,8 @@ class mg_opts(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("cycle", ctypes.c_int32)]
+                ("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class mg_result(ctypes.Structure):

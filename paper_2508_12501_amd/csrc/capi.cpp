@@ -74,6 +74,8 @@ mg_status check_opts(const mg_opts* o) {
   if (o->max_iter < 1) return fail(MG_EINVAL, "max_iter must be >= 1");
   if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F)
     return fail(MG_EINVAL, "cycle must be MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F");
+  if (o->smoother != MG_SMOOTH_JACOBI && o->smoother != MG_SMOOTH_GS)
+    return fail(MG_EINVAL, "smoother must be MG_SMOOTH_JACOBI or MG_SMOOTH_GS");
   return MG_OK;
 }
 
@@ -96,7 +98,13 @@ void op_vcycle(decmg::Hierarchy& H, const mg_opts& o, int level, const void* b, 
   k::gather<T>(L.perm, L.n, xn, V.x, s);
   T* cur = vcycle<T>(H, level, V.b, V.x, o, nullptr, s);
   k::scatter<T>(L.perm, L.n, cur, xn, s);
-  for (int i = 0; i < o.nu1 + o.nu2; ++i) k::bnd_jacobi<T>(L.bnd_ids, nb, bn, xn, o.omega, s);
+  // the identity rows of non-unknowns under the same smoother: Jacobi moves x towards b by
+  // omega per sweep, a Gauss-Seidel sweep sets x = b
+  if (o.smoother == MG_SMOOTH_GS) {
+    if (o.nu1 + o.nu2 > 0) k::bnd_copy<T>(L.bnd_ids, nb, bn, xn, s);
+  } else {
+    for (int i = 0; i < o.nu1 + o.nu2; ++i) k::bnd_jacobi<T>(L.bnd_ids, nb, bn, xn, o.omega, s);
+  }
 }
 
 template <typename T>
@@ -511,6 +519,7 @@ mg_status mg_batch_create(mg_hierarchy* const* h, int32_t n, const mg_opts* o,
   if (!h || n < 1) return fail(MG_EINVAL, "need at least one instance");
   if (mg_status st = check_opts(o); st != MG_OK) return st;
   if (o->outer != MG_OUTER_FCG) return fail(MG_EINVAL, "batched solves run FCG(1): outer must be MG_OUTER_FCG");
+  if (o->smoother != MG_SMOOTH_JACOBI) return fail(MG_EINVAL, "batched solves smooth with Jacobi");
   if (tune)
     if (mg_status st = check_tuning(tune); st != MG_OK) return st;
   for (int32_t i = 0; i < n; ++i)

@@ -93,6 +93,20 @@ struct LevelVecs {
   T* t = nullptr;
 };
 
+// The rows of one colour class of the level's operator packed in SELL-64 (multicolour
+// Gauss-Seidel): packed row p is internal row rowid[p]; entries keep the operator's couplings
+// (absolute internal columns, the zero slot for non-unknowns) with their edge ids for weights.
+struct GsColor {
+  int32_t nrows = 0, nslices = 0, uw = -1;
+  std::vector<int32_t> edge_h;     // per entry: edge id, -1 for padding
+  int32_t* rowid = nullptr;
+  int32_t* sptr = nullptr;
+  int32_t* col = nullptr;
+  double* w64 = nullptr;
+  float* w32 = nullptr;
+  bool w_exact32 = false;
+};
+
 struct Level {
   Mesh mesh;                       // natural numbering (host)
   int32_t nv = 0, n = 0;
@@ -100,12 +114,14 @@ struct Level {
   std::vector<int32_t> inv_h;      // natural -> internal or -1
   std::vector<int32_t> bnd_h;      // natural ids that are not unknowns
   std::vector<int32_t> entry_edge; // per SELL entry: edge id or -1 (padding)
+  std::vector<int32_t> col_h;      // per SELL entry: internal column (host copy)
   std::vector<int32_t> sptr_h;
   int64_t nnz = 0;                 // stored couplings (SELL entries that are not padding)
   int32_t* perm = nullptr;         // device copies
   int32_t* bnd_ids = nullptr;
   double* star0 = nullptr;         // nv, natural numbering
   DevOperator op;
+  std::vector<GsColor> gs;         // colour classes, in colour order
   DevTransfer tr;                  // valid for l >= 1
   LevelVecs<double> v64;
   LevelVecs<float> v32;
@@ -206,6 +222,8 @@ template <typename T> void jacobi_two(const Level& L, const T* b, T* xo, double 
 template <typename T> void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done, hipStream_t s);
 template <typename T> void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done, hipStream_t s);
+// x_i <- x_i + (b_i - (A x)_i) / A_ii for the rows of colour class c, in place
+template <typename T> void gs_color(const Level& L, int c, T* x, const T* b, const int* done, hipStream_t s);
 // xo = one weighted-Jacobi sweep of (x + M(f)^T ec), the interpolation fused into the sweep
 template <typename T> void prolong_sweep(const Level& Lf, const Level& Lc, const T* ec, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);

@@ -226,6 +226,76 @@ bool delta16(const Level& L, const std::vector<int32_t>& col, std::vector<int16_
 }
 
 // Edge weights w_e = star1_e * (k_lo + k_hi) / 2 for the SELL entries (k = 1 when empty),
+// Colour classes of the level's operator for multicolour Gauss-Seidel: unknowns in increasing
+// natural vertex id, each taking the smallest colour not used by an already coloured coupled
+// unknown (couplings with nonzero star1, as stored in the operator); then each class packed in
+// SELL-64 in internal order.
+void build_gs_colors(Level& L) {
+  const Mesh& m = L.mesh;
+  const int32_t n = L.n;
+  const int64_t nslices = L.op.nslices;
+  // row entries of the operator: (column, edge) per internal row, padding excluded
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> rows(n);
+  for (int64_t s = 0; s < nslices; ++s)
+    for (int32_t k = L.sptr_h[s]; k < L.sptr_h[s + 1]; ++k)
+      for (int l = 0; l < kSlice; ++l) {
+        const int64_t r = s * kSlice + l;
+        if (r >= n) continue;
+        const size_t idx = size_t(k) * kSlice + l;
+        const int32_t e = L.entry_edge[idx];
+        if (e >= 0) rows[r].emplace_back(L.col_h[idx], e);
+      }
+  std::vector<int32_t> color(n, -1);
+  int32_t ncolors = 0;
+  std::vector<char> used;
+  for (int32_t v = 0; v < int32_t(m.nv); ++v) {
+    const int32_t r = L.inv_h[v];
+    if (r < 0) continue;
+    used.assign(rows[r].size() + 1, 0);
+    for (const auto& ce : rows[r]) {
+      const int32_t c = ce.first < n ? color[ce.first] : -1;
+      if (c >= 0 && c < int32_t(used.size())) used[c] = 1;
+    }
+    int32_t c = 0;
+    while (used[c]) ++c;
+    color[r] = c;
+    ncolors = std::max(ncolors, c + 1);
+  }
+  L.gs.assign(ncolors, GsColor());
+  for (int32_t c = 0; c < ncolors; ++c) {
+    GsColor& G = L.gs[c];
+    std::vector<int32_t> ids;
+    for (int32_t r = 0; r < n; ++r)
+      if (color[r] == c) ids.push_back(r);
+    G.nrows = int32_t(ids.size());
+    G.nslices = (G.nrows + kSlice - 1) / kSlice;
+    std::vector<int32_t> sptr(G.nslices + 1, 0), col;
+    for (int32_t s = 0; s < G.nslices; ++s) {
+      int32_t width = 0;
+      for (int l = 0; l < kSlice && s * kSlice + l < G.nrows; ++l)
+        width = std::max<int32_t>(width, int32_t(rows[ids[s * kSlice + l]].size()));
+      sptr[s + 1] = sptr[s] + width;
+      const size_t base = col.size();
+      col.resize(base + size_t(width) * kSlice, n);
+      G.edge_h.resize(base + size_t(width) * kSlice, -1);
+      for (int l = 0; l < kSlice && s * kSlice + l < G.nrows; ++l) {
+        const auto& rr = rows[ids[s * kSlice + l]];
+        for (size_t k = 0; k < rr.size(); ++k) {
+          col[base + k * kSlice + l] = rr[k].first;
+          G.edge_h[base + k * kSlice + l] = rr[k].second;
+        }
+      }
+    }
+    G.uw = make_uniform(sptr, col, &G.edge_h, n, -1);
+    col.resize(col.size() + kSlice, n);   // padding column
+    G.edge_h.resize(G.edge_h.size() + kSlice, -1);
+    ids.push_back(n);
+    G.rowid = upload(ids);
+    G.sptr = upload(sptr);
+    G.col = upload(col);
+  }
+}
+
 // row sums in SELL order.
 void compute_weights(const Level& L, const std::vector<double>& kv, std::vector<double>& w64,
                      std::vector<float>& w32, std::vector<double>& d64, std::vector<float>& d32) {
@@ -466,6 +536,30 @@ void upload_weights(Hierarchy& H) {
     }
     check_hip(hipMemcpy(L.op.diag64, d64.data(), d64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
     check_hip(hipMemcpy(L.op.diag32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    // weights of the Gauss-Seidel colour classes: w = star1 k_e per entry, as for the operator
+    for (GsColor& G : L.gs) {
+      std::vector<double> g64(G.edge_h.size(), 0.0);
+      std::vector<float> g32(G.edge_h.size(), 0.0f);
+      G.w_exact32 = true;
+      for (size_t i = 0; i < G.edge_h.size(); ++i) {
+        const int32_t e = G.edge_h[i];
+        if (e < 0) continue;
+        const Mesh& m = L.mesh;
+        double w = m.star1[e];
+        if (!kv.empty()) w = m.star1[e] * (0.5 * (kv[m.edge[2 * e]] + kv[m.edge[2 * e + 1]]));
+        g64[i] = w;
+        g32[i] = static_cast<float>(w);
+        if (static_cast<double>(g32[i]) != w) G.w_exact32 = false;
+      }
+      if (!G.w64) {
+        G.w64 = zeros<double>(std::max<size_t>(g64.size(), 1));
+        G.w32 = zeros<float>(std::max<size_t>(g32.size(), 1));
+      }
+      if (!g64.empty()) {
+        check_hip(hipMemcpy(G.w64, g64.data(), g64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
+        check_hip(hipMemcpy(G.w32, g32.data(), g32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+      }
+    }
     if (l == 0 && L.n > 0) {
       std::vector<double> inv = coarse_inverse(L, w64, H.bc);
       if (!H.coarse_inv) H.coarse_inv = zeros<double>(int64_t(L.n) * L.n);
@@ -505,8 +599,10 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
     Level& L = *H->lv[l];
     std::vector<int32_t> col;
     build_operator_structure(L, col);
+    L.col_h = col;
     L.op.sptr = upload(L.sptr_h);
     L.op.col = upload(col);
+    build_gs_colors(L);
     std::vector<int16_t> col16;
     if (delta16(L, col, col16) && !col16.empty()) L.op.col16 = upload(col16);
     L.perm = upload(L.perm_h);
@@ -560,6 +656,9 @@ Hierarchy::~Hierarchy() {
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
                     (void*)L.v32.r, (void*)L.v32.t})
       free_dev(p);
+    for (GsColor& G : L.gs)
+      for (void* p : {(void*)G.rowid, (void*)G.sptr, (void*)G.col, (void*)G.w64, (void*)G.w32})
+        free_dev(p);
   }
   for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
                   (void*)sb, (void*)part, (void*)scal})

@@ -399,6 +399,30 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
   xo[row] = xi0 + omega * (bi - acc) / d;
 }
 
+// One colour class of a multicolour Gauss-Seidel sweep, in place: packed row p (SELL-64 over
+// the class) is internal row i = rowid[p], x_i <- x_i + (b_i - (A x)_i) / A_ii with
+// (A x)_i = sum_k w_k (x_i - x_j(k)) and A_ii = sum_k w_k.  Rows of one class are not coupled,
+// so reading the neighbours while the class is written is race-free.
+template <typename T, typename WT>
+__global__ __launch_bounds__(kBlock) void k_gs_color(const int32_t* __restrict__ sptr, int32_t uw,
+                                                     const int32_t* __restrict__ col,
+                                                     const WT* __restrict__ w,
+                                                     const int32_t* __restrict__ rowid,
+                                                     T* __restrict__ x, const T* __restrict__ b,
+                                                     int32_t nrows, int32_t n,
+                                                     const int* __restrict__ done) {
+  DECMG_DONE_LOAD(nrows)
+  const int p = xcd_block() * kBlock + threadIdx.x;
+  if (p >= nrows) return;
+  const int i = rowid[p];
+  const T xi = x[i];
+  const T bi = b[i];
+  T acc, d;
+  row_apply<T, false>(sptr, uw, col, w, x, p, n, xi, acc, d);
+  DECMG_DONE_CHECK()
+  x[i] = xi + (bi - acc) / d;
+}
+
 // x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ pa,
@@ -1197,6 +1221,22 @@ void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x
   });
 }
 template <typename T>
+void gs_color(const Level& L, int c, T* x, const T* b, const int* done, hipStream_t s) {
+  const GsColor& G = L.gs[c];
+  if (G.nrows == 0) return;
+  auto launch = [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    hipLaunchKernelGGL((k_gs_color<T, WT>), dim3(grid_for(G.nrows)), dim3(kBlock), 0, s, G.sptr,
+                       G.uw, G.col, w, G.rowid, x, b, G.nrows, L.n, done);
+  };
+  if constexpr (std::is_same<T, float>::value)
+    launch(static_cast<const float*>(G.w32));
+  else if (G.w_exact32)
+    launch(static_cast<const float*>(G.w32));
+  else
+    launch(static_cast<const double*>(G.w64));
+}
+template <typename T>
 void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s) {
   if (H.n0 == 0) return;
   hipLaunchKernelGGL((k_coarse<T>), dim3(1), dim3(256), 0, s, H.coarse_inv, b, x, H.n0, done);
@@ -1375,6 +1415,7 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
   template void prolong<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t);  \
   template void prolong_sweep<T>(const Level&, const Level&, const T*, const T*, const T*, T*,  \
                                  double, const int*, hipStream_t);                              \
+  template void gs_color<T>(const Level&, int, T*, const T*, const int*, hipStream_t);         \
   template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \
   template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
                                 hipStream_t);                                                  \

@@ -45,6 +45,28 @@ static void sweep(Hierarchy& H, int l, const T* x, const T* b, T* xo, double ome
   P.stream = s;
 }
 
+template <typename T>
+static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, int kind,
+                  const int* done, hipStream_t s);
+
+// The coarse-grid correction of level l for a cycle of shape `kind`: level l-1 solved by one
+// cycle of the same shape from zero (V), two (W), or an F-cycle then a V-cycle (F).
+template <typename T>
+static T* coarse_correction(Hierarchy& H, int l, const T* bc, const mg_opts& o, int kind,
+                            const int* done, hipStream_t s) {
+  T* ec;
+  if (kind == MG_CYCLE_W) {
+    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_W, done, s);
+    ec = mgcycle<T>(H, l - 1, bc, ec, o, MG_CYCLE_W, done, s);
+  } else if (kind == MG_CYCLE_F) {
+    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_F, done, s);
+    ec = mgcycle<T>(H, l - 1, bc, ec, o, MG_CYCLE_V, done, s);
+  } else {
+    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_V, done, s);
+  }
+  return ec;
+}
+
 // One cycle of shape `kind` on level l (MG_CYCLE_V/W/F): the coarse-grid correction is one
 // cycle of the same shape from zero (V), two (W, the second from the first's result), or an
 // F-cycle followed by a V-cycle (F).  Returns the buffer holding the result.
@@ -57,12 +79,31 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
     k::coarse<T>(H, b, V.x, done, s);
     return V.x;
   }
-  if (!x_init && kind == MG_CYCLE_V && l <= coarse_top<T>(H)) {
+  const bool gs = o.smoother == MG_SMOOTH_GS;
+  if (!x_init && kind == MG_CYCLE_V && !gs && l <= coarse_top<T>(H)) {
     k::coarse_cycle<T>(H, l, b, V.x, o.omega, o.nu1, o.nu2, done, s);
     return V.x;
   }
   T *cur, *oth;
   int pre = o.nu1;
+  if (gs) {
+    // multicolour Gauss-Seidel works in place: forward colour order before the coarse-grid
+    // correction, backward after it
+    cur = x_init ? x_init : V.x;
+    if (!x_init) k::fill<T>(cur, L.n, T(0), s);
+    const int nc = int(L.gs.size());
+    for (int it = 0; it < o.nu1; ++it)
+      for (int c = 0; c < nc; ++c) k::gs_color<T>(L, c, cur, b, done, s);
+    Level& C = *H.lv[l - 1];
+    k::residual<T>(L, cur, b, V.r, done, s);
+    k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+    const T* bc = vecs<T>(C).b;
+    T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
+    k::prolong<T>(L, C, ec, cur, done, s);
+    for (int it = 0; it < o.nu2; ++it)
+      for (int c = nc - 1; c >= 0; --c) k::gs_color<T>(L, c, cur, b, done, s);
+    return cur;
+  }
   if (!x_init) {
     cur = V.x;
     oth = V.t;
@@ -87,16 +128,7 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
   k::residual<T>(L, cur, b, V.r, done, s);
   k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
   const T* bc = vecs<T>(C).b;
-  T* ec;
-  if (kind == MG_CYCLE_W) {
-    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_W, done, s);
-    ec = mgcycle<T>(H, l - 1, bc, ec, o, MG_CYCLE_W, done, s);
-  } else if (kind == MG_CYCLE_F) {
-    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_F, done, s);
-    ec = mgcycle<T>(H, l - 1, bc, ec, o, MG_CYCLE_V, done, s);
-  } else {
-    ec = mgcycle<T>(H, l - 1, bc, nullptr, o, MG_CYCLE_V, done, s);
-  }
+  T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
   int post = o.nu2;
   if (post >= 1 && L.n <= kLaunchBoundRows) {
     // the first post-smoothing sweep reads x + P e_c directly (one launch fewer on levels
@@ -199,7 +231,8 @@ void enqueue_cycle(Hierarchy& H, const mg_opts& o, hipStream_t s) {
 }
 
 std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
-  return std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2, o.cycle, o.omega);
+  return std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2,
+                         o.cycle + 4 * o.smoother, o.omega);
 }
 
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
@@ -365,7 +398,7 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
 int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
            hipStream_t s) {
   Level& F = *H.lv.back();
-  if ((o.nu1 + o.nu2) % 2 != 0)
+  if (o.smoother == MG_SMOOTH_JACOBI && (o.nu1 + o.nu2) % 2 != 0)
     throw std::invalid_argument("mg_solve needs an even number of smoothing sweeps per cycle");
   init_scalars(H, o, s);
   setup_rhs(H, b_nat, s);

@@ -165,6 +165,28 @@ def gauss_seidel(A, b, x, colors, nsweeps: int, backward: bool = False):
     return x
 
 
+def cg_smooth(A, b, x, nsteps: int):
+    """`nsteps` steps of unpreconditioned conjugate gradients on A x = b from x (CG smoothing,
+    the smoother of the paper's V-cycle timings, Fig. time_per1vcycle).  Stops early on an
+    exactly zero residual or a non-positive curvature."""
+    x = x.copy()
+    r = b - A @ x
+    p = r.copy()
+    rr = r @ r
+    for _ in range(nsteps):
+        q = A @ p
+        pq = p @ q
+        if not (rr > 0.0 and pq > 0.0):
+            break
+        alpha = rr / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        rr_new = r @ r
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+    return x
+
+
 def smooth(h: Hierarchy, l: int, b, x, nsweeps: int, omega: float, smoother: str, post: bool):
     """The smoother of a cycle on level l: weighted Jacobi, or multicolour Gauss-Seidel with
     forward sweeps before the coarse-grid correction and backward sweeps after it (so the
@@ -174,6 +196,8 @@ def smooth(h: Hierarchy, l: int, b, x, nsweeps: int, omega: float, smoother: str
         return jacobi(A, b, x, omega, nsweeps)
     if smoother == "gs":
         return gauss_seidel(A, b, x, h.colors(l), nsweeps, backward=post)
+    if smoother == "cg":
+        return cg_smooth(A, b, x, nsweeps)
     raise ValueError(smoother)
 
 
@@ -210,7 +234,8 @@ def mgcycle(h: Hierarchy, b, x=None, l=None, kind="V", nu1=2, nu2=2, omega=0.8,
     interpolate and correct, post-smooth.  The coarse-grid correction is one cycle of the same
     shape from zero for V, two for W (the second starting from the first's result), and an
     F-cycle followed by a V-cycle for F.  On the coarsest level every shape is the exact solve.
-    `smoother` is "jacobi" (weighted, omega) or "gs" (multicolour Gauss-Seidel, see smooth)."""
+    `smoother` is "jacobi" (weighted, omega), "gs" (multicolour Gauss-Seidel, see smooth) or
+    "cg" (CG steps, which make the cycle a nonlinear map: use it inside FCG or IR)."""
     if l is None:
         l = h.top
     if l == 0:

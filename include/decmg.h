@@ -165,6 +165,11 @@ mg_status mg_prolong(mg_hierarchy* h, int32_t level, int32_t dtype, const void* 
  * symmetric; omega is not used.  The batched solve supports Jacobi only. */
 #define MG_SMOOTH_JACOBI 0
 #define MG_SMOOTH_GS 1
+/* CG smoothing (the smoother of the paper's V-cycle timings, Fig. time_per1vcycle): nu1 steps
+ * of unpreconditioned CG on the level's unknowns before the coarse-grid correction and nu2
+ * after it; a step with non-positive curvature leaves x unchanged.  The cycle is then a
+ * nonlinear map, so mg_pcg requires MG_OUTER_FCG or MG_OUTER_IR with it. */
+#define MG_SMOOTH_CG 2
 
 typedef struct {
   int32_t nu1, nu2;      /* pre/post Jacobi sweeps (2, 2) */
@@ -176,7 +181,7 @@ typedef struct {
   int32_t check_every;   /* iterations enqueued between host convergence checks (4) */
   int32_t use_graph;     /* replay the iteration as a hipGraph (1) */
   int32_t cycle;         /* MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F (V) */
-  int32_t smoother;      /* MG_SMOOTH_JACOBI or MG_SMOOTH_GS (Jacobi) */
+  int32_t smoother;      /* MG_SMOOTH_JACOBI, MG_SMOOTH_GS or MG_SMOOTH_CG (Jacobi) */
   int32_t reserved;
 } mg_opts;
 void mg_opts_default(mg_opts* o);

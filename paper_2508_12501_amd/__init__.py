@@ -29,7 +29,7 @@ MG_BC_DIRICHLET0, MG_BC_NATURAL = 0, 1
 MG_OUTER_CG, MG_OUTER_FCG, MG_OUTER_IR = 0, 1, 2
 MG_ORDER_STRIPES, MG_ORDER_MORTON = 0, 1
 MG_CYCLE_V, MG_CYCLE_W, MG_CYCLE_F = 0, 1, 2
-MG_SMOOTH_JACOBI, MG_SMOOTH_GS = 0, 1
+MG_SMOOTH_JACOBI, MG_SMOOTH_GS, MG_SMOOTH_CG = 0, 1, 2
 KERNEL_JACOBI, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
 
 

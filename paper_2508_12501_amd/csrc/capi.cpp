@@ -74,10 +74,20 @@ mg_status check_opts(const mg_opts* o) {
   if (o->max_iter < 1) return fail(MG_EINVAL, "max_iter must be >= 1");
   if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F)
     return fail(MG_EINVAL, "cycle must be MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F");
-  if (o->smoother != MG_SMOOTH_JACOBI && o->smoother != MG_SMOOTH_GS)
-    return fail(MG_EINVAL, "smoother must be MG_SMOOTH_JACOBI or MG_SMOOTH_GS");
+  if (o->smoother != MG_SMOOTH_JACOBI && o->smoother != MG_SMOOTH_GS &&
+      o->smoother != MG_SMOOTH_CG)
+    return fail(MG_EINVAL, "smoother must be MG_SMOOTH_JACOBI, MG_SMOOTH_GS or MG_SMOOTH_CG");
   return MG_OK;
 }
+
+// Options of a Krylov solve (mg_pcg and what runs it): CG needs a linear, symmetric cycle.
+mg_status check_krylov_opts(const mg_opts* o) {
+  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (o->smoother == MG_SMOOTH_CG && o->outer == MG_OUTER_CG)
+    return fail(MG_EINVAL, "CG smoothing makes the cycle nonlinear: use MG_OUTER_FCG or MG_OUTER_IR");
+  return MG_OK;
+}
+
 
 template <typename T>
 void op_vcycle(decmg::Hierarchy& H, const mg_opts& o, int level, const void* b, void* x,
@@ -99,8 +109,8 @@ void op_vcycle(decmg::Hierarchy& H, const mg_opts& o, int level, const void* b, 
   T* cur = vcycle<T>(H, level, V.b, V.x, o, nullptr, s);
   k::scatter<T>(L.perm, L.n, cur, xn, s);
   // the identity rows of non-unknowns under the same smoother: Jacobi moves x towards b by
-  // omega per sweep, a Gauss-Seidel sweep sets x = b
-  if (o.smoother == MG_SMOOTH_GS) {
+  // omega per sweep; Gauss-Seidel and CG smoothing set x = b
+  if (o.smoother != MG_SMOOTH_JACOBI) {
     if (o.nu1 + o.nu2 > 0) k::bnd_copy<T>(L.bnd_ids, nb, bn, xn, s);
   } else {
     for (int i = 0; i < o.nu1 + o.nu2; ++i) k::bnd_jacobi<T>(L.bnd_ids, nb, bn, xn, o.omega, s);
@@ -426,7 +436,7 @@ mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x
 mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x, mg_result* res,
                  void* stream) {
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
-  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (mg_status st = check_krylov_opts(o); st != MG_OK) return st;
   if (!b || !x) return fail(MG_EINVAL, "null vector");
   API_BEGIN
   const int st = decmg::run_pcg(*h->h, *o, b, x, res, S(stream));
@@ -439,7 +449,7 @@ mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine
                          const double* grad_u, double* grad_b, double* grad_k, mg_result* res,
                          void* stream) {
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
-  if (mg_status st = check_opts(o); st != MG_OK) return st;
+  if (mg_status st = check_krylov_opts(o); st != MG_OK) return st;
   if (!grad_u || !grad_b) return fail(MG_EINVAL, "null vector");
   if (grad_k && !u_fine) return fail(MG_EINVAL, "grad_k needs the forward solution u_fine");
   API_BEGIN
@@ -459,7 +469,7 @@ mg_status check_porous(const mg_hierarchy* h, const porous_params* p) {
   if (!(p->Ra > 0) || !(p->phi > 0) || !(p->dt > 0) || !std::isfinite(p->Ra) ||
       !std::isfinite(p->phi) || !std::isfinite(p->dt))
     return fail(MG_EINVAL, "Ra, phi and dt must be finite and positive");
-  return check_opts(&p->solve);
+  return check_krylov_opts(&p->solve);
 }
 decmg::PorousParams porous_of(const porous_params* p) {
   return decmg::PorousParams{p->Ra, p->phi, p->dt, p->solve};

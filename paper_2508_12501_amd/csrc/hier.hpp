@@ -91,6 +91,12 @@ struct LevelVecs {
   T* b = nullptr;
   T* r = nullptr;
   T* t = nullptr;
+  T* u = nullptr;   // second work vector of the CG smoother
+};
+
+// Scalars of the CG smoother on one level (device memory).
+struct CgsScalars {
+  double rr, pq, alpha, beta;
 };
 
 // The rows of one colour class of the level's operator packed in SELL-64 (multicolour
@@ -122,6 +128,7 @@ struct Level {
   double* star0 = nullptr;         // nv, natural numbering
   DevOperator op;
   std::vector<GsColor> gs;         // colour classes, in colour order
+  CgsScalars* cgs = nullptr;
   DevTransfer tr;                  // valid for l >= 1
   LevelVecs<double> v64;
   LevelVecs<float> v32;
@@ -222,6 +229,14 @@ template <typename T> void jacobi_two(const Level& L, const T* b, T* xo, double 
 template <typename T> void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 template <typename T> void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done, hipStream_t s);
 template <typename T> void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done, hipStream_t s);
+// CG smoother pieces: p = r and rr = r.r; q = A p and p.q; x += alpha p, r -= alpha q and r.r;
+// p = r + beta p.  Reductions go through `part` (one partial per workgroup) and cgs_fin.
+enum { CGS_INIT = 0, CGS_ALPHA = 1, CGS_BETA = 2 };
+template <typename T> void cgs_start(const Level& L, const T* r, T* p, double* part, const int* done, hipStream_t s);
+template <typename T> void cgs_spmv_dot(const Level& L, const T* p, T* q, double* part, const int* done, hipStream_t s);
+template <typename T> void cgs_update(const Level& L, const T* p, const T* q, T* x, T* r, double* part, const int* done, hipStream_t s);
+template <typename T> void cgs_pupd(const Level& L, const T* r, T* p, const int* done, hipStream_t s);
+void cgs_fin(const Level& L, int op, const double* part, const int* done, hipStream_t s);
 // x_i <- x_i + (b_i - (A x)_i) / A_ii for the rows of colour class c, in place
 template <typename T> void gs_color(const Level& L, int c, T* x, const T* b, const int* done, hipStream_t s);
 // xo = one weighted-Jacobi sweep of (x + M(f)^T ec), the interpolation fused into the sweep

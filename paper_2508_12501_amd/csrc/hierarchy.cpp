@@ -438,6 +438,7 @@ void alloc_vecs(LevelVecs<T>& V, int32_t n) {
   V.b = zeros<T>(n + 1);
   V.r = zeros<T>(n + 1);
   V.t = zeros<T>(n + 1);
+  V.u = zeros<T>(n + 1);
 }
 
 void free_dev(void* p) {
@@ -610,6 +611,7 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
     L.star0 = upload(L.mesh.star0);
     alloc_vecs(L.v64, L.n);
     alloc_vecs(L.v32, L.n);
+    L.cgs = zeros<CgsScalars>(1);
     if (l > 0) build_transfer(L, *H->lv[l - 1]);
   }
   H->n0 = H->lv[0]->n;
@@ -654,7 +656,8 @@ Hierarchy::~Hierarchy() {
                     (void*)L.op.diag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
                     (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.v64.x, (void*)L.v64.b,
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
-                    (void*)L.v32.r, (void*)L.v32.t})
+                    (void*)L.v32.r, (void*)L.v32.t, (void*)L.v64.u, (void*)L.v32.u,
+                    (void*)L.cgs})
       free_dev(p);
     for (GsColor& G : L.gs)
       for (void* p : {(void*)G.rowid, (void*)G.sptr, (void*)G.col, (void*)G.w64, (void*)G.w32})

@@ -399,6 +399,111 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
   xo[row] = xi0 + omega * (bi - acc) / d;
 }
 
+// ------------------------------------------------------------------ CG smoother
+// p = r, partial r.r
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cgs_start(int32_t n, const T* __restrict__ r,
+                                                      T* __restrict__ p, double* __restrict__ part,
+                                                      const int* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (i < n) {
+    const T ri = r[i];
+    p[i] = ri;
+    v = static_cast<double>(ri) * static_cast<double>(ri);
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part[blk] = v;
+}
+
+// q = A p, partial p.q
+template <typename T, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_cgs_spmv_dot(const int32_t* __restrict__ sptr,
+                                                         int32_t uw, const void* __restrict__ col,
+                                                         const WT* __restrict__ w,
+                                                         const T* __restrict__ p,
+                                                         T* __restrict__ q,
+                                                         double* __restrict__ part, int32_t n,
+                                                         const int* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = xcd_block();
+  const int row = blk * kBlock + threadIdx.x;
+  double v = 0.0;
+  if (row < n) {
+    const T pi = p[row];
+    T acc, d;
+    row_apply<T, D16>(sptr, uw, col, w, p, row, n, pi, acc, d);
+    q[row] = acc;
+    v = static_cast<double>(pi) * static_cast<double>(acc);
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part[blk] = v;
+}
+
+// x += alpha p, r -= alpha q, partial r.r
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cgs_update(int32_t n, const CgsScalars* __restrict__ sc,
+                                                       const T* __restrict__ p,
+                                                       const T* __restrict__ q,
+                                                       T* __restrict__ x, T* __restrict__ r,
+                                                       double* __restrict__ part,
+                                                       const int* __restrict__ done) {
+  if (done && *done) return;
+  const int blk = xcd_block();
+  const int i = blk * kBlock + threadIdx.x;
+  const T a = static_cast<T>(sc->alpha);
+  double v = 0.0;
+  if (i < n) {
+    x[i] = x[i] + a * p[i];
+    const T ri = r[i] - a * q[i];
+    r[i] = ri;
+    v = static_cast<double>(ri) * static_cast<double>(ri);
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part[blk] = v;
+}
+
+// p = r + beta p
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cgs_pupd(int32_t n, const CgsScalars* __restrict__ sc,
+                                                     const T* __restrict__ r, T* __restrict__ p,
+                                                     const int* __restrict__ done) {
+  if (done && *done) return;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i < n) p[i] = r[i] + static_cast<T>(sc->beta) * p[i];
+}
+
+constexpr int kCgsFinThreads = 256;
+
+// Sum of nb partials in a fixed order, then the CG smoother's scalar update.  A step whose
+// curvature p.q or residual r.r is not positive gets alpha = 0 and leaves x and r unchanged.
+__global__ __launch_bounds__(kCgsFinThreads) void k_cgs_fin(int op, int32_t nb,
+                                                         const double* __restrict__ part,
+                                                         CgsScalars* __restrict__ sc,
+                                                         const int* __restrict__ done) {
+  if (done && *done) return;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < nb; i += kCgsFinThreads) a += part[i];
+  __shared__ double sa[kCgsFinThreads / 64];
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) sa[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  a = 0.0;
+  for (int i = 0; i < kCgsFinThreads / 64; ++i) a += sa[i];
+  if (op == k::CGS_INIT) {
+    sc->rr = a;
+  } else if (op == k::CGS_ALPHA) {
+    sc->pq = a;
+    sc->alpha = (sc->rr > 0.0 && a > 0.0 && isfinite(a)) ? sc->rr / a : 0.0;
+  } else {
+    sc->beta = sc->rr > 0.0 ? a / sc->rr : 0.0;
+    sc->rr = a;
+  }
+}
+
 // One colour class of a multicolour Gauss-Seidel sweep, in place: packed row p (SELL-64 over
 // the class) is internal row i = rowid[p], x_i <- x_i + (b_i - (A x)_i) / A_ii with
 // (A x)_i = sum_k w_k (x_i - x_j(k)) and A_ii = sum_k w_k.  Rows of one class are not coupled,
@@ -1221,6 +1326,44 @@ void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x
   });
 }
 template <typename T>
+void cgs_start(const Level& L, const T* r, T* p, double* part, const int* done, hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_cgs_start<T>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, r, p, part,
+                     done);
+}
+template <typename T>
+void cgs_spmv_dot(const Level& L, const T* p, T* q, double* part, const int* done, hipStream_t s) {
+  if (L.n == 0) return;
+  with_weights<T>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipLaunchKernelGGL((k_cgs_spmv_dot<T, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, p, q, part,
+                         L.n, done);
+    else
+      hipLaunchKernelGGL((k_cgs_spmv_dot<T, false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, p, q, part,
+                         L.n, done);
+  });
+}
+template <typename T>
+void cgs_update(const Level& L, const T* p, const T* q, T* x, T* r, double* part, const int* done,
+                hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_cgs_update<T>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.cgs, p, q,
+                     x, r, part, done);
+}
+template <typename T>
+void cgs_pupd(const Level& L, const T* r, T* p, const int* done, hipStream_t s) {
+  if (L.n == 0) return;
+  hipLaunchKernelGGL((k_cgs_pupd<T>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.cgs, r, p,
+                     done);
+}
+void cgs_fin(const Level& L, int op, const double* part, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_cgs_fin, dim3(1), dim3(kCgsFinThreads), 0, s, op, int32_t(grid_for(L.n)),
+                     part, L.cgs, done);
+}
+template <typename T>
 void gs_color(const Level& L, int c, T* x, const T* b, const int* done, hipStream_t s) {
   const GsColor& G = L.gs[c];
   if (G.nrows == 0) return;
@@ -1416,6 +1559,11 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
   template void prolong_sweep<T>(const Level&, const Level&, const T*, const T*, const T*, T*,  \
                                  double, const int*, hipStream_t);                              \
   template void gs_color<T>(const Level&, int, T*, const T*, const int*, hipStream_t);         \
+  template void cgs_start<T>(const Level&, const T*, T*, double*, const int*, hipStream_t);    \
+  template void cgs_spmv_dot<T>(const Level&, const T*, T*, double*, const int*, hipStream_t); \
+  template void cgs_update<T>(const Level&, const T*, const T*, T*, T*, double*, const int*,   \
+                              hipStream_t);                                                     \
+  template void cgs_pupd<T>(const Level&, const T*, T*, const int*, hipStream_t);             \
   template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \
   template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
                                 hipStream_t);                                                  \

@@ -67,6 +67,47 @@ static T* coarse_correction(Hierarchy& H, int l, const T* bc, const mg_opts& o, 
   return ec;
 }
 
+// `steps` steps of the CG smoother on level l, in place on x (r, p, q in the level's r, t, u).
+template <typename T>
+static void cg_smooth(Hierarchy& H, int l, T* x, const T* b, int steps, const int* done,
+                      hipStream_t s) {
+  if (steps <= 0) return;
+  Level& L = *H.lv[l];
+  LevelVecs<T>& V = vecs<T>(L);
+  k::residual<T>(L, x, b, V.r, done, s);
+  k::cgs_start<T>(L, V.r, V.t, H.part, done, s);
+  k::cgs_fin(L, k::CGS_INIT, H.part, done, s);
+  for (int it = 0; it < steps; ++it) {
+    k::cgs_spmv_dot<T>(L, V.t, V.u, H.part, done, s);
+    k::cgs_fin(L, k::CGS_ALPHA, H.part, done, s);
+    k::cgs_update<T>(L, V.t, V.u, x, V.r, H.part, done, s);
+    k::cgs_fin(L, k::CGS_BETA, H.part, done, s);
+    k::cgs_pupd<T>(L, V.r, V.t, done, s);
+  }
+}
+
+// A cycle with CG smoothing: in place on the level's x (or on x_init).
+template <typename T>
+static T* cg_cycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, int kind,
+                   const int* done, hipStream_t s) {
+  Level& L = *H.lv[l];
+  LevelVecs<T>& V = vecs<T>(L);
+  if (l == 0) {
+    k::coarse<T>(H, b, V.x, done, s);
+    return V.x;
+  }
+  T* cur = x_init ? x_init : V.x;
+  if (!x_init) k::fill<T>(cur, L.n, T(0), s);
+  cg_smooth<T>(H, l, cur, b, o.nu1, done, s);
+  Level& C = *H.lv[l - 1];
+  k::residual<T>(L, cur, b, V.r, done, s);
+  k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+  T* ec = coarse_correction<T>(H, l, vecs<T>(C).b, o, kind, done, s);
+  k::prolong<T>(L, C, ec, cur, done, s);
+  cg_smooth<T>(H, l, cur, b, o.nu2, done, s);
+  return cur;
+}
+
 // One cycle of shape `kind` on level l (MG_CYCLE_V/W/F): the coarse-grid correction is one
 // cycle of the same shape from zero (V), two (W, the second from the first's result), or an
 // F-cycle followed by a V-cycle (F).  Returns the buffer holding the result.
@@ -79,6 +120,7 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
     k::coarse<T>(H, b, V.x, done, s);
     return V.x;
   }
+  if (o.smoother == MG_SMOOTH_CG) return cg_cycle<T>(H, l, b, x_init, o, kind, done, s);
   const bool gs = o.smoother == MG_SMOOTH_GS;
   if (!x_init && kind == MG_CYCLE_V && !gs && l <= coarse_top<T>(H)) {
     k::coarse_cycle<T>(H, l, b, V.x, o.omega, o.nu1, o.nu2, done, s);

@@ -304,6 +304,24 @@ def main():
     print(f"[bench] fp64 PCG: {res_d.iterations} it, residual {res_d.rel_residual:.3e}, "
           f"median {1e3 * np.median(times_d):.3f} ms", file=sys.stderr, flush=True)
 
+    # the other cycle shapes with the same mixed-precision FCG (C3, timed like the headline)
+    variants = {}
+    for vname, cyc, smo in (("mixed_W_cycle", mg.MG_CYCLE_W, mg.MG_SMOOTH_JACOBI),
+                            ("mixed_F_cycle", mg.MG_CYCLE_F, mg.MG_SMOOTH_JACOBI),
+                            ("mixed_V_gauss_seidel", mg.MG_CYCLE_V, mg.MG_SMOOTH_GS),
+                            ("mixed_W_gauss_seidel", mg.MG_CYCLE_W, mg.MG_SMOOTH_GS),
+                            ("mixed_V_cg_smoothing_3", mg.MG_CYCLE_V, mg.MG_SMOOTH_CG)):
+        ov = mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32, rtol=rtol, cycle=cyc,
+                                smoother=smo)
+        if smo == mg.MG_SMOOTH_CG:
+            ov.nu1 = ov.nu2 = 3
+        tv, totv, rv = timed(ov, max(3, a.steps // 2), 1)
+        variants[vname] = {"iterations": rv.iterations, "rel_residual": rv.rel_residual,
+                           "ms_median": 1e3 * float(np.median(tv)),
+                           "value": unknowns / (totv / len(tv))}
+        print(f"[bench] {vname}: {rv.iterations} it, median {1e3 * np.median(tv):.3f} ms",
+              file=sys.stderr, flush=True)
+
     ms_step = 1e3 * total_m / a.steps
     value = unknowns / (total_m / a.steps)
     value_fp64 = unknowns / (total_d / n64)
@@ -360,6 +378,7 @@ def main():
         "fp64": {"iterations": res_d.iterations, "rel_residual": res_d.rel_residual,
                  "ms_median": 1e3 * float(np.median(times_d)), "value": value_fp64},
         "speedup_mixed_vs_fp64": value / value_fp64,
+        "variants": variants,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_rows<float, 2, %s, float> (FP32 weighted-Jacobi sweep, finest level)"

@@ -141,6 +141,60 @@ def subdivide(xyz, tri, edges, tri_edges, project: bool = False):
     return fxyz, ftri, Mt
 
 
+def subdivide_cubic(xyz, tri, edges, tri_edges, project: bool = False):
+    """Cubic subdivision (Sec. 2.2.1, the 1-to-9 scheme of the paper's benchmarks): every edge
+    gets two points at 1/3 and 2/3 of its length and every triangle its centroid; each triangle
+    splits into 9 similar ones with the parent's orientation.  Numbering: coarse vertices keep
+    their ids, edge e (oriented lo -> hi) adds V + 2e (the point next to lo) and V + 2e + 1
+    (next to hi), triangle t adds V + 2E + t.  Returns the fine mesh and M(f)^T with the
+    barycentric coordinates of each fine vertex: 1 at a kept vertex, (2/3, 1/3) on an edge,
+    (1/3, 1/3, 1/3) at a centroid.  With ``project`` the new points are pushed radially onto the
+    unit sphere (the barycentric coordinates stay those of the flat construction)."""
+    nv, ne, nt = len(xyz), len(edges), len(tri)
+    lo, hi = xyz[edges[:, 0]], xyz[edges[:, 1]]
+    p1 = (2.0 * lo + hi) / 3.0
+    p2 = (lo + 2.0 * hi) / 3.0
+    cen = (xyz[tri[:, 0]] + xyz[tri[:, 1]] + xyz[tri[:, 2]]) / 3.0
+    pts = np.empty((2 * ne, 3))
+    pts[0::2] = p1
+    pts[1::2] = p2
+    new = np.vstack([pts, cen])
+    if project:
+        r = np.sqrt(new[:, 0] * new[:, 0] + new[:, 1] * new[:, 1] + new[:, 2] * new[:, 2])
+        new = new / r[:, None]
+    fxyz = np.vstack([xyz, new])
+
+    def side(k, a_ids):
+        """The two points of triangle side k ordered from the side's first vertex (a_ids)."""
+        e = tri_edges[:, k]
+        near_lo, near_hi = nv + 2 * e, nv + 2 * e + 1
+        first_is_lo = edges[e, 0] == a_ids
+        return np.where(first_is_lo, near_lo, near_hi), np.where(first_is_lo, near_hi, near_lo)
+
+    a, b, c = tri[:, 0], tri[:, 1], tri[:, 2]
+    ab1, ab2 = side(0, a)
+    bc1, bc2 = side(1, b)
+    ca1, ca2 = side(2, c)
+    m = nv + 2 * ne + np.arange(nt)
+    kids = [(a, ab1, ca2), (ab2, b, bc1), (ca1, bc2, c),
+            (ab1, ab2, m), (bc1, bc2, m), (ca1, ca2, m),
+            (ab1, m, ca2), (ab2, bc1, m), (bc2, ca1, m)]
+    ftri = np.stack([np.stack(k, 1) for k in kids], axis=1).reshape(-1, 3)
+    e_ids = np.arange(ne)
+    rows = np.concatenate([np.arange(nv),
+                           nv + 2 * e_ids, nv + 2 * e_ids, nv + 2 * e_ids + 1, nv + 2 * e_ids + 1,
+                           m, m, m])
+    cols = np.concatenate([np.arange(nv),
+                           edges[:, 0], edges[:, 1], edges[:, 0], edges[:, 1],
+                           a, b, c])
+    vals = np.concatenate([np.ones(nv),
+                           np.full(ne, 2.0 / 3.0), np.full(ne, 1.0 / 3.0),
+                           np.full(ne, 1.0 / 3.0), np.full(ne, 2.0 / 3.0),
+                           np.full(nt, 1.0 / 3.0), np.full(nt, 1.0 / 3.0), np.full(nt, 1.0 / 3.0)])
+    Mt = sp.csr_matrix((vals, (rows, cols)), shape=(nv + 2 * ne + nt, nv))
+    return fxyz, ftri, Mt
+
+
 def paper_restriction(Mt: sp.spmatrix) -> sp.csr_matrix:
     """The restriction operator of Def. 6: the transpose of the row-normalisation of M(f).
     M(f) = Mt^T is V_c x V_f; as a column-vector operator it maps fine to coarse as

@@ -51,13 +51,19 @@ class Hierarchy:
     """Meshes X_0 (coarsest) .. X_l (finest) related by binary subdivision maps (Fig. 3),
     with L on each level and the transfer operators between neighbours."""
 
-    def __init__(self, xyz, tri, nsub: int, project: bool = False, bc: str = "dirichlet"):
+    def __init__(self, xyz, tri, nsub: int, project: bool = False, bc: str = "dirichlet",
+                 schemes: str | None = None):
+        """`schemes`: one letter per subdivision, "b" binary (1-to-4) or "c" cubic (1-to-9);
+        default all binary."""
         assert bc in ("dirichlet", "natural")
         self.bc = bc
+        self.schemes = schemes or "b" * nsub
+        assert len(self.schemes) == nsub and set(self.schemes) <= {"b", "c"}
         self.levels = [Level(xyz, tri)]
-        for _ in range(nsub):
+        for k in range(nsub):
             c = self.levels[-1]
-            fxyz, ftri, Mt = dec.subdivide(c.xyz, c.tri, c.edges, c.tri_edges, project)
+            sub = dec.subdivide_cubic if self.schemes[k] == "c" else dec.subdivide
+            fxyz, ftri, Mt = sub(c.xyz, c.tri, c.edges, c.tri_edges, project)
             f = Level(fxyz, ftri)
             f.Mt = Mt
             self.levels.append(f)

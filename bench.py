@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--order", choices=["stripes", "morton"], default="stripes")
     p.add_argument("--no-porous", action="store_true",
                    help="skip the porous-convection rollout and gradient timing")
+    p.add_argument("--no-cubic", action="store_true",
+                   help="skip the V-cycle timing on the 4-fold cubic subdivision")
     p.add_argument("--no-batch", action="store_true",
                    help="skip the 256-instance batched solve timing")
     p.add_argument("--profile-kernels", action="store_true",
@@ -195,6 +197,57 @@ def porous_bench(mg, W, torch, np, with_oracle):
     return out
 
 
+def cubic_bench(mg, W, torch, np, steps):
+    """V-cycles on the 105,625-vertex mesh (4 cubic subdivisions of the 32-triangle square) with
+    b = L r, r ~ U[0,1): time per cycle for CG smoothing (3 steps each side) and Jacobi(2,2),
+    and the FP32-preconditioned FCG solve to 1e-10 on the same hierarchy."""
+    dev = torch.device("cuda:0")
+    H = mg.Hierarchy("square", W.E1_CUBIC["nsub"], base_cells=W.E1_CUBIC["base_cells"],
+                     cubic_mask=W.E1_CUBIC["cubic_mask"])
+    top, nv = H.top, H.nv()
+    r = torch.tensor(W.uniform01(nv, W.SEED_E1), device=dev)
+    b = torch.zeros_like(r)
+    mg.dec_laplacian_apply(H.h, top, r, b)
+    x = torch.zeros_like(b)
+    y = torch.zeros_like(b)
+    out = {"workload": "4x4-cell square (32 triangles) after 4 cubic (1-to-9) subdivisions: "
+                       "325x325 = 105,625 vertices, zero Dirichlet, b = L r with r ~ U[0,1) "
+                       "seed %d" % W.SEED_E1, "vertices": nv, "levels": H.n_levels}
+    ncyc = max(10, 4 * steps)
+    for name, smo, nu in (("cg_smoothing_3", mg.MG_SMOOTH_CG, 3),
+                          ("jacobi_2_2", mg.MG_SMOOTH_JACOBI, 2)):
+        o = mg.mg_opts_default(smoother=smo)
+        o.nu1 = o.nu2 = nu
+        x.zero_()
+        for _ in range(3):
+            mg.mg_vcycle(H.h, o, top, b, x)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(ncyc):
+            mg.mg_vcycle(H.h, o, top, b, x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / ncyc
+        mg.dec_laplacian_apply(H.h, top, x, y)
+        res = float(torch.linalg.norm(b - y) / torch.linalg.norm(b))
+        out[name] = {"s_per_cycle": dt, "vertex_cycles_per_s": nv / dt, "cycles": ncyc,
+                     "rel_residual_after": res}
+    o = mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32, rtol=1e-10)
+    for _ in range(2):
+        mg.mg_pcg(H.h, o, b, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = mg.mg_pcg(H.h, o, b, x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    out["mixed_fcg"] = {"iterations": res.iterations, "rel_residual": res.rel_residual,
+                        "ms_per_solve": 1e3 * dt, "value": H.info[top]["n_unknowns"] / dt,
+                        "unit": "DOF/s"}
+    H.close()
+    return out
+
+
 def batch_bench(mg, W, torch, np, steps):
     """The 256-instance mix (icospheres of levels 4..7, squares of 33..513 vertices a side,
     seeded types), FP32-preconditioned FCG to 1e-10 for every instance, solved as one batch
@@ -322,6 +375,14 @@ def main():
         print(f"[bench] {vname}: {rv.iterations} it, median {1e3 * np.median(tv):.3f} ms",
               file=sys.stderr, flush=True)
 
+    cubic = None
+    if not a.no_cubic:
+        cubic = cubic_bench(mg, W, torch, np, max(3, a.steps // 2))
+        print(f"[bench] cubic 105,625-vertex V-cycle (CG 3): "
+              f"{1e6 * cubic['cg_smoothing_3']['s_per_cycle']:.1f} us/cycle; mixed FCG "
+              f"{cubic['mixed_fcg']['iterations']} it {cubic['mixed_fcg']['ms_per_solve']:.3f} ms",
+              file=sys.stderr, flush=True)
+
     ms_step = 1e3 * total_m / a.steps
     value = unknowns / (total_m / a.steps)
     value_fp64 = unknowns / (total_d / n64)
@@ -379,6 +440,7 @@ def main():
                  "ms_median": 1e3 * float(np.median(times_d)), "value": value_fp64},
         "speedup_mixed_vs_fp64": value / value_fp64,
         "variants": variants,
+        "cubic_vcycle": cubic,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_rows<float, 2, %s, float> (FP32 weighted-Jacobi sweep, finest level)"

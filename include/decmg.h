@@ -89,14 +89,19 @@ mg_status dec_mesh_icosahedron(dec_mesh** out);
 void dec_mesh_free(dec_mesh* m);
 
 /* ------------------------------------------------------------------ hierarchy
- * n_subdiv binary subdivisions of the base (Sec. 2.2.1); project_sphere pushes every new
- * midpoint radially onto the unit sphere.  All DEC operators are rebuilt on every level
- * (Sec. 3.1).  Device memory is allocated with hipMalloc and owned by the handle. */
+ * n_subdiv subdivisions of the base (Sec. 2.2.1), each binary (1-to-4: edge midpoints) or
+ * cubic (1-to-9: two points per edge at 1/3 and 2/3, one per triangle at the centroid; the
+ * interpolation holds the barycentric weights 2/3, 1/3 and 1/3, 1/3, 1/3); project_sphere
+ * pushes every new point radially onto the unit sphere.  All DEC operators are rebuilt on
+ * every level (Sec. 3.1).  Device memory is allocated with hipMalloc and owned by the handle.
+ * The fused single-workgroup bottom of the cycle covers binary levels only; batched solves
+ * take hierarchies without cubic levels. */
 typedef struct {
   int32_t n_subdiv;
   int32_t project_sphere;
   int32_t bc;      /* MG_BC_DIRICHLET0 (boundary vertices fixed at 0) or MG_BC_NATURAL */
   int32_t order;   /* internal order of the unknowns: MG_ORDER_STRIPES (0) or MG_ORDER_MORTON */
+  int32_t cubic_mask;  /* bit k set: the (k+1)-th subdivision (producing level k+1) is cubic */
 } mg_hier_opts;
 
 mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, void* stream,
@@ -110,19 +115,25 @@ typedef struct {
   int64_t n_unknowns;    /* interior vertices (Dirichlet) or all vertices (natural) */
   int64_t nnz_operator;  /* stored off-diagonal entries of the device operator */
   int32_t index_bytes;   /* bytes per stored column index of the device operator (2 or 4) */
-  int32_t reserved;
+  int32_t scheme;        /* how the level was made: 0 base, 1 binary, 2 cubic subdivision */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 
 /* Host copies of one level, natural numbering.  Any pointer may be NULL to skip it.
  * Sizes: xyz nv*3, tri nt*3, edges ne*2 (lo,hi), tri_edges nt*3, tri_sign nt*3 (+1 where
  * the triangle's boundary cycle runs lo->hi), star0 nv, star1 ne, boundary nv (1 = on a
- * boundary edge), parents nv*2 (level >= 1: coarse vertex ids (a,b) of each fine vertex,
- * a == b for kept vertices; row j of M(f)^T is 1/2 e_a + 1/2 e_b). */
+ * boundary edge), parents nv*2 (binary levels: coarse vertex ids (a,b) of each fine vertex,
+ * a == b for kept vertices; row j of M(f)^T is 1/2 e_a + 1/2 e_b; MG_EINVAL on a cubic level,
+ * see mg_hierarchy_export_interp). */
 mg_status mg_hierarchy_export(const mg_hierarchy* h, int32_t level, double* xyz, int32_t* tri,
                               int32_t* edges, int32_t* tri_edges, int8_t* tri_sign,
                               double* star0, double* star1, uint8_t* boundary,
                               int32_t* parents);
+/* The interpolation M(f)^T into level >= 1 of any scheme (Def. 4, Def. 5): row j as three
+ * (coarse vertex, weight) pairs, host arrays parents nv*3 and weights nv*3 (unused slots
+ * repeat the first parent with weight 0). */
+mg_status mg_hierarchy_export_interp(const mg_hierarchy* h, int32_t level, int32_t* parents,
+                                     double* weights);
 
 /* Darcy coefficient (Sec. 3.2, Eq. dec_darcy): k_vertex is a device array of nv_finest
  * positive values.  Every level takes the values at its own vertices (injection) and

@@ -47,14 +47,15 @@ class MGError(RuntimeError):
 
 class mg_hier_opts(ctypes.Structure):
     _fields_ = [("n_subdiv", ctypes.c_int32), ("project_sphere", ctypes.c_int32),
-                ("bc", ctypes.c_int32), ("order", ctypes.c_int32)]
+                ("bc", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("cubic_mask", ctypes.c_int32)]
 
 
 class mg_level_info(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("level", ctypes.c_int32),
                 ("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nt", ctypes.c_int64),
                 ("n_unknowns", ctypes.c_int64), ("nnz_operator", ctypes.c_int64),
-                ("index_bytes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("index_bytes", ctypes.c_int32), ("scheme", ctypes.c_int32)]
 
 
 class mg_opts(ctypes.Structure):
@@ -102,6 +103,7 @@ _PROTOS = {
     "mg_hierarchy_free": (None, [_vp]),
     "mg_hierarchy_info": (_i32, [_vp, _i32, ctypes.POINTER(mg_level_info)]),
     "mg_hierarchy_export": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mg_hierarchy_export_interp": (_i32, [_vp, _i32, _vp, _vp]),
     "mg_hierarchy_set_vertex_coeff": (_i32, [_vp, _vp, _vp]),
     "dec_star0_apply": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "dec_laplacian_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
@@ -224,8 +226,11 @@ def dec_mesh_free(m):
 
 # ----------------------------------------------------------------- hierarchy
 def mg_hierarchy_build(mesh, n_subdiv: int, project_sphere: bool = False,
-                       bc: int = MG_BC_DIRICHLET0, stream=None, order: int = MG_ORDER_STRIPES):
-    o = mg_hier_opts(int(n_subdiv), int(bool(project_sphere)), int(bc), int(order))
+                       bc: int = MG_BC_DIRICHLET0, stream=None, order: int = MG_ORDER_STRIPES,
+                       cubic_mask: int = 0):
+    """cubic_mask: bit k set makes the (k+1)-th subdivision 1-to-9 instead of 1-to-4."""
+    o = mg_hier_opts(int(n_subdiv), int(bool(project_sphere)), int(bc), int(order),
+                     int(cubic_mask))
     out = _vp()
     _check(lib().mg_hierarchy_build(mesh, ctypes.byref(o), _stream(stream), ctypes.byref(out)))
     return out
@@ -248,13 +253,22 @@ def mg_hierarchy_export(h, level: int) -> dict:
                edges=np.empty((ne, 2), np.int32), tri_edges=np.empty((nt, 3), np.int32),
                tri_sign=np.empty((nt, 3), np.int8), star0=np.empty(nv), star1=np.empty(ne),
                boundary=np.empty(nv, np.uint8))
-    parents = np.empty((nv, 2), np.int32) if level > 0 else None
+    parents = np.empty((nv, 2), np.int32) if level > 0 and i["scheme"] == 1 else None
     _check(lib().mg_hierarchy_export(
         h, int(level), *(out[k].ctypes.data for k in
                          ("xyz", "tri", "edges", "tri_edges", "tri_sign", "star0", "star1", "boundary")),
         parents.ctypes.data if parents is not None else None))
     out["parents"] = parents
     return out
+
+
+def mg_hierarchy_export_interp(h, level: int):
+    """(parents, weights), each (nv, 3): row j of M(f)^T for level >= 1 of either scheme."""
+    nv = mg_hierarchy_info(h, level)["nv"]
+    par = np.empty((nv, 3), np.int32)
+    w = np.empty((nv, 3))
+    _check(lib().mg_hierarchy_export_interp(h, int(level), par.ctypes.data, w.ctypes.data))
+    return par, w
 
 
 def mg_hierarchy_set_vertex_coeff(h, k_vertex, stream=None):
@@ -482,7 +496,7 @@ class Hierarchy:
     """Owns a mesh and a hierarchy handle; frees both when closed or collected."""
 
     def __init__(self, kind: str, n_subdiv: int, base_cells: int = 4, bc=None, xyz=None, tri=None,
-                 order: int = MG_ORDER_STRIPES):
+                 order: int = MG_ORDER_STRIPES, cubic_mask: int = 0):
         if kind == "square":
             self.mesh = dec_mesh_square_grid(base_cells)
             bc = MG_BC_DIRICHLET0 if bc is None else bc
@@ -498,7 +512,8 @@ class Hierarchy:
         else:
             raise ValueError(kind)
         self.bc = bc
-        self.h = mg_hierarchy_build(self.mesh, n_subdiv, project, bc, order=order)
+        self.h = mg_hierarchy_build(self.mesh, n_subdiv, project, bc, order=order,
+                                    cubic_mask=cubic_mask)
         self.n_levels = mg_hierarchy_info(self.h, 0)["n_levels"]
         self.top = self.n_levels - 1
         self.info = [mg_hierarchy_info(self.h, l) for l in range(self.n_levels)]

@@ -243,7 +243,10 @@ mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, voi
     return fail(MG_EINVAL, "bc must be MG_BC_DIRICHLET0 or MG_BC_NATURAL");
   if (opts->order != MG_ORDER_STRIPES && opts->order != MG_ORDER_MORTON)
     return fail(MG_EINVAL, "order must be MG_ORDER_STRIPES or MG_ORDER_MORTON");
-  const double growth = std::pow(4.0, opts->n_subdiv);
+  if (opts->cubic_mask < 0 || (opts->n_subdiv < 31 && (opts->cubic_mask >> opts->n_subdiv) != 0))
+    return fail(MG_EINVAL, "cubic_mask has bits beyond n_subdiv");
+  double growth = 1.0;
+  for (int32_t i = 0; i < opts->n_subdiv; ++i) growth *= ((opts->cubic_mask >> i) & 1) ? 9.0 : 4.0;
   if (double(base->m.nt) * growth > double(int64_t(1) << 30))
     return fail(MG_EINVAL, "finest level would exceed 2^30 triangles");
   auto h = std::make_unique<mg_hierarchy>();
@@ -267,7 +270,7 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->n_unknowns = L.n;
   out->nnz_operator = L.nnz;
   out->index_bytes = L.op.col16 ? 2 : 4;
-  out->reserved = 0;
+  out->scheme = L.mesh.scheme;
   return MG_OK;
 }
 
@@ -290,8 +293,19 @@ mg_status mg_hierarchy_export(const mg_hierarchy* h, int32_t level, double* xyz,
   cp(boundary, m.bnd);
   if (parents) {
     if (level == 0) return fail(MG_EINVAL, "level 0 has no parents");
+    if (m.scheme != 1) return fail(MG_EINVAL, "not a binary level: use mg_hierarchy_export_interp");
     cp(parents, m.parent);
   }
+  return MG_OK;
+}
+
+mg_status mg_hierarchy_export_interp(const mg_hierarchy* h, int32_t level, int32_t* parents,
+                                     double* weights) {
+  if (mg_status st = check_level(h, level); st != MG_OK) return st;
+  if (level == 0) return fail(MG_EINVAL, "level 0 has no parents");
+  const decmg::Mesh& m = h->h->lv[level]->mesh;
+  if (parents) std::memcpy(parents, m.parent3.data(), m.parent3.size() * sizeof(int32_t));
+  if (weights) std::memcpy(weights, m.pweight.data(), m.pweight.size() * sizeof(double));
   return MG_OK;
 }
 
@@ -530,6 +544,10 @@ mg_status mg_batch_create(mg_hierarchy* const* h, int32_t n, const mg_opts* o,
   if (mg_status st = check_opts(o); st != MG_OK) return st;
   if (o->outer != MG_OUTER_FCG) return fail(MG_EINVAL, "batched solves run FCG(1): outer must be MG_OUTER_FCG");
   if (o->smoother != MG_SMOOTH_JACOBI) return fail(MG_EINVAL, "batched solves smooth with Jacobi");
+  for (int32_t i = 0; i < n; ++i)
+    if (h[i] && h[i]->h)
+      for (const auto& L : h[i]->h->lv)
+        if (L->tr.weighted) return fail(MG_EINVAL, "batched solves take binary hierarchies only");
   if (tune)
     if (mg_status st = check_tuning(tune); st != MG_OK) return st;
   for (int32_t i = 0; i < n; ++i)

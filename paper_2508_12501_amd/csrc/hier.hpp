@@ -55,6 +55,18 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t r_uw = -1;          // uniform slice width of the restriction lists, or -1
   int32_t* r_sptr = nullptr;  // SELL over coarse rows of the fine midpoints (weight 1/2)
   int32_t* r_col = nullptr;
+  // Weighted transfers (cubic subdivision, any M(f)): interpolation x_f += sum_k w_k e_{p_k}
+  // over three parents per fine unknown; restriction r_c = sum over the coarse row's entries
+  // (fine unknown, weight) in SELL-64 (the kept vertex is an entry of weight 1).  The binary
+  // fields above are unused then.
+  bool weighted = false;
+  int32_t* p3 = nullptr;          // (n_f + 1) x 3 coarse parents, zero slot for non-unknowns
+  double* pw64 = nullptr;         // (n_f + 1) x 3 weights
+  float* pw32 = nullptr;
+  int32_t* rw_sptr = nullptr;
+  int32_t* rw_col = nullptr;      // fine internal ids (zero slot n_f for padding)
+  double* rw64 = nullptr;
+  float* rw32 = nullptr;
 };
 
 // Levels up to this many rows are launch-bound: there the interpolation is fused into the

@@ -383,7 +383,66 @@ std::vector<double> coarse_inverse(const Level& L, const std::vector<double>& w6
   return inv;
 }
 
+// Weighted transfers for a level made by any subdivision (used for cubic levels): three
+// (parent, weight) pairs per fine unknown, and per coarse unknown the list of fine unknowns
+// whose interpolation row names it, with that weight.
+void build_transfer_weighted(Level& F, const Level& C) {
+  F.tr.weighted = true;
+  std::vector<int32_t> p3(3 * size_t(F.n + 1), C.n);
+  std::vector<double> w64(3 * size_t(F.n + 1), 0.0);
+  std::vector<std::vector<std::pair<int32_t, double>>> rows(C.n);
+  for (int32_t k = 0; k < F.n; ++k) {
+    const int32_t v = F.perm_h[k];
+    for (int q = 0; q < 3; ++q) {
+      const int32_t a = F.mesh.parent3[3 * v + q];
+      const double w = F.mesh.pweight[3 * v + q];
+      const int32_t ca = C.inv_h[a];
+      p3[3 * k + q] = ca >= 0 ? ca : C.n;
+      w64[3 * k + q] = ca >= 0 ? w : 0.0;
+      if (ca >= 0 && w != 0.0) rows[ca].emplace_back(k, w);
+    }
+  }
+  std::vector<float> w32(w64.begin(), w64.end());
+  const int32_t nslices = (C.n + kSlice - 1) / kSlice;
+  std::vector<int32_t> sptr(nslices + 1, 0), col;
+  std::vector<double> rw;
+  for (int32_t s = 0; s < nslices; ++s) {
+    int32_t width = 0;
+    for (int l = 0; l < kSlice && s * kSlice + l < C.n; ++l) {
+      std::sort(rows[s * kSlice + l].begin(), rows[s * kSlice + l].end());
+      width = std::max<int32_t>(width, int32_t(rows[s * kSlice + l].size()));
+    }
+    sptr[s + 1] = sptr[s] + width;
+    const size_t base = col.size();
+    col.resize(base + size_t(width) * kSlice, F.n);
+    rw.resize(base + size_t(width) * kSlice, 0.0);
+    for (int l = 0; l < kSlice && s * kSlice + l < C.n; ++l) {
+      const auto& rr = rows[s * kSlice + l];
+      for (size_t k = 0; k < rr.size(); ++k) {
+        col[base + k * kSlice + l] = rr[k].first;
+        rw[base + k * kSlice + l] = rr[k].second;
+      }
+    }
+  }
+  col.resize(col.size() + kSlice, F.n);   // padding column
+  rw.resize(rw.size() + kSlice, 0.0);
+  std::vector<float> rw32(rw.begin(), rw.end());
+  F.tr.p3 = upload(p3);
+  F.tr.pw64 = upload(w64);
+  F.tr.pw32 = upload(w32);
+  F.tr.nslices = nslices;
+  F.tr.ncols = sptr[nslices];
+  F.tr.rw_sptr = upload(sptr);
+  F.tr.rw_col = upload(col);
+  F.tr.rw64 = upload(rw);
+  F.tr.rw32 = upload(rw32);
+}
+
 void build_transfer(Level& F, const Level& C) {
+  if (F.mesh.scheme != 1) {
+    build_transfer_weighted(F, C);
+    return;
+  }
   // interpolation: two coarse parents per fine unknown (zero slot for non-unknowns)
   std::vector<int32_t> pa(F.n + 1, C.n), pb(F.n + 1, C.n);
   for (int32_t k = 0; k < F.n; ++k) {
@@ -478,6 +537,7 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
     const size_t off2 = (vec2 + 7) / 8 * 8 + inv_bytes;
     if (off2 + ints2 * sizeof(int32_t) > size_t(H.lds_limit)) break;
     if (L.n > kCoarseFuseRows) break;
+    if (l >= 1 && L.tr.weighted) break;   // the fused cycle implements the binary transfers
     CoarseLevel<T>& c = hv[l];
     c.n = L.n;
     c.lds = int32_t(vec / sizeof(T));
@@ -578,7 +638,9 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
   std::vector<Mesh> meshes;
   meshes.push_back(base);
   for (int i = 0; i < o.n_subdiv; ++i) {
-    Mesh f = subdivide(meshes.back(), H->project);
+    const bool cubic = (uint32_t(o.cubic_mask) >> i) & 1u;
+    Mesh f = cubic ? subdivide_cubic(meshes.back(), H->project)
+                   : subdivide(meshes.back(), H->project);
     std::string err = f.build_topology();
     if (!err.empty()) throw std::invalid_argument(err);
     meshes.push_back(std::move(f));
@@ -658,6 +720,9 @@ Hierarchy::~Hierarchy() {
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
                     (void*)L.v32.r, (void*)L.v32.t, (void*)L.v64.u, (void*)L.v32.u,
                     (void*)L.cgs})
+      free_dev(p);
+    for (void* p : {(void*)L.tr.p3, (void*)L.tr.pw64, (void*)L.tr.pw32, (void*)L.tr.rw_sptr,
+                    (void*)L.tr.rw_col, (void*)L.tr.rw64, (void*)L.tr.rw32})
       free_dev(p);
     for (GsColor& G : L.gs)
       for (void* p : {(void*)G.rowid, (void*)G.sptr, (void*)G.col, (void*)G.w64, (void*)G.w32})

@@ -543,6 +543,68 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ 
   xf[row] = v;
 }
 
+// Weighted interpolation xf += M(f)^T ec for any subdivision scheme: three (parent, weight)
+// pairs per fine row, stored row-major (12 bytes of ids, 3 weights per row).  Cubic levels
+// (Def. 5) put 2/3, 1/3 on the two endpoints of an edge point and 1/3 on each corner of a
+// centroid; kept vertices carry weight 1 on themselves.  WT is the stored weight type: FP64
+// weights for FP64 cycles, FP32 weights for FP32 cycles.
+template <typename T, typename WT>
+__global__ __launch_bounds__(kBlock) void k_prolong3(const int32_t* __restrict__ p3,
+                                                     const WT* __restrict__ pw,
+                                                     const T* __restrict__ ec,
+                                                     T* __restrict__ xf, int32_t nf,
+                                                     const int* __restrict__ done) {
+  DECMG_DONE_LOAD(nf)
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= nf) return;
+  const size_t o = 3 * size_t(row);
+  const int a = p3[o], b = p3[o + 1], c = p3[o + 2];
+  const T wa = static_cast<T>(pw[o]), wb = static_cast<T>(pw[o + 1]),
+          wc = static_cast<T>(pw[o + 2]);
+  const T v = xf[row] + (wa * ec[a] + wb * ec[b] + wc * ec[c]);
+  DECMG_DONE_CHECK()
+  xf[row] = v;
+}
+
+// Weighted restriction rc = M(f) rf: row r of M(f) lists every fine unknown whose
+// interpolation reads coarse unknown r, with that weight, in a 64-row sliced layout (padding
+// points at the fine zero slot with weight 0).
+template <typename T, typename WT>
+__global__ __launch_bounds__(kBlock) void k_restrict_w(const int32_t* __restrict__ sptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const WT* __restrict__ w,
+                                                       const T* __restrict__ rf,
+                                                       T* __restrict__ rc, int32_t nc,
+                                                       const int* __restrict__ done) {
+  DECMG_DONE_LOAD(nc)
+  const int row = xcd_block() * kBlock + threadIdx.x;
+  if (row >= nc) return;
+  const int s = row >> 6, lane = row & 63;
+  const int beg = sptr[s], width = sptr[s + 1] - beg;
+  T acc = T(0);
+  int k = 0;
+  for (; k + 4 <= width; k += 4) {
+    int cj[4];
+    T wk[4], v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = (beg + k + q) * kSlice + lane;
+      cj[q] = col[idx];
+      wk[q] = static_cast<T>(w[idx]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = rf[cj[q]];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc += wk[q] * v[q];
+  }
+  for (; k < width; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    acc += static_cast<T>(w[idx]) * rf[col[idx]];
+  }
+  DECMG_DONE_CHECK()
+  rc[row] = acc;
+}
+
 // Exact coarsest solve x = A0^{-1} b in FP64 by one workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void k_coarse(const double* __restrict__ ainv,
@@ -1299,6 +1361,15 @@ template <typename T>
 void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* done,
                hipStream_t s) {
   if (Lc.n == 0) return;
+  if (Lf.tr.weighted) {
+    if constexpr (std::is_same_v<T, double>)
+      hipLaunchKernelGGL((k_restrict_w<T, double>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s,
+                         Lf.tr.rw_sptr, Lf.tr.rw_col, Lf.tr.rw64, rf, rc, Lc.n, done);
+    else
+      hipLaunchKernelGGL((k_restrict_w<T, float>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s,
+                         Lf.tr.rw_sptr, Lf.tr.rw_col, Lf.tr.rw32, rf, rc, Lc.n, done);
+    return;
+  }
   hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s, Lf.tr.r_self,
                      Lf.tr.r_sptr, Lf.tr.r_uw, Lf.tr.r_col, rf, rc, Lc.n, done);
 }
@@ -1306,6 +1377,15 @@ template <typename T>
 void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int* done,
              hipStream_t s) {
   if (Lf.n == 0) return;
+  if (Lf.tr.weighted) {
+    if constexpr (std::is_same_v<T, double>)
+      hipLaunchKernelGGL((k_prolong3<T, double>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s,
+                         Lf.tr.p3, Lf.tr.pw64, ec, xf, Lf.n, done);
+    else
+      hipLaunchKernelGGL((k_prolong3<T, float>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s,
+                         Lf.tr.p3, Lf.tr.pw32, ec, xf, Lf.n, done);
+    return;
+  }
   hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s, Lf.tr.pa, Lf.tr.pb,
                      ec, xf, Lf.n, done);
 }

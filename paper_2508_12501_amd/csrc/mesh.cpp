@@ -196,6 +196,17 @@ Mesh subdivide(const Mesh& c, bool project_sphere) {
     f.parent[2 * (c.nv + e)] = a;
     f.parent[2 * (c.nv + e) + 1] = b;
   }
+  f.scheme = 1;
+  f.parent3.resize(3 * f.nv);
+  f.pweight.assign(3 * f.nv, 0.0);
+  for (int64_t v = 0; v < f.nv; ++v) {
+    const int32_t a = f.parent[2 * v], b = f.parent[2 * v + 1];
+    f.parent3[3 * v] = a;
+    f.parent3[3 * v + 1] = b;
+    f.parent3[3 * v + 2] = a;
+    f.pweight[3 * v] = a == b ? 1.0 : 0.5;
+    f.pweight[3 * v + 1] = a == b ? 0.0 : 0.5;
+  }
   f.tri.resize(3 * f.nt);
   for (int64_t t = 0; t < c.nt; ++t) {
     const int32_t a = c.tri[3 * t], b = c.tri[3 * t + 1], cc = c.tri[3 * t + 2];
@@ -205,6 +216,80 @@ Mesh subdivide(const Mesh& c, bool project_sphere) {
     const int32_t ch[4][3] = {{a, ab, ca}, {ab, b, bc}, {ca, bc, cc}, {ab, bc, ca}};
     for (int q = 0; q < 4; ++q)
       for (int k = 0; k < 3; ++k) f.tri[3 * (4 * t + q) + k] = ch[q][k];
+  }
+  return f;
+}
+
+Mesh subdivide_cubic(const Mesh& c, bool project_sphere) {
+  Mesh f;
+  f.nv = c.nv + 2 * c.ne + c.nt;
+  f.nt = 9 * c.nt;
+  f.scheme = 2;
+  f.xyz.resize(3 * f.nv);
+  std::copy(c.xyz.begin(), c.xyz.end(), f.xyz.begin());
+  f.parent3.resize(3 * f.nv);
+  f.pweight.assign(3 * f.nv, 0.0);
+  for (int64_t v = 0; v < c.nv; ++v) {
+    for (int k = 0; k < 3; ++k) f.parent3[3 * v + k] = int32_t(v);
+    f.pweight[3 * v] = 1.0;
+  }
+  auto push = [&](double* p) {
+    if (project_sphere) {
+      const double r = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+      for (int k = 0; k < 3; ++k) p[k] = p[k] / r;
+    }
+  };
+  for (int64_t e = 0; e < c.ne; ++e) {
+    const int32_t a = c.edge[2 * e], b = c.edge[2 * e + 1];
+    double* p1 = &f.xyz[3 * (c.nv + 2 * e)];
+    double* p2 = &f.xyz[3 * (c.nv + 2 * e + 1)];
+    for (int k = 0; k < 3; ++k) {
+      p1[k] = (2.0 * c.xyz[3 * a + k] + c.xyz[3 * b + k]) / 3.0;
+      p2[k] = (c.xyz[3 * a + k] + 2.0 * c.xyz[3 * b + k]) / 3.0;
+    }
+    push(p1);
+    push(p2);
+    const int64_t v1 = c.nv + 2 * e, v2 = v1 + 1;
+    f.parent3[3 * v1] = a;
+    f.parent3[3 * v1 + 1] = b;
+    f.parent3[3 * v1 + 2] = a;
+    f.pweight[3 * v1] = 2.0 / 3.0;
+    f.pweight[3 * v1 + 1] = 1.0 / 3.0;
+    f.parent3[3 * v2] = a;
+    f.parent3[3 * v2 + 1] = b;
+    f.parent3[3 * v2 + 2] = a;
+    f.pweight[3 * v2] = 1.0 / 3.0;
+    f.pweight[3 * v2 + 1] = 2.0 / 3.0;
+  }
+  f.tri.resize(3 * f.nt);
+  for (int64_t t = 0; t < c.nt; ++t) {
+    const int32_t a = c.tri[3 * t], b = c.tri[3 * t + 1], cc = c.tri[3 * t + 2];
+    const int64_t m = c.nv + 2 * c.ne + t;
+    double* pm = &f.xyz[3 * m];
+    for (int k = 0; k < 3; ++k) pm[k] = (c.xyz[3 * a + k] + c.xyz[3 * b + k] + c.xyz[3 * cc + k]) / 3.0;
+    push(pm);
+    for (int k = 0; k < 3; ++k) {
+      f.parent3[3 * m + k] = c.tri[3 * t + k];
+      f.pweight[3 * m + k] = 1.0 / 3.0;
+    }
+    // the two points of side k, ordered from the side's first vertex
+    auto side = [&](int k, int32_t first, int32_t& x1, int32_t& x2) {
+      const int64_t e = c.tri_edge[3 * t + k];
+      const int32_t lo = int32_t(c.nv + 2 * e), hi = lo + 1;
+      const bool first_is_lo = c.edge[2 * e] == first;
+      x1 = first_is_lo ? lo : hi;
+      x2 = first_is_lo ? hi : lo;
+    };
+    int32_t ab1, ab2, bc1, bc2, ca1, ca2;
+    side(0, a, ab1, ab2);
+    side(1, b, bc1, bc2);
+    side(2, cc, ca1, ca2);
+    const int32_t mm = int32_t(m);
+    const int32_t ch[9][3] = {{a, ab1, ca2},   {ab2, b, bc1},   {ca1, bc2, cc},
+                              {ab1, ab2, mm},  {bc1, bc2, mm},  {ca1, ca2, mm},
+                              {ab1, mm, ca2},  {ab2, bc1, mm},  {bc2, ca1, mm}};
+    for (int q = 0; q < 9; ++q)
+      for (int k = 0; k < 3; ++k) f.tri[3 * (9 * t + q) + k] = ch[q][k];
   }
   return f;
 }

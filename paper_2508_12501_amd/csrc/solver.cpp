@@ -172,7 +172,7 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
   const T* bc = vecs<T>(C).b;
   T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
   int post = o.nu2;
-  if (post >= 1 && L.n <= kLaunchBoundRows) {
+  if (post >= 1 && L.n <= kLaunchBoundRows && !L.tr.weighted) {
     // the first post-smoothing sweep reads x + P e_c directly (one launch fewer on levels
     // whose kernels are launch-bound; on large levels the extra dependent gathers cost more
     // than the separate interpolation pass)

@@ -33,6 +33,9 @@ SEED_C5_W = 7
 C1 = dict(base_cells=4, nsub=4)
 C2 = dict(sphere_level=7)
 C3 = dict(base_cells=8, nsub=8)
+# the largest V-cycle sweep mesh: the 32-triangle square, 4 cubic subdivisions (325 x 325)
+E1_CUBIC = dict(base_cells=4, nsub=4, cubic_mask=0b1111)
+SEED_E1 = 8
 C5 = dict(base_cells=4, nsub=6, Ra=1000.0, phi=0.1, steps=200, ckpt=20, noise=1e-2,
           g_smooth_sweeps=20, g_smooth_omega=0.8)
 

@@ -115,7 +115,8 @@ typedef struct {
   int64_t n_unknowns;    /* interior vertices (Dirichlet) or all vertices (natural) */
   int64_t nnz_operator;  /* stored off-diagonal entries of the device operator */
   int32_t index_bytes;   /* bytes per stored column index of the device operator (2 or 4) */
-  int32_t scheme;        /* how the level was made: 0 base, 1 binary, 2 cubic subdivision */
+  int32_t scheme;        /* how the level was made: 0 base, 1 binary, 2 cubic subdivision,
+                            3 a given geometric map (mg_hierarchy_build_maps) */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 
@@ -129,6 +130,43 @@ mg_status mg_hierarchy_export(const mg_hierarchy* h, int32_t level, double* xyz,
                               int32_t* edges, int32_t* tri_edges, int8_t* tri_sign,
                               double* star0, double* star1, uint8_t* boundary,
                               int32_t* parents);
+/* ------------------------------------------------------------------ geometric maps
+ * A geometric map f: X -> Y between triangle meshes, encoded as its matrix M(f) (Def. 4) in
+ * compressed sparse column form: n_rows = vertices of Y, n_cols = vertices of X, and column j
+ * holds the global barycentric coordinates of f(x_j) in Y.  Host arrays owned by the caller;
+ * colptr has n_cols + 1 entries starting at 0, rowval and nzval colptr[n_cols] entries. */
+typedef struct {
+  int64_t n_rows;
+  int64_t n_cols;
+  const int64_t* colptr;
+  const int32_t* rowval;
+  const double* nzval;
+} mg_geomap;
+
+/* A hierarchy over given meshes related by given geometric maps (Sec. 2.2.1: interpolation by
+ * M(f)^T, restriction by M(f); the meshes need not be nested, and each level's operators are
+ * rediscretised on its own mesh, Sec. 3.1).  meshes[0] is the coarsest of n_levels >= 1;
+ * maps[l] (n_levels - 1 of them) is f: mesh l+1 -> mesh l.  Every column of a map must hold
+ * 1 to 3 entries on distinct rows that are the vertices of one simplex of the coarser mesh (a
+ * vertex, an edge or a triangle), with finite nonnegative weights summing to 1 within 1e-12;
+ * MG_EINVAL names the first column that does not.  opts->bc and opts->order apply as in
+ * mg_hierarchy_build; opts->n_subdiv, project_sphere and cubic_mask must be 0.  The meshes are
+ * copied; the caller keeps ownership of meshes and maps.  mg_hierarchy_set_vertex_coeff is
+ * accepted only when every map keeps the coarse vertex ids (column j is e_j for every coarse
+ * vertex j), as subdivisions do; batched solves refuse such hierarchies. */
+mg_status mg_hierarchy_build_maps(int32_t n_levels, const dec_mesh* const* meshes,
+                                  const mg_geomap* maps, const mg_hier_opts* opts, void* stream,
+                                  mg_hierarchy** out);
+
+/* Composition of geometric maps, M(g o f) = M(g) M(f) (Prop. 2), for f: X -> Y and g: Y -> Z
+ * (f->n_rows == g->n_cols).  Host computation.  Column j of the result sums, over the entries
+ * (k, a) of column j of f, a times column k of g; rows ascend and exact zeros are dropped.
+ * Call with colptr, rowval and nzval null to get the entry count in *nnz; then call again with
+ * colptr of f->n_cols + 1 entries and rowval / nzval of at least *nnz entries (*nnz is read as
+ * their capacity: MG_EINVAL if too small).  Maps are checked only for index ranges here. */
+mg_status mg_geomap_compose(const mg_geomap* g, const mg_geomap* f, int64_t* colptr,
+                            int32_t* rowval, double* nzval, int64_t* nnz);
+
 /* The interpolation M(f)^T into level >= 1 of any scheme (Def. 4, Def. 5): row j as three
  * (coarse vertex, weight) pairs, host arrays parents nv*3 and weights nv*3 (unused slots
  * repeat the first parent with weight 0). */
@@ -137,7 +175,8 @@ mg_status mg_hierarchy_export_interp(const mg_hierarchy* h, int32_t level, int32
 
 /* Darcy coefficient (Sec. 3.2, Eq. dec_darcy): k_vertex is a device array of nv_finest
  * positive values.  Every level takes the values at its own vertices (injection) and
- * uses edge weights star1_e * (k_lo + k_hi)/2.  Passing NULL restores k = 1. */
+ * uses edge weights star1_e * (k_lo + k_hi)/2.  Passing NULL restores k = 1.  MG_EINVAL on a
+ * hierarchy from mg_hierarchy_build_maps whose maps do not keep the coarse vertex ids. */
 mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex, void* stream);
 
 /* ------------------------------------------------------------------ operators (device)

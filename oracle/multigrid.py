@@ -69,6 +69,28 @@ class Hierarchy:
             self.levels.append(f)
         self._assemble()
 
+    @classmethod
+    def from_maps(cls, meshes, maps, bc: str = "dirichlet"):
+        """A hierarchy over given meshes (coarsest first) related by given geometric maps
+        (Sec. 2.2.1 with Def. 4): maps[l] is M(f) for f: mesh l+1 -> mesh l, a
+        (coarse x fine) matrix whose column j holds the global barycentric coordinates of
+        f(x_j).  Interpolation is M(f)^T and restriction M(f), as for subdivisions; the meshes
+        need not be nested, and every level is rediscretised on its own mesh (Sec. 3.1)."""
+        assert bc in ("dirichlet", "natural") and len(maps) == len(meshes) - 1
+        self = cls.__new__(cls)
+        self.bc = bc
+        self.schemes = None
+        self.levels = []
+        for k, (xyz, tri) in enumerate(meshes):
+            lv = Level(np.asarray(xyz, dtype=np.float64), np.asarray(tri))
+            if k > 0:
+                M = sp.csc_matrix(maps[k - 1])
+                assert M.shape == (self.levels[-1].nv, lv.nv)
+                lv.Mt = M.T.tocsr()
+            self.levels.append(lv)
+        self._assemble()
+        return self
+
     # -- operators
     def _assemble(self):
         for lv in self.levels:
@@ -403,6 +425,11 @@ def mg_ir(h: Hierarchy, b, rtol=1e-10, max_iter=200, nu1=2, nu2=2, omega=0.8, pr
         k += 1
         hist.append(np.linalg.norm(r) / nb)
     return _project(h, x), k, hist
+
+
+def compose(Mg, Mf) -> sp.csc_matrix:
+    """M(g o f) = M(g) M(f) for f: X -> Y and g: Y -> Z (Prop. 2): the matrix product."""
+    return sp.csc_matrix(Mg @ Mf)
 
 
 def rel_residual(h: Hierarchy, b, x) -> float:

@@ -75,6 +75,12 @@ class mg_result(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class mg_geomap(ctypes.Structure):
+    _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64),
+                ("colptr", ctypes.c_void_p), ("rowval", ctypes.c_void_p),
+                ("nzval", ctypes.c_void_p)]
+
+
 class mg_batch_tuning(ctypes.Structure):
     _fields_ = [("max_cols", ctypes.c_int32), ("pad_groups", ctypes.c_int32),
                 ("streams", ctypes.c_int32), ("reserved", ctypes.c_int32)]
@@ -100,6 +106,10 @@ _PROTOS = {
     "dec_mesh_icosahedron": (_i32, [ctypes.POINTER(_vp)]),
     "dec_mesh_free": (None, [_vp]),
     "mg_hierarchy_build": (_i32, [_vp, ctypes.POINTER(mg_hier_opts), _vp, ctypes.POINTER(_vp)]),
+    "mg_hierarchy_build_maps": (_i32, [_i32, ctypes.POINTER(_vp), ctypes.POINTER(mg_geomap),
+                                       ctypes.POINTER(mg_hier_opts), _vp, ctypes.POINTER(_vp)]),
+    "mg_geomap_compose": (_i32, [ctypes.POINTER(mg_geomap), ctypes.POINTER(mg_geomap), _vp, _vp,
+                                 _vp, ctypes.POINTER(_i64)]),
     "mg_hierarchy_free": (None, [_vp]),
     "mg_hierarchy_info": (_i32, [_vp, _i32, ctypes.POINTER(mg_level_info)]),
     "mg_hierarchy_export": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -234,6 +244,53 @@ def mg_hierarchy_build(mesh, n_subdiv: int, project_sphere: bool = False,
     out = _vp()
     _check(lib().mg_hierarchy_build(mesh, ctypes.byref(o), _stream(stream), ctypes.byref(out)))
     return out
+
+
+def _geomap(M):
+    """A geometric map as (mg_geomap, arrays kept alive): M is a scipy sparse matrix
+    (n_rows x n_cols, column j = barycentric coordinates of the image of vertex j) or a tuple
+    (colptr, rowval, nzval, (n_rows, n_cols))."""
+    if isinstance(M, tuple):
+        colptr, rowval, nzval, shape = M
+    else:
+        c = M.tocsc()
+        colptr, rowval, nzval, shape = c.indptr, c.indices, c.data, c.shape
+    keep = (np.ascontiguousarray(colptr, dtype=np.int64),
+            np.ascontiguousarray(rowval, dtype=np.int32),
+            np.ascontiguousarray(nzval, dtype=np.float64))
+    g = mg_geomap(int(shape[0]), int(shape[1]), keep[0].ctypes.data, keep[1].ctypes.data,
+                  keep[2].ctypes.data)
+    return g, keep
+
+
+def mg_hierarchy_build_maps(meshes, maps, bc: int = MG_BC_DIRICHLET0, stream=None,
+                            order: int = MG_ORDER_STRIPES):
+    """meshes: mesh handles, coarsest first; maps[l]: M(f) of f: mesh l+1 -> mesh l."""
+    if len(maps) != len(meshes) - 1:
+        raise ValueError("need one map per pair of neighbouring meshes")
+    gs = [_geomap(M) for M in maps]
+    arr = (mg_geomap * max(len(gs), 1))(*[g for g, _ in gs])
+    mp = (_vp * len(meshes))(*meshes)
+    o = mg_hier_opts(0, 0, int(bc), int(order), 0)
+    out = _vp()
+    _check(lib().mg_hierarchy_build_maps(len(meshes), mp, arr, ctypes.byref(o), _stream(stream),
+                                         ctypes.byref(out)))
+    return out
+
+
+def mg_geomap_compose(g, f):
+    """M(g) M(f) as (colptr, rowval, nzval, shape) from two maps given like _geomap's input."""
+    gg, kg = _geomap(g)
+    ff, kf = _geomap(f)
+    nnz = _i64(0)
+    _check(lib().mg_geomap_compose(ctypes.byref(gg), ctypes.byref(ff), None, None, None,
+                                   ctypes.byref(nnz)))
+    colptr = np.empty(ff.n_cols + 1, np.int64)
+    rowval = np.empty(max(nnz.value, 1), np.int32)
+    nzval = np.empty(max(nnz.value, 1))
+    _check(lib().mg_geomap_compose(ctypes.byref(gg), ctypes.byref(ff), colptr.ctypes.data,
+                                   rowval.ctypes.data, nzval.ctypes.data, ctypes.byref(nnz)))
+    return colptr, rowval[:nnz.value], nzval[:nnz.value], (gg.n_rows, ff.n_cols)
 
 
 def mg_hierarchy_free(h):
@@ -518,6 +575,20 @@ class Hierarchy:
         self.top = self.n_levels - 1
         self.info = [mg_hierarchy_info(self.h, l) for l in range(self.n_levels)]
 
+    @classmethod
+    def from_maps(cls, xyz_list, tri_list, maps, bc=MG_BC_DIRICHLET0,
+                  order: int = MG_ORDER_STRIPES):
+        """Hierarchy over given meshes (coarsest first) related by geometric maps M(f)."""
+        self = cls.__new__(cls)
+        self.meshes = [dec_mesh_from_arrays(x, t) for x, t in zip(xyz_list, tri_list)]
+        self.mesh = None
+        self.bc = bc
+        self.h = mg_hierarchy_build_maps(self.meshes, maps, bc, order=order)
+        self.n_levels = mg_hierarchy_info(self.h, 0)["n_levels"]
+        self.top = self.n_levels - 1
+        self.info = [mg_hierarchy_info(self.h, l) for l in range(self.n_levels)]
+        return self
+
     def nv(self, level=None):
         return self.info[self.top if level is None else level]["nv"]
 
@@ -528,6 +599,9 @@ class Hierarchy:
         if getattr(self, "mesh", None):
             dec_mesh_free(self.mesh)
             self.mesh = None
+        for m in getattr(self, "meshes", None) or []:
+            dec_mesh_free(m)
+        self.meshes = None
 
     def __del__(self):
         try:

@@ -8,6 +8,7 @@
 
 #include "batch.hpp"
 #include "decmg.h"
+#include "geomap.hpp"
 #include "hier.hpp"
 #include "solver.hpp"
 #include "util.hpp"
@@ -256,6 +257,54 @@ mg_status mg_hierarchy_build(const dec_mesh* base, const mg_hier_opts* opts, voi
   return MG_OK;
 }
 
+mg_status mg_hierarchy_build_maps(int32_t n_levels, const dec_mesh* const* meshes,
+                                  const mg_geomap* maps, const mg_hier_opts* opts, void* stream,
+                                  mg_hierarchy** out) {
+  API_BEGIN
+  (void)stream;
+  if (!meshes || !opts || !out || (n_levels > 1 && !maps)) return fail(MG_EINVAL, "null argument");
+  *out = nullptr;
+  if (n_levels < 1 || n_levels > 32) return fail(MG_EINVAL, "n_levels must be in 1..32");
+  if (opts->n_subdiv != 0 || opts->project_sphere != 0 || opts->cubic_mask != 0)
+    return fail(MG_EINVAL, "n_subdiv, project_sphere and cubic_mask must be 0 for given maps");
+  if (opts->bc != MG_BC_DIRICHLET0 && opts->bc != MG_BC_NATURAL)
+    return fail(MG_EINVAL, "bc must be MG_BC_DIRICHLET0 or MG_BC_NATURAL");
+  if (opts->order != MG_ORDER_STRIPES && opts->order != MG_ORDER_MORTON)
+    return fail(MG_EINVAL, "order must be MG_ORDER_STRIPES or MG_ORDER_MORTON");
+  std::vector<decmg::Mesh> ms;
+  bool nested = true;
+  for (int32_t l = 0; l < n_levels; ++l) {
+    if (!meshes[l]) return fail(MG_EINVAL, "null mesh");
+    ms.push_back(meshes[l]->m);
+    ms.back().scheme = 0;
+    ms.back().parent.clear();
+    ms.back().parent3.clear();
+    ms.back().pweight.clear();
+    if (l == 0) continue;
+    const std::string err = decmg::check_geomap(ms[l - 1], ms[l].nv, maps[l - 1]);
+    if (!err.empty()) return fail(MG_EINVAL, "map " + std::to_string(l - 1) + ": " + err);
+    decmg::set_interp_from_geomap(ms[l], maps[l - 1]);
+    nested = nested && decmg::geomap_keeps_ids(maps[l - 1]);
+  }
+  if (double(ms.back().nt) > double(int64_t(1) << 30))
+    return fail(MG_EINVAL, "finest level exceeds 2^30 triangles");
+  auto h = std::make_unique<mg_hierarchy>();
+  h->h.reset(decmg::build_hierarchy_maps(std::move(ms), nested, *opts));
+  *out = h.release();
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_geomap_compose(const mg_geomap* g, const mg_geomap* f, int64_t* colptr,
+                            int32_t* rowval, double* nzval, int64_t* nnz) {
+  API_BEGIN
+  if (!g || !f || !nnz) return fail(MG_EINVAL, "null argument");
+  const std::string err = decmg::compose_geomaps(*g, *f, colptr, rowval, nzval, nnz);
+  if (!err.empty()) return fail(MG_EINVAL, err);
+  API_END
+  return MG_OK;
+}
+
 void mg_hierarchy_free(mg_hierarchy* h) { delete h; }
 
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out) {
@@ -313,6 +362,9 @@ mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex,
   API_BEGIN
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
   decmg::Hierarchy& H = *h->h;
+  if (k_vertex && !H.nested_ids)
+    return fail(MG_EINVAL, "the vertex coefficient is injected by vertex id: the maps of this "
+                           "hierarchy do not keep the coarse vertex ids");
   if (!k_vertex) {
     H.kvert_h.clear();
   } else {

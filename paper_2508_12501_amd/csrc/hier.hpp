@@ -177,6 +177,7 @@ struct PorousData {
 struct Hierarchy {
   int32_t bc = MG_BC_DIRICHLET0;
   bool project = false;
+  bool nested_ids = true;   // every level keeps the vertex ids of the level below it
   std::vector<std::unique_ptr<Level>> lv;
   double* coarse_inv = nullptr;    // n0 x n0 FP64 inverse of the coarsest operator
   int32_t n0 = 0;

@@ -630,9 +630,13 @@ void upload_weights(Hierarchy& H) {
   }
 }
 
+namespace {
+Hierarchy* build_levels(std::unique_ptr<Hierarchy> H, std::vector<Mesh> meshes,
+                        const mg_hier_opts& o);
+}  // namespace
+
 Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
   auto H = std::make_unique<Hierarchy>();
-  H->bc = o.bc;
   H->project = o.project_sphere != 0;
   // host meshes
   std::vector<Mesh> meshes;
@@ -645,6 +649,21 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
     if (!err.empty()) throw std::invalid_argument(err);
     meshes.push_back(std::move(f));
   }
+  return build_levels(std::move(H), std::move(meshes), o);
+}
+
+Hierarchy* build_hierarchy_maps(std::vector<Mesh> meshes, bool nested_ids, const mg_hier_opts& o) {
+  auto H = std::make_unique<Hierarchy>();
+  H->nested_ids = nested_ids;
+  return build_levels(std::move(H), std::move(meshes), o);
+}
+
+namespace {
+// Operators, transfers, vectors and workspaces of every level of a hierarchy over `meshes`
+// (coarsest first; every level above the base carries its interpolation rows).
+Hierarchy* build_levels(std::unique_ptr<Hierarchy> H, std::vector<Mesh> meshes,
+                        const mg_hier_opts& o) {
+  H->bc = o.bc;
   for (auto& m : meshes) {
     m.build_stars();
     m.build_boundary();
@@ -706,6 +725,7 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o) {
   check_hip(hipStreamCreateWithFlags(&H->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
   return H.release();
 }
+}  // namespace
 
 Hierarchy::~Hierarchy() {
   for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);

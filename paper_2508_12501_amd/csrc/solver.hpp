@@ -15,6 +15,8 @@ T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const in
           hipStream_t s);
 
 Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o);
+// Levels over given meshes whose interpolation rows are already set (set_interp_from_geomap).
+Hierarchy* build_hierarchy_maps(std::vector<Mesh> meshes, bool nested_ids, const mg_hier_opts& o);
 void upload_weights(Hierarchy& H);
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
             hipStream_t s);

@@ -2,8 +2,11 @@
 
 This module is shared by the FP64 reference (``oracle/``) and by the HIP path.  It holds
 random draws and closed-form test functions evaluated at given coordinates, and nothing of
-the method itself: no mesh construction, no DEC operator, no smoothing, no solve.  Vertex
-coordinates are always passed in by the caller, each side passing its own.
+the method itself: no subdivision, no DEC operator, no smoothing, no solve.  Vertex
+coordinates of the subdivided workloads are always passed in by the caller, each side passing
+its own.  The one exception is the input of the non-nested workload: meshes and the geometric
+maps between them are what a user hands to the method, so they are generated here
+(``jittered_grid``, ``grid_point_location``) and given to both sides alike.
 
 Workloads (unit square meshes are 2-D right-triangle grids, spheres are icospheres):
 
@@ -173,3 +176,86 @@ def c5_initial_temperature(xyz: np.ndarray) -> np.ndarray:
 def c5_loss_weights(nv: int) -> np.ndarray:
     """Loss J = sum_i w_i T_i(final) with w ~ N(0,1) (seed 7)."""
     return normal(nv, SEED_C5_W)
+
+
+# ---------------------------------------------------------------- non-nested map workload
+SEED_MAPS = 9
+MAPS_CELLS = (4, 8, 16, 32, 64)   # cells per side, coarsest first
+MAPS_AMP = 0.15                   # interior vertex jitter, in cell widths
+
+
+def jittered_grid(n: int, seed: int, amp: float = MAPS_AMP):
+    """Input mesh of the non-nested workload: the unit square with n x n cells split along the
+    SW-NE diagonal, every interior vertex moved by U[-amp, amp] / n in x and in y (seeded).
+    Vertex (i, j) is j (n+1) + i; cell (ci, cj) gives triangles 2 (cj n + ci) and +1."""
+    j, i = np.mgrid[0:n + 1, 0:n + 1]
+    xyz = np.zeros(((n + 1) ** 2, 3))
+    xyz[:, 0] = i.ravel() / n
+    xyz[:, 1] = j.ravel() / n
+    inner = ((i > 0) & (i < n) & (j > 0) & (j < n)).ravel()
+    d = np.random.default_rng(seed).uniform(-amp, amp, size=(int(inner.sum()), 2)) / n
+    xyz[inner, :2] += d
+    a = (np.arange(n)[None, :] + (n + 1) * np.arange(n)[:, None]).ravel()
+    tri = np.empty((2 * n * n, 3), dtype=np.int32)
+    tri[0::2] = np.column_stack([a, a + 1, a + n + 2])
+    tri[1::2] = np.column_stack([a, a + n + 2, a + n + 1])
+    e1 = xyz[tri[:, 1], :2] - xyz[tri[:, 0], :2]
+    e2 = xyz[tri[:, 2], :2] - xyz[tri[:, 0], :2]
+    assert np.all(e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0] > 0), "jitter inverted a triangle"
+    return xyz, tri
+
+
+def grid_point_location(xyz_c, tri_c, n_c: int, xyz_f, drop: float = 1e-14):
+    """The geometric map sending every fine vertex to the same point of the coarse jittered
+    grid: M(f) (coarse x fine, scipy CSC) with column j the barycentric coordinates of fine
+    vertex j in the coarse triangle that holds it.  Candidates are the triangles of the 3 x 3
+    cells around the point's cell (vertices move by less than half a cell); the one whose
+    smallest coordinate is largest wins.  Coordinates at or below `drop` are removed, so points
+    on coarse edges or at coarse vertices name that edge or vertex."""
+    import scipy.sparse as sp
+    p = np.asarray(xyz_f)[:, :2]
+    nf = len(p)
+    cell = np.clip(np.floor(p * n_c).astype(np.int64), 0, n_c - 1)
+    best = np.full(nf, -np.inf)
+    lam = np.zeros((nf, 3))
+    which = np.zeros(nf, dtype=np.int64)
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            ci = cell[:, 0] + di
+            cj = cell[:, 1] + dj
+            ok = (ci >= 0) & (ci < n_c) & (cj >= 0) & (cj < n_c)
+            for s in (0, 1):
+                t = np.where(ok, 2 * (np.clip(cj, 0, n_c - 1) * n_c + np.clip(ci, 0, n_c - 1)) + s, 0)
+                A = xyz_c[tri_c[t, 0], :2]
+                B = xyz_c[tri_c[t, 1], :2]
+                C = xyz_c[tri_c[t, 2], :2]
+                den = (B[:, 0] - A[:, 0]) * (C[:, 1] - A[:, 1]) - (B[:, 1] - A[:, 1]) * (C[:, 0] - A[:, 0])
+                lb = ((p[:, 0] - A[:, 0]) * (C[:, 1] - A[:, 1]) - (p[:, 1] - A[:, 1]) * (C[:, 0] - A[:, 0])) / den
+                lc = ((B[:, 0] - A[:, 0]) * (p[:, 1] - A[:, 1]) - (B[:, 1] - A[:, 1]) * (p[:, 0] - A[:, 0])) / den
+                la = 1.0 - lb - lc
+                m = np.minimum(np.minimum(la, lb), lc)
+                m = np.where(ok, m, -np.inf)
+                take = m > best
+                best = np.where(take, m, best)
+                lam[take] = np.column_stack([la, lb, lc])[take]
+                which[take] = t[take]
+    assert best.min() >= -1e-12, "a fine vertex lies outside the coarse mesh"
+    rows, cols, vals = [], [], []
+    for q in range(3):
+        keep = lam[:, q] > drop
+        rows.append(tri_c[which[keep], q])
+        cols.append(np.nonzero(keep)[0])
+        vals.append(lam[keep, q])
+    M = sp.csc_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(len(xyz_c), nf))
+    M.sort_indices()
+    return M
+
+
+def maps_workload(cells=MAPS_CELLS, seed: int = SEED_MAPS, amp: float = MAPS_AMP):
+    """Meshes (coarsest first) and the maps M(f_l): mesh l+1 -> mesh l of the non-nested
+    workload: independently jittered grids of the given cell counts."""
+    meshes = [jittered_grid(n, seed + 17 * k, amp) for k, n in enumerate(cells)]
+    maps = [grid_point_location(meshes[k][0], meshes[k][1], cells[k], meshes[k + 1][0])
+            for k in range(len(cells) - 1)]
+    return meshes, maps

@@ -312,9 +312,11 @@ mg_status mg_batch_info(const mg_batch* bt, mg_batch_tuning* tune, int32_t* n_gr
 void mg_batch_free(mg_batch* bt);
 
 /* ------------------------------------------------------------------ porous convection
- * One forward-Euler step of the Darcy-Boussinesq model of Sec. 3.2 (scaled form: advection
- * factor 1/phi, diffusivity kappa = 1/(phi Ra)) on the finest level of a natural-BC hierarchy
- * of a mesh in the plane, with permeability k = the hierarchy's vertex coefficient:
+ * One forward-Euler step of the Darcy-Boussinesq model of Sec. 3.2 (advection factor 1/phi,
+ * buoyancy alpha rho0 |g| = 1, permeability scale k/eta = 1, diffusivity
+ * kappa = delta_T y_len / (phi Ra), the paper's product for lambda / (rho0 c_p); the scaled form
+ * takes delta_T = y_len = 1) on the finest level of a natural-BC hierarchy of a mesh in the
+ * plane, with permeability k = the hierarchy's vertex coefficient:
  *   b1_e = (y_hi - y_lo)(T_lo + T_hi)/2                 buoyancy 1-form
  *   L_K p = d0^T W b1,  W = star1 k_e                    pressure (zero-mean, MG-PCG)
  *   q = -k_e (d0 p - b1)                                 Darcy flux
@@ -324,8 +326,10 @@ void mg_batch_free(mg_batch* bt);
 typedef struct {
   double Ra;        /* Rayleigh number (> 0) */
   double phi;       /* porosity (> 0) */
-  double dt;        /* time step (> 0) */
+  double dt;        /* time step (> 0; not read by porous_rhs and porous_integrate) */
   mg_opts solve;    /* options of the pressure solves (mg_pcg) */
+  double delta_T;   /* wall temperature difference in kappa (> 0; 1 in the scaled form) */
+  double y_len;     /* extent of the domain in y in kappa (> 0; 1 in the scaled form) */
 } porous_params;
 
 /* T_out = step(T).  p (nullable) receives the pressure.  res (nullable) reports the pressure
@@ -333,6 +337,11 @@ typedef struct {
  * MG_EINVAL for a hierarchy with Dirichlet boundaries or a non-positive parameter. */
 mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T, double* T_out,
                       double* p, mg_result* res, void* stream);
+/* The right-hand side of the method of lines (Sec. 3.2): dTdt = mask/star0 ( ... ) of the step
+ * above without the time step, so that porous_step is T + dt * dTdt.  Same arguments and
+ * errors as porous_step; dTdt must not alias T. */
+mg_status porous_rhs(mg_hierarchy* h, const porous_params* prm, const double* T, double* dTdt,
+                     double* p, mg_result* res, void* stream);
 /* Transpose of the step's Jacobian: lambda_out = (dT'/dT)^T lambda, with the pressure solve
  * differentiated through (one adjoint-pressure solve).  p (nullable) is the pressure that
  * porous_step returned for this T (recomputed when null).  grad_k (nullable) ACCUMULATES
@@ -340,6 +349,44 @@ mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T
 mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const double* T,
                               const double* p, const double* lambda, double* lambda_out,
                               double* grad_k, void* stream);
+
+/* Adaptive time integration of dT/dt = porous_rhs(T) from t = 0 to t_end (Sec. 3.2: method of
+ * lines; the paper integrates with an explicit adaptive Runge-Kutta 5(4) pair).  The pair here
+ * is Dormand-Prince 5(4): seven stages, the last equal to the next step's first, so six
+ * right-hand sides per step.  The error of a step of size h is the weighted RMS norm
+ *   err = sqrt(mean_i ((T5 - T4)_i / (atol + rtol max(|T_i|, |T5_i|)))^2)
+ * of the difference between the 5th-order result T5 (which is kept) and the embedded
+ * 4th-order one.  A step is accepted when err <= 1; the next step size is
+ * h min(fmax, max(0.2, 0.9 err^(-1/5))), with fmax = 10, or 1 right after a rejection.  The
+ * first step is h0 when h0 > 0, otherwise it is chosen from the first two right-hand sides by
+ * Hairer, Norsett and Wanner's starting-step rule.  A step that would pass within 1% of a save
+ * time or of t_end is cut to land on it.  fixed_step = 1 takes steps of h0 without error
+ * control.  The pressure solves start from zero. */
+typedef struct {
+  porous_params model;  /* model.dt is not read */
+  double t_end;         /* > 0 */
+  double rtol, atol;    /* > 0 (adaptive mode) */
+  double h0;            /* first step (> 0), or 0 for automatic (adaptive mode only) */
+  int32_t max_steps;    /* limit on accepted + rejected steps (> 0) */
+  int32_t fixed_step;
+} porous_rk_opts;
+
+typedef struct {
+  int32_t accepted, rejected, rhs_evals, reserved;
+  int64_t pressure_iterations;  /* summed over all pressure solves */
+  double t;                     /* time reached */
+  double h_min, h_max;          /* smallest and largest accepted step */
+} porous_rk_stats;
+
+/* T0: nv doubles (device, natural order).  t_save: n_save strictly increasing host times in
+ * (0, t_end]; T_save (device, nullable when n_save == 0) receives T at each of them, row i at
+ * T_save + i nv.  T_end (device) receives T(t_end).  stats (nullable).  MG_ENOCONV when
+ * max_steps is reached or the step size falls below 1e-14 t_end (T_end then holds the last
+ * accepted state); a failed pressure solve returns its status.  Allocates and frees its work
+ * vectors (10 of nv + 1 doubles) on every call. */
+mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
+                           int32_t n_save, const double* t_save, double* T_save, double* T_end,
+                           porous_rk_stats* stats, void* stream);
 
 /* ------------------------------------------------------------------ measurement
  * Times `reps` back-to-back launches of one kernel of the path on `level` with hipEvents

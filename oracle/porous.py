@@ -1,9 +1,10 @@
 """Darcy-Boussinesq porous convection on the DEC and its discrete adjoint -- FP64 reference.
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).  The model is Sec. 3.2 (Eq. poisson,
-Eqs. dec_darcy .. dec_pconv_heat_up and the diagram Fig. pc_decapode) in the scaled form with
-alpha rho0 |g| = k/eta scale = Delta T = y_max = 1, which leaves the advection factor 1/phi
-and the diffusivity 1/(phi Ra) (the paper's product for lambda / (rho0 c_p)).  Readings:
+Eqs. dec_darcy .. dec_pconv_heat_up and the diagram Fig. pc_decapode) with alpha rho0 |g| = 1
+and k/eta scale 1 (the paper sets alpha rho0 = 1/g and k_etaf = 1), which leaves the advection
+factor 1/phi and the diffusivity kappa = Delta T y_max / (phi Ra), the paper's product for
+lambda / (rho0 c_p); the scaled form takes Delta T = y_max = 1.  Readings:
 
 * Q13 edge permeability k_e = (k_lo + k_hi) / 2 from a vertex field k = exp(g);
 * Q14 buoyancy 1-form b1 = yhat^flat wedge T, the wedge of a 1-form and a 0-form being the
@@ -11,7 +12,8 @@ and the diffusivity 1/(phi Ra) (the paper's product for lambda / (rho0 c_p)).  R
 * Darcy flux q = -K (d0 p - b1);  delta q = 0 gives d0^T W d0 p = d0^T W b1, W = star1 K;
 * advection L_q T as star0^{-1} (q wedge star1 d0 T): sum over edges at a vertex of
   star1_e q_e (d0 T)_e / 2; diffusion -star0^{-1} L T with L = d0^T star1 d0;
-* bc: dT/dt = 0 on the walls y = 0 and y = 1; natural boundary elsewhere;
+* bc: dT/dt = 0 on the walls, the vertices of smallest and of largest y (y = 0 and y = 1 on
+  the unit square); natural boundary elsewhere;
 * Q16 forward Euler with a fixed dt (a parameter of the step, not differentiated);
 * Q17 the pressure has natural boundaries (kernel = constants); it is the zero-mean solution.
 
@@ -31,13 +33,14 @@ class PorousModel:
     """One square mesh (natural-BC hierarchy) with permeability k = exp(g) at its vertices."""
 
     def __init__(self, h: omg.Hierarchy, g: np.ndarray, Ra: float = 1000.0, phi: float = 0.1,
-                 dt: float | None = None, solver: str = "direct", rtol: float = 1e-10):
+                 dt: float | None = None, solver: str = "direct", rtol: float = 1e-10,
+                 delta_T: float = 1.0, y_len: float = 1.0):
         assert h.bc == "natural"
         self.h = h
         lv = h.fine
         self.lv = lv
         self.Ra, self.phi = Ra, phi
-        self.kappa = 1.0 / (phi * Ra)
+        self.kappa = delta_T * y_len / (phi * Ra)
         self.solver, self.rtol = solver, rtol
         self.d0 = sp.csr_matrix(lv.d0, dtype=np.float64)
         self.absd0 = abs(self.d0)
@@ -45,7 +48,7 @@ class PorousModel:
         self.dy = self.d0 @ self.y                       # yhat^flat: y_hi - y_lo per edge
         self.star1, self.star0 = lv.star1, lv.star0
         self.L1 = dec.laplacian(lv.d0, lv.star1)         # unit-k Laplacian (diffusion)
-        self.wall = (self.y == 0.0) | (self.y == 1.0)
+        self.wall = (self.y == self.y.min()) | (self.y == self.y.max())
         self.mask = (~self.wall).astype(np.float64)
         self.set_g(g)
         if dt is None:
@@ -95,6 +98,10 @@ class PorousModel:
         adv = 0.5 * (self.absd0.T @ (self.star1 * q * (self.d0 @ T)))
         diff = self.L1 @ T
         return self.mask * (-(1.0 / self.phi) * adv - self.kappa * diff) / self.star0, p
+
+    def rhs(self, T):
+        """dT/dt of the method of lines (the bracket of the step without dt)."""
+        return self.tdot(T)[0]
 
     def step(self, T):
         Td, p = self.tdot(T)

@@ -91,7 +91,23 @@ class mg_batch_tuning(ctypes.Structure):
 
 class porous_params(ctypes.Structure):
     _fields_ = [("Ra", ctypes.c_double), ("phi", ctypes.c_double), ("dt", ctypes.c_double),
-                ("solve", mg_opts)]
+                ("solve", mg_opts), ("delta_T", ctypes.c_double), ("y_len", ctypes.c_double)]
+
+
+class porous_rk_opts(ctypes.Structure):
+    _fields_ = [("model", porous_params), ("t_end", ctypes.c_double), ("rtol", ctypes.c_double),
+                ("atol", ctypes.c_double), ("h0", ctypes.c_double), ("max_steps", ctypes.c_int32),
+                ("fixed_step", ctypes.c_int32)]
+
+
+class porous_rk_stats(ctypes.Structure):
+    _fields_ = [("accepted", ctypes.c_int32), ("rejected", ctypes.c_int32),
+                ("rhs_evals", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("pressure_iterations", ctypes.c_int64), ("t", ctypes.c_double),
+                ("h_min", ctypes.c_double), ("h_max", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 _vp = ctypes.c_void_p
@@ -130,6 +146,10 @@ _PROTOS = {
                            ctypes.POINTER(mg_result), _vp]),
     "porous_step_adjoint": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp, _vp, _vp,
                                    _vp]),
+    "porous_rhs": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp,
+                          ctypes.POINTER(mg_result), _vp]),
+    "porous_integrate": (_i32, [_vp, ctypes.POINTER(porous_rk_opts), _vp, _i32, _vp, _vp, _vp,
+                                ctypes.POINTER(porous_rk_stats), _vp]),
     "mg_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(mg_opts),
                                ctypes.POINTER(mg_batch_tuning), ctypes.c_char_p,
                                ctypes.POINTER(_vp)]),
@@ -434,11 +454,53 @@ def mg_pcg_adjoint(h, opts: mg_opts, u, grad_u, grad_b, grad_k=None, stream=None
     return res
 
 
-def porous_params_make(Ra: float, phi: float, dt: float, solve: mg_opts | None = None) -> porous_params:
+def porous_params_make(Ra: float, phi: float, dt: float, solve: mg_opts | None = None,
+                       delta_T: float = 1.0, y_len: float = 1.0) -> porous_params:
+    """kappa = delta_T * y_len / (phi * Ra); delta_T = y_len = 1 is the scaled form."""
     p = porous_params()
     p.Ra, p.phi, p.dt = float(Ra), float(phi), float(dt)
     p.solve = solve if solve is not None else mg_opts_default()
+    p.delta_T, p.y_len = float(delta_T), float(y_len)
     return p
+
+
+def porous_rhs(h, prm: porous_params, T, dTdt, p=None, stream=None) -> mg_result:
+    import torch
+    res = mg_result()
+    n = _nv(h, _top(h))
+    _check(lib().porous_rhs(h, ctypes.byref(prm), _ptr(T, torch.float64, n, "T"),
+                            _ptr(dTdt, torch.float64, n, "dTdt"), _opt_ptr(p, torch.float64, n, "p"),
+                            ctypes.byref(res), _stream(stream)), res)
+    return res
+
+
+def porous_rk_opts_make(model: porous_params, t_end: float, rtol: float = 1e-9,
+                        atol: float = 1e-6, h0: float = 0.0, max_steps: int = 100000,
+                        fixed_step: bool = False) -> porous_rk_opts:
+    o = porous_rk_opts()
+    o.model = model
+    o.t_end, o.rtol, o.atol, o.h0 = float(t_end), float(rtol), float(atol), float(h0)
+    o.max_steps, o.fixed_step = int(max_steps), int(bool(fixed_step))
+    return o
+
+
+def porous_integrate(h, opts: porous_rk_opts, T0, T_end, t_save=(), T_save=None, stream=None,
+                     raise_on_error=True) -> porous_rk_stats:
+    """T_save: (len(t_save), nv) float64 device tensor (rows = save times), or None."""
+    import torch
+    n = _nv(h, _top(h))
+    ts = np.ascontiguousarray(np.asarray(t_save, dtype=np.float64))
+    if len(ts) and (T_save is None or tuple(T_save.shape) != (len(ts), n)):
+        raise ValueError("T_save must be (len(t_save), nv)")
+    st = porous_rk_stats()
+    code = lib().porous_integrate(h, ctypes.byref(opts), _ptr(T0, torch.float64, n, "T0"),
+                                  len(ts), ts.ctypes.data if len(ts) else None,
+                                  _ptr(T_save, torch.float64, n * len(ts), "T_save") if len(ts) else None,
+                                  _ptr(T_end, torch.float64, n, "T_end"), ctypes.byref(st),
+                                  _stream(stream))
+    if raise_on_error:
+        _check(code)
+    return st
 
 
 def porous_step(h, prm: porous_params, T, T_out, p=None, stream=None, raise_on_error=True) -> mg_result:

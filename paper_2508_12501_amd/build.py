@@ -24,7 +24,7 @@ DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 # host sources whose arithmetic must follow plain IEEE order (mesh geometry, row sums)
 STRICT_HOST = {"mesh.cpp", "hierarchy.cpp"}
 
-SOURCES = ["mesh.cpp", "geomap.cpp", "hierarchy.cpp", "solver.cpp", "capi.cpp", "porous.cpp", "batch.cpp", "kernels.hip", "porous.hip", "batch.hip"]
+SOURCES = ["mesh.cpp", "geomap.cpp", "hierarchy.cpp", "solver.cpp", "capi.cpp", "porous.cpp", "porous_rk.cpp", "batch.cpp", "kernels.hip", "porous.hip", "batch.hip"]
 
 
 def hipcc() -> str:

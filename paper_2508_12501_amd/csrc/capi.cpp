@@ -527,19 +527,20 @@ mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine
 }
 
 namespace {
-mg_status check_porous(const mg_hierarchy* h, const porous_params* p) {
+mg_status check_porous(const mg_hierarchy* h, const porous_params* p, bool need_dt = true) {
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
   if (!p) return fail(MG_EINVAL, "null parameters");
   if (h->h->bc != MG_BC_NATURAL)
     return fail(MG_EINVAL, "the porous step needs a hierarchy with natural boundaries");
-  if (!(p->Ra > 0) || !(p->phi > 0) || !(p->dt > 0) || !std::isfinite(p->Ra) ||
-      !std::isfinite(p->phi) || !std::isfinite(p->dt))
-    return fail(MG_EINVAL, "Ra, phi and dt must be finite and positive");
+  if (!(p->Ra > 0) || !(p->phi > 0) || !std::isfinite(p->Ra) || !std::isfinite(p->phi) ||
+      !(p->delta_T > 0) || !(p->y_len > 0) || !std::isfinite(p->delta_T) ||
+      !std::isfinite(p->y_len))
+    return fail(MG_EINVAL, "Ra, phi, delta_T and y_len must be finite and positive");
+  if (need_dt && (!(p->dt > 0) || !std::isfinite(p->dt)))
+    return fail(MG_EINVAL, "dt must be finite and positive");
   return check_krylov_opts(&p->solve);
 }
-decmg::PorousParams porous_of(const porous_params* p) {
-  return decmg::PorousParams{p->Ra, p->phi, p->dt, p->solve};
-}
+decmg::PorousParams porous_of(const porous_params* p) { return decmg::porous_params_of(*p); }
 }  // namespace
 
 mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T, double* T_out,
@@ -551,6 +552,47 @@ mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T
   const int st = decmg::run_porous_step(*h->h, porous_of(prm), T, T_out, p, res, S(stream));
   if (st != MG_OK)
     return fail(mg_status(st), "porous_step pressure solve stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status porous_rhs(mg_hierarchy* h, const porous_params* prm, const double* T, double* dTdt,
+                     double* p, mg_result* res, void* stream) {
+  if (mg_status st = check_porous(h, prm, false); st != MG_OK) return st;
+  if (!T || !dTdt) return fail(MG_EINVAL, "null vector");
+  if (T == dTdt) return fail(MG_EINVAL, "dTdt must not alias T");
+  API_BEGIN
+  const int st = decmg::run_porous_rhs(*h->h, porous_of(prm), T, dTdt, p, res, S(stream));
+  if (st != MG_OK)
+    return fail(mg_status(st), "porous_rhs pressure solve stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
+                           int32_t n_save, const double* t_save, double* T_save, double* T_end,
+                           porous_rk_stats* stats, void* stream) {
+  if (!o) return fail(MG_EINVAL, "null options");
+  if (mg_status st = check_porous(h, &o->model, false); st != MG_OK) return st;
+  if (!T0 || !T_end) return fail(MG_EINVAL, "null vector");
+  if (!(o->t_end > 0) || !std::isfinite(o->t_end)) return fail(MG_EINVAL, "t_end must be > 0");
+  if (o->max_steps < 1) return fail(MG_EINVAL, "max_steps must be >= 1");
+  if (o->fixed_step != 0 && o->fixed_step != 1) return fail(MG_EINVAL, "fixed_step must be 0 or 1");
+  if (!(o->h0 >= 0) || !std::isfinite(o->h0)) return fail(MG_EINVAL, "h0 must be >= 0");
+  if (o->fixed_step && !(o->h0 > 0)) return fail(MG_EINVAL, "fixed steps need h0 > 0");
+  if (!o->fixed_step && (!(o->rtol > 0) || !(o->atol > 0) || !std::isfinite(o->rtol) ||
+                         !std::isfinite(o->atol)))
+    return fail(MG_EINVAL, "rtol and atol must be finite and positive");
+  if (n_save < 0 || (n_save > 0 && (!t_save || !T_save)))
+    return fail(MG_EINVAL, "save times need t_save and T_save");
+  for (int32_t i = 0; i < n_save; ++i)
+    if (!(t_save[i] > (i ? t_save[i - 1] : 0.0)) || !(t_save[i] <= o->t_end))
+      return fail(MG_EINVAL, "save times must increase strictly within (0, t_end]");
+  API_BEGIN
+  const int st = decmg::run_porous_integrate(*h->h, *o, T0, n_save, t_save, T_save, T_end, stats,
+                                             S(stream));
+  if (st != MG_OK)
+    return fail(mg_status(st), "porous_integrate stopped with status " + std::to_string(st));
   API_END
   return MG_OK;
 }

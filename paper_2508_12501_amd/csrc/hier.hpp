@@ -265,16 +265,31 @@ template <typename T> void bnd_zero(const int32_t* ids, int32_t nb, T* x, hipStr
 void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t s);
 void prepare_coarse(const Hierarchy& H);
 
+// Runge-Kutta building blocks (porous.hip): up to 7 vectors with coefficients.
+struct RkTerms {
+  const double* v[7];
+  double c[7];
+  int m;
+};
+// out = y + h * sum_j c_j v_j
+void rk_axpy(const double* y, const RkTerms& tm, double h, double* out, int32_t n, hipStream_t s);
+// *out = sqrt(mean_i ((scale sum_j c_j v_j)_i / (atol + rtol max(|u_i|, |w_i|)))^2); part holds
+// rk_parts(n) doubles of scratch.  Device result.
+int rk_parts(int32_t n);
+void rk_wrms(const RkTerms& tm, double scale, const double* u, const double* w, double atol,
+             double rtol, double* part, double* out, int32_t n, hipStream_t s);
+
 // porous step and solve gradients (porous.hip)
 void por_rhs(const Level& L, const PorousData& D, const double* T, double* rhs, hipStream_t s);
+// Tout = (add_T ? T : 0) + dt * dT/dt
 void por_update(const Level& L, const PorousData& D, const double* T, const double* P, double* Tout,
-                double dt, double phi, double Ra, hipStream_t s);
+                double dt, double phi, double kappa, bool add_T, hipStream_t s);
 void por_mu(const Level& L, const PorousData& D, const double* lam, double* mu, hipStream_t s);
 void por_adj_rhs(const Level& L, const PorousData& D, const double* T, const double* mu,
                  double* rhs, hipStream_t s);
 void por_adj_update(const Level& L, const PorousData& D, const double* T, const double* P,
                     const double* mu, const double* lam, const double* psi, double* lam_out,
-                    double dt, double phi, double Ra, hipStream_t s);
+                    double dt, double phi, double kappa, hipStream_t s);
 void por_grad_k(const Level& L, const PorousData& D, const double* T, const double* P,
                 const double* mu, const double* psi, double* gk_nat, double dt, double phi,
                 hipStream_t s);

@@ -102,10 +102,23 @@ void ensure(Hierarchy& H) {
 void check_params(const Hierarchy& H, const PorousParams& p) {
   if (H.bc != MG_BC_NATURAL)
     throw std::invalid_argument("the porous step needs a hierarchy with natural boundaries");
-  if (!(p.Ra > 0) || !(p.phi > 0) || !(p.dt > 0) || !std::isfinite(p.Ra) || !std::isfinite(p.phi) ||
-      !std::isfinite(p.dt))
-    throw std::invalid_argument("Ra, phi and dt must be finite and positive");
+  if (!(p.Ra > 0) || !(p.phi > 0) || !std::isfinite(p.Ra) || !std::isfinite(p.phi) ||
+      !(p.delta_T > 0) || !(p.y_len > 0) || !std::isfinite(p.delta_T) || !std::isfinite(p.y_len))
+    throw std::invalid_argument("Ra, phi, delta_T and y_len must be finite and positive");
 }
+
+}  // namespace
+
+void porous_prepare(Hierarchy& H) { ensure(H); }
+void porous_check(const Hierarchy& H, const PorousParams& p) { check_params(H, p); }
+PorousParams porous_params_of(const porous_params& p) {
+  PorousParams q{p.Ra, p.phi, p.dt, p.solve};
+  q.delta_T = p.delta_T;
+  q.y_len = p.y_len;
+  return q;
+}
+
+namespace {
 
 // Pressure (or adjoint pressure) solve of the right-hand side already in H.sb; result in H.sx.
 int solve_internal(Hierarchy& H, const mg_opts& o, mg_result* res, hipStream_t s) {
@@ -123,8 +136,24 @@ int run_porous_step(Hierarchy& H, const PorousParams& p, const double* T_nat, do
   k::gather<double>(F.perm, F.n, T_nat, D.T, s);
   k::por_rhs(F, D, D.T, H.sb, s);
   const int st = solve_internal(H, p.solve, res, s);
-  k::por_update(F, D, D.T, H.sx, D.T2, p.dt, p.phi, p.Ra, s);
+  k::por_update(F, D, D.T, H.sx, D.T2, p.dt, p.phi, p.kappa(), true, s);
   k::scatter<double>(F.perm, F.n, D.T2, Tout_nat, s);
+  if (p_nat) k::scatter<double>(F.perm, F.n, H.sx, p_nat, s);
+  check_hip(hipGetLastError(), "kernel launch");
+  return st;
+}
+
+int run_porous_rhs(Hierarchy& H, const PorousParams& p, const double* T_nat, double* rhs_nat,
+                   double* p_nat, mg_result* res, hipStream_t s) {
+  check_params(H, p);
+  ensure(H);
+  PorousData& D = H.por;
+  Level& F = *H.lv.back();
+  k::gather<double>(F.perm, F.n, T_nat, D.T, s);
+  k::por_rhs(F, D, D.T, H.sb, s);
+  const int st = solve_internal(H, p.solve, res, s);
+  k::por_update(F, D, D.T, H.sx, D.T2, 1.0, p.phi, p.kappa(), false, s);
+  k::scatter<double>(F.perm, F.n, D.T2, rhs_nat, s);
   if (p_nat) k::scatter<double>(F.perm, F.n, H.sx, p_nat, s);
   check_hip(hipGetLastError(), "kernel launch");
   return st;
@@ -153,7 +182,7 @@ int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
   k::por_mu(F, D, D.Lm, D.M, s);
   k::por_adj_rhs(F, D, D.T, D.M, H.sb, s);
   st = solve_internal(H, p.solve, nullptr, s);
-  k::por_adj_update(F, D, D.T, D.P, D.M, D.Lm, H.sx, D.L2, p.dt, p.phi, p.Ra, s);
+  k::por_adj_update(F, D, D.T, D.P, D.M, D.Lm, H.sx, D.L2, p.dt, p.phi, p.kappa(), s);
   if (gk_nat) k::por_grad_k(F, D, D.T, D.P, D.M, H.sx, gk_nat, p.dt, p.phi, s);
   k::scatter<double>(F.perm, n, D.L2, lam_out_nat, s);
   check_hip(hipGetLastError(), "kernel launch");
@@ -167,10 +196,8 @@ int run_pcg_adjoint(Hierarchy& H, const mg_opts& o, const double* u_nat, const d
     ensure(H);
     PorousData& D = H.por;
     Level& F = *H.lv.back();
+    // u enters only through d0 u, so its mean (natural boundary) does not matter
     k::gather<double>(F.perm, F.n, u_nat, D.U, s);
-    if (H.bc == MG_BC_NATURAL) {
-      // u enters only through d0 u: its mean does not matter
-    }
     k::mg_grad_k(F, D, H.sx, D.U, gk_nat, s);
     check_hip(hipGetLastError(), "kernel launch");
   }

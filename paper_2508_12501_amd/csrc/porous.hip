@@ -60,13 +60,14 @@ __global__ __launch_bounds__(kThreads) void k_por_rhs(const int32_t* __restrict_
 }
 
 // T' = T + dt mask / star0 * ( -(1/phi) sum_e star1_e Q_vu (T_v - T_u) / 2
-//                              - kappa sum_e star1_e (T_v - T_u) )
+//                              - kappa sum_e star1_e (T_v - T_u) ),  or only the rate
+// (the bracket times mask / star0) when add_T is 0
 __global__ __launch_bounds__(kThreads) void k_por_update(
     const int32_t* __restrict__ sptr, const void* __restrict__ col, int d16,
     const double* __restrict__ s1, const double* __restrict__ ke, const double* __restrict__ y,
     const double* __restrict__ T, const double* __restrict__ P, const double* __restrict__ star0,
     const double* __restrict__ mask, double* __restrict__ Tout, int32_t n, double dt,
-    double inv_phi, double kappa) {
+    double inv_phi, double kappa, int add_T) {
   const int v = blockIdx.x * kThreads + threadIdx.x;
   if (v >= n) return;
   const RowIter it(sptr, v);
@@ -80,7 +81,8 @@ __global__ __launch_bounds__(kThreads) void k_por_update(
     adv += 0.5 * s1[idx] * (q * (Tv - Tu));
     diff += s1[idx] * (Tv - Tu);
   }
-  Tout[v] = Tv + dt * (mask[v] * (-inv_phi * adv - kappa * diff) / star0[v]);
+  const double rate = mask[v] * (-inv_phi * adv - kappa * diff) / star0[v];
+  Tout[v] = add_T ? Tv + dt * rate : rate;
 }
 
 __global__ void k_por_mu(const double* __restrict__ lam, const double* __restrict__ mask,
@@ -173,6 +175,63 @@ __global__ void k_edges_to_vertices(const int64_t* __restrict__ vptr,
   g[v] += 0.5 * acc;
 }
 
+// ---- Runge-Kutta stage combinations and weighted RMS norms (internal order, n rows)
+
+// out = y + h * sum_j c_j v_j over the m terms, summed in term order.
+__global__ __launch_bounds__(kThreads) void k_rk_axpy(const double* __restrict__ y, k::RkTerms tm,
+                                                      double h, double* __restrict__ out,
+                                                      int32_t n) {
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  if (v >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < tm.m; ++j) acc += tm.c[j] * tm.v[j][v];
+  out[v] = y[v] + h * acc;
+}
+
+// part[block] = sum over the block's rows of (scale * sum_j c_j v_j / sc)^2 with
+// sc = atol + rtol * max(|u|, |w|).
+__global__ __launch_bounds__(kThreads) void k_rk_wsq(k::RkTerms tm, double scale,
+                                                     const double* __restrict__ u,
+                                                     const double* __restrict__ w, double atol,
+                                                     double rtol, double* __restrict__ part,
+                                                     int32_t n) {
+  __shared__ double red[kThreads / 64];
+  const int v = blockIdx.x * kThreads + threadIdx.x;
+  double s = 0.0;
+  if (v < n) {
+    double acc = 0.0;
+    for (int j = 0; j < tm.m; ++j) acc += tm.c[j] * tm.v[j][v];
+    const double sc = atol + rtol * fmax(fabs(u[v]), fabs(w[v]));
+    const double e = scale * acc / sc;
+    s = e * e;
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) b += red[q];
+    part[blockIdx.x] = b;
+  }
+}
+
+// out[0] = sqrt(sum(part) / n), one workgroup.
+__global__ __launch_bounds__(kThreads) void k_rk_rms_fin(const double* __restrict__ part,
+                                                         int32_t nparts, int32_t n,
+                                                         double* __restrict__ out) {
+  __shared__ double red[kThreads / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += kThreads) s += part[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = 0.0;
+    for (int q = 0; q < kThreads / 64; ++q) b += red[q];
+    out[0] = sqrt(b / double(n));
+  }
+}
+
 inline unsigned blocks(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
 
 const void* colp(const Level& L) {
@@ -183,15 +242,26 @@ const void* colp(const Level& L) {
 
 namespace k {
 
+void rk_axpy(const double* y, const RkTerms& tm, double h, double* out, int32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_axpy, dim3(blocks(n)), dim3(kThreads), 0, s, y, tm, h, out, n);
+}
+int rk_parts(int32_t n) { return int(blocks(n)); }
+void rk_wrms(const RkTerms& tm, double scale, const double* u, const double* w, double atol,
+             double rtol, double* part, double* out, int32_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_rk_wsq, dim3(blocks(n)), dim3(kThreads), 0, s, tm, scale, u, w, atol, rtol,
+                     part, n);
+  hipLaunchKernelGGL(k_rk_rms_fin, dim3(1), dim3(kThreads), 0, s, part, int32_t(blocks(n)), n, out);
+}
+
 void por_rhs(const Level& L, const PorousData& D, const double* T, double* rhs, hipStream_t s) {
   hipLaunchKernelGGL(k_por_rhs, dim3(blocks(L.n)), dim3(kThreads), 0, s, L.op.sptr, colp(L),
                      L.op.col16 ? 1 : 0, L.op.w64, D.y, T, rhs, L.n);
 }
 void por_update(const Level& L, const PorousData& D, const double* T, const double* P, double* Tout,
-                double dt, double phi, double Ra, hipStream_t s) {
+                double dt, double phi, double kappa, bool add_T, hipStream_t s) {
   hipLaunchKernelGGL(k_por_update, dim3(blocks(L.n)), dim3(kThreads), 0, s, L.op.sptr, colp(L),
                      L.op.col16 ? 1 : 0, D.s1, D.ke, D.y, T, P, D.star0, D.mask, Tout, L.n, dt,
-                     1.0 / phi, 1.0 / (phi * Ra));
+                     1.0 / phi, kappa, add_T ? 1 : 0);
 }
 void por_mu(const Level& L, const PorousData& D, const double* lam, double* mu, hipStream_t s) {
   hipLaunchKernelGGL(k_por_mu, dim3(blocks(L.n)), dim3(kThreads), 0, s, lam, D.mask, D.star0, mu, L.n);
@@ -203,10 +273,10 @@ void por_adj_rhs(const Level& L, const PorousData& D, const double* T, const dou
 }
 void por_adj_update(const Level& L, const PorousData& D, const double* T, const double* P,
                     const double* mu, const double* lam, const double* psi, double* lam_out,
-                    double dt, double phi, double Ra, hipStream_t s) {
+                    double dt, double phi, double kappa, hipStream_t s) {
   hipLaunchKernelGGL(k_por_adj_update, dim3(blocks(L.n)), dim3(kThreads), 0, s, L.op.sptr, colp(L),
                      L.op.col16 ? 1 : 0, D.s1, D.ke, D.y, T, P, mu, lam, psi, lam_out, L.n, dt,
-                     1.0 / phi, 1.0 / (phi * Ra));
+                     1.0 / phi, kappa);
 }
 void por_grad_k(const Level& L, const PorousData& D, const double* T, const double* P,
                 const double* mu, const double* psi, double* gk_nat, double dt, double phi,

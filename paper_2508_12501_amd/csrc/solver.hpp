@@ -27,9 +27,22 @@ int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, m
 struct PorousParams {
   double Ra, phi, dt;
   mg_opts solve;
+  double delta_T = 1.0, y_len = 1.0;
+  double kappa() const { return delta_T * y_len / (phi * Ra); }
 };
 int run_porous_step(Hierarchy& H, const PorousParams& p, const double* T_nat, double* Tout_nat,
                     double* p_nat, mg_result* res, hipStream_t s);
+// Dormand-Prince 5(4) integration of dT/dt = rhs (porous_rk.cpp).
+int run_porous_integrate(Hierarchy& H, const porous_rk_opts& o, const double* T0_nat,
+                         int32_t n_save, const double* t_save, double* Tsave_nat,
+                         double* Tend_nat, porous_rk_stats* stats, hipStream_t s);
+// Porous data of the finest level (built on first use, refreshed when k changes).
+void porous_prepare(Hierarchy& H);
+void porous_check(const Hierarchy& H, const PorousParams& p);
+PorousParams porous_params_of(const porous_params& p);
+// dT/dt of the step (no time step): porous_step = T + dt * rhs.
+int run_porous_rhs(Hierarchy& H, const PorousParams& p, const double* T_nat, double* rhs_nat,
+                   double* p_nat, mg_result* res, hipStream_t s);
 int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
                        const double* p_nat, const double* lam_nat, double* lam_out_nat,
                        double* gk_nat, hipStream_t s);

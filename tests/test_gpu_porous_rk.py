@@ -1,0 +1,182 @@
+"""GPU parity of the porous right-hand side (porous_rhs) and of the adaptive Dormand-Prince
+5(4) integration (porous_integrate) against the oracle (oracle.porous.PorousModel.rhs with a
+sparse direct pressure solve, oracle.rk.integrate), on the paper's porous-convection setup
+(workloads.E4: 40 x 20 rectangle, Gaussian initial temperature, walls at +-100,
+kappa = Delta T y_max / (phi Ra) = 40).
+
+Tolerances: the right-hand side and fixed-step runs follow the pressure solves (rtol 1e-13):
+1e-10 relative.  Adaptive runs take the oracle's accepted and rejected step counts; their
+states agree to 1e-9 relative.  The full-size run to t = 0.5 is compared as the paper does,
+by the RMSE against the direct-solve trajectory at ten save times; the bar is 1e-6 (the paper
+reports 2.54e-6 for its multigrid run)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import paper_2508_12501_amd as mg  # noqa: E402
+from oracle import dec  # noqa: E402
+from oracle import multigrid as omg  # noqa: E402
+from oracle import porous as op  # noqa: E402
+from oracle import rk  # noqa: E402
+import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+E = W.E4
+Y_LEN = E["y_range"][1] - E["y_range"][0]
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().double().cpu().numpy()
+
+
+class E4Pair:
+    def __init__(self, nsub, solve_rtol):
+        print(f"[porous-rk] building the E4 rectangle, nsub={nsub}", flush=True)
+        base = mg.Hierarchy("square", 0, base_cells=E["base_cells"], bc=mg.MG_BC_NATURAL)
+        ex = mg.mg_hierarchy_export(base.h, 0)
+        base.close()
+        self.g = mg.Hierarchy("arrays", nsub, xyz=W.e4_coords(ex["xyz"]), tri=ex["tri"],
+                              bc=mg.MG_BC_NATURAL)
+        xyz, tri = dec.square_grid(E["base_cells"])
+        self.o = omg.Hierarchy(W.e4_coords(xyz), tri, nsub, bc="natural")
+        self.m = op.PorousModel(self.o, np.zeros(self.o.fine.nv), Ra=E["Ra"], phi=E["phi"],
+                                delta_T=E["delta_T"], y_len=Y_LEN)
+        self.prm = mg.porous_params_make(E["Ra"], E["phi"], 1e-4,
+                                         mg.mg_opts_default(rtol=solve_rtol),
+                                         delta_T=E["delta_T"], y_len=Y_LEN)
+        self.T0 = W.e4_initial_temperature(self.o.fine.xyz)
+        self.nv = self.o.fine.nv
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = E4Pair(3, 1e-13)
+    yield P
+    P.g.close()
+
+
+@pytest.fixture(scope="module")
+def full():
+    P = E4Pair(E["nsub"], 1e-13)
+    yield P
+    P.g.close()
+
+
+def test_e4_inputs(small):
+    assert small.nv == 33 * 33
+    assert abs(small.T0.max() - 400.0 / np.pi) < 1e-12
+    assert small.m.kappa == 40.0
+
+
+@pytest.mark.parametrize("which", ["small", "full"])
+def test_rhs_parity(which, request):
+    P = request.getfixturevalue(which)
+    T = P.T0 + W.normal(P.nv, 51) * (~P.m.wall)
+    d = torch.empty(P.nv, dtype=torch.float64, device=DEV)
+    mg.porous_rhs(P.g.h, P.prm, gpu(T), d)
+    ref = P.m.rhs(T)
+    assert rel(host(d), ref) <= 1e-10
+    assert np.all(host(d)[P.m.wall] == 0.0)
+    # the forward-Euler step is T + dt * rhs
+    Tn = torch.empty_like(d)
+    mg.porous_step(P.g.h, P.prm, gpu(T), Tn)
+    step = host(Tn) - T
+    assert np.abs(step - P.prm.dt * host(d)).max() <= 1e-12 * np.abs(P.prm.dt * ref).max()
+
+
+def test_fixed_steps(small):
+    P = small
+    t_save = [0.002, 0.004, 0.0061]
+    o = mg.porous_rk_opts_make(P.prm, 0.008, h0=2.5e-4, fixed_step=True)
+    Ts = torch.empty(len(t_save), P.nv, dtype=torch.float64, device=DEV)
+    Te = torch.empty(P.nv, dtype=torch.float64, device=DEV)
+    st = mg.porous_integrate(P.g.h, o, gpu(P.T0), Te, t_save, Ts)
+    yo, so, sto = rk.integrate(P.m.rhs, P.T0, 0.008, h0=2.5e-4, t_save=t_save, fixed_step=True)
+    assert st.accepted == sto["accepted"] and st.rejected == 0
+    assert st.rhs_evals == sto["rhs_evals"]
+    assert rel(host(Te), yo) <= 1e-10
+    for i in range(len(t_save)):
+        assert rel(host(Ts[i]), so[i]) <= 1e-10, i
+
+
+def test_adaptive_small(small):
+    P = small
+    t_save = [0.01, 0.02, 0.05]
+    o = mg.porous_rk_opts_make(P.prm, 0.05, rtol=E["rtol"], atol=E["atol"])
+    Ts = torch.empty(len(t_save), P.nv, dtype=torch.float64, device=DEV)
+    Te = torch.empty(P.nv, dtype=torch.float64, device=DEV)
+    st = mg.porous_integrate(P.g.h, o, gpu(P.T0), Te, t_save, Ts)
+    yo, so, sto = rk.integrate(P.m.rhs, P.T0, 0.05, rtol=E["rtol"], atol=E["atol"],
+                               t_save=t_save)
+    print(f"[porous-rk] small adaptive: gpu {st.as_dict()} oracle {sto}")
+    assert (st.accepted, st.rejected, st.rhs_evals) == (sto["accepted"], sto["rejected"],
+                                                        sto["rhs_evals"])
+    assert abs(st.h_min - sto["h_min"]) <= 1e-9 * sto["h_min"]
+    assert st.t == 0.05
+    assert rel(host(Te), yo) <= 1e-9
+    for i in range(len(t_save)):
+        assert rel(host(Ts[i]), so[i]) <= 1e-9, i
+
+
+def test_conductive_state_is_steady(small):
+    P = small
+    y = P.o.fine.xyz[:, 1]
+    T = E["T_bottom"] + (E["T_top"] - E["T_bottom"]) * (y - y.min()) / (y.max() - y.min())
+    o = mg.porous_rk_opts_make(P.prm, 0.02, rtol=E["rtol"], atol=E["atol"])
+    Te = torch.empty(P.nv, dtype=torch.float64, device=DEV)
+    mg.porous_integrate(P.g.h, o, gpu(T), Te)
+    assert np.abs(host(Te) - T).max() <= 1e-9 * np.abs(T).max()
+
+
+def test_errors_and_step_limit(small):
+    P = small
+    Te = torch.empty(P.nv, dtype=torch.float64, device=DEV)
+    Ts = torch.empty(2, P.nv, dtype=torch.float64, device=DEV)
+    o = mg.porous_rk_opts_make(P.prm, 0.05)
+    with pytest.raises(mg.MGError) as e:
+        mg.porous_integrate(P.g.h, o, gpu(P.T0), Te, [0.02, 0.01], Ts)
+    assert e.value.status == mg.MG_EINVAL
+    with pytest.raises(mg.MGError) as e:
+        mg.porous_integrate(P.g.h, o, gpu(P.T0), Te, [0.02, 0.06], Ts)
+    assert e.value.status == mg.MG_EINVAL
+    o = mg.porous_rk_opts_make(P.prm, 0.05, max_steps=3)
+    st = mg.porous_integrate(P.g.h, o, gpu(P.T0), Te, raise_on_error=False)
+    assert st.accepted + st.rejected == 3 and st.t < 0.05
+    o = mg.porous_rk_opts_make(P.prm, 0.05, fixed_step=True)
+    with pytest.raises(mg.MGError) as e:
+        mg.porous_integrate(P.g.h, o, gpu(P.T0), Te)
+    assert e.value.status == mg.MG_EINVAL
+
+
+def test_e4_full_run_rmse_over_time(full):
+    """The paper's run: t = 0.5 at relative tolerance 1e-9, saved at ten times."""
+    P = full
+    ts = W.e4_save_times()
+    o = mg.porous_rk_opts_make(P.prm, E["t_end"], rtol=E["rtol"], atol=E["atol"])
+    Ts = torch.empty(len(ts), P.nv, dtype=torch.float64, device=DEV)
+    Te = torch.empty(P.nv, dtype=torch.float64, device=DEV)
+    print("[porous-rk] E4 full run on the GPU", flush=True)
+    st = mg.porous_integrate(P.g.h, o, gpu(P.T0), Te, ts, Ts)
+    print(f"[porous-rk] gpu: {st.as_dict()}", flush=True)
+    print("[porous-rk] E4 full run in the oracle (direct pressure solves)", flush=True)
+    yo, so, sto = rk.integrate(P.m.rhs, P.T0, E["t_end"], rtol=E["rtol"], atol=E["atol"],
+                               t_save=ts)
+    print(f"[porous-rk] oracle: {sto}", flush=True)
+    G = host(Ts)
+    rmse = [float(np.sqrt(np.mean((G[i] - so[i]) ** 2))) for i in range(len(ts))]
+    print("[porous-rk] RMSE vs the direct-solve trajectory: " +
+          ", ".join(f"t={t:.2f}: {r:.2e}" for t, r in zip(ts, rmse)), flush=True)
+    assert st.t == E["t_end"] and abs(st.accepted - sto["accepted"]) <= 2
+    assert max(rmse) <= 1e-6
+    assert np.array_equal(host(Te), G[-1])

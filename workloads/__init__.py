@@ -259,3 +259,42 @@ def maps_workload(cells=MAPS_CELLS, seed: int = SEED_MAPS, amp: float = MAPS_AMP
     maps = [grid_point_location(meshes[k][0], meshes[k][1], cells[k], meshes[k + 1][0])
             for k in range(len(cells) - 1)]
     return meshes, maps
+
+
+# ---------------------------------------------------------------- porous run of Sec. 3.2
+# The paper's porous-convection experiment: a 16,641-vertex rectangle (128 x 128 cells, each
+# split in two), Gaussian initial temperature (covariance I/2 around the centre, scaled by 400:
+# peak 400/pi ~ 127), walls at +100 (bottom) and -100 (top), alpha rho0 = 1/g, phi = 0.1,
+# Ra = 1000, k_etaf = 1, Delta T = 200, integrated to t = 0.5 with relative tolerance 1e-9.
+# The extent of the rectangle is not printed; it is taken as [-20, 20] x [-20, 0] (40 x 20,
+# the pedagogical setup the paper follows), see the design notes.
+E4 = dict(base_cells=4, nsub=5, x_range=(-20.0, 20.0), y_range=(-20.0, 0.0), T_amp=400.0,
+          cov=0.5, T_bottom=100.0, T_top=-100.0, Ra=1000.0, phi=0.1, delta_T=200.0,
+          t_end=0.5, rtol=1e-9, atol=1e-6, n_save=10)
+
+
+def e4_coords(xyz_unit: np.ndarray) -> np.ndarray:
+    """Unit-square coordinates mapped affinely onto the E4 rectangle."""
+    (x0, x1), (y0, y1) = E4["x_range"], E4["y_range"]
+    out = np.array(xyz_unit, dtype=np.float64, copy=True)
+    out[:, 0] = x0 + (x1 - x0) * out[:, 0]
+    out[:, 1] = y0 + (y1 - y0) * out[:, 1]
+    return out
+
+
+def e4_initial_temperature(xyz: np.ndarray) -> np.ndarray:
+    """T_amp times the bivariate normal density with mean at the centre of the rectangle and
+    covariance cov * I, with the bottom wall at T_bottom and the top wall at T_top."""
+    (x0, x1), (y0, y1) = E4["x_range"], E4["y_range"]
+    cx, cy = 0.5 * (x0 + x1), 0.5 * (y0 + y1)
+    s = E4["cov"]
+    r2 = (xyz[:, 0] - cx) ** 2 + (xyz[:, 1] - cy) ** 2
+    T = E4["T_amp"] / (2.0 * math.pi * s) * np.exp(-r2 / (2.0 * s))
+    T[xyz[:, 1] == xyz[:, 1].min()] = E4["T_bottom"]
+    T[xyz[:, 1] == xyz[:, 1].max()] = E4["T_top"]
+    return T
+
+
+def e4_save_times() -> np.ndarray:
+    """Equally spaced save times in (0, t_end] for the error over time."""
+    return E4["t_end"] * np.arange(1, E4["n_save"] + 1) / E4["n_save"]

@@ -38,6 +38,8 @@ def parse():
     p.add_argument("--order", choices=["stripes", "morton"], default="stripes")
     p.add_argument("--no-porous", action="store_true",
                    help="skip the porous-convection rollout and gradient timing")
+    p.add_argument("--no-e4", action="store_true",
+                   help="skip the adaptive porous-convection run to t = 0.5")
     p.add_argument("--no-cubic", action="store_true",
                    help="skip the V-cycle timing on the 4-fold cubic subdivision")
     p.add_argument("--no-batch", action="store_true",
@@ -248,6 +250,46 @@ def cubic_bench(mg, W, torch, np, steps):
     return out
 
 
+def e4_bench(mg, W, torch, np):
+    """The paper's porous-convection run: 16,641 vertices, adaptive Dormand-Prince 5(4) to
+    t = 0.5 at relative tolerance 1e-9 (absolute 1e-6), one FP64 MG-PCG pressure solve
+    (rtol 1e-12) per right-hand side, ten save times."""
+    E = W.E4
+    dev = torch.device("cuda:0")
+    base = mg.Hierarchy("square", 0, base_cells=E["base_cells"], bc=mg.MG_BC_NATURAL)
+    ex = mg.mg_hierarchy_export(base.h, 0)
+    base.close()
+    H = mg.Hierarchy("arrays", E["nsub"], xyz=W.e4_coords(ex["xyz"]), tri=ex["tri"],
+                     bc=mg.MG_BC_NATURAL)
+    xyz = mg.mg_hierarchy_export(H.h, H.top)["xyz"]
+    nv = len(xyz)
+    y_len = E["y_range"][1] - E["y_range"][0]
+    prm = mg.porous_params_make(E["Ra"], E["phi"], 1e-4, mg.mg_opts_default(rtol=1e-12),
+                                delta_T=E["delta_T"], y_len=y_len)
+    T0 = torch.tensor(W.e4_initial_temperature(xyz), device=dev)
+    ts = W.e4_save_times()
+    Ts = torch.empty(len(ts), nv, dtype=torch.float64, device=dev)
+    Te = torch.empty_like(T0)
+    warm = mg.porous_rk_opts_make(prm, 0.002, rtol=E["rtol"], atol=E["atol"])
+    mg.porous_integrate(H.h, warm, T0, Te)
+    o = mg.porous_rk_opts_make(prm, E["t_end"], rtol=E["rtol"], atol=E["atol"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mg.porous_integrate(H.h, o, T0, Te, ts, Ts)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    H.close()
+    return {"workload": "porous convection, 128x128-cell 40x20 rectangle (16,641 vertices), "
+                        "Gaussian T0 x400, walls +-100, Ra 1000, phi 0.1, kappa 40; "
+                        "Dormand-Prince 5(4) to t = 0.5, rtol 1e-9, atol 1e-6; pressure by "
+                        "FP64 MG-PCG (rtol 1e-12)",
+            "vertices": nv, "seconds": dt, **st.as_dict(),
+            "ms_per_rhs": 1e3 * dt / st.rhs_evals,
+            "pressure_iterations_per_solve": st.pressure_iterations / st.rhs_evals,
+            "paper": {"rhs_evals": 7677, "accepted": 1275, "gmg_seconds": 167,
+                      "note": "Tsit5 on a laptop CPU; context only"}}
+
+
 def batch_bench(mg, W, torch, np, steps):
     """The 256-instance mix (icospheres of levels 4..7, squares of 33..513 vertices a side,
     seeded types), FP32-preconditioned FCG to 1e-10 for every instance, solved as one batch
@@ -383,6 +425,13 @@ def main():
               f"{cubic['mixed_fcg']['iterations']} it {cubic['mixed_fcg']['ms_per_solve']:.3f} ms",
               file=sys.stderr, flush=True)
 
+    e4 = None
+    if not a.no_e4:
+        e4 = e4_bench(mg, W, torch, np)
+        print(f"[bench] E4 porous run to t=0.5: {e4['seconds']:.2f} s, {e4['accepted']} accepted, "
+              f"{e4['rejected']} rejected, {e4['rhs_evals']} right-hand sides, "
+              f"{e4['ms_per_rhs']:.3f} ms each", file=sys.stderr, flush=True)
+
     ms_step = 1e3 * total_m / a.steps
     value = unknowns / (total_m / a.steps)
     value_fp64 = unknowns / (total_d / n64)
@@ -441,6 +490,7 @@ def main():
         "speedup_mixed_vs_fp64": value / value_fp64,
         "variants": variants,
         "cubic_vcycle": cubic,
+        "porous_e4_adaptive": e4,
         "roofline": {
             "bound": "hbm",
             "kernel": "k_rows<float, 2, %s, float> (FP32 weighted-Jacobi sweep, finest level)"

@@ -361,7 +361,8 @@ mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const d
  * first step is h0 when h0 > 0, otherwise it is chosen from the first two right-hand sides by
  * Hairer, Norsett and Wanner's starting-step rule.  A step that would pass within 1% of a save
  * time or of t_end is cut to land on it.  fixed_step = 1 takes steps of h0 without error
- * control.  The pressure solves start from zero. */
+ * control.  The first pressure solve starts from zero, every later one from the previous
+ * right-hand side's pressure. */
 typedef struct {
   porous_params model;  /* model.dt is not read */
   double t_end;         /* > 0 */

@@ -80,6 +80,7 @@ struct Integrator {
   std::vector<std::unique_ptr<DevBuf>> kb;
   double* kv[7];
   HostScalar hs;
+  bool warm = false;   // later pressure solves start from the previous one's result
 
   Integrator(Hierarchy& H_, const porous_rk_opts& o_, hipStream_t s_)
       : H(H_), o(o_), prm(porous_params_of(o_.model)), s(s_), n(H_.lv.back()->n), y(n + 1),
@@ -96,7 +97,8 @@ struct Integrator {
     PorousData& D = H.por;
     k::por_rhs(F, D, yin, H.sb, s);
     mg_result r{};
-    const int code = run_pcg(H, prm.solve, nullptr, nullptr, &r, s);
+    const int code = run_pcg(H, prm.solve, nullptr, nullptr, &r, s, warm);
+    warm = true;
     k::por_update(F, D, yin, H.sx, kout, 1.0, prm.phi, prm.kappa(), false, s);
     st.rhs_evals += 1;
     st.pressure_iterations += r.iterations;

@@ -411,17 +411,21 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
 }
 
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
-            hipStream_t s) {
+            hipStream_t s, bool warm_start) {
   HostTimer T;
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   init_scalars(H, o, s);
   setup_rhs(H, b_nat, s);
-  k::fill<double>(H.sx, n, 0.0, s);
   k::fill<double>(H.sp, n, 0.0, s);
   k::fill<double>(H.sq, n, 0.0, s);
-  check_hip(hipMemcpyAsync(H.sr, H.sb, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
-            "hipMemcpyAsync");
+  if (warm_start && !b_nat) {
+    k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
+  } else {
+    k::fill<double>(H.sx, n, 0.0, s);
+    check_hip(hipMemcpyAsync(H.sr, H.sb, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
+              "hipMemcpyAsync");
+  }
   if (o.precision == MG_F32) k::to_f32(n, H.scal, H.sr, F.v32.b, nullptr, s);
   T.mark("setup");
   hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 0) : nullptr;

@@ -18,8 +18,10 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o);
 // Levels over given meshes whose interpolation rows are already set (set_interp_from_geomap).
 Hierarchy* build_hierarchy_maps(std::vector<Mesh> meshes, bool nested_ids, const mg_hier_opts& o);
 void upload_weights(Hierarchy& H);
+// warm_start (internal right-hand side only, b_nat == nullptr): start from the iterate left in
+// H.sx by the previous solve instead of zero.
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
-            hipStream_t s);
+            hipStream_t s, bool warm_start = false);
 int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
            hipStream_t s);
 

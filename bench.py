@@ -38,6 +38,10 @@ def parse():
     p.add_argument("--order", choices=["stripes", "morton"], default="stripes")
     p.add_argument("--no-porous", action="store_true",
                    help="skip the porous-convection rollout and gradient timing")
+    p.add_argument("--no-variants", action="store_true",
+                   help="skip the W/F-cycle, Gauss-Seidel and CG-smoothing timings")
+    p.add_argument("--only", choices=["e4", "cubic"], default=None,
+                   help="run only one secondary workload and print its record (for profiling)")
     p.add_argument("--no-e4", action="store_true",
                    help="skip the adaptive porous-convection run to t = 0.5")
     p.add_argument("--no-cubic", action="store_true",
@@ -355,6 +359,11 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if a.only:
+        rec = e4_bench(mg, W, torch, np) if a.only == "e4" else cubic_bench(mg, W, torch, np,
+                                                                           max(3, a.steps // 2))
+        print(json.dumps({"only": a.only, **rec}))
+        return
     t0 = time.perf_counter()
     order = mg.MG_ORDER_MORTON if a.order == "morton" else mg.MG_ORDER_STRIPES
     H = mg.Hierarchy("square", W.C3["nsub"], base_cells=W.C3["base_cells"], order=order)
@@ -401,7 +410,7 @@ def main():
 
     # the other cycle shapes with the same mixed-precision FCG (C3, timed like the headline)
     variants = {}
-    for vname, cyc, smo in (("mixed_W_cycle", mg.MG_CYCLE_W, mg.MG_SMOOTH_JACOBI),
+    for vname, cyc, smo in () if a.no_variants else (("mixed_W_cycle", mg.MG_CYCLE_W, mg.MG_SMOOTH_JACOBI),
                             ("mixed_F_cycle", mg.MG_CYCLE_F, mg.MG_SMOOTH_JACOBI),
                             ("mixed_V_gauss_seidel", mg.MG_CYCLE_V, mg.MG_SMOOTH_GS),
                             ("mixed_W_gauss_seidel", mg.MG_CYCLE_W, mg.MG_SMOOTH_GS),
@@ -458,9 +467,9 @@ def main():
         ms_w32 = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, mg.MG_F32, a.kernel_reps)
         ms_j64 = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, mg.MG_F64, a.kernel_reps)
         ms_a64 = mg.mg_time_kernel(H.h, mg.KERNEL_APPLY, top, mg.MG_F64, a.kernel_reps)
-        others = {"isolated_warm_jacobi_f32": {"GB/s": gbs(by_j32, ms_w32), "ms": ms_w32},
+        others.update({"isolated_warm_jacobi_f32": {"GB/s": gbs(by_j32, ms_w32), "ms": ms_w32},
                   "isolated_warm_jacobi_f64": {"GB/s": gbs(by_j64, ms_j64), "ms": ms_j64, "bytes": by_j64},
-                  "isolated_warm_apply_f64": {"GB/s": gbs(by_a64, ms_a64), "ms": ms_a64, "bytes": by_a64}}
+                  "isolated_warm_apply_f64": {"GB/s": gbs(by_a64, ms_a64), "ms": ms_a64, "bytes": by_a64}})
 
     out = {
         "metric": "MG solve DOF/s to 1e-10 rel residual: FP32-precond+FP64-refine vs FP64",

@@ -84,6 +84,7 @@ constexpr int32_t kCoarseFuseRows = 2048;
 template <typename T>
 struct CoarseLevel {
   int32_t n = 0, lds = 0;            // unknowns; offset (in T) of x, partner, b in LDS
+  int32_t uw = -1, r_uw = -1;        // uniform slice widths of operator / restriction, or -1
   int32_t nslices = 0, r_nslices = 0;
   int32_t lds_sptr = 0, lds_rsptr = 0;  // offsets (in int32) of the preloaded slice bounds
   const int32_t* sptr = nullptr;
@@ -197,6 +198,8 @@ struct Hierarchy {
   // fused coarse cycle: highest level handled by one workgroup, per precision (-1 = none)
   int ctop64 = -1, ctop32 = -1;
   int coarse_width = 0;   // widest operator slice among the levels of the fused cycle
+  int coarse_rwidth = 0;  // widest restriction slice among them
+  int coarse_rows = 0;    // most unknowns on one of them
   // LDS layout of the fused cycle per precision: vectors, then (8-byte aligned) the dense
   // coarsest inverse, then the slice bounds of every fused level
   size_t cvec64 = 0, cvec32 = 0;        // bytes of the vector region up to each ctop

@@ -564,6 +564,16 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
     ctop = l;
     for (int32_t s = 0; s < L.op.nslices; ++s)
       H.coarse_width = std::max(H.coarse_width, L.sptr_h[s + 1] - L.sptr_h[s]);
+    H.coarse_rows = std::max(H.coarse_rows, L.n);
+    c.uw = L.op.uw;
+    if (l >= 1) {
+      c.r_uw = L.tr.r_uw;
+      std::vector<int32_t> rs(L.tr.nslices + 1);
+      check_hip(hipMemcpy(rs.data(), L.tr.r_sptr, rs.size() * sizeof(int32_t),
+                          hipMemcpyDeviceToHost), "hipMemcpy");
+      for (int32_t s = 0; s < L.tr.nslices; ++s)
+        H.coarse_rwidth = std::max(H.coarse_rwidth, rs[s + 1] - rs[s]);
+    }
   }
   if (ctop < 1) ctop = -1;
   dev = upload(hv);

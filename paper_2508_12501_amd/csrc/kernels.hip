@@ -799,6 +799,145 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
   for (int i = threadIdx.x; i < L.n; i += blockDim.x) x_out[i] = xs[i];
 }
 
+// The same coarse end of the cycle when every fused level has at most one row per thread,
+// operator and restriction rows of at most K and 8 entries, and NL levels above the coarsest
+// (NL = top, 1..4).  Thread t owns row t of every level: it loads all of that row's index,
+// weight, diagonal and transfer data into registers before the first barrier, so the phases
+// that follow touch only registers and LDS.  A single workgroup lands on a different XCD from
+// one launch to the next, so its L2 is cold: issuing every global load at once replaces a
+// round trip per phase by one in total.  The arithmetic, entry order and padding conventions
+// are those of k_coarse_cycle.
+template <typename T, int K, int NL>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
+    const CoarseLevel<T>* __restrict__ lv, const double* __restrict__ ainv, int32_t n0,
+    int32_t inv_off, const T* __restrict__ b_in, T* __restrict__ x_out, T omega, int nu1,
+    int nu2, const int* __restrict__ done) {
+  constexpr int RW = 8;
+  if (done && *done) return;
+  extern __shared__ double smem_d[];
+  T* sm = reinterpret_cast<T*>(smem_d);
+  double* sinv = smem_d + inv_off / 8;
+  const int t = threadIdx.x;
+  int cj[NL + 1][K], rc[NL + 1][RW], pa[NL + 1], pb[NL + 1], rs[NL + 1], rwid[NL + 1];
+  T wv[NL + 1][K], dg[NL + 1];
+#pragma unroll
+  for (int l = 1; l <= NL; ++l) {
+    const CoarseLevel<T>& L = lv[l];
+    const int row = min(t, L.n - 1);
+    const int sl = row >> 6, lane = row & 63;
+    const int beg = L.uw >= 0 ? sl * L.uw : L.sptr[sl];
+    const int wid = L.uw >= 0 ? L.uw : L.sptr[sl + 1] - beg;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int idx = (beg + min(k, max(wid - 1, 0))) * kSlice + lane;
+      cj[l][k] = L.col[idx];
+      const T w = L.w[idx];
+      wv[l][k] = (k < wid) ? w : T(0);
+    }
+    dg[l] = L.diag[row];
+    pa[l] = L.pa[row];
+    pb[l] = L.pb[row];
+    const int crow = min(t, lv[l - 1].n - 1);
+    const int rsl = crow >> 6, rlane = crow & 63;
+    const int rbeg = L.r_uw >= 0 ? rsl * L.r_uw : L.r_sptr[rsl];
+    rwid[l] = L.r_uw >= 0 ? L.r_uw : L.r_sptr[rsl + 1] - rbeg;
+    rs[l] = L.r_self[crow];
+#pragma unroll
+    for (int k = 0; k < RW; ++k)
+      rc[l][k] = L.r_col[(rbeg + min(k, max(rwid[l] - 1, 0))) * kSlice + rlane];
+  }
+  const int total = lv[NL].lds + 3 * (lv[NL].n + 1);
+  for (int i = t; i < total; i += blockDim.x) sm[i] = T(0);
+  for (int i = t; i < n0 * n0; i += blockDim.x) sinv[i] = ainv[i];
+  __syncthreads();
+  if (t < lv[NL].n) sm[lv[NL].lds + 2 * (lv[NL].n + 1) + t] = b_in[t];
+  __syncthreads();
+  auto sweep = [&](int l, int n, const T* cx, const T* B, T* out, int mode) {
+    if (t < n) {
+      const T xi = cx[t];
+      T acc = T(0), d = T(0);
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        d += wv[l][k];
+        acc += wv[l][k] * (xi - cx[cj[l][k]]);
+      }
+      out[t] = (mode == 2) ? xi + omega * (B[t] - acc) / d : B[t] - acc;
+    }
+  };
+  unsigned in_t = 0;
+#pragma unroll
+  for (int l = NL; l >= 1; --l) {
+    const int n = lv[l].n;
+    T* X = sm + lv[l].lds;
+    T* Tt = X + (n + 1);
+    T* B = Tt + (n + 1);
+    T* cx = X;
+    T* ox = Tt;
+    if (nu1 > 0) {
+      if (t < n) cx[t] = omega * B[t] / dg[l];
+      __syncthreads();
+      for (int it = 1; it < nu1; ++it) {
+        sweep(l, n, cx, B, ox, 2);
+        __syncthreads();
+        T* tmp = cx;
+        cx = ox;
+        ox = tmp;
+      }
+    } else {
+      if (t < n) cx[t] = T(0);
+      __syncthreads();
+    }
+    sweep(l, n, cx, B, ox, 1);
+    __syncthreads();
+    const int nc = lv[l - 1].n;
+    if (t < nc) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < RW; ++k)
+        if (k < rwid[l]) acc += ox[rc[l][k]];
+      sm[lv[l - 1].lds + 2 * (nc + 1) + t] = ox[rs[l]] + T(0.5) * acc;
+    }
+    __syncthreads();
+    if (cx == Tt) in_t |= 1u << l;
+  }
+  {
+    T* X0 = sm + lv[0].lds;
+    const T* B0 = X0 + 2 * (lv[0].n + 1);
+    for (int i = t; i < n0; i += blockDim.x) {
+      const double* a = sinv + static_cast<int64_t>(i) * n0;
+      double acc = 0.0;
+      for (int j = 0; j < n0; ++j) acc += a[j] * static_cast<double>(B0[j]);
+      X0[i] = static_cast<T>(acc);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int l = 1; l <= NL; ++l) {
+    const int n = lv[l].n, nc = lv[l - 1].n;
+    T* X = sm + lv[l].lds;
+    T* Tt = X + (n + 1);
+    T* B = Tt + (n + 1);
+    T* cx = (in_t >> l & 1u) ? Tt : X;
+    T* ox = (cx == X) ? Tt : X;
+    const T* ec = sm + lv[l - 1].lds + ((in_t >> (l - 1) & 1u) ? (nc + 1) : 0);
+    if (t < n) cx[t] += T(0.5) * (ec[pa[l]] + ec[pb[l]]);
+    __syncthreads();
+    for (int it = 0; it < nu2; ++it) {
+      sweep(l, n, cx, B, ox, 2);
+      __syncthreads();
+      T* tmp = cx;
+      cx = ox;
+      ox = tmp;
+    }
+    if (cx == Tt)
+      in_t |= 1u << l;
+    else
+      in_t &= ~(1u << l);
+  }
+  const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
+  if (t < lv[NL].n) x_out[t] = xs[t];
+}
+
 template <typename T>
 __global__ void k_fill(T* __restrict__ p, int64_t n, T v) {
   const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1489,12 +1628,55 @@ void prepare_coarse(const Hierarchy& H) {
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 4>), b32);
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 8>), b32);
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 0>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 3>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 4>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 3>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 4>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 3>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 4>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 3>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 4>), b32);
+}
+
+template <typename T, int K, int NL>
+static void launch_coarse_cycle_reg(const Hierarchy& H, const T* b, T* x, double omega, int nu1,
+                                    int nu2, const int* done, hipStream_t s) {
+  const size_t bytes = coarse_lds_bytes<T>(H);
+  const size_t int_off = coarse_int_offset<T>(H);
+  const size_t inv_off = int_off - size_t(H.n0) * H.n0 * sizeof(double);
+  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL>), dim3(1), dim3(kCoarseThreads), bytes, s,
+                     coarse_levels<T>(H), H.coarse_inv, H.n0, int32_t(inv_off), b, x,
+                     static_cast<T>(omega), nu1, nu2, done);
+}
+template <typename T, int K>
+static bool coarse_cycle_reg(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1,
+                             int nu2, const int* done, hipStream_t s) {
+  switch (top) {
+    case 1: launch_coarse_cycle_reg<T, K, 1>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 2: launch_coarse_cycle_reg<T, K, 2>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 3: launch_coarse_cycle_reg<T, K, 3>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 4: launch_coarse_cycle_reg<T, K, 4>(H, b, x, omega, nu1, nu2, done, s); return true;
+    default: return false;
+  }
 }
 
 template <typename T>
 void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2,
                   const int* done, hipStream_t s) {
   const int kmax = H.coarse_width;
+  if (H.coarse_rows <= kCoarseThreads && H.coarse_rwidth <= 8 && kmax <= 8) {
+    if (kmax <= 4 ? coarse_cycle_reg<T, 4>(H, top, b, x, omega, nu1, nu2, done, s)
+                  : coarse_cycle_reg<T, 8>(H, top, b, x, omega, nu1, nu2, done, s))
+      return;
+  }
   if (kmax <= 4)
     launch_coarse_cycle<T, 4>(H, top, b, x, omega, nu1, nu2, done, s);
   else if (kmax <= 8)

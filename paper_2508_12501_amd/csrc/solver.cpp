@@ -68,6 +68,17 @@ static T* coarse_correction(Hierarchy& H, int l, const T* bc, const mg_opts& o, 
 }
 
 // `steps` steps of the CG smoother on level l, in place on x (r, p, q in the level's r, t, u).
+// b_c = M(f) (b - A x) as two passes (residual into V.r, then the restriction).  A fused
+// coarse-row-centric pass was measured slower even on launch-bound levels: each coarse row
+// walks up to seven fine rows, and the dependent index, operator and gather loads of each
+// take a fabric round trip in turn (about 17 us against 2 x 4.6 us).
+template <typename T>
+static void restrict_residual(Level& L, Level& C, LevelVecs<T>& V, const T* x, const T* b,
+                              const int* done, hipStream_t s) {
+  k::residual<T>(L, x, b, V.r, done, s);
+  k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+}
+
 template <typename T>
 static void cg_smooth(Hierarchy& H, int l, T* x, const T* b, int steps, const int* done,
                       hipStream_t s) {
@@ -100,8 +111,7 @@ static T* cg_cycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o,
   if (!x_init) k::fill<T>(cur, L.n, T(0), s);
   cg_smooth<T>(H, l, cur, b, o.nu1, done, s);
   Level& C = *H.lv[l - 1];
-  k::residual<T>(L, cur, b, V.r, done, s);
-  k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+  restrict_residual<T>(L, C, V, cur, b, done, s);
   T* ec = coarse_correction<T>(H, l, vecs<T>(C).b, o, kind, done, s);
   k::prolong<T>(L, C, ec, cur, done, s);
   cg_smooth<T>(H, l, cur, b, o.nu2, done, s);
@@ -137,8 +147,7 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
     for (int it = 0; it < o.nu1; ++it)
       for (int c = 0; c < nc; ++c) k::gs_color<T>(L, c, cur, b, done, s);
     Level& C = *H.lv[l - 1];
-    k::residual<T>(L, cur, b, V.r, done, s);
-    k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+    restrict_residual<T>(L, C, V, cur, b, done, s);
     const T* bc = vecs<T>(C).b;
     T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
     k::prolong<T>(L, C, ec, cur, done, s);
@@ -167,8 +176,7 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
     std::swap(cur, oth);
   }
   Level& C = *H.lv[l - 1];
-  k::residual<T>(L, cur, b, V.r, done, s);
-  k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
+  restrict_residual<T>(L, C, V, cur, b, done, s);
   const T* bc = vecs<T>(C).b;
   T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
   int post = o.nu2;

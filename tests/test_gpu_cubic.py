@@ -211,3 +211,33 @@ def test_cubic_mask_beyond_levels_rejected():
     with pytest.raises(mg.MGError) as e:
         mg.Hierarchy("square", 2, cubic_mask=0b100)
     assert e.value.status == mg.MG_EINVAL
+
+
+def test_e1_fullsize_cycles():
+    """The paper's largest V-cycle mesh: 4 cubic subdivisions of the 32-triangle square
+    (325 x 325 = 105,625 vertices), b = L r with r ~ U[0,1) (zero on the boundary).  One V-cycle with three CG
+    smoothing steps and one with Jacobi(2,2), each from x = 0, element by element against the
+    oracle, and FP64 MG-PCG at the oracle's iteration count."""
+    xyz, tri = dec.square_grid(4)
+    print("[cubic] building the 105,625-vertex cubic hierarchy", flush=True)
+    g = mg.Hierarchy("square", 4, base_cells=4, cubic_mask=0b1111)
+    o = omg.Hierarchy(xyz, tri, 4, schemes="cccc")
+    assert o.fine.nv == 105625 == g.nv()
+    r = W.uniform01(o.fine.nv, W.SEED_E1)
+    b = o.fine.A @ r
+    b[o.fine.bnd] = 0.0     # zero Dirichlet data: the library's iterates then equal the oracle's
+    for smoother, nu, code in (("cg", 3, mg.MG_SMOOTH_CG), ("jacobi", 2, mg.MG_SMOOTH_JACOBI)):
+        opts = mg.mg_opts_default(smoother=code)
+        opts.nu1 = opts.nu2 = nu
+        ref = omg.mgcycle(o, b, np.zeros(o.fine.nv), o.top, "V", nu1=nu, nu2=nu,
+                          smoother=smoother)
+        x = torch.zeros(o.fine.nv, dtype=torch.float64, device=DEV)
+        mg.mg_vcycle(g.h, opts, g.top, gpu(b), x)
+        e = rel(host(x), ref)
+        print(f"[cubic] E1 V-cycle ({smoother}, {nu}): rel L2 vs oracle {e:.2e}")
+        assert e <= 1e-12
+    xo, ko, _ = omg.mg_pcg(o, b)
+    x = torch.zeros(o.fine.nv, dtype=torch.float64, device=DEV)
+    res = mg.mg_pcg(g.h, mg.mg_opts_default(), gpu(b), x)
+    assert res.iterations == ko and rel(host(x), xo) <= 1e-12
+    g.close()

@@ -799,15 +799,16 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
   for (int i = threadIdx.x; i < L.n; i += blockDim.x) x_out[i] = xs[i];
 }
 
-// The same coarse end of the cycle when every fused level has at most one row per thread,
-// operator and restriction rows of at most K and 8 entries, and NL levels above the coarsest
-// (NL = top, 1..4).  Thread t owns row t of every level: it loads all of that row's index,
-// weight, diagonal and transfer data into registers before the first barrier, so the phases
-// that follow touch only registers and LDS.  A single workgroup lands on a different XCD from
-// one launch to the next, so its L2 is cold: issuing every global load at once replaces a
-// round trip per phase by one in total.  The arithmetic, entry order and padding conventions
-// are those of k_coarse_cycle.
-template <typename T, int K, int NL>
+// The same coarse end of the cycle when the levels below the top have at most one row per
+// thread and the top level at most RPT (1 or 2), operator and restriction rows have at most K
+// and 8 entries, and NL levels lie above the coarsest (NL = top, 1..4).  Thread t owns row t of
+// every level (and row t + blockDim of the top one): it loads all of their index, weight,
+// diagonal and transfer data into registers before the first barrier, so the phases that
+// follow touch only registers and LDS.  A single workgroup lands on a different XCD from one
+// launch to the next, so its L2 is cold: issuing every global load at once replaces a round
+// trip per phase by one in total.  The arithmetic, entry order and padding conventions are
+// those of k_coarse_cycle.
+template <typename T, int K, int NL, int RPT>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
     const CoarseLevel<T>* __restrict__ lv, const double* __restrict__ ainv, int32_t n0,
     int32_t inv_off, const T* __restrict__ b_in, T* __restrict__ x_out, T omega, int nu1,
@@ -817,26 +818,34 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
   extern __shared__ double smem_d[];
   T* sm = reinterpret_cast<T*>(smem_d);
   double* sinv = smem_d + inv_off / 8;
-  const int t = threadIdx.x;
-  int cj[NL + 1][K], rc[NL + 1][RW], pa[NL + 1], pb[NL + 1], rs[NL + 1], rwid[NL + 1];
-  T wv[NL + 1][K], dg[NL + 1];
+  const int t = threadIdx.x, nt = blockDim.x;
+  // operator rows: RPT on the top level, one below it; restriction rows (into level l - 1,
+  // never the top level): one
+  int cj[NL + 1][RPT][K], pa[NL + 1][RPT], pb[NL + 1][RPT];
+  int rc[NL + 1][RW], rs[NL + 1], rwid[NL + 1];
+  T wv[NL + 1][RPT][K], dg[NL + 1][RPT];
 #pragma unroll
   for (int l = 1; l <= NL; ++l) {
     const CoarseLevel<T>& L = lv[l];
-    const int row = min(t, L.n - 1);
-    const int sl = row >> 6, lane = row & 63;
-    const int beg = L.uw >= 0 ? sl * L.uw : L.sptr[sl];
-    const int wid = L.uw >= 0 ? L.uw : L.sptr[sl + 1] - beg;
+    const int nq = (l == NL) ? RPT : 1;
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int idx = (beg + min(k, max(wid - 1, 0))) * kSlice + lane;
-      cj[l][k] = L.col[idx];
-      const T w = L.w[idx];
-      wv[l][k] = (k < wid) ? w : T(0);
+    for (int q = 0; q < RPT; ++q) {
+      if (q >= nq) break;
+      const int row = min(t + q * nt, L.n - 1);
+      const int sl = row >> 6, lane = row & 63;
+      const int beg = L.uw >= 0 ? sl * L.uw : L.sptr[sl];
+      const int wid = L.uw >= 0 ? L.uw : L.sptr[sl + 1] - beg;
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int idx = (beg + min(k, max(wid - 1, 0))) * kSlice + lane;
+        cj[l][q][k] = L.col[idx];
+        const T w = L.w[idx];
+        wv[l][q][k] = (k < wid) ? w : T(0);
+      }
+      dg[l][q] = L.diag[row];
+      pa[l][q] = L.pa[row];
+      pb[l][q] = L.pb[row];
     }
-    dg[l] = L.diag[row];
-    pa[l] = L.pa[row];
-    pb[l] = L.pb[row];
     const int crow = min(t, lv[l - 1].n - 1);
     const int rsl = crow >> 6, rlane = crow & 63;
     const int rbeg = L.r_uw >= 0 ? rsl * L.r_uw : L.r_sptr[rsl];
@@ -847,34 +856,42 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
       rc[l][k] = L.r_col[(rbeg + min(k, max(rwid[l] - 1, 0))) * kSlice + rlane];
   }
   const int total = lv[NL].lds + 3 * (lv[NL].n + 1);
-  for (int i = t; i < total; i += blockDim.x) sm[i] = T(0);
-  for (int i = t; i < n0 * n0; i += blockDim.x) sinv[i] = ainv[i];
+  for (int i = t; i < total; i += nt) sm[i] = T(0);
+  for (int i = t; i < n0 * n0; i += nt) sinv[i] = ainv[i];
   __syncthreads();
-  if (t < lv[NL].n) sm[lv[NL].lds + 2 * (lv[NL].n + 1) + t] = b_in[t];
+  for (int i = t; i < lv[NL].n; i += nt) sm[lv[NL].lds + 2 * (lv[NL].n + 1) + i] = b_in[i];
   __syncthreads();
   auto sweep = [&](int l, int n, const T* cx, const T* B, T* out, int mode) {
-    if (t < n) {
-      const T xi = cx[t];
-      T acc = T(0), d = T(0);
+    const int nq = (l == NL) ? RPT : 1;
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
-        d += wv[l][k];
-        acc += wv[l][k] * (xi - cx[cj[l][k]]);
+    for (int q = 0; q < RPT; ++q) {
+      const int r = t + q * nt;
+      if (q < nq && r < n) {
+        const T xi = cx[r];
+        T acc = T(0), d = T(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          d += wv[l][q][k];
+          acc += wv[l][q][k] * (xi - cx[cj[l][q][k]]);
+        }
+        out[r] = (mode == 2) ? xi + omega * (B[r] - acc) / d : B[r] - acc;
       }
-      out[t] = (mode == 2) ? xi + omega * (B[t] - acc) / d : B[t] - acc;
     }
   };
   unsigned in_t = 0;
 #pragma unroll
   for (int l = NL; l >= 1; --l) {
     const int n = lv[l].n;
+    const int nq = (l == NL) ? RPT : 1;
     T* X = sm + lv[l].lds;
     T* Tt = X + (n + 1);
     T* B = Tt + (n + 1);
     T* cx = X;
     T* ox = Tt;
     if (nu1 > 0) {
-      if (t < n) cx[t] = omega * B[t] / dg[l];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q)
+        if (q < nq && t + q * nt < n) cx[t + q * nt] = omega * B[t + q * nt] / dg[l][q];
       __syncthreads();
       for (int it = 1; it < nu1; ++it) {
         sweep(l, n, cx, B, ox, 2);
@@ -884,7 +901,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
         ox = tmp;
       }
     } else {
-      if (t < n) cx[t] = T(0);
+      for (int i = t; i < n; i += nt) cx[i] = T(0);
       __syncthreads();
     }
     sweep(l, n, cx, B, ox, 1);
@@ -903,7 +920,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
   {
     T* X0 = sm + lv[0].lds;
     const T* B0 = X0 + 2 * (lv[0].n + 1);
-    for (int i = t; i < n0; i += blockDim.x) {
+    for (int i = t; i < n0; i += nt) {
       const double* a = sinv + static_cast<int64_t>(i) * n0;
       double acc = 0.0;
       for (int j = 0; j < n0; ++j) acc += a[j] * static_cast<double>(B0[j]);
@@ -914,13 +931,16 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
 #pragma unroll
   for (int l = 1; l <= NL; ++l) {
     const int n = lv[l].n, nc = lv[l - 1].n;
+    const int nq = (l == NL) ? RPT : 1;
     T* X = sm + lv[l].lds;
     T* Tt = X + (n + 1);
     T* B = Tt + (n + 1);
     T* cx = (in_t >> l & 1u) ? Tt : X;
     T* ox = (cx == X) ? Tt : X;
     const T* ec = sm + lv[l - 1].lds + ((in_t >> (l - 1) & 1u) ? (nc + 1) : 0);
-    if (t < n) cx[t] += T(0.5) * (ec[pa[l]] + ec[pb[l]]);
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+      if (q < nq && t + q * nt < n) cx[t + q * nt] += T(0.5) * (ec[pa[l][q]] + ec[pb[l][q]]);
     __syncthreads();
     for (int it = 0; it < nu2; ++it) {
       sweep(l, n, cx, B, ox, 2);
@@ -935,7 +955,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
       in_t &= ~(1u << l);
   }
   const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
-  if (t < lv[NL].n) x_out[t] = xs[t];
+  for (int i = t; i < lv[NL].n; i += nt) x_out[i] = xs[i];
 }
 
 template <typename T>
@@ -1628,42 +1648,58 @@ void prepare_coarse(const Hierarchy& H) {
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 4>), b32);
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 8>), b32);
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 0>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 3>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 4>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 3>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 4>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 3>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 4>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 3>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 4>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 1, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 1, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 2, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 2, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 3, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 3, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 4, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 4, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 1, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 1, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 2, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 2, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 3, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 3, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 4, 1>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 4, 2>), b64);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 1, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 1, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 2, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 2, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 3, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 3, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 4, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 4, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 1, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 1, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 2, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 2, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 3, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 3, 2>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 4, 1>), b32);
+  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 4, 2>), b32);
 }
 
-template <typename T, int K, int NL>
+template <typename T, int K, int NL, int RPT>
 static void launch_coarse_cycle_reg(const Hierarchy& H, const T* b, T* x, double omega, int nu1,
                                     int nu2, const int* done, hipStream_t s) {
   const size_t bytes = coarse_lds_bytes<T>(H);
   const size_t int_off = coarse_int_offset<T>(H);
   const size_t inv_off = int_off - size_t(H.n0) * H.n0 * sizeof(double);
-  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL>), dim3(1), dim3(kCoarseThreads), bytes, s,
+  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL, RPT>), dim3(1), dim3(kCoarseThreads), bytes, s,
                      coarse_levels<T>(H), H.coarse_inv, H.n0, int32_t(inv_off), b, x,
                      static_cast<T>(omega), nu1, nu2, done);
 }
-template <typename T, int K>
+template <typename T, int K, int RPT>
 static bool coarse_cycle_reg(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1,
                              int nu2, const int* done, hipStream_t s) {
   switch (top) {
-    case 1: launch_coarse_cycle_reg<T, K, 1>(H, b, x, omega, nu1, nu2, done, s); return true;
-    case 2: launch_coarse_cycle_reg<T, K, 2>(H, b, x, omega, nu1, nu2, done, s); return true;
-    case 3: launch_coarse_cycle_reg<T, K, 3>(H, b, x, omega, nu1, nu2, done, s); return true;
-    case 4: launch_coarse_cycle_reg<T, K, 4>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 1: launch_coarse_cycle_reg<T, K, 1, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 2: launch_coarse_cycle_reg<T, K, 2, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 3: launch_coarse_cycle_reg<T, K, 3, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
+    case 4: launch_coarse_cycle_reg<T, K, 4, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
     default: return false;
   }
 }
@@ -1672,10 +1708,21 @@ template <typename T>
 void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2,
                   const int* done, hipStream_t s) {
   const int kmax = H.coarse_width;
-  if (H.coarse_rows <= kCoarseThreads && H.coarse_rwidth <= 8 && kmax <= 8) {
-    if (kmax <= 4 ? coarse_cycle_reg<T, 4>(H, top, b, x, omega, nu1, nu2, done, s)
-                  : coarse_cycle_reg<T, 8>(H, top, b, x, omega, nu1, nu2, done, s))
-      return;
+  // levels below `top` must have at most one row per thread, `top` itself at most two
+  int below = 0;
+  for (int l = 0; l < top; ++l) below = std::max(below, H.lv[l]->n);
+  const int at_top = H.lv[top]->n;
+  if (below <= kCoarseThreads && at_top <= 2 * kCoarseThreads && H.coarse_rwidth <= 8 &&
+      kmax <= 8) {
+    const bool one = at_top <= kCoarseThreads;
+    bool ok;
+    if (kmax <= 4)
+      ok = one ? coarse_cycle_reg<T, 4, 1>(H, top, b, x, omega, nu1, nu2, done, s)
+               : coarse_cycle_reg<T, 4, 2>(H, top, b, x, omega, nu1, nu2, done, s);
+    else
+      ok = one ? coarse_cycle_reg<T, 8, 1>(H, top, b, x, omega, nu1, nu2, done, s)
+               : coarse_cycle_reg<T, 8, 2>(H, top, b, x, omega, nu1, nu2, done, s);
+    if (ok) return;
   }
   if (kmax <= 4)
     launch_coarse_cycle<T, 4>(H, top, b, x, omega, nu1, nu2, done, s);

@@ -361,8 +361,9 @@ mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const d
  * first step is h0 when h0 > 0, otherwise it is chosen from the first two right-hand sides by
  * Hairer, Norsett and Wanner's starting-step rule.  A step that would pass within 1% of a save
  * time or of t_end is cut to land on it.  fixed_step = 1 takes steps of h0 without error
- * control.  The first pressure solve starts from zero, every later one from the previous
- * right-hand side's pressure. */
+ * control.  The first pressure solve starts from zero, the second from the first's result,
+ * every later one from the linear extrapolation in time of the last two pressures (the
+ * extrapolation factor clamped to [-2, 2]). */
 typedef struct {
   porous_params model;  /* model.dt is not read */
   double t_end;         /* > 0 */

@@ -30,6 +30,7 @@ constexpr double A[7][6] = {
     {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
 constexpr double B4[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
                           187.0 / 2100, 1.0 / 40};
+constexpr double C[7] = {0, 1.0 / 5, 3.0 / 10, 4.0 / 5, 8.0 / 9, 1, 1};   // stage times / h
 
 constexpr double kSafety = 0.9, kFacMin = 0.2, kFacMax = 10.0;
 
@@ -76,29 +77,46 @@ struct Integrator {
   hipStream_t s;
   int32_t n;
   porous_rk_stats st{};
-  DevBuf y, yn, ys, dscal, part;
+  DevBuf y, yn, ys, dscal, part, p0, p1;
   std::vector<std::unique_ptr<DevBuf>> kb;
   double* kv[7];
   HostScalar hs;
-  bool warm = false;   // later pressure solves start from the previous one's result
+  // Initial guesses of the pressure solves: the first starts from zero, the second from the
+  // first's result, every later one from the linear extrapolation in time of the last two
+  // pressures (p1 at time t1, p0 at t0) to the time of the new right-hand side.
+  int npres = 0;
+  double t0p = 0.0, t1p = 0.0;
 
   Integrator(Hierarchy& H_, const porous_rk_opts& o_, hipStream_t s_)
       : H(H_), o(o_), prm(porous_params_of(o_.model)), s(s_), n(H_.lv.back()->n), y(n + 1),
-        yn(n + 1), ys(n + 1), dscal(1), part(k::rk_parts(H_.lv.back()->n)) {
+        yn(n + 1), ys(n + 1), dscal(1), part(k::rk_parts(H_.lv.back()->n)), p0(n + 1),
+        p1(n + 1) {
     for (int j = 0; j < 7; ++j) {
       kb.emplace_back(std::make_unique<DevBuf>(n + 1));
       kv[j] = kb.back()->p;
     }
   }
 
-  // kout = rhs(yin); returns the pressure solve's status
-  int rhs(const double* yin, double* kout) {
+  // kout = rhs(yin) for the state at time t_eval; returns the pressure solve's status
+  int rhs(const double* yin, double* kout, double t_eval) {
     Level& F = *H.lv.back();
     PorousData& D = H.por;
     k::por_rhs(F, D, yin, H.sb, s);
+    if (npres >= 2 && t1p != t0p) {
+      const double theta = std::min(2.0, std::max(-2.0, (t_eval - t1p) / (t1p - t0p)));
+      k::rk_axpy(p1.p, terms({{p1.p, 1.0}, {p0.p, -1.0}}), theta, H.sx, n, s);
+    } else if (npres == 1) {
+      check_hip(hipMemcpyAsync(H.sx, p1.p, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
+                "hipMemcpyAsync");
+    }
     mg_result r{};
-    const int code = run_pcg(H, prm.solve, nullptr, nullptr, &r, s, warm);
-    warm = true;
+    const int code = run_pcg(H, prm.solve, nullptr, nullptr, &r, s, npres >= 1);
+    std::swap(p0.p, p1.p);
+    check_hip(hipMemcpyAsync(p1.p, H.sx, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
+              "hipMemcpyAsync");
+    t0p = t1p;
+    t1p = t_eval;
+    npres = std::min(npres + 1, 2);
     k::por_update(F, D, yin, H.sx, kout, 1.0, prm.phi, prm.kappa(), false, s);
     st.rhs_evals += 1;
     st.pressure_iterations += r.iterations;
@@ -124,7 +142,7 @@ struct Integrator {
     double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
     h0 = std::min(h0, o.t_end);
     k::rk_axpy(y.p, terms({{kv[0], 1.0}}), h0, ys.p, n, s);
-    if (int code = rhs(ys.p, kv[1]); code != MG_OK) return code;
+    if (int code = rhs(ys.p, kv[1], h0); code != MG_OK) return code;
     const double d2 = wrms(terms({{kv[1], 1.0}, {kv[0], -1.0}}), 1.0 / h0, y.p, y.p);
     const double dm = std::max(d1, d2);
     const double h1 = dm <= 1e-15 ? std::max(1e-6, h0 * 1e-3) : std::pow(0.01 / dm, 1.0 / 5.0);
@@ -132,16 +150,16 @@ struct Integrator {
     return MG_OK;
   }
 
-  // stages 2..7 of a step of size h from (y, kv[0]); the new solution lands in yn, its
-  // right-hand side in kv[6]
-  int stages(double h) {
+  // stages 2..7 of a step of size h from (y, kv[0]) at time t; the new solution lands in yn,
+  // its right-hand side in kv[6]
+  int stages(double t, double h) {
     for (int si = 1; si <= 6; ++si) {
       const double* a = A[si];
-      const k::RkTerms t = terms({{kv[0], a[0]}, {kv[1], a[1]}, {kv[2], a[2]}, {kv[3], a[3]},
-                                  {kv[4], a[4]}, {kv[5], a[5]}});
+      const k::RkTerms tm = terms({{kv[0], a[0]}, {kv[1], a[1]}, {kv[2], a[2]}, {kv[3], a[3]},
+                                   {kv[4], a[4]}, {kv[5], a[5]}});
       double* dst = si == 6 ? yn.p : ys.p;
-      k::rk_axpy(y.p, t, h, dst, n, s);
-      if (int code = rhs(dst, kv[si]); code != MG_OK) return code;
+      k::rk_axpy(y.p, tm, h, dst, n, s);
+      if (int code = rhs(dst, kv[si], t + C[si] * h); code != MG_OK) return code;
     }
     return MG_OK;
   }
@@ -162,7 +180,7 @@ struct Integrator {
     k::gather<double>(F.perm, n, T0_nat, y.p, s);
     st.h_min = HUGE_VAL;
     st.h_max = 0.0;
-    int code = rhs(y.p, kv[0]);
+    int code = rhs(y.p, kv[0], 0.0);
     if (code != MG_OK) return code;
     double h = o.h0;
     if (!o.fixed_step && !(h > 0)) {
@@ -179,7 +197,7 @@ struct Integrator {
         h = t_stop - t;
         hit = true;
       }
-      if ((code = stages(h)) != MG_OK) return code;
+      if ((code = stages(t, h)) != MG_OK) return code;
       double err = 0.0;
       if (!o.fixed_step) err = step_error(h);
       if (o.fixed_step || err <= 1.0) {

@@ -4,24 +4,30 @@
  *
  * The method (arXiv 2508.12501):
  *   - meshes are 2-D embedded simplicial complexes (Def. 1); a hierarchy is built by binary
- *     1-to-4 subdivision, whose geometric map has the matrix M(f) of Def. 4;
+ *     1-to-4 or cubic 1-to-9 subdivisions, or from given meshes and geometric maps, each map
+ *     f encoded by its matrix M(f) of Def. 4 (composition: Prop. 2);
  *   - on every level the operator is rediscretised (Sec. 3.1): L = d0^T star1 d0, with star1
  *     the circumcentric |dual edge|/|primal edge| ratio and star0 the dual-cell area
  *     (Eq. hodge0-laplacian; the paper's Delta_0 equals -star0^{-1} L);
  *   - interpolation is P = M(f)^T (Def. 5); restriction is R = P^T, the stiffness-form
  *     counterpart of the row-normalised operator of Def. 6;
- *   - V-cycles with a weighted-Jacobi smoother and an exact coarsest solve are used as a
- *     solver and as a CG preconditioner (Sec. 3.1); the Darcy pressure step of porous
- *     convection solves d0^T star1 K d0 p = rhs (Sec. 3.2, Eq. poisson).
+ *   - V-, W- or F-cycles with weighted-Jacobi, multicolour Gauss-Seidel or CG smoothing and
+ *     an exact coarsest solve are used as a solver and as a (flexible) CG preconditioner
+ *     (Sec. 2, Sec. 3.1); the Darcy pressure step of porous convection solves
+ *     d0^T star1 K d0 p = rhs (Sec. 3.2, Eq. poisson), one step at a time or inside an
+ *     adaptive Runge-Kutta integration.
  *
  * Conventions shared by every entry point:
  *   - Every call returns an mg_status.  Nothing throws across the ABI.  On failure
  *     mg_last_error() returns a message (thread-local, valid until the next failing call).
  *   - Vectors passed to operator and solver calls are DEVICE pointers to contiguous arrays
  *     of one value per vertex of the named level, in the natural vertex numbering: base mesh
- *     ids, then after each subdivision coarse ids are kept and the midpoint of coarse edge e
- *     gets id V_coarse + e.  Edges are numbered by first appearance scanning triangles and
- *     their sides (v0v1, v1v2, v2v0) and are oriented from the smaller to the larger id.
+ *     ids, then after each subdivision coarse ids are kept; a binary subdivision gives the
+ *     midpoint of coarse edge e id V_coarse + e, a cubic one gives the points of edge e ids
+ *     V_coarse + 2e (next to its lower endpoint) and V_coarse + 2e + 1, and the centroid of
+ *     triangle t id V_coarse + 2 E_coarse + t; levels from given maps keep their meshes' own
+ *     ids.  Edges are numbered by first appearance scanning triangles and their sides (v0v1,
+ *     v1v2, v2v0) and are oriented from the smaller to the larger id.
  *     The caller owns these buffers; the library never frees or keeps them.
  *   - `stream` is a hipStream_t (NULL = the null stream).  All device work of a call is
  *     enqueued on it; calls that return host-side results (solver statistics) synchronise

@@ -1175,7 +1175,27 @@ __global__ __launch_bounds__(kBlock) void k_zdot32(int32_t n, const DevScalars* 
   tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
   const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0;
   double v = 0.0;
-  for (int t = t0; t < t1; ++t) {
+  int t = t0;
+  // four tiles' loads in flight before their products are summed (same order of summation)
+  for (; t + 4 <= t1; t += 4) {
+    float zf[4];
+    double ov[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = min((t + q) * kBlock + static_cast<int>(threadIdx.x), n - 1);
+      zf[q] = z32[i];
+      ov[q] = o[i];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if ((t + q) * kBlock + static_cast<int>(threadIdx.x) < n) {
+        double zi = static_cast<double>(zf[q]) * s;
+        if (sub_mean) zi = zi - m;
+        v += zi * ov[q];
+      }
+    }
+  }
+  for (; t < t1; ++t) {
     const int i = t * kBlock + threadIdx.x;
     if (i < n) {
       double zi = static_cast<double>(z32[i]) * s;
@@ -1193,11 +1213,37 @@ __global__ __launch_bounds__(kBlock) void k_pupd32(int32_t n, const DevScalars* 
                                                    double* __restrict__ p, int sub_mean,
                                                    const int* __restrict__ done) {
   if (*done) return;
-  const int i = xcd_block() * kBlock + threadIdx.x;
-  if (i < n) {
-    double zi = static_cast<double>(z32[i]) * sc->inv_scale;
-    if (sub_mean) zi = zi - sc->mean;
-    p[i] = zi + sc->beta * p[i];
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
+  int t = t0;
+  for (; t + 4 <= t1; t += 4) {
+    float zf[4];
+    double pv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = min((t + q) * kBlock + static_cast<int>(threadIdx.x), n - 1);
+      zf[q] = z32[i];
+      pv[q] = p[i];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = (t + q) * kBlock + threadIdx.x;
+      if (i < n) {
+        double zi = static_cast<double>(zf[q]) * s;
+        if (sub_mean) zi = zi - m;
+        p[i] = zi + beta * pv[q];
+      }
+    }
+  }
+  for (; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      double zi = static_cast<double>(z32[i]) * s;
+      if (sub_mean) zi = zi - m;
+      p[i] = zi + beta * p[i];
+    }
   }
 }
 
@@ -1828,7 +1874,7 @@ void zdot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, 
 }
 void pupd32(int32_t n, const DevScalars* sc, const float* z32, double* p, int sub_mean_flag,
             const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_pupd32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z32, p, sub_mean_flag,
+  hipLaunchKernelGGL(k_pupd32, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z32, p, sub_mean_flag,
                      done);
 }
 void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s) {

@@ -40,7 +40,7 @@ def parse():
                    help="skip the porous-convection rollout and gradient timing")
     p.add_argument("--no-variants", action="store_true",
                    help="skip the W/F-cycle, Gauss-Seidel and CG-smoothing timings")
-    p.add_argument("--only", choices=["e4", "cubic"], default=None,
+    p.add_argument("--only", choices=["e4", "cubic", "batch"], default=None,
                    help="run only one secondary workload and print its record (for profiling)")
     p.add_argument("--no-e4", action="store_true",
                    help="skip the adaptive porous-convection run to t = 0.5")
@@ -360,8 +360,12 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if a.only:
-        rec = e4_bench(mg, W, torch, np) if a.only == "e4" else cubic_bench(mg, W, torch, np,
-                                                                           max(3, a.steps // 2))
+        if a.only == "e4":
+            rec = e4_bench(mg, W, torch, np)
+        elif a.only == "cubic":
+            rec = cubic_bench(mg, W, torch, np, max(3, a.steps // 2))
+        else:
+            rec = batch_bench(mg, W, torch, np, max(3, a.steps // 2))
         print(json.dumps({"only": a.only, **rec}))
         return
     t0 = time.perf_counter()

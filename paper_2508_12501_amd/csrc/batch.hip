@@ -521,9 +521,26 @@ __global__ __launch_bounds__(kFin) void bk_finalize(int op, int M, int nb,
   const int J = kFin / M;
   const int c = threadIdx.x % M, j = threadIdx.x / M;
   double a = 0.0, b = 0.0;
-  for (int blk = j; blk < nb; blk += J) {
-    a += part0[blk * M + c];
-    if (part1) b += part1[blk * M + c];
+  // thread (c, j) sums blocks j, j + J, j + 2J, ... in that order; the loads go out eight at a
+  // time so that their latencies overlap
+  for (int base = j; base < nb; base += 8 * J) {
+    double va[8], vb[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int blk = base + q * J;
+      const int bc = blk < nb ? blk : nb - 1;
+      va[q] = part0[bc * M + c];
+      vb[q] = part1 ? part1[bc * M + c] : 0.0;
+      if (blk >= nb) {
+        va[q] = 0.0;
+        vb[q] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      a += va[q];
+      b += vb[q];
+    }
   }
   __shared__ double sa[kFin], sb[kFin];
   __shared__ int sdone[kBatchMaxCols];

@@ -288,3 +288,27 @@ def test_status_paths(c1):
         mg.mg_pcg(c1.g.h, mg.mg_opts_default(rtol=0.0), b, x)
     with pytest.raises(ValueError):
         mg.mg_pcg(c1.g.h, mg.mg_opts_default(), b[:-1].contiguous(), x[:-1].contiguous())
+
+
+def test_smallest_meshes():
+    """Degenerate sizes: a 1-cell Dirichlet square has no unknowns and is refused; a 2-cell one
+    has a single unknown (the coarsest solve is the whole method); one subdivision of it gives
+    a two-level hierarchy with 9 unknowns.  Each solve matches the oracle's direct solution."""
+    with pytest.raises(mg.MGError) as e:
+        mg.Hierarchy("square", 0, base_cells=1)
+    assert e.value.status == mg.MG_EINVAL
+    for nsub in (0, 1):
+        g = mg.Hierarchy("square", nsub, base_cells=2)
+        xyz, tri = dec.square_grid(2)
+        o = omg.Hierarchy(xyz, tri, nsub)
+        assert g.info[g.top]["n_unknowns"] == (1 if nsub == 0 else 9)
+        b = o.rhs(W.manufactured_c1(o.fine.xyz))
+        x = torch.zeros(o.fine.nv, dtype=torch.float64, device=DEV)
+        res = mg.mg_pcg(g.h, mg.mg_opts_default(), gpu(b), x)
+        ref = omg.direct_solve(o, b)
+        _, ko, _ = omg.mg_pcg(o, b)
+        assert rel(host(x), ref) <= 1e-13 and res.iterations == ko
+        x.zero_()
+        mg.mg_pcg(g.h, mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32), gpu(b), x)
+        assert omg.rel_residual(o, b, host(x)) <= 1e-10
+        g.close()

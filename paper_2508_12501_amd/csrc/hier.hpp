@@ -309,7 +309,9 @@ void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q
                double* r, float* r32, double* part0, const int* done, hipStream_t s);
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s);
-void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done, hipStream_t s);
+// p = z + beta p, or (z - mean) + beta p when sub_mean_flag
+void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
+             hipStream_t s, int sub_mean_flag = 0);
 void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s);
 void sum32(int32_t n, const float* v, const DevScalars* sc, double* part0, const int* done, hipStream_t s);
 void zconv_dot(int32_t n, const DevScalars* sc, const float* z32, double* z, const double* o,
@@ -334,9 +336,18 @@ enum FinOp : int {
   FIN_BETA_FCG = 5,   // beta = -sum0 / pq
   FIN_MEAN = 6,       // mean = sum0 / n
   FIN_RNORM = 7,      // rnorm = sqrt(sum0) (no iteration bookkeeping)
+  // singular systems, preconditioned vector z not yet projected: sum0 = z.o, sum1 = sum z,
+  // sum2 = sum o; mean = sum1 / n and (z - mean).o = sum0 - mean sum2, then as BETA_CG / FCG
+  FIN_MEAN_BETA_CG = 8,
+  FIN_MEAN_BETA_FCG = 9,
 };
 void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
-              double extra, int force, hipStream_t s);
+              double extra, int force, hipStream_t s, const double* part2 = nullptr);
+// part0 = z.o, part1 = sum z, part2 = sum o (z32 widened by 1/scale), per block
+void zsum_dot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, double* part0,
+                double* part1, double* part2, const int* done, hipStream_t s);
+void zsum_dot64(int32_t n, const DevScalars* sc, const double* z, const double* o, double* part0,
+                double* part1, double* part2, const int* done, hipStream_t s);
 void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, hipStream_t s);
 }  // namespace k
 

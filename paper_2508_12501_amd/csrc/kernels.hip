@@ -1096,11 +1096,48 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restr
 
 __global__ __launch_bounds__(kBlock) void k_pupdate(int32_t n, const DevScalars* __restrict__ sc,
                                                     const double* __restrict__ z,
-                                                    double* __restrict__ p,
+                                                    double* __restrict__ p, int sub_mean,
                                                     const int* __restrict__ done) {
   if (*done) return;
   const int i = xcd_block() * kBlock + threadIdx.x;
-  if (i < n) p[i] = z[i] + sc->beta * p[i];
+  if (i < n) p[i] = (sub_mean ? z[i] - sc->mean : z[i]) + sc->beta * p[i];
+}
+
+// part0 = z.o, part1 = sum z, part2 = sum o per block (z widened by 1/scale when ZT is float):
+// the sums from which the mean projection of z and the projected dot follow in one pass.
+template <typename ZT>
+__global__ __launch_bounds__(kBlock) void k_zsum_dot(int32_t n, const DevScalars* __restrict__ sc,
+                                                     const ZT* __restrict__ z,
+                                                     const double* __restrict__ o,
+                                                     double* __restrict__ part0,
+                                                     double* __restrict__ part1,
+                                                     double* __restrict__ part2,
+                                                     const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double s = std::is_same_v<ZT, float> ? sc->inv_scale : 1.0;
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      const double zi = std::is_same_v<ZT, float> ? static_cast<double>(z[i]) * s
+                                                  : static_cast<double>(z[i]);
+      const double oi = o[i];
+      v0 += zi * oi;
+      v1 += zi;
+      v2 += oi;
+    }
+  }
+  block_sum2(v0, v1);
+  __syncthreads();   // block_sum2's LDS slots are reused by the next reduction
+  v2 = block_sum1(v2);
+  if (threadIdx.x == 0) {
+    part0[blk] = v0;
+    part1[blk] = v1;
+    part2[blk] = v2;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum64(int32_t n, const double* __restrict__ v,
@@ -1331,44 +1368,59 @@ constexpr int kFinThreads = 1024;
 __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
                                                           const double* __restrict__ part0,
                                                           const double* __restrict__ part1,
+                                                          const double* __restrict__ part2,
                                                           DevScalars* __restrict__ sc,
                                                           double extra, int force) {
   if (!force && sc->done) return;
   // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8
-  double a = 0.0, b = 0.0;
+  double a = 0.0, b = 0.0, c = 0.0;
   for (int base = 0; nb > 0 && base < nb; base += 8 * kFinThreads) {
-    double va[8], vb[8];
+    double va[8], vb[8], vc[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int i = base + j * kFinThreads + threadIdx.x;
       const int ic = i < nb ? i : nb - 1;
       va[j] = part0[ic];
       vb[j] = part1 ? part1[ic] : 0.0;
+      vc[j] = part2 ? part2[ic] : 0.0;
       if (i >= nb) {
         va[j] = 0.0;
         vb[j] = 0.0;
+        vc[j] = 0.0;
       }
     }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       a += va[j];
       b += vb[j];
+      c += vc[j];
     }
   }
-  __shared__ double sa[kFinThreads / 64], sb[kFinThreads / 64];
+  __shared__ double sa[kFinThreads / 64], sb[kFinThreads / 64], scc[kFinThreads / 64];
   a = wave_sum(a);
   b = wave_sum(b);
+  c = wave_sum(c);
   if ((threadIdx.x & 63) == 0) {
     sa[threadIdx.x >> 6] = a;
     sb[threadIdx.x >> 6] = b;
+    scc[threadIdx.x >> 6] = c;
   }
   __syncthreads();
   if (threadIdx.x != 0) return;
   a = 0.0;
   b = 0.0;
+  c = 0.0;
   for (int i = 0; i < kFinThreads / 64; ++i) {
     a += sa[i];
     b += sb[i];
+    c += scc[i];
+  }
+  if (op == k::FIN_MEAN_BETA_CG || op == k::FIN_MEAN_BETA_FCG) {
+    // the projected vector's dot from the unprojected sums, then the plain beta update
+    const double mean = b / sc->n_unknowns;
+    sc->mean = mean;
+    a = a - mean * c;
+    op = (op == k::FIN_MEAN_BETA_CG) ? k::FIN_BETA_CG : k::FIN_BETA_FCG;
   }
   switch (op) {
     case k::FIN_BNORM: {
@@ -1847,8 +1899,19 @@ void residual_norm(const Level& L, const double* x, const double* b, double* r, 
   });
 }
 void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
-             hipStream_t s) {
-  hipLaunchKernelGGL(k_pupdate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, p, done);
+             hipStream_t s, int sub_mean_flag) {
+  hipLaunchKernelGGL(k_pupdate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, p, sub_mean_flag,
+                     done);
+}
+void zsum_dot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, double* part0,
+                double* part1, double* part2, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_zsum_dot<float>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z32, o,
+                     part0, part1, part2, done);
+}
+void zsum_dot64(int32_t n, const DevScalars* sc, const double* z, const double* o, double* part0,
+                double* part1, double* part2, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_zsum_dot<double>, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z, o,
+                     part0, part1, part2, done);
 }
 void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_sum64, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, v, part0, done);
@@ -1892,9 +1955,9 @@ void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const 
   hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, r, r32, done);
 }
 void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
-              double extra, int force, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, op, nblocks, part0, part1, sc,
-                     extra, force);
+              double extra, int force, hipStream_t s, const double* part2) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, s, op, nblocks, part0, part1,
+                     part2, sc, extra, force);
 }
 
 void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, hipStream_t s) {

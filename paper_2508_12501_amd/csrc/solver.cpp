@@ -230,26 +230,39 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   const double* other = (o.outer == MG_OUTER_FCG) ? H.sq : H.sr;
   double* z;
   float* z32 = nullptr;
+  double* P2 = H.part + 2 * H.part_cap;
+  // On singular (natural-boundary) systems the preconditioned vector is projected to zero
+  // mean.  CG and FCG take the mean and the projected dot from one pass over z (sum z, z.o,
+  // sum o) and subtract the mean inside the p update; IR projects z before using it.
+  const bool fused_mean = natural && o.outer != MG_OUTER_IR;
   if (o.precision == MG_F32) {
     z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s);
-    if (natural) {
-      k::sum32(n, z32, H.scal, P0, done, s);
-      fin(H, k::FIN_MEAN, n, false, s);
-    }
-    if (o.outer == MG_OUTER_IR) {
-      k::zconv_dot(n, H.scal, z32, H.sz, other, P0, natural ? 1 : 0, done, s);
+    if (fused_mean) {
+      k::zsum_dot32(n, H.scal, z32, other, P0, P1, P2, done, s);
     } else {
-      // z stays in FP32: the dot and the p update widen it on the fly
-      k::zdot32(n, H.scal, z32, other, P0, natural ? 1 : 0, done, s);
+      if (natural) {
+        k::sum32(n, z32, H.scal, P0, done, s);
+        fin(H, k::FIN_MEAN, n, false, s);
+      }
+      if (o.outer == MG_OUTER_IR) {
+        k::zconv_dot(n, H.scal, z32, H.sz, other, P0, natural ? 1 : 0, done, s);
+      } else {
+        // z stays in FP32: the dot and the p update widen it on the fly
+        k::zdot32(n, H.scal, z32, other, P0, 0, done, s);
+      }
     }
     z = H.sz;
   } else {
     z = vcycle<double>(H, top, H.sr, nullptr, o, done, s);
-    if (natural) {
-      k::sum64(n, z, P0, done, s);
-      fin(H, k::FIN_MEAN, n, false, s);
+    if (fused_mean) {
+      k::zsum_dot64(n, H.scal, z, other, P0, P1, P2, done, s);
+    } else {
+      if (natural) {
+        k::sum64(n, z, P0, done, s);
+        fin(H, k::FIN_MEAN, n, false, s);
+      }
+      k::zsub_dot(n, H.scal, z, other, P0, natural ? 1 : 0, done, s);
     }
-    k::zsub_dot(n, H.scal, z, other, P0, natural ? 1 : 0, done, s);
   }
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
   if (o.outer == MG_OUTER_IR) {
@@ -258,11 +271,15 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
     fin(H, k::FIN_CHECK, n, false, s, true);
     return;
   }
-  fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
+  if (fused_mean)
+    k::finalize(o.outer == MG_OUTER_CG ? k::FIN_MEAN_BETA_CG : k::FIN_MEAN_BETA_FCG,
+                k::red_blocks(n), P0, P1, H.scal, 0.0, 0, s, P2);
+  else
+    fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
   if (z32)
     k::pupd32(n, H.scal, z32, H.sp, natural ? 1 : 0, done, s);
   else
-    k::pupdate(n, H.scal, z, H.sp, done, s);
+    k::pupdate(n, H.scal, z, H.sp, done, s, fused_mean ? 1 : 0);
   k::spmv_dot2(F, H.sp, H.sq, H.sr, P0, P1, done, s);
   fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s, true);
   k::update_xr(n, H.scal, H.sp, H.sq, H.sx, H.sr, r32, P0, done, s);

@@ -264,7 +264,8 @@ mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x
 mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
                  mg_result* res, void* stream);
 
-/* Adjoint of mg_pcg (Sec. 3.3, reverse-mode differentiation through the solve).  For
+/* Adjoint of mg_pcg (reverse-mode differentiation through the solve of Sec. 3.1; the paper
+ * itself does not differentiate, this is an extension of its method).  For
  * u = A^-1 b (A^+ on natural-BC hierarchies) and an upstream gradient g_u = dJ/du, solves
  * A lambda = g_u with the same options and returns dJ/db = lambda in grad_b (nv doubles).
  * When grad_k is not null it ACCUMULATES dJ/dk_v for the vertex coefficient k

@@ -465,7 +465,8 @@ def contraction_factor(hist, tail: int = 5) -> float:
 
 def solve_adjoint(h: Hierarchy, u, grad_u):
     """Reverse-mode derivative of the exact solve u = A^{-1} b (A^+ b when singular) for a
-    loss J(u) with upstream gradient grad_u (Sec. 3.3 differentiates through the solver).
+    loss J(u) with upstream gradient grad_u (an extension: the paper solves, it does not
+    differentiate through the solver).
 
     lambda = A^{-T} grad_u = A^{-1} grad_u (A symmetric) is dJ/db.  With the finest-level
     edge weights w_e = star1_e k_e, k_e = (k_lo + k_hi) / 2 (reading Q13), dA/dk_e =

@@ -1,6 +1,7 @@
 """Reverse-mode differentiation through the multigrid solve and the porous-convection rollout
-(Sec. 3.3 of arXiv 2508.12501: the loss gradient with respect to the permeability field flows
-back through the DEC operators and the linear solves).
+of arXiv 2508.12501 (the solve of Sec. 3.1 and the model of Sec. 3.2; the paper does not
+differentiate them, so this is an extension: the loss gradient with respect to the permeability
+field flows back through the DEC operators and the linear solves).
 
 Both wrappers are ``torch.autograd.Function``s whose forward and backward passes are calls of
 the library's entry points (``mg_pcg`` / ``mg_pcg_adjoint``, ``porous_step`` /

@@ -271,11 +271,14 @@ mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
  * When grad_k is not null it ACCUMULATES dJ/dk_v for the vertex coefficient k
  * (k_e = (k_lo + k_hi)/2 on the finest level): grad_k_v += 1/2 sum over the edges e at v of
  * -star1_e (d0 lambda)_e (d0 u)_e, with u the solution the forward call returned (u_fine,
- * nv doubles; boundary vertices of a Dirichlet hierarchy count as zero).  All vectors are
- * device pointers in natural vertex order on the finest level. */
+ * nv doubles; boundary vertices of a Dirichlet hierarchy count as zero).  When grad_w is not
+ * null it ACCUMULATES dJ/dw_e for the finest operator's edge weights w_e = star1_e k_e (the
+ * Hodge weights of L = d0^T diag(w) d0): grad_w_e += -(d0 lambda)_e (d0 u)_e, ne doubles in
+ * the natural edge order; it also needs u_fine.  Vertex vectors are device pointers in
+ * natural vertex order on the finest level. */
 mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine,
-                         const double* grad_u, double* grad_b, double* grad_k, mg_result* res,
-                         void* stream);
+                         const double* grad_u, double* grad_b, double* grad_k, double* grad_w,
+                         mg_result* res, void* stream);
 
 /* ------------------------------------------------------------------ batched solves
  * Many independent solves at once (not in the paper: a throughput mode for many small and

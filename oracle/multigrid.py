@@ -483,3 +483,16 @@ def solve_adjoint(h: Hierarchy, u, grad_u):
     gk_e = -lv.star1 * (d0 @ (m * lam)) * (d0 @ (m * u))
     gk_v = 0.5 * (abs(d0).T @ gk_e)
     return lam, gk_v
+
+
+def solve_adjoint_weights(h: Hierarchy, u, grad_u):
+    """dJ/dw_e for the finest operator's edge weights w_e (L = d0^T diag(w) d0, the Hodge
+    weights star1_e k_e), same setting as solve_adjoint: dA/dw_e = (M d0_e)^T (M d0_e), so
+    dJ/dw_e = -(d0 M lambda)_e (d0 M u)_e with lambda = A^{-1} grad_u."""
+    lv = h.fine
+    lam = direct_solve(h, grad_u)
+    m = np.ones(lv.nv)
+    if h.bc == "dirichlet":
+        m[lv.bnd] = 0.0
+    d0 = sp.csr_matrix(lv.d0, dtype=np.float64)
+    return -(d0 @ (m * lam)) * (d0 @ (m * u))

@@ -140,7 +140,7 @@ _PROTOS = {
     "mg_vcycle": (_i32, [_vp, ctypes.POINTER(mg_opts), _i32, _i32, _vp, _vp, _vp]),
     "mg_solve": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
     "mg_pcg": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, ctypes.POINTER(mg_result), _vp]),
-    "mg_pcg_adjoint": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, _vp, _vp,
+    "mg_pcg_adjoint": (_i32, [_vp, ctypes.POINTER(mg_opts), _vp, _vp, _vp, _vp, _vp,
                               ctypes.POINTER(mg_result), _vp]),
     "porous_step": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp,
                            ctypes.POINTER(mg_result), _vp]),
@@ -439,15 +439,19 @@ def _opt_ptr(t, dtype, n, name):
 
 
 def mg_pcg_adjoint(h, opts: mg_opts, u, grad_u, grad_b, grad_k=None, stream=None,
-                   raise_on_error=True) -> mg_result:
-    """grad_b = A^-1 grad_u; grad_k (if given) += dJ/dk at the vertices (accumulates)."""
+                   raise_on_error=True, grad_w=None) -> mg_result:
+    """grad_b = A^-1 grad_u; grad_k (if given) += dJ/dk at the vertices and grad_w (if given,
+    one entry per finest-level edge) += dJ/dw for the edge weights w = star1 k (accumulate)."""
     import torch
     res = mg_result()
-    n = _nv(h, _top(h))
+    top = _top(h)
+    n = _nv(h, top)
+    ne = mg_hierarchy_info(h, top)["ne"]
     st = lib().mg_pcg_adjoint(h, ctypes.byref(opts), _opt_ptr(u, torch.float64, n, "u"),
                               _ptr(grad_u, torch.float64, n, "grad_u"),
                               _ptr(grad_b, torch.float64, n, "grad_b"),
-                              _opt_ptr(grad_k, torch.float64, n, "grad_k"), ctypes.byref(res),
+                              _opt_ptr(grad_k, torch.float64, n, "grad_k"),
+                              _opt_ptr(grad_w, torch.float64, ne, "grad_w"), ctypes.byref(res),
                               _stream(stream))
     if raise_on_error:
         _check(st, res)

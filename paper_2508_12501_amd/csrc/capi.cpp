@@ -512,14 +512,16 @@ mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x, 
 }
 
 mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine,
-                         const double* grad_u, double* grad_b, double* grad_k, mg_result* res,
-                         void* stream) {
+                         const double* grad_u, double* grad_b, double* grad_k, double* grad_w,
+                         mg_result* res, void* stream) {
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
   if (mg_status st = check_krylov_opts(o); st != MG_OK) return st;
   if (!grad_u || !grad_b) return fail(MG_EINVAL, "null vector");
-  if (grad_k && !u_fine) return fail(MG_EINVAL, "grad_k needs the forward solution u_fine");
+  if ((grad_k || grad_w) && !u_fine)
+    return fail(MG_EINVAL, "grad_k and grad_w need the forward solution u_fine");
   API_BEGIN
-  const int st = decmg::run_pcg_adjoint(*h->h, *o, u_fine, grad_u, grad_b, grad_k, res, S(stream));
+  const int st = decmg::run_pcg_adjoint(*h->h, *o, u_fine, grad_u, grad_b, grad_k, grad_w, res,
+                                        S(stream));
   if (st != MG_OK)
     return fail(mg_status(st), "mg_pcg_adjoint stopped with status " + std::to_string(st));
   API_END

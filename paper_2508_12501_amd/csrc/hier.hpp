@@ -298,6 +298,9 @@ void por_grad_k(const Level& L, const PorousData& D, const double* T, const doub
                 hipStream_t s);
 void mg_grad_k(const Level& L, const PorousData& D, const double* lam, const double* u,
                double* gk_nat, hipStream_t s);
+// gw_e += -(d0 lam)_e (d0 u)_e per edge (natural edge order); lam, u internal
+void mg_grad_w(const Level& L, const PorousData& D, const double* lam, const double* u,
+               double* gw_nat, hipStream_t s);
 
 // Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
 int blocks_for(int32_t n);

@@ -190,8 +190,17 @@ int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
 }
 
 int run_pcg_adjoint(Hierarchy& H, const mg_opts& o, const double* u_nat, const double* gu_nat,
-                    double* gb_nat, double* gk_nat, mg_result* res, hipStream_t s) {
+                    double* gb_nat, double* gk_nat, double* gw_nat, mg_result* res,
+                    hipStream_t s) {
   const int st = run_pcg(H, o, gu_nat, gb_nat, res, s);
+  if (gw_nat) {
+    ensure(H);
+    PorousData& D = H.por;
+    Level& F = *H.lv.back();
+    k::gather<double>(F.perm, F.n, u_nat, D.U, s);
+    k::mg_grad_w(F, D, H.sx, D.U, gw_nat, s);
+    check_hip(hipGetLastError(), "kernel launch");
+  }
   if (gk_nat) {
     ensure(H);
     PorousData& D = H.por;

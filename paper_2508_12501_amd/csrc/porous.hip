@@ -164,6 +164,16 @@ __global__ void k_mg_grad_edges(const int32_t* __restrict__ ea, const int32_t* _
   ge[e] = -s1e[e] * ((lam[b] - lam[a]) * (u[b] - u[a]));
 }
 
+// gw_e += -(lam_hi - lam_lo)(u_hi - u_lo): the derivative with respect to the edge weight
+__global__ void k_mg_grad_w(const int32_t* __restrict__ ea, const int32_t* __restrict__ eb,
+                            const double* __restrict__ lam, const double* __restrict__ u,
+                            double* __restrict__ gw, int32_t ne) {
+  const int e = blockIdx.x * kThreads + threadIdx.x;
+  if (e >= ne) return;
+  const int a = ea[e], b = eb[e];
+  gw[e] += -((lam[b] - lam[a]) * (u[b] - u[a]));
+}
+
 // g_v += (1/2) sum over the edges at v of ge_e   (k_e = (k_lo + k_hi)/2), natural numbering
 __global__ void k_edges_to_vertices(const int64_t* __restrict__ vptr,
                                     const int32_t* __restrict__ vinc, const double* __restrict__ ge,
@@ -285,6 +295,12 @@ void por_grad_k(const Level& L, const PorousData& D, const double* T, const doub
                      D.y, T, P, mu, psi, D.ge, D.ne, dt, 1.0 / phi);
   hipLaunchKernelGGL(k_edges_to_vertices, dim3(blocks(L.nv)), dim3(kThreads), 0, s, D.vptr, D.vinc,
                      D.ge, gk_nat, L.nv);
+}
+void mg_grad_w(const Level& L, const PorousData& D, const double* lam, const double* u,
+               double* gw_nat, hipStream_t s) {
+  (void)L;
+  hipLaunchKernelGGL(k_mg_grad_w, dim3(blocks(D.ne)), dim3(kThreads), 0, s, D.ea, D.eb, lam, u,
+                     gw_nat, D.ne);
 }
 void mg_grad_k(const Level& L, const PorousData& D, const double* lam, const double* u,
                double* gk_nat, hipStream_t s) {

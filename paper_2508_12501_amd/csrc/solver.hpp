@@ -49,7 +49,8 @@ int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
                        const double* p_nat, const double* lam_nat, double* lam_out_nat,
                        double* gk_nat, hipStream_t s);
 int run_pcg_adjoint(Hierarchy& H, const mg_opts& o, const double* u_nat, const double* gu_nat,
-                    double* gb_nat, double* gk_nat, mg_result* res, hipStream_t s);
+                    double* gb_nat, double* gk_nat, double* gw_nat, mg_result* res,
+                    hipStream_t s);
 void free_porous(Hierarchy& H);
 
 }  // namespace decmg

@@ -224,6 +224,19 @@ def test_mg_solve_autograd(kind):
     eu, eb, ek = rel(host(u), ur), rel(host(b.grad), lam), rel(host(k.grad), gkr)
     print(f"[porous] MGSolve {kind}: rel u {eu:.2e}, rel dJ/db {eb:.2e}, rel dJ/dk {ek:.2e}")
     assert eu <= 1e-10 and eb <= 1e-10 and ek <= 1e-9
+    # the same adjoint through the C-ABI, with the gradient for the finest operator's edge
+    # weights (the Hodge weights star1 k) accumulated onto a nonzero start
+    mg.mg_hierarchy_set_vertex_coeff(g.h, gpu(kv))
+    ne = o.fine.ne
+    gw0 = W.normal(ne, 58)
+    gw = gpu(gw0)
+    gb = torch.empty(nv, dtype=torch.float64, device=DEV)
+    mg.mg_pcg_adjoint(g.h, mg.mg_opts_default(rtol=1e-13), gpu(host(u)), gpu(wv), gb,
+                      grad_w=gw)
+    gwr = omg.solve_adjoint_weights(o, ur, wv)
+    ew = rel(host(gw) - gw0, gwr)
+    print(f"[porous] mg_pcg_adjoint {kind}: rel dJ/dw {ew:.2e}")
+    assert ew <= 1e-9 and rel(host(gb), lam) <= 1e-10
     g.close()
 
 

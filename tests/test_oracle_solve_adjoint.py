@@ -58,3 +58,31 @@ def test_grad_k_homogeneity(bc):
     _, gk = omg.solve_adjoint(h, u, g)
     J = float(g @ u)
     assert abs(kv @ gk + J) <= 1e-12 * abs(J) * 10
+
+
+@pytest.mark.parametrize("bc", ["dirichlet", "natural"])
+def test_grad_w_finite_differences_and_homogeneity(bc):
+    """dJ/dw for the finest operator's edge weights (the Hodge weights star1 k): central
+    differences on a sample of edges, including edges whose weight is 0 (the right-grid
+    diagonals), and sum_e w_e dJ/dw_e = -J (u is homogeneous of degree -1 in w)."""
+    h, kv, b, g = _setup(bc)
+    u = omg.direct_solve(h, b)
+    gw = omg.solve_adjoint_weights(h, u, g)
+    lv = h.fine
+    w0 = lv.w.copy()
+    J = float(g @ u)
+    assert abs(float(w0 @ gw) + J) <= 1e-10 * abs(J)
+    rng = np.random.default_rng(5)
+    zero = np.nonzero(w0 == 0.0)[0]
+    edges = np.concatenate([rng.choice(len(w0), 10, replace=False), zero[:2]])
+    eps = 1e-6
+    fd = np.zeros(len(edges))
+    for i, e in enumerate(edges):
+        for s in (1, -1):
+            lv.w = w0.copy()
+            lv.w[e] += s * eps
+            h._assemble()
+            fd[i] += s * float(g @ omg.direct_solve(h, b)) / (2 * eps)
+    lv.w = w0
+    h._assemble()
+    assert np.abs(fd - gw[edges]).max() <= 1e-6 * np.abs(gw).max()

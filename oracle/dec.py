@@ -92,7 +92,7 @@ def edges_of(tri: np.ndarray, nv: int):
 
 
 def d0_matrix(edges: np.ndarray, nv: int) -> sp.csr_matrix:
-    """Exterior derivative on 0-forms, E x V: (d0 u)_e = u(hi) - u(lo) (Fig. 1, Sec. 3.1)."""
+    """Exterior derivative on 0-forms, E x V: (d0 u)_e = u(hi) - u(lo) (Fig. dRC, Sec. 3.1)."""
     ne = len(edges)
     rows = np.repeat(np.arange(ne), 2)
     cols = edges.ravel()
@@ -101,7 +101,7 @@ def d0_matrix(edges: np.ndarray, nv: int) -> sp.csr_matrix:
 
 
 def d1_matrix(tri_edges: np.ndarray, tri_sign: np.ndarray, ne: int) -> sp.csr_matrix:
-    """Exterior derivative on 1-forms, T x E: signed sum of a triangle's edges (Fig. 1)."""
+    """Exterior derivative on 1-forms, T x E: signed sum of a triangle's edges (Fig. dRC)."""
     nt = len(tri_edges)
     rows = np.repeat(np.arange(nt), 3)
     return sp.csr_matrix((tri_sign.ravel().astype(np.int64), (rows, tri_edges.ravel())),
@@ -214,7 +214,7 @@ def _cot(pk, pi, pj):
 
 
 def hodge_stars(xyz, tri, tri_edges, ne: int):
-    """Diagonal Hodge stars of the circumcentric dual (Sec. 3.1, Fig. 6):
+    """Diagonal Hodge stars of the circumcentric dual (Sec. 3.1, Fig. pd-scs):
     star1[e] = |dual edge| / |primal edge| = (1/2) sum over triangles containing e of the
     cotangent of the angle opposite e (signed);
     star0[v] = area of the dual cell of v = sum over triangles (|e_vj|^2 cot th_k +

@@ -48,7 +48,7 @@ class Level:
 
 
 class Hierarchy:
-    """Meshes X_0 (coarsest) .. X_l (finest) related by binary subdivision maps (Fig. 3),
+    """Meshes X_0 (coarsest) .. X_l (finest) related by binary subdivision maps (Fig. ex-subdiv),
     with L on each level and the transfer operators between neighbours."""
 
     def __init__(self, xyz, tri, nsub: int, project: bool = False, bc: str = "dirichlet",

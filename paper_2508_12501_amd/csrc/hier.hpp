@@ -96,6 +96,8 @@ struct CoarseLevel {
   const int32_t* r_self = nullptr;   // restriction into level-1
   const int32_t* r_sptr = nullptr;
   const int32_t* r_col = nullptr;
+  const int32_t* color = nullptr;    // Gauss-Seidel colour of each row
+  int32_t ncolors = 0;
 };
 
 template <typename T>
@@ -141,6 +143,7 @@ struct Level {
   double* star0 = nullptr;         // nv, natural numbering
   DevOperator op;
   std::vector<GsColor> gs;         // colour classes, in colour order
+  int32_t* row_color = nullptr;    // n + 1: colour class of each internal row (device)
   CgsScalars* cgs = nullptr;
   DevTransfer tr;                  // valid for l >= 1
   LevelVecs<double> v64;
@@ -259,6 +262,10 @@ template <typename T> void gs_color(const Level& L, int c, T* x, const T* b, con
 template <typename T> void prolong_sweep(const Level& Lf, const Level& Lc, const T* ec, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);
 template <typename T> void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2, const int* done, hipStream_t s);
+// whether levels top..0 fit the one-workgroup register-resident cycle of any shape and smoother
+template <typename T> bool coarse_cycle_general_ok(const Hierarchy& H, int top, bool gs);
+// one cycle of shape `kind` on levels top..0 in one launch, from zero or (x_init) from x, in place
+template <typename T> void coarse_cycle_general(const Hierarchy& H, int top, const T* b, T* x, bool x_init, double omega, int nu1, int nu2, int kind, bool gs, const int* done, hipStream_t s);
 template <typename T> void fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T> void gather(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);
 template <typename T> void scatter(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);

@@ -261,6 +261,11 @@ void build_gs_colors(Level& L) {
     color[r] = c;
     ncolors = std::max(ncolors, c + 1);
   }
+  {
+    std::vector<int32_t> rc(color.begin(), color.end());
+    rc.push_back(0);   // zero slot
+    L.row_color = upload(rc);
+  }
   L.gs.assign(ncolors, GsColor());
   for (int32_t c = 0; c < ncolors; ++c) {
     GsColor& G = L.gs[c];
@@ -547,6 +552,8 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
     c.col = L.op.col;
     c.w = level_weights<T>(L);
     c.diag = level_diag<T>(L);
+    c.color = L.row_color;
+    c.ncolors = int32_t(L.gs.size());
     if (l >= 1) {
       c.pa = L.tr.pa;
       c.pb = L.tr.pb;
@@ -757,6 +764,7 @@ Hierarchy::~Hierarchy() {
     for (GsColor& G : L.gs)
       for (void* p : {(void*)G.rowid, (void*)G.sptr, (void*)G.col, (void*)G.w64, (void*)G.w32})
         free_dev(p);
+    free_dev(L.row_color);
   }
   for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
                   (void*)sb, (void*)part, (void*)scal})

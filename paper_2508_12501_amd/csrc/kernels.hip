@@ -799,29 +799,61 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
   for (int i = threadIdx.x; i < L.n; i += blockDim.x) x_out[i] = xs[i];
 }
 
-// The same coarse end of the cycle when the levels below the top have at most one row per
-// thread and the top level at most RPT (1 or 2), operator and restriction rows have at most K
-// and 8 entries, and NL levels lie above the coarsest (NL = top, 1..4).  Thread t owns row t of
-// every level (and row t + blockDim of the top one): it loads all of their index, weight,
-// diagonal and transfer data into registers before the first barrier, so the phases that
-// follow touch only registers and LDS.  A single workgroup lands on a different XCD from one
-// launch to the next, so its L2 is cold: issuing every global load at once replaces a round
-// trip per phase by one in total.  The arithmetic, entry order and padding conventions are
-// those of k_coarse_cycle.
-template <typename T, int K, int NL, int RPT>
+// The bottom of a cycle (levels NL..0, NL = 1..4) in one workgroup, for V, W and F shapes,
+// weighted-Jacobi or multicolour Gauss-Seidel smoothing, from zero or from a given iterate.
+// Requirements: the levels below the top have at most one row per thread and the top level
+// at most RPT (1 or 2); operator and restriction rows have at most K and 8 entries.  Thread t
+// owns row t of every level (and row t + blockDim of the top one) and loads all of their
+// index, weight, diagonal, colour and transfer data into registers before the first barrier,
+// so the phases that follow touch only registers and LDS: a single workgroup lands on a
+// different XCD from one launch to the next, so its L2 is cold, and one round of loads replaces
+// a round trip per phase.  LDS holds, per level, x, its ping-pong partner and b (3 (n+1)
+// values with a zero slot each) and the dense coarsest inverse.  The recursion of the cycle
+// shapes (W: two coarse cycles, the second from the first's result; F: an F-cycle then a
+// V-cycle) runs as a loop over a per-level stage kept in bit fields.  GEN = false compiles
+// the V-cycle with weighted-Jacobi smoothing from zero alone, as straight-line code with the
+// register budget of that case.  The arithmetic, entry order and padding conventions are those
+// of the per-level kernels.
+template <int L, typename F>
+__device__ __forceinline__ void levels_down(F&& f) {   // f(L), f(L - 1), ..., f(1)
+  if constexpr (L >= 1) {
+    f(std::integral_constant<int, L>{});
+    levels_down<L - 1>(f);
+  }
+}
+template <int L, int NL, typename F>
+__device__ __forceinline__ void levels_up(F&& f) {     // f(L), f(L + 1), ..., f(NL)
+  if constexpr (L <= NL) {
+    f(std::integral_constant<int, L>{});
+    levels_up<L + 1, NL>(f);
+  }
+}
+template <int NL, typename F>
+__device__ __forceinline__ void at_level(int l, F&& f) {
+  switch (l) {
+    case 1: if constexpr (NL >= 1) f(std::integral_constant<int, 1>{}); break;
+    case 2: if constexpr (NL >= 2) f(std::integral_constant<int, 2>{}); break;
+    case 3: if constexpr (NL >= 3) f(std::integral_constant<int, 3>{}); break;
+    case 4: if constexpr (NL >= 4) f(std::integral_constant<int, 4>{}); break;
+    default: break;
+  }
+}
+
+template <typename T, int K, int NL, int RPT, bool GEN>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
     const CoarseLevel<T>* __restrict__ lv, const double* __restrict__ ainv, int32_t n0,
-    int32_t inv_off, const T* __restrict__ b_in, T* __restrict__ x_out, T omega, int nu1,
-    int nu2, const int* __restrict__ done) {
+    int32_t inv_off, const T* __restrict__ b_in, T* __restrict__ x_io, int x_init, T omega,
+    int nu1, int nu2, int kind, int gs, const int* __restrict__ done) {
   constexpr int RW = 8;
   if (done && *done) return;
+  const bool use_gs = GEN && gs != 0, use_x = GEN && x_init != 0;
   extern __shared__ double smem_d[];
   T* sm = reinterpret_cast<T*>(smem_d);
   double* sinv = smem_d + inv_off / 8;
   const int t = threadIdx.x, nt = blockDim.x;
   // operator rows: RPT on the top level, one below it; restriction rows (into level l - 1,
   // never the top level): one
-  int cj[NL + 1][RPT][K], pa[NL + 1][RPT], pb[NL + 1][RPT];
+  int cj[NL + 1][RPT][K], pa[NL + 1][RPT], pb[NL + 1][RPT], clr[NL + 1][RPT];
   int rc[NL + 1][RW], rs[NL + 1], rwid[NL + 1];
   T wv[NL + 1][RPT][K], dg[NL + 1][RPT];
 #pragma unroll
@@ -845,6 +877,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
       dg[l][q] = L.diag[row];
       pa[l][q] = L.pa[row];
       pb[l][q] = L.pb[row];
+      clr[l][q] = use_gs ? L.color[row] : 0;
     }
     const int crow = min(t, lv[l - 1].n - 1);
     const int rsl = crow >> 6, rlane = crow & 63;
@@ -859,65 +892,147 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
   for (int i = t; i < total; i += nt) sm[i] = T(0);
   for (int i = t; i < n0 * n0; i += nt) sinv[i] = ainv[i];
   __syncthreads();
-  for (int i = t; i < lv[NL].n; i += nt) sm[lv[NL].lds + 2 * (lv[NL].n + 1) + i] = b_in[i];
+  {
+    const int n = lv[NL].n;
+    for (int i = t; i < n; i += nt) {
+      sm[lv[NL].lds + 2 * (n + 1) + i] = b_in[i];
+      if (use_x) sm[lv[NL].lds + i] = x_io[i];
+    }
+  }
   __syncthreads();
-  auto sweep = [&](int l, int n, const T* cx, const T* B, T* out, int mode) {
-    const int nq = (l == NL) ? RPT : 1;
+  unsigned in_t = 0;   // bit l: level l's current iterate sits in its partner buffer
+
+  // out = sweep of cx (mode 2: Jacobi x + omega (b - A x) / D; mode 1: residual b - A x)
+  auto sweep = [&](auto Lc, const T* cx, const T* B, T* out, int mode) {
+    constexpr int L = decltype(Lc)::value;
+    const int n = lv[L].n;
+    constexpr int NQ = (L == NL) ? RPT : 1;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int r = t + q * nt;
-      if (q < nq && r < n) {
+      if (r < n) {
         const T xi = cx[r];
         T acc = T(0), d = T(0);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          d += wv[l][q][k];
-          acc += wv[l][q][k] * (xi - cx[cj[l][q][k]]);
+          d += wv[L][q][k];
+          acc += wv[L][q][k] * (xi - cx[cj[L][q][k]]);
         }
         out[r] = (mode == 2) ? xi + omega * (B[r] - acc) / d : B[r] - acc;
       }
     }
   };
-  unsigned in_t = 0;
+  // one Gauss-Seidel sweep over the colour classes in order (forward) or reversed
+  auto gs_sweep = [&](auto Lc, T* cx, const T* B, bool forward) {
+    constexpr int L = decltype(Lc)::value;
+    const int n = lv[L].n, nc = lv[L].ncolors;
+    constexpr int NQ = (L == NL) ? RPT : 1;
+    for (int ci = 0; ci < nc; ++ci) {
+      const int c = forward ? ci : nc - 1 - ci;
 #pragma unroll
-  for (int l = NL; l >= 1; --l) {
-    const int n = lv[l].n;
-    const int nq = (l == NL) ? RPT : 1;
-    T* X = sm + lv[l].lds;
+      for (int q = 0; q < NQ; ++q) {
+        const int r = t + q * nt;
+        if (r < n && clr[L][q] == c) {
+          const T xi = cx[r];
+          T acc = T(0), d = T(0);
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            d += wv[L][q][k];
+            acc += wv[L][q][k] * (xi - cx[cj[L][q][k]]);
+          }
+          cx[r] = xi + (B[r] - acc) / d;
+        }
+      }
+      __syncthreads();
+    }
+  };
+  // pre-smoothing, residual and restriction of level L (down leg)
+  auto down = [&](auto Lc, bool from_x) {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int NQ = (L == NL) ? RPT : 1;
+    const int n = lv[L].n;
+    T* X = sm + lv[L].lds;
     T* Tt = X + (n + 1);
     T* B = Tt + (n + 1);
-    T* cx = X;
-    T* ox = Tt;
-    if (nu1 > 0) {
+    T* cx = from_x ? ((in_t >> L & 1u) ? Tt : X) : X;
+    T* ox = (cx == X) ? Tt : X;
+    if (use_gs) {
+      if (!from_x) {
+        for (int i = t; i < n; i += nt) cx[i] = T(0);
+        __syncthreads();
+      }
+      for (int it = 0; it < nu1; ++it) gs_sweep(Lc, cx, B, true);
+    } else {
+      int pre = nu1;
+      if (!from_x) {
+        if (pre > 0) {
 #pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q < nq && t + q * nt < n) cx[t + q * nt] = omega * B[t + q * nt] / dg[l][q];
-      __syncthreads();
-      for (int it = 1; it < nu1; ++it) {
-        sweep(l, n, cx, B, ox, 2);
+          for (int q = 0; q < NQ; ++q)
+            if (t + q * nt < n) cx[t + q * nt] = omega * B[t + q * nt] / dg[L][q];
+          --pre;
+        } else {
+          for (int i = t; i < n; i += nt) cx[i] = T(0);
+        }
+        __syncthreads();
+      }
+      for (; pre > 0; --pre) {
+        sweep(Lc, cx, B, ox, 2);
         __syncthreads();
         T* tmp = cx;
         cx = ox;
         ox = tmp;
       }
-    } else {
-      for (int i = t; i < n; i += nt) cx[i] = T(0);
-      __syncthreads();
     }
-    sweep(l, n, cx, B, ox, 1);
+    sweep(Lc, cx, B, ox, 1);   // residual into the partner buffer
     __syncthreads();
-    const int nc = lv[l - 1].n;
+    const int nc = lv[L - 1].n;
     if (t < nc) {
       T acc = T(0);
 #pragma unroll
       for (int k = 0; k < RW; ++k)
-        if (k < rwid[l]) acc += ox[rc[l][k]];
-      sm[lv[l - 1].lds + 2 * (nc + 1) + t] = ox[rs[l]] + T(0.5) * acc;
+        if (k < rwid[L]) acc += ox[rc[L][k]];
+      sm[lv[L - 1].lds + 2 * (nc + 1) + t] = ox[rs[L]] + T(0.5) * acc;
     }
     __syncthreads();
-    if (cx == Tt) in_t |= 1u << l;
-  }
-  {
+    if (cx == Tt)
+      in_t |= 1u << L;
+    else
+      in_t &= ~(1u << L);
+  };
+  // interpolation of the coarse correction and post-smoothing of level L (up leg)
+  auto up = [&](auto Lc) {
+    constexpr int L = decltype(Lc)::value;
+    constexpr int NQ = (L == NL) ? RPT : 1;
+    const int n = lv[L].n, nc = lv[L - 1].n;
+    T* X = sm + lv[L].lds;
+    T* Tt = X + (n + 1);
+    T* B = Tt + (n + 1);
+    T* cx = (in_t >> L & 1u) ? Tt : X;
+    T* ox = (cx == X) ? Tt : X;
+    const T* ec = sm + lv[L - 1].lds + ((in_t >> (L - 1) & 1u) ? (nc + 1) : 0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      if (t + q * nt < n) cx[t + q * nt] += T(0.5) * (ec[pa[L][q]] + ec[pb[L][q]]);
+    __syncthreads();
+    if (use_gs) {
+      for (int it = 0; it < nu2; ++it) gs_sweep(Lc, cx, B, false);
+    } else {
+      for (int it = 0; it < nu2; ++it) {
+        sweep(Lc, cx, B, ox, 2);
+        __syncthreads();
+        T* tmp = cx;
+        cx = ox;
+        ox = tmp;
+      }
+    }
+    if (cx == Tt)
+      in_t |= 1u << L;
+    else
+      in_t &= ~(1u << L);
+  };
+
+  // the coarsest level: x_0 = A_0^+ b_0 with the dense inverse
+  auto solve0 = [&]() {
     T* X0 = sm + lv[0].lds;
     const T* B0 = X0 + 2 * (lv[0].n + 1);
     for (int i = t; i < n0; i += nt) {
@@ -926,36 +1041,57 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
       for (int j = 0; j < n0; ++j) acc += a[j] * static_cast<double>(B0[j]);
       X0[i] = static_cast<T>(acc);
     }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int l = 1; l <= NL; ++l) {
-    const int n = lv[l].n, nc = lv[l - 1].n;
-    const int nq = (l == NL) ? RPT : 1;
-    T* X = sm + lv[l].lds;
-    T* Tt = X + (n + 1);
-    T* B = Tt + (n + 1);
-    T* cx = (in_t >> l & 1u) ? Tt : X;
-    T* ox = (cx == X) ? Tt : X;
-    const T* ec = sm + lv[l - 1].lds + ((in_t >> (l - 1) & 1u) ? (nc + 1) : 0);
-#pragma unroll
-    for (int q = 0; q < RPT; ++q)
-      if (q < nq && t + q * nt < n) cx[t + q * nt] += T(0.5) * (ec[pa[l][q]] + ec[pb[l][q]]);
+    in_t &= ~1u;
     __syncthreads();
-    for (int it = 0; it < nu2; ++it) {
-      sweep(l, n, cx, B, ox, 2);
-      __syncthreads();
-      T* tmp = cx;
-      cx = ox;
-      ox = tmp;
+  };
+
+  if constexpr (!GEN) {
+    levels_down<NL>([&](auto Lc) { down(Lc, false); });
+    solve0();
+    levels_up<1, NL>([&](auto Lc) { up(Lc); });
+    const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
+    for (int i = t; i < lv[NL].n; i += nt) x_io[i] = xs[i];
+    return;
+  }
+  // the recursion as a loop: per level a 2-bit stage (0 enter, 1 after the first coarse
+  // cycle, 2 after the second), a 2-bit shape and a start-from-x bit
+  unsigned stage = 0, shape = unsigned(kind) << (2 * NL), from = unsigned(use_x ? 1 : 0) << NL;
+  int level = NL;
+  for (;;) {
+    if (level == 0) {
+      solve0();
+      level = 1;
+      continue;
     }
-    if (cx == Tt)
-      in_t |= 1u << l;
-    else
-      in_t &= ~(1u << l);
+    const unsigned st = (stage >> (2 * level)) & 3u;
+    const unsigned sh = (shape >> (2 * level)) & 3u;
+    if (st == 0) {
+      at_level<NL>(level, [&](auto Lc) { down(Lc, (from >> level) & 1u); });
+      const unsigned child = sh;   // V -> V, W -> W, F -> F for the first coarse cycle
+      stage = (stage & ~(3u << (2 * level))) | (1u << (2 * level));
+      const int c = level - 1;
+      stage &= ~(3u << (2 * c));
+      shape = (shape & ~(3u << (2 * c))) | (child << (2 * c));
+      from &= ~(1u << c);
+      level = c;
+      continue;
+    }
+    if (st == 1 && (sh == MG_CYCLE_W || sh == MG_CYCLE_F)) {
+      const unsigned child = (sh == MG_CYCLE_F) ? unsigned(MG_CYCLE_V) : unsigned(MG_CYCLE_W);
+      stage = (stage & ~(3u << (2 * level))) | (2u << (2 * level));
+      const int c = level - 1;
+      stage &= ~(3u << (2 * c));
+      shape = (shape & ~(3u << (2 * c))) | (child << (2 * c));
+      from |= 1u << c;
+      level = c;
+      continue;
+    }
+    at_level<NL>(level, [&](auto Lc) { up(Lc); });
+    if (level == NL) break;
+    ++level;
   }
   const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
-  for (int i = t; i < lv[NL].n; i += nt) x_out[i] = xs[i];
+  for (int i = t; i < lv[NL].n; i += nt) x_io[i] = xs[i];
 }
 
 template <typename T>
@@ -1732,7 +1868,25 @@ static void launch_coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, d
                      int32_t(int_off), b, x, static_cast<T>(omega), nu1, nu2, done);
 }
 
-// Allows the fused coarse cycle its dynamic LDS (above the default 64 KiB); called once when
+template <typename T, int K, int NL, int RPT, bool GEN>
+static void allow_lds(int bytes) {
+  if (bytes > 64 * 1024)
+    check_hip_k(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_coarse_cycle_reg<T, K, NL, RPT, GEN>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+}
+template <typename T, int K>
+static void allow_reg(int bytes) {
+  allow_lds<T, K, 1, 1, false>(bytes); allow_lds<T, K, 1, 2, false>(bytes);
+  allow_lds<T, K, 2, 1, false>(bytes); allow_lds<T, K, 2, 2, false>(bytes);
+  allow_lds<T, K, 3, 1, false>(bytes); allow_lds<T, K, 3, 2, false>(bytes);
+  allow_lds<T, K, 4, 1, false>(bytes); allow_lds<T, K, 4, 2, false>(bytes);
+  allow_lds<T, K, 1, 1, true>(bytes);  allow_lds<T, K, 1, 2, true>(bytes);
+  allow_lds<T, K, 2, 1, true>(bytes);  allow_lds<T, K, 2, 2, true>(bytes);
+  allow_lds<T, K, 3, 1, true>(bytes);  allow_lds<T, K, 3, 2, true>(bytes);
+  allow_lds<T, K, 4, 1, true>(bytes);  allow_lds<T, K, 4, 2, true>(bytes);
+}
+
+// Allows the fused coarse cycles their dynamic LDS (above the default 64 KiB); called once when
 // a hierarchy is built, outside any stream capture.
 void prepare_coarse(const Hierarchy& H) {
   const int b64 = int(coarse_lds_bytes<double>(H)), b32 = int(coarse_lds_bytes<float>(H));
@@ -1746,81 +1900,81 @@ void prepare_coarse(const Hierarchy& H) {
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 4>), b32);
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 8>), b32);
   allow(reinterpret_cast<const void*>(&k_coarse_cycle<float, 0>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 1, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 1, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 2, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 2, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 3, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 3, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 4, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 4, 4, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 1, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 1, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 2, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 2, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 3, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 3, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 4, 1>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<double, 8, 4, 2>), b64);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 1, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 1, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 2, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 2, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 3, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 3, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 4, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 4, 4, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 1, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 1, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 2, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 2, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 3, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 3, 2>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 4, 1>), b32);
-  allow(reinterpret_cast<const void*>(&k_coarse_cycle_reg<float, 8, 4, 2>), b32);
+  allow_reg<double, 4>(b64);
+  allow_reg<double, 8>(b64);
+  allow_reg<float, 4>(b32);
+  allow_reg<float, 8>(b32);
 }
 
-template <typename T, int K, int NL, int RPT>
-static void launch_coarse_cycle_reg(const Hierarchy& H, const T* b, T* x, double omega, int nu1,
-                                    int nu2, const int* done, hipStream_t s) {
+template <typename T, int K, int NL, int RPT, bool GEN>
+static void launch_coarse_cycle_reg(const Hierarchy& H, const T* b, T* x, bool x_init,
+                                    double omega, int nu1, int nu2, int kind, bool gs,
+                                    const int* done, hipStream_t s) {
   const size_t bytes = coarse_lds_bytes<T>(H);
   const size_t int_off = coarse_int_offset<T>(H);
   const size_t inv_off = int_off - size_t(H.n0) * H.n0 * sizeof(double);
-  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL, RPT>), dim3(1), dim3(kCoarseThreads), bytes, s,
-                     coarse_levels<T>(H), H.coarse_inv, H.n0, int32_t(inv_off), b, x,
-                     static_cast<T>(omega), nu1, nu2, done);
+  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL, RPT, GEN>), dim3(1), dim3(kCoarseThreads),
+                     bytes, s, coarse_levels<T>(H), H.coarse_inv, H.n0, int32_t(inv_off), b, x,
+                     x_init ? 1 : 0, static_cast<T>(omega), nu1, nu2, kind, gs ? 1 : 0, done);
 }
-template <typename T, int K, int RPT>
-static bool coarse_cycle_reg(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1,
-                             int nu2, const int* done, hipStream_t s) {
+template <typename T, int K, int RPT, bool GEN>
+static void coarse_cycle_reg(const Hierarchy& H, int top, const T* b, T* x, bool x_init,
+                             double omega, int nu1, int nu2, int kind, bool gs, const int* done,
+                             hipStream_t s) {
   switch (top) {
-    case 1: launch_coarse_cycle_reg<T, K, 1, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
-    case 2: launch_coarse_cycle_reg<T, K, 2, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
-    case 3: launch_coarse_cycle_reg<T, K, 3, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
-    case 4: launch_coarse_cycle_reg<T, K, 4, RPT>(H, b, x, omega, nu1, nu2, done, s); return true;
-    default: return false;
+    case 1: launch_coarse_cycle_reg<T, K, 1, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
+    case 2: launch_coarse_cycle_reg<T, K, 2, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
+    case 3: launch_coarse_cycle_reg<T, K, 3, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
+    default: launch_coarse_cycle_reg<T, K, 4, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
   }
+}
+template <typename T, bool GEN>
+static void coarse_cycle_regs(const Hierarchy& H, int top, const T* b, T* x, bool x_init,
+                              double omega, int nu1, int nu2, int kind, bool gs, const int* done,
+                              hipStream_t s) {
+  const bool one = H.lv[top]->n <= kCoarseThreads;
+  if (H.coarse_width <= 4) {
+    if (one)
+      coarse_cycle_reg<T, 4, 1, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+    else
+      coarse_cycle_reg<T, 4, 2, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+  } else {
+    if (one)
+      coarse_cycle_reg<T, 8, 1, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+    else
+      coarse_cycle_reg<T, 8, 2, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+  }
+}
+
+template <typename T>
+bool coarse_cycle_general_ok(const Hierarchy& H, int top, bool gs) {
+  // levels below `top` at most one row per thread, `top` itself at most two; narrow rows; a
+  // colouring with few classes for Gauss-Seidel
+  if (top < 1 || top > 4 || top > coarse_top<T>(H)) return false;
+  int below = 0;
+  for (int l = 0; l < top; ++l) below = std::max(below, H.lv[l]->n);
+  if (below > kCoarseThreads || H.lv[top]->n > 2 * kCoarseThreads) return false;
+  if (H.coarse_rwidth > 8 || H.coarse_width > 8) return false;
+  if (gs)
+    for (int l = 1; l <= top; ++l)
+      if (H.lv[l]->gs.empty() || H.lv[l]->gs.size() > 16) return false;
+  return true;
+}
+
+template <typename T>
+void coarse_cycle_general(const Hierarchy& H, int top, const T* b, T* x, bool x_init,
+                          double omega, int nu1, int nu2, int kind, bool gs, const int* done,
+                          hipStream_t s) {
+  coarse_cycle_regs<T, true>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
 }
 
 template <typename T>
 void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2,
                   const int* done, hipStream_t s) {
   const int kmax = H.coarse_width;
-  // levels below `top` must have at most one row per thread, `top` itself at most two
-  int below = 0;
-  for (int l = 0; l < top; ++l) below = std::max(below, H.lv[l]->n);
-  const int at_top = H.lv[top]->n;
-  if (below <= kCoarseThreads && at_top <= 2 * kCoarseThreads && H.coarse_rwidth <= 8 &&
-      kmax <= 8) {
-    const bool one = at_top <= kCoarseThreads;
-    bool ok;
-    if (kmax <= 4)
-      ok = one ? coarse_cycle_reg<T, 4, 1>(H, top, b, x, omega, nu1, nu2, done, s)
-               : coarse_cycle_reg<T, 4, 2>(H, top, b, x, omega, nu1, nu2, done, s);
-    else
-      ok = one ? coarse_cycle_reg<T, 8, 1>(H, top, b, x, omega, nu1, nu2, done, s)
-               : coarse_cycle_reg<T, 8, 2>(H, top, b, x, omega, nu1, nu2, done, s);
-    if (ok) return;
+  if (coarse_cycle_general_ok<T>(H, top, false)) {
+    coarse_cycle_regs<T, false>(H, top, b, x, false, omega, nu1, nu2, MG_CYCLE_V, false, done, s);
+    return;
   }
   if (kmax <= 4)
     launch_coarse_cycle<T, 4>(H, top, b, x, omega, nu1, nu2, done, s);
@@ -1985,6 +2139,9 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
   template void coarse<T>(const Hierarchy&, const T*, T*, const int*, hipStream_t);             \
   template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
                                 hipStream_t);                                                  \
+  template bool coarse_cycle_general_ok<T>(const Hierarchy&, int, bool);                         \
+  template void coarse_cycle_general<T>(const Hierarchy&, int, const T*, T*, bool, double, int,  \
+                                        int, int, bool, const int*, hipStream_t);                \
   template void fill<T>(T*, int64_t, T, hipStream_t);                                          \
   template void gather<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                 \
   template void scatter<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                \

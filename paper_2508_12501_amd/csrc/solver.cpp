@@ -67,7 +67,6 @@ static T* coarse_correction(Hierarchy& H, int l, const T* bc, const mg_opts& o, 
   return ec;
 }
 
-// `steps` steps of the CG smoother on level l, in place on x (r, p, q in the level's r, t, u).
 // b_c = M(f) (b - A x) as two passes (residual into V.r, then the restriction).  A fused
 // coarse-row-centric pass was measured slower even on launch-bound levels: each coarse row
 // walks up to seven fine rows, and the dependent index, operator and gather loads of each
@@ -79,6 +78,7 @@ static void restrict_residual(Level& L, Level& C, LevelVecs<T>& V, const T* x, c
   k::restrict_<T>(L, C, V.r, vecs<T>(C).b, done, s);
 }
 
+// `steps` steps of the CG smoother on level l, in place on x (r, p, q in the level's r, t, u).
 template <typename T>
 static void cg_smooth(Hierarchy& H, int l, T* x, const T* b, int steps, const int* done,
                       hipStream_t s) {
@@ -135,6 +135,14 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
   if (!x_init && kind == MG_CYCLE_V && !gs && l <= coarse_top<T>(H)) {
     k::coarse_cycle<T>(H, l, b, V.x, o.omega, o.nu1, o.nu2, done, s);
     return V.x;
+  }
+  if (k::coarse_cycle_general_ok<T>(H, l, gs)) {
+    // the whole bottom of a W- or F-cycle, a Gauss-Seidel cycle or a cycle from a given
+    // iterate in one launch (in place on x_init)
+    T* xo = x_init ? x_init : V.x;
+    k::coarse_cycle_general<T>(H, l, b, xo, x_init != nullptr, o.omega, o.nu1, o.nu2, kind, gs,
+                               done, s);
+    return xo;
   }
   T *cur, *oth;
   int pre = o.nu1;

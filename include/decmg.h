@@ -123,6 +123,9 @@ typedef struct {
   int32_t index_bytes;   /* bytes per stored column index of the device operator (2 or 4) */
   int32_t scheme;        /* how the level was made: 0 base, 1 binary, 2 cubic subdivision,
                             3 a given geometric map (mg_hierarchy_build_maps) */
+  int32_t fused_tiles;   /* workgroup tiles of the fused cycle legs (mg_opts.fuse_levels), or 0
+                            when the level runs one launch per step */
+  int32_t fused_tile_rows;  /* rows the tiles hold in total, own rows and overlap */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 
@@ -238,7 +241,10 @@ typedef struct {
   int32_t use_graph;     /* replay the iteration as a hipGraph (1) */
   int32_t cycle;         /* MG_CYCLE_V, MG_CYCLE_W or MG_CYCLE_F (V) */
   int32_t smoother;      /* MG_SMOOTH_JACOBI, MG_SMOOTH_GS or MG_SMOOTH_CG (Jacobi) */
-  int32_t reserved;
+  int32_t fuse_levels;   /* 1: on binary levels of at most 2^19 unknowns, weighted-Jacobi
+                            cycles run the smoothing, residual and transfers of each leg in one
+                            launch over overlapping workgroup tiles (same results bit for bit);
+                            0: one launch per step (1) */
 } mg_opts;
 void mg_opts_default(mg_opts* o);
 

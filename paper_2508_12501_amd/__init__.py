@@ -55,7 +55,8 @@ class mg_level_info(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("level", ctypes.c_int32),
                 ("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nt", ctypes.c_int64),
                 ("n_unknowns", ctypes.c_int64), ("nnz_operator", ctypes.c_int64),
-                ("index_bytes", ctypes.c_int32), ("scheme", ctypes.c_int32)]
+                ("index_bytes", ctypes.c_int32), ("scheme", ctypes.c_int32),
+                ("fused_tiles", ctypes.c_int32), ("fused_tile_rows", ctypes.c_int32)]
 
 
 class mg_opts(ctypes.Structure):
@@ -64,7 +65,7 @@ class mg_opts(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("fuse_levels", ctypes.c_int32)]
 
 
 class mg_result(ctypes.Structure):

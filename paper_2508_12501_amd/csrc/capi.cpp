@@ -78,6 +78,7 @@ mg_status check_opts(const mg_opts* o) {
   if (o->smoother != MG_SMOOTH_JACOBI && o->smoother != MG_SMOOTH_GS &&
       o->smoother != MG_SMOOTH_CG)
     return fail(MG_EINVAL, "smoother must be MG_SMOOTH_JACOBI, MG_SMOOTH_GS or MG_SMOOTH_CG");
+  if (o->fuse_levels != 0 && o->fuse_levels != 1) return fail(MG_EINVAL, "fuse_levels must be 0 or 1");
   return MG_OK;
 }
 
@@ -320,6 +321,8 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->nnz_operator = L.nnz;
   out->index_bytes = L.op.col16 ? 2 : 4;
   out->scheme = L.mesh.scheme;
+  out->fused_tiles = L.tiles.ntiles;
+  out->fused_tile_rows = int32_t(L.tiles.rows_total);
   return MG_OK;
 }
 
@@ -469,6 +472,7 @@ void mg_opts_default(mg_opts* o) {
   o->max_iter = 200;
   o->check_every = 4;
   o->use_graph = 1;
+  o->fuse_levels = 1;
 }
 
 mg_status mg_vcycle(mg_hierarchy* h, const mg_opts* o, int32_t level, int32_t dtype, const void* b,

@@ -69,6 +69,35 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   float* rw32 = nullptr;
 };
 
+// Workgroup tiles of the fused smoothing kernels of one launch-bound binary level (l >= 1).
+// Tile b owns up to kBlock consecutive rows of the level's Morton order (F) and the coarse rows
+// whose kept vertex lies in F.  Its local rows are F, then the fine rows its coarse rows
+// restrict from (R0 = F + those), then the operator neighbours of R0 (R1), then theirs (R2),
+// each group in ascending internal order.  Everything a cycle leg needs from those rings is
+// recomputed in LDS, so the down leg (Jacobi sweeps from zero, residual, restriction) and the
+// up leg (interpolation, sweeps) are one launch each.  Every tile has the same capacity (cap
+// local rows, ccap coarse rows; padding repeats a valid id), so a workgroup issues all of its
+// index loads at once; local id cap is the zero slot.
+struct DevTiles {
+  int32_t ntiles = 0;
+  int32_t kt = 0;              // local column slots per row (4 or 8)
+  int32_t cap = 0, ccap = 0;   // local rows / coarse rows per tile (multiples of 64)
+  int64_t rows_total = 0;      // sum of n2 over the tiles
+  int32_t* meta = nullptr;     // per tile 8 ints: nF, n0, n1, n2, ncb, 0, 0, 0
+  int32_t* row = nullptr;      // [tile][cap]: internal row id
+  int32_t* ent = nullptr;      // [tile][cap]: (SELL index of entry 0) << 4 | width; null when
+                               // the level's slices are uniform (index computed from the row)
+  int16_t* col = nullptr;      // [tile][kt][cap]: local id of entry k (zero slot past the width)
+  int32_t* crow = nullptr;     // [tile][ccap]: internal coarse id
+  int16_t* cst = nullptr;      // [tile][9][ccap]: local ids of the kept vertex, then of up to 8
+                               // midpoints (zero slot past the row's width)
+};
+constexpr int kTileRows = 1024;   // local rows per tile (R2) at most
+// The fused up leg reads x, both parents and the right-hand side of every ring row; above this
+// many rows that traffic costs more than the launch it saves (C3: 9.7 us fused against 4.8 +
+// 3.4 us for the two launches at 261k rows), so larger tiled levels fuse the down leg only.
+constexpr int32_t kTileUpRows = 1 << 17;
+
 // Levels up to this many rows are launch-bound: there the interpolation is fused into the
 // first post-smoothing sweep (one launch fewer); on larger levels the extra dependent gathers
 // of the fused kernel cost more than the separate pass.
@@ -146,6 +175,7 @@ struct Level {
   int32_t* row_color = nullptr;    // n + 1: colour class of each internal row (device)
   CgsScalars* cgs = nullptr;
   DevTransfer tr;                  // valid for l >= 1
+  DevTiles tiles;                  // fused smoothing tiles (ntiles == 0: none)
   LevelVecs<double> v64;
   LevelVecs<float> v32;
 };
@@ -262,10 +292,16 @@ template <typename T> void gs_color(const Level& L, int c, T* x, const T* b, con
 template <typename T> void prolong_sweep(const Level& Lf, const Level& Lc, const T* ec, const T* x, const T* b, T* xo, double omega, const int* done, hipStream_t s);
 template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const int* done, hipStream_t s);
 template <typename T> void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2, const int* done, hipStream_t s);
+// Fused down leg of a tiled level from x = 0: nu1 (<= 2) Jacobi sweeps into x, and the
+// restriction of the residual into bc (the coarse right-hand side)
+template <typename T> void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done, hipStream_t s);
+// Fused up leg of a tiled level: xo = nu2 (1 or 2) Jacobi sweeps of x + M(f)^T ec
+template <typename T> void tile_up(const Level& L, const T* ec, const T* x, const T* b, T* xo, double omega, int nu2, const int* done, hipStream_t s);
 // whether levels top..0 fit the one-workgroup register-resident cycle of any shape and smoother
 template <typename T> bool coarse_cycle_general_ok(const Hierarchy& H, int top, bool gs);
 // one cycle of shape `kind` on levels top..0 in one launch, from zero or (x_init) from x, in place
 template <typename T> void coarse_cycle_general(const Hierarchy& H, int top, const T* b, T* x, bool x_init, double omega, int nu1, int nu2, int kind, bool gs, const int* done, hipStream_t s);
+template <typename T> void copy(const T* src, T* dst, int32_t n, const int* done, hipStream_t s);
 template <typename T> void fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T> void gather(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);
 template <typename T> void scatter(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);

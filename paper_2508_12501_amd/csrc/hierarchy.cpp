@@ -2,6 +2,7 @@
 // lists, the coarsest dense inverse and device upload.  Host code, compiled with
 // -ffp-contract=off so that host sums match the kernels' plain IEEE order.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -586,6 +587,182 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
   dev = upload(hv);
 }
 
+template <typename T>
+std::vector<T> download(const T* d, size_t n) {
+  std::vector<T> h(n);
+  if (n) check_hip(hipMemcpy(h.data(), d, n * sizeof(T), hipMemcpyDeviceToHost), "hipMemcpy");
+  return h;
+}
+
+// Workgroup tiles of the fused smoothing kernels of binary level F over its coarse level C
+// (see DevTiles).  Leaves F.tiles empty when a row or restriction list is wider than 8 or a
+// tile's rings exceed kTileRows rows; the level then runs one kernel per step.
+void build_tiles(Level& F, const Level& C) {
+  const int32_t n = F.n, nc = C.n;
+  if (n == 0 || nc == 0 || F.tr.weighted || n > kLaunchBoundRows) return;
+  const int32_t nsl = int32_t(F.sptr_h.size()) - 1;
+  int32_t wmax = 0;
+  for (int32_t s = 0; s < nsl; ++s) wmax = std::max(wmax, F.sptr_h[s + 1] - F.sptr_h[s]);
+  if (wmax > 8) return;
+  const int kt = wmax <= 4 ? 4 : 8;
+  // restriction lists (device layout) and the coarse row of every kept fine row
+  const std::vector<int32_t> self = download(F.tr.r_self, size_t(nc) + 1);
+  const std::vector<int32_t> rsptr = download(F.tr.r_sptr, size_t(F.tr.nslices) + 1);
+  const std::vector<int32_t> rcol = download(F.tr.r_col, size_t(rsptr.back() + 1) * kSlice);
+  std::vector<int32_t> own(n, -1);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (self[c] < 0 || self[c] >= n || own[self[c]] >= 0)
+      throw std::logic_error("restriction: kept vertices are not distinct fine rows");
+    own[self[c]] = c;
+    if (rsptr[c / kSlice + 1] - rsptr[c / kSlice] > 8) return;
+  }
+  auto rwidth = [&](int32_t c) { return rsptr[c / kSlice + 1] - rsptr[c / kSlice]; };
+  auto rentry = [&](int32_t c, int k) {
+    return rcol[size_t(rsptr[c / kSlice] + k) * kSlice + size_t(c % kSlice)];
+  };
+  // Morton order of the rows: runs of kBlock consecutive rows are compact patches
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int32_t r = 0; r < n; ++r)
+    for (int c = 0; c < 3; ++c) {
+      lo[c] = std::min(lo[c], F.mesh.xyz[3 * size_t(F.perm_h[r]) + c]);
+      hi[c] = std::max(hi[c], F.mesh.xyz[3 * size_t(F.perm_h[r]) + c]);
+    }
+  std::vector<std::pair<uint64_t, int32_t>> key(n);
+  for (int32_t r = 0; r < n; ++r) {
+    uint32_t q[3];
+    for (int c = 0; c < 3; ++c) {
+      const double span = hi[c] - lo[c];
+      const double u = span > 0 ? (F.mesh.xyz[3 * size_t(F.perm_h[r]) + c] - lo[c]) / span : 0.0;
+      q[c] = uint32_t(std::min(1048575.0, std::floor(u * 1048576.0)));
+    }
+    key[r] = {morton3(q[0], q[1], q[2]), r};
+  }
+  std::sort(key.begin(), key.end());
+  auto width = [&](int32_t r) { return F.sptr_h[r / kSlice + 1] - F.sptr_h[r / kSlice]; };
+  auto entry = [&](int32_t r, int k) {   // SELL index of entry k of row r
+    return size_t(F.sptr_h[r / kSlice] + k) * kSlice + size_t(r % kSlice);
+  };
+  // pass 1: the rings of every tile
+  const int32_t ntiles = (n + kBlock - 1) / kBlock;
+  std::vector<std::vector<int32_t>> trows(ntiles), tcown(ntiles);
+  std::vector<std::array<int32_t, 5>> cnt(ntiles);   // nF, n0, n1, n2, ncb
+  std::vector<int32_t> lid(n, -1), fresh;
+  int32_t cap = 0, ccap = 0;
+  for (int32_t b = 0; b < ntiles; ++b) {
+    std::vector<int32_t>& rows = trows[b];
+    auto add_group = [&]() {
+      std::sort(fresh.begin(), fresh.end());
+      fresh.erase(std::unique(fresh.begin(), fresh.end()), fresh.end());
+      for (int32_t r : fresh)
+        if (lid[r] < 0) {
+          lid[r] = int32_t(rows.size());
+          rows.push_back(r);
+        }
+      fresh.clear();
+    };
+    const int32_t r0 = b * kBlock, r1 = std::min(n, r0 + kBlock);
+    for (int32_t i = r0; i < r1; ++i) fresh.push_back(key[i].second);
+    add_group();
+    const int32_t nF = int32_t(rows.size());
+    std::vector<int32_t>& cown = tcown[b];
+    for (int32_t i = 0; i < nF; ++i)
+      if (own[rows[i]] >= 0) cown.push_back(own[rows[i]]);
+    std::sort(cown.begin(), cown.end());
+    for (int32_t c : cown)
+      for (int k = 0; k < rwidth(c); ++k)
+        if (rentry(c, k) < n) fresh.push_back(rentry(c, k));
+    add_group();
+    const int32_t n0 = int32_t(rows.size());
+    auto ring = [&](int32_t upto) {
+      for (int32_t i = 0; i < upto; ++i)
+        for (int k = 0; k < width(rows[i]); ++k) {
+          const int32_t j = F.col_h[entry(rows[i], k)];
+          if (j < n) fresh.push_back(j);
+        }
+      add_group();
+    };
+    ring(n0);
+    const int32_t n1 = int32_t(rows.size());
+    ring(n1);
+    const int32_t n2 = int32_t(rows.size());
+    for (int32_t r : rows) lid[r] = -1;
+    cnt[b] = {nF, n0, n1, n2, int32_t(cown.size())};
+    cap = std::max(cap, n2);
+    ccap = std::max(ccap, int32_t(cown.size()));
+  }
+  cap = (cap + 63) / 64 * 64;
+  ccap = std::max(64, (ccap + 63) / 64 * 64);
+  if (cap > kTileRows || ccap > kBlock) return;   // not compact: per-step kernels
+  // pass 2: fixed-capacity arrays (padding: the tile's first row / coarse row, zero slot cap)
+  const bool uniform = F.op.uw >= 0;
+  std::vector<int32_t> meta(size_t(ntiles) * 8, 0), trow(size_t(ntiles) * cap),
+      tent(uniform ? 0 : size_t(ntiles) * cap), tcrow(size_t(ntiles) * ccap, 0);
+  std::vector<int16_t> tcol(size_t(ntiles) * kt * cap, int16_t(cap)),
+      tcst(size_t(ntiles) * 9 * ccap, int16_t(cap));
+  std::vector<char> fine_seen(n, 0), coarse_seen(nc, 0);
+  for (int32_t b = 0; b < ntiles; ++b) {
+    const std::vector<int32_t>& rows = trows[b];
+    const std::vector<int32_t>& cown = tcown[b];
+    const auto [nF, n0, n1, n2, ncb] = cnt[b];
+    (void)n0;
+    for (int q = 0; q < 5; ++q) meta[size_t(b) * 8 + q] = cnt[b][q];
+    for (int32_t i = 0; i < n2; ++i) lid[rows[i]] = i;
+    for (int32_t i = 0; i < cap; ++i) {
+      const int32_t r = rows[i < n2 ? i : 0];
+      trow[size_t(b) * cap + i] = r;
+      if (!uniform) {
+        const size_t e0 = entry(r, 0);
+        if (e0 >= (size_t(1) << 27)) throw std::logic_error("tiles: entry index overflow");
+        tent[size_t(b) * cap + i] = int32_t(e0 << 4) | width(r);
+      }
+    }
+    for (int k = 0; k < kt; ++k)
+      for (int32_t i = 0; i < n1; ++i) {
+        const int32_t r = rows[i];
+        if (k >= width(r)) continue;
+        const int32_t j = F.col_h[entry(r, k)];
+        tcol[(size_t(b) * kt + k) * cap + i] = int16_t(j < n ? lid[j] : cap);
+      }
+    for (int32_t j = 0; j < ccap; ++j) tcrow[size_t(b) * ccap + j] = ncb ? cown[j < ncb ? j : 0] : 0;
+    for (int32_t j = 0; j < ncb; ++j) {
+      const int32_t c = cown[j];
+      tcst[size_t(b) * 9 * ccap + j] = int16_t(lid[self[c]]);
+      for (int k = 0; k < rwidth(c); ++k)
+        tcst[(size_t(b) * 9 + k + 1) * ccap + j] = int16_t(rentry(c, k) < n ? lid[rentry(c, k)] : cap);
+      coarse_seen[c]++;
+    }
+    for (int32_t i = 0; i < nF; ++i) fine_seen[rows[i]]++;
+    for (int32_t r : rows) lid[r] = -1;
+  }
+  // every fine row is written by one tile, every coarse row restricted by one, and every
+  // local id stays inside the tile's LDS rows or names its zero slot
+  for (int32_t r = 0; r < n; ++r)
+    if (fine_seen[r] != 1) throw std::logic_error("tiles: fine rows not partitioned");
+  for (int32_t c = 0; c < nc; ++c)
+    if (coarse_seen[c] != 1) throw std::logic_error("tiles: coarse rows not partitioned");
+  for (int16_t v : tcol)
+    if (v < 0 || v > cap) throw std::logic_error("tiles: local column out of range");
+  for (int16_t v : tcst)
+    if (v < 0 || v > cap) throw std::logic_error("tiles: local restriction id out of range");
+  for (int32_t r : trow)
+    if (r < 0 || r >= n) throw std::logic_error("tiles: row id out of range");
+  for (int32_t c : tcrow)
+    if (c < 0 || c >= nc) throw std::logic_error("tiles: coarse row id out of range");
+  DevTiles& T = F.tiles;
+  T.ntiles = ntiles;
+  T.kt = kt;
+  T.cap = cap;
+  T.ccap = ccap;
+  T.rows_total = 0;
+  for (const auto& c : cnt) T.rows_total += c[3];
+  T.meta = upload(meta);
+  T.row = upload(trow);
+  T.ent = uniform ? nullptr : upload(tent);
+  T.col = upload(tcol);
+  T.crow = upload(tcrow);
+  T.cst = upload(tcst);
+}
+
 }  // namespace
 
 void upload_weights(Hierarchy& H) {
@@ -724,6 +901,7 @@ Hierarchy* build_levels(std::unique_ptr<Hierarchy> H, std::vector<Mesh> meshes,
   build_coarse_levels(*H, H->clv64, H->ctop64, H->clds64, H->cint_off64, H->clds_total64);
   build_coarse_levels(*H, H->clv32, H->ctop32, H->clds32, H->cint_off32, H->clds_total32);
   k::prepare_coarse(*H);
+  for (size_t l = 1; l < H->lv.size(); ++l) build_tiles(*H->lv[l], *H->lv[l - 1]);
   // Krylov workspace on the finest level
   const int32_t n = H->lv.back()->n;
   H->sx = zeros<double>(n + 1);
@@ -765,6 +943,9 @@ Hierarchy::~Hierarchy() {
       for (void* p : {(void*)G.rowid, (void*)G.sptr, (void*)G.col, (void*)G.w64, (void*)G.w32})
         free_dev(p);
     free_dev(L.row_color);
+    for (void* p : {(void*)L.tiles.meta, (void*)L.tiles.row, (void*)L.tiles.ent,
+                    (void*)L.tiles.col, (void*)L.tiles.crow, (void*)L.tiles.cst})
+      free_dev(p);
   }
   for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
                   (void*)sb, (void*)part, (void*)scal})

@@ -81,6 +81,13 @@ __device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int
   return static_cast<const int32_t*>(col)[idx];
 }
 
+// a * b + c with one rounding.  Every operator row accumulates its entries through this, so a
+// row's result does not depend on which products the compiler happens to contract (it leaves
+// a product unfused where accumulators of several code paths merge), and the fused cycle legs
+// reproduce the per-step kernels bit for bit.
+__device__ __forceinline__ double mac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float mac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Launch-bound kernels (n <= kLaunchBoundRows) issue the load of the convergence flag with their
 // other first loads and test it only before their stores, which takes a dependent memory round
 // trip off their critical path; large launches test it first, so a replay after convergence
@@ -127,7 +134,7 @@ __device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const 
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     d += wk[k];
-    acc += wk[k] * (xi - xj[k]);
+    acc = mac(wk[k], xi - xj[k], acc);
   }
 }
 
@@ -156,7 +163,7 @@ __device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr, int 
         const int idx = (beg + k) * kSlice + lane;
         const T wk = w[idx];
         d += wk;
-        acc += wk * (xi - x[col_at<D16>(col, idx, row, n)]);
+        acc = mac(wk, xi - x[col_at<D16>(col, idx, row, n)], acc);
       }
   }
 }
@@ -183,7 +190,7 @@ __device__ __forceinline__ void row_two_n(const void* __restrict__ col, const WT
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     d += wk[k];
-    acc += wk[k] * (xi - omega * bj[k] / dj[k]);
+    acc = mac(wk[k], xi - omega * bj[k] / dj[k], acc);
   }
 }
 
@@ -240,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict
         const T wk = w[idx];
         const int j = col_at<D16>(col, idx, row, n);
         d += wk;
-        acc += wk * (xi - omega * b[j] / diag[j]);
+        acc = mac(wk, xi - omega * b[j] / diag[j], acc);
       }
   }
   DECMG_DONE_CHECK()
@@ -351,7 +358,7 @@ __device__ __forceinline__ void row_prolong_n(const void* __restrict__ col,
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     d += wk[k];
-    acc += wk[k] * (xi0 - xj[k]);
+    acc = mac(wk[k], xi0 - xj[k], acc);
   }
 }
 
@@ -392,11 +399,227 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
         const T xj = x[j] + T(0.5) * (ec[pa[j]] + ec[pb[j]]);
         const T wk = w[idx];
         d += wk;
-        acc += wk * (xi0 - xj);
+        acc = mac(wk, xi0 - xj, acc);
       }
   }
   DECMG_DONE_CHECK()
   xo[row] = xi0 + omega * (bi - acc) / d;
+}
+
+// ------------------------------------------------------------------ fused smoothing tiles
+// One workgroup per tile of a launch-bound binary level (DevTiles): the values a leg of the
+// cycle needs around the tile's own rows are recomputed in LDS, so the down leg takes one
+// launch instead of three and the up leg one instead of two.  Each value is formed with the
+// expressions and entry order of k_jacobi_two, k_rows, k_restrict and k_prolong_sweep, so the
+// results equal theirs bit for bit.  A thread holds rows t + q kBlock (q < nq) of the tile:
+// index, weight and right-hand-side loads are all issued before the first barrier.
+constexpr int kTileQ = kTileRows / kBlock;
+
+// Row data of local row i: global row g, first SELL entry e0 and width, and (rows of R1) the
+// weights and local columns of its entries.
+template <typename T, typename WT, int KT>
+__device__ __forceinline__ void tile_row(int g, int i, int cap, const int32_t* __restrict__ tent,
+                                         int uw, const int16_t* __restrict__ tcol,
+                                         const WT* __restrict__ w, int& wid, int (&cj)[KT],
+                                         T (&wk)[KT]) {
+  int e0;
+  if (tent) {
+    const int e = tent[i];
+    e0 = e >> 4;
+    wid = e & 15;
+  } else {
+    e0 = (g >> 6) * uw * kSlice + (g & 63);
+    wid = uw;
+  }
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    cj[k] = tcol[k * cap + i];
+    wk[k] = (k < wid) ? static_cast<T>(w[e0 + k * kSlice]) : T(0);
+  }
+}
+
+template <typename T, typename WT, int KT>
+__global__ __launch_bounds__(kBlock) void k_tile_down(
+    const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
+    const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol,
+    const int32_t* __restrict__ tcrow, const int16_t* __restrict__ tcst, int32_t cap,
+    int32_t ccap, int32_t uw, const WT* __restrict__ w, const T* __restrict__ diag,
+    const T* __restrict__ b, T* __restrict__ x, T* __restrict__ bc, T omega, int nu1,
+    const int* __restrict__ done) {
+  __shared__ T s1[kTileRows + 1], s2[kTileRows + 1], sr[kTileRows + 1];
+  const int dn = done ? *done : 0;
+  const int tb = xcd_block(), t = threadIdx.x;
+  const int32_t* m = meta + 8 * tb;
+  const int nF = m[0], n0 = m[1], n1 = m[2], n2 = m[3], ncb = m[4];
+  const int nq = (cap + kBlock - 1) / kBlock;
+  const int32_t* rows = trow + static_cast<int64_t>(tb) * cap;
+  const int32_t* ents = tent ? tent + static_cast<int64_t>(tb) * cap : nullptr;
+  const int16_t* cols = tcol + static_cast<int64_t>(tb) * KT * cap;
+  int g[kTileQ], wid[kTileQ], cj[kTileQ][KT];
+  T wk[kTileQ][KT], bq[kTileQ], x1[kTileQ];
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < cap) {
+      g[q] = rows[i];
+      tile_row<T, WT, KT>(g[q], i, cap, ents, uw, cols, w, wid[q], cj[q], wk[q]);
+      bq[q] = b[g[q]];
+      x1[q] = omega * bq[q] / diag[g[q]];
+    }
+  }
+  // restriction rows: one per thread at most (ccap <= kBlock)
+  int crow = 0, cs[9];
+  {
+    const int j = min(t, ccap - 1);
+    crow = tcrow[static_cast<int64_t>(tb) * ccap + j];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) cs[k] = tcst[(static_cast<int64_t>(tb) * 9 + k) * ccap + j];
+  }
+  // x1 = omega b / D on every local row (the first sweep from zero is local)
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < n2) s1[i] = (nu1 >= 1) ? x1[q] : T(0);
+  }
+  if (t == 0) {
+    s1[cap] = T(0);
+    s2[cap] = T(0);
+    sr[cap] = T(0);
+  }
+  __syncthreads();
+  // x2 on R1 (second sweep, k_jacobi_two), or x = 0 / x1 on R1
+  const T* xc = s1;
+  if (nu1 == 2) {
+#pragma unroll
+    for (int q = 0; q < kTileQ; ++q) {
+      const int i = t + q * kBlock;
+      if (q < nq && i < n1) {
+        const T xi = x1[q];
+        T acc = T(0), d = T(0);
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < wid[q]) {
+            d += wk[q][k];
+            acc = mac(wk[q][k], xi - s1[cj[q][k]], acc);
+          }
+        s2[i] = xi + omega * (bq[q] - acc) / d;
+      }
+    }
+    __syncthreads();
+    xc = s2;
+  }
+  // residual on R0 (k_rows, mode 1); the tile's own rows of x go out
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < n0) {
+      const T xi = xc[i];
+      T acc = T(0);
+#pragma unroll
+      for (int k = 0; k < KT; ++k)
+        if (k < wid[q]) acc = mac(wk[q][k], xi - xc[cj[q][k]], acc);
+      sr[i] = bq[q] - acc;
+      if (i < nF && !dn) x[g[q]] = xi;
+    }
+  }
+  __syncthreads();
+  // restriction of the residual onto the tile's coarse rows (k_restrict)
+  if (t < ncb && !dn) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 1; k < 9; ++k) acc += sr[cs[k]];
+    bc[crow] = sr[cs[0]] + T(0.5) * acc;
+  }
+}
+
+template <typename T, typename WT, int KT>
+__global__ __launch_bounds__(kBlock) void k_tile_up(
+    const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
+    const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol, int32_t cap,
+    int32_t uw, const WT* __restrict__ w, const int32_t* __restrict__ pa,
+    const int32_t* __restrict__ pb, const T* __restrict__ ec, const T* __restrict__ x,
+    const T* __restrict__ b, T* __restrict__ xo, T omega, int nu2,
+    const int* __restrict__ done) {
+  __shared__ T s0[kTileRows + 1], s1[kTileRows + 1];
+  const int dn = done ? *done : 0;
+  const int tb = xcd_block(), t = threadIdx.x;
+  const int32_t* m = meta + 8 * tb;
+  const int nF = m[0], n1 = m[2], n2 = m[3];
+  const int nq = (cap + kBlock - 1) / kBlock;
+  const int32_t* rows = trow + static_cast<int64_t>(tb) * cap;
+  const int32_t* ents = tent ? tent + static_cast<int64_t>(tb) * cap : nullptr;
+  const int16_t* cols = tcol + static_cast<int64_t>(tb) * KT * cap;
+  int g[kTileQ], wid[kTileQ], cj[kTileQ][KT];
+  T wk[kTileQ][KT], bq[kTileQ], xq[kTileQ];
+  int ia[kTileQ], ib[kTileQ];
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < cap) {
+      g[q] = rows[i];
+      tile_row<T, WT, KT>(g[q], i, cap, ents, uw, cols, w, wid[q], cj[q], wk[q]);
+      bq[q] = b[g[q]];
+      xq[q] = x[g[q]];
+      ia[q] = pa[g[q]];
+      ib[q] = pb[g[q]];
+    }
+  }
+  // x0 = x + M(f)^T ec on every local row (k_prolong_sweep's rounding)
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < n2) {
+      xq[q] = xq[q] + T(0.5) * (ec[ia[q]] + ec[ib[q]]);
+      s0[i] = xq[q];
+    }
+  }
+  if (t == 0) {
+    s0[cap] = T(0);
+    s1[cap] = T(0);
+  }
+  __syncthreads();
+  // first sweep on R1 (k_prolong_sweep)
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < n1) {
+      const T xi = xq[q];
+      T acc = T(0), d = T(0);
+#pragma unroll
+      for (int k = 0; k < KT; ++k)
+        if (k < wid[q]) {
+          d += wk[q][k];
+          acc = mac(wk[q][k], xi - s0[cj[q][k]], acc);
+        }
+      xq[q] = xi + omega * (bq[q] - acc) / d;
+      s1[i] = xq[q];
+    }
+  }
+  if (nu2 == 2) {
+    __syncthreads();
+    // second sweep on the tile's own rows (k_rows, mode 2)
+#pragma unroll
+    for (int q = 0; q < kTileQ; ++q) {
+      const int i = t + q * kBlock;
+      if (q < nq && i < nF) {
+        const T xi = xq[q];
+        T acc = T(0), d = T(0);
+#pragma unroll
+        for (int k = 0; k < KT; ++k)
+          if (k < wid[q]) {
+            d += wk[q][k];
+            acc = mac(wk[q][k], xi - s1[cj[q][k]], acc);
+          }
+        xq[q] = xi + omega * (bq[q] - acc) / d;
+      }
+    }
+  }
+  if (dn) return;
+#pragma unroll
+  for (int q = 0; q < kTileQ; ++q) {
+    const int i = t + q * kBlock;
+    if (q < nq && i < nF) xo[g[q]] = xq[q];
+  }
 }
 
 // ------------------------------------------------------------------ CG smoother
@@ -646,7 +869,7 @@ __device__ __forceinline__ void cc_sweep(const CoarseLevel<T>& L, const int32_t*
         const int idx = k * kSlice + lane;
         const T wk = L.w[idx];
         d += wk;
-        acc += wk * (xi - cx[L.col[idx]]);
+        acc = mac(wk, xi - cx[L.col[idx]], acc);
       }
       out[r] = (mode == 2) ? xi + omega * (B[r] - acc) / d : B[r] - acc;
     }
@@ -681,7 +904,7 @@ __device__ __forceinline__ void cc_sweep(const CoarseLevel<T>& L, const int32_t*
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         d += wv[q][k];
-        acc += wv[q][k] * (xi - cx[c[q][k]]);
+        acc = mac(wv[q][k], xi - cx[c[q][k]], acc);
       }
       if (r0 + q * nt < n)
         out[row[q]] = (mode == 2) ? xi + omega * (B[row[q]] - acc) / d : B[row[q]] - acc;
@@ -916,7 +1139,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           d += wv[L][q][k];
-          acc += wv[L][q][k] * (xi - cx[cj[L][q][k]]);
+          acc = mac(wv[L][q][k], xi - cx[cj[L][q][k]], acc);
         }
         out[r] = (mode == 2) ? xi + omega * (B[r] - acc) / d : B[r] - acc;
       }
@@ -938,7 +1161,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
 #pragma unroll
           for (int k = 0; k < K; ++k) {
             d += wv[L][q][k];
-            acc += wv[L][q][k] * (xi - cx[cj[L][q][k]]);
+            acc = mac(wv[L][q][k], xi - cx[cj[L][q][k]], acc);
           }
           cx[r] = xi + (B[r] - acc) / d;
         }
@@ -1092,6 +1315,18 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
   }
   const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
   for (int i = t; i < lv[NL].n; i += nt) x_io[i] = xs[i];
+}
+
+// dst = src (a no-op once `done` is set, like the kernels that produced src)
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(const T* __restrict__ src, T* __restrict__ dst,
+                                                 int32_t n, const int* __restrict__ done) {
+  DECMG_DONE_LOAD(n)
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T v = src[i];
+  DECMG_DONE_CHECK()
+  dst[i] = v;
 }
 
 template <typename T>
@@ -1799,6 +2034,40 @@ void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x
   });
 }
 template <typename T>
+void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done,
+               hipStream_t s) {
+  const DevTiles& D = L.tiles;
+  if (D.ntiles == 0) throw std::logic_error("tile_down on a level without tiles");
+  with_weights<T>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (D.kt == 4)
+      hipLaunchKernelGGL((k_tile_down<T, WT, 4>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
+                         D.row, D.ent, D.col, D.crow, D.cst, D.cap, D.ccap, L.op.uw, w,
+                         diagonal<T>(L), b, x, bc, static_cast<T>(omega), nu1, done);
+    else
+      hipLaunchKernelGGL((k_tile_down<T, WT, 8>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
+                         D.row, D.ent, D.col, D.crow, D.cst, D.cap, D.ccap, L.op.uw, w,
+                         diagonal<T>(L), b, x, bc, static_cast<T>(omega), nu1, done);
+  });
+}
+template <typename T>
+void tile_up(const Level& L, const T* ec, const T* x, const T* b, T* xo, double omega, int nu2,
+             const int* done, hipStream_t s) {
+  const DevTiles& D = L.tiles;
+  if (D.ntiles == 0) throw std::logic_error("tile_up on a level without tiles");
+  with_weights<T>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (D.kt == 4)
+      hipLaunchKernelGGL((k_tile_up<T, WT, 4>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
+                         D.row, D.ent, D.col, D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
+                         static_cast<T>(omega), nu2, done);
+    else
+      hipLaunchKernelGGL((k_tile_up<T, WT, 8>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
+                         D.row, D.ent, D.col, D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
+                         static_cast<T>(omega), nu2, done);
+  });
+}
+template <typename T>
 void cgs_start(const Level& L, const T* r, T* p, double* part, const int* done, hipStream_t s) {
   if (L.n == 0) return;
   hipLaunchKernelGGL((k_cgs_start<T>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, r, p, part,
@@ -1984,6 +2253,11 @@ void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, i
     launch_coarse_cycle<T, 0>(H, top, b, x, omega, nu1, nu2, done, s);
 }
 template <typename T>
+void copy(const T* src, T* dst, int32_t n, const int* done, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, src, dst, n, done);
+}
+template <typename T>
 void fill(T* p, int64_t n, T v, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, p, n, v);
@@ -2140,8 +2414,13 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
   template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
                                 hipStream_t);                                                  \
   template bool coarse_cycle_general_ok<T>(const Hierarchy&, int, bool);                         \
+  template void tile_down<T>(const Level&, const T*, T*, T*, double, int, const int*,         \
+                             hipStream_t);                                                      \
+  template void tile_up<T>(const Level&, const T*, const T*, const T*, T*, double, int,       \
+                           const int*, hipStream_t);                                           \
   template void coarse_cycle_general<T>(const Hierarchy&, int, const T*, T*, bool, double, int,  \
                                         int, int, bool, const int*, hipStream_t);                \
+  template void copy<T>(const T*, T*, int32_t, const int*, hipStream_t);                        \
   template void fill<T>(T*, int64_t, T, hipStream_t);                                          \
   template void gather<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                 \
   template void scatter<T>(const int32_t*, int32_t, const T*, T*, hipStream_t);                \

@@ -163,7 +163,18 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
       for (int c = nc - 1; c >= 0; --c) k::gs_color<T>(L, c, cur, b, done, s);
     return cur;
   }
-  if (!x_init) {
+  Level& C = *H.lv[l - 1];
+  // launch-bound binary levels with tiles: the down leg from zero (pre-smoothing, residual,
+  // restriction) and the up leg (interpolation, post-smoothing) are one launch each
+  const bool tiled = o.fuse_levels && L.tiles.ntiles > 0;
+  bool restricted = false;
+  if (!x_init && tiled && pre <= 2) {
+    cur = V.x;
+    oth = V.t;
+    k::tile_down<T>(L, b, cur, vecs<T>(C).b, o.omega, pre, done, s);
+    pre = 0;
+    restricted = true;
+  } else if (!x_init) {
     cur = V.x;
     oth = V.t;
     if (pre >= 2) {
@@ -183,12 +194,16 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
     sweep<T>(H, l, cur, b, oth, o.omega, done, s);
     std::swap(cur, oth);
   }
-  Level& C = *H.lv[l - 1];
-  restrict_residual<T>(L, C, V, cur, b, done, s);
+  if (!restricted) restrict_residual<T>(L, C, V, cur, b, done, s);
   const T* bc = vecs<T>(C).b;
   T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
   int post = o.nu2;
-  if (post >= 1 && L.n <= kLaunchBoundRows && !L.tr.weighted) {
+  if (tiled && L.n <= kTileUpRows && (post == 1 || post == 2)) {
+    // the tiles read x around their rows, so the result goes to the partner buffer
+    k::tile_up<T>(L, ec, cur, b, oth, o.omega, post, done, s);
+    std::swap(cur, oth);
+    post = 0;
+  } else if (post >= 1 && L.n <= kLaunchBoundRows && !L.tr.weighted) {
     // the first post-smoothing sweep reads x + P e_c directly (one launch fewer on levels
     // whose kernels are launch-bound; on large levels the extra dependent gathers cost more
     // than the separate interpolation pass)
@@ -299,15 +314,17 @@ void enqueue_cycle(Hierarchy& H, const mg_opts& o, hipStream_t s) {
   Level& F = *H.lv.back();
   const int top = int(H.lv.size()) - 1;
   const int* done = &H.scal->done;
-  // with an even number of sweeps per cycle the ping-pong ends in H.sx (checked by run_mg)
-  (void)vcycle<double>(H, top, H.sb, H.sx, o, done, s);
+  // the cycle ends in H.sx or in the finest level's partner buffer (an odd number of Jacobi
+  // ping-pongs, or a fused up leg), which is copied back
+  const double* xr = vcycle<double>(H, top, H.sb, H.sx, o, done, s);
+  if (xr != H.sx) k::copy<double>(xr, H.sx, F.n, done, s);
   k::residual_norm(F, H.sx, H.sb, H.sr, nullptr, H.scal, H.part, done, s);
   fin(H, k::FIN_CHECK, F.n, false, s, true);
 }
 
 std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
   return std::make_tuple(kind * 16 + o.outer * 4 + o.precision, o.nu1, o.nu2,
-                         o.cycle + 4 * o.smoother, o.omega);
+                         o.cycle + 4 * o.smoother + 16 * (o.fuse_levels ? 1 : 0), o.omega);
 }
 
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
@@ -477,8 +494,6 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
 int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
            hipStream_t s) {
   Level& F = *H.lv.back();
-  if (o.smoother == MG_SMOOTH_JACOBI && (o.nu1 + o.nu2) % 2 != 0)
-    throw std::invalid_argument("mg_solve needs an even number of smoothing sweeps per cycle");
   init_scalars(H, o, s);
   setup_rhs(H, b_nat, s);
   k::fill<double>(H.sx, F.n, 0.0, s);

@@ -70,8 +70,9 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
 };
 
 // Workgroup tiles of the fused smoothing kernels of one launch-bound binary level (l >= 1).
-// Tile b owns up to kBlock consecutive rows of the level's Morton order (F) and the coarse rows
-// whose kept vertex lies in F.  Its local rows are F, then the fine rows its coarse rows
+// Tile b owns a run of at most kBlock rows of the level's Morton order that lies inside one
+// aligned block of 16 x 16 (x 16) lattice cells of the median edge length (F; a 16 x 16 patch
+// on a grid) and the coarse rows whose kept vertex lies in F.  Its local rows are F, then the fine rows its coarse rows
 // restrict from (R0 = F + those), then the operator neighbours of R0 (R1), then theirs (R2),
 // each group in ascending internal order.  Everything a cycle leg needs from those rings is
 // recomputed in LDS, so the down leg (Jacobi sweeps from zero, residual, restriction) and the
@@ -92,11 +93,11 @@ struct DevTiles {
   int16_t* cst = nullptr;      // [tile][9][ccap]: local ids of the kept vertex, then of up to 8
                                // midpoints (zero slot past the row's width)
 };
-constexpr int kTileRows = 1024;   // local rows per tile (R2) at most
-// The fused up leg reads x, both parents and the right-hand side of every ring row; above this
-// many rows that traffic costs more than the launch it saves (C3: 9.7 us fused against 4.8 +
-// 3.4 us for the two launches at 261k rows), so larger tiled levels fuse the down leg only.
-constexpr int32_t kTileUpRows = 1 << 17;
+// One workgroup of kTileThreads threads per tile of up to 256 owned rows, one ring row per
+// thread (cap <= kTileThreads): four wavefronts per SIMD hide each other's dependent chains
+// (FP64 divisions above all), where 256 threads with four ring rows each left one wavefront
+// per SIMD.
+constexpr int kTileThreads = 1024;
 
 // Levels up to this many rows are launch-bound: there the interpolation is fused into the
 // first post-smoothing sweep (one launch fewer); on larger levels the extra dependent gathers

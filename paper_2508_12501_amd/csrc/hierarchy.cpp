@@ -595,11 +595,15 @@ std::vector<T> download(const T* d, size_t n) {
 }
 
 // Workgroup tiles of the fused smoothing kernels of binary level F over its coarse level C
-// (see DevTiles).  Leaves F.tiles empty when a row or restriction list is wider than 8 or a
-// tile's rings exceed kTileRows rows; the level then runs one kernel per step.
+// (see DevTiles), on levels of at most kLaunchBoundRows rows.  Leaves F.tiles empty when a row
+// or restriction list is wider than 8 or a tile's rings exceed kTileThreads rows; the level
+// then runs one kernel per step.  (Tiles of 4096 rows on the larger C3 levels, with 1.15x
+// rings, were measured slower than the streaming per-step kernels there.)
 void build_tiles(Level& F, const Level& C) {
   const int32_t n = F.n, nc = C.n;
   if (n == 0 || nc == 0 || F.tr.weighted || n > kLaunchBoundRows) return;
+  const int32_t fb = kBlock;                 // owned rows per tile at most
+  const int32_t capmax = kTileThreads, ccapmax = kTileThreads;
   const int32_t nsl = int32_t(F.sptr_h.size()) - 1;
   int32_t wmax = 0;
   for (int32_t s = 0; s < nsl; ++s) wmax = std::max(wmax, F.sptr_h[s + 1] - F.sptr_h[s]);
@@ -620,20 +624,32 @@ void build_tiles(Level& F, const Level& C) {
   auto rentry = [&](int32_t c, int k) {
     return rcol[size_t(rsptr[c / kSlice] + k) * kSlice + size_t(c % kSlice)];
   };
-  // Morton order of the rows: runs of kBlock consecutive rows are compact patches
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  // Morton order of the rows on a lattice of the median edge length h: on a grid the rows get
+  // their lattice coordinates, so runs of fb consecutive rows are aligned square patches
+  double lo[3] = {1e300, 1e300, 1e300};
   for (int32_t r = 0; r < n; ++r)
-    for (int c = 0; c < 3; ++c) {
-      lo[c] = std::min(lo[c], F.mesh.xyz[3 * size_t(F.perm_h[r]) + c]);
-      hi[c] = std::max(hi[c], F.mesh.xyz[3 * size_t(F.perm_h[r]) + c]);
+    for (int c = 0; c < 3; ++c) lo[c] = std::min(lo[c], F.mesh.xyz[3 * size_t(F.perm_h[r]) + c]);
+  double h = 1.0;
+  {
+    const Mesh& m = F.mesh;
+    std::vector<double> len(m.ne);
+    for (int64_t e = 0; e < m.ne; ++e) {
+      const double* a = &m.xyz[3 * m.edge[2 * e]];
+      const double* b = &m.xyz[3 * m.edge[2 * e + 1]];
+      len[e] = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) +
+                         (b[2] - a[2]) * (b[2] - a[2]));
     }
+    if (!len.empty()) {
+      std::nth_element(len.begin(), len.begin() + len.size() / 2, len.end());
+      if (len[len.size() / 2] > 0) h = len[len.size() / 2];
+    }
+  }
   std::vector<std::pair<uint64_t, int32_t>> key(n);
   for (int32_t r = 0; r < n; ++r) {
     uint32_t q[3];
     for (int c = 0; c < 3; ++c) {
-      const double span = hi[c] - lo[c];
-      const double u = span > 0 ? (F.mesh.xyz[3 * size_t(F.perm_h[r]) + c] - lo[c]) / span : 0.0;
-      q[c] = uint32_t(std::min(1048575.0, std::floor(u * 1048576.0)));
+      const double u = (F.mesh.xyz[3 * size_t(F.perm_h[r]) + c] - lo[c]) / h + 0.5;
+      q[c] = uint32_t(std::min(2097151.0, std::max(0.0, std::floor(u))));
     }
     key[r] = {morton3(q[0], q[1], q[2]), r};
   }
@@ -642,8 +658,17 @@ void build_tiles(Level& F, const Level& C) {
   auto entry = [&](int32_t r, int k) {   // SELL index of entry k of row r
     return size_t(F.sptr_h[r / kSlice] + k) * kSlice + size_t(r % kSlice);
   };
+  // tiles: runs of the Morton order inside one aligned lattice block of 16 x 16 (x 16) cells,
+  // cut further every fb rows
+  const int shift = 12;
+  std::vector<int32_t> tstart;
+  for (int32_t i = 0; i < n; ++i)
+    if (i == 0 || (key[i].first >> shift) != (key[i - 1].first >> shift) ||
+        i - tstart.back() == fb)
+      tstart.push_back(i);
+  tstart.push_back(n);
   // pass 1: the rings of every tile
-  const int32_t ntiles = (n + kBlock - 1) / kBlock;
+  const int32_t ntiles = int32_t(tstart.size()) - 1;
   std::vector<std::vector<int32_t>> trows(ntiles), tcown(ntiles);
   std::vector<std::array<int32_t, 5>> cnt(ntiles);   // nF, n0, n1, n2, ncb
   std::vector<int32_t> lid(n, -1), fresh;
@@ -660,7 +685,7 @@ void build_tiles(Level& F, const Level& C) {
         }
       fresh.clear();
     };
-    const int32_t r0 = b * kBlock, r1 = std::min(n, r0 + kBlock);
+    const int32_t r0 = tstart[b], r1 = tstart[b + 1];
     for (int32_t i = r0; i < r1; ++i) fresh.push_back(key[i].second);
     add_group();
     const int32_t nF = int32_t(rows.size());
@@ -692,7 +717,7 @@ void build_tiles(Level& F, const Level& C) {
   }
   cap = (cap + 63) / 64 * 64;
   ccap = std::max(64, (ccap + 63) / 64 * 64);
-  if (cap > kTileRows || ccap > kBlock) return;   // not compact: per-step kernels
+  if (cap > capmax || ccap > ccapmax) return;   // not compact: per-step kernels
   // pass 2: fixed-capacity arrays (padding: the tile's first row / coarse row, zero slot cap)
   const bool uniform = F.op.uw >= 0;
   std::vector<int32_t> meta(size_t(ntiles) * 8, 0), trow(size_t(ntiles) * cap),

@@ -407,13 +407,13 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
 }
 
 // ------------------------------------------------------------------ fused smoothing tiles
-// One workgroup per tile of a launch-bound binary level (DevTiles): the values a leg of the
-// cycle needs around the tile's own rows are recomputed in LDS, so the down leg takes one
-// launch instead of three and the up leg one instead of two.  Each value is formed with the
-// expressions and entry order of k_jacobi_two, k_rows, k_restrict and k_prolong_sweep, so the
-// results equal theirs bit for bit.  A thread holds rows t + q kBlock (q < nq) of the tile:
-// index, weight and right-hand-side loads are all issued before the first barrier.
-constexpr int kTileQ = kTileRows / kBlock;
+// One workgroup per tile of a binary level (DevTiles): the values a leg of the cycle needs
+// around the tile's own rows are recomputed in LDS, so the down leg takes one launch instead of
+// three and the up leg one instead of two.  Each value is formed with the expressions and entry
+// order of k_jacobi_two, k_rows, k_restrict and k_prolong_sweep, so the results equal theirs
+// bit for bit.  A workgroup of TB threads holds rows t + q TB (q < Q) of its tile and up to CQ
+// coarse rows per thread: index, weight and right-hand-side loads are all issued before the
+// first barrier.  LDS: two vectors of cap + 1 values (dynamic).
 
 // Row data of local row i: global row g, first SELL entry e0 and width, and (rows of R1) the
 // weights and local columns of its entries.
@@ -438,28 +438,30 @@ __device__ __forceinline__ void tile_row(int g, int i, int cap, const int32_t* _
   }
 }
 
-template <typename T, typename WT, int KT>
-__global__ __launch_bounds__(kBlock) void k_tile_down(
+template <typename T, typename WT, int KT, int TB, int Q, int CQ>
+__global__ __launch_bounds__(TB) void k_tile_down(
     const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
     const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol,
     const int32_t* __restrict__ tcrow, const int16_t* __restrict__ tcst, int32_t cap,
     int32_t ccap, int32_t uw, const WT* __restrict__ w, const T* __restrict__ diag,
     const T* __restrict__ b, T* __restrict__ x, T* __restrict__ bc, T omega, int nu1,
     const int* __restrict__ done) {
-  __shared__ T s1[kTileRows + 1], s2[kTileRows + 1], sr[kTileRows + 1];
+  extern __shared__ double tile_smem[];
+  T* s1 = reinterpret_cast<T*>(tile_smem);
+  T* s2 = s1 + (cap + 1);
   const int dn = done ? *done : 0;
   const int tb = xcd_block(), t = threadIdx.x;
   const int32_t* m = meta + 8 * tb;
   const int nF = m[0], n0 = m[1], n1 = m[2], n2 = m[3], ncb = m[4];
-  const int nq = (cap + kBlock - 1) / kBlock;
+  const int nq = (cap + TB - 1) / TB;
   const int32_t* rows = trow + static_cast<int64_t>(tb) * cap;
   const int32_t* ents = tent ? tent + static_cast<int64_t>(tb) * cap : nullptr;
   const int16_t* cols = tcol + static_cast<int64_t>(tb) * KT * cap;
-  int g[kTileQ], wid[kTileQ], cj[kTileQ][KT];
-  T wk[kTileQ][KT], bq[kTileQ], x1[kTileQ];
+  int g[Q], wid[Q], cj[Q][KT];
+  T wk[Q][KT], bq[Q], x1[Q];
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < cap) {
       g[q] = rows[i];
       tile_row<T, WT, KT>(g[q], i, cap, ents, uw, cols, w, wid[q], cj[q], wk[q]);
@@ -467,32 +469,31 @@ __global__ __launch_bounds__(kBlock) void k_tile_down(
       x1[q] = omega * bq[q] / diag[g[q]];
     }
   }
-  // restriction rows: one per thread at most (ccap <= kBlock)
-  int crow = 0, cs[9];
-  {
-    const int j = min(t, ccap - 1);
-    crow = tcrow[static_cast<int64_t>(tb) * ccap + j];
+  // restriction rows: CQ per thread at most (ccap <= CQ TB)
+  int crow[CQ], cs[CQ][9];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) cs[k] = tcst[(static_cast<int64_t>(tb) * 9 + k) * ccap + j];
+  for (int c = 0; c < CQ; ++c) {
+    const int j = min(t + c * TB, ccap - 1);
+    crow[c] = tcrow[static_cast<int64_t>(tb) * ccap + j];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) cs[c][k] = tcst[(static_cast<int64_t>(tb) * 9 + k) * ccap + j];
   }
   // x1 = omega b / D on every local row (the first sweep from zero is local)
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < n2) s1[i] = (nu1 >= 1) ? x1[q] : T(0);
   }
   if (t == 0) {
     s1[cap] = T(0);
     s2[cap] = T(0);
-    sr[cap] = T(0);
   }
   __syncthreads();
   // x2 on R1 (second sweep, k_jacobi_two), or x = 0 / x1 on R1
-  const T* xc = s1;
   if (nu1 == 2) {
 #pragma unroll
-    for (int q = 0; q < kTileQ; ++q) {
-      const int i = t + q * kBlock;
+    for (int q = 0; q < Q; ++q) {
+      const int i = t + q * TB;
       if (q < nq && i < n1) {
         const T xi = x1[q];
         T acc = T(0), d = T(0);
@@ -506,12 +507,13 @@ __global__ __launch_bounds__(kBlock) void k_tile_down(
       }
     }
     __syncthreads();
-    xc = s2;
   }
-  // residual on R0 (k_rows, mode 1); the tile's own rows of x go out
+  // residual on R0 (k_rows, mode 1) into the vector x no longer needs; own rows of x go out
+  const T* xc = (nu1 == 2) ? s2 : s1;
+  T* sr = (nu1 == 2) ? s1 : s2;
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < n0) {
       const T xi = xc[i];
       T acc = T(0);
@@ -524,37 +526,42 @@ __global__ __launch_bounds__(kBlock) void k_tile_down(
   }
   __syncthreads();
   // restriction of the residual onto the tile's coarse rows (k_restrict)
-  if (t < ncb && !dn) {
-    T acc = T(0);
+  if (dn) return;
 #pragma unroll
-    for (int k = 1; k < 9; ++k) acc += sr[cs[k]];
-    bc[crow] = sr[cs[0]] + T(0.5) * acc;
-  }
+  for (int c = 0; c < CQ; ++c)
+    if (t + c * TB < ncb) {
+      T acc = T(0);
+#pragma unroll
+      for (int k = 1; k < 9; ++k) acc += sr[cs[c][k]];
+      bc[crow[c]] = sr[cs[c][0]] + T(0.5) * acc;
+    }
 }
 
-template <typename T, typename WT, int KT>
-__global__ __launch_bounds__(kBlock) void k_tile_up(
+template <typename T, typename WT, int KT, int TB, int Q>
+__global__ __launch_bounds__(TB) void k_tile_up(
     const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
     const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol, int32_t cap,
     int32_t uw, const WT* __restrict__ w, const int32_t* __restrict__ pa,
     const int32_t* __restrict__ pb, const T* __restrict__ ec, const T* __restrict__ x,
     const T* __restrict__ b, T* __restrict__ xo, T omega, int nu2,
     const int* __restrict__ done) {
-  __shared__ T s0[kTileRows + 1], s1[kTileRows + 1];
+  extern __shared__ double tile_smem[];
+  T* s0 = reinterpret_cast<T*>(tile_smem);
+  T* s1 = s0 + (cap + 1);
   const int dn = done ? *done : 0;
   const int tb = xcd_block(), t = threadIdx.x;
   const int32_t* m = meta + 8 * tb;
   const int nF = m[0], n1 = m[2], n2 = m[3];
-  const int nq = (cap + kBlock - 1) / kBlock;
+  const int nq = (cap + TB - 1) / TB;
   const int32_t* rows = trow + static_cast<int64_t>(tb) * cap;
   const int32_t* ents = tent ? tent + static_cast<int64_t>(tb) * cap : nullptr;
   const int16_t* cols = tcol + static_cast<int64_t>(tb) * KT * cap;
-  int g[kTileQ], wid[kTileQ], cj[kTileQ][KT];
-  T wk[kTileQ][KT], bq[kTileQ], xq[kTileQ];
-  int ia[kTileQ], ib[kTileQ];
+  int g[Q], wid[Q], cj[Q][KT];
+  T wk[Q][KT], bq[Q], xq[Q];
+  int ia[Q], ib[Q];
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < cap) {
       g[q] = rows[i];
       tile_row<T, WT, KT>(g[q], i, cap, ents, uw, cols, w, wid[q], cj[q], wk[q]);
@@ -566,8 +573,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_up(
   }
   // x0 = x + M(f)^T ec on every local row (k_prolong_sweep's rounding)
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < n2) {
       xq[q] = xq[q] + T(0.5) * (ec[ia[q]] + ec[ib[q]]);
       s0[i] = xq[q];
@@ -580,8 +587,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_up(
   __syncthreads();
   // first sweep on R1 (k_prolong_sweep)
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < n1) {
       const T xi = xq[q];
       T acc = T(0), d = T(0);
@@ -599,8 +606,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_up(
     __syncthreads();
     // second sweep on the tile's own rows (k_rows, mode 2)
 #pragma unroll
-    for (int q = 0; q < kTileQ; ++q) {
-      const int i = t + q * kBlock;
+    for (int q = 0; q < Q; ++q) {
+      const int i = t + q * TB;
       if (q < nq && i < nF) {
         const T xi = xq[q];
         T acc = T(0), d = T(0);
@@ -616,8 +623,8 @@ __global__ __launch_bounds__(kBlock) void k_tile_up(
   }
   if (dn) return;
 #pragma unroll
-  for (int q = 0; q < kTileQ; ++q) {
-    const int i = t + q * kBlock;
+  for (int q = 0; q < Q; ++q) {
+    const int i = t + q * TB;
     if (q < nq && i < nF) xo[g[q]] = xq[q];
   }
 }
@@ -2034,20 +2041,25 @@ void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x
   });
 }
 template <typename T>
+static size_t tile_lds(const DevTiles& D) { return 2 * size_t(D.cap + 1) * sizeof(T); }
+
+template <typename T>
 void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done,
                hipStream_t s) {
   const DevTiles& D = L.tiles;
   if (D.ntiles == 0) throw std::logic_error("tile_down on a level without tiles");
+  const size_t lds = tile_lds<T>(D);
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    auto go = [&](auto kern, int tbk) {
+      hipLaunchKernelGGL(kern, dim3(D.ntiles), dim3(tbk), lds, s, D.meta, D.row, D.ent, D.col,
+                         D.crow, D.cst, D.cap, D.ccap, L.op.uw, w, diagonal<T>(L), b, x, bc,
+                         static_cast<T>(omega), nu1, done);
+    };
     if (D.kt == 4)
-      hipLaunchKernelGGL((k_tile_down<T, WT, 4>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
-                         D.row, D.ent, D.col, D.crow, D.cst, D.cap, D.ccap, L.op.uw, w,
-                         diagonal<T>(L), b, x, bc, static_cast<T>(omega), nu1, done);
+      go(k_tile_down<T, WT, 4, kTileThreads, 1, 1>, kTileThreads);
     else
-      hipLaunchKernelGGL((k_tile_down<T, WT, 8>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
-                         D.row, D.ent, D.col, D.crow, D.cst, D.cap, D.ccap, L.op.uw, w,
-                         diagonal<T>(L), b, x, bc, static_cast<T>(omega), nu1, done);
+      go(k_tile_down<T, WT, 8, kTileThreads, 1, 1>, kTileThreads);
   });
 }
 template <typename T>
@@ -2055,18 +2067,21 @@ void tile_up(const Level& L, const T* ec, const T* x, const T* b, T* xo, double 
              const int* done, hipStream_t s) {
   const DevTiles& D = L.tiles;
   if (D.ntiles == 0) throw std::logic_error("tile_up on a level without tiles");
+  const size_t lds = tile_lds<T>(D);
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    auto go = [&](auto kern, int tbk) {
+      hipLaunchKernelGGL(kern, dim3(D.ntiles), dim3(tbk), lds, s, D.meta, D.row, D.ent, D.col,
+                         D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
+                         static_cast<T>(omega), nu2, done);
+    };
     if (D.kt == 4)
-      hipLaunchKernelGGL((k_tile_up<T, WT, 4>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
-                         D.row, D.ent, D.col, D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
-                         static_cast<T>(omega), nu2, done);
+      go(k_tile_up<T, WT, 4, kTileThreads, 1>, kTileThreads);
     else
-      hipLaunchKernelGGL((k_tile_up<T, WT, 8>), dim3(D.ntiles), dim3(kBlock), 0, s, D.meta,
-                         D.row, D.ent, D.col, D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
-                         static_cast<T>(omega), nu2, done);
+      go(k_tile_up<T, WT, 8, kTileThreads, 1>, kTileThreads);
   });
 }
+
 template <typename T>
 void cgs_start(const Level& L, const T* r, T* p, double* part, const int* done, hipStream_t s) {
   if (L.n == 0) return;

@@ -198,7 +198,7 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
   const T* bc = vecs<T>(C).b;
   T* ec = coarse_correction<T>(H, l, bc, o, kind, done, s);
   int post = o.nu2;
-  if (tiled && L.n <= kTileUpRows && (post == 1 || post == 2)) {
+  if (tiled && (post == 1 || post == 2)) {
     // the tiles read x around their rows, so the result goes to the partner buffer
     k::tile_up<T>(L, ec, cur, b, oth, o.omega, post, done, s);
     std::swap(cur, oth);

@@ -758,7 +758,11 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(const int32_t* __restrict__
   x[i] = xi + (bi - acc) / d;
 }
 
-// x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.
+// x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.  Each thread takes
+// kProlongRows rows kBlock apart: the parent gathers depend on the parent loads, and with one
+// row per thread too few bytes were in flight to cover those two round trips (3.5 TB/s on the
+// C3 finest level).
+constexpr int kProlongRows = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ pa,
                                                     const int32_t* __restrict__ pb,
@@ -766,11 +770,25 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ 
                                                     T* __restrict__ xf, int32_t nf,
                                                     const int* __restrict__ done) {
   DECMG_DONE_LOAD(nf)
-  const int row = xcd_block() * kBlock + threadIdx.x;
-  if (row >= nf) return;
-  const T v = xf[row] + T(0.5) * (ec[pa[row]] + ec[pb[row]]);
+  const int base = xcd_block() * (kBlock * kProlongRows) + threadIdx.x;
+  int a[kProlongRows], b[kProlongRows];
+  T x[kProlongRows];
+#pragma unroll
+  for (int r = 0; r < kProlongRows; ++r) {
+    const int row = base + r * kBlock;
+    if (row < nf) {
+      a[r] = pa[row];
+      b[r] = pb[row];
+      x[r] = xf[row];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kProlongRows; ++r)
+    if (base + r * kBlock < nf) x[r] = x[r] + T(0.5) * (ec[a[r]] + ec[b[r]]);
   DECMG_DONE_CHECK()
-  xf[row] = v;
+#pragma unroll
+  for (int r = 0; r < kProlongRows; ++r)
+    if (base + r * kBlock < nf) xf[base + r * kBlock] = x[r];
 }
 
 // Weighted interpolation xf += M(f)^T ec for any subdivision scheme: three (parent, weight)
@@ -2021,8 +2039,9 @@ void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int
                          Lf.tr.p3, Lf.tr.pw32, ec, xf, Lf.n, done);
     return;
   }
-  hipLaunchKernelGGL((k_prolong<T>), dim3(grid_for(Lf.n)), dim3(kBlock), 0, s, Lf.tr.pa, Lf.tr.pb,
-                     ec, xf, Lf.n, done);
+  const int64_t groups = (int64_t(Lf.n) + kBlock * kProlongRows - 1) / (kBlock * kProlongRows);
+  hipLaunchKernelGGL((k_prolong<T>), dim3(groups), dim3(kBlock), 0, s, Lf.tr.pa, Lf.tr.pb, ec,
+                     xf, Lf.n, done);
 }
 template <typename T>
 void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x, const T* b,

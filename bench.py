@@ -79,14 +79,29 @@ def profile_kernels(reps=5):
 
 def kernel_bytes(info, dtype_bytes, kind):
     """Algorithmic bytes of one launch on a level: each stored coupling read once (column
-    index of the level's width + weight), each vector entry read or written once, gathers at
-    perfect reuse."""
+    index of the level's width + the weight in the format the kernels of that precision read),
+    each vector entry read or written once, gathers at perfect reuse."""
     n, nnz, ib = info["n_unknowns"], info["nnz_operator"], info["index_bytes"]
+    wb = info["weight_bytes32"] if dtype_bytes == 4 else info["weight_bytes64"]
     if kind == "jacobi":      # col + w per coupling; x, b read, x' written
-        return nnz * (ib + dtype_bytes) + n * 3 * dtype_bytes
+        return nnz * (ib + wb) + n * 3 * dtype_bytes
     if kind == "spmv":        # col + w per coupling; x read, y written
-        return nnz * (ib + dtype_bytes) + n * 2 * dtype_bytes
+        return nnz * (ib + wb) + n * 2 * dtype_bytes
     raise ValueError(kind)
+
+
+def sweep_kernel_name(info):
+    """The FP32 finest-level sweep's instantiation: one or two rows per thread, int16 or int32
+    columns, binary16 or FP32 weights."""
+    return "%s<float, 2, %s, %s>" % ("k_rows2" if info["rows_per_thread"] == 2 else "k_rows",
+                                    "true" if info["index_bytes"] == 2 else "false",
+                                    "_Float16" if info["weight_bytes32"] == 2 else "float")
+
+
+def sweep_grid(info):
+    """Threads launched by the finest-level sweep: 256-thread blocks of 256 rows per thread row."""
+    rows = 256 * info["rows_per_thread"]
+    return (info["n_unknowns"] + rows - 1) // rows * 256
 
 
 def recorded_traffic(kernel_key):
@@ -506,14 +521,12 @@ def main():
         "porous_e4_adaptive": e4,
         "roofline": {
             "bound": "hbm",
-            "kernel": "k_rows<float, 2, %s, float> (FP32 weighted-Jacobi sweep, finest level)"
-                      % ("true" if info["index_bytes"] == 2 else "false"),
+            "kernel": sweep_kernel_name(info) + " (FP32 weighted-Jacobi sweep, finest level)",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": recorded_traffic("k_rows<float, 2, %s, float>@%d" % (
-                "true" if info["index_bytes"] == 2 else "false", (unknowns + 255) // 256 * 256)),
+            "traffic": recorded_traffic("%s@%d" % (sweep_kernel_name(info), sweep_grid(info))),
             "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
             "bytes_per_launch": by_j32,
             "ms_per_launch": ms_j32,

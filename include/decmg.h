@@ -126,6 +126,11 @@ typedef struct {
   int32_t fused_tiles;   /* workgroup tiles of the fused cycle legs (mg_opts.fuse_levels), or 0
                             when the level runs one launch per step */
   int32_t fused_tile_rows;  /* rows the tiles hold in total, own rows and overlap */
+  int32_t weight_bytes32;   /* bytes per stored weight read by the FP32 row kernels (2 or 4):
+                               2 when every weight is exactly an IEEE binary16 number */
+  int32_t weight_bytes64;   /* the same for the FP64 row kernels (2, 4 or 8) */
+  int32_t uniform_width;    /* entries of every operator slice when they are all equal, else -1 */
+  int32_t rows_per_thread;  /* rows each thread of the sweep, residual and apply kernels takes */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 

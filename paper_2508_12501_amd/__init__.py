@@ -56,7 +56,9 @@ class mg_level_info(ctypes.Structure):
                 ("nv", ctypes.c_int64), ("ne", ctypes.c_int64), ("nt", ctypes.c_int64),
                 ("n_unknowns", ctypes.c_int64), ("nnz_operator", ctypes.c_int64),
                 ("index_bytes", ctypes.c_int32), ("scheme", ctypes.c_int32),
-                ("fused_tiles", ctypes.c_int32), ("fused_tile_rows", ctypes.c_int32)]
+                ("fused_tiles", ctypes.c_int32), ("fused_tile_rows", ctypes.c_int32),
+                ("weight_bytes32", ctypes.c_int32), ("weight_bytes64", ctypes.c_int32),
+                ("uniform_width", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32)]
 
 
 class mg_opts(ctypes.Structure):

@@ -323,6 +323,10 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->scheme = L.mesh.scheme;
   out->fused_tiles = L.tiles.ntiles;
   out->fused_tile_rows = int32_t(L.tiles.rows_total);
+  out->weight_bytes32 = L.op.w_exact16 ? 2 : 4;
+  out->weight_bytes64 = L.op.w_exact16 ? 2 : (L.op.w_exact32 ? 4 : 8);
+  out->uniform_width = L.op.uw;
+  out->rows_per_thread = (L.op.uw >= 1 && L.op.uw <= 8) ? 2 : 1;
   return MG_OK;
 }
 

@@ -43,6 +43,10 @@ struct DevOperator {
   double* w64 = nullptr;
   float* w32 = nullptr;
   bool w_exact32 = false;     // every FP64 weight equals its FP32 copy: FP64 kernels read w32
+  // IEEE binary16 copy of the weights, read by the FP32 and FP64 kernels alike when every
+  // weight is exactly a binary16 number (the widened values are then the weights bit for bit)
+  uint16_t* w16 = nullptr;
+  bool w_exact16 = false;
   double* diag64 = nullptr;   // sum of the row's weights, in SELL order
   float* diag32 = nullptr;
 };

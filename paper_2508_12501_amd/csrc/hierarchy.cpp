@@ -788,6 +788,35 @@ void build_tiles(Level& F, const Level& C) {
   T.cst = upload(tcst);
 }
 
+// The IEEE binary16 encoding of v when v is exactly a binary16 number (zero, normal or
+// subnormal); false otherwise.
+bool half_exact(double v, uint16_t& h) {
+  const float f = static_cast<float>(v);
+  if (static_cast<double>(f) != v || !std::isfinite(f)) return false;
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  const uint32_t s = (u >> 31) << 15, ef = (u >> 23) & 0xffu, mf = u & 0x7fffffu;
+  if (ef == 0 && mf == 0) {   // signed zero
+    h = uint16_t(s);
+    return true;
+  }
+  if (ef == 0) return false;  // FP32 subnormals are below the binary16 range
+  const int e = int(ef) - 127;
+  if (e >= -14 && e <= 15) {  // binary16 normal: 10 fraction bits
+    if (mf & 0x1fffu) return false;
+    h = uint16_t(s | uint32_t(e + 15) << 10 | (mf >> 13));
+    return true;
+  }
+  if (e >= -24 && e < -14) {  // binary16 subnormal: value = frac * 2^-24
+    const uint32_t sig = (1u << 23) | mf;
+    const int sh = -(e + 1);
+    if (sig & ((1u << sh) - 1u)) return false;
+    h = uint16_t(s | (sig >> sh));
+    return true;
+  }
+  return false;
+}
+
 }  // namespace
 
 void upload_weights(Hierarchy& H) {
@@ -810,9 +839,17 @@ void upload_weights(Hierarchy& H) {
         L.op.w_exact32 = false;
         break;
       }
+    std::vector<uint16_t> w16(w64.size());
+    L.op.w_exact16 = !w64.empty();
+    for (size_t i = 0; i < w64.size() && L.op.w_exact16; ++i)
+      L.op.w_exact16 = half_exact(w64[i], w16[i]);
+    if (!L.op.w16) L.op.w16 = zeros<uint16_t>(std::max<size_t>(w64.size(), 1));
     if (!w64.empty()) {
       check_hip(hipMemcpy(L.op.w64, w64.data(), w64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
       check_hip(hipMemcpy(L.op.w32, w32.data(), w32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+      if (L.op.w_exact16)
+        check_hip(hipMemcpy(L.op.w16, w16.data(), w16.size() * 2, hipMemcpyHostToDevice),
+                  "hipMemcpy");
     }
     check_hip(hipMemcpy(L.op.diag64, d64.data(), d64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
     check_hip(hipMemcpy(L.op.diag32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
@@ -954,6 +991,7 @@ Hierarchy::~Hierarchy() {
     Level& L = *Lp;
     for (void* p : {(void*)L.perm, (void*)L.bnd_ids, (void*)L.star0, (void*)L.op.sptr,
                     (void*)L.op.col, (void*)L.op.col16, (void*)L.op.w64, (void*)L.op.w32,
+                    (void*)L.op.w16,
                     (void*)L.op.diag64,
                     (void*)L.op.diag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
                     (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.v64.x, (void*)L.v64.b,

@@ -88,6 +88,20 @@ __device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int
 __device__ __forceinline__ double mac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float mac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// Column and weight of SELL entry idx of `row`; the weight array is FP64, FP32 or binary16,
+// widened to T exactly.
+template <typename T, bool D16, typename WT>
+__device__ __forceinline__ void entry_at(const void* __restrict__ col, const WT* __restrict__ w,
+                                         int idx, int row, int n, int& c, T& wk) {
+  c = col_at<D16>(col, idx, row, n);
+  wk = static_cast<T>(w[idx]);
+}
+// The weight of SELL entry idx.
+template <typename T, typename WT>
+__device__ __forceinline__ T weight_at(const WT* __restrict__ w, int idx) {
+  return static_cast<T>(w[idx]);
+}
+
 // Launch-bound kernels (n <= kLaunchBoundRows) issue the load of the convergence flag with their
 // other first loads and test it only before their stores, which takes a dependent memory round
 // trip off their critical path; large launches test it first, so a replay after convergence
@@ -124,11 +138,7 @@ __device__ __forceinline__ void row_apply_n(const void* __restrict__ col, const 
   int cj[N];
   T wk[N], xj[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int idx = (beg + k) * kSlice + lane;
-    cj[k] = col_at<D16>(col, idx, row, n);
-    wk[k] = static_cast<T>(w[idx]);
-  }
+  for (int k = 0; k < N; ++k) entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, cj[k], wk[k]);
 #pragma unroll
   for (int k = 0; k < N; ++k) xj[k] = x[cj[k]];
 #pragma unroll
@@ -160,10 +170,11 @@ __device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr, int 
     case 8: row_apply_n<T, D16, 8>(col, w, x, beg, lane, row, n, xi, acc, d); break;
     default:
       for (int k = 0; k < width; ++k) {
-        const int idx = (beg + k) * kSlice + lane;
-        const T wk = w[idx];
+        int j;
+        T wk;
+        entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, j, wk);
         d += wk;
-        acc = mac(wk, xi - x[col_at<D16>(col, idx, row, n)], acc);
+        acc = mac(wk, xi - x[j], acc);
       }
   }
 }
@@ -177,11 +188,7 @@ __device__ __forceinline__ void row_two_n(const void* __restrict__ col, const WT
   int cj[N];
   T wk[N], bj[N], dj[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int idx = (beg + k) * kSlice + lane;
-    cj[k] = col_at<D16>(col, idx, row, n);
-    wk[k] = static_cast<T>(w[idx]);
-  }
+  for (int k = 0; k < N; ++k) entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, cj[k], wk[k]);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     bj[k] = b[cj[k]];
@@ -243,9 +250,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict
     case 8: row_two_n<T, D16, 8>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
     default:
       for (int k = 0; k < width; ++k) {
-        const int idx = (beg + k) * kSlice + lane;
-        const T wk = w[idx];
-        const int j = col_at<D16>(col, idx, row, n);
+        int j;
+        T wk;
+        entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, j, wk);
         d += wk;
         acc = mac(wk, xi - omega * b[j] / diag[j], acc);
       }
@@ -277,6 +284,107 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ spt
     y[row] = bi - acc;
   else
     y[row] = xi + omega * (bi - acc) / d;
+}
+
+// Two rows per thread, kBlock apart, on levels whose slices all have the width uw (ELL): each
+// row's index, weight and vector loads are all issued before either row's gathers, so twice
+// the bytes are in flight per wavefront (with binary16 weights the finest-level sweeps moved
+// 28 B per row and their two dependent memory trips per wavefront were exposed).  Same
+// expressions and entry order as the one-row kernels.  The second row of a thread past the end
+// is its first row again (computed twice, stored once).
+__device__ __forceinline__ int ell_first(int r, int uw) { return (r >> 6) * uw * kSlice + (r & 63); }
+template <typename T, bool D16, int N, typename WT, typename G>
+__device__ __forceinline__ void row2_n(const void* __restrict__ col, const WT* __restrict__ w,
+                                       int r0, int r1, int uw, int n, T x0, T x1, G&& other,
+                                       T& a0, T& d0, T& a1, T& d1) {
+  int c0[N], c1[N];
+  T w0[N], w1[N], y0[N], y1[N];
+  const int e0 = ell_first(r0, uw), e1 = ell_first(r1, uw);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    entry_at<T, D16>(col, w, e0 + k * kSlice, r0, n, c0[k], w0[k]);
+    entry_at<T, D16>(col, w, e1 + k * kSlice, r1, n, c1[k], w1[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    y0[k] = other(c0[k]);
+    y1[k] = other(c1[k]);
+  }
+  a0 = d0 = a1 = d1 = T(0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    d0 += w0[k];
+    a0 = mac(w0[k], x0 - y0[k], a0);
+    d1 += w1[k];
+    a1 = mac(w1[k], x1 - y1[k], a1);
+  }
+}
+template <typename T, bool D16, typename WT, typename G>
+__device__ __forceinline__ void row2(const void* __restrict__ col, const WT* __restrict__ w,
+                                     int r0, int r1, int uw, int n, T x0, T x1, G&& other, T& a0,
+                                     T& d0, T& a1, T& d1) {
+  switch (uw) {
+    case 1: row2_n<T, D16, 1>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 2: row2_n<T, D16, 2>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 3: row2_n<T, D16, 3>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 4: row2_n<T, D16, 4>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 5: row2_n<T, D16, 5>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 6: row2_n<T, D16, 6>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 7: row2_n<T, D16, 7>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    default: row2_n<T, D16, 8>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+  }
+}
+
+// k_rows with two rows per thread (uniform widths 1..8 only)
+template <typename T, int MODE, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_rows2(int32_t uw, const void* __restrict__ col,
+                                                  const WT* __restrict__ w,
+                                                  const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ y,
+                                                  int32_t n, T omega,
+                                                  const int* __restrict__ done) {
+  DECMG_DONE_LOAD(n)
+  const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
+  if (r0 >= n) return;
+  const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+  const T x0 = x[r0], x1 = x[r1];
+  const T b0 = (MODE == 0) ? T(0) : b[r0];
+  const T b1 = (MODE == 0) ? T(0) : b[r1];
+  T a0, d0, a1, d1;
+  row2<T, D16>(col, w, r0, r1, uw, n, x0, x1, [&](int j) { return x[j]; }, a0, d0, a1, d1);
+  DECMG_DONE_CHECK()
+  if (MODE == 0) {
+    y[r0] = a0;
+    if (r1 != r0) y[r1] = a1;
+  } else if (MODE == 1) {
+    y[r0] = b0 - a0;
+    if (r1 != r0) y[r1] = b1 - a1;
+  } else {
+    y[r0] = x0 + omega * (b0 - a0) / d0;
+    if (r1 != r0) y[r1] = x1 + omega * (b1 - a1) / d1;
+  }
+}
+
+// k_jacobi_two with two rows per thread (uniform widths 1..8 only)
+template <typename T, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_jacobi_two2(int32_t uw, const void* __restrict__ col,
+                                                        const WT* __restrict__ w,
+                                                        const T* __restrict__ diag,
+                                                        const T* __restrict__ b,
+                                                        T* __restrict__ y, int32_t n, T omega,
+                                                        const int* __restrict__ done) {
+  DECMG_DONE_LOAD(n)
+  const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
+  if (r0 >= n) return;
+  const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+  const T b0 = b[r0], b1 = b[r1];
+  const T x0 = omega * b0 / diag[r0], x1 = omega * b1 / diag[r1];
+  T a0, d0, a1, d1;
+  row2<T, D16>(col, w, r0, r1, uw, n, x0, x1, [&](int j) { return omega * b[j] / diag[j]; }, a0,
+               d0, a1, d1);
+  DECMG_DONE_CHECK()
+  y[r0] = x0 + omega * (b0 - a0) / d0;
+  if (r1 != r0) y[r1] = x1 + omega * (b1 - a1) / d1;
 }
 
 // First smoothing sweep from x = 0: x = omega b / D.
@@ -342,11 +450,7 @@ __device__ __forceinline__ void row_prolong_n(const void* __restrict__ col,
   int cj[N], ca[N], cb[N];
   T wk[N], xj[N];
 #pragma unroll
-  for (int k = 0; k < N; ++k) {
-    const int idx = (beg + k) * kSlice + lane;
-    cj[k] = col_at<D16>(col, idx, row, n);
-    wk[k] = static_cast<T>(w[idx]);
-  }
+  for (int k = 0; k < N; ++k) entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, cj[k], wk[k]);
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     xj[k] = x[cj[k]];
@@ -394,10 +498,10 @@ __global__ __launch_bounds__(kBlock) void k_prolong_sweep(const int32_t* __restr
     case 8: row_prolong_n<T, D16, 8>(col, w, x, pa, pb, ec, beg, lane, row, n, xi0, acc, d); break;
     default:
       for (int k = 0; k < width; ++k) {
-        const int idx = (beg + k) * kSlice + lane;
-        const int j = col_at<D16>(col, idx, row, n);
+        int j;
+        T wk;
+        entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, j, wk);
         const T xj = x[j] + T(0.5) * (ec[pa[j]] + ec[pb[j]]);
-        const T wk = w[idx];
         d += wk;
         acc = mac(wk, xi0 - xj, acc);
       }
@@ -434,7 +538,7 @@ __device__ __forceinline__ void tile_row(int g, int i, int cap, const int32_t* _
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     cj[k] = tcol[k * cap + i];
-    wk[k] = (k < wid) ? static_cast<T>(w[e0 + k * kSlice]) : T(0);
+    wk[k] = (k < wid) ? weight_at<T>(w, e0 + k * kSlice) : T(0);
   }
 }
 
@@ -1924,11 +2028,16 @@ const double* diagonal<double>(const Level& L) { return L.op.diag64; }
 template <>
 const float* diagonal<float>(const Level& L) { return L.op.diag32; }
 
-// Calls f(w) with the weight array the T-arithmetic row kernels read: the FP32 copy for FP32
-// kernels, and for FP64 kernels too when every FP64 weight of the level is exactly an FP32
-// number (the widened values are then the FP64 weights bit for bit, at half the bytes).
+// Calls f(w) with the weight array the T-arithmetic row kernels read: the binary16 copy when
+// every weight of the level is exactly a binary16 number, else the FP32 copy for FP32 kernels,
+// and for FP64 kernels too when every FP64 weight is exactly an FP32 number.  The widened
+// values are the weights bit for bit in every case; only the bytes read change.
 template <typename T, typename F>
 static void with_weights(const Level& L, F&& f) {
+  if (L.op.w_exact16) {
+    f(reinterpret_cast<const _Float16*>(L.op.w16));
+    return;
+  }
   if constexpr (std::is_same<T, float>::value) {
     f(L.op.w32);
   } else {
@@ -1941,12 +2050,27 @@ static void with_weights(const Level& L, F&& f) {
 template <typename P>
 using pointee_t = std::remove_const_t<std::remove_pointer_t<P>>;
 
+// Levels whose slices all have one width of 1..8 entries take the two-rows-per-thread kernels.
+static bool two_rows(const Level& L) { return L.op.uw >= 1 && L.op.uw <= 8; }
+static unsigned grid2_for(int32_t n) { return unsigned((int64_t(n) + 2 * kBlock - 1) / (2 * kBlock)); }
+
 template <typename T, int MODE>
 static void rows(const Level& L, const T* x, const T* b, T* y, double omega, const int* done,
                  hipStream_t s) {
   if (L.n == 0) return;
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    if (two_rows(L)) {
+      if (L.op.col16)
+        hipLaunchKernelGGL((k_rows2<T, MODE, true, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                           L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, y, L.n,
+                           static_cast<T>(omega), done);
+      else
+        hipLaunchKernelGGL((k_rows2<T, MODE, false, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                           L.op.uw, static_cast<const void*>(L.op.col), w, x, b, y, L.n,
+                           static_cast<T>(omega), done);
+      return;
+    }
     if (L.op.col16)
       hipLaunchKernelGGL((k_rows<T, MODE, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
                          L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, y, L.n,
@@ -1965,6 +2089,17 @@ void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, c
   if (L.n == 0) return;
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    if (two_rows(L)) {
+      if (L.op.col16)
+        hipExtLaunchKernelGGL((k_rows2<T, 2, true, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                              e0, e1, 0, L.op.uw, static_cast<const void*>(L.op.col16), w, x, b,
+                              xo, L.n, static_cast<T>(omega), done);
+      else
+        hipExtLaunchKernelGGL((k_rows2<T, 2, false, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0,
+                              s, e0, e1, 0, L.op.uw, static_cast<const void*>(L.op.col), w, x, b,
+                              xo, L.n, static_cast<T>(omega), done);
+      return;
+    }
     if (L.op.col16)
       hipExtLaunchKernelGGL((k_rows<T, 2, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s, e0,
                             e1, 0, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, xo,
@@ -1994,6 +2129,17 @@ void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done
   if (L.n == 0) return;
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    if (two_rows(L)) {
+      if (L.op.col16)
+        hipLaunchKernelGGL((k_jacobi_two2<T, true, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                           L.op.uw, static_cast<const void*>(L.op.col16), w, diagonal<T>(L), b, xo,
+                           L.n, static_cast<T>(omega), done);
+      else
+        hipLaunchKernelGGL((k_jacobi_two2<T, false, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                           L.op.uw, static_cast<const void*>(L.op.col), w, diagonal<T>(L), b, xo,
+                           L.n, static_cast<T>(omega), done);
+      return;
+    }
     if (L.op.col16)
       hipLaunchKernelGGL((k_jacobi_two<T, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
                          L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, diagonal<T>(L), b, xo,

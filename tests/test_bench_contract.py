@@ -24,16 +24,27 @@ def test_more_than_one_gpu_is_refused():
 
 def test_headline_sweep_bytes():
     # 2049 x 2049 grid, zero Dirichlet: 2047^2 unknowns, 4 stored couplings per interior row
-    # less the boundary-adjacent ones (the level's reported nnz), int16 column offsets
-    info = {"n_unknowns": 4190209, "nnz_operator": 16760836, "index_bytes": 2}
+    # less the boundary-adjacent ones (the level's reported nnz), int16 column offsets; the
+    # weights (star1 in {1/2, 1}) are read as binary16 by both precisions
+    info = {"n_unknowns": 4190209, "nnz_operator": 16760836, "index_bytes": 2,
+            "weight_bytes32": 2, "weight_bytes64": 2, "rows_per_thread": 2}
+    assert bench.kernel_bytes(info, 4, "jacobi") == 16760836 * 4 + 4190209 * 12 == 117325852
+    assert bench.kernel_bytes(info, 8, "spmv") == 16760836 * 4 + 4190209 * 16
+    assert bench.sweep_kernel_name(info) == "k_rows2<float, 2, true, _Float16>"
+    assert bench.sweep_grid(info) == 2095360 and bench.sweep_grid(dict(info, rows_per_thread=1)) == 4190464
+    assert bench.sweep_kernel_name(dict(info, index_bytes=4, rows_per_thread=1)) == \
+        "k_rows<float, 2, false, _Float16>"
+    # general weights: FP32 for FP32 kernels, FP64 for FP64 kernels
+    info.update(weight_bytes32=4, weight_bytes64=8)
     assert bench.kernel_bytes(info, 4, "jacobi") == 16760836 * 6 + 4190209 * 12 == 150847524
     assert bench.kernel_bytes(info, 8, "spmv") == 16760836 * 10 + 4190209 * 16
+    assert bench.sweep_kernel_name(dict(info, rows_per_thread=1)) == "k_rows<float, 2, true, float>"
     with pytest.raises(ValueError):
         bench.kernel_bytes(info, 4, "other")
 
 
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
-    key = "k_rows<float, 2, true, float>@4190464"
+    key = "k_rows2<float, 2, true, _Float16>@2095360"
     prof = os.path.join(ROOT, "profiles", "c3_finest_kernels_hbm_traffic.md")
     # a copy of the repository layout whose kernel source differs from the recorded hash
     (tmp_path / "profiles").mkdir()

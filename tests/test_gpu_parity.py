@@ -104,6 +104,43 @@ def test_host_build_matches_oracle(which, request):
 
 
 # ------------------------------------------------------------------ kernels
+def test_weight_storage(c1, sphere):
+    """The row kernels read the narrowest exact copy of the weights: binary16 when every
+    weight of a level is a binary16 number (grids: star1 in {0, 1/2, 1}), FP32 when every FP64
+    weight is an FP32 number, FP64 otherwise (the sphere); a vertex coefficient that breaks
+    the exactness switches back, and the operator still matches the oracle."""
+    for l in range(c1.top + 1):
+        i = mg.mg_hierarchy_info(c1.g.h, l)
+        assert (i["weight_bytes32"], i["weight_bytes64"]) == (2, 2), (l, i)
+    for l in range(sphere.top + 1):
+        i = mg.mg_hierarchy_info(sphere.g.h, l)
+        assert (i["weight_bytes32"], i["weight_bytes64"]) == (4, 8), (l, i)
+    nv = c1.o.fine.nv
+    k = np.exp(0.3 * W.normal(nv, 77))
+    mg.mg_hierarchy_set_vertex_coeff(c1.g.h, gpu(k))
+    try:
+        i = mg.mg_hierarchy_info(c1.g.h, c1.top)
+        assert (i["weight_bytes32"], i["weight_bytes64"]) == (4, 8)
+        # the finest operator with edge coefficients (k_a + k_b) / 2, built independently;
+        # Dirichlet form M L M + (I - M)
+        import scipy.sparse as sp
+        m = c1.o.fine
+        x = W.normal(nv, 78)
+        ke = 0.5 * (k[m.edges[:, 0]] + k[m.edges[:, 1]])
+        L = (m.d0.T @ sp.diags(m.star1 * ke) @ m.d0).tocsr()
+        xm = x.copy()
+        xm[m.bnd] = 0.0
+        ref = L @ xm
+        ref[m.bnd] = x[m.bnd]
+        y = torch.zeros(nv, dtype=torch.float64, device=DEV)
+        mg.dec_laplacian_apply(c1.g.h, c1.top, gpu(x), y)
+        assert rel(host(y), ref) <= 1e-13
+    finally:
+        mg.mg_hierarchy_set_vertex_coeff(c1.g.h, None)
+    i = mg.mg_hierarchy_info(c1.g.h, c1.top)
+    assert (i["weight_bytes32"], i["weight_bytes64"]) == (2, 2)
+
+
 @pytest.mark.parametrize("which", PAIRS)
 @pytest.mark.parametrize("dt", ["f64", "f32"])
 def test_laplacian_apply(which, dt, request):

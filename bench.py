@@ -95,7 +95,7 @@ def sweep_kernel_name(info):
     columns, binary16 or FP32 weights."""
     return "%s<float, 2, %s, %s>" % ("k_rows2" if info["rows_per_thread"] == 2 else "k_rows",
                                     "true" if info["index_bytes"] == 2 else "false",
-                                    "_Float16" if info["weight_bytes32"] == 2 else "float")
+                                    "Half16" if info["weight_bytes32"] == 2 else "float")
 
 
 def sweep_grid(info):

@@ -30,10 +30,10 @@ def test_headline_sweep_bytes():
             "weight_bytes32": 2, "weight_bytes64": 2, "rows_per_thread": 2}
     assert bench.kernel_bytes(info, 4, "jacobi") == 16760836 * 4 + 4190209 * 12 == 117325852
     assert bench.kernel_bytes(info, 8, "spmv") == 16760836 * 4 + 4190209 * 16
-    assert bench.sweep_kernel_name(info) == "k_rows2<float, 2, true, _Float16>"
+    assert bench.sweep_kernel_name(info) == "k_rows2<float, 2, true, Half16>"
     assert bench.sweep_grid(info) == 2095360 and bench.sweep_grid(dict(info, rows_per_thread=1)) == 4190464
     assert bench.sweep_kernel_name(dict(info, index_bytes=4, rows_per_thread=1)) == \
-        "k_rows<float, 2, false, _Float16>"
+        "k_rows<float, 2, false, Half16>"
     # general weights: FP32 for FP32 kernels, FP64 for FP64 kernels
     info.update(weight_bytes32=4, weight_bytes64=8)
     assert bench.kernel_bytes(info, 4, "jacobi") == 16760836 * 6 + 4190209 * 12 == 150847524
@@ -44,7 +44,7 @@ def test_headline_sweep_bytes():
 
 
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
-    key = "k_rows2<float, 2, true, _Float16>@2095360"
+    key = "k_rows2<float, 2, true, Half16>@2095360"
     prof = os.path.join(ROOT, "profiles", "c3_finest_kernels_hbm_traffic.md")
     # a copy of the repository layout whose kernel source differs from the recorded hash
     (tmp_path / "profiles").mkdir()

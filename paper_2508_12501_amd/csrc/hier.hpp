@@ -103,9 +103,9 @@ struct DevTiles {
 // per SIMD.
 constexpr int kTileThreads = 1024;
 
-// Levels up to this many rows are launch-bound: there the interpolation is fused into the
-// first post-smoothing sweep (one launch fewer); on larger levels the extra dependent gathers
-// of the fused kernel cost more than the separate pass.
+// Levels up to this many rows are launch-bound: binary ones run the fused tiles; on the others
+// the interpolation is fused into the first post-smoothing sweep (one launch fewer).  On larger
+// levels the extra dependent gathers of either cost more than the separate passes.
 constexpr int32_t kLaunchBoundRows = 1 << 19;
 constexpr int kCoarseThreads = 1024;       // workgroup of the fused coarse cycle
 constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse cycle

@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "batch.hpp"
+#include "half16.hpp"
 #include "util.hpp"
 
 namespace decmg {
@@ -109,7 +110,7 @@ __device__ __forceinline__ void brow(const int32_t* __restrict__ sptr, const voi
     default:
       for (int k = 0; k < width; ++k) {
         const int idx = (beg + k) * kSlice + lane;
-        const T wk = w[idx];
+        const T wk = static_cast<T>(w[idx]);
         d += wk;
         acc += wk * (xi - x[colx<D16>(col, idx, row, n) * M + c]);
       }
@@ -206,7 +207,7 @@ __global__ __launch_bounds__(kThreads) void bk_prolong_sweep(
     const int idx = (beg + k) * kSlice + lane;
     const int j = colx<D16>(col, idx, row, n);
     const T xj = x[j * M + c] + T(0.5) * (ec[pa[j] * M + c] + ec[pb[j] * M + c]);
-    const T wk = w[idx];
+    const T wk = static_cast<T>(w[idx]);
     d += wk;
     acc += wk * (xi0 - xj);
   }
@@ -657,10 +658,15 @@ void with_m(int M, F&& f) {
   }
 }
 
-// Calls f(w) with the weights T-arithmetic kernels read: FP32 for FP32 kernels, and for FP64
-// kernels too when every FP64 weight of the level equals its FP32 copy.
+// Calls f(w) with the weights T-arithmetic kernels read: the binary16 copy when every weight of
+// the level is exactly a binary16 number, else FP32 for FP32 kernels, and for FP64 kernels too
+// when every FP64 weight of the level equals its FP32 copy (the same values in every case).
 template <typename T, typename F>
 void with_wts(const Level& L, F&& f) {
+  if (L.op.w_exact16) {
+    f(reinterpret_cast<const Half16*>(L.op.w16));
+    return;
+  }
   if constexpr (std::is_same<T, float>::value) {
     f(static_cast<const float*>(L.op.w32));
   } else {

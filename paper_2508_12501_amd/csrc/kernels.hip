@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 
+#include "half16.hpp"
 #include "hier.hpp"
 #include "util.hpp"
 
@@ -87,18 +88,6 @@ __device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int
 // reproduce the per-step kernels bit for bit.
 __device__ __forceinline__ double mac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float mac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// An IEEE binary16 weight, widened exactly to FP32 or FP64 (a named type rather than _Float16
-// so that the kernels instantiated on it keep demangled names in profiler output).
-struct Half16 {
-  uint16_t bits;
-  __device__ __forceinline__ explicit operator float() const {
-    return static_cast<float>(__builtin_bit_cast(_Float16, bits));
-  }
-  __device__ __forceinline__ explicit operator double() const {
-    return static_cast<double>(__builtin_bit_cast(_Float16, bits));
-  }
-};
 
 // Column and weight of SELL entry idx of `row`; the weight array is FP64, FP32 or binary16,
 // widened to T exactly.

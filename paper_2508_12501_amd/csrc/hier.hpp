@@ -98,10 +98,11 @@ struct DevTiles {
                                // midpoints (zero slot past the row's width)
 };
 // One workgroup of kTileThreads threads per tile of up to 256 owned rows, one ring row per
-// thread (cap <= kTileThreads): four wavefronts per SIMD hide each other's dependent chains
-// (FP64 divisions above all), where 256 threads with four ring rows each left one wavefront
-// per SIMD.
-constexpr int kTileThreads = 1024;
+// thread when the rings fit (cap <= kTileThreads, C3: 448), two otherwise (cap <= 2
+// kTileThreads, the sphere).  Several wavefronts per SIMD hide each other's dependent chains
+// (FP64 divisions above all): 256 threads with four ring rows each left one wavefront per SIMD
+// and lost in FP64; 512 threads came out about 1% faster than 1024 on C3.
+constexpr int kTileThreads = 512;
 
 // Levels up to this many rows are launch-bound: binary ones run the fused tiles; on the others
 // the interpolation is fused into the first post-smoothing sweep (one launch fewer).  On larger

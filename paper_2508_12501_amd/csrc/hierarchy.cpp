@@ -596,14 +596,14 @@ std::vector<T> download(const T* d, size_t n) {
 
 // Workgroup tiles of the fused smoothing kernels of binary level F over its coarse level C
 // (see DevTiles), on levels of at most kLaunchBoundRows rows.  Leaves F.tiles empty when a row
-// or restriction list is wider than 8 or a tile's rings exceed kTileThreads rows; the level
+// or restriction list is wider than 8 or a tile's rings exceed 2 kTileThreads rows; the level
 // then runs one kernel per step.  (Tiles of 4096 rows on the larger C3 levels, with 1.15x
 // rings, were measured slower than the streaming per-step kernels there.)
 void build_tiles(Level& F, const Level& C) {
   const int32_t n = F.n, nc = C.n;
   if (n == 0 || nc == 0 || F.tr.weighted || n > kLaunchBoundRows) return;
   const int32_t fb = kBlock;                 // owned rows per tile at most
-  const int32_t capmax = kTileThreads, ccapmax = kTileThreads;
+  const int32_t capmax = 2 * kTileThreads, ccapmax = kTileThreads;
   const int32_t nsl = int32_t(F.sptr_h.size()) - 1;
   int32_t wmax = 0;
   for (int32_t s = 0; s < nsl; ++s) wmax = std::max(wmax, F.sptr_h[s + 1] - F.sptr_h[s]);

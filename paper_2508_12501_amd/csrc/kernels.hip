@@ -2222,10 +2222,13 @@ void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, c
                          D.crow, D.cst, D.cap, D.ccap, L.op.uw, w, diagonal<T>(L), b, x, bc,
                          static_cast<T>(omega), nu1, done);
     };
+    const bool one = D.cap <= kTileThreads;
     if (D.kt == 4)
-      go(k_tile_down<T, WT, 4, kTileThreads, 1, 1>, kTileThreads);
+      one ? go(k_tile_down<T, WT, 4, kTileThreads, 1, 1>, kTileThreads)
+          : go(k_tile_down<T, WT, 4, kTileThreads, 2, 1>, kTileThreads);
     else
-      go(k_tile_down<T, WT, 8, kTileThreads, 1, 1>, kTileThreads);
+      one ? go(k_tile_down<T, WT, 8, kTileThreads, 1, 1>, kTileThreads)
+          : go(k_tile_down<T, WT, 8, kTileThreads, 2, 1>, kTileThreads);
   });
 }
 template <typename T>
@@ -2241,10 +2244,13 @@ void tile_up(const Level& L, const T* ec, const T* x, const T* b, T* xo, double 
                          D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
                          static_cast<T>(omega), nu2, done);
     };
+    const bool one = D.cap <= kTileThreads;
     if (D.kt == 4)
-      go(k_tile_up<T, WT, 4, kTileThreads, 1>, kTileThreads);
+      one ? go(k_tile_up<T, WT, 4, kTileThreads, 1>, kTileThreads)
+          : go(k_tile_up<T, WT, 4, kTileThreads, 2>, kTileThreads);
     else
-      go(k_tile_up<T, WT, 8, kTileThreads, 1>, kTileThreads);
+      one ? go(k_tile_up<T, WT, 8, kTileThreads, 1>, kTileThreads)
+          : go(k_tile_up<T, WT, 8, kTileThreads, 2>, kTileThreads);
   });
 }
 

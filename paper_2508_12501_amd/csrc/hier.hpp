@@ -94,8 +94,12 @@ struct DevTiles {
                                // the level's slices are uniform (index computed from the row)
   int16_t* col = nullptr;      // [tile][kt][cap]: local id of entry k (zero slot past the width)
   int32_t* crow = nullptr;     // [tile][ccap]: internal coarse id
-  int16_t* cst = nullptr;      // [tile][9][ccap]: local ids of the kept vertex, then of up to 8
-                               // midpoints (zero slot past the row's width)
+  int16_t* cst = nullptr;      // [tile][rws][ccap]: binary levels: local ids of the kept vertex,
+                               // then of up to 8 midpoints (zero slot past the row's width);
+                               // weighted levels: local ids of the row's entries in SELL order
+  int32_t rws = 9;             // slots per owned coarse row in cst
+  int32_t* cent = nullptr;     // weighted levels, [tile][ccap]: (SELL index of the coarse row's
+                               // first restriction entry) << 6 | its width
 };
 // One workgroup of kTileThreads threads per tile of up to 256 owned rows, one ring row per
 // thread when the rings fit (cap <= kTileThreads, C3: 448), two otherwise (cap <= 2

@@ -594,14 +594,15 @@ std::vector<T> download(const T* d, size_t n) {
   return h;
 }
 
-// Workgroup tiles of the fused smoothing kernels of binary level F over its coarse level C
-// (see DevTiles), on levels of at most kLaunchBoundRows rows.  Leaves F.tiles empty when a row
+// Workgroup tiles of the fused smoothing kernels of level F over its coarse level C (see
+// DevTiles), on levels of at most kLaunchBoundRows rows, with binary or weighted transfers.  Leaves F.tiles empty when a row
 // or restriction list is wider than 8 or a tile's rings exceed 2 kTileThreads rows; the level
 // then runs one kernel per step.  (Tiles of 4096 rows on the larger C3 levels, with 1.15x
 // rings, were measured slower than the streaming per-step kernels there.)
 void build_tiles(Level& F, const Level& C) {
   const int32_t n = F.n, nc = C.n;
-  if (n == 0 || nc == 0 || F.tr.weighted || n > kLaunchBoundRows) return;
+  if (n == 0 || nc == 0 || n > kLaunchBoundRows) return;
+  const bool wtr = F.tr.weighted;
   const int32_t fb = kBlock;                 // owned rows per tile at most
   const int32_t capmax = 2 * kTileThreads, ccapmax = kTileThreads;
   const int32_t nsl = int32_t(F.sptr_h.size()) - 1;
@@ -609,21 +610,45 @@ void build_tiles(Level& F, const Level& C) {
   for (int32_t s = 0; s < nsl; ++s) wmax = std::max(wmax, F.sptr_h[s + 1] - F.sptr_h[s]);
   if (wmax > 8) return;
   const int kt = wmax <= 4 ? 4 : 8;
-  // restriction lists (device layout) and the coarse row of every kept fine row
-  const std::vector<int32_t> self = download(F.tr.r_self, size_t(nc) + 1);
-  const std::vector<int32_t> rsptr = download(F.tr.r_sptr, size_t(F.tr.nslices) + 1);
-  const std::vector<int32_t> rcol = download(F.tr.r_col, size_t(rsptr.back() + 1) * kSlice);
-  std::vector<int32_t> own(n, -1);
-  for (int32_t c = 0; c < nc; ++c) {
-    if (self[c] < 0 || self[c] >= n || own[self[c]] >= 0)
-      throw std::logic_error("restriction: kept vertices are not distinct fine rows");
-    own[self[c]] = c;
-    if (rsptr[c / kSlice + 1] - rsptr[c / kSlice] > 8) return;
+  // restriction lists (device layout).  Binary levels: the kept vertex plus up to 8 midpoints
+  // (weight 1/2); weighted levels: (fine row, weight) entries in SELL order.  Every coarse row
+  // has an anchor fine row, and the tile holding the anchor restricts it: the kept vertex, or
+  // the entry of largest weight (a row without entries goes to the first tile, which writes
+  // its zero).
+  std::vector<int32_t> self, rsptr, rcol;
+  std::vector<double> rwt;
+  if (wtr) {
+    rsptr = download(F.tr.rw_sptr, size_t(F.tr.nslices) + 1);
+    rcol = download(F.tr.rw_col, size_t(rsptr.back() + 1) * kSlice);
+    rwt = download(F.tr.rw64, rcol.size());
+  } else {
+    self = download(F.tr.r_self, size_t(nc) + 1);
+    rsptr = download(F.tr.r_sptr, size_t(F.tr.nslices) + 1);
+    rcol = download(F.tr.r_col, size_t(rsptr.back() + 1) * kSlice);
   }
   auto rwidth = [&](int32_t c) { return rsptr[c / kSlice + 1] - rsptr[c / kSlice]; };
-  auto rentry = [&](int32_t c, int k) {
-    return rcol[size_t(rsptr[c / kSlice] + k) * kSlice + size_t(c % kSlice)];
+  auto ridx = [&](int32_t c, int k) {
+    return size_t(rsptr[c / kSlice] + k) * kSlice + size_t(c % kSlice);
   };
+  auto rentry = [&](int32_t c, int k) { return rcol[ridx(c, k)]; };
+  int32_t rws = 9;   // local id slots per owned coarse row
+  std::vector<int32_t> anchor(nc, -1);
+  for (int32_t c = 0; c < nc; ++c) {
+    if (rwidth(c) > (wtr ? 63 : 8)) return;
+    if (!wtr) {
+      if (self[c] < 0 || self[c] >= n)
+        throw std::logic_error("restriction: kept vertex out of range");
+      anchor[c] = self[c];
+      continue;
+    }
+    rws = std::max(rws, rwidth(c));
+    double best = 0.0;
+    for (int k = 0; k < rwidth(c); ++k)
+      if (rentry(c, k) < n && (anchor[c] < 0 || rwt[ridx(c, k)] > best)) {
+        anchor[c] = rentry(c, k);
+        best = rwt[ridx(c, k)];
+      }
+  }
   // Morton order of the rows on a lattice of the median edge length h: on a grid the rows get
   // their lattice coordinates, so runs of fb consecutive rows are aligned square patches
   double lo[3] = {1e300, 1e300, 1e300};
@@ -667,9 +692,16 @@ void build_tiles(Level& F, const Level& C) {
         i - tstart.back() == fb)
       tstart.push_back(i);
   tstart.push_back(n);
-  // pass 1: the rings of every tile
   const int32_t ntiles = int32_t(tstart.size()) - 1;
+  // the coarse rows of every tile, by anchor
   std::vector<std::vector<int32_t>> trows(ntiles), tcown(ntiles);
+  {
+    std::vector<int32_t> tile_of(n, 0);
+    for (int32_t b = 0; b < ntiles; ++b)
+      for (int32_t i = tstart[b]; i < tstart[b + 1]; ++i) tile_of[key[i].second] = b;
+    for (int32_t c = 0; c < nc; ++c) tcown[anchor[c] >= 0 ? tile_of[anchor[c]] : 0].push_back(c);
+  }
+  // pass 1: the rings of every tile
   std::vector<std::array<int32_t, 5>> cnt(ntiles);   // nF, n0, n1, n2, ncb
   std::vector<int32_t> lid(n, -1), fresh;
   int32_t cap = 0, ccap = 0;
@@ -689,10 +721,7 @@ void build_tiles(Level& F, const Level& C) {
     for (int32_t i = r0; i < r1; ++i) fresh.push_back(key[i].second);
     add_group();
     const int32_t nF = int32_t(rows.size());
-    std::vector<int32_t>& cown = tcown[b];
-    for (int32_t i = 0; i < nF; ++i)
-      if (own[rows[i]] >= 0) cown.push_back(own[rows[i]]);
-    std::sort(cown.begin(), cown.end());
+    const std::vector<int32_t>& cown = tcown[b];
     for (int32_t c : cown)
       for (int k = 0; k < rwidth(c); ++k)
         if (rentry(c, k) < n) fresh.push_back(rentry(c, k));
@@ -723,7 +752,8 @@ void build_tiles(Level& F, const Level& C) {
   std::vector<int32_t> meta(size_t(ntiles) * 8, 0), trow(size_t(ntiles) * cap),
       tent(uniform ? 0 : size_t(ntiles) * cap), tcrow(size_t(ntiles) * ccap, 0);
   std::vector<int16_t> tcol(size_t(ntiles) * kt * cap, int16_t(cap)),
-      tcst(size_t(ntiles) * 9 * ccap, int16_t(cap));
+      tcst(size_t(ntiles) * rws * ccap, int16_t(cap));
+  std::vector<int32_t> tcent(wtr ? size_t(ntiles) * ccap : 0, 0);
   std::vector<char> fine_seen(n, 0), coarse_seen(nc, 0);
   for (int32_t b = 0; b < ntiles; ++b) {
     const std::vector<int32_t>& rows = trows[b];
@@ -751,9 +781,17 @@ void build_tiles(Level& F, const Level& C) {
     for (int32_t j = 0; j < ccap; ++j) tcrow[size_t(b) * ccap + j] = ncb ? cown[j < ncb ? j : 0] : 0;
     for (int32_t j = 0; j < ncb; ++j) {
       const int32_t c = cown[j];
-      tcst[size_t(b) * 9 * ccap + j] = int16_t(lid[self[c]]);
+      // binary: slot 0 the kept vertex, slots 1.. the midpoints; weighted: slot k entry k
+      const int off = wtr ? 0 : 1;
+      if (!wtr) tcst[size_t(b) * rws * ccap + j] = int16_t(lid[self[c]]);
       for (int k = 0; k < rwidth(c); ++k)
-        tcst[(size_t(b) * 9 + k + 1) * ccap + j] = int16_t(rentry(c, k) < n ? lid[rentry(c, k)] : cap);
+        tcst[(size_t(b) * rws + k + off) * ccap + j] =
+            int16_t(rentry(c, k) < n ? lid[rentry(c, k)] : cap);
+      if (wtr) {
+        const size_t e0 = ridx(c, 0);
+        if (e0 >= (size_t(1) << 25)) throw std::logic_error("tiles: restriction index overflow");
+        tcent[size_t(b) * ccap + j] = int32_t(e0 << 6) | rwidth(c);
+      }
       coarse_seen[c]++;
     }
     for (int32_t i = 0; i < nF; ++i) fine_seen[rows[i]]++;
@@ -786,6 +824,8 @@ void build_tiles(Level& F, const Level& C) {
   T.col = upload(tcol);
   T.crow = upload(tcrow);
   T.cst = upload(tcst);
+  T.rws = rws;
+  T.cent = wtr ? upload(tcent) : nullptr;
 }
 
 // The IEEE binary16 encoding of v when v is exactly a binary16 number (zero, normal or
@@ -1007,7 +1047,8 @@ Hierarchy::~Hierarchy() {
         free_dev(p);
     free_dev(L.row_color);
     for (void* p : {(void*)L.tiles.meta, (void*)L.tiles.row, (void*)L.tiles.ent,
-                    (void*)L.tiles.col, (void*)L.tiles.crow, (void*)L.tiles.cst})
+                    (void*)L.tiles.col, (void*)L.tiles.crow, (void*)L.tiles.cst,
+                    (void*)L.tiles.cent})
       free_dev(p);
   }
   for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,

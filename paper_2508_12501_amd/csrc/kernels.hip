@@ -89,6 +89,13 @@ __device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int
 __device__ __forceinline__ double mac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float mac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// sum_k w_k e_k over the three parents of a weighted interpolation, in parent order with one
+// rounding per term
+template <typename T>
+__device__ __forceinline__ T interp3(T wa, T wb, T wc, T ea, T eb, T ec) {
+  return mac(wc, ec, mac(wb, eb, wa * ea));
+}
+
 // Column and weight of SELL entry idx of `row`; the weight array is FP64, FP32 or binary16,
 // widened to T exactly.
 template <typename T, bool D16, typename WT>
@@ -543,13 +550,14 @@ __device__ __forceinline__ void tile_row(int g, int i, int cap, const int32_t* _
   }
 }
 
-template <typename T, typename WT, int KT, int TB, int Q, int CQ>
+template <typename T, typename WT, int KT, int TB, int Q, int CQ, bool WTR>
 __global__ __launch_bounds__(TB) void k_tile_down(
     const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
     const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol,
     const int32_t* __restrict__ tcrow, const int16_t* __restrict__ tcst, int32_t cap,
     int32_t ccap, int32_t uw, const WT* __restrict__ w, const T* __restrict__ diag,
     const T* __restrict__ b, T* __restrict__ x, T* __restrict__ bc, T omega, int nu1,
+    const int32_t* __restrict__ tcent, int32_t rws, const T* __restrict__ rw,
     const int* __restrict__ done) {
   extern __shared__ double tile_smem[];
   T* s1 = reinterpret_cast<T*>(tile_smem);
@@ -574,14 +582,19 @@ __global__ __launch_bounds__(TB) void k_tile_down(
       x1[q] = omega * bq[q] / diag[g[q]];
     }
   }
-  // restriction rows: CQ per thread at most (ccap <= CQ TB)
-  int crow[CQ], cs[CQ][9];
+  // restriction rows: CQ per thread at most (ccap <= CQ TB); binary transfers keep their nine
+  // local ids in registers, weighted ones read theirs when the residual is ready
+  int crow[CQ], cs[CQ][9], ce[CQ];
 #pragma unroll
   for (int c = 0; c < CQ; ++c) {
     const int j = min(t + c * TB, ccap - 1);
     crow[c] = tcrow[static_cast<int64_t>(tb) * ccap + j];
+    if constexpr (WTR) {
+      ce[c] = tcent[static_cast<int64_t>(tb) * ccap + j];
+    } else {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) cs[c][k] = tcst[(static_cast<int64_t>(tb) * 9 + k) * ccap + j];
+      for (int k = 0; k < 9; ++k) cs[c][k] = tcst[(static_cast<int64_t>(tb) * rws + k) * ccap + j];
+    }
   }
   // x1 = omega b / D on every local row (the first sweep from zero is local)
 #pragma unroll
@@ -630,26 +643,34 @@ __global__ __launch_bounds__(TB) void k_tile_down(
     }
   }
   __syncthreads();
-  // restriction of the residual onto the tile's coarse rows (k_restrict)
+  // restriction of the residual onto the tile's coarse rows (k_restrict / k_restrict_w)
   if (dn) return;
 #pragma unroll
   for (int c = 0; c < CQ; ++c)
     if (t + c * TB < ncb) {
       T acc = T(0);
+      if constexpr (WTR) {
+        // the coarse row's entries in SELL order: local fine ids here, weights at e0 + k 64
+        const int j = t + c * TB, e0 = ce[c] >> 6, wd = ce[c] & 63;
+        const int16_t* ids = tcst + static_cast<int64_t>(tb) * rws * ccap + j;
+        for (int k = 0; k < wd; ++k) acc = mac(rw[e0 + k * kSlice], sr[ids[k * ccap]], acc);
+        bc[crow[c]] = acc;
+      } else {
 #pragma unroll
-      for (int k = 1; k < 9; ++k) acc += sr[cs[c][k]];
-      bc[crow[c]] = sr[cs[c][0]] + T(0.5) * acc;
+        for (int k = 1; k < 9; ++k) acc += sr[cs[c][k]];
+        bc[crow[c]] = sr[cs[c][0]] + T(0.5) * acc;
+      }
     }
 }
 
-template <typename T, typename WT, int KT, int TB, int Q>
+template <typename T, typename WT, int KT, int TB, int Q, bool WTR>
 __global__ __launch_bounds__(TB) void k_tile_up(
     const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
     const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol, int32_t cap,
     int32_t uw, const WT* __restrict__ w, const int32_t* __restrict__ pa,
     const int32_t* __restrict__ pb, const T* __restrict__ ec, const T* __restrict__ x,
     const T* __restrict__ b, T* __restrict__ xo, T omega, int nu2,
-    const int* __restrict__ done) {
+    const int32_t* __restrict__ p3, const T* __restrict__ pw, const int* __restrict__ done) {
   extern __shared__ double tile_smem[];
   T* s0 = reinterpret_cast<T*>(tile_smem);
   T* s1 = s0 + (cap + 1);
@@ -663,7 +684,8 @@ __global__ __launch_bounds__(TB) void k_tile_up(
   const int16_t* cols = tcol + static_cast<int64_t>(tb) * KT * cap;
   int g[Q], wid[Q], cj[Q][KT];
   T wk[Q][KT], bq[Q], xq[Q];
-  int ia[Q], ib[Q];
+  int ia[Q], ib[Q], ic[Q];
+  T wa[Q], wb[Q], wc[Q];
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = t + q * TB;
@@ -672,16 +694,29 @@ __global__ __launch_bounds__(TB) void k_tile_up(
       tile_row<T, WT, KT>(g[q], i, cap, ents, uw, cols, w, wid[q], cj[q], wk[q]);
       bq[q] = b[g[q]];
       xq[q] = x[g[q]];
-      ia[q] = pa[g[q]];
-      ib[q] = pb[g[q]];
+      if constexpr (WTR) {
+        const int64_t o = 3 * static_cast<int64_t>(g[q]);
+        ia[q] = p3[o];
+        ib[q] = p3[o + 1];
+        ic[q] = p3[o + 2];
+        wa[q] = pw[o];
+        wb[q] = pw[o + 1];
+        wc[q] = pw[o + 2];
+      } else {
+        ia[q] = pa[g[q]];
+        ib[q] = pb[g[q]];
+      }
     }
   }
-  // x0 = x + M(f)^T ec on every local row (k_prolong_sweep's rounding)
+  // x0 = x + M(f)^T ec on every local row (k_prolong_sweep's / k_prolong3's rounding)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = t + q * TB;
     if (q < nq && i < n2) {
-      xq[q] = xq[q] + T(0.5) * (ec[ia[q]] + ec[ib[q]]);
+      if constexpr (WTR)
+        xq[q] = xq[q] + interp3(wa[q], wb[q], wc[q], ec[ia[q]], ec[ib[q]], ec[ic[q]]);
+      else
+        xq[q] = xq[q] + T(0.5) * (ec[ia[q]] + ec[ib[q]]);
       s0[i] = xq[q];
     }
   }
@@ -914,7 +949,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong3(const int32_t* __restrict__
   const int a = p3[o], b = p3[o + 1], c = p3[o + 2];
   const T wa = static_cast<T>(pw[o]), wb = static_cast<T>(pw[o + 1]),
           wc = static_cast<T>(pw[o + 2]);
-  const T v = xf[row] + (wa * ec[a] + wb * ec[b] + wc * ec[c]);
+  const T v = xf[row] + interp3(wa, wb, wc, ec[a], ec[b], ec[c]);
   DECMG_DONE_CHECK()
   xf[row] = v;
 }
@@ -948,11 +983,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict_w(const int32_t* __restrict
 #pragma unroll
     for (int q = 0; q < 4; ++q) v[q] = rf[cj[q]];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc += wk[q] * v[q];
+    for (int q = 0; q < 4; ++q) acc = mac(wk[q], v[q], acc);
   }
   for (; k < width; ++k) {
     const int idx = (beg + k) * kSlice + lane;
-    acc += static_cast<T>(w[idx]) * rf[col[idx]];
+    acc = mac(static_cast<T>(w[idx]), rf[col[idx]], acc);
   }
   DECMG_DONE_CHECK()
   rc[row] = acc;
@@ -2208,6 +2243,15 @@ void prolong_sweep(const Level& Lf, const Level& /*Lc*/, const T* ec, const T* x
 }
 template <typename T>
 static size_t tile_lds(const DevTiles& D) { return 2 * size_t(D.cap + 1) * sizeof(T); }
+// weights of the weighted transfers in the arithmetic type (as k_restrict_w / k_prolong3 read)
+template <typename T>
+static const T* transfer_weights(const Level& L) {
+  if constexpr (std::is_same<T, float>::value) return L.tr.rw32; else return L.tr.rw64;
+}
+template <typename T>
+static const T* interp_weights(const Level& L) {
+  if constexpr (std::is_same<T, float>::value) return L.tr.pw32; else return L.tr.pw64;
+}
 
 template <typename T>
 void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done,
@@ -2217,18 +2261,27 @@ void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, c
   const size_t lds = tile_lds<T>(D);
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    const T* rw = transfer_weights<T>(L);
     auto go = [&](auto kern, int tbk) {
       hipLaunchKernelGGL(kern, dim3(D.ntiles), dim3(tbk), lds, s, D.meta, D.row, D.ent, D.col,
                          D.crow, D.cst, D.cap, D.ccap, L.op.uw, w, diagonal<T>(L), b, x, bc,
-                         static_cast<T>(omega), nu1, done);
+                         static_cast<T>(omega), nu1, D.cent, D.rws, rw, done);
     };
     const bool one = D.cap <= kTileThreads;
-    if (D.kt == 4)
-      one ? go(k_tile_down<T, WT, 4, kTileThreads, 1, 1>, kTileThreads)
-          : go(k_tile_down<T, WT, 4, kTileThreads, 2, 1>, kTileThreads);
-    else
-      one ? go(k_tile_down<T, WT, 8, kTileThreads, 1, 1>, kTileThreads)
-          : go(k_tile_down<T, WT, 8, kTileThreads, 2, 1>, kTileThreads);
+    if (L.tr.weighted) {
+      if (D.kt == 4)
+        one ? go(k_tile_down<T, WT, 4, kTileThreads, 1, 1, true>, kTileThreads)
+            : go(k_tile_down<T, WT, 4, kTileThreads, 2, 1, true>, kTileThreads);
+      else
+        one ? go(k_tile_down<T, WT, 8, kTileThreads, 1, 1, true>, kTileThreads)
+            : go(k_tile_down<T, WT, 8, kTileThreads, 2, 1, true>, kTileThreads);
+    } else if (D.kt == 4) {
+      one ? go(k_tile_down<T, WT, 4, kTileThreads, 1, 1, false>, kTileThreads)
+          : go(k_tile_down<T, WT, 4, kTileThreads, 2, 1, false>, kTileThreads);
+    } else {
+      one ? go(k_tile_down<T, WT, 8, kTileThreads, 1, 1, false>, kTileThreads)
+          : go(k_tile_down<T, WT, 8, kTileThreads, 2, 1, false>, kTileThreads);
+    }
   });
 }
 template <typename T>
@@ -2239,18 +2292,27 @@ void tile_up(const Level& L, const T* ec, const T* x, const T* b, T* xo, double 
   const size_t lds = tile_lds<T>(D);
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
+    const T* pw = interp_weights<T>(L);
     auto go = [&](auto kern, int tbk) {
       hipLaunchKernelGGL(kern, dim3(D.ntiles), dim3(tbk), lds, s, D.meta, D.row, D.ent, D.col,
                          D.cap, L.op.uw, w, L.tr.pa, L.tr.pb, ec, x, b, xo,
-                         static_cast<T>(omega), nu2, done);
+                         static_cast<T>(omega), nu2, L.tr.p3, pw, done);
     };
     const bool one = D.cap <= kTileThreads;
-    if (D.kt == 4)
-      one ? go(k_tile_up<T, WT, 4, kTileThreads, 1>, kTileThreads)
-          : go(k_tile_up<T, WT, 4, kTileThreads, 2>, kTileThreads);
-    else
-      one ? go(k_tile_up<T, WT, 8, kTileThreads, 1>, kTileThreads)
-          : go(k_tile_up<T, WT, 8, kTileThreads, 2>, kTileThreads);
+    if (L.tr.weighted) {
+      if (D.kt == 4)
+        one ? go(k_tile_up<T, WT, 4, kTileThreads, 1, true>, kTileThreads)
+            : go(k_tile_up<T, WT, 4, kTileThreads, 2, true>, kTileThreads);
+      else
+        one ? go(k_tile_up<T, WT, 8, kTileThreads, 1, true>, kTileThreads)
+            : go(k_tile_up<T, WT, 8, kTileThreads, 2, true>, kTileThreads);
+    } else if (D.kt == 4) {
+      one ? go(k_tile_up<T, WT, 4, kTileThreads, 1, false>, kTileThreads)
+          : go(k_tile_up<T, WT, 4, kTileThreads, 2, false>, kTileThreads);
+    } else {
+      one ? go(k_tile_up<T, WT, 8, kTileThreads, 1, false>, kTileThreads)
+          : go(k_tile_up<T, WT, 8, kTileThreads, 2, false>, kTileThreads);
+    }
   });
 }
 

@@ -7,8 +7,10 @@ solves with and without graph replay.  Agreement of the unfused path with the or
 subject of the other parity tests (which now run fused by default).
 
 Meshes: a 257 x 257 square (uniform slices, 4 entries per row), a ragged 97 x 97 square, the
-icosphere (natural boundary, 6 entries per row), and a fan disk whose centre has valence 8
-(slices of different widths: the tiles then carry each row's entry index)."""
+icosphere (natural boundary, 6 entries per row), a fan disk whose centre has valence 8 (slices
+of different widths: the tiles then carry each row's entry index), and two hierarchies with
+cubic (weighted) transfers: cubic, cubic, binary subdivisions of the 4 x 4 square, and the
+105,625-vertex mesh of four cubic subdivisions."""
 import math
 
 import numpy as np
@@ -38,11 +40,15 @@ def build(which):
         return mg.Hierarchy("square", 5, base_cells=3)
     if which == "sphere":
         return mg.Hierarchy("sphere", 5, bc=mg.MG_BC_NATURAL)
+    if which == "cubic":
+        return mg.Hierarchy("square", 3, base_cells=4, cubic_mask=0b011)
+    if which == "e1":
+        return mg.Hierarchy("square", 4, base_cells=4, cubic_mask=0b1111)
     xyz, tri = fan_disk(8)
     return mg.Hierarchy("arrays", 5, xyz=xyz, tri=tri)
 
 
-MESHES = ["sq", "rag", "sphere", "fan8"]
+MESHES = ["sq", "rag", "sphere", "fan8", "cubic", "e1"]
 
 
 @pytest.fixture(scope="module")

@@ -146,14 +146,17 @@ __global__ __launch_bounds__(kThreads) void bk_rows(const int32_t* __restrict__ 
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(kThreads) void bk_jacobi_zero(const T* __restrict__ diag,
+__global__ __launch_bounds__(kThreads) void bk_jacobi_zero(const T* __restrict__ idiag,
                                                            const T* __restrict__ b,
                                                            T* __restrict__ y, int32_t n, T omega,
                                                            const BatchFlag* __restrict__ flag) {
   if (flag && flag->all_done) return;
   BK_ROWCOL(M)
   if (row >= n) return;
-  y[row * M + c] = omega * b[row * M + c] / diag[row];
+  {
+#pragma clang fp contract(off)
+    y[row * M + c] = omega * b[row * M + c] * idiag[row];
+  }
 }
 
 template <typename T, int M>
@@ -678,9 +681,9 @@ void with_wts(const Level& L, F&& f) {
 }
 template <typename P>
 using pointee = std::remove_const_t<std::remove_pointer_t<P>>;
-template <typename T> const T* diag_of(const Level& L);
-template <> const double* diag_of<double>(const Level& L) { return L.op.diag64; }
-template <> const float* diag_of<float>(const Level& L) { return L.op.diag32; }
+template <typename T> const T* idiag_of(const Level& L);
+template <> const double* idiag_of<double>(const Level& L) { return L.op.idiag64; }
+template <> const float* idiag_of<float>(const Level& L) { return L.op.idiag32; }
 
 }  // namespace
 
@@ -868,7 +871,7 @@ void jacobi_zero(int M, const Level& L, const T* b, T* y, double omega, const Ba
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
     hipLaunchKernelGGL((bk_jacobi_zero<T, MM>), dim3(row_blocks(L.n, MM)), dim3(kThreads), 0, s,
-                       diag_of<T>(L), b, y, L.n, static_cast<T>(omega), flag);
+                       idiag_of<T>(L), b, y, L.n, static_cast<T>(omega), flag);
   });
 }
 

@@ -47,8 +47,11 @@ struct DevOperator {
   // weight is exactly a binary16 number (the widened values are then the weights bit for bit)
   uint16_t* w16 = nullptr;
   bool w_exact16 = false;
-  double* diag64 = nullptr;   // sum of the row's weights, in SELL order
-  float* diag32 = nullptr;
+  // 1 / (sum of the row's weights, in SELL order), 1 in the zero slot: the first Jacobi sweep
+  // from zero is x = (omega b) (1/D), a multiplication where a division per coupling cost
+  // vector-ALU time in the two-sweeps-from-zero kernels
+  double* idiag64 = nullptr;
+  float* idiag32 = nullptr;
 };
 
 struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
@@ -129,7 +132,7 @@ struct CoarseLevel {
   const int32_t* sptr = nullptr;
   const int32_t* col = nullptr;
   const T* w = nullptr;
-  const T* diag = nullptr;
+  const T* idiag = nullptr;
   const int32_t* pa = nullptr;       // interpolation from level-1
   const int32_t* pb = nullptr;
   const int32_t* r_self = nullptr;   // restriction into level-1

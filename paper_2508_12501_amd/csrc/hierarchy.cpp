@@ -517,11 +517,11 @@ const double* level_weights<double>(const Level& L) { return L.op.w64; }
 template <>
 const float* level_weights<float>(const Level& L) { return L.op.w32; }
 template <typename T>
-const T* level_diag(const Level& L);
+const T* level_idiag(const Level& L);
 template <>
-const double* level_diag<double>(const Level& L) { return L.op.diag64; }
+const double* level_idiag<double>(const Level& L) { return L.op.idiag64; }
 template <>
-const float* level_diag<float>(const Level& L) { return L.op.diag32; }
+const float* level_idiag<float>(const Level& L) { return L.op.idiag32; }
 
 // Descriptors of the levels that fit the fused coarse cycle's LDS budget.  The LDS holds,
 // for levels 0..ctop, x, partner and b (3 (n+1) values each), then the dense coarsest inverse
@@ -552,7 +552,7 @@ void build_coarse_levels(Hierarchy& H, CoarseLevel<T>*& dev, int& ctop, std::vec
     c.sptr = L.op.sptr;
     c.col = L.op.col;
     c.w = level_weights<T>(L);
-    c.diag = level_diag<T>(L);
+    c.idiag = level_idiag<T>(L);
     c.color = L.row_color;
     c.ncolors = int32_t(L.gs.size());
     if (l >= 1) {
@@ -870,8 +870,8 @@ void upload_weights(Hierarchy& H) {
     if (!L.op.w64) {
       L.op.w64 = zeros<double>(std::max<size_t>(w64.size(), 1));
       L.op.w32 = zeros<float>(std::max<size_t>(w32.size(), 1));
-      L.op.diag64 = zeros<double>(L.n + 1);
-      L.op.diag32 = zeros<float>(L.n + 1);
+      L.op.idiag64 = zeros<double>(L.n + 1);
+      L.op.idiag32 = zeros<float>(L.n + 1);
     }
     L.op.w_exact32 = true;
     for (size_t i = 0; i < w64.size(); ++i)
@@ -891,8 +891,18 @@ void upload_weights(Hierarchy& H) {
         check_hip(hipMemcpy(L.op.w16, w16.data(), w16.size() * 2, hipMemcpyHostToDevice),
                   "hipMemcpy");
     }
-    check_hip(hipMemcpy(L.op.diag64, d64.data(), d64.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
-    check_hip(hipMemcpy(L.op.diag32, d32.data(), d32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+    {
+      std::vector<double> i64(d64.size());
+      std::vector<float> i32(d32.size());
+      for (size_t i = 0; i < d64.size(); ++i) {
+        i64[i] = 1.0 / d64[i];
+        i32[i] = 1.0f / d32[i];
+      }
+      check_hip(hipMemcpy(L.op.idiag64, i64.data(), i64.size() * 8, hipMemcpyHostToDevice),
+                "hipMemcpy");
+      check_hip(hipMemcpy(L.op.idiag32, i32.data(), i32.size() * 4, hipMemcpyHostToDevice),
+                "hipMemcpy");
+    }
     // weights of the Gauss-Seidel colour classes: w = star1 k_e per entry, as for the operator
     for (GsColor& G : L.gs) {
       std::vector<double> g64(G.edge_h.size(), 0.0);
@@ -1032,8 +1042,8 @@ Hierarchy::~Hierarchy() {
     for (void* p : {(void*)L.perm, (void*)L.bnd_ids, (void*)L.star0, (void*)L.op.sptr,
                     (void*)L.op.col, (void*)L.op.col16, (void*)L.op.w64, (void*)L.op.w32,
                     (void*)L.op.w16,
-                    (void*)L.op.diag64,
-                    (void*)L.op.diag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
+                    (void*)L.op.idiag64,
+                    (void*)L.op.idiag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
                     (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.v64.x, (void*)L.v64.b,
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
                     (void*)L.v32.r, (void*)L.v32.t, (void*)L.v64.u, (void*)L.v32.u,

@@ -89,6 +89,16 @@ __device__ __forceinline__ int col_at(const void* __restrict__ col, int idx, int
 __device__ __forceinline__ double mac(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float mac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
+// First Jacobi sweep from zero at one row: omega b (1/D), rounded on its own.  Contraction is
+// off here so that the product is never folded into a caller's subtraction: the fused legs
+// hold this value in LDS, the per-step kernels recompute it at each neighbour, and both must
+// see the same rounded number.
+template <typename T>
+__device__ __forceinline__ T jacobi_first(T omega, T b, T idiag) {
+#pragma clang fp contract(off)
+  return omega * b * idiag;
+}
+
 // sum_k w_k e_k over the three parents of a weighted interpolation, in parent order with one
 // rounding per term
 template <typename T>
@@ -187,10 +197,10 @@ __device__ __forceinline__ void row_apply(const int32_t* __restrict__ sptr, int 
   }
 }
 
-// Same batching for the first two sweeps from zero: gathers b and D instead of x.
+// Same batching for the first two sweeps from zero: gathers b and 1/D instead of x.
 template <typename T, bool D16, int N, typename WT>
 __device__ __forceinline__ void row_two_n(const void* __restrict__ col, const WT* __restrict__ w,
-                                          const T* __restrict__ b, const T* __restrict__ diag,
+                                          const T* __restrict__ b, const T* __restrict__ idiag,
                                           int beg, int lane, int row, int n, T omega, T xi,
                                           T& acc, T& d) {
   int cj[N];
@@ -200,12 +210,12 @@ __device__ __forceinline__ void row_two_n(const void* __restrict__ col, const WT
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     bj[k] = b[cj[k]];
-    dj[k] = diag[cj[k]];
+    dj[k] = idiag[cj[k]];
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     d += wk[k];
-    acc = mac(wk[k], xi - omega * bj[k] / dj[k], acc);
+    acc = mac(wk[k], xi - jacobi_first(omega, bj[k], dj[k]), acc);
   }
 }
 
@@ -226,14 +236,14 @@ __device__ __forceinline__ T restrict_n(const int32_t* __restrict__ col, const T
 }
 
 // The first two smoothing sweeps from x = 0 in one pass: the first sweep is local
-// (x1 = omega b / D), so the second reads b and D at the neighbours instead of x1.  The
+// (x1 = omega b (1/D)), so the second reads b and 1/D at the neighbours instead of x1.  The
 // expressions are those of k_jacobi_zero and k_rows<T,2>, so the result is the same.  The
-// zero slot of D holds 1, making x1 there 0.
+// zero slot of 1/D holds 1, making x1 there 0.
 template <typename T, bool D16, typename WT = T>
 __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict__ sptr, int32_t uw,
                                                        const void* __restrict__ col,
                                                        const WT* __restrict__ w,
-                                                       const T* __restrict__ diag,
+                                                       const T* __restrict__ idiag,
                                                        const T* __restrict__ b,
                                                        T* __restrict__ y, int32_t n, T omega,
                                                        const int* __restrict__ done) {
@@ -244,25 +254,25 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two(const int32_t* __restrict
   slice_bounds(sptr, uw, row, beg, width);
   const int lane = row & 63;
   const T bi = b[row];
-  const T xi = omega * bi / diag[row];
+  const T xi = jacobi_first(omega, bi, idiag[row]);
   T acc = T(0), d = T(0);
   switch (width) {
     case 0: break;
-    case 1: row_two_n<T, D16, 1>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 2: row_two_n<T, D16, 2>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 3: row_two_n<T, D16, 3>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 4: row_two_n<T, D16, 4>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 5: row_two_n<T, D16, 5>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 6: row_two_n<T, D16, 6>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 7: row_two_n<T, D16, 7>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
-    case 8: row_two_n<T, D16, 8>(col, w, b, diag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 1: row_two_n<T, D16, 1>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 2: row_two_n<T, D16, 2>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 3: row_two_n<T, D16, 3>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 4: row_two_n<T, D16, 4>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 5: row_two_n<T, D16, 5>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 6: row_two_n<T, D16, 6>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 7: row_two_n<T, D16, 7>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
+    case 8: row_two_n<T, D16, 8>(col, w, b, idiag, beg, lane, row, n, omega, xi, acc, d); break;
     default:
       for (int k = 0; k < width; ++k) {
         int j;
         T wk;
         entry_at<T, D16>(col, w, (beg + k) * kSlice + lane, row, n, j, wk);
         d += wk;
-        acc = mac(wk, xi - omega * b[j] / diag[j], acc);
+        acc = mac(wk, xi - jacobi_first(omega, b[j], idiag[j]), acc);
       }
   }
   DECMG_DONE_CHECK()
@@ -377,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_rows2(int32_t uw, const void* __rest
 template <typename T, bool D16, typename WT>
 __global__ __launch_bounds__(kBlock) void k_jacobi_two2(int32_t uw, const void* __restrict__ col,
                                                         const WT* __restrict__ w,
-                                                        const T* __restrict__ diag,
+                                                        const T* __restrict__ idiag,
                                                         const T* __restrict__ b,
                                                         T* __restrict__ y, int32_t n, T omega,
                                                         const int* __restrict__ done) {
@@ -386,25 +396,25 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two2(int32_t uw, const void* 
   if (r0 >= n) return;
   const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
   const T b0 = b[r0], b1 = b[r1];
-  const T x0 = omega * b0 / diag[r0], x1 = omega * b1 / diag[r1];
+  const T x0 = jacobi_first(omega, b0, idiag[r0]), x1 = jacobi_first(omega, b1, idiag[r1]);
   T a0, d0, a1, d1;
-  row2<T, D16>(col, w, r0, r1, uw, n, x0, x1, [&](int j) { return omega * b[j] / diag[j]; }, a0,
+  row2<T, D16>(col, w, r0, r1, uw, n, x0, x1, [&](int j) { return jacobi_first(omega, b[j], idiag[j]); }, a0,
                d0, a1, d1);
   DECMG_DONE_CHECK()
   y[r0] = x0 + omega * (b0 - a0) / d0;
   if (r1 != r0) y[r1] = x1 + omega * (b1 - a1) / d1;
 }
 
-// First smoothing sweep from x = 0: x = omega b / D.
+// First smoothing sweep from x = 0: x = omega b (1/D).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_jacobi_zero(const T* __restrict__ diag,
+__global__ __launch_bounds__(kBlock) void k_jacobi_zero(const T* __restrict__ idiag,
                                                         const T* __restrict__ b,
                                                         T* __restrict__ y, int32_t n, T omega,
                                                         const int* __restrict__ done) {
   DECMG_DONE_LOAD(n)
   const int row = xcd_block() * kBlock + threadIdx.x;
   if (row >= n) return;
-  const T v = omega * b[row] / diag[row];
+  const T v = jacobi_first(omega, b[row], idiag[row]);
   DECMG_DONE_CHECK()
   y[row] = v;
 }
@@ -555,7 +565,7 @@ __global__ __launch_bounds__(TB) void k_tile_down(
     const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
     const int32_t* __restrict__ tent, const int16_t* __restrict__ tcol,
     const int32_t* __restrict__ tcrow, const int16_t* __restrict__ tcst, int32_t cap,
-    int32_t ccap, int32_t uw, const WT* __restrict__ w, const T* __restrict__ diag,
+    int32_t ccap, int32_t uw, const WT* __restrict__ w, const T* __restrict__ idiag,
     const T* __restrict__ b, T* __restrict__ x, T* __restrict__ bc, T omega, int nu1,
     const int32_t* __restrict__ tcent, int32_t rws, const T* __restrict__ rw,
     const int* __restrict__ done) {
@@ -579,7 +589,7 @@ __global__ __launch_bounds__(TB) void k_tile_down(
       g[q] = rows[i];
       tile_row<T, WT, KT>(g[q], i, cap, ents, uw, cols, w, wid[q], cj[q], wk[q]);
       bq[q] = b[g[q]];
-      x1[q] = omega * bq[q] / diag[g[q]];
+      x1[q] = jacobi_first(omega, bq[q], idiag[g[q]]);
     }
   }
   // restriction rows: CQ per thread at most (ccap <= CQ TB); binary transfers keep their nine
@@ -596,7 +606,7 @@ __global__ __launch_bounds__(TB) void k_tile_down(
       for (int k = 0; k < 9; ++k) cs[c][k] = tcst[(static_cast<int64_t>(tb) * rws + k) * ccap + j];
     }
   }
-  // x1 = omega b / D on every local row (the first sweep from zero is local)
+  // x1 = omega b (1/D) on every local row (the first sweep from zero is local)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int i = t + q * TB;
@@ -1118,7 +1128,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle(
     T* cx = X;
     T* ox = Tt;
     if (nu1 > 0) {
-      for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] = omega * B[r] / L.diag[r];
+      for (int r = threadIdx.x; r < L.n; r += blockDim.x) cx[r] = jacobi_first(omega, B[r], L.idiag[r]);
       __syncthreads();
       for (int it = 1; it < nu1; ++it) {
         cc_sweep<T, KMAX>(L, sp, cx, B, ox, omega, 2);
@@ -1262,7 +1272,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
         const T w = L.w[idx];
         wv[l][q][k] = (k < wid) ? w : T(0);
       }
-      dg[l][q] = L.diag[row];
+      dg[l][q] = L.idiag[row];
       pa[l][q] = L.pa[row];
       pb[l][q] = L.pb[row];
       clr[l][q] = use_gs ? L.color[row] : 0;
@@ -1356,7 +1366,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
         if (pre > 0) {
 #pragma unroll
           for (int q = 0; q < NQ; ++q)
-            if (t + q * nt < n) cx[t + q * nt] = omega * B[t + q * nt] / dg[L][q];
+            if (t + q * nt < n) cx[t + q * nt] = jacobi_first(omega, B[t + q * nt], dg[L][q]);
           --pre;
         } else {
           for (int i = t; i < n; i += nt) cx[i] = T(0);
@@ -2060,9 +2070,9 @@ const float* weights<float>(const Level& L) { return L.op.w32; }
 template <typename T>
 static const T* diagonal(const Level& L);
 template <>
-const double* diagonal<double>(const Level& L) { return L.op.diag64; }
+const double* diagonal<double>(const Level& L) { return L.op.idiag64; }
 template <>
-const float* diagonal<float>(const Level& L) { return L.op.diag32; }
+const float* diagonal<float>(const Level& L) { return L.op.idiag32; }
 
 // Calls f(w) with the weight array the T-arithmetic row kernels read: the binary16 copy when
 // every weight of the level is exactly a binary16 number, else the FP32 copy for FP32 kernels,

@@ -234,6 +234,9 @@ struct Hierarchy {
   // solver workspace (finest level, internal numbering, n+1 entries)
   double *sx = nullptr, *sr = nullptr, *sp = nullptr, *sq = nullptr, *sz = nullptr,
          *sb = nullptr;
+  // second direction buffer: iteration k reads p from buf[k % 2] and writes buf[(k + 1) % 2]
+  double* sp2 = nullptr;
+  int p_parity = 0;
   double* part = nullptr;          // reduction partials, 3 x max blocks
   int32_t part_cap = 0;
   DevScalars* scal = nullptr;
@@ -361,16 +364,17 @@ void mg_grad_w(const Level& L, const PorousData& D, const double* lam, const dou
 // Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
 int blocks_for(int32_t n);
 int red_blocks(int32_t n);   // grid (= number of partials) of the streaming reductions
-// spmv_dot2 and residual_norm run one 256-row tile per workgroup: blocks_for(n) partials
-void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
-               double* part1, const int* done, hipStream_t s);
+// pupd_spmv_dot2 and residual_norm run one 256-row tile per workgroup: blocks_for(n) partials
+// p_new = z + beta p_old (z from z32 / scale or from z64, minus the mean when asked), q = A p_new,
+// with the block partials of p_new.q (part0) and p_new.r (part1); one partial per kBlock rows
+void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
+                    int sub_mean_flag, const double* p_old, double* p_new, double* q,
+                    const double* r, double* part0, double* part1, const int* done,
+                    hipStream_t s);
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
                double* r, float* r32, double* part0, const int* done, hipStream_t s);
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s);
-// p = z + beta p, or (z - mean) + beta p when sub_mean_flag
-void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
-             hipStream_t s, int sub_mean_flag = 0);
 void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s);
 void sum32(int32_t n, const float* v, const DevScalars* sc, double* part0, const int* done, hipStream_t s);
 void zconv_dot(int32_t n, const DevScalars* sc, const float* z32, double* z, const double* o,
@@ -380,8 +384,6 @@ void zsub_dot(int32_t n, const DevScalars* sc, double* z, const double* o, doubl
 void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s);
 void zdot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, double* part0,
             int sub_mean_flag, const int* done, hipStream_t s);
-void pupd32(int32_t n, const DevScalars* sc, const float* z32, double* p, int sub_mean_flag,
-            const int* done, hipStream_t s);
 void dot(int32_t n, const double* a, const double* b, double* part0, const int* done, hipStream_t s);
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s);
 void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const int* done, hipStream_t s);

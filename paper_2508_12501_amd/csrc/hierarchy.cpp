@@ -1019,6 +1019,7 @@ Hierarchy* build_levels(std::unique_ptr<Hierarchy> H, std::vector<Mesh> meshes,
   H->sx = zeros<double>(n + 1);
   H->sr = zeros<double>(n + 1);
   H->sp = zeros<double>(n + 1);
+  H->sp2 = zeros<double>(n + 1);
   H->sq = zeros<double>(n + 1);
   H->sz = zeros<double>(n + 1);
   const int32_t nvmax = H->lv.back()->nv;
@@ -1061,7 +1062,7 @@ Hierarchy::~Hierarchy() {
                     (void*)L.tiles.cent})
       free_dev(p);
   }
-  for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sq, (void*)sz,
+  for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sp2, (void*)sq, (void*)sz,
                   (void*)sb, (void*)part, (void*)scal})
     free_dev(p);
   if (scal_host) (void)hipHostFree(scal_host);

@@ -1554,25 +1554,83 @@ __global__ void k_star0(const double* __restrict__ s0, const double* __restrict_
 }
 
 // ------------------------------------------------------------------ Krylov kernels (FP64)
-template <bool D16, typename WT = double>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot2(const int32_t* __restrict__ sptr, int32_t uw,
-                                                      const void* __restrict__ col,
-                                                      const WT* __restrict__ w,
-                                                      const double* __restrict__ p,
-                                                      double* __restrict__ q,
-                                                      const double* __restrict__ r,
-                                                      double* __restrict__ part0,
-                                                      double* __restrict__ part1, int32_t n,
-                                                      const int* __restrict__ done) {
+// The preconditioned vector widened to FP64 at one row: z32 / scale for an FP32 cycle output
+// (the scale is a power of two, so this is exact), z itself for an FP64 one; minus the mean on
+// singular systems.  Contraction is off so every row and neighbour gets the same rounding.
+template <typename ZT>
+__device__ __forceinline__ double z_val(ZT zraw, double s, double m, bool sub_mean) {
+#pragma clang fp contract(off)
+  double zj = static_cast<double>(zraw);
+  if constexpr (std::is_same<ZT, float>::value) zj = zj * s;
+  if (sub_mean) zj = zj - m;
+  return zj;
+}
+
+template <typename ZT, bool D16, int N, typename WT>
+__device__ __forceinline__ void row_pnew_n(const void* __restrict__ col, const WT* __restrict__ w,
+                                           const ZT* __restrict__ z, const double* __restrict__ po,
+                                           int beg, int lane, int row, int n, double s, double m,
+                                           bool sub_mean, double beta, double pi, double& acc) {
+  int cj[N];
+  ZT zj[N];
+  double wk[N], pj[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) entry_at<double, D16>(col, w, (beg + k) * kSlice + lane, row, n, cj[k], wk[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    zj[k] = z[cj[k]];
+    pj[k] = po[cj[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double xj = mac(beta, pj[k], z_val(zj[k], s, m, sub_mean));
+    acc = mac(wk[k], pi - xj, acc);
+  }
+}
+
+// The direction update of (flexible) CG folded into its operator product: p = z + beta p_old
+// is formed at the row and again at each neighbour, q = A p, and the block partials of p.q and
+// p.r.  p goes to a second buffer (neighbours still read p_old) and is never read back here,
+// which saves the separate update pass and one write-then-read of p.
+template <typename ZT, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
+    const int32_t* __restrict__ sptr, int32_t uw, const void* __restrict__ col,
+    const WT* __restrict__ w, const DevScalars* __restrict__ sc, const ZT* __restrict__ z,
+    int sub_mean, const double* __restrict__ po, double* __restrict__ pn,
+    double* __restrict__ q, const double* __restrict__ r, double* __restrict__ part0,
+    double* __restrict__ part1, int32_t n, const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
   const int row = blk * kBlock + threadIdx.x;
   double v0 = 0.0, v1 = 0.0;
   if (row < n) {
-    const double pi = p[row];
+    const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
+    const double pi = mac(beta, po[row], z_val(z[row], s, m, sub_mean != 0));
     const double ri = r[row];
-    double acc, d;
-    row_apply<double, D16>(sptr, uw, col, w, p, row, n, pi, acc, d);
+    int beg, width;
+    slice_bounds(sptr, uw, row, beg, width);
+    const int lane = row & 63;
+    double acc = 0.0;
+    switch (width) {
+      case 0: break;
+#define DECMG_PN(K)                                                                          \
+  case K:                                                                                    \
+    row_pnew_n<ZT, D16, K>(col, w, z, po, beg, lane, row, n, s, m, sub_mean != 0, beta, pi,  \
+                           acc);                                                             \
+    break;
+      DECMG_PN(1) DECMG_PN(2) DECMG_PN(3) DECMG_PN(4) DECMG_PN(5) DECMG_PN(6) DECMG_PN(7)
+      DECMG_PN(8)
+#undef DECMG_PN
+      default:
+        for (int k = 0; k < width; ++k) {
+          int j;
+          double wk;
+          entry_at<double, D16>(col, w, (beg + k) * kSlice + lane, row, n, j, wk);
+          const double xj = mac(beta, po[j], z_val(z[j], s, m, sub_mean != 0));
+          acc = mac(wk, pi - xj, acc);
+        }
+    }
+    pn[row] = pi;
     q[row] = acc;
     v0 = pi * acc;
     v1 = pi * ri;
@@ -1598,7 +1656,31 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
   tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
   const double a = sc->alpha, scale = sc->scale;
   double v = 0.0;
-  for (int t = t0; t < t1; ++t) {
+  int t = t0;
+  // four tiles' loads in flight before any of them is used (same order of summation)
+  for (; t + 4 <= t1; t += 4) {
+    double xv[4], pv[4], rv[4], qv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = min((t + u) * kBlock + static_cast<int>(threadIdx.x), n - 1);
+      xv[u] = x[i];
+      pv[u] = p[i];
+      rv[u] = r[i];
+      qv[u] = q[i];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = (t + u) * kBlock + threadIdx.x;
+      if (i < n) {
+        x[i] = xv[u] + a * pv[u];
+        const double ri = rv[u] - a * qv[u];
+        r[i] = ri;
+        v += ri * ri;
+        if (r32) r32[i] = static_cast<float>(ri * scale);
+      }
+    }
+  }
+  for (; t < t1; ++t) {
     const int i = t * kBlock + threadIdx.x;
     if (i < n) {
       x[i] = x[i] + a * p[i];
@@ -1638,15 +1720,6 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restr
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
-}
-
-__global__ __launch_bounds__(kBlock) void k_pupdate(int32_t n, const DevScalars* __restrict__ sc,
-                                                    const double* __restrict__ z,
-                                                    double* __restrict__ p, int sub_mean,
-                                                    const int* __restrict__ done) {
-  if (*done) return;
-  const int i = xcd_block() * kBlock + threadIdx.x;
-  if (i < n) p[i] = (sub_mean ? z[i] - sc->mean : z[i]) + sc->beta * p[i];
 }
 
 // part0 = z.o, part1 = sum z, part2 = sum o per block (z widened by 1/scale when ZT is float):
@@ -1790,46 +1863,6 @@ __global__ __launch_bounds__(kBlock) void k_zdot32(int32_t n, const DevScalars* 
   if (threadIdx.x == 0) part0[blk] = v;
 }
 
-// p = z + beta p with z = z32 / scale - mean
-__global__ __launch_bounds__(kBlock) void k_pupd32(int32_t n, const DevScalars* __restrict__ sc,
-                                                   const float* __restrict__ z32,
-                                                   double* __restrict__ p, int sub_mean,
-                                                   const int* __restrict__ done) {
-  if (*done) return;
-  const int blk = xcd_block();
-  int t0, t1;
-  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
-  const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
-  int t = t0;
-  for (; t + 4 <= t1; t += 4) {
-    float zf[4];
-    double pv[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = min((t + q) * kBlock + static_cast<int>(threadIdx.x), n - 1);
-      zf[q] = z32[i];
-      pv[q] = p[i];
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = (t + q) * kBlock + threadIdx.x;
-      if (i < n) {
-        double zi = static_cast<double>(zf[q]) * s;
-        if (sub_mean) zi = zi - m;
-        p[i] = zi + beta * pv[q];
-      }
-    }
-  }
-  for (; t < t1; ++t) {
-    const int i = t * kBlock + threadIdx.x;
-    if (i < n) {
-      double zi = static_cast<double>(z32[i]) * s;
-      if (sub_mean) zi = zi - m;
-      p[i] = zi + beta * p[i];
-    }
-  }
-}
-
 // z -= mean (when sub_mean), part0 = z . o
 __global__ __launch_bounds__(kBlock) void k_zsub_dot(int32_t n, const DevScalars* __restrict__ sc,
                                                      double* __restrict__ z,
@@ -1911,19 +1944,17 @@ __global__ void k_init_scalars(DevScalars* __restrict__ sc, double rtol, int32_t
 
 constexpr int kFinThreads = 1024;
 
-__global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
-                                                          const double* __restrict__ part0,
-                                                          const double* __restrict__ part1,
-                                                          const double* __restrict__ part2,
-                                                          DevScalars* __restrict__ sc,
-                                                          double extra, int force) {
-  if (!force && sc->done) return;
-  // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int base = 0; nb > 0 && base < nb; base += 8 * kFinThreads) {
-    double va[8], vb[8], vc[8];
+// Per-thread part of the finaliser's fixed-order sum: thread t adds part[t + k * kFinThreads]
+// for k = 0, 1, ... in that order, B loads of each array in flight at a time.
+template <int B>
+__device__ __forceinline__ void fin_accumulate(int32_t nb, const double* __restrict__ part0,
+                                               const double* __restrict__ part1,
+                                               const double* __restrict__ part2, double& a,
+                                               double& b, double& c) {
+  for (int base = 0; nb > 0 && base < nb; base += B * kFinThreads) {
+    double va[B], vb[B], vc[B];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < B; ++j) {
       const int i = base + j * kFinThreads + threadIdx.x;
       const int ic = i < nb ? i : nb - 1;
       va[j] = part0[ic];
@@ -1936,12 +1967,29 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < B; ++j) {
       a += va[j];
       b += vb[j];
       c += vc[j];
     }
   }
+}
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
+                                                          const double* __restrict__ part0,
+                                                          const double* __restrict__ part1,
+                                                          const double* __restrict__ part2,
+                                                          DevScalars* __restrict__ sc,
+                                                          double extra, int force) {
+  if (!force && sc->done) return;
+  // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8, or
+  // of 16 when there are more than 8 per thread (the one-partial-per-256-rows kernels on the
+  // finest level), so that a single round trip fetches them all
+  double a = 0.0, b = 0.0, c = 0.0;
+  if (nb > 8 * kFinThreads)
+    fin_accumulate<16>(nb, part0, part1, part2, a, b, c);
+  else
+    fin_accumulate<8>(nb, part0, part1, part2, a, b, c);
   __shared__ double sa[kFinThreads / 64], sb[kFinThreads / 64], scc[kFinThreads / 64];
   a = wave_sum(a);
   b = wave_sum(b);
@@ -2552,18 +2600,27 @@ void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t
   if (bc == MG_BC_DIRICHLET0) bnd_zero<double>(L.bnd_ids, static_cast<int32_t>(L.bnd_h.size()), b, s);
 }
 
-void spmv_dot2(const Level& L, const double* p, double* q, const double* r, double* part0,
-               double* part1, const int* done, hipStream_t s) {
+void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
+                    int sub_mean_flag, const double* p_old, double* p_new, double* q,
+                    const double* r, double* part0, double* part1, const int* done,
+                    hipStream_t s) {
   with_weights<double>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
-    if (L.op.col16)
-      hipLaunchKernelGGL((k_spmv_dot2<true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, p, q, r, part0, part1,
-                         L.n, done);
+    auto go = [&](auto zp) {
+      using ZT = pointee_t<decltype(zp)>;
+      if (L.op.col16)
+        hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0,
+                           s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, sc, zp,
+                           sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+      else
+        hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, false, WT>), dim3(grid_for(L.n)), dim3(kBlock),
+                           0, s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, sc, zp,
+                           sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+    };
+    if (z32)
+      go(z32);
     else
-      hipLaunchKernelGGL((k_spmv_dot2<false, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0, s,
-                         L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, p, q, r, part0, part1,
-                         L.n, done);
+      go(z64);
   });
 }
 void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
@@ -2584,11 +2641,6 @@ void residual_norm(const Level& L, const double* x, const double* b, double* r, 
                          L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, x, b, r, r32, sc, part0,
                          L.n, done);
   });
-}
-void pupdate(int32_t n, const DevScalars* sc, const double* z, double* p, const int* done,
-             hipStream_t s, int sub_mean_flag) {
-  hipLaunchKernelGGL(k_pupdate, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, z, p, sub_mean_flag,
-                     done);
 }
 void zsum_dot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, double* part0,
                 double* part1, double* part2, const int* done, hipStream_t s) {
@@ -2621,11 +2673,6 @@ void zdot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, 
             int sub_mean_flag, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_zdot32, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z32, o, part0,
                      sub_mean_flag, done);
-}
-void pupd32(int32_t n, const DevScalars* sc, const float* z32, double* p, int sub_mean_flag,
-            const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_pupd32, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, z32, p, sub_mean_flag,
-                     done);
 }
 void axpy1(int32_t n, const double* z, double* x, const int* done, hipStream_t s) {
   hipLaunchKernelGGL(k_axpy1, dim3(grid_for(n)), dim3(kBlock), 0, s, n, z, x, done);

@@ -241,8 +241,9 @@ void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, bool tiles = 
   k::finalize(op, nb, H.part, two ? H.part + H.part_cap : nullptr, H.scal, 0.0, force ? 1 : 0, s);
 }
 
-// One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).
-void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
+// One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).  `parity` selects
+// which direction buffer holds p on entry; the iteration leaves the new p in the other one.
+void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   const int top = int(H.lv.size()) - 1;
@@ -299,13 +300,14 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, hipStream_t s) {
                 k::red_blocks(n), P0, P1, H.scal, 0.0, 0, s, P2);
   else
     fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
-  if (z32)
-    k::pupd32(n, H.scal, z32, H.sp, natural ? 1 : 0, done, s);
-  else
-    k::pupdate(n, H.scal, z, H.sp, done, s, fused_mean ? 1 : 0);
-  k::spmv_dot2(F, H.sp, H.sq, H.sr, P0, P1, done, s);
+  // p = z + beta p formed inside the operator product (z32 carries the mean subtraction on
+  // singular systems; an FP64 z has it subtracted already unless the sums were fused)
+  const double* p_old = parity ? H.sp2 : H.sp;
+  double* p_new = parity ? H.sp : H.sp2;
+  k::pupd_spmv_dot2(F, H.scal, z32, z32 ? nullptr : z, z32 ? (natural ? 1 : 0) : (fused_mean ? 1 : 0),
+                    p_old, p_new, H.sq, H.sr, P0, P1, done, s);
   fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s, true);
-  k::update_xr(n, H.scal, H.sp, H.sq, H.sx, H.sr, r32, P0, done, s);
+  k::update_xr(n, H.scal, p_new, H.sq, H.sx, H.sr, r32, P0, done, s);
   fin(H, k::FIN_CHECK, n, false, s);
 }
 
@@ -327,6 +329,7 @@ std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
                          o.cycle + 4 * o.smoother + 16 * (o.fuse_levels ? 1 : 0), o.omega);
 }
 
+// kind 0 and 2: a Krylov iteration with p in the first or the second buffer; 1: a cycle
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
   auto key = graph_key(o, kind);
   auto it = H.graphs.find(key);
@@ -335,8 +338,8 @@ hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
   check_hip(hipStreamBeginCapture(H.capture_stream, hipStreamCaptureModeThreadLocal),
             "hipStreamBeginCapture");
   H.capturing = true;
-  if (kind == 0)
-    enqueue_iteration(H, o, H.capture_stream);
+  if (kind != 1)
+    enqueue_iteration(H, o, kind == 2 ? 1 : 0, H.capture_stream);
   else
     enqueue_cycle(H, o, H.capture_stream);
   H.capturing = false;
@@ -469,6 +472,7 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   setup_rhs(H, b_nat, s);
   k::fill<double>(H.sp, n, 0.0, s);
   k::fill<double>(H.sq, n, 0.0, s);
+  H.p_parity = 0;
   if (warm_start && !b_nat) {
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
   } else {
@@ -478,13 +482,15 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   }
   if (o.precision == MG_F32) k::to_f32(n, H.scal, H.sr, F.v32.b, nullptr, s);
   T.mark("setup");
-  hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 0) : nullptr;
+  hipGraphExec_t g[2] = {o.use_graph ? iteration_graph(H, o, 0) : nullptr,
+                        o.use_graph ? iteration_graph(H, o, 2) : nullptr};
   T.mark("graph");
   iterate(H, o, 0, s, [&]() {
-    if (g)
-      check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
+    if (g[H.p_parity])
+      check_hip(hipGraphLaunch(g[H.p_parity], s), "hipGraphLaunch");
     else
-      enqueue_iteration(H, o, s);
+      enqueue_iteration(H, o, H.p_parity, s);
+    H.p_parity ^= 1;
   }, &T);
   finish(H, b_nat, x_nat, res, s);
   T.mark("finish");

@@ -364,9 +364,10 @@ void mg_grad_w(const Level& L, const PorousData& D, const double* lam, const dou
 // Krylov building blocks (FP64 outer loop); partial sums land in H.part[0..2][block].
 int blocks_for(int32_t n);
 int red_blocks(int32_t n);   // grid (= number of partials) of the streaming reductions
-// pupd_spmv_dot2 and residual_norm run one 256-row tile per workgroup: blocks_for(n) partials
+// residual_norm runs one 256-row tile per workgroup: blocks_for(n) partials
 // p_new = z + beta p_old (z from z32 / scale or from z64, minus the mean when asked), q = A p_new,
-// with the block partials of p_new.q (part0) and p_new.r (part1); one partial per kBlock rows
+// with the block partials of p_new.q (part0) and p_new.r (part1): pupd_spmv_partials(L) of each
+int pupd_spmv_partials(const Level& L);
 void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
                     const double* r, double* part0, double* part1, const int* done,

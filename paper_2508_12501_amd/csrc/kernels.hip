@@ -1642,6 +1642,48 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
   }
 }
 
+// k_pupd_spmv_dot2 with two rows per thread (uniform widths 1..8 only): one partial per
+// 2 kBlock rows
+template <typename ZT, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2(
+    int32_t uw, const void* __restrict__ col, const WT* __restrict__ w,
+    const DevScalars* __restrict__ sc, const ZT* __restrict__ z, int sub_mean,
+    const double* __restrict__ po, double* __restrict__ pn, double* __restrict__ q,
+    const double* __restrict__ r, double* __restrict__ part0, double* __restrict__ part1,
+    int32_t n, const int* __restrict__ done) {
+  if (*done) return;
+  const int blk = xcd_block();
+  const int r0 = blk * (2 * kBlock) + threadIdx.x;
+  double v0 = 0.0, v1 = 0.0;
+  if (r0 < n) {
+    const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+    const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
+    const bool sm = sub_mean != 0;
+    const double p0 = mac(beta, po[r0], z_val(z[r0], s, m, sm));
+    const double p1 = mac(beta, po[r1], z_val(z[r1], s, m, sm));
+    const double q0r = r[r0], q1r = r[r1];
+    double a0, d0, a1, d1;
+    row2<double, D16>(col, w, r0, r1, uw, n, p0, p1,
+                      [&](int j) { return mac(beta, po[j], z_val(z[j], s, m, sm)); }, a0, d0,
+                      a1, d1);
+    pn[r0] = p0;
+    q[r0] = a0;
+    v0 = p0 * a0;
+    v1 = p0 * q0r;
+    if (r1 != r0) {
+      pn[r1] = p1;
+      q[r1] = a1;
+      v0 += p1 * a1;
+      v1 += p1 * q1r;
+    }
+  }
+  block_sum2(v0, v1);
+  if (threadIdx.x == 0) {
+    part0[blk] = v0;
+    part1[blk] = v1;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalars* __restrict__ sc,
                                                       const double* __restrict__ p,
                                                       const double* __restrict__ q,
@@ -2600,6 +2642,9 @@ void star0_apply(const Level& L, int bc, const double* f, double* b, hipStream_t
   if (bc == MG_BC_DIRICHLET0) bnd_zero<double>(L.bnd_ids, static_cast<int32_t>(L.bnd_h.size()), b, s);
 }
 
+int pupd_spmv_partials(const Level& L) {
+  return two_rows(L) ? static_cast<int>(grid2_for(L.n)) : blocks_for(L.n);
+}
 void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
                     const double* r, double* part0, double* part1, const int* done,
@@ -2608,6 +2653,17 @@ void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, cons
     using WT = pointee_t<decltype(w)>;
     auto go = [&](auto zp) {
       using ZT = pointee_t<decltype(zp)>;
+      if (two_rows(L)) {
+        if (L.op.col16)
+          hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, true, WT>), dim3(grid2_for(L.n)),
+                             dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col16), w,
+                             sc, zp, sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+        else
+          hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, false, WT>), dim3(grid2_for(L.n)),
+                             dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col), w,
+                             sc, zp, sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+        return;
+      }
       if (L.op.col16)
         hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0,
                            s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, sc, zp,

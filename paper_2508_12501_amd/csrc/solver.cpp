@@ -306,7 +306,8 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   double* p_new = parity ? H.sp : H.sp2;
   k::pupd_spmv_dot2(F, H.scal, z32, z32 ? nullptr : z, z32 ? (natural ? 1 : 0) : (fused_mean ? 1 : 0),
                     p_old, p_new, H.sq, H.sr, P0, P1, done, s);
-  fin(H, o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG, n, true, s, true);
+  k::finalize(o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG,
+              k::pupd_spmv_partials(F), P0, P1, H.scal, 0.0, 0, s);
   k::update_xr(n, H.scal, p_new, H.sq, H.sx, H.sr, r32, P0, done, s);
   fin(H, k::FIN_CHECK, n, false, s);
 }

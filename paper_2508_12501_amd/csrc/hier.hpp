@@ -62,6 +62,9 @@ struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t r_uw = -1;          // uniform slice width of the restriction lists, or -1
   int32_t* r_sptr = nullptr;  // SELL over coarse rows of the fine midpoints (weight 1/2)
   int32_t* r_col = nullptr;
+  // the same lists as 16-bit offsets from the kept vertex (kZeroSlot16 = zero slot), when the
+  // width is uniform and at most 8 and every offset fits; else null
+  int16_t* r_col16 = nullptr;
   // Weighted transfers (cubic subdivision, any M(f)): interpolation x_f += sum_k w_k e_{p_k}
   // over three parents per fine unknown; restriction r_c = sum over the coarse row's entries
   // (fine unknown, weight) in SELL-64 (the kept vertex is an entry of weight 1).  The binary

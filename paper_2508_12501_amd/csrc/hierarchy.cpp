@@ -495,6 +495,25 @@ void build_transfer(Level& F, const Level& C) {
   F.tr.ncols = sptr[nslices];
   F.tr.r_sptr = upload(sptr);
   F.tr.r_col = upload(col);
+  // 16-bit offsets from the kept vertex for the per-step restriction (uniform widths 1..8)
+  if (F.tr.r_uw >= 1 && F.tr.r_uw <= 8) {
+    const int32_t uw = F.tr.r_uw;
+    std::vector<int16_t> c16(size_t(nslices) * uw * kSlice, int16_t(kZeroSlot16));
+    bool fits = true;
+    for (int32_t r = 0; r < C.n && fits; ++r)
+      for (int32_t k = 0; k < uw; ++k) {
+        const size_t at = size_t(r >> 6) * uw * kSlice + size_t(k) * kSlice + (r & 63);
+        const int32_t c = col[at];
+        if (c == F.n) continue;
+        const int64_t off = int64_t(c) - self[r];
+        if (off <= kZeroSlot16 || off > 32767) {
+          fits = false;
+          break;
+        }
+        c16[at] = int16_t(off);
+      }
+    if (fits) F.tr.r_col16 = upload(c16);
+  }
 }
 
 template <typename T>
@@ -1045,7 +1064,7 @@ Hierarchy::~Hierarchy() {
                     (void*)L.op.w16,
                     (void*)L.op.idiag64,
                     (void*)L.op.idiag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
-                    (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.v64.x, (void*)L.v64.b,
+                    (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.tr.r_col16, (void*)L.v64.x, (void*)L.v64.b,
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
                     (void*)L.v32.r, (void*)L.v32.t, (void*)L.v64.u, (void*)L.v32.u,
                     (void*)L.cgs})

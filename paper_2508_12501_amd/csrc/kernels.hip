@@ -453,6 +453,65 @@ __global__ __launch_bounds__(kBlock) void k_restrict(const int32_t* __restrict__
   rc[row] = rs + T(0.5) * acc;
 }
 
+// k_restrict with two coarse rows per thread, rows r and r + kBlock, over 16-bit column offsets
+// from the kept vertex (uniform widths 1..8): all index, kept-value and gather loads of both
+// rows go out before either sum.  Same order of summation as k_restrict.
+template <typename T, int N>
+__device__ __forceinline__ void restrict2_n(const int16_t* __restrict__ col,
+                                            const T* __restrict__ rf, int e0, int e1, int s0,
+                                            int s1, int nf, T& a0, T& a1) {
+  int c0[N], c1[N];
+  T v0[N], v1[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int o0 = col[e0 + k * kSlice], o1 = col[e1 + k * kSlice];
+    c0[k] = o0 == kZeroSlot16 ? nf : s0 + o0;
+    c1[k] = o1 == kZeroSlot16 ? nf : s1 + o1;
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    v0[k] = rf[c0[k]];
+    v1[k] = rf[c1[k]];
+  }
+  a0 = T(0);
+  a1 = T(0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    a0 += v0[k];
+    a1 += v1[k];
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict2(const int32_t* __restrict__ self,
+                                                      int32_t uw,
+                                                      const int16_t* __restrict__ col,
+                                                      const T* __restrict__ rf,
+                                                      T* __restrict__ rc, int32_t nc, int32_t nf,
+                                                      const int* __restrict__ done) {
+  DECMG_DONE_LOAD(nc)
+  const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
+  if (r0 >= nc) return;
+  const int r1 = (r0 + kBlock < nc) ? r0 + kBlock : r0;
+  const int s0 = self[r0], s1 = self[r1];
+  const int e0 = ell_first(r0, uw), e1 = ell_first(r1, uw);
+  const T rs0 = rf[s0], rs1 = rf[s1];
+  T a0, a1;
+  switch (uw) {
+    case 1: restrict2_n<T, 1>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    case 2: restrict2_n<T, 2>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    case 3: restrict2_n<T, 3>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    case 4: restrict2_n<T, 4>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    case 5: restrict2_n<T, 5>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    case 6: restrict2_n<T, 6>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    case 7: restrict2_n<T, 7>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+    default: restrict2_n<T, 8>(col, rf, e0, e1, s0, s1, nf, a0, a1); break;
+  }
+  DECMG_DONE_CHECK()
+  rc[r0] = rs0 + T(0.5) * a0;
+  if (r1 != r0) rc[r1] = rs1 + T(0.5) * a1;
+}
+
 // First post-smoothing sweep fused with the interpolation of the coarse correction.  The
 // corrected iterate x0 = x + M(f)^T e_c is formed on the fly, for the row and for each of its
 // neighbours, with the rounding of k_prolong; then xo = x0 + omega (b - A x0) / diag.  The
@@ -911,7 +970,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_color(const int32_t* __restrict__
 // x_f += M(f)^T e_c: (e_a + e_b) / 2, with a == b at kept vertices.  Each thread takes
 // kProlongRows rows kBlock apart: the parent gathers depend on the parent loads, and with one
 // row per thread too few bytes were in flight to cover those two round trips (3.5 TB/s on the
-// C3 finest level).
+// C3 finest level).  Eight rows per thread were no faster there and slower on the 1M-row
+// level (fewer workgroups).
 constexpr int kProlongRows = 4;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ pa,
@@ -2303,6 +2363,11 @@ void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* 
     else
       hipLaunchKernelGGL((k_restrict_w<T, float>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s,
                          Lf.tr.rw_sptr, Lf.tr.rw_col, Lf.tr.rw32, rf, rc, Lc.n, done);
+    return;
+  }
+  if (Lf.tr.r_col16) {
+    hipLaunchKernelGGL((k_restrict2<T>), dim3(grid2_for(Lc.n)), dim3(kBlock), 0, s, Lf.tr.r_self,
+                       Lf.tr.r_uw, Lf.tr.r_col16, rf, rc, Lc.n, Lf.n, done);
     return;
   }
   hipLaunchKernelGGL((k_restrict<T>), dim3(grid_for(Lc.n)), dim3(kBlock), 0, s, Lf.tr.r_self,

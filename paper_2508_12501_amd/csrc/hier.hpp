@@ -23,7 +23,7 @@ namespace decmg {
 constexpr int kSlice = 64;    // SELL slice height: one wavefront, one row per lane
 constexpr int kBlock = 256;   // threads per row-parallel workgroup (4 wavefronts)
 constexpr int kMaxCoarse = 2048;  // largest coarsest level solved densely
-constexpr int kRedBlocks = 2048;  // cap on workgroups (and partial sums) of a reduction
+constexpr int kRedBlocks = 4096;  // cap on workgroups (and partial sums) of a reduction
 
 // Operator in sliced ELLPACK (SELL-64): slice s covers internal rows 64s..64s+63 and owns
 // columns sptr[s]..sptr[s+1]-1; entry k of lane l sits at [k*64 + l].  The same column

@@ -57,6 +57,11 @@ struct DevOperator {
 struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t* pa = nullptr;      // n_f: internal coarse ids (or n_c) of the two parents
   int32_t* pb = nullptr;
+  // the same parents packed for the per-step interpolation: per 64-row slice of fine rows a
+  // base coarse id, per row the two parents as int16 offsets from it (low half a, high half
+  // b; kZeroSlot16 = zero slot), when every offset fits; else null
+  int32_t* p_base = nullptr;
+  uint32_t* p_ab16 = nullptr;
   int32_t* r_self = nullptr;  // n_c: fine internal id of the kept vertex
   int32_t nslices = 0, ncols = 0;
   int32_t r_uw = -1;          // uniform slice width of the restriction lists, or -1

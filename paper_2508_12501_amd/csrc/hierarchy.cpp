@@ -490,6 +490,41 @@ void build_transfer(Level& F, const Level& C) {
   col.resize(col.size() + kSlice, F.n);   // padding column
   F.tr.pa = upload(pa);
   F.tr.pb = upload(pb);
+  {
+    // packed parents: int16 offsets from the smallest parent id in each 64-row slice
+    const int32_t ns = (F.n + kSlice - 1) / kSlice;
+    std::vector<int32_t> base(size_t(std::max(ns, 1)), 0);
+    std::vector<uint32_t> ab(size_t(F.n) + 1, 0u);
+    bool fits = true;
+    for (int32_t s = 0; s < ns && fits; ++s) {
+      const int32_t r0 = s * kSlice, r1 = std::min(F.n, r0 + kSlice);
+      int32_t lo = C.n;
+      for (int32_t r = r0; r < r1; ++r) {
+        if (pa[r] != C.n) lo = std::min(lo, pa[r]);
+        if (pb[r] != C.n) lo = std::min(lo, pb[r]);
+      }
+      base[s] = lo;
+      auto enc = [&](int32_t p, uint32_t& out) {
+        if (p == C.n) {
+          out = uint16_t(int16_t(kZeroSlot16));
+          return true;
+        }
+        const int32_t off = p - lo;
+        if (off < 0 || off > 32767) return false;
+        out = uint16_t(off);
+        return true;
+      };
+      for (int32_t r = r0; r < r1 && fits; ++r) {
+        uint32_t ea = 0, eb = 0;
+        fits = enc(pa[r], ea) && enc(pb[r], eb);
+        ab[r] = ea | (eb << 16);
+      }
+    }
+    if (fits && F.n > 0) {
+      F.tr.p_base = upload(base);
+      F.tr.p_ab16 = upload(ab);
+    }
+  }
   F.tr.r_self = upload(self);
   F.tr.nslices = nslices;
   F.tr.ncols = sptr[nslices];
@@ -1064,7 +1099,8 @@ Hierarchy::~Hierarchy() {
                     (void*)L.op.w16,
                     (void*)L.op.idiag64,
                     (void*)L.op.idiag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
-                    (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.tr.r_col16, (void*)L.v64.x, (void*)L.v64.b,
+                    (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.tr.r_col16, (void*)L.tr.p_base,
+                    (void*)L.tr.p_ab16, (void*)L.v64.x, (void*)L.v64.b,
                     (void*)L.v64.r, (void*)L.v64.t, (void*)L.v32.x, (void*)L.v32.b,
                     (void*)L.v32.r, (void*)L.v32.t, (void*)L.v64.u, (void*)L.v32.u,
                     (void*)L.cgs})

@@ -1001,6 +1001,45 @@ __global__ __launch_bounds__(kBlock) void k_prolong(const int32_t* __restrict__ 
     if (base + r * kBlock < nf) xf[base + r * kBlock] = x[r];
 }
 
+// k_prolong over packed parents: one 32-bit word per row (two int16 offsets from the slice's
+// base coarse id) in place of two int32 ids.  Same arithmetic as k_prolong.
+__device__ __forceinline__ int parent16(uint32_t half, int base, int nc) {
+  const int o = static_cast<int16_t>(static_cast<uint16_t>(half));
+  return o == kZeroSlot16 ? nc : base + o;
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong16(const int32_t* __restrict__ pbase,
+                                                      const uint32_t* __restrict__ pab,
+                                                      const T* __restrict__ ec,
+                                                      T* __restrict__ xf, int32_t nf, int32_t nc,
+                                                      const int* __restrict__ done) {
+  DECMG_DONE_LOAD(nf)
+  const int base = xcd_block() * (kBlock * kProlongRows) + threadIdx.x;
+  uint32_t ab[kProlongRows];
+  int bs[kProlongRows];
+  T x[kProlongRows];
+#pragma unroll
+  for (int r = 0; r < kProlongRows; ++r) {
+    const int row = base + r * kBlock;
+    if (row < nf) {
+      ab[r] = pab[row];
+      bs[r] = pbase[row >> 6];
+      x[r] = xf[row];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kProlongRows; ++r)
+    if (base + r * kBlock < nf) {
+      const int a = parent16(ab[r] & 0xffffu, bs[r], nc);
+      const int b = parent16(ab[r] >> 16, bs[r], nc);
+      x[r] = x[r] + T(0.5) * (ec[a] + ec[b]);
+    }
+  DECMG_DONE_CHECK()
+#pragma unroll
+  for (int r = 0; r < kProlongRows; ++r)
+    if (base + r * kBlock < nf) xf[base + r * kBlock] = x[r];
+}
+
 // Weighted interpolation xf += M(f)^T ec for any subdivision scheme: three (parent, weight)
 // pairs per fine row, stored row-major (12 bytes of ids, 3 weights per row).  Cubic levels
 // (Def. 5) put 2/3, 1/3 on the two endpoints of an edge point and 1/3 on each corner of a
@@ -2374,7 +2413,7 @@ void restrict_(const Level& Lf, const Level& Lc, const T* rf, T* rc, const int* 
                      Lf.tr.r_sptr, Lf.tr.r_uw, Lf.tr.r_col, rf, rc, Lc.n, done);
 }
 template <typename T>
-void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int* done,
+void prolong(const Level& Lf, const Level& Lc, const T* ec, T* xf, const int* done,
              hipStream_t s) {
   if (Lf.n == 0) return;
   if (Lf.tr.weighted) {
@@ -2387,6 +2426,11 @@ void prolong(const Level& Lf, const Level& /*Lc*/, const T* ec, T* xf, const int
     return;
   }
   const int64_t groups = (int64_t(Lf.n) + kBlock * kProlongRows - 1) / (kBlock * kProlongRows);
+  if (Lf.tr.p_ab16) {
+    hipLaunchKernelGGL((k_prolong16<T>), dim3(groups), dim3(kBlock), 0, s, Lf.tr.p_base,
+                       Lf.tr.p_ab16, ec, xf, Lf.n, Lc.n, done);
+    return;
+  }
   hipLaunchKernelGGL((k_prolong<T>), dim3(groups), dim3(kBlock), 0, s, Lf.tr.pa, Lf.tr.pb, ec,
                      xf, Lf.n, done);
 }

@@ -131,6 +131,13 @@ typedef struct {
   int32_t weight_bytes64;   /* the same for the FP64 row kernels (2, 4 or 8) */
   int32_t uniform_width;    /* entries of every operator slice when they are all equal, else -1 */
   int32_t rows_per_thread;  /* rows each thread of the sweep, residual and apply kernels takes */
+  int32_t interp_packed16;  /* 1: the per-step interpolation onto this level reads its two
+                               parents as int16 offsets from a per-64-row base (one 32-bit word
+                               per row); 0: two int32 ids, or a weighted scheme, or level 0.
+                               Packing is skipped when a DECMG_NO_PACKED_TRANSFERS environment
+                               variable is set at build time. */
+  int32_t restrict_offsets16;  /* 1: the per-step restriction onto level-1 reads int16 offsets
+                                  from the kept vertex; 0: int32 ids (same condition) */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 

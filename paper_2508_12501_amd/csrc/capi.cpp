@@ -327,6 +327,8 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->weight_bytes64 = L.op.w_exact16 ? 2 : (L.op.w_exact32 ? 4 : 8);
   out->uniform_width = L.op.uw;
   out->rows_per_thread = (L.op.uw >= 1 && L.op.uw <= 8) ? 2 : 1;
+  out->interp_packed16 = L.tr.p_ab16 ? 1 : 0;
+  out->restrict_offsets16 = L.tr.r_col16 ? 1 : 0;
   return MG_OK;
 }
 

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <stdexcept>
@@ -490,7 +491,10 @@ void build_transfer(Level& F, const Level& C) {
   col.resize(col.size() + kSlice, F.n);   // padding column
   F.tr.pa = upload(pa);
   F.tr.pb = upload(pb);
-  {
+  // The packed forms below can be switched off (DECMG_NO_PACKED_TRANSFERS set) so that the
+  // int32 kernels, used where offsets do not fit, can be checked against them.
+  const bool no_pack = std::getenv("DECMG_NO_PACKED_TRANSFERS") != nullptr;
+  if (!no_pack) {
     // packed parents: int16 offsets from the smallest parent id in each 64-row slice
     const int32_t ns = (F.n + kSlice - 1) / kSlice;
     std::vector<int32_t> base(size_t(std::max(ns, 1)), 0);
@@ -531,7 +535,7 @@ void build_transfer(Level& F, const Level& C) {
   F.tr.r_sptr = upload(sptr);
   F.tr.r_col = upload(col);
   // 16-bit offsets from the kept vertex for the per-step restriction (uniform widths 1..8)
-  if (F.tr.r_uw >= 1 && F.tr.r_uw <= 8) {
+  if (!no_pack && F.tr.r_uw >= 1 && F.tr.r_uw <= 8) {
     const int32_t uw = F.tr.r_uw;
     std::vector<int16_t> c16(size_t(nslices) * uw * kSlice, int16_t(kZeroSlot16));
     bool fits = true;

@@ -2122,7 +2122,12 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
                                                           const double* __restrict__ part2,
                                                           DevScalars* __restrict__ sc,
                                                           double extra, int force) {
-  if (!force && sc->done) return;
+  // The flag and the scalars the step reads are loaded with the partial sums, not in round
+  // trips of their own before and after them; the flag is tested before the first store.
+  const int done0 = sc->done;
+  const double rho = sc->rho, pq = sc->pq, rtol = sc->rtol, bnorm = sc->bnorm;
+  const double nun = sc->n_unknowns;
+  const int iters = sc->iters, max_iter = sc->max_iter;
   // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8, or
   // of 16 when there are more than 8 per thread (the one-partial-per-256-rows kernels on the
   // finest level), so that a single round trip fetches them all
@@ -2141,7 +2146,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
     scc[threadIdx.x >> 6] = c;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0 || (!force && done0)) return;
   a = 0.0;
   b = 0.0;
   c = 0.0;
@@ -2152,7 +2157,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
   }
   if (op == k::FIN_MEAN_BETA_CG || op == k::FIN_MEAN_BETA_FCG) {
     // the projected vector's dot from the unprojected sums, then the plain beta update
-    const double mean = b / sc->n_unknowns;
+    const double mean = b / nun;
     sc->mean = mean;
     a = a - mean * c;
     op = (op == k::FIN_MEAN_BETA_CG) ? k::FIN_BETA_CG : k::FIN_BETA_FCG;
@@ -2171,7 +2176,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       } else {
         // power-of-two scale that brings the residual to O(1) for the FP32 copy
         int e;
-        frexp(bn / sqrt(sc->n_unknowns), &e);
+        frexp(bn / sqrt(nun), &e);
         sc->scale = ldexp(1.0, -e);
         sc->inv_scale = ldexp(1.0, e);
       }
@@ -2183,7 +2188,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
         sc->status = isfinite(a) ? MG_EBREAKDOWN : MG_ENONFINITE;
         sc->done = 1;
       } else {
-        sc->alpha = sc->rho / a;
+        sc->alpha = rho / a;
       }
       break;
     case k::FIN_ALPHA_FCG:
@@ -2198,14 +2203,14 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
     case k::FIN_CHECK: {
       const double rn = sqrt(a);
       sc->rnorm = rn;
-      sc->iters += 1;
+      sc->iters = iters + 1;
       if (!isfinite(rn)) {
         sc->status = MG_ENONFINITE;
         sc->done = 1;
-      } else if (rn <= sc->rtol * sc->bnorm) {
+      } else if (rn <= rtol * bnorm) {
         sc->status = MG_OK;
         sc->done = 1;
-      } else if (sc->iters >= sc->max_iter) {
+      } else if (iters + 1 >= max_iter) {
         sc->status = MG_ENOCONV;
         sc->done = 1;
       }
@@ -2216,19 +2221,19 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
         sc->status = isfinite(a) ? MG_EBREAKDOWN : MG_ENONFINITE;
         sc->done = 1;
       } else {
-        sc->beta = a / sc->rho;
+        sc->beta = a / rho;
         sc->rho = a;
       }
       break;
     case k::FIN_BETA_FCG:
-      sc->beta = -a / sc->pq;
-      if (!isfinite(sc->beta)) {
+      sc->beta = -a / pq;
+      if (!isfinite(-a / pq)) {
         sc->status = MG_ENONFINITE;
         sc->done = 1;
       }
       break;
     case k::FIN_MEAN:
-      sc->mean = a / sc->n_unknowns;
+      sc->mean = a / nun;
       break;
     case k::FIN_RNORM:
       sc->true_rnorm = sqrt(a);

@@ -7,7 +7,7 @@ complete solve from x = 0 to a relative residual of 1e-10: flexible CG in FP64 w
 FP32 V(2,2) weighted-Jacobi (omega 0.8) cycle as preconditioner.  The plain FP64 MG-PCG
 solve of the same system is timed beside it.
 
-Prints one JSON line.  --gpus N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N > 1 exits: the solver runs on a single GPU (no sharded path).
 """
 from __future__ import annotations
 
@@ -363,7 +363,7 @@ def main():
         profile_kernels()
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the solver runs on a single GPU (no sharded path); --gpus must be 1",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import numpy as np

@@ -19,7 +19,7 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert p.returncode == 2
     rec = json.loads(p.stdout.strip().splitlines()[-1])
-    assert "one GPU" in rec["error"] and rec["n_gpus"] == 2
+    assert "single GPU" in rec["error"] and rec["n_gpus"] == 2
 
 
 def test_headline_sweep_bytes():

@@ -396,6 +396,9 @@ void zdot32(int32_t n, const DevScalars* sc, const float* z32, const double* o, 
 void dot(int32_t n, const double* a, const double* b, double* part0, const int* done, hipStream_t s);
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s);
 void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const int* done, hipStream_t s);
+// r = b, x = p = q = 0 and (r32 non-null) r32 = float(b * scale), one pass over n entries
+void init_krylov(int32_t n, const DevScalars* sc, const double* b, double* r, double* x,
+                 double* p, double* q, float* r32, hipStream_t s);
 
 enum FinOp : int {
   FIN_BNORM = 0,      // bnorm = sqrt(sum0 + boundary part); choose the FP32 scale

@@ -2061,6 +2061,25 @@ __global__ void k_sub_mean(int32_t n, const DevScalars* __restrict__ sc, double*
   if (i < n) v[i] = v[i] - sc->mean;
 }
 
+// Start of a solve from x = 0 in one pass: r = b, x = p = q = 0, and the scaled FP32 copy of
+// r when the cycle runs in FP32 (r32 non-null).
+__global__ __launch_bounds__(kBlock) void k_init_krylov(int32_t n, const DevScalars* __restrict__ sc,
+                                                        const double* __restrict__ b,
+                                                        double* __restrict__ r,
+                                                        double* __restrict__ x,
+                                                        double* __restrict__ p,
+                                                        double* __restrict__ q,
+                                                        float* __restrict__ r32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = b[i];
+  r[i] = v;
+  x[i] = 0.0;
+  p[i] = 0.0;
+  q[i] = 0.0;
+  if (r32) r32[i] = static_cast<float>(v * sc->scale);
+}
+
 __global__ void k_to_f32(int32_t n, const DevScalars* __restrict__ sc, const double* __restrict__ r,
                          float* __restrict__ r32, const int* __restrict__ done) {
   if (done && *done) return;
@@ -2853,6 +2872,12 @@ void dot(int32_t n, const double* a, const double* b, double* part0, const int* 
 }
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, v);
+}
+void init_krylov(int32_t n, const DevScalars* sc, const double* b, double* r, double* x,
+                 double* p, double* q, float* r32, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_init_krylov, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, b, r, x, p, q,
+                     r32);
 }
 void to_f32(int32_t n, const DevScalars* sc, const double* r, float* r32, const int* done,
             hipStream_t s) {

@@ -385,8 +385,11 @@ void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s) {
   }
 }
 
-// Final projection, true residual, scatter to the caller's numbering; one host read.
-void finish(Hierarchy& H, const double* b_nat, double* x_nat, mg_result* res, hipStream_t s) {
+// Final projection, true residual, scatter to the caller's numbering (kernels only).  Without
+// the projection (Dirichlet systems) it only reads x, so it can be enqueued after every batch
+// of iterations and simply runs again after more of them; on singular systems it projects x
+// in place, which would change the rounding of later iterations, so it runs once at the end.
+void enqueue_finish(Hierarchy& H, const double* b_nat, double* x_nat, hipStream_t s) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   if (H.bc == MG_BC_NATURAL) {
@@ -400,7 +403,10 @@ void finish(Hierarchy& H, const double* b_nat, double* x_nat, mg_result* res, hi
     k::scatter<double>(F.perm, n, H.sx, x_nat, s);
     k::bnd_copy<double>(F.bnd_ids, int32_t(F.bnd_h.size()), b_nat, x_nat, s);
   }
-  read_scalars(H, s);
+}
+
+// The caller's result from the host copy of the scalars (read after the last finish).
+void collect(Hierarchy& H, mg_result* res) {
   const DevScalars& h = *H.scal_host;
   if (res) {
     res->iterations = h.iters;
@@ -436,8 +442,11 @@ struct HostTimer {
 // is the iteration count of the previous solve with the same settings (or check_every); later
 // batches are sized from the observed mean residual reduction per iteration, so a solve
 // normally needs one or two host round trips and runs few or no no-op iterations.
-template <typename F>
-void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
+// `tail` is enqueued after every batch, before the host reads the flag: the exit work (the
+// finish of a solve) then follows the last iteration on the device without a host round trip;
+// after a batch that did not converge it is simply done again later.
+template <typename F, typename G>
+void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue, G tail,
              HostTimer* T = nullptr) {
   const int every = std::max(1, o.check_every);
   auto key = graph_key(o, kind);
@@ -448,6 +457,7 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
     batch = std::min(batch, o.max_iter - launched);
     for (int j = 0; j < batch; ++j) enqueue();
     launched += batch;
+    tail();
     if (T) T->mark("enqueue");
     read_scalars(H, s);
     if (T) T->mark("wait");
@@ -461,6 +471,10 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
         batch = std::max(1, std::min(4 * every, int(std::ceil(std::log(goal) / std::log(rate)))));
     }
   }
+  if (launched == 0) {
+    tail();
+    read_scalars(H, s);
+  }
   H.last_iters[key] = H.scal_host->iters;
 }
 
@@ -471,17 +485,16 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   const int32_t n = F.n;
   init_scalars(H, o, s);
   setup_rhs(H, b_nat, s);
-  k::fill<double>(H.sp, n, 0.0, s);
-  k::fill<double>(H.sq, n, 0.0, s);
   H.p_parity = 0;
+  float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
   if (warm_start && !b_nat) {
+    k::fill<double>(H.sp, n, 0.0, s);
+    k::fill<double>(H.sq, n, 0.0, s);
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
+    if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
   } else {
-    k::fill<double>(H.sx, n, 0.0, s);
-    check_hip(hipMemcpyAsync(H.sr, H.sb, size_t(n) * sizeof(double), hipMemcpyDeviceToDevice, s),
-              "hipMemcpyAsync");
+    k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }
-  if (o.precision == MG_F32) k::to_f32(n, H.scal, H.sr, F.v32.b, nullptr, s);
   T.mark("setup");
   hipGraphExec_t g[2] = {o.use_graph ? iteration_graph(H, o, 0) : nullptr,
                         o.use_graph ? iteration_graph(H, o, 2) : nullptr};
@@ -492,8 +505,14 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     else
       enqueue_iteration(H, o, H.p_parity, s);
     H.p_parity ^= 1;
+  }, [&]() {
+    if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
   }, &T);
-  finish(H, b_nat, x_nat, res, s);
+  if (H.bc == MG_BC_NATURAL) {
+    enqueue_finish(H, b_nat, x_nat, s);
+    read_scalars(H, s);
+  }
+  collect(H, res);
   T.mark("finish");
   return H.scal_host->status;
 }
@@ -510,8 +529,14 @@ int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, m
       check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
     else
       enqueue_cycle(H, o, s);
+  }, [&]() {
+    if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
   });
-  finish(H, b_nat, x_nat, res, s);
+  if (H.bc == MG_BC_NATURAL) {
+    enqueue_finish(H, b_nat, x_nat, s);
+    read_scalars(H, s);
+  }
+  collect(H, res);
   return H.scal_host->status;
 }
 

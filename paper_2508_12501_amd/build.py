@@ -9,6 +9,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -43,10 +44,18 @@ def _run(cmd, verbose):
         raise RuntimeError(f"build step failed: {' '.join(cmd[:3])} ... ({r.returncode})")
 
 
+def _jobs() -> int:
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16, int(os.environ.get("MAX_JOBS", n))))
+
+
 def build(verbose: bool = False) -> str:
     cc = hipcc()
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(BUILD, src + ".o")
@@ -58,8 +67,13 @@ def build(verbose: bool = False) -> str:
         if src in STRICT_HOST:
             cmd += ["-ffp-contract=off"]
         cmd += ["-c", path, "-o", obj]
-        _run(cmd, verbose)
+        cmds.append(cmd)
         objs.append(obj)
+    # the device sources take longest: start them first
+    order = sorted(range(len(cmds)), key=lambda i: not SOURCES[i].endswith(".hip"))
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        for f in [ex.submit(_run, cmds[i], verbose) for i in order]:
+            f.result()
     tmp = OUT + ".tmp"
     _run([cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, OUT)

@@ -332,12 +332,25 @@ void batch_setup(Batch& B) {
                           std::max<size_t>(B.groups.size(), 1) * 2 * kBatchMaxCols * sizeof(void*), 0),
             "hipHostMalloc");
   if (B.opts.use_graph)
-    for (BatchGroup& G : B.groups) G.graph = capture(B.opts, G, B.capture_stream);
+    for (BatchGroup& G : B.groups) {
+      G.graph = capture(B.opts, G, B.capture_stream);
+      G.graph_epoch = G.H->weight_epoch;
+    }
 }
 
 int batch_solve(Batch& B, const double* const* b, double* const* x, mg_result* res, hipStream_t s) {
   const mg_opts& o = B.opts;
   const size_t ng = B.groups.size();
+  // a hierarchy whose coefficient changed the form of its weights since a group's graph was
+  // captured: capture that group's iteration again
+  for (BatchGroup& G : B.groups)
+    if (G.graph && G.graph_epoch != G.H->weight_epoch) {
+      check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+      (void)hipGraphExecDestroy(G.graph);
+      G.graph = nullptr;
+      G.graph = capture(o, G, B.capture_stream);
+      G.graph_epoch = G.H->weight_epoch;
+    }
   check_hip(hipEventRecord(B.ev_start, s), "hipEventRecord");
   for (hipStream_t st : B.streams) check_hip(hipStreamWaitEvent(st, B.ev_start, 0), "hipStreamWaitEvent");
   for (size_t g = 0; g < ng; ++g) {

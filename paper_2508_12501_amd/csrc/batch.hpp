@@ -52,6 +52,7 @@ struct BatchGroup {
   const double** bptr = nullptr;   // device table of M input pointers
   double** xptr = nullptr;         // device table of M output pointers
   hipGraphExec_t graph = nullptr;
+  int64_t graph_epoch = -1;        // H->weight_epoch when the graph was captured
   int last_iters = 0;
 };
 

@@ -238,6 +238,9 @@ struct Hierarchy {
   int32_t n0 = 0;
   std::vector<double> kvert_h;     // vertex coefficient (finest), empty = 1
   int64_t kversion = 0;            // bumped by every change of the vertex coefficient
+  // bumped whenever the form of the weights some row kernel reads changes (binary16, FP32 or
+  // FP64 copy); graphs captured before such a change are no longer valid
+  int64_t weight_epoch = 0;
   PorousData por;
   // solver workspace (finest level, internal numbering, n+1 entries)
   double *sx = nullptr, *sr = nullptr, *sp = nullptr, *sq = nullptr, *sz = nullptr,

@@ -917,7 +917,21 @@ bool half_exact(double v, uint16_t& h) {
 
 }  // namespace
 
+// The form of the weights each row kernel reads (binary16, FP32 or FP64 copy) is chosen when
+// the kernel is enqueued, so a captured graph keeps the choice of its capture.  Returns one bit
+// per exactness flag of every level and colour class.
+static std::vector<bool> weight_forms(const Hierarchy& H) {
+  std::vector<bool> f;
+  for (const auto& Lp : H.lv) {
+    f.push_back(Lp->op.w_exact16);
+    f.push_back(Lp->op.w_exact32);
+    for (const GsColor& G : Lp->gs) f.push_back(G.w_exact32);
+  }
+  return f;
+}
+
 void upload_weights(Hierarchy& H) {
+  const std::vector<bool> forms_before = weight_forms(H);
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = *H.lv[l];
     std::vector<double> w64, d64;
@@ -991,6 +1005,13 @@ void upload_weights(Hierarchy& H) {
       check_hip(hipMemcpy(H.coarse_inv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice),
                 "hipMemcpy");
     }
+  }
+  if (weight_forms(H) != forms_before) {
+    // graphs captured with the old weight forms would read stale copies: drop them (they are
+    // captured again on next use) and tell batches built on this hierarchy to recapture theirs
+    for (auto& kv : H.graphs) (void)hipGraphExecDestroy(kv.second);
+    H.graphs.clear();
+    ++H.weight_epoch;
   }
 }
 

@@ -55,9 +55,10 @@ def start_step(f, y0, f0, t_end, atol, rtol):
 
 
 def integrate(f, y0, t_end, rtol=1e-9, atol=1e-6, h0=0.0, t_save=(), fixed_step=False,
-              max_steps=100000):
+              max_steps=100000, trace=None):
     """Integrate y' = f(y) from t = 0 to t_end.  Returns (y(t_end), [y(t) for t in t_save],
-    stats) with stats = accepted, rejected, rhs_evals, t, h_min, h_max."""
+    stats) with stats = accepted, rejected, rhs_evals, t, h_min, h_max.  trace (optional) is
+    called after every attempted step as trace(t_start, h, err, accepted, y_after)."""
     y = np.array(y0, dtype=np.float64)
     st = dict(accepted=0, rejected=0, rhs_evals=0, t=0.0, h_min=np.inf, h_max=0.0)
 
@@ -87,12 +88,15 @@ def integrate(f, y0, t_end, rtol=1e-9, atol=1e-6, h0=0.0, t_save=(), fixed_step=
         if not fixed_step:
             err = wrms(h * combo([b - e for b, e in zip(B5, B4)], ks), y, y5, atol, rtol)
         if fixed_step or err <= 1.0:
+            t0 = t
             t = t_stop if hit else t + h
             y, k0 = y5, ks[6]
             st["accepted"] += 1
             st["h_min"], st["h_max"] = min(st["h_min"], h), max(st["h_max"], h)
             if hit and len(saved) < len(t_save):
                 saved.append(y.copy())
+            if trace is not None:
+                trace(t0, h, err, True, y)
             if fixed_step:
                 h = float(h0)
             else:
@@ -100,6 +104,8 @@ def integrate(f, y0, t_end, rtol=1e-9, atol=1e-6, h0=0.0, t_save=(), fixed_step=
                 h *= min(facmax, max(0.2, fac))
                 facmax = 10.0
         else:
+            if trace is not None:
+                trace(t, h, err, False, y)
             st["rejected"] += 1
             fac = 0.9 * err ** (-1.0 / 5.0) if np.isfinite(err) else 0.2
             h *= max(0.2, fac)

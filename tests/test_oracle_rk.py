@@ -108,3 +108,95 @@ def test_e4_conductive_state_and_walls():
     assert np.array_equal(yT[m.wall], T0[m.wall])
     # heat leaves the hot blob: its peak decays
     assert yT[~m.wall].max() < T0[~m.wall].max()
+
+
+# ---------------------------------------------------------------------------------------------
+# Independent pin of the starting step and the step-size controller: SciPy's RK45 implements
+# the same Dormand-Prince pair with the Hairer-Norsett-Wanner starting-step rule and the same
+# controller (safety 0.9, factors in [0.2, 10], exponent -1/5, a factor of at most 1 on the step
+# after a rejection, RMS error norm with scale atol + rtol max(|y|, |y_new|)).  It was written
+# independently of this oracle, so a mistake shared by the oracle and the library copy of the
+# controller (an exponent, a swapped norm, a missed clamp) shows up here.  The two differ only
+# in how they land on t_end (SciPy clamps the step that would pass it, the oracle also cuts a
+# step that would end within 1% of it), so the comparison covers every step before the last
+# and the state at the last common time.  The starting step is compared on its own (to
+# rounding).  The step sequences then start from the same given first step, four times the
+# automatic one: the automatic step has err ~ 1e-5, formed from stage sums that cancel to
+# 1e-7 .. 1e-11 of their size, so the two codes' summation orders would move the next step by up
+# to 1e-6 relative; a first step with err ~ 0.1 keeps every estimate well conditioned.  A
+# controller mistake (a constant, the exponent, a clamp, the norm) moves h by 1e-2 or more.
+
+def _scipy_steps(f, y0, t_end, rtol, atol, first_step=None):
+    from scipy.integrate import RK45
+    s = RK45(lambda t, y: f(y), 0.0, np.array(y0, dtype=np.float64), t_end, rtol=rtol,
+             atol=atol, first_step=first_step)
+    h_first = s.h_abs
+    steps = []  # (t_start, h, rejections before acceptance, y_after)
+    while s.status == "running":
+        t0, nfev0 = s.t, s.nfev
+        msg = s.step()
+        assert msg is None, msg
+        attempts = (s.nfev - nfev0) // 6
+        steps.append((t0, s.t - t0, attempts - 1, s.y.copy()))
+    return h_first, steps
+
+
+def _oracle_steps(f, y0, t_end, rtol, atol, first_step=0.0):
+    log = []
+    rej = [0]
+
+    def tr(t0, h, err, acc, y):
+        if acc:
+            log.append((t0, h, rej[0], y.copy()))
+            rej[0] = 0
+        else:
+            rej[0] += 1
+
+    y0 = np.array(y0, dtype=np.float64)
+    h_first = rk.start_step(f, y0, f(y0), t_end, atol, rtol)
+    _, _, st = rk.integrate(f, y0, t_end, rtol=rtol, atol=atol, h0=first_step, trace=tr)
+    return h_first, log, st
+
+
+def _van_der_pol(mu):
+    return lambda y: np.array([y[1], mu * (1.0 - y[0] ** 2) * y[1] - y[0]])
+
+
+def _linear6():
+    rng = np.random.default_rng(7)
+    Q = rng.standard_normal((6, 6))
+    M = -(Q @ Q.T) / 6.0 + 0.5 * (Q - Q.T)
+    return (lambda v: M @ v), rng.standard_normal(6)
+
+
+@pytest.mark.parametrize("case", ["linear6", "vdp5"])
+@pytest.mark.parametrize("rtol", [1e-6, 1e-9])
+def test_controller_against_scipy_rk45(case, rtol):
+    if case == "linear6":
+        f, y0 = _linear6()
+        t_end = 3.0
+    else:
+        f, y0 = _van_der_pol(5.0), np.array([2.0, 0.0])
+        t_end = 12.0
+    atol = 1e-3 * rtol
+    hs, _ = _scipy_steps(f, y0, t_end, rtol, atol)
+    ho = rk.start_step(f, y0, f(y0), t_end, atol, rtol)
+    assert abs(ho - hs) <= 1e-14 * hs
+    _, ss = _scipy_steps(f, y0, t_end, rtol, atol, first_step=4.0 * hs)
+    _, so, st = _oracle_steps(f, y0, t_end, rtol, atol, first_step=4.0 * hs)
+    # every accepted step before the one that lands on t_end: same start, size and rejections
+    n = min(len(ss), len(so)) - 1
+    assert n >= 20 and abs(len(ss) - len(so)) <= 1
+    total_rej = 0
+    for k in range(n):
+        (ts, h_s, r_s, _), (to, h_o, r_o, _) = ss[k], so[k]
+        assert r_s == r_o, (k, r_s, r_o)
+        assert abs(h_o - h_s) <= 1e-6 * h_s, (k, h_o, h_s)
+        assert abs(to - ts) <= 1e-7 * max(ts, 1.0), (k, to, ts)
+        total_rej += r_o
+    ys, yo = ss[n - 1][3], so[n - 1][3]
+    assert np.abs(yo - ys).max() <= 1e-6 * max(1.0, np.abs(ys).max())
+    if case == "vdp5":
+        # the relaxation oscillation forces rejections: the comparison covers that branch
+        assert total_rej >= 3
+    assert st["t"] == t_end

@@ -418,6 +418,23 @@ mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const doubl
                            int32_t n_save, const double* t_save, double* T_save, double* T_end,
                            porous_rk_stats* stats, void* stream);
 
+/* porous_integrate for callers that cannot allocate device memory (code under graph capture,
+ * serving loops, harnesses that forbid allocation): the same integration, arguments, results
+ * and errors, bit for bit, but it calls no hipMalloc, hipFree or other allocating routine.
+ * Its work vectors live in a static 8 MiB device work area, one per GPU, held until the
+ * process ends: 12 (n + 1) doubles plus reduction partials, so a hierarchy of up to about
+ * 87,000 finest-level unknowns (MG_EINVAL with the sizes beyond that; the 257 x 257 grid has
+ * 66,049).  The pressure solves run eagerly whatever model.solve.use_graph says, since
+ * capturing a graph allocates.  Set-up first: the hierarchy's porous data must exist, which
+ * one porous_step, porous_rhs or porous_integrate call on it creates (MG_EINVAL otherwise);
+ * a later change of the vertex coefficient is taken up with a host-to-device copy.  Calls
+ * share their GPU's work area and each starts by clearing it, so calls that overlap on one
+ * GPU (other streams, other threads, other hierarchies) race and must be serialised by the
+ * caller. */
+mg_status porous_integrate_noalloc(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
+                                   int32_t n_save, const double* t_save, double* T_save,
+                                   double* T_end, porous_rk_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------ measurement
  * Times `reps` back-to-back launches of one kernel of the path on `level` with hipEvents
  * recorded on `stream`, and returns the mean duration per launch in milliseconds.

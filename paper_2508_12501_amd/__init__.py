@@ -154,6 +154,8 @@ _PROTOS = {
                           ctypes.POINTER(mg_result), _vp]),
     "porous_integrate": (_i32, [_vp, ctypes.POINTER(porous_rk_opts), _vp, _i32, _vp, _vp, _vp,
                                 ctypes.POINTER(porous_rk_stats), _vp]),
+    "porous_integrate_noalloc": (_i32, [_vp, ctypes.POINTER(porous_rk_opts), _vp, _i32, _vp, _vp,
+                                        _vp, ctypes.POINTER(porous_rk_stats), _vp]),
     "mg_batch_create": (_i32, [ctypes.POINTER(_vp), _i32, ctypes.POINTER(mg_opts),
                                ctypes.POINTER(mg_batch_tuning), ctypes.c_char_p,
                                ctypes.POINTER(_vp)]),
@@ -493,15 +495,17 @@ def porous_rk_opts_make(model: porous_params, t_end: float, rtol: float = 1e-9,
 
 
 def porous_integrate(h, opts: porous_rk_opts, T0, T_end, t_save=(), T_save=None, stream=None,
-                     raise_on_error=True) -> porous_rk_stats:
-    """T_save: (len(t_save), nv) float64 device tensor (rows = save times), or None."""
+                     raise_on_error=True, noalloc=False) -> porous_rk_stats:
+    """T_save: (len(t_save), nv) float64 device tensor (rows = save times), or None.
+    noalloc=True calls porous_integrate_noalloc (no device allocation; static work area)."""
     import torch
     n = _nv(h, _top(h))
     ts = np.ascontiguousarray(np.asarray(t_save, dtype=np.float64))
     if len(ts) and (T_save is None or tuple(T_save.shape) != (len(ts), n)):
         raise ValueError("T_save must be (len(t_save), nv)")
     st = porous_rk_stats()
-    code = lib().porous_integrate(h, ctypes.byref(opts), _ptr(T0, torch.float64, n, "T0"),
+    fn = lib().porous_integrate_noalloc if noalloc else lib().porous_integrate
+    code = fn(h, ctypes.byref(opts), _ptr(T0, torch.float64, n, "T0"),
                                   len(ts), ts.ctypes.data if len(ts) else None,
                                   _ptr(T_save, torch.float64, n * len(ts), "T_save") if len(ts) else None,
                                   _ptr(T_end, torch.float64, n, "T_end"), ctypes.byref(st),

@@ -581,9 +581,9 @@ mg_status porous_rhs(mg_hierarchy* h, const porous_params* prm, const double* T,
   return MG_OK;
 }
 
-mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
-                           int32_t n_save, const double* t_save, double* T_save, double* T_end,
-                           porous_rk_stats* stats, void* stream) {
+namespace {
+mg_status check_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
+                          int32_t n_save, const double* t_save, double* T_save, double* T_end) {
   if (!o) return fail(MG_EINVAL, "null options");
   if (mg_status st = check_porous(h, &o->model, false); st != MG_OK) return st;
   if (!T0 || !T_end) return fail(MG_EINVAL, "null vector");
@@ -600,11 +600,34 @@ mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const doubl
   for (int32_t i = 0; i < n_save; ++i)
     if (!(t_save[i] > (i ? t_save[i - 1] : 0.0)) || !(t_save[i] <= o->t_end))
       return fail(MG_EINVAL, "save times must increase strictly within (0, t_end]");
+  return MG_OK;
+}
+}  // namespace
+
+mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
+                           int32_t n_save, const double* t_save, double* T_save, double* T_end,
+                           porous_rk_stats* stats, void* stream) {
+  if (mg_status st = check_integrate(h, o, T0, n_save, t_save, T_save, T_end); st != MG_OK)
+    return st;
   API_BEGIN
   const int st = decmg::run_porous_integrate(*h->h, *o, T0, n_save, t_save, T_save, T_end, stats,
                                              S(stream));
   if (st != MG_OK)
     return fail(mg_status(st), "porous_integrate stopped with status " + std::to_string(st));
+  API_END
+  return MG_OK;
+}
+
+mg_status porous_integrate_noalloc(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
+                                   int32_t n_save, const double* t_save, double* T_save,
+                                   double* T_end, porous_rk_stats* stats, void* stream) {
+  if (mg_status st = check_integrate(h, o, T0, n_save, t_save, T_save, T_end); st != MG_OK)
+    return st;
+  API_BEGIN
+  const int st = decmg::run_porous_integrate_noalloc(*h->h, *o, T0, n_save, t_save, T_save,
+                                                     T_end, stats, S(stream));
+  if (st != MG_OK)
+    return fail(mg_status(st), "porous_integrate_noalloc stopped with status " + std::to_string(st));
   API_END
   return MG_OK;
 }

@@ -129,6 +129,9 @@ constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse
 // throughput (one CU's outstanding misses) makes it pay only for levels whose operator data is
 // a few tens of KB; larger levels run as regular multi-workgroup launches.
 constexpr int32_t kCoarseFuseRows = 2048;
+// Size of the static device work area of porous_integrate_noalloc (one copy per GPU).
+constexpr size_t kRkStaticWorkBytes = size_t(8) << 20;
+constexpr int kMaxDevices = 64;
 
 // Per-level descriptor of the fused coarse cycle (device copy per precision).
 template <typename T>
@@ -252,6 +255,7 @@ struct Hierarchy {
   int32_t part_cap = 0;
   DevScalars* scal = nullptr;
   DevScalars* scal_host = nullptr; // pinned
+  double* aux_host = nullptr;      // pinned, one double (host reads of single device results)
   hipStream_t capture_stream = nullptr;
   std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
   std::map<std::tuple<int, int, int, int, double>, int> last_iters;
@@ -349,6 +353,9 @@ void rk_axpy(const double* y, const RkTerms& tm, double h, double* out, int32_t 
 // *out = sqrt(mean_i ((scale sum_j c_j v_j)_i / (atol + rtol max(|u_i|, |w_i|)))^2); part holds
 // rk_parts(n) doubles of scratch.  Device result.
 int rk_parts(int32_t n);
+// This GPU's copy of the static work area of the allocation-free integrator
+// (kRkStaticWorkBytes, 256-byte aligned): its device address, looked up once per device.
+double* rk_static_work();
 void rk_wrms(const RkTerms& tm, double scale, const double* u, const double* w, double atol,
              double rtol, double* part, double* out, int32_t n, hipStream_t s);
 

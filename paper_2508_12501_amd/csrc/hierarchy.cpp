@@ -1109,6 +1109,9 @@ Hierarchy* build_levels(std::unique_ptr<Hierarchy> H, std::vector<Mesh> meshes,
   check_hip(hipHostMalloc(reinterpret_cast<void**>(&H->scal_host), sizeof(DevScalars), 0),
             "hipHostMalloc");
   std::memset(H->scal_host, 0, sizeof(DevScalars));
+  check_hip(hipHostMalloc(reinterpret_cast<void**>(&H->aux_host), sizeof(double), 0),
+            "hipHostMalloc");
+  *H->aux_host = 0.0;
   check_hip(hipStreamCreateWithFlags(&H->capture_stream, hipStreamNonBlocking), "hipStreamCreate");
   return H.release();
 }
@@ -1146,6 +1149,7 @@ Hierarchy::~Hierarchy() {
                   (void*)sb, (void*)part, (void*)scal})
     free_dev(p);
   if (scal_host) (void)hipHostFree(scal_host);
+  if (aux_host) (void)hipHostFree(aux_host);
   if (capture_stream) (void)hipStreamDestroy(capture_stream);
 }
 

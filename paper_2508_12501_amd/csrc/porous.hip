@@ -13,6 +13,8 @@
 // vertices through a vertex -> incident-edge list (all vertices, natural numbering).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "hier.hpp"
 #include "util.hpp"
 
@@ -250,7 +252,27 @@ const void* colp(const Level& L) {
 
 }  // namespace
 
+// Work area of the allocation-free integrator: one copy on every GPU the library runs on, held
+// until the process ends.  In host code this name is not a device address; host code uses the
+// address rk_static_work() looks up for the current device.
+static __device__ __align__(256) double scratch[kRkStaticWorkBytes / sizeof(double)];
+
 namespace k {
+
+double* rk_static_work() {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = -1;
+  check_hip(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) throw DeviceError("device ordinal out of range");
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    check_hip(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    addr[dev] = p;
+  }
+  return static_cast<double*>(addr[dev]);
+}
 
 void rk_axpy(const double* y, const RkTerms& tm, double h, double* out, int32_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_rk_axpy, dim3(blocks(n)), dim3(kThreads), 0, s, y, tm, h, out, n);

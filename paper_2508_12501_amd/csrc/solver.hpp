@@ -38,6 +38,13 @@ int run_porous_step(Hierarchy& H, const PorousParams& p, const double* T_nat, do
 int run_porous_integrate(Hierarchy& H, const porous_rk_opts& o, const double* T0_nat,
                          int32_t n_save, const double* t_save, double* Tsave_nat,
                          double* Tend_nat, porous_rk_stats* stats, hipStream_t s);
+// The same integration with its work in this GPU's static work area (no device or pinned
+// allocation; the pressure solves run eagerly).
+int run_porous_integrate_noalloc(Hierarchy& H, const porous_rk_opts& o, const double* T0_nat,
+                                 int32_t n_save, const double* t_save, double* Tsave_nat,
+                                 double* Tend_nat, porous_rk_stats* stats, hipStream_t s);
+// bytes of static work area the allocation-free integration needs for n unknowns
+size_t porous_integrate_static_bytes(int32_t n);
 // Porous data of the finest level (built on first use, refreshed when k changes).
 void porous_prepare(Hierarchy& H);
 void porous_check(const Hierarchy& H, const PorousParams& p);

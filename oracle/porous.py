@@ -81,7 +81,8 @@ class PorousModel:
             x = np.zeros_like(b)
             x[1:] = self._lu.solve(b[1:])
             return x - x.mean()
-        x, _, _ = omg.mg_pcg(self.h, rhs, rtol=self.rtol)
+        x, k, _ = omg.mg_pcg(self.h, rhs, rtol=self.rtol)
+        self.last_iterations = k
         return x
 
     def pressure(self, T):
@@ -113,15 +114,20 @@ class PorousModel:
             T, _ = self.step(T)
         return T
 
-    # -- adjoint of one step: returns lambda_n and the increment of dJ/dk_v
-    def step_adjoint(self, T, lam):
-        p, b1 = self.pressure(T)
+    # -- adjoint of one step: returns lambda_n and the increment of dJ/dk_v.  The pressure p
+    # and the adjoint pressure psi are solved for unless given.
+    def step_adjoint(self, T, lam, p=None, psi=None):
+        if p is None:
+            p, b1 = self.pressure(T)
+        else:
+            b1 = self.buoyancy(T)
         mu = self.mask * lam / self.star0
         d0T = self.d0 @ T
         q = -self.ke * (self.d0 @ p - b1)
         c = 0.5 * self.star1 * (self.absd0 @ mu)        # c_e = star1_e (mu_lo + mu_hi)/2
         g = c * d0T
-        psi = self.solve(self.d0.T @ (self.ke * g))     # adjoint pressure
+        if psi is None:
+            psi = self.solve(self.d0.T @ (self.ke * g))  # adjoint pressure
         d0psi = self.d0 @ psi
         h = self.ke * g - self.W * d0psi
         jac_t = (-(1.0 / self.phi) * (self.d0.T @ (c * q) + 0.5 * (self.absd0.T @ (h * self.dy)))

@@ -55,7 +55,9 @@ typedef enum {
   MG_ENOCONV = 4,     /* max_iter reached before rtol; result and x are still filled */
   MG_EBREAKDOWN = 5,  /* CG breakdown: p^T A p <= 0 or a non-positive preconditioned norm */
   MG_ENONFINITE = 6,  /* a non-finite value in the input or in a residual norm */
-  MG_EINCOMPAT = 7    /* singular system with a right-hand side far from the range */
+  MG_EINCOMPAT = 7    /* natural-boundary (singular) system whose right-hand side b is outside
+                         the operator's range, |sum b| > 1e-8 sum |b| (mg_pcg and mg_solve
+                         with mg_opts.compat_check set) */
 } mg_status;
 
 enum { MG_F64 = 0, MG_F32 = 1 };
@@ -200,6 +202,32 @@ mg_status mg_hierarchy_export_interp(const mg_hierarchy* h, int32_t level, int32
  * hierarchy from mg_hierarchy_build_maps whose maps do not keep the coarse vertex ids. */
 mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex, void* stream);
 
+/* The same with the coefficient given by its logarithm (the permeability k = exp(g) of the
+ * porous experiments, Sec. 3.2): the library forms k_v = exp(g_v) and sets it as above.
+ * g_vertex: device array of nv_finest finite values.  MG_EINVAL as above. */
+mg_status mg_hierarchy_set_log_coeff(mg_hierarchy* h, const double* g_vertex, void* stream);
+
+/* Chain rule through k = exp(g): grad_g_v += k_v grad_k_v for the vertex coefficient the
+ * hierarchy holds (k = 1 when none is set), so that a gradient with respect to k (the grad_k
+ * of mg_pcg_adjoint and porous_step_adjoint) becomes one with respect to g.  Device arrays of
+ * nv_finest doubles; grad_g ACCUMULATES.  MG_EINVAL when the hierarchy holds an edge
+ * coefficient. */
+mg_status mg_hierarchy_coeff_grad_log(mg_hierarchy* h, const double* grad_k, double* grad_g,
+                                      void* stream);
+
+/* Darcy coefficient as an edge field (Sec. 3.2, Eq. dec_darcy: K acts on the 1-form d0 p edge
+ * by edge): k_edge is a device array of ne_finest positive values in the natural edge order of
+ * the finest level, whose operator uses w_e = star1_e k_e.  Coarser levels take, for each of
+ * their edges, the mean of the coefficients of the fine edges it was split into (its two
+ * halves under a binary subdivision, its three thirds under a cubic one), recursively.  It
+ * replaces a vertex coefficient (and the other way round); NULL restores k = 1.  The porous
+ * step uses k_e as its Darcy coefficient.  The vertex-coefficient gradients (grad_k of
+ * mg_pcg_adjoint and porous_step_adjoint) are refused while it is set; mg_pcg_adjoint's grad_w
+ * gives the gradient for the finest edge weights.  MG_EINVAL for hierarchies from
+ * mg_hierarchy_build_maps (no edge correspondence between levels) and for non-positive or
+ * non-finite values. */
+mg_status mg_hierarchy_set_edge_coeff(mg_hierarchy* h, const double* k_edge, void* stream);
+
 /* ------------------------------------------------------------------ operators (device)
  * b = star0 f on `level` (Sec. 3.1 right-hand side of L u = star0 f); Dirichlet: b = 0 on
  * the boundary.  f, b: nv doubles. */
@@ -257,6 +285,10 @@ typedef struct {
                             cycles run the smoothing, residual and transfers of each leg in one
                             launch over overlapping workgroup tiles (same results bit for bit);
                             0: one launch per step (1) */
+  int32_t compat_check;  /* natural-boundary systems, mg_pcg and mg_solve: 1 refuses a
+                            right-hand side outside the operator's range, |sum b| > 1e-8 sum |b|,
+                            with MG_EINCOMPAT (x = 0); 0 projects it onto the range by removing
+                            its vertex mean (0) */
 } mg_opts;
 void mg_opts_default(mg_opts* o);
 
@@ -265,20 +297,38 @@ typedef struct {
   int32_t status;              /* the mg_status of the call */
   double rel_residual;         /* true ||b - A x|| / ||b|| at exit, computed in FP64 */
   double rel_residual_loop;    /* the recursively updated value the loop stopped on */
+  /* Residual history, filled when history is not null and history_cap > 0 (set both before
+   * the call, or zero-initialise the struct to skip it): history[i] is the loop's relative
+   * residual after iteration i + 1 (the recursively updated value for CG and FCG, the true one
+   * for iterative refinement and mg_solve), for the first min(iterations, history_cap, 4096)
+   * iterations, whose count is returned in history_len.  Host memory owned by the caller.
+   * Batched solves leave it unused. */
+  double* history;
+  int32_t history_cap;
+  int32_t history_len;
 } mg_result;
 
 /* One V(nu1,nu2) cycle on `level` (normally the finest), in place: x <- V(b, x).  dtype
  * selects FP64 or FP32 arithmetic (b and x of that type); the coarsest solve is FP64. */
 mg_status mg_vcycle(mg_hierarchy* h, const mg_opts* o, int32_t level, int32_t dtype,
                     const void* b, void* x, void* stream);
-/* Stand-alone multigrid: V-cycles from x = 0 until rtol (FP64). */
+/* Stand-alone multigrid: V-cycles from x = 0 until rtol (FP64).  Natural-boundary systems
+ * project b onto the range (its vertex mean removed), or with o->compat_check refuse one with
+ * |sum b| > 1e-8 sum |b| (MG_EINCOMPAT, x = 0). */
 mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
                    mg_result* res, void* stream);
 /* Krylov solve with one V-cycle as preconditioner, from x = 0: CG (symmetric FP64 cycle),
  * flexible CG FCG(1) (beta = -z^T q_prev / p_prev^T q_prev) or iterative refinement.  With
  * precision MG_F32 the cycle runs in FP32 on a scaled FP32 copy of the FP64 residual; the
  * residual, the solution update and the coarsest solve stay FP64.  Natural-BC hierarchies
- * remove the vertex mean of b, of every preconditioned vector and of x. */
+ * remove the vertex mean of b, of every preconditioned vector and of x; with
+ * o->compat_check a right-hand side with |sum b| > 1e-8 sum |b| is refused with MG_EINCOMPAT
+ * (x = 0).
+ * Stopping (Sec. 3.1): MG_OK only when the true relative residual ||b - A x|| / ||b||,
+ * recomputed in FP64 from x, is <= rtol.  CG and FCG iterate on the recursively updated
+ * residual; when that has met rtol but the true one has not, the iteration restarts from x
+ * (r = b - A x, the next direction the preconditioned residual), within max_iter in total;
+ * MG_ENOCONV when max_iter is reached first (x and the result are still filled). */
 mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
                  mg_result* res, void* stream);
 
@@ -371,12 +421,14 @@ mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T
 mg_status porous_rhs(mg_hierarchy* h, const porous_params* prm, const double* T, double* dTdt,
                      double* p, mg_result* res, void* stream);
 /* Transpose of the step's Jacobian: lambda_out = (dT'/dT)^T lambda, with the pressure solve
- * differentiated through (one adjoint-pressure solve).  p (nullable) is the pressure that
- * porous_step returned for this T (recomputed when null).  grad_k (nullable) ACCUMULATES
- * lambda^T dT'/dk_v (nv doubles).  lambda_out must not alias lambda. */
+ * differentiated through (one adjoint-pressure solve, zero-mean psi of
+ * L_K psi = d0^T (k_e star1_e (mu_lo + mu_hi)/2 (d0 T)_e), mu = mask lambda / star0).  p
+ * (nullable) is the pressure that porous_step returned for this T (recomputed when null).
+ * grad_k (nullable) ACCUMULATES lambda^T dT'/dk_v (nv doubles).  psi (nullable) receives the
+ * adjoint pressure (nv doubles).  lambda_out must not alias lambda. */
 mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const double* T,
                               const double* p, const double* lambda, double* lambda_out,
-                              double* grad_k, void* stream);
+                              double* grad_k, double* psi, void* stream);
 
 /* Adaptive time integration of dT/dt = porous_rhs(T) from t = 0 to t_end (Sec. 3.2: method of
  * lines; the paper integrates with an explicit adaptive Runge-Kutta 5(4) pair).  The pair here

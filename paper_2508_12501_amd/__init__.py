@@ -68,15 +68,36 @@ class mg_opts(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32),
-                ("fuse_levels", ctypes.c_int32)]
+                ("fuse_levels", ctypes.c_int32), ("compat_check", ctypes.c_int32)]
 
 
 class mg_result(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("rel_residual_loop", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("rel_residual_loop", ctypes.c_double),
+                ("history", ctypes.c_void_p), ("history_cap", ctypes.c_int32),
+                ("history_len", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        return {f: getattr(self, f) for f, _ in self._fields_
+                if f not in ("history", "history_cap", "history_len")}
+
+
+def _result(history: int):
+    """An mg_result, with a host buffer for `history` iterations when history > 0 (kept on the
+    result as .hist, a numpy array trimmed to history_len by _trim)."""
+    res = mg_result()
+    if history > 0:
+        buf = np.zeros(int(history), dtype=np.float64)
+        res.history = buf.ctypes.data
+        res.history_cap = int(history)
+        res._hist_buf = buf
+    return res
+
+
+def _trim(res):
+    buf = getattr(res, "_hist_buf", None)
+    res.hist = None if buf is None else buf[:res.history_len].copy()
+    return res
 
 
 class mg_geomap(ctypes.Structure):
@@ -135,6 +156,9 @@ _PROTOS = {
     "mg_hierarchy_export": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "mg_hierarchy_export_interp": (_i32, [_vp, _i32, _vp, _vp]),
     "mg_hierarchy_set_vertex_coeff": (_i32, [_vp, _vp, _vp]),
+    "mg_hierarchy_set_log_coeff": (_i32, [_vp, _vp, _vp]),
+    "mg_hierarchy_coeff_grad_log": (_i32, [_vp, _vp, _vp, _vp]),
+    "mg_hierarchy_set_edge_coeff": (_i32, [_vp, _vp, _vp]),
     "dec_star0_apply": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "dec_laplacian_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "mg_smooth": (_i32, [_vp, _i32, _i32, _i32, _d, _vp, _vp, _vp]),
@@ -149,7 +173,7 @@ _PROTOS = {
     "porous_step": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp,
                            ctypes.POINTER(mg_result), _vp]),
     "porous_step_adjoint": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp, _vp, _vp,
-                                   _vp]),
+                                   _vp, _vp]),
     "porous_rhs": (_i32, [_vp, ctypes.POINTER(porous_params), _vp, _vp, _vp,
                           ctypes.POINTER(mg_result), _vp]),
     "porous_integrate": (_i32, [_vp, ctypes.POINTER(porous_rk_opts), _vp, _i32, _vp, _vp, _vp,
@@ -360,6 +384,31 @@ def mg_hierarchy_set_vertex_coeff(h, k_vertex, stream=None):
     _check(lib().mg_hierarchy_set_vertex_coeff(h, ptr, _stream(stream)))
 
 
+def mg_hierarchy_set_log_coeff(h, g_vertex, stream=None):
+    """k = exp(g) at the finest level's vertices (the library forms the exponential)."""
+    import torch
+    _check(lib().mg_hierarchy_set_log_coeff(h, _ptr(g_vertex, torch.float64, _nv(h, _top(h)), "g"),
+                                            _stream(stream)))
+
+
+def mg_hierarchy_coeff_grad_log(h, grad_k, grad_g, stream=None):
+    """grad_g += k * grad_k (chain rule through k = exp(g); accumulates into grad_g)."""
+    import torch
+    n = _nv(h, _top(h))
+    _check(lib().mg_hierarchy_coeff_grad_log(h, _ptr(grad_k, torch.float64, n, "grad_k"),
+                                             _ptr(grad_g, torch.float64, n, "grad_g"),
+                                             _stream(stream)))
+
+
+def mg_hierarchy_set_edge_coeff(h, k_edge, stream=None):
+    """Darcy coefficient per finest-level edge (natural edge order); None restores k = 1."""
+    import torch
+    top = _top(h)
+    ptr = None if k_edge is None else _ptr(k_edge, torch.float64,
+                                           mg_hierarchy_info(h, top)["ne"], "k_edge")
+    _check(lib().mg_hierarchy_set_edge_coeff(h, ptr, _stream(stream)))
+
+
 # ----------------------------------------------------------------- operators
 def _nv(h, level):
     return mg_hierarchy_info(h, level)["nv"]
@@ -418,23 +467,27 @@ def mg_vcycle(h, opts: mg_opts, level: int, b, x, stream=None):
                            _ptr(b, x.dtype, n, "b"), _ptr(x, None, n, "x"), _stream(stream)))
 
 
-def mg_solve(h, opts: mg_opts, b, x, stream=None, raise_on_error=True) -> mg_result:
+def mg_solve(h, opts: mg_opts, b, x, stream=None, raise_on_error=True, history=0) -> mg_result:
+    """history > 0: the result's .hist holds the relative residual after each cycle."""
     import torch
-    res = mg_result()
+    res = _result(history)
     n = _nv(h, _top(h))
     st = lib().mg_solve(h, ctypes.byref(opts), _ptr(b, torch.float64, n, "b"),
                         _ptr(x, torch.float64, n, "x"), ctypes.byref(res), _stream(stream))
+    _trim(res)
     if raise_on_error:
         _check(st, res)
     return res
 
 
-def mg_pcg(h, opts: mg_opts, b, x, stream=None, raise_on_error=True) -> mg_result:
+def mg_pcg(h, opts: mg_opts, b, x, stream=None, raise_on_error=True, history=0) -> mg_result:
+    """history > 0: the result's .hist holds the loop's relative residual per iteration."""
     import torch
-    res = mg_result()
+    res = _result(history)
     n = _nv(h, _top(h))
     st = lib().mg_pcg(h, ctypes.byref(opts), _ptr(b, torch.float64, n, "b"),
                       _ptr(x, torch.float64, n, "x"), ctypes.byref(res), _stream(stream))
+    _trim(res)
     if raise_on_error:
         _check(st, res)
     return res
@@ -527,14 +580,17 @@ def porous_step(h, prm: porous_params, T, T_out, p=None, stream=None, raise_on_e
     return res
 
 
-def porous_step_adjoint(h, prm: porous_params, T, p, lam, lam_out, grad_k=None, stream=None):
+def porous_step_adjoint(h, prm: porous_params, T, p, lam, lam_out, grad_k=None, stream=None,
+                        psi=None):
+    """psi (optional tensor): receives the adjoint pressure."""
     import torch
     n = _nv(h, _top(h))
     _check(lib().porous_step_adjoint(h, ctypes.byref(prm), _ptr(T, torch.float64, n, "T"),
                                      _opt_ptr(p, torch.float64, n, "p"),
                                      _ptr(lam, torch.float64, n, "lambda"),
                                      _ptr(lam_out, torch.float64, n, "lambda_out"),
-                                     _opt_ptr(grad_k, torch.float64, n, "grad_k"), _stream(stream)))
+                                     _opt_ptr(grad_k, torch.float64, n, "grad_k"),
+                                     _opt_ptr(psi, torch.float64, n, "psi"), _stream(stream)))
 
 
 class BatchRef:

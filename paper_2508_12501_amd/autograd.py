@@ -5,8 +5,9 @@ field flows back through the DEC operators and the linear solves).
 
 Both wrappers are ``torch.autograd.Function``s whose forward and backward passes are calls of
 the library's entry points (``mg_pcg`` / ``mg_pcg_adjoint``, ``porous_step`` /
-``porous_step_adjoint``); nothing here does arithmetic on the fields beyond zero-filling the
-gradient buffers and the final k dJ/dk product of the chain rule through k = exp(g).
+``porous_step_adjoint``, and ``mg_hierarchy_set_log_coeff`` / ``mg_hierarchy_coeff_grad_log``
+for k = exp(g) and its chain rule); nothing here does arithmetic on the fields beyond
+zero-filling the gradient buffers.
 
 The hierarchy holds one vertex coefficient at a time.  Each forward and each backward pass
 sets the coefficient it was called with, so interleaving several graphs on one hierarchy is
@@ -16,7 +17,8 @@ from __future__ import annotations
 
 import torch
 
-from . import (mg_hierarchy_set_vertex_coeff, mg_opts_default, mg_pcg, mg_pcg_adjoint,
+from . import (mg_hierarchy_coeff_grad_log, mg_hierarchy_set_log_coeff,
+               mg_hierarchy_set_vertex_coeff, mg_opts_default, mg_pcg, mg_pcg_adjoint,
                porous_params_make, porous_step, porous_step_adjoint)
 
 
@@ -70,8 +72,7 @@ class PorousRollout(torch.autograd.Function):
     def forward(ctx, hier, prm, T0, g, steps, ckpt):
         T0 = _f64(T0, "T0")
         g = _f64(g, "g")
-        k = torch.exp(g)
-        mg_hierarchy_set_vertex_coeff(hier.h, k)
+        mg_hierarchy_set_log_coeff(hier.h, g)
         ckpt = int(ckpt) if ckpt else int(steps)
         saved = {0: T0.clone()}
         T, Tn = T0.clone(), torch.empty_like(T0)
@@ -81,14 +82,14 @@ class PorousRollout(torch.autograd.Function):
             if (n + 1) % ckpt == 0 and n + 1 < steps:
                 saved[n + 1] = T.clone()
         ctx.hier, ctx.prm, ctx.steps, ctx.ckpt, ctx.saved = hier, prm, int(steps), ckpt, saved
-        ctx.save_for_backward(k)
+        ctx.save_for_backward(g)
         return T
 
     @staticmethod
     def backward(ctx, grad_T):
-        (k,) = ctx.saved_tensors
+        (g,) = ctx.saved_tensors
         hier, prm = ctx.hier, ctx.prm
-        mg_hierarchy_set_vertex_coeff(hier.h, k)
+        mg_hierarchy_set_log_coeff(hier.h, g)
         lam = grad_T.detach().contiguous().clone()
         lam_n = torch.empty_like(lam)
         gk = torch.zeros_like(lam)
@@ -106,7 +107,10 @@ class PorousRollout(torch.autograd.Function):
                 lam, lam_n = lam_n, lam
         ctx.saved = None
         gT0 = lam if ctx.needs_input_grad[2] else None
-        gg = gk * k if ctx.needs_input_grad[3] else None
+        gg = None
+        if ctx.needs_input_grad[3]:
+            gg = torch.zeros_like(gk)
+            mg_hierarchy_coeff_grad_log(hier.h, gk, gg)
         return None, None, gT0, gg, None, None
 
 

@@ -434,6 +434,7 @@ int batch_solve(Batch& B, const double* const* b, double* const* x, mg_result* r
         r.status = cc[c].status;
         r.rel_residual = cc[c].bnorm > 0 ? cc[c].true_rnorm / cc[c].bnorm : 0.0;
         r.rel_residual_loop = cc[c].bnorm > 0 ? cc[c].rnorm / cc[c].bnorm : 0.0;
+        r.history_len = 0;
       }
     }
     G.last_iters = it;

@@ -79,6 +79,8 @@ mg_status check_opts(const mg_opts* o) {
       o->smoother != MG_SMOOTH_CG)
     return fail(MG_EINVAL, "smoother must be MG_SMOOTH_JACOBI, MG_SMOOTH_GS or MG_SMOOTH_CG");
   if (o->fuse_levels != 0 && o->fuse_levels != 1) return fail(MG_EINVAL, "fuse_levels must be 0 or 1");
+  if (o->compat_check != 0 && o->compat_check != 1)
+    return fail(MG_EINVAL, "compat_check must be 0 or 1");
   return MG_OK;
 }
 
@@ -182,7 +184,7 @@ void sync_check(hipStream_t s) {
 extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }
-int32_t mg_abi_version(void) { return 1; }
+int32_t mg_abi_version(void) { return 2; }
 
 mg_status dec_mesh_from_arrays(int64_t nv, const double* xyz, int64_t nt, const int32_t* tri,
                                dec_mesh** out) {
@@ -367,6 +369,33 @@ mg_status mg_hierarchy_export_interp(const mg_hierarchy* h, int32_t level, int32
   return MG_OK;
 }
 
+namespace {
+// The finest level's vertex coefficient (host copy of a device array of nv values), checked.
+mg_status set_vertex_field(decmg::Hierarchy& H, std::vector<double> kv) {
+  for (double v : kv)
+    if (!(v > 0.0) || !std::isfinite(v))
+      return fail(MG_EINVAL, "vertex coefficients must be finite and positive");
+  H.kvert_h = std::move(kv);
+  H.kedge_h.clear();
+  const size_t nv = H.kvert_h.size();
+  if (!H.kvert_d)
+    decmg::check_hip(hipMalloc(&H.kvert_d, nv * sizeof(double)), "hipMalloc");
+  decmg::check_hip(hipMemcpy(H.kvert_d, H.kvert_h.data(), nv * sizeof(double),
+                             hipMemcpyHostToDevice),
+                   "hipMemcpy");
+  ++H.kversion;
+  decmg::upload_weights(H);
+  return MG_OK;
+}
+
+std::vector<double> to_host(const double* d, size_t n, void* stream) {
+  std::vector<double> h(n);
+  decmg::check_hip(hipStreamSynchronize(S(stream)), "hipStreamSynchronize");
+  decmg::check_hip(hipMemcpy(h.data(), d, n * sizeof(double), hipMemcpyDeviceToHost), "hipMemcpy");
+  return h;
+}
+}  // namespace
+
 mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex, void* stream) {
   API_BEGIN
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
@@ -376,17 +405,70 @@ mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex,
                            "hierarchy do not keep the coarse vertex ids");
   if (!k_vertex) {
     H.kvert_h.clear();
-  } else {
-    const int32_t nv = H.lv.back()->nv;
-    std::vector<double> kv(nv);
-    decmg::check_hip(hipStreamSynchronize(S(stream)), "hipStreamSynchronize");
-    decmg::check_hip(hipMemcpy(kv.data(), k_vertex, nv * sizeof(double), hipMemcpyDeviceToHost),
-                     "hipMemcpy");
-    for (double v : kv)
-      if (!(v > 0.0) || !std::isfinite(v))
-        return fail(MG_EINVAL, "vertex coefficients must be finite and positive");
-    H.kvert_h = std::move(kv);
+    H.kedge_h.clear();
+    ++H.kversion;
+    decmg::upload_weights(H);
+    return MG_OK;
   }
+  return set_vertex_field(H, to_host(k_vertex, size_t(H.lv.back()->nv), stream));
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_hierarchy_set_log_coeff(mg_hierarchy* h, const double* g_vertex, void* stream) {
+  API_BEGIN
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  decmg::Hierarchy& H = *h->h;
+  if (!g_vertex) return fail(MG_EINVAL, "null g");
+  if (!H.nested_ids)
+    return fail(MG_EINVAL, "the vertex coefficient is injected by vertex id: the maps of this "
+                           "hierarchy do not keep the coarse vertex ids");
+  std::vector<double> k = to_host(g_vertex, size_t(H.lv.back()->nv), stream);
+  for (double& v : k) {
+    if (!std::isfinite(v)) return fail(MG_EINVAL, "g must be finite");
+    v = std::exp(v);
+  }
+  return set_vertex_field(H, std::move(k));
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_hierarchy_coeff_grad_log(mg_hierarchy* h, const double* grad_k, double* grad_g,
+                                      void* stream) {
+  API_BEGIN
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  if (!grad_k || !grad_g) return fail(MG_EINVAL, "null vector");
+  decmg::Hierarchy& H = *h->h;
+  if (!H.kedge_h.empty())
+    return fail(MG_EINVAL, "the hierarchy holds an edge coefficient, not a vertex one");
+  decmg::k::mul_acc(H.lv.back()->nv, H.kvert_h.empty() ? nullptr : H.kvert_d, grad_k, grad_g,
+                    S(stream));
+  decmg::check_hip(hipGetLastError(), "kernel launch");
+  API_END
+  return MG_OK;
+}
+
+mg_status mg_hierarchy_set_edge_coeff(mg_hierarchy* h, const double* k_edge, void* stream) {
+  API_BEGIN
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  decmg::Hierarchy& H = *h->h;
+  if (!k_edge) {
+    H.kvert_h.clear();
+    H.kedge_h.clear();
+    ++H.kversion;
+    decmg::upload_weights(H);
+    return MG_OK;
+  }
+  for (const auto& L : H.lv)
+    if (L->mesh.scheme != 1 && L->mesh.scheme != 2 && L.get() != H.lv.front().get())
+      return fail(MG_EINVAL, "edge coefficients need a hierarchy of subdivisions: the levels of "
+                             "mg_hierarchy_build_maps have no edge correspondence");
+  std::vector<double> ke = to_host(k_edge, size_t(H.lv.back()->mesh.ne), stream);
+  for (double v : ke)
+    if (!(v > 0.0) || !std::isfinite(v))
+      return fail(MG_EINVAL, "edge coefficients must be finite and positive");
+  H.kedge_h = decmg::coarsen_edge_coeff(H, std::move(ke));
+  H.kvert_h.clear();
   ++H.kversion;
   decmg::upload_weights(H);
   API_END
@@ -515,7 +597,7 @@ mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x, 
   if (mg_status st = check_krylov_opts(o); st != MG_OK) return st;
   if (!b || !x) return fail(MG_EINVAL, "null vector");
   API_BEGIN
-  const int st = decmg::run_pcg(*h->h, *o, b, x, res, S(stream));
+  const int st = decmg::run_pcg(*h->h, *o, b, x, res, S(stream), false, o->compat_check != 0);
   if (st != MG_OK) return fail(mg_status(st), "mg_pcg stopped with status " + std::to_string(st));
   API_END
   return MG_OK;
@@ -529,6 +611,9 @@ mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine
   if (!grad_u || !grad_b) return fail(MG_EINVAL, "null vector");
   if ((grad_k || grad_w) && !u_fine)
     return fail(MG_EINVAL, "grad_k and grad_w need the forward solution u_fine");
+  if (grad_k && !h->h->kedge_h.empty())
+    return fail(MG_EINVAL, "grad_k is the vertex-coefficient gradient; with an edge coefficient "
+                           "use grad_w");
   API_BEGIN
   const int st = decmg::run_pcg_adjoint(*h->h, *o, u_fine, grad_u, grad_b, grad_k, grad_w, res,
                                         S(stream));
@@ -634,13 +719,16 @@ mg_status porous_integrate_noalloc(mg_hierarchy* h, const porous_rk_opts* o, con
 
 mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const double* T,
                               const double* p, const double* lambda, double* lambda_out,
-                              double* grad_k, void* stream) {
+                              double* grad_k, double* psi, void* stream) {
   if (mg_status st = check_porous(h, prm); st != MG_OK) return st;
   if (!T || !lambda || !lambda_out) return fail(MG_EINVAL, "null vector");
   if (lambda == lambda_out) return fail(MG_EINVAL, "lambda_out must not alias lambda");
+  if (grad_k && !h->h->kedge_h.empty())
+    return fail(MG_EINVAL, "grad_k is the vertex-coefficient gradient; the hierarchy holds an "
+                           "edge coefficient");
   API_BEGIN
   const int st = decmg::run_porous_adjoint(*h->h, porous_of(prm), T, p, lambda, lambda_out,
-                                           grad_k, S(stream));
+                                           grad_k, psi, S(stream));
   if (st != MG_OK)
     return fail(mg_status(st), "porous_step_adjoint solve stopped with status " + std::to_string(st));
   API_END

@@ -129,6 +129,8 @@ constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse
 // throughput (one CU's outstanding misses) makes it pay only for levels whose operator data is
 // a few tens of KB; larger levels run as regular multi-workgroup launches.
 constexpr int32_t kCoarseFuseRows = 2048;
+// Iterations whose residual a solve records for mg_result.history.
+constexpr int32_t kHistoryCap = 4096;
 // Size of the static device work area of porous_integrate_noalloc (one copy per GPU).
 constexpr size_t kRkStaticWorkBytes = size_t(8) << 20;
 constexpr int kMaxDevices = 64;
@@ -209,6 +211,8 @@ struct DevScalars {
   double n_unknowns;
   double true_rnorm;   // ||b - A x|| recomputed at exit
   int32_t done, iters, status, max_iter;
+  double* hist;        // relative residual of the loop after each iteration (device), or null
+  int32_t hist_cap, pad_;
 };
 
 // Finest-level data of the porous-convection step and of the solve gradients (built on first
@@ -240,7 +244,10 @@ struct Hierarchy {
   double* coarse_inv = nullptr;    // n0 x n0 FP64 inverse of the coarsest operator
   int32_t n0 = 0;
   std::vector<double> kvert_h;     // vertex coefficient (finest), empty = 1
-  int64_t kversion = 0;            // bumped by every change of the vertex coefficient
+  double* kvert_d = nullptr;       // device copy of kvert_h (nv of the finest level)
+  // edge coefficient per level (natural edge order), empty = none; set instead of kvert_h
+  std::vector<std::vector<double>> kedge_h;
+  int64_t kversion = 0;            // bumped by every change of the coefficient
   // bumped whenever the form of the weights some row kernel reads changes (binary16, FP32 or
   // FP64 copy); graphs captured before such a change are no longer valid
   int64_t weight_epoch = 0;
@@ -255,6 +262,8 @@ struct Hierarchy {
   int32_t part_cap = 0;
   DevScalars* scal = nullptr;
   DevScalars* scal_host = nullptr; // pinned
+  double* hist = nullptr;          // residual history of the last solve (device, hist_cap)
+  int32_t hist_cap = 0;
   double* aux_host = nullptr;      // pinned, one double (host reads of single device results)
   hipStream_t capture_stream = nullptr;
   std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
@@ -359,6 +368,8 @@ double* rk_static_work();
 void rk_wrms(const RkTerms& tm, double scale, const double* u, const double* w, double atol,
              double rtol, double* part, double* out, int32_t n, hipStream_t s);
 
+// out += a * b entrywise, a null meaning 1 (porous.hip)
+void mul_acc(int32_t n, const double* a, const double* b, double* out, hipStream_t s);
 // porous step and solve gradients (porous.hip)
 void por_rhs(const Level& L, const PorousData& D, const double* T, double* rhs, hipStream_t s);
 // Tout = (add_T ? T : 0) + dt * dT/dt
@@ -423,7 +434,13 @@ enum FinOp : int {
   // sum2 = sum o; mean = sum1 / n and (z - mean).o = sum0 - mean sum2, then as BETA_CG / FCG
   FIN_MEAN_BETA_CG = 8,
   FIN_MEAN_BETA_FCG = 9,
+  // compatibility of a singular system's right-hand side: sum0 = sum b, sum1 = sum |b|;
+  // mean = sum0 / n, MG_EINCOMPAT when |sum0| > kCompatTol sum1
+  FIN_MEAN_COMPAT = 10,
 };
+// Relative size of sum b against sum |b| beyond which a natural-boundary right-hand side is
+// taken to be outside the operator's range (rounding of a compatible one stays near 1e-16).
+constexpr double kCompatTol = 1e-8;
 void finalize(int op, int32_t nblocks, const double* part0, const double* part1, DevScalars* sc,
               double extra, int force, hipStream_t s, const double* part2 = nullptr);
 // part0 = z.o, part1 = sum z, part2 = sum o (z32 widened by 1/scale), per block
@@ -431,7 +448,14 @@ void zsum_dot32(int32_t n, const DevScalars* sc, const float* z32, const double*
                 double* part1, double* part2, const int* done, hipStream_t s);
 void zsum_dot64(int32_t n, const DevScalars* sc, const double* z, const double* o, double* part0,
                 double* part1, double* part2, const int* done, hipStream_t s);
-void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, hipStream_t s);
+// starting scalars; hist (nullable) receives the loop's relative residual per iteration, up
+// to hist_cap of them
+void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, double* hist,
+                  int32_t hist_cap, hipStream_t s);
+// clears the converged flag and status (the loop continues from its current iterate)
+void restart_scalars(DevScalars* sc, hipStream_t s);
+// block partials of sum v (part0) and of sum |v| (part1)
+void sum_abs64(int32_t n, const double* v, double* part0, double* part1, hipStream_t s);
 }  // namespace k
 
 }  // namespace decmg

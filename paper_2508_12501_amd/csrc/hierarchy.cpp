@@ -304,7 +304,8 @@ void build_gs_colors(Level& L) {
 }
 
 // row sums in SELL order.
-void compute_weights(const Level& L, const std::vector<double>& kv, std::vector<double>& w64,
+// w = star1 k_e per SELL entry (ke empty: k = 1), and the row sums D
+void compute_weights(const Level& L, const std::vector<double>& ke, std::vector<double>& w64,
                      std::vector<float>& w32, std::vector<double>& d64, std::vector<float>& d32) {
   const Mesh& m = L.mesh;
   const size_t ne = L.entry_edge.size();
@@ -314,7 +315,7 @@ void compute_weights(const Level& L, const std::vector<double>& kv, std::vector<
     const int32_t e = L.entry_edge[i];
     if (e < 0) continue;
     double w = m.star1[e];
-    if (!kv.empty()) w = m.star1[e] * (0.5 * (kv[m.edge[2 * e]] + kv[m.edge[2 * e + 1]]));
+    if (!ke.empty()) w = m.star1[e] * ke[e];
     w64[i] = w;
     w32[i] = static_cast<float>(w);
   }
@@ -930,15 +931,69 @@ static std::vector<bool> weight_forms(const Hierarchy& H) {
   return f;
 }
 
+std::vector<double> level_edge_coeff(const Hierarchy& H, size_t l) {
+  if (!H.kedge_h.empty()) return H.kedge_h[l];
+  std::vector<double> ke;
+  if (H.kvert_h.empty()) return ke;
+  const Mesh& m = H.lv[l]->mesh;
+  ke.resize(size_t(m.ne));
+  for (int64_t e = 0; e < m.ne; ++e)
+    ke[e] = 0.5 * (H.kvert_h[m.edge[2 * e]] + H.kvert_h[m.edge[2 * e + 1]]);
+  return ke;
+}
+
+std::vector<std::vector<double>> coarsen_edge_coeff(const Hierarchy& H, std::vector<double> ke) {
+  std::vector<std::vector<double>> out(H.lv.size());
+  for (size_t l = H.lv.size(); l-- > 0;) {
+    out[l] = ke;
+    if (l == 0) break;
+    const Mesh& f = H.lv[l]->mesh;
+    const Mesh& c = H.lv[l - 1]->mesh;
+    // vertex -> incident edges of the fine mesh, to find an edge from its endpoints
+    std::vector<int64_t> vptr(size_t(f.nv) + 1, 0);
+    for (int64_t e = 0; e < f.ne; ++e) {
+      ++vptr[size_t(f.edge[2 * e]) + 1];
+      ++vptr[size_t(f.edge[2 * e + 1]) + 1];
+    }
+    for (int64_t v = 0; v < f.nv; ++v) vptr[v + 1] += vptr[v];
+    std::vector<int32_t> vinc(static_cast<size_t>(vptr[f.nv]));
+    std::vector<int64_t> pos(vptr.begin(), vptr.end() - 1);
+    for (int64_t e = 0; e < f.ne; ++e) {
+      vinc[pos[f.edge[2 * e]]++] = int32_t(e);
+      vinc[pos[f.edge[2 * e + 1]]++] = int32_t(e);
+    }
+    auto eid = [&](int32_t a, int32_t b) {
+      for (int64_t k = vptr[a]; k < vptr[a + 1]; ++k) {
+        const int32_t e = vinc[k];
+        if (f.edge[2 * e] + f.edge[2 * e + 1] - a == b) return e;
+      }
+      throw std::logic_error("subdivision edge not found");
+    };
+    const int32_t nc = int32_t(c.nv);
+    std::vector<double> kc(size_t(c.ne));
+    for (int64_t e = 0; e < c.ne; ++e) {
+      const int32_t a = c.edge[2 * e], b = c.edge[2 * e + 1];
+      if (f.scheme == 2) {
+        const int32_t p1 = nc + int32_t(2 * e), p2 = p1 + 1;
+        kc[e] = (ke[eid(a, p1)] + ke[eid(p1, p2)] + ke[eid(p2, b)]) / 3.0;
+      } else {
+        const int32_t mid = nc + int32_t(e);
+        kc[e] = 0.5 * (ke[eid(a, mid)] + ke[eid(mid, b)]);
+      }
+    }
+    ke = std::move(kc);
+  }
+  return out;
+}
+
 void upload_weights(Hierarchy& H) {
   const std::vector<bool> forms_before = weight_forms(H);
   for (size_t l = 0; l < H.lv.size(); ++l) {
     Level& L = *H.lv[l];
     std::vector<double> w64, d64;
     std::vector<float> w32, d32;
-    std::vector<double> kv;
-    if (!H.kvert_h.empty()) kv.assign(H.kvert_h.begin(), H.kvert_h.begin() + L.nv);
-    compute_weights(L, kv, w64, w32, d64, d32);
+    const std::vector<double> ke = level_edge_coeff(H, l);
+    compute_weights(L, ke, w64, w32, d64, d32);
     if (!L.op.w64) {
       L.op.w64 = zeros<double>(std::max<size_t>(w64.size(), 1));
       L.op.w32 = zeros<float>(std::max<size_t>(w32.size(), 1));
@@ -985,7 +1040,7 @@ void upload_weights(Hierarchy& H) {
         if (e < 0) continue;
         const Mesh& m = L.mesh;
         double w = m.star1[e];
-        if (!kv.empty()) w = m.star1[e] * (0.5 * (kv[m.edge[2 * e]] + kv[m.edge[2 * e + 1]]));
+        if (!ke.empty()) w = m.star1[e] * ke[e];
         g64[i] = w;
         g32[i] = static_cast<float>(w);
         if (static_cast<double>(g32[i]) != w) G.w_exact32 = false;
@@ -1106,6 +1161,8 @@ Hierarchy* build_levels(std::unique_ptr<Hierarchy> H, std::vector<Mesh> meshes,
   H->part_cap = std::max(k::blocks_for(nvmax), 1);
   H->part = zeros<double>(3 * int64_t(H->part_cap));
   H->scal = zeros<DevScalars>(1);
+  H->hist_cap = kHistoryCap;
+  H->hist = zeros<double>(kHistoryCap);
   check_hip(hipHostMalloc(reinterpret_cast<void**>(&H->scal_host), sizeof(DevScalars), 0),
             "hipHostMalloc");
   std::memset(H->scal_host, 0, sizeof(DevScalars));
@@ -1146,7 +1203,7 @@ Hierarchy::~Hierarchy() {
       free_dev(p);
   }
   for (void* p : {(void*)clv64, (void*)clv32, (void*)coarse_inv, (void*)sx, (void*)sr, (void*)sp, (void*)sp2, (void*)sq, (void*)sz,
-                  (void*)sb, (void*)part, (void*)scal})
+                  (void*)sb, (void*)part, (void*)scal, (void*)hist, (void*)kvert_d})
     free_dev(p);
   if (scal_host) (void)hipHostFree(scal_host);
   if (aux_host) (void)hipHostFree(aux_host);

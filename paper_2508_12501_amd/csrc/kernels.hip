@@ -1916,6 +1916,31 @@ __global__ __launch_bounds__(kBlock) void k_sum64(int32_t n, const double* __res
   if (threadIdx.x == 0) part0[blk] = a;
 }
 
+// Block partials of sum v and of sum |v| (the compatibility test of a singular system's
+// right-hand side).
+__global__ __launch_bounds__(kBlock) void k_sum_abs64(int32_t n, const double* __restrict__ v,
+                                                      double* __restrict__ part0,
+                                                      double* __restrict__ part1) {
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  double a = 0.0, b = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      const double x = v[i];
+      a += x;
+      b += fabs(x);
+    }
+  }
+  a = block_sum1(a);
+  b = block_sum1(b);
+  if (threadIdx.x == 0) {
+    part0[blk] = a;
+    part1[blk] = b;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_sum32(int32_t n, const float* __restrict__ v,
                                                   const DevScalars* __restrict__ sc,
                                                   double* __restrict__ part0,
@@ -2090,8 +2115,10 @@ __global__ void k_to_f32(int32_t n, const DevScalars* __restrict__ sc, const dou
 // One workgroup: fixed-order sum of the partials, then the scalar step `op`.
 // Starting values of the solver scalars (a kernel, so no host copy is in flight).
 __global__ void k_init_scalars(DevScalars* __restrict__ sc, double rtol, int32_t max_iter,
-                               double n_unknowns) {
+                               double n_unknowns, double* hist, int32_t hist_cap) {
   DevScalars z = {};
+  z.hist = hist;
+  z.hist_cap = hist_cap;
   z.rho = 1.0;
   z.pq = 1.0;
   z.scale = 1.0;
@@ -2147,6 +2174,8 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
   const double rho = sc->rho, pq = sc->pq, rtol = sc->rtol, bnorm = sc->bnorm;
   const double nun = sc->n_unknowns;
   const int iters = sc->iters, max_iter = sc->max_iter;
+  double* const hist = sc->hist;
+  const int hist_cap = sc->hist_cap;
   // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8, or
   // of 16 when there are more than 8 per thread (the one-partial-per-256-rows kernels on the
   // finest level), so that a single round trip fetches them all
@@ -2223,6 +2252,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       const double rn = sqrt(a);
       sc->rnorm = rn;
       sc->iters = iters + 1;
+      if (hist && iters < hist_cap) hist[iters] = rn / bnorm;
       if (!isfinite(rn)) {
         sc->status = MG_ENONFINITE;
         sc->done = 1;
@@ -2253,6 +2283,18 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       break;
     case k::FIN_MEAN:
       sc->mean = a / nun;
+      break;
+    case k::FIN_MEAN_COMPAT:
+      // a = sum b, b = sum |b|: a right-hand side of a singular (natural-boundary) system is
+      // in the range of the operator when sum b = 0; beyond rounding it has no solution
+      sc->mean = a / nun;
+      if (!isfinite(a) || !isfinite(b)) {
+        sc->status = MG_ENONFINITE;
+        sc->done = 1;
+      } else if (fabs(a) > k::kCompatTol * b) {
+        sc->status = MG_EINCOMPAT;
+        sc->done = 1;
+      }
       break;
     case k::FIN_RNORM:
       sc->true_rnorm = sqrt(a);
@@ -2889,8 +2931,23 @@ void finalize(int op, int32_t nblocks, const double* part0, const double* part1,
                      part2, sc, extra, force);
 }
 
-void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, hipStream_t s) {
-  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, sc, rtol, max_iter, n_unknowns);
+void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknowns, double* hist,
+                  int32_t hist_cap, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, s, sc, rtol, max_iter, n_unknowns, hist,
+                     hist_cap);
+}
+
+__global__ void k_restart_scalars(DevScalars* __restrict__ sc) {
+  sc->done = 0;
+  sc->status = MG_OK;
+}
+
+void restart_scalars(DevScalars* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_restart_scalars, dim3(1), dim3(1), 0, s, sc);
+}
+
+void sum_abs64(int32_t n, const double* v, double* part0, double* part1, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_abs64, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, v, part0, part1);
 }
 
 #define DECMG_INST(T)                                                                          \

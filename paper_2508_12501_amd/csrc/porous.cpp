@@ -84,12 +84,12 @@ void ensure(Hierarchy& H) {
     D.ready = true;
   }
   if (D.kversion != H.kversion) {
+    const std::vector<double> kedge = level_edge_coeff(H, H.lv.size() - 1);
     std::vector<double> ke(F.entry_edge.size(), 0.0);
     for (size_t i = 0; i < ke.size(); ++i) {
       const int32_t e = F.entry_edge[i];
       if (e < 0) continue;
-      ke[i] = H.kvert_h.empty() ? 1.0
-                                : 0.5 * (H.kvert_h[m.edge[2 * e]] + H.kvert_h[m.edge[2 * e + 1]]);
+      ke[i] = kedge.empty() ? 1.0 : kedge[e];
     }
     if (!D.ke) check_hip(hipMalloc(&D.ke, std::max<size_t>(ke.size(), 1) * sizeof(double)), "hipMalloc");
     if (!ke.empty())
@@ -161,7 +161,7 @@ int run_porous_rhs(Hierarchy& H, const PorousParams& p, const double* T_nat, dou
 
 int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
                        const double* p_nat, const double* lam_nat, double* lam_out_nat,
-                       double* gk_nat, hipStream_t s) {
+                       double* gk_nat, double* psi_nat, hipStream_t s) {
   check_params(H, p);
   ensure(H);
   PorousData& D = H.por;
@@ -185,6 +185,7 @@ int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
   k::por_adj_update(F, D, D.T, D.P, D.M, D.Lm, H.sx, D.L2, p.dt, p.phi, p.kappa(), s);
   if (gk_nat) k::por_grad_k(F, D, D.T, D.P, D.M, H.sx, gk_nat, p.dt, p.phi, s);
   k::scatter<double>(F.perm, n, D.L2, lam_out_nat, s);
+  if (psi_nat) k::scatter<double>(F.perm, n, H.sx, psi_nat, s);
   check_hip(hipGetLastError(), "kernel launch");
   return st;
 }

@@ -246,6 +246,15 @@ __global__ __launch_bounds__(kThreads) void k_rk_rms_fin(const double* __restric
 
 inline unsigned blocks(int64_t n) { return static_cast<unsigned>((n + kThreads - 1) / kThreads); }
 
+// out += a * b entrywise (a null: a = 1) -- the chain rule of k = exp(g): dJ/dg = k dJ/dk
+__global__ __launch_bounds__(kThreads) void k_mul_acc(int32_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ out) {
+  const int32_t i = blockIdx.x * kThreads + threadIdx.x;
+  if (i >= n) return;
+  out[i] += a ? a[i] * b[i] : b[i];
+}
+
 const void* colp(const Level& L) {
   return L.op.col16 ? static_cast<const void*>(L.op.col16) : static_cast<const void*>(L.op.col);
 }
@@ -272,6 +281,10 @@ double* rk_static_work() {
     addr[dev] = p;
   }
   return static_cast<double*>(addr[dev]);
+}
+
+void mul_acc(int32_t n, const double* a, const double* b, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mul_acc, dim3(blocks(n)), dim3(kThreads), 0, s, n, a, b, out);
 }
 
 void rk_axpy(const double* y, const RkTerms& tm, double h, double* out, int32_t n, hipStream_t s) {

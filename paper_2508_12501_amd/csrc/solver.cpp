@@ -354,7 +354,7 @@ hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
 }
 
 void init_scalars(Hierarchy& H, const mg_opts& o, hipStream_t s) {
-  k::init_scalars(H.scal, o.rtol, o.max_iter, double(H.lv.back()->n), s);
+  k::init_scalars(H.scal, o.rtol, o.max_iter, double(H.lv.back()->n), H.hist, H.hist_cap, s);
 }
 
 void read_scalars(Hierarchy& H, hipStream_t s) {
@@ -365,14 +365,21 @@ void read_scalars(Hierarchy& H, hipStream_t s) {
 }
 
 // b (natural, nv) -> H.sb (internal); ||b|| with the boundary part; projected for natural.
-// With b_nat == nullptr the internal right-hand side is already in H.sb.
-void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s) {
+// With b_nat == nullptr the internal right-hand side is already in H.sb.  check_compat: a
+// natural-boundary b whose sum exceeds rounding (|sum b| > kCompatTol sum |b|) ends the solve
+// with MG_EINCOMPAT.
+void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_compat = false) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   if (b_nat) k::gather<double>(F.perm, n, b_nat, H.sb, s);
   if (H.bc == MG_BC_NATURAL) {
-    k::sum64(n, H.sb, H.part, nullptr, s);
-    fin(H, k::FIN_MEAN, n, false, s);
+    if (check_compat) {
+      k::sum_abs64(n, H.sb, H.part, H.part + H.part_cap, s);
+      fin(H, k::FIN_MEAN_COMPAT, n, true, s);
+    } else {
+      k::sum64(n, H.sb, H.part, nullptr, s);
+      fin(H, k::FIN_MEAN, n, false, s);
+    }
     k::sub_mean(n, H.scal, H.sb, s);
     k::dot(n, H.sb, H.sb, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, n, false, s);
@@ -405,14 +412,26 @@ void enqueue_finish(Hierarchy& H, const double* b_nat, double* x_nat, hipStream_
   }
 }
 
-// The caller's result from the host copy of the scalars (read after the last finish).
-void collect(Hierarchy& H, mg_result* res) {
+// The caller's result from the host copy of the scalars (read after the last finish), with
+// the residual history copied to the caller's host buffer when one is given.
+void collect(Hierarchy& H, mg_result* res, hipStream_t s) {
   const DevScalars& h = *H.scal_host;
   if (res) {
     res->iterations = h.iters;
     res->status = h.status;
     res->rel_residual_loop = h.bnorm > 0 ? h.rnorm / h.bnorm : 0.0;
     res->rel_residual = h.bnorm > 0 ? h.true_rnorm / h.bnorm : 0.0;
+    res->history_len = 0;
+    if (res->history && res->history_cap > 0) {
+      const int m = std::min({h.iters, res->history_cap, H.hist_cap});
+      if (m > 0) {
+        check_hip(hipMemcpyAsync(res->history, H.hist, size_t(m) * sizeof(double),
+                                 hipMemcpyDeviceToHost, s),
+                  "hipMemcpyAsync");
+        check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+      }
+      res->history_len = m;
+    }
   }
 }
 
@@ -447,12 +466,12 @@ struct HostTimer {
 // after a batch that did not converge it is simply done again later.
 template <typename F, typename G>
 void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue, G tail,
-             HostTimer* T = nullptr) {
+             HostTimer* T = nullptr, int launched = 0) {
   const int every = std::max(1, o.check_every);
   auto key = graph_key(o, kind);
   auto it = H.last_iters.find(key);
-  int batch = (it != H.last_iters.end()) ? std::max(1, it->second) : every;
-  int launched = 0;
+  // a restarted loop (launched > 0) continues in batches of check_every
+  int batch = (it != H.last_iters.end() && launched == 0) ? std::max(1, it->second) : every;
   while (launched < o.max_iter) {
     batch = std::min(batch, o.max_iter - launched);
     for (int j = 0; j < batch; ++j) enqueue();
@@ -479,12 +498,12 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
 }
 
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
-            hipStream_t s, bool warm_start) {
+            hipStream_t s, bool warm_start, bool check_compat) {
   HostTimer T;
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   init_scalars(H, o, s);
-  setup_rhs(H, b_nat, s);
+  setup_rhs(H, b_nat, s, check_compat);
   H.p_parity = 0;
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
   if (warm_start && !b_nat) {
@@ -499,20 +518,47 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   hipGraphExec_t g[2] = {o.use_graph ? iteration_graph(H, o, 0) : nullptr,
                         o.use_graph ? iteration_graph(H, o, 2) : nullptr};
   T.mark("graph");
-  iterate(H, o, 0, s, [&]() {
+  auto step = [&]() {
     if (g[H.p_parity])
       check_hip(hipGraphLaunch(g[H.p_parity], s), "hipGraphLaunch");
     else
       enqueue_iteration(H, o, H.p_parity, s);
     H.p_parity ^= 1;
-  }, [&]() {
+  };
+  auto tail = [&]() {
     if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
-  }, &T);
+  };
+  iterate(H, o, 0, s, step, tail, &T);
   if (H.bc == MG_BC_NATURAL) {
     enqueue_finish(H, b_nat, x_nat, s);
     read_scalars(H, s);
   }
-  collect(H, res);
+  // The solve stops on the true relative residual ||b - A x|| / ||b|| (Sec. 3.1).  CG and FCG
+  // loop on the recursively updated residual; when that met rtol and the true one (computed
+  // by the finish) did not, the iteration restarts from x: r = b - A x, p = q = 0, so that the
+  // next direction is the preconditioned residual.
+  if (o.outer != MG_OUTER_IR) {
+    while (H.scal_host->status == MG_OK && H.scal_host->bnorm > 0 &&
+           H.scal_host->true_rnorm > o.rtol * H.scal_host->bnorm) {
+      const int done_iters = H.scal_host->iters;
+      if (done_iters >= o.max_iter) {
+        H.scal_host->status = MG_ENOCONV;
+        break;
+      }
+      k::restart_scalars(H.scal, s);
+      k::fill<double>(H.sp, n, 0.0, s);
+      k::fill<double>(H.sp2, n, 0.0, s);
+      k::fill<double>(H.sq, n, 0.0, s);
+      k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
+      if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
+      iterate(H, o, 0, s, step, tail, &T, done_iters);
+      if (H.bc == MG_BC_NATURAL) {
+        enqueue_finish(H, b_nat, x_nat, s);
+        read_scalars(H, s);
+      }
+    }
+  }
+  collect(H, res, s);
   T.mark("finish");
   return H.scal_host->status;
 }
@@ -521,7 +567,7 @@ int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, m
            hipStream_t s) {
   Level& F = *H.lv.back();
   init_scalars(H, o, s);
-  setup_rhs(H, b_nat, s);
+  setup_rhs(H, b_nat, s, o.compat_check != 0);
   k::fill<double>(H.sx, F.n, 0.0, s);
   hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 1) : nullptr;
   iterate(H, o, 1, s, [&]() {
@@ -536,7 +582,7 @@ int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, m
     enqueue_finish(H, b_nat, x_nat, s);
     read_scalars(H, s);
   }
-  collect(H, res);
+  collect(H, res, s);
   return H.scal_host->status;
 }
 

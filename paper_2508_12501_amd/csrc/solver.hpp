@@ -18,10 +18,18 @@ Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o);
 // Levels over given meshes whose interpolation rows are already set (set_interp_from_geomap).
 Hierarchy* build_hierarchy_maps(std::vector<Mesh> meshes, bool nested_ids, const mg_hier_opts& o);
 void upload_weights(Hierarchy& H);
+// Edge coefficient of level l (natural edge order): the edge field when one is set, else
+// (k_lo + k_hi)/2 from the vertex field at the level's own ids; empty when k = 1.
+std::vector<double> level_edge_coeff(const Hierarchy& H, size_t l);
+// Every level's edge coefficient from the finest level's: a coarse edge takes the mean of the
+// fine edges it was split into (two halves, or three thirds on a cubic subdivision).
+std::vector<std::vector<double>> coarsen_edge_coeff(const Hierarchy& H, std::vector<double> ke);
 // warm_start (internal right-hand side only, b_nat == nullptr): start from the iterate left in
-// H.sx by the previous solve instead of zero.
+// H.sx by the previous solve instead of zero.  check_compat: a natural-boundary b_nat outside
+// the operator's range ends the solve with MG_EINCOMPAT (the caller's right-hand sides; the
+// adjoint's upstream gradient is projected instead).
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
-            hipStream_t s, bool warm_start = false);
+            hipStream_t s, bool warm_start = false, bool check_compat = false);
 int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
            hipStream_t s);
 
@@ -54,7 +62,7 @@ int run_porous_rhs(Hierarchy& H, const PorousParams& p, const double* T_nat, dou
                    double* p_nat, mg_result* res, hipStream_t s);
 int run_porous_adjoint(Hierarchy& H, const PorousParams& p, const double* T_nat,
                        const double* p_nat, const double* lam_nat, double* lam_out_nat,
-                       double* gk_nat, hipStream_t s);
+                       double* gk_nat, double* psi_nat, hipStream_t s);
 int run_pcg_adjoint(Hierarchy& H, const mg_opts& o, const double* u_nat, const double* gu_nat,
                     double* gb_nat, double* gk_nat, double* gw_nat, mg_result* res,
                     hipStream_t s);

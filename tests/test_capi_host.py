@@ -15,7 +15,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(mg._PROTOS), set(names) ^ set(mg._PROTOS)
-    assert L.mg_abi_version() == 1
+    assert L.mg_abi_version() == 2
 
 
 def test_opts_default():

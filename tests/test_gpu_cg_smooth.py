@@ -2,7 +2,9 @@
 (multigrid.mgcycle with smoother="cg").  Right-hand sides and initial guesses are zero on the
 Dirichlet boundary (the smoother iterates on the unknowns; the oracle's identity rows then
 carry zero residual) and have zero mean on the sphere.  Tolerances: one FP64 cycle 1e-12, FP32 cycle 1e-4 (the CG coefficients
-are data dependent), FP64 FCG/IR solves at the oracle's iteration count 1e-10."""
+are data dependent), FP64 FCG/IR solves and stand-alone cycles at the oracle's iteration count
+1e-12 (the same algorithm: nonlinear cycles, but the rounding of the CG coefficients stays at
+the level of the operator products it divides, ~1e-15 measured)."""
 import numpy as np
 import pytest
 
@@ -101,11 +103,12 @@ def test_cg_smoothed_solvers(which, request):
         res = mg.mg_pcg(P.g.h, mg.mg_opts_default(outer=outer, **CG), gpu(b), x)
         print(f"[cgs] {which} outer {outer}: {res.iterations} iterations (oracle {ko}), "
               f"rel L2 {rel(host(x), xo):.2e}")
-        assert res.iterations == ko and rel(host(x), xo) <= 1e-10
+        assert res.iterations == ko and rel(host(x), xo) <= 1e-12
     xs, ks, _ = omg.mg_solve(P.o, b, nu1=3, nu2=3, smoother="cg")
     x.zero_()
     res = mg.mg_solve(P.g.h, mg.mg_opts_default(**CG), gpu(b), x)
-    assert res.iterations == ks and rel(host(x), xs) <= 1e-10
+    print(f"[cgs] {which} cycles: {res.iterations} (oracle {ks}), rel L2 {rel(host(x), xs):.2e}")
+    assert res.iterations == ks and rel(host(x), xs) <= 1e-12
     x.zero_()
     mg.mg_pcg(P.g.h, mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32, **CG),
               gpu(b), x)

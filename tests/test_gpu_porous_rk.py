@@ -6,12 +6,14 @@ kappa = Delta T y_max / (phi Ra) = 40).
 
 Tolerances: the right-hand side and fixed-step runs follow the pressure solves (rtol 1e-13):
 1e-10 relative.  Short adaptive runs take the oracle's accepted and rejected step counts;
-their states agree to 1e-9 relative.  The full-size run to t = 0.5 is compared as the paper
-does, by the RMSE against the direct-solve trajectory at ten save times: over 1,300 steps
-near the explicit stability limit the two step sequences part at a rejection or two, so the
-states differ at the level of the integration tolerance; the bar is the RMSE the paper reports
-for its own multigrid run, 2.54e-6 (Table pc-comparisons), and the accepted step counts agree
-to 1%."""
+their states agree to 1e-9 relative and their smallest steps to 1e-7 relative (the error
+estimate is a small difference of stage rates, so pressure solves that agree to 1e-13 move the
+chosen steps by a few 1e-8).  The full-size run to t = 0.5 is compared as the paper does, by
+the RMSE against the direct-solve trajectory at ten save times: over 1,300 steps near the
+explicit stability limit the two step sequences part at a rejection or two, so the states
+differ at the level of the integration tolerance; the bar is the integrator's absolute
+tolerance, 1e-6 (the paper reports 2.54e-6 for its own multigrid run, Table pc-comparisons,
+printed beside it as context), and the accepted step counts agree to 1%."""
 import numpy as np
 import pytest
 
@@ -126,8 +128,8 @@ def test_adaptive_small(small):
     assert (st.accepted, st.rejected, st.rhs_evals) == (sto["accepted"], sto["rejected"],
                                                         sto["rhs_evals"])
     # the error estimate is a small difference of stage rates, so pressure solves that agree
-    # to 1e-13 move the chosen step sizes by far more than that (still far below 1e-5)
-    assert abs(st.h_min - sto["h_min"]) <= 1e-5 * sto["h_min"]
+    # to 1e-13 move the chosen step sizes by far more than that (a few 1e-8)
+    assert abs(st.h_min - sto["h_min"]) <= 1e-7 * sto["h_min"]
     assert st.t == 0.05
     assert rel(host(Te), yo) <= 1e-9
     for i in range(len(t_save)):
@@ -181,7 +183,8 @@ def test_e4_full_run_rmse_over_time(full):
     G = host(Ts)
     rmse = [float(np.sqrt(np.mean((G[i] - so[i]) ** 2))) for i in range(len(ts))]
     print("[porous-rk] RMSE vs the direct-solve trajectory: " +
-          ", ".join(f"t={t:.2f}: {r:.2e}" for t, r in zip(ts, rmse)), flush=True)
+          ", ".join(f"t={t:.2f}: {r:.2e}" for t, r in zip(ts, rmse)) +
+          " (the paper's multigrid run: 2.54e-6, Table pc-comparisons)", flush=True)
     assert st.t == E["t_end"] and abs(st.accepted - sto["accepted"]) <= 0.01 * sto["accepted"]
-    assert max(rmse) <= 2.54e-6   # the paper's multigrid run (Table pc-comparisons)
+    assert max(rmse) <= E["atol"]   # 1e-6
     assert np.array_equal(host(Te), G[-1])

@@ -5,10 +5,14 @@ Tolerances (relative L2):
 * the edge kernels alone (buoyancy, flux, advection, diffusion and their transposes), fed the
   GPU's own pressure and adjoint pressure: 1e-14 (summation order only); the adjoint is run
   at dt = 1 there, so that its increment is not hidden under the rounding of lambda;
-* the same algorithm: against the oracle's MG-PCG pressure solves at the same rtol (1e-13),
-  with equal iteration counts: the rate dT/dt, the pressure, the adjoint step, the 12-step
-  rollout gradient and the full C5 gradient to 1e-12.  (The step increment T' - T itself is
-  ~1e-5 of T, so its rounding alone is ~1e-11 of it: the rate is compared instead);
+* the same algorithm: against the oracle's MG-PCG pressure solves at the same rtol (1e-13;
+  1e-12 on the full C5 mesh), with equal iteration counts: the rate dT/dt, the pressure, the
+  adjoint lambda, the loss and dJ/dT0 to 1e-12.  The coefficient gradients (dJ/dk, dJ/dg) are
+  products with the Darcy flux q = -k (d0 p - b1), which cancels: |d0 p| / |q| ~ 91 on these
+  near-conductive fields, so the pressures' rounding reaches them multiplied by that factor;
+  their bar is 1e-12 times it (measured: 7e-13 for one step, 1.1e-11 over the 200 C5 steps).
+  (The step increment T' - T itself is ~1e-5 of T, so its rounding alone is ~1e-11 of it: the
+  rate is compared instead);
 * against the oracle's exact (direct) solves: pressure and step increment 1e-10, adjoint and
   rollout gradients 1e-9 (the solve tolerance times the operator's condition number bounds
   the gap);
@@ -76,6 +80,12 @@ class PorousPair:
                                        rtol=1e-13)
         self.T0 = W.c5_initial_temperature(self.o.fine.xyz)
         mg.mg_hierarchy_set_vertex_coeff(self.g.h, torch.exp(self.g_gpu))
+        # cancellation in the Darcy flux q = -k (d0 p - b1): |d0 p| / |d0 p - b1| at T0 (~91
+        # for these fields).  Gradients with respect to the coefficient are products with q, so
+        # the pressures' rounding reaches them multiplied by this factor.
+        p, b1 = self.model.pressure(self.T0)
+        d0p = self.model.d0 @ p
+        self.kappa_q = float(np.linalg.norm(d0p) / np.linalg.norm(d0p - b1))
 
     def prm(self, rtol=1e-13):
         return mg.porous_params_make(RA, PHI, self.dt, mg.mg_opts_default(rtol=rtol))
@@ -185,8 +195,9 @@ def test_porous_adjoint_same_algorithm(which, request):
     mg.porous_step_adjoint(P.g.h, P.prm(), T, None, gpu(lam0), lo, gk)
     lr, gr = P.model_mg.step_adjoint(P.T0, lam0)
     el, eg = rel(host(lo) - lam0, lr - lam0), rel(host(gk), gr)
-    print(f"[porous] {which} adjoint, same algorithm: rel dlambda {el:.2e}, rel dJ/dk {eg:.2e}")
-    assert el <= 1e-12 and eg <= 1e-12
+    print(f"[porous] {which} adjoint, same algorithm: rel dlambda {el:.2e}, rel dJ/dk {eg:.2e} "
+          f"(flux cancellation {P.kappa_q:.0f})")
+    assert el <= 1e-12 and eg <= 1e-12 * P.kappa_q
 
 
 def test_porous_conductive_state(p65):
@@ -254,7 +265,7 @@ def test_rollout_gradient_matches_oracle(p65):
     ej, eg, eT = abs(Jg.item() - J) / abs(J), rel(host(g.grad), gg), rel(host(T0.grad), gT)
     print(f"[porous] rollout {steps} steps, same algorithm: rel J {ej:.2e}, rel dJ/dg {eg:.2e}, "
           f"rel dJ/dT0 {eT:.2e}")
-    assert ej <= 1e-12 and eg <= 1e-12 and eT <= 1e-12
+    assert ej <= 1e-12 and eT <= 1e-12 and eg <= 1e-12 * p65.kappa_q
 
 
 def test_rollout_finite_differences(p25):
@@ -350,7 +361,7 @@ def test_c5_fullsize_gradient():
     oracle's discrete adjoint."""
     P = PorousPair(W.C5["base_cells"], W.C5["nsub"])
     # rtol 1e-12 on this mesh: 1e-13 is below the attainable true residual of its pressure
-    # solves (they would run to max_iter), in the library and in the oracle alike
+    # solves (they would run to max_iter, in the library and in the oracle alike)
     P.model_mg.rtol = 1e-12
     steps, ckpt = W.C5["steps"], W.C5["ckpt"]
     w = W.c5_loss_weights(P.nv)
@@ -372,6 +383,6 @@ def test_c5_fullsize_gradient():
     J, gg, gT = P.model_mg.loss_and_grad(P.T0, w, steps, ckpt)
     ej, eg, eT = abs(Jg.item() - J) / abs(J), rel(host(g.grad), gg), rel(host(T0.grad), gT)
     print(f"[porous] C5 full, same algorithm: rel J {ej:.2e}, rel dJ/dg {eg:.2e}, "
-          f"rel dJ/dT0 {eT:.2e}")
-    assert ej <= 1e-12 and eg <= 1e-12 and eT <= 1e-12
+          f"rel dJ/dT0 {eT:.2e} (flux cancellation {P.kappa_q:.0f})")
+    assert ej <= 1e-12 and eT <= 1e-12 and eg <= 1e-12 * P.kappa_q
     P.g.close()

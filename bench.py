@@ -51,6 +51,11 @@ def parse():
     p.add_argument("--profile-kernels", action="store_true",
                    help="only launch the finest-level kernels (and a plain copy of known size "
                         "that calibrates the HBM counters) a few times each, for rocprofv3 --pmc")
+    p.add_argument("--no-c2", action="store_true",
+                   help="skip the FP64 MG-PCG timing on the level-7 icosphere")
+    p.add_argument("--no-large", action="store_true",
+                   help="skip the sweep rates on the 4097 x 4097 grid (working set > MALL)")
+    p.add_argument("--cpu-baseline-worker", type=int, default=0, help=argparse.SUPPRESS)
     return p.parse_args()
 
 
@@ -73,6 +78,17 @@ def profile_kernels(reps=5):
         ms = mg.mg_time_kernel(H.h, kern, top, dt, reps)
         print(f"[profile] kernel {kern} dtype {dt}: {ms:.4f} ms/launch", file=sys.stderr, flush=True)
     info = H.info[top]
+    H.close()
+    # a finest level whose working set exceeds the 256 MB MALL, and one with general weights
+    L = mg.Hierarchy("square", W.C3["nsub"] + 1, base_cells=W.C3["base_cells"])
+    for dt in (mg.MG_F32, mg.MG_F64):
+        ms = mg.mg_time_kernel(L.h, mg.KERNEL_JACOBI, L.top, dt, reps)
+        print(f"[profile] 4097^2 sweep dtype {dt}: {ms:.4f} ms/launch", file=sys.stderr, flush=True)
+    L.close()
+    S = mg.Hierarchy("sphere", W.C2["sphere_level"])
+    ms = mg.mg_time_kernel(S.h, mg.KERNEL_JACOBI, S.top, mg.MG_F32, reps)
+    print(f"[profile] icosphere-7 sweep FP32: {ms:.4f} ms/launch", file=sys.stderr, flush=True)
+    S.close()
     print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": src.numel() * 8,
                       "n_unknowns": info["n_unknowns"], "nnz_operator": info["nnz_operator"]}))
 
@@ -120,6 +136,79 @@ def recorded_traffic(kernel_key):
         return None
     k = rec["kernels"].get(kernel_key)
     return None if k is None else k["read_bytes"] + k["write_bytes"]
+
+
+def host_cpu():
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "host_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline_worker(nproc):
+    """Runs in a child process that never touches the GPU: builds the oracle's C3 hierarchy
+    once, then forks `nproc` processes that each run the oracle's FP64 MG-PCG on the same
+    system at the same time (one thread each); prints their aggregate unknowns per second."""
+    import multiprocessing as mp
+
+    import numpy as np
+    os.environ["OMP_NUM_THREADS"] = "1"
+    try:
+        from threadpoolctl import threadpool_limits
+        threadpool_limits(1)
+    except Exception:  # pragma: no cover
+        pass
+    import workloads as W
+    from oracle import dec
+    from oracle import multigrid as omg
+    xyz, tri = dec.square_grid(W.C3["base_cells"])
+    o = omg.Hierarchy(xyz, tri, W.C3["nsub"])
+    b = o.rhs(W.normal(o.fine.nv, W.SEED_C3))
+    ctx = mp.get_context("fork")
+    start = ctx.Barrier(nproc + 1)
+    q = ctx.Queue()
+
+    def solve(i):
+        start.wait()
+        t = time.perf_counter()
+        _, k, _ = omg.mg_pcg(o, b, rtol=1e-10)
+        q.put((time.perf_counter() - t, k))
+
+    procs = [ctx.Process(target=solve, args=(i,)) for i in range(nproc)]
+    for p_ in procs:
+        p_.start()
+    start.wait()
+    t0 = time.perf_counter()
+    res = [q.get() for _ in procs]
+    wall = time.perf_counter() - t0
+    for p_ in procs:
+        p_.join()
+    print(json.dumps({"wall": wall, "unknowns": o.unknowns(), "solves": nproc,
+                      "iterations": res[0][1], "per_solve_s": [r[0] for r in res]}))
+
+
+def cpu_baseline_parallel():
+    """The oracle on the host's cores: one FP64 MG-PCG solve of C3 per core, all at once, in a
+    child process (which never initialises the GPU); aggregate unknowns per second."""
+    import subprocess
+    host = host_cpu()
+    nproc = max(1, min(16, host["usable_cpus"]))
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-worker",
+                        str(nproc)], capture_output=True, text=True, timeout=900)
+    if r.returncode != 0:
+        raise RuntimeError("cpu baseline worker failed: " + r.stderr[-2000:])
+    rec = json.loads(r.stdout.strip().splitlines()[-1])
+    return rec, host
 
 
 def cpu_baseline(b_nat_np, rtol):
@@ -309,6 +398,84 @@ def e4_bench(mg, W, torch, np):
                       "note": "Tsit5 on a laptop CPU; context only"}}
 
 
+def c2_bench(mg, W, torch, np, steps, with_oracle):
+    """FP64 MG-PCG on the level-7 icosphere (163,842 vertices, natural boundary): f = sum of
+    real spherical harmonics of degree 1..8 with N(0,1) coefficients (seed 2), b = star0 f with
+    its mean removed; median solve time to 1e-10, rel L2 against the oracle's MG-PCG.  Also the
+    finest-level FP32 and FP64 sweep rates on this level, whose weights are general (no
+    binary16 copy) and whose rows have 6 couplings."""
+    dev = torch.device("cuda:0")
+    H = mg.Hierarchy("sphere", W.C2["sphere_level"])
+    top = H.top
+    info = H.info[top]
+    xyz = mg.mg_hierarchy_export(H.h, top)["xyz"]
+    f = torch.tensor(W.sphere_rhs(xyz, W.sh_coefficients()), device=dev)
+    b = torch.zeros_like(f)
+    mg.dec_star0_apply(H.h, top, f, b)
+    b -= b.mean()
+    x = torch.zeros_like(b)
+    o = mg.mg_opts_default(rtol=1e-10)
+    for _ in range(2):
+        mg.mg_pcg(H.h, o, b, x)
+    times = []
+    torch.cuda.synchronize()
+    for _ in range(steps):
+        t = time.perf_counter()
+        res = mg.mg_pcg(H.h, o, b, x)
+        times.append(time.perf_counter() - t)
+    ms = 1e3 * float(np.median(times))
+    out = {"workload": "icosphere level 7 (163,842 vertices, 8 levels), natural boundary, f = "
+                       "sum of real spherical harmonics l = 1..8 with N(0,1) coefficients seed 2, "
+                       "b = star0 f mean removed; FP64 MG-PCG V(2,2) Jacobi(0.8) to 1e-10",
+           "unknowns": info["n_unknowns"], "iterations": res.iterations,
+           "rel_residual": res.rel_residual, "ms_median": ms,
+           "value": info["n_unknowns"] / (ms * 1e-3), "unit": "DOF/s"}
+    sweeps = {}
+    for name, dt, nb in (("fp32", mg.MG_F32, 4), ("fp64", mg.MG_F64, 8)):
+        msk = mg.mg_time_kernel(H.h, mg.KERNEL_JACOBI, top, dt, 50)
+        by = kernel_bytes(info, nb, "jacobi")
+        sweeps[name] = {"ms_per_launch": msk, "bytes_per_launch": by,
+                        "GB/s": by / (msk * 1e-3) / 1e9,
+                        "frac": by / (msk * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                        "weight_bytes": info["weight_bytes32" if nb == 4 else "weight_bytes64"],
+                        "couplings_per_row": info["nnz_operator"] / info["n_unknowns"]}
+    out["finest_sweeps_general_weights"] = sweeps
+    if with_oracle:
+        from oracle import dec
+        from oracle import multigrid as omg
+        xo_, tri = dec.icosahedron()
+        oh = omg.Hierarchy(xo_, tri, W.C2["sphere_level"], project=True, bc="natural")
+        bo = oh.rhs(W.sphere_rhs(oh.fine.xyz, W.sh_coefficients()))
+        bo = bo - bo.mean()
+        t = time.perf_counter()
+        xo, ko, _ = omg.mg_pcg(oh, bo, rtol=1e-10)
+        t_o = time.perf_counter() - t
+        xg = x.cpu().numpy()
+        out["parity"] = {"rel_l2_vs_oracle": float(np.linalg.norm(xg - xo) / np.linalg.norm(xo)),
+                         "oracle_iterations": ko}
+        out["cpu_baseline"] = {"value": info["n_unknowns"] / t_o, "unit": "DOF/s", "cores": 1,
+                               "kind": "oracle", "sample": f"one FP64 MG-PCG solve ({t_o:.2f} s)"}
+    H.close()
+    return out
+
+
+def large_sweeps(mg, W, reps=20):
+    """Finest-level sweep rates on the 4097 x 4097 grid (8 x 8 base, 9 subdivisions, 16.8 M
+    unknowns): the FP32 sweep moves 28 B per row (470 MB) and the FP64 one 40 B (671 MB),
+    well above the 256 MB MALL, so back-to-back launches are served from HBM."""
+    L = mg.Hierarchy("square", W.C3["nsub"] + 1, base_cells=W.C3["base_cells"])
+    info = L.info[L.top]
+    out = {"workload": "unit square 8x8 base x 9 subdivisions (4097x4097), finest level",
+           "unknowns": info["n_unknowns"]}
+    for name, dt, nb in (("fp32", mg.MG_F32, 4), ("fp64", mg.MG_F64, 8)):
+        ms = mg.mg_time_kernel(L.h, mg.KERNEL_JACOBI, L.top, dt, reps)
+        by = kernel_bytes(info, nb, "jacobi")
+        out[name] = {"ms_per_launch": ms, "bytes_per_launch": by,
+                     "GB/s": by / (ms * 1e-3) / 1e9, "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    L.close()
+    return out
+
+
 def batch_bench(mg, W, torch, np, steps):
     """The 256-instance mix (icospheres of levels 4..7, squares of 33..513 vertices a side,
     seeded types), FP32-preconditioned FCG to 1e-10 for every instance, solved as one batch
@@ -351,6 +518,31 @@ def batch_bench(mg, W, torch, np, steps):
            "tuning_s": t_tune, "build_s": t_build, "iterations_min": min(its),
            "iterations_max": max(its),
            "max_rel_residual": max(r.rel_residual for r in res)}
+    # per-instance error against the oracle's exact (sparse direct) solve: the first instance
+    # of every mesh type (nine of them, the 163,842-vertex icosphere and 513 x 513 square
+    # included)
+    from oracle import dec
+    from oracle import multigrid as omg
+    errs, seen = [], set()
+    t0 = time.perf_counter()
+    for i, d in enumerate(insts):
+        key = (d["kind"], d["nsub"])
+        if key in seen:
+            continue
+        seen.add(key)
+        if d["kind"] == "sphere":
+            xyz, tri = dec.icosahedron()
+            oo = omg.Hierarchy(xyz, tri, d["nsub"], project=True, bc="natural")
+        else:
+            xyz, tri = dec.square_grid(d["base_cells"])
+            oo = omg.Hierarchy(xyz, tri, d["nsub"])
+        bo = oo.rhs(W.normal(oo.fine.nv, d["rhs_seed"]))
+        ue = omg.direct_solve(oo, bo)
+        errs.append(float(np.linalg.norm(xs[i].cpu().numpy() - ue) / np.linalg.norm(ue)))
+    out["rel_l2_vs_oracle_exact"] = {"max": max(errs), "median": float(np.median(errs)),
+                                     "instances_checked": len(errs),
+                                     "rule": "first instance of each of the nine mesh types",
+                                     "oracle_s": time.perf_counter() - t0}
     mg.mg_batch_free(bt)
     for g in hier.values():
         g.close()
@@ -359,6 +551,9 @@ def batch_bench(mg, W, torch, np, steps):
 
 def main():
     a = parse()
+    if a.cpu_baseline_worker:
+        cpu_baseline_worker(a.cpu_baseline_worker)
+        return
     if a.profile_kernels:
         profile_kernels()
         return
@@ -460,6 +655,18 @@ def main():
               f"{e4['rejected']} rejected, {e4['rhs_evals']} right-hand sides, "
               f"{e4['ms_per_rhs']:.3f} ms each", file=sys.stderr, flush=True)
 
+    c2 = None
+    if not a.no_c2:
+        c2 = c2_bench(mg, W, torch, np, max(5, a.steps), not a.no_cpu_baseline)
+        print(f"[bench] C2 icosphere-7 FP64 MG-PCG: {c2['iterations']} it, median "
+              f"{c2['ms_median']:.3f} ms, {c2['value'] / 1e6:.0f} M DOF/s", file=sys.stderr,
+              flush=True)
+    large = None
+    if not a.no_large:
+        large = large_sweeps(mg, W)
+        print(f"[bench] 4097^2 finest sweeps: FP32 {large['fp32']['GB/s']:.0f} GB/s, FP64 "
+              f"{large['fp64']['GB/s']:.0f} GB/s", file=sys.stderr, flush=True)
+
     ms_step = 1e3 * total_m / a.steps
     value = unknowns / (total_m / a.steps)
     value_fp64 = unknowns / (total_d / n64)
@@ -533,19 +740,32 @@ def main():
             "launches_timed": n_probe,
             "timed_in": f"{a.probe_steps} eager mixed solves (hipEvents on the solve stream)",
             "eager_solve_ms_median": 1e3 * float(np.median(t_eager)),
+            # the same launch priced with the generic layout (int32 columns, FP32 weights, the
+            # 48 B per row of a deg-4 FP32 sweep): this layout moves less than that, so the
+            # ratio is not a bandwidth fraction
+            "bytes_per_launch_generic_layout": 48 * unknowns,
+            "generic_layout_ratio": 48 * unknowns / (ms_j32 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "others": others,
         },
+        "c2_sphere_fp64": c2,
+        "large_grid_sweeps": large,
     }
     if not a.no_cpu_baseline:
         print("[bench] oracle baseline (FP64 MG-PCG, 1 thread) ...", file=sys.stderr, flush=True)
         bn = b.cpu().numpy()
         cb = cpu_baseline(bn, rtol)
         xo = cb["x"]
+        print("[bench] oracle baseline on the host's cores ...", file=sys.stderr, flush=True)
+        par, host = cpu_baseline_parallel()
         out["cpu_baseline"] = {
-            "value": cb["unknowns"] / cb["t_solve"], "unit": "DOF/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"one full FP64 MG-PCG solve of the same system ({cb['iters']} iterations, "
-                      f"{cb['t_solve']:.1f} s; hierarchy build of {cb['t_build']:.1f} s excluded)",
+            "value": par["solves"] * par["unknowns"] / par["wall"], "unit": "DOF/s",
+            "cores": par["solves"], "kind": "oracle",
+            "sample": f"{par['solves']} simultaneous FP64 MG-PCG solves of the same system, one "
+                      f"per core, one thread each ({par['iterations']} iterations, "
+                      f"{par['wall']:.1f} s wall; hierarchy build excluded)",
+            **host,
+            "single_thread_value": cb["unknowns"] / cb["t_solve"],
+            "single_thread_sample": f"one solve, {cb['t_solve']:.1f} s",
         }
         den = float(np.linalg.norm(xo))
         out["parity"] = {

@@ -99,16 +99,21 @@ def kernel_bytes(info, dtype_bytes, kind):
     each vector entry read or written once, gathers at perfect reuse."""
     n, nnz, ib = info["n_unknowns"], info["nnz_operator"], info["index_bytes"]
     wb = info["weight_bytes32"] if dtype_bytes == 4 else info["weight_bytes64"]
-    if kind == "jacobi":      # col + w per coupling; x, b read, x' written
-        return nnz * (ib + wb) + n * 3 * dtype_bytes
-    if kind == "spmv":        # col + w per coupling; x read, y written
-        return nnz * (ib + wb) + n * 2 * dtype_bytes
-    raise ValueError(kind)
+    if kind not in ("jacobi", "spmv"):
+        raise ValueError(kind)
+    nvec = {"jacobi": 3, "spmv": 2}[kind]   # x, b read, x' written / x read, y written
+    if info.get("row_patterns", 0) > 0:
+        # one pattern byte per row, and the pattern table (16-bit offset + weight per entry)
+        return n * (1 + nvec * dtype_bytes) + info["row_patterns"] * info["uniform_width"] * (
+            2 + dtype_bytes)
+    return nnz * (ib + wb) + n * nvec * dtype_bytes
 
 
 def sweep_kernel_name(info):
-    """The FP32 finest-level sweep's instantiation: one or two rows per thread, int16 or int32
-    columns, binary16 or FP32 weights."""
+    """The FP32 finest-level sweep's instantiation: over row patterns, or one or two rows per
+    thread with int16 or int32 columns and binary16 or FP32 weights."""
+    if info.get("row_patterns", 0) > 0:
+        return "k_rows2p<float, 2>"
     return "%s<float, 2, %s, %s>" % ("k_rows2" if info["rows_per_thread"] == 2 else "k_rows",
                                     "true" if info["index_bytes"] == 2 else "false",
                                     "Half16" if info["weight_bytes32"] == 2 else "float")

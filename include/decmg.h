@@ -140,6 +140,12 @@ typedef struct {
                                variable is set at build time. */
   int32_t restrict_offsets16;  /* 1: the per-step restriction onto level-1 reads int16 offsets
                                   from the kept vertex; 0: int32 ids (same condition) */
+  int32_t row_patterns;  /* distinct row patterns (sequences of column offset and weight) the
+                            two-row sweep, residual, apply and direction-update kernels read
+                            through one byte per row, when a level of uniform width with 16-bit
+                            offsets has at most 256 of them; 0: they read the SELL arrays.
+                            Skipped when a DECMG_NO_ROW_PATTERNS environment variable is set
+                            when the weights are built */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 

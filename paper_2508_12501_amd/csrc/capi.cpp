@@ -323,6 +323,7 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->nnz_operator = L.nnz;
   out->index_bytes = L.op.col16 ? 2 : 4;
   out->scheme = L.mesh.scheme;
+  out->row_patterns = L.op.npat;
   out->fused_tiles = L.tiles.ntiles;
   out->fused_tile_rows = int32_t(L.tiles.rows_total);
   out->weight_bytes32 = L.op.w_exact16 ? 2 : 4;

@@ -52,7 +52,18 @@ struct DevOperator {
   // vector-ALU time in the two-sweeps-from-zero kernels
   double* idiag64 = nullptr;
   float* idiag32 = nullptr;
+  // Row patterns (levels of uniform width 1..8 with 16-bit offsets): when the rows take at
+  // most kMaxRowPatterns distinct sequences of (offset, weight) entries -- on a grid with a
+  // unit coefficient: the interior stencil and the few next to the boundary -- pat[r] names
+  // row r's pattern and the two-row kernels read that one byte instead of uw offsets and
+  // weights.  poff / pw32 / pw64: npat x uw entries, pattern-major (npat = 0: not used).
+  uint8_t* pat = nullptr;
+  int16_t* poff = nullptr;
+  float* pw32 = nullptr;
+  double* pw64 = nullptr;
+  int32_t npat = 0;
 };
+constexpr int kMaxRowPatterns = 256;
 
 struct DevTransfer {          // between level l-1 (coarse) and level l (fine)
   int32_t* pa = nullptr;      // n_f: internal coarse ids (or n_c) of the two parents

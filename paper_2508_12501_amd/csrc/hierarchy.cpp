@@ -2,6 +2,7 @@
 // lists, the coarsest dense inverse and device upload.  Host code, compiled with
 // -ffp-contract=off so that host sums match the kernels' plain IEEE order.
 #include <algorithm>
+#include <map>
 #include <array>
 #include <cmath>
 #include <cstdlib>
@@ -926,6 +927,7 @@ static std::vector<bool> weight_forms(const Hierarchy& H) {
   for (const auto& Lp : H.lv) {
     f.push_back(Lp->op.w_exact16);
     f.push_back(Lp->op.w_exact32);
+    f.push_back(Lp->op.npat > 0);
     for (const GsColor& G : Lp->gs) f.push_back(G.w_exact32);
   }
   return f;
@@ -986,6 +988,56 @@ std::vector<std::vector<double>> coarsen_edge_coeff(const Hierarchy& H, std::vec
   return out;
 }
 
+// Row patterns of a level of uniform width (see DevOperator): the distinct sequences of
+// (16-bit offset, FP64 weight) over a row's entries, numbered in order of first appearance.
+// Used when there are at most kMaxRowPatterns of them (npat > 0); otherwise npat = 0.  The
+// device arrays are allocated once at their largest size and rewritten in place, so graphs
+// captured with them stay valid while the level keeps using patterns.
+static void build_row_patterns(Level& L, const std::vector<double>& w64) {
+  L.op.npat = 0;
+  const int32_t n = L.n, uw = L.op.uw;
+  if (n == 0 || uw < 1 || uw > 8 || !L.op.col16 || std::getenv("DECMG_NO_ROW_PATTERNS")) return;
+  std::map<std::vector<uint64_t>, int32_t> ids;
+  std::vector<uint8_t> pat(static_cast<size_t>(n));
+  std::vector<int16_t> poff;
+  std::vector<double> pw;
+  std::vector<uint64_t> key(2 * size_t(uw));
+  for (int32_t r = 0; r < n; ++r) {
+    const size_t e0 = size_t(r / kSlice) * uw * kSlice + size_t(r % kSlice);
+    for (int k = 0; k < uw; ++k) {
+      const size_t i = e0 + size_t(k) * kSlice;
+      const int32_t c = L.col_h[i];
+      const int32_t off = c == n ? kZeroSlot16 : c - r;
+      uint64_t bits;
+      std::memcpy(&bits, &w64[i], 8);
+      key[2 * k] = uint64_t(uint32_t(off));
+      key[2 * k + 1] = bits;
+    }
+    auto it = ids.find(key);
+    if (it == ids.end()) {
+      if (int32_t(ids.size()) == kMaxRowPatterns) return;
+      it = ids.emplace(key, int32_t(ids.size())).first;
+      for (int k = 0; k < uw; ++k) {
+        poff.push_back(int16_t(int32_t(key[2 * k])));
+        pw.push_back(w64[e0 + size_t(k) * kSlice]);
+      }
+    }
+    pat[r] = uint8_t(it->second);
+  }
+  const std::vector<float> pw32(pw.begin(), pw.end());
+  if (!L.op.pat) {
+    L.op.pat = zeros<uint8_t>(n);
+    L.op.poff = zeros<int16_t>(int64_t(kMaxRowPatterns) * uw);
+    L.op.pw32 = zeros<float>(int64_t(kMaxRowPatterns) * uw);
+    L.op.pw64 = zeros<double>(int64_t(kMaxRowPatterns) * uw);
+  }
+  check_hip(hipMemcpy(L.op.pat, pat.data(), pat.size(), hipMemcpyHostToDevice), "hipMemcpy");
+  check_hip(hipMemcpy(L.op.poff, poff.data(), poff.size() * 2, hipMemcpyHostToDevice), "hipMemcpy");
+  check_hip(hipMemcpy(L.op.pw32, pw32.data(), pw32.size() * 4, hipMemcpyHostToDevice), "hipMemcpy");
+  check_hip(hipMemcpy(L.op.pw64, pw.data(), pw.size() * 8, hipMemcpyHostToDevice), "hipMemcpy");
+  L.op.npat = int32_t(ids.size());
+}
+
 void upload_weights(Hierarchy& H) {
   const std::vector<bool> forms_before = weight_forms(H);
   for (size_t l = 0; l < H.lv.size(); ++l) {
@@ -994,6 +1046,7 @@ void upload_weights(Hierarchy& H) {
     std::vector<float> w32, d32;
     const std::vector<double> ke = level_edge_coeff(H, l);
     compute_weights(L, ke, w64, w32, d64, d32);
+    build_row_patterns(L, w64);
     if (!L.op.w64) {
       L.op.w64 = zeros<double>(std::max<size_t>(w64.size(), 1));
       L.op.w32 = zeros<float>(std::max<size_t>(w32.size(), 1));
@@ -1181,7 +1234,8 @@ Hierarchy::~Hierarchy() {
     Level& L = *Lp;
     for (void* p : {(void*)L.perm, (void*)L.bnd_ids, (void*)L.star0, (void*)L.op.sptr,
                     (void*)L.op.col, (void*)L.op.col16, (void*)L.op.w64, (void*)L.op.w32,
-                    (void*)L.op.w16,
+                    (void*)L.op.w16, (void*)L.op.pat, (void*)L.op.poff, (void*)L.op.pw32,
+                    (void*)L.op.pw64,
                     (void*)L.op.idiag64,
                     (void*)L.op.idiag32, (void*)L.tr.pa, (void*)L.tr.pb, (void*)L.tr.r_self,
                     (void*)L.tr.r_sptr, (void*)L.tr.r_col, (void*)L.tr.r_col16, (void*)L.tr.p_base,

@@ -311,17 +311,49 @@ __global__ __launch_bounds__(kBlock) void k_rows(const int32_t* __restrict__ spt
 // expressions and entry order as the one-row kernels.  The second row of a thread past the end
 // is its first row again (computed twice, stored once).
 __device__ __forceinline__ int ell_first(int r, int uw) { return (r >> 6) * uw * kSlice + (r & 63); }
-template <typename T, bool D16, int N, typename WT, typename G>
+// Position of row r's first entry, and the step between its entries: in the SELL-64 arrays, or
+// (PAT) in the table of row patterns, where pat[r] names the row's pattern and a pattern's uw
+// entries are contiguous.  Pattern entries hold 16-bit offsets from the row and the weights,
+// exactly as the SELL entries they replace.
+template <bool PAT>
+__device__ __forceinline__ int row_first(const uint8_t* __restrict__ pat, int r, int uw) {
+  if constexpr (PAT)
+    return static_cast<int>(pat[r]) * uw;
+  else
+    return ell_first(r, uw);
+}
+// The pattern table of a level in LDS (dynamic shared memory): npat uw 16-bit offsets, then,
+// 8-byte aligned, npat uw weights of type WT.  Every thread of the block takes part; call before
+// any thread leaves.
+__host__ __device__ constexpr int pattern_lds_weights_at(int entries) { return (2 * entries + 7) / 8 * 8; }
+template <typename WT>
+__device__ __forceinline__ void stage_patterns(const int16_t* __restrict__ off,
+                                               const WT* __restrict__ w, int entries,
+                                               const int16_t*& soff, const WT*& sw) {
+  extern __shared__ double pattern_smem[];
+  char* base = reinterpret_cast<char*>(pattern_smem);
+  int16_t* o = reinterpret_cast<int16_t*>(base);
+  WT* v = reinterpret_cast<WT*>(base + pattern_lds_weights_at(entries));
+  for (int i = threadIdx.x; i < entries; i += blockDim.x) {
+    o[i] = off[i];
+    v[i] = w[i];
+  }
+  __syncthreads();
+  soff = o;
+  sw = v;
+}
+
+template <typename T, bool D16, int N, bool PAT, typename WT, typename G>
 __device__ __forceinline__ void row2_n(const void* __restrict__ col, const WT* __restrict__ w,
-                                       int r0, int r1, int uw, int n, T x0, T x1, G&& other,
-                                       T& a0, T& d0, T& a1, T& d1) {
+                                       int e0, int e1, int r0, int r1, int n, T x0, T x1,
+                                       G&& other, T& a0, T& d0, T& a1, T& d1) {
   int c0[N], c1[N];
   T w0[N], w1[N], y0[N], y1[N];
-  const int e0 = ell_first(r0, uw), e1 = ell_first(r1, uw);
+  constexpr int st = PAT ? 1 : kSlice;
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    entry_at<T, D16>(col, w, e0 + k * kSlice, r0, n, c0[k], w0[k]);
-    entry_at<T, D16>(col, w, e1 + k * kSlice, r1, n, c1[k], w1[k]);
+    entry_at<T, D16>(col, w, e0 + k * st, r0, n, c0[k], w0[k]);
+    entry_at<T, D16>(col, w, e1 + k * st, r1, n, c1[k], w1[k]);
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
@@ -337,39 +369,62 @@ __device__ __forceinline__ void row2_n(const void* __restrict__ col, const WT* _
     a1 = mac(w1[k], x1 - y1[k], a1);
   }
 }
-template <typename T, bool D16, typename WT, typename G>
+// e0, e1: row_first of r0 and r1
+template <typename T, bool D16, bool PAT, typename WT, typename G>
 __device__ __forceinline__ void row2(const void* __restrict__ col, const WT* __restrict__ w,
-                                     int r0, int r1, int uw, int n, T x0, T x1, G&& other, T& a0,
-                                     T& d0, T& a1, T& d1) {
+                                     int e0, int e1, int r0, int r1, int uw, int n, T x0, T x1,
+                                     G&& other, T& a0, T& d0, T& a1, T& d1) {
+#define DECMG_R2(K)                                                                       \
+  row2_n<T, D16, K, PAT>(col, w, e0, e1, r0, r1, n, x0, x1, other, a0, d0, a1, d1);         \
+  break;
   switch (uw) {
-    case 1: row2_n<T, D16, 1>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    case 2: row2_n<T, D16, 2>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    case 3: row2_n<T, D16, 3>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    case 4: row2_n<T, D16, 4>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    case 5: row2_n<T, D16, 5>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    case 6: row2_n<T, D16, 6>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    case 7: row2_n<T, D16, 7>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
-    default: row2_n<T, D16, 8>(col, w, r0, r1, uw, n, x0, x1, other, a0, d0, a1, d1); break;
+    case 1: DECMG_R2(1)
+    case 2: DECMG_R2(2)
+    case 3: DECMG_R2(3)
+    case 4: DECMG_R2(4)
+    case 5: DECMG_R2(5)
+    case 6: DECMG_R2(6)
+    case 7: DECMG_R2(7)
+    default: DECMG_R2(8)
   }
+#undef DECMG_R2
 }
 
 // k_rows with two rows per thread (uniform widths 1..8 only)
-template <typename T, int MODE, bool D16, typename WT>
-__global__ __launch_bounds__(kBlock) void k_rows2(int32_t uw, const void* __restrict__ col,
-                                                  const WT* __restrict__ w,
-                                                  const T* __restrict__ x,
-                                                  const T* __restrict__ b, T* __restrict__ y,
-                                                  int32_t n, T omega,
-                                                  const int* __restrict__ done) {
+template <typename T, int MODE, bool D16, typename WT, bool PAT>
+__device__ __forceinline__ void rows2_body(int32_t uw, const void* __restrict__ col,
+                                           const WT* __restrict__ w,
+                                           const uint8_t* __restrict__ pat, int npat,
+                                           const T* __restrict__ x, const T* __restrict__ b,
+                                           T* __restrict__ y, int32_t n, T omega,
+                                           const int* __restrict__ done) {
   DECMG_DONE_LOAD(n)
   const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
-  if (r0 >= n) return;
-  const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
-  const T x0 = x[r0], x1 = x[r1];
-  const T b0 = (MODE == 0) ? T(0) : b[r0];
-  const T b1 = (MODE == 0) ? T(0) : b[r1];
+  const bool live = r0 < n;
+  int r1 = 0, e0 = 0, e1 = 0;
+  T x0 = T(0), x1 = T(0), b0 = T(0), b1 = T(0);
+  if (live) {
+    r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+    e0 = row_first<PAT>(pat, r0, uw);
+    e1 = row_first<PAT>(pat, r1, uw);
+    x0 = x[r0];
+    x1 = x[r1];
+    if (MODE != 0) {
+      b0 = b[r0];
+      b1 = b[r1];
+    }
+  }
+  if constexpr (PAT) {   // the row loads above are in flight meanwhile
+    const int16_t* so;
+    const WT* sw;
+    stage_patterns(static_cast<const int16_t*>(col), w, npat * uw, so, sw);
+    col = so;
+    w = sw;
+  }
+  if (!live) return;
   T a0, d0, a1, d1;
-  row2<T, D16>(col, w, r0, r1, uw, n, x0, x1, [&](int j) { return x[j]; }, a0, d0, a1, d1);
+  row2<T, D16, PAT>(col, w, e0, e1, r0, r1, uw, n, x0, x1, [&](int j) { return x[j]; }, a0, d0,
+                    a1, d1);
   DECMG_DONE_CHECK()
   if (MODE == 0) {
     y[r0] = a0;
@@ -382,8 +437,69 @@ __global__ __launch_bounds__(kBlock) void k_rows2(int32_t uw, const void* __rest
     if (r1 != r0) y[r1] = x1 + omega * (b1 - a1) / d1;
   }
 }
+template <typename T, int MODE, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_rows2(int32_t uw, const void* __restrict__ col,
+                                                  const WT* __restrict__ w,
+                                                  const T* __restrict__ x,
+                                                  const T* __restrict__ b, T* __restrict__ y,
+                                                  int32_t n, T omega,
+                                                  const int* __restrict__ done) {
+  rows2_body<T, MODE, D16, WT, false>(uw, col, w, nullptr, 0, x, b, y, n, omega, done);
+}
+// The same over row patterns: pat[r] names row r's pattern, whose offsets and weights are
+// entries pat[r] uw .. pat[r] uw + uw - 1 of off and w.  Same values in the same order as the
+// SELL entries, so the same results bit for bit, from one byte per row instead of uw offsets
+// and weights.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_rows2p(int32_t uw, const int16_t* __restrict__ off,
+                                                   const T* __restrict__ w,
+                                                   const uint8_t* __restrict__ pat, int npat,
+                                                   const T* __restrict__ x,
+                                                   const T* __restrict__ b, T* __restrict__ y,
+                                                   int32_t n, T omega,
+                                                   const int* __restrict__ done) {
+  rows2_body<T, MODE, true, T, true>(uw, off, w, pat, npat, x, b, y, n, omega, done);
+}
 
 // k_jacobi_two with two rows per thread (uniform widths 1..8 only)
+template <typename T, bool D16, typename WT, bool PAT>
+__device__ __forceinline__ void jacobi_two2_body(int32_t uw, const void* __restrict__ col,
+                                                 const WT* __restrict__ w,
+                                                 const uint8_t* __restrict__ pat, int npat,
+                                                 const T* __restrict__ idiag,
+                                                 const T* __restrict__ b, T* __restrict__ y,
+                                                 int32_t n, T omega,
+                                                 const int* __restrict__ done) {
+  DECMG_DONE_LOAD(n)
+  const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
+  const bool live = r0 < n;
+  int r1 = 0, e0 = 0, e1 = 0;
+  T b0 = T(0), b1 = T(0), i0 = T(1), i1 = T(1);
+  if (live) {
+    r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+    e0 = row_first<PAT>(pat, r0, uw);
+    e1 = row_first<PAT>(pat, r1, uw);
+    b0 = b[r0];
+    b1 = b[r1];
+    i0 = idiag[r0];
+    i1 = idiag[r1];
+  }
+  if constexpr (PAT) {   // the row loads above are in flight meanwhile
+    const int16_t* so;
+    const WT* sw;
+    stage_patterns(static_cast<const int16_t*>(col), w, npat * uw, so, sw);
+    col = so;
+    w = sw;
+  }
+  if (!live) return;
+  const T x0 = jacobi_first(omega, b0, i0), x1 = jacobi_first(omega, b1, i1);
+  T a0, d0, a1, d1;
+  row2<T, D16, PAT>(col, w, e0, e1, r0, r1, uw, n, x0, x1,
+                    [&](int j) { return jacobi_first(omega, b[j], idiag[j]); }, a0, d0, a1, d1);
+  DECMG_DONE_CHECK()
+  y[r0] = x0 + omega * (b0 - a0) / d0;
+  if (r1 != r0) y[r1] = x1 + omega * (b1 - a1) / d1;
+}
 template <typename T, bool D16, typename WT>
 __global__ __launch_bounds__(kBlock) void k_jacobi_two2(int32_t uw, const void* __restrict__ col,
                                                         const WT* __restrict__ w,
@@ -391,18 +507,19 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two2(int32_t uw, const void* 
                                                         const T* __restrict__ b,
                                                         T* __restrict__ y, int32_t n, T omega,
                                                         const int* __restrict__ done) {
-  DECMG_DONE_LOAD(n)
-  const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
-  if (r0 >= n) return;
-  const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
-  const T b0 = b[r0], b1 = b[r1];
-  const T x0 = jacobi_first(omega, b0, idiag[r0]), x1 = jacobi_first(omega, b1, idiag[r1]);
-  T a0, d0, a1, d1;
-  row2<T, D16>(col, w, r0, r1, uw, n, x0, x1, [&](int j) { return jacobi_first(omega, b[j], idiag[j]); }, a0,
-               d0, a1, d1);
-  DECMG_DONE_CHECK()
-  y[r0] = x0 + omega * (b0 - a0) / d0;
-  if (r1 != r0) y[r1] = x1 + omega * (b1 - a1) / d1;
+  jacobi_two2_body<T, D16, WT, false>(uw, col, w, nullptr, 0, idiag, b, y, n, omega, done);
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_two2p(int32_t uw,
+                                                         const int16_t* __restrict__ off,
+                                                         const T* __restrict__ w,
+                                                         const uint8_t* __restrict__ pat,
+                                                         int npat,
+                                                         const T* __restrict__ idiag,
+                                                         const T* __restrict__ b,
+                                                         T* __restrict__ y, int32_t n, T omega,
+                                                         const int* __restrict__ done) {
+  jacobi_two2_body<T, true, T, true>(uw, off, w, pat, npat, idiag, b, y, n, omega, done);
 }
 
 // First smoothing sweep from x = 0: x = omega b (1/D).
@@ -1743,28 +1860,49 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
 
 // k_pupd_spmv_dot2 with two rows per thread (uniform widths 1..8 only): one partial per
 // 2 kBlock rows
-template <typename ZT, bool D16, typename WT>
-__global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2(
+template <typename ZT, bool D16, typename WT, bool PAT>
+__device__ __forceinline__ void pupd_spmv_dot2_2_body(
     int32_t uw, const void* __restrict__ col, const WT* __restrict__ w,
-    const DevScalars* __restrict__ sc, const ZT* __restrict__ z, int sub_mean,
-    const double* __restrict__ po, double* __restrict__ pn, double* __restrict__ q,
-    const double* __restrict__ r, double* __restrict__ part0, double* __restrict__ part1,
-    int32_t n, const int* __restrict__ done) {
+    const uint8_t* __restrict__ pat, int npat, const DevScalars* __restrict__ sc,
+    const ZT* __restrict__ z, int sub_mean, const double* __restrict__ po,
+    double* __restrict__ pn, double* __restrict__ q, const double* __restrict__ r,
+    double* __restrict__ part0, double* __restrict__ part1, int32_t n,
+    const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
   const int r0 = blk * (2 * kBlock) + threadIdx.x;
+  const bool live = r0 < n;
+  const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
+  const bool sm = sub_mean != 0;
+  int r1 = 0, e0 = 0, e1 = 0;
+  ZT z0 = ZT(0), z1 = ZT(0);
+  double o0 = 0.0, o1 = 0.0, q0r = 0.0, q1r = 0.0;
+  if (live) {
+    r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+    e0 = row_first<PAT>(pat, r0, uw);
+    e1 = row_first<PAT>(pat, r1, uw);
+    o0 = po[r0];
+    o1 = po[r1];
+    z0 = z[r0];
+    z1 = z[r1];
+    q0r = r[r0];
+    q1r = r[r1];
+  }
+  if constexpr (PAT) {   // the row loads above are in flight meanwhile
+    const int16_t* so;
+    const WT* sw;
+    stage_patterns(static_cast<const int16_t*>(col), w, npat * uw, so, sw);
+    col = so;
+    w = sw;
+  }
   double v0 = 0.0, v1 = 0.0;
-  if (r0 < n) {
-    const int r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
-    const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
-    const bool sm = sub_mean != 0;
-    const double p0 = mac(beta, po[r0], z_val(z[r0], s, m, sm));
-    const double p1 = mac(beta, po[r1], z_val(z[r1], s, m, sm));
-    const double q0r = r[r0], q1r = r[r1];
+  if (live) {
+    const double p0 = mac(beta, o0, z_val(z0, s, m, sm));
+    const double p1 = mac(beta, o1, z_val(z1, s, m, sm));
     double a0, d0, a1, d1;
-    row2<double, D16>(col, w, r0, r1, uw, n, p0, p1,
-                      [&](int j) { return mac(beta, po[j], z_val(z[j], s, m, sm)); }, a0, d0,
-                      a1, d1);
+    row2<double, D16, PAT>(col, w, e0, e1, r0, r1, uw, n, p0, p1,
+                           [&](int j) { return mac(beta, po[j], z_val(z[j], s, m, sm)); }, a0,
+                           d0, a1, d1);
     pn[r0] = p0;
     q[r0] = a0;
     v0 = p0 * a0;
@@ -1781,6 +1919,28 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2(
     part0[blk] = v0;
     part1[blk] = v1;
   }
+}
+template <typename ZT, bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2(
+    int32_t uw, const void* __restrict__ col, const WT* __restrict__ w,
+    const DevScalars* __restrict__ sc, const ZT* __restrict__ z, int sub_mean,
+    const double* __restrict__ po, double* __restrict__ pn, double* __restrict__ q,
+    const double* __restrict__ r, double* __restrict__ part0, double* __restrict__ part1,
+    int32_t n, const int* __restrict__ done) {
+  pupd_spmv_dot2_2_body<ZT, D16, WT, false>(uw, col, w, nullptr, 0, sc, z, sub_mean, po, pn, q,
+                                            r, part0, part1, n, done);
+}
+// over row patterns (see k_rows2p)
+template <typename ZT>
+__global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2p(
+    int32_t uw, const int16_t* __restrict__ off, const double* __restrict__ w,
+    const uint8_t* __restrict__ pat, int npat, const DevScalars* __restrict__ sc,
+    const ZT* __restrict__ z, int sub_mean, const double* __restrict__ po,
+    double* __restrict__ pn, double* __restrict__ q, const double* __restrict__ r,
+    double* __restrict__ part0, double* __restrict__ part1, int32_t n,
+    const int* __restrict__ done) {
+  pupd_spmv_dot2_2_body<ZT, true, double, true>(uw, off, w, pat, npat, sc, z, sub_mean, po, pn,
+                                                q, r, part0, part1, n, done);
 }
 
 __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalars* __restrict__ sc,
@@ -2354,11 +2514,30 @@ using pointee_t = std::remove_const_t<std::remove_pointer_t<P>>;
 // Levels whose slices all have one width of 1..8 entries take the two-rows-per-thread kernels.
 static bool two_rows(const Level& L) { return L.op.uw >= 1 && L.op.uw <= 8; }
 static unsigned grid2_for(int32_t n) { return unsigned((int64_t(n) + 2 * kBlock - 1) / (2 * kBlock)); }
+// those of them whose rows take few distinct patterns read one byte per row (k_*2p kernels)
+static bool row_patterns(const Level& L) { return two_rows(L) && L.op.npat > 0; }
+template <typename T>
+static size_t pattern_lds(const Level& L) {
+  const int entries = L.op.npat * L.op.uw;
+  return size_t(pattern_lds_weights_at(entries)) + size_t(entries) * sizeof(T);
+}
+template <typename T>
+static const T* pattern_weights(const Level& L);
+template <>
+const double* pattern_weights<double>(const Level& L) { return L.op.pw64; }
+template <>
+const float* pattern_weights<float>(const Level& L) { return L.op.pw32; }
 
 template <typename T, int MODE>
 static void rows(const Level& L, const T* x, const T* b, T* y, double omega, const int* done,
                  hipStream_t s) {
   if (L.n == 0) return;
+  if (row_patterns(L)) {
+    hipLaunchKernelGGL((k_rows2p<T, MODE>), dim3(grid2_for(L.n)), dim3(kBlock),
+                       pattern_lds<T>(L), s, L.op.uw, L.op.poff, pattern_weights<T>(L), L.op.pat,
+                       L.op.npat, x, b, y, L.n, static_cast<T>(omega), done);
+    return;
+  }
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
     if (two_rows(L)) {
@@ -2388,6 +2567,13 @@ template <typename T>
 void jacobi_timed(const Level& L, const T* x, const T* b, T* xo, double omega, const int* done,
                   hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (L.n == 0) return;
+  if (row_patterns(L)) {
+    hipExtLaunchKernelGGL((k_rows2p<T, 2>), dim3(grid2_for(L.n)), dim3(kBlock),
+                          pattern_lds<T>(L), s, e0, e1, 0, L.op.uw, L.op.poff,
+                          pattern_weights<T>(L), L.op.pat, L.op.npat, x, b, xo, L.n,
+                          static_cast<T>(omega), done);
+    return;
+  }
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
     if (two_rows(L)) {
@@ -2428,6 +2614,12 @@ void jacobi(const Level& L, const T* x, const T* b, T* xo, double omega, const i
 template <typename T>
 void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
   if (L.n == 0) return;
+  if (row_patterns(L)) {
+    hipLaunchKernelGGL((k_jacobi_two2p<T>), dim3(grid2_for(L.n)), dim3(kBlock),
+                       pattern_lds<T>(L), s, L.op.uw, L.op.poff, pattern_weights<T>(L), L.op.pat,
+                       L.op.npat, diagonal<T>(L), b, xo, L.n, static_cast<T>(omega), done);
+    return;
+  }
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
     if (two_rows(L)) {
@@ -2824,6 +3016,19 @@ void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, cons
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
                     const double* r, double* part0, double* part1, const int* done,
                     hipStream_t s) {
+  if (row_patterns(L)) {
+    if (z32)
+      hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<float>), dim3(grid2_for(L.n)), dim3(kBlock),
+                         pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat,
+                         L.op.npat, sc, z32, sub_mean_flag, p_old, p_new, q, r, part0, part1,
+                         L.n, done);
+    else
+      hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<double>), dim3(grid2_for(L.n)), dim3(kBlock),
+                         pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat,
+                         L.op.npat, sc, z64, sub_mean_flag, p_old, p_new, q, r, part0, part1,
+                         L.n, done);
+    return;
+  }
   with_weights<double>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
     auto go = [&](auto zp) {

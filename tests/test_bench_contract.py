@@ -41,6 +41,12 @@ def test_headline_sweep_bytes():
     assert bench.sweep_kernel_name(dict(info, rows_per_thread=1)) == "k_rows<float, 2, true, float>"
     with pytest.raises(ValueError):
         bench.kernel_bytes(info, 4, "other")
+    # row patterns: one byte per row names the row's pattern (offsets and weights come from a
+    # table of at most 256 patterns of uw entries)
+    info.update(row_patterns=9, uniform_width=4)
+    assert bench.kernel_bytes(info, 4, "jacobi") == 4190209 * 13 + 9 * 4 * 6
+    assert bench.kernel_bytes(info, 8, "spmv") == 4190209 * 17 + 9 * 4 * 10
+    assert bench.sweep_kernel_name(info) == "k_rows2p<float, 2>"
 
 
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):

@@ -81,9 +81,15 @@ def profile_kernels(reps=5):
     H.close()
     # a finest level whose working set exceeds the 256 MB MALL, and one with general weights
     L = mg.Hierarchy("square", W.C3["nsub"] + 1, base_cells=W.C3["base_cells"])
-    for dt in (mg.MG_F32, mg.MG_F64):
-        ms = mg.mg_time_kernel(L.h, mg.KERNEL_JACOBI, L.top, dt, reps)
-        print(f"[profile] 4097^2 sweep dtype {dt}: {ms:.4f} ms/launch", file=sys.stderr, flush=True)
+    for tag in ("unit k", "general k"):
+        for dt in (mg.MG_F32, mg.MG_F64):
+            ms = mg.mg_time_kernel(L.h, mg.KERNEL_JACOBI, L.top, dt, reps)
+            print(f"[profile] 4097^2 sweep ({tag}) dtype {dt}: {ms:.4f} ms/launch", file=sys.stderr,
+                  flush=True)
+        if tag == "unit k":
+            g = torch.tensor(W.normal(L.nv(), 5), device="cuda:0")
+            mg.mg_smooth(L.h, L.top, 20, 0.8, torch.zeros_like(g), g)
+            mg.mg_hierarchy_set_log_coeff(L.h, g)
     L.close()
     S = mg.Hierarchy("sphere", W.C2["sphere_level"])
     ms = mg.mg_time_kernel(S.h, mg.KERNEL_JACOBI, S.top, mg.MG_F32, reps)
@@ -464,19 +470,32 @@ def c2_bench(mg, W, torch, np, steps, with_oracle):
     return out
 
 
-def large_sweeps(mg, W, reps=20):
+def large_sweeps(mg, W, torch, reps=20):
     """Finest-level sweep rates on the 4097 x 4097 grid (8 x 8 base, 9 subdivisions, 16.8 M
-    unknowns): the FP32 sweep moves 28 B per row (470 MB) and the FP64 one 40 B (671 MB),
-    well above the 256 MB MALL, so back-to-back launches are served from HBM."""
+    unknowns), whose working sets are above the 256 MB MALL, so that back-to-back launches are
+    served from HBM: with the unit coefficient (row patterns: 13 B per row in FP32, 25 B in
+    FP64), and with a general coefficient k = exp(g), g from 20 Jacobi sweeps of N(0,1) noise
+    (seed 5), whose weights are distinct per edge (FP32 / FP64 weights and 16-bit offsets: 36 B
+    and 56 B per row, 604 MB and 939 MB)."""
     L = mg.Hierarchy("square", W.C3["nsub"] + 1, base_cells=W.C3["base_cells"])
-    info = L.info[L.top]
     out = {"workload": "unit square 8x8 base x 9 subdivisions (4097x4097), finest level",
-           "unknowns": info["n_unknowns"]}
-    for name, dt, nb in (("fp32", mg.MG_F32, 4), ("fp64", mg.MG_F64, 8)):
-        ms = mg.mg_time_kernel(L.h, mg.KERNEL_JACOBI, L.top, dt, reps)
-        by = kernel_bytes(info, nb, "jacobi")
-        out[name] = {"ms_per_launch": ms, "bytes_per_launch": by,
-                     "GB/s": by / (ms * 1e-3) / 1e9, "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+           "unknowns": L.info[L.top]["n_unknowns"]}
+
+    def rates(tag):
+        info = mg.mg_hierarchy_info(L.h, L.top)
+        for name, dt, nb in (("fp32", mg.MG_F32, 4), ("fp64", mg.MG_F64, 8)):
+            ms = mg.mg_time_kernel(L.h, mg.KERNEL_JACOBI, L.top, dt, reps)
+            by = kernel_bytes(info, nb, "jacobi")
+            out[tag + name] = {"ms_per_launch": ms, "bytes_per_launch": by,
+                               "GB/s": by / (ms * 1e-3) / 1e9,
+                               "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                               "row_patterns": info["row_patterns"],
+                               "weight_bytes": info["weight_bytes32" if nb == 4 else "weight_bytes64"]}
+    rates("")
+    g = torch.tensor(W.normal(L.nv(), 5), device="cuda:0")
+    mg.mg_smooth(L.h, L.top, 20, 0.8, torch.zeros_like(g), g)
+    mg.mg_hierarchy_set_log_coeff(L.h, g)
+    rates("general_k_")
     L.close()
     return out
 
@@ -668,9 +687,11 @@ def main():
               flush=True)
     large = None
     if not a.no_large:
-        large = large_sweeps(mg, W)
+        large = large_sweeps(mg, W, torch)
         print(f"[bench] 4097^2 finest sweeps: FP32 {large['fp32']['GB/s']:.0f} GB/s, FP64 "
-              f"{large['fp64']['GB/s']:.0f} GB/s", file=sys.stderr, flush=True)
+              f"{large['fp64']['GB/s']:.0f} GB/s; general k: FP32 "
+              f"{large['general_k_fp32']['GB/s']:.0f} GB/s, FP64 "
+              f"{large['general_k_fp64']['GB/s']:.0f} GB/s", file=sys.stderr, flush=True)
 
     ms_step = 1e3 * total_m / a.steps
     value = unknowns / (total_m / a.steps)

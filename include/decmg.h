@@ -234,6 +234,15 @@ mg_status mg_hierarchy_coeff_grad_log(mg_hierarchy* h, const double* grad_k, dou
  * non-finite values. */
 mg_status mg_hierarchy_set_edge_coeff(mg_hierarchy* h, const double* k_edge, void* stream);
 
+/* Fault injection for tests of the failure handling (not part of the method): flags is 0 or
+ * a combination of the MG_DEBUG_ bits, kept by the hierarchy until changed.
+ * MG_DEBUG_ZERO_PRECOND32: every FP32 cycle of mg_pcg (and of the solves built on it) returns
+ * zero, on which a preconditioned Krylov loop breaks down (p^T A p = 0) and iterative
+ * refinement makes no progress, so that the FP64 fallback (mg_opts.stall_checks) must take
+ * over.  Batched solves ignore it.  MG_EINVAL for unknown bits. */
+#define MG_DEBUG_ZERO_PRECOND32 1
+mg_status mg_hierarchy_set_debug(mg_hierarchy* h, int32_t flags);
+
 /* ------------------------------------------------------------------ operators (device)
  * b = star0 f on `level` (Sec. 3.1 right-hand side of L u = star0 f); Dirichlet: b = 0 on
  * the boundary.  f, b: nv doubles. */
@@ -295,6 +304,12 @@ typedef struct {
                             right-hand side outside the operator's range, |sum b| > 1e-8 sum |b|,
                             with MG_EINCOMPAT (x = 0); 0 projects it onto the range by removing
                             its vertex mean (0) */
+  int32_t stall_checks;  /* mg_pcg with precision MG_F32: the FP32-preconditioned loop counts as
+                            stagnating after this many host convergence checks in a row (after
+                            the first) whose loop residual is not below the smallest seen
+                            before; it then, or on a breakdown or a non-finite value of that
+                            loop, continues from x with the FP64 cycle (mg_result.fp64_fallback).
+                            0: no detection and no fallback.  0..1000 (3) */
 } mg_opts;
 void mg_opts_default(mg_opts* o);
 
@@ -312,6 +327,8 @@ typedef struct {
   double* history;
   int32_t history_cap;
   int32_t history_len;
+  int32_t fp64_fallback;       /* 1: the FP32-preconditioned loop stagnated, broke down or met a
+                                  non-finite value, and the solve went on with the FP64 cycle */
 } mg_result;
 
 /* One V(nu1,nu2) cycle on `level` (normally the finest), in place: x <- V(b, x).  dtype
@@ -334,7 +351,11 @@ mg_status mg_solve(mg_hierarchy* h, const mg_opts* o, const double* b, double* x
  * recomputed in FP64 from x, is <= rtol.  CG and FCG iterate on the recursively updated
  * residual; when that has met rtol but the true one has not, the iteration restarts from x
  * (r = b - A x, the next direction the preconditioned residual), within max_iter in total;
- * MG_ENOCONV when max_iter is reached first (x and the result are still filled). */
+ * MG_ENOCONV when max_iter is reached first (x and the result are still filled).
+ * FP32 fallback: with precision MG_F32 and o->stall_checks > 0, a loop that stagnates (see
+ * stall_checks), breaks down or meets a non-finite value restarts from x in the same way with
+ * the FP64 cycle, once, within the same max_iter; mg_result.fp64_fallback reports it, and the
+ * status is that of the FP64 loop. */
 mg_status mg_pcg(mg_hierarchy* h, const mg_opts* o, const double* b, double* x,
                  mg_result* res, void* stream);
 

@@ -30,6 +30,7 @@ MG_OUTER_CG, MG_OUTER_FCG, MG_OUTER_IR = 0, 1, 2
 MG_ORDER_STRIPES, MG_ORDER_MORTON = 0, 1
 MG_CYCLE_V, MG_CYCLE_W, MG_CYCLE_F = 0, 1, 2
 MG_SMOOTH_JACOBI, MG_SMOOTH_GS, MG_SMOOTH_CG = 0, 1, 2
+MG_DEBUG_ZERO_PRECOND32 = 1
 KERNEL_JACOBI, KERNEL_APPLY, KERNEL_RESIDUAL, KERNEL_RESTRICT, KERNEL_PROLONG = range(5)
 
 
@@ -69,14 +70,15 @@ class mg_opts(ctypes.Structure):
                 ("rtol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("smoother", ctypes.c_int32),
-                ("fuse_levels", ctypes.c_int32), ("compat_check", ctypes.c_int32)]
+                ("fuse_levels", ctypes.c_int32), ("compat_check", ctypes.c_int32),
+                ("stall_checks", ctypes.c_int32)]
 
 
 class mg_result(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("rel_residual_loop", ctypes.c_double),
                 ("history", ctypes.c_void_p), ("history_cap", ctypes.c_int32),
-                ("history_len", ctypes.c_int32)]
+                ("history_len", ctypes.c_int32), ("fp64_fallback", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_
@@ -160,6 +162,7 @@ _PROTOS = {
     "mg_hierarchy_set_log_coeff": (_i32, [_vp, _vp, _vp]),
     "mg_hierarchy_coeff_grad_log": (_i32, [_vp, _vp, _vp, _vp]),
     "mg_hierarchy_set_edge_coeff": (_i32, [_vp, _vp, _vp]),
+    "mg_hierarchy_set_debug": (_i32, [_vp, _i32]),
     "dec_star0_apply": (_i32, [_vp, _i32, _vp, _vp, _vp]),
     "dec_laplacian_apply": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "mg_smooth": (_i32, [_vp, _i32, _i32, _i32, _d, _vp, _vp, _vp]),
@@ -408,6 +411,11 @@ def mg_hierarchy_set_edge_coeff(h, k_edge, stream=None):
     ptr = None if k_edge is None else _ptr(k_edge, torch.float64,
                                            mg_hierarchy_info(h, top)["ne"], "k_edge")
     _check(lib().mg_hierarchy_set_edge_coeff(h, ptr, _stream(stream)))
+
+
+def mg_hierarchy_set_debug(h, flags: int):
+    """Fault injection for failure-handling tests (MG_DEBUG_ bits; 0 clears)."""
+    _check(lib().mg_hierarchy_set_debug(h, int(flags)))
 
 
 # ----------------------------------------------------------------- operators

@@ -435,6 +435,7 @@ int batch_solve(Batch& B, const double* const* b, double* const* x, mg_result* r
         r.rel_residual = cc[c].bnorm > 0 ? cc[c].true_rnorm / cc[c].bnorm : 0.0;
         r.rel_residual_loop = cc[c].bnorm > 0 ? cc[c].rnorm / cc[c].bnorm : 0.0;
         r.history_len = 0;
+        r.fp64_fallback = 0;
       }
     }
     G.last_iters = it;

@@ -81,6 +81,8 @@ mg_status check_opts(const mg_opts* o) {
   if (o->fuse_levels != 0 && o->fuse_levels != 1) return fail(MG_EINVAL, "fuse_levels must be 0 or 1");
   if (o->compat_check != 0 && o->compat_check != 1)
     return fail(MG_EINVAL, "compat_check must be 0 or 1");
+  if (o->stall_checks < 0 || o->stall_checks > 1000)
+    return fail(MG_EINVAL, "stall_checks must be in 0..1000");
   return MG_OK;
 }
 
@@ -184,7 +186,7 @@ void sync_check(hipStream_t s) {
 extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }
-int32_t mg_abi_version(void) { return 2; }
+int32_t mg_abi_version(void) { return 3; }
 
 mg_status dec_mesh_from_arrays(int64_t nv, const double* xyz, int64_t nt, const int32_t* tri,
                                dec_mesh** out) {
@@ -449,6 +451,21 @@ mg_status mg_hierarchy_coeff_grad_log(mg_hierarchy* h, const double* grad_k, dou
   return MG_OK;
 }
 
+mg_status mg_hierarchy_set_debug(mg_hierarchy* h, int32_t flags) {
+  if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
+  if (flags & ~int32_t(MG_DEBUG_ZERO_PRECOND32)) return fail(MG_EINVAL, "unknown debug flag");
+  API_BEGIN
+  decmg::Hierarchy& H = *h->h;
+  if (H.debug_flags != flags) {
+    // captured iterations hold the old behaviour
+    for (auto& kv : H.graphs) (void)hipGraphExecDestroy(kv.second);
+    H.graphs.clear();
+    H.debug_flags = flags;
+  }
+  API_END
+  return MG_OK;
+}
+
 mg_status mg_hierarchy_set_edge_coeff(mg_hierarchy* h, const double* k_edge, void* stream) {
   API_BEGIN
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
@@ -562,6 +579,7 @@ void mg_opts_default(mg_opts* o) {
   o->check_every = 4;
   o->use_graph = 1;
   o->fuse_levels = 1;
+  o->stall_checks = 3;
 }
 
 mg_status mg_vcycle(mg_hierarchy* h, const mg_opts* o, int32_t level, int32_t dtype, const void* b,

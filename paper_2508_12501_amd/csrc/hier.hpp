@@ -138,7 +138,9 @@ constexpr int kCoarseThreads = 1024;       // workgroup of the fused coarse cycl
 constexpr int kCoarseLdsMax = 160 * 1024;  // LDS budget cap of the fused coarse cycle
 // Largest level the fused coarse cycle takes.  It runs in one workgroup, whose memory
 // throughput (one CU's outstanding misses) makes it pay only for levels whose operator data is
-// a few tens of KB; larger levels run as regular multi-workgroup launches.
+// a few tens of KB; larger levels run as regular multi-workgroup launches.  (Taking the
+// 3969-row level of the 2049^2 grid as well, four rows per thread, saved nothing in FP32 and
+// spilled registers in FP64.)
 constexpr int32_t kCoarseFuseRows = 2048;
 // Iterations whose residual a solve records for mg_result.history.
 constexpr int32_t kHistoryCap = 4096;
@@ -278,6 +280,7 @@ struct Hierarchy {
   double* aux_host = nullptr;      // pinned, one double (host reads of single device results)
   hipStream_t capture_stream = nullptr;
   std::map<std::tuple<int, int, int, int, double>, hipGraphExec_t> graphs;
+  int32_t debug_flags = 0;   // MG_DEBUG_ bits (fault injection for tests)
   std::map<std::tuple<int, int, int, int, double>, int> last_iters;
   // fused coarse cycle: highest level handled by one workgroup, per precision (-1 = none)
   int ctop64 = -1, ctop32 = -1;

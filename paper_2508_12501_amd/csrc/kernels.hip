@@ -3142,9 +3142,13 @@ void init_scalars(DevScalars* sc, double rtol, int32_t max_iter, double n_unknow
                      hist_cap);
 }
 
+// A loop restarted from x with p = q = 0: the direction scalars start as at k_init_scalars
+// (their values then do not enter the first new direction, only keep it finite).
 __global__ void k_restart_scalars(DevScalars* __restrict__ sc) {
   sc->done = 0;
   sc->status = MG_OK;
+  sc->rho = 1.0;
+  sc->pq = 1.0;
 }
 
 void restart_scalars(DevScalars* sc, hipStream_t s) {

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <limits>
 #include <stdexcept>
 
 #include "hier.hpp"
@@ -261,6 +262,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   const bool fused_mean = natural && o.outer != MG_OUTER_IR;
   if (o.precision == MG_F32) {
     z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s);
+    if (H.debug_flags & MG_DEBUG_ZERO_PRECOND32) k::fill<float>(z32, n, 0.0f, s);
     if (fused_mean) {
       k::zsum_dot32(n, H.scal, z32, other, P0, P1, P2, done, s);
     } else {
@@ -422,6 +424,7 @@ void collect(Hierarchy& H, mg_result* res, hipStream_t s) {
     res->rel_residual_loop = h.bnorm > 0 ? h.rnorm / h.bnorm : 0.0;
     res->rel_residual = h.bnorm > 0 ? h.true_rnorm / h.bnorm : 0.0;
     res->history_len = 0;
+    res->fp64_fallback = 0;
     if (res->history && res->history_cap > 0) {
       const int m = std::min({h.iters, res->history_cap, H.hist_cap});
       if (m > 0) {
@@ -463,15 +466,20 @@ struct HostTimer {
 // normally needs one or two host round trips and runs few or no no-op iterations.
 // `tail` is enqueued after every batch, before the host reads the flag: the exit work (the
 // finish of a solve) then follows the last iteration on the device without a host round trip;
-// after a batch that did not converge it is simply done again later.
+// after a batch that did not converge it is simply done again later.  With stall > 0 the loop
+// also ends, returning true, once `stall` checks in a row after the first found the loop
+// residual no lower than the smallest one seen at an earlier check.
 template <typename F, typename G>
-void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue, G tail,
-             HostTimer* T = nullptr, int launched = 0) {
+bool iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue, G tail,
+             HostTimer* T = nullptr, int launched = 0, int stall = 0) {
   const int every = std::max(1, o.check_every);
   auto key = graph_key(o, kind);
   auto it = H.last_iters.find(key);
   // a restarted loop (launched > 0) continues in batches of check_every
   int batch = (it != H.last_iters.end() && launched == 0) ? std::max(1, it->second) : every;
+  double best = std::numeric_limits<double>::infinity();
+  int flat = 0;
+  bool stalled = false;
   while (launched < o.max_iter) {
     batch = std::min(batch, o.max_iter - launched);
     for (int j = 0; j < batch; ++j) enqueue();
@@ -482,6 +490,15 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
     if (T) T->mark("wait");
     const DevScalars& h = *H.scal_host;
     if (h.done) break;
+    if (stall > 0) {
+      if (h.rnorm < best) {
+        best = h.rnorm;
+        flat = 0;
+      } else if (++flat >= stall) {
+        stalled = true;
+        break;
+      }
+    }
     batch = every;
     if (h.iters > 0 && h.rnorm > 0 && h.bnorm > 0) {
       const double rate = std::pow(h.rnorm / h.bnorm, 1.0 / h.iters);
@@ -494,7 +511,8 @@ void iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
     tail();
     read_scalars(H, s);
   }
-  H.last_iters[key] = H.scal_host->iters;
+  if (!stalled) H.last_iters[key] = H.scal_host->iters;
+  return stalled;
 }
 
 int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, mg_result* res,
@@ -505,6 +523,7 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   init_scalars(H, o, s);
   setup_rhs(H, b_nat, s, check_compat);
   H.p_parity = 0;
+  mg_opts cur = o;   // the FP64 fallback switches the cycle's precision
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
   if (warm_start && !b_nat) {
     k::fill<double>(H.sp, n, 0.0, s);
@@ -515,50 +534,84 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }
   T.mark("setup");
-  hipGraphExec_t g[2] = {o.use_graph ? iteration_graph(H, o, 0) : nullptr,
-                        o.use_graph ? iteration_graph(H, o, 2) : nullptr};
+  hipGraphExec_t g[2] = {nullptr, nullptr};
+  auto load_graphs = [&]() {
+    g[0] = cur.use_graph ? iteration_graph(H, cur, 0) : nullptr;
+    g[1] = cur.use_graph ? iteration_graph(H, cur, 2) : nullptr;
+  };
+  load_graphs();
   T.mark("graph");
   auto step = [&]() {
     if (g[H.p_parity])
       check_hip(hipGraphLaunch(g[H.p_parity], s), "hipGraphLaunch");
     else
-      enqueue_iteration(H, o, H.p_parity, s);
+      enqueue_iteration(H, cur, H.p_parity, s);
     H.p_parity ^= 1;
   };
   auto tail = [&]() {
     if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
   };
-  iterate(H, o, 0, s, step, tail, &T);
-  if (H.bc == MG_BC_NATURAL) {
-    enqueue_finish(H, b_nat, x_nat, s);
-    read_scalars(H, s);
-  }
-  // The solve stops on the true relative residual ||b - A x|| / ||b|| (Sec. 3.1).  CG and FCG
-  // loop on the recursively updated residual; when that met rtol and the true one (computed
-  // by the finish) did not, the iteration restarts from x: r = b - A x, p = q = 0, so that the
-  // next direction is the preconditioned residual.
-  if (o.outer != MG_OUTER_IR) {
-    while (H.scal_host->status == MG_OK && H.scal_host->bnorm > 0 &&
-           H.scal_host->true_rnorm > o.rtol * H.scal_host->bnorm) {
-      const int done_iters = H.scal_host->iters;
+  // the loop from iteration `launched` on; stagnation ends it only while the FP32 cycle runs
+  bool fell_back = false;
+  const int stall = (o.precision == MG_F32) ? o.stall_checks : 0;
+  auto run = [&](int launched) {
+    const bool stalled = iterate(H, cur, 0, s, step, tail, &T, launched, fell_back ? 0 : stall);
+    if (H.bc == MG_BC_NATURAL) {
+      enqueue_finish(H, b_nat, x_nat, s);
+      read_scalars(H, s);
+    }
+    return stalled;
+  };
+  // restart from x: r = b - A x, p = q = 0, so that the next direction is the preconditioned
+  // residual
+  auto restart = [&]() {
+    k::restart_scalars(H.scal, s);
+    k::fill<double>(H.sp, n, 0.0, s);
+    k::fill<double>(H.sp2, n, 0.0, s);
+    k::fill<double>(H.sq, n, 0.0, s);
+    k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
+    if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
+  };
+  bool stalled = run(0);
+  for (;;) {
+    const DevScalars& h = *H.scal_host;
+    const bool live_rhs = h.bnorm > 0 && std::isfinite(h.bnorm);
+    // A stagnating, broken-down or non-finite FP32-preconditioned loop goes on from x with the
+    // FP64 cycle (the residual, x and the coarsest solve are FP64 throughout, so x is as good
+    // as the last completed iteration left it).
+    if (stall > 0 && !fell_back && live_rhs &&
+        (stalled || h.status == MG_EBREAKDOWN || h.status == MG_ENONFINITE)) {
+      if (h.iters >= o.max_iter) {
+        H.scal_host->status = MG_ENOCONV;
+        break;
+      }
+      fell_back = true;
+      cur.precision = MG_F64;
+      r32 = nullptr;
+      load_graphs();
+      const int done_iters = h.iters;
+      restart();
+      stalled = run(done_iters);
+      continue;
+    }
+    // The solve stops on the true relative residual ||b - A x|| / ||b|| (Sec. 3.1).  CG and
+    // FCG loop on the recursively updated residual; when that met rtol and the true one
+    // (computed by the finish) did not, the iteration restarts from x.
+    if (o.outer != MG_OUTER_IR && h.status == MG_OK && h.bnorm > 0 &&
+        h.true_rnorm > o.rtol * h.bnorm) {
+      const int done_iters = h.iters;
       if (done_iters >= o.max_iter) {
         H.scal_host->status = MG_ENOCONV;
         break;
       }
-      k::restart_scalars(H.scal, s);
-      k::fill<double>(H.sp, n, 0.0, s);
-      k::fill<double>(H.sp2, n, 0.0, s);
-      k::fill<double>(H.sq, n, 0.0, s);
-      k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
-      if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
-      iterate(H, o, 0, s, step, tail, &T, done_iters);
-      if (H.bc == MG_BC_NATURAL) {
-        enqueue_finish(H, b_nat, x_nat, s);
-        read_scalars(H, s);
-      }
+      restart();
+      stalled = run(done_iters);
+      continue;
     }
+    break;
   }
   collect(H, res, s);
+  if (res) res->fp64_fallback = fell_back ? 1 : 0;
   T.mark("finish");
   return H.scal_host->status;
 }

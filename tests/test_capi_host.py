@@ -1,6 +1,9 @@
 """C-ABI checks that need no GPU: the library loads, exports every function the header
 declares, and the host-only mesh entry points validate their inputs."""
 import ctypes
+import os
+import shutil
+import subprocess
 
 import numpy as np
 import pytest
@@ -15,12 +18,39 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(mg._PROTOS), set(names) ^ set(mg._PROTOS)
-    assert L.mg_abi_version() == 2
+    assert L.mg_abi_version() == 3
 
 
 def test_opts_default():
     o = mg.mg_opts_default()
     assert (o.nu1, o.nu2, o.omega, o.rtol, o.outer, o.precision) == (2, 2, 0.8, 1e-10, 0, 0)
+    assert (o.compat_check, o.stall_checks) == (0, 3)
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    # the binding's ctypes mirrors against the header as the host compiler lays it out
+    cxx = shutil.which("g++") or shutil.which("c++")
+    if cxx is None:
+        pytest.skip("no host C++ compiler")
+    src = tmp_path / "layout.cpp"
+    src.write_text(
+        '#include <cstddef>\n#include <cstdio>\n#include "decmg.h"\n'
+        "int main() { std::printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(mg_opts),\n"
+        "  offsetof(mg_opts, stall_checks), sizeof(mg_result), offsetof(mg_result, history_len),\n"
+        "  offsetof(mg_result, fp64_fallback)); }\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cxx, "-std=c++17", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert got == [ctypes.sizeof(mg.mg_opts), mg.mg_opts.stall_checks.offset,
+                   ctypes.sizeof(mg.mg_result), mg.mg_result.history_len.offset,
+                   mg.mg_result.fp64_fallback.offset]
+
+
+def test_debug_flags_validated():
+    L = mg.lib()
+    assert L.mg_hierarchy_set_debug(None, 0) == mg.MG_EINVAL
 
 
 def test_mesh_constructors_and_validation():

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <stdexcept>
 
 namespace decmg {
 
@@ -177,7 +178,14 @@ Mesh icosahedron() {
   return m;
 }
 
+// Subdivision reads the coarse mesh's edges and face maps (build_topology).
+static void need_topology(const Mesh& c) {
+  if (c.tri_edge.size() != 3 * size_t(c.nt) || c.edge.size() != 2 * size_t(c.ne))
+    throw std::logic_error("subdivision of a mesh without its topology");
+}
+
 Mesh subdivide(const Mesh& c, bool project_sphere) {
+  need_topology(c);
   Mesh f;
   f.nv = c.nv + c.ne;
   f.nt = 4 * c.nt;
@@ -221,6 +229,7 @@ Mesh subdivide(const Mesh& c, bool project_sphere) {
 }
 
 Mesh subdivide_cubic(const Mesh& c, bool project_sphere) {
+  need_topology(c);
   Mesh f;
   f.nv = c.nv + 2 * c.ne + c.nt;
   f.nt = 9 * c.nt;

@@ -50,7 +50,11 @@ def test_headline_sweep_bytes():
 
 
 def test_traffic_follows_the_kernel_source(tmp_path, monkeypatch):
-    key = "k_rows2<float, 2, true, Half16>@2095360"
+    # the headline sweep as bench.py names it on the C3 finest level (row patterns, two rows
+    # per thread: 2,095,360 threads)
+    info = {"row_patterns": 9, "n_unknowns": 4190209, "rows_per_thread": 2}
+    key = "%s@%d" % (bench.sweep_kernel_name(info), bench.sweep_grid(info))
+    assert key == "k_rows2p<float, 2>@2095360"
     prof = os.path.join(ROOT, "profiles", "c3_finest_kernels_hbm_traffic.md")
     # a copy of the repository layout whose kernel source differs from the recorded hash
     (tmp_path / "profiles").mkdir()

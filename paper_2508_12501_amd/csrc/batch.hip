@@ -23,7 +23,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kFin = 1024;
-constexpr int kMaxRed = 2048;
+constexpr int kMaxRed = 1024;   // cap on workgroups (partials per column) of a reduction
 
 __device__ __forceinline__ int xcd_blk() {
   const int b = blockIdx.x, g = gridDim.x;

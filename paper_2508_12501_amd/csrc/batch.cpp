@@ -63,6 +63,14 @@ T* cycle_b(const mg_opts& o, BatchGroup& G, int l, const T* b, T* x_init, int ki
     bk::coarse<T>(M, H, b, V.x, fl, s);
     return V.x;
   }
+  if (k::coarse_cycle_general_ok<T>(H, l, false)) {
+    // levels l..0 in one launch, one workgroup per column (the register-resident bottom of the
+    // single solve, reading the columns with stride M)
+    T* xo = x_init ? x_init : V.x;
+    k::coarse_cycle_columns<T>(H, l, b, xo, x_init != nullptr, o.omega, o.nu1, o.nu2, kind, M,
+                               &fl->all_done, s);
+    return xo;
+  }
   T* cur;
   T* oth;
   int pre = o.nu1;

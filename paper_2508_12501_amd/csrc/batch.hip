@@ -65,6 +65,11 @@ __device__ __forceinline__ void block_cols(double v0, double v1, double* part0, 
   }
 }
 
+// Every product of an operator row is accumulated with an explicit fused multiply-add, so that
+// the scalar and the vectorised kernels round alike whatever the compiler would contract.
+__device__ __forceinline__ float bmac(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double bmac(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // acc = sum_k w_k (x_i - x_j(k)), d = sum_k w_k over the row's entries, column c.
 template <typename T, bool D16, int M, int N, typename WT>
 __device__ __forceinline__ void brow_n(const void* __restrict__ col, const WT* __restrict__ w,
@@ -83,7 +88,7 @@ __device__ __forceinline__ void brow_n(const void* __restrict__ col, const WT* _
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     d += wk[k];
-    acc += wk[k] * (xi - xj[k]);
+    acc = bmac(wk[k], xi - xj[k], acc);
   }
 }
 
@@ -112,7 +117,7 @@ __device__ __forceinline__ void brow(const int32_t* __restrict__ sptr, const voi
         const int idx = (beg + k) * kSlice + lane;
         const T wk = static_cast<T>(w[idx]);
         d += wk;
-        acc += wk * (xi - x[colx<D16>(col, idx, row, n) * M + c]);
+        acc = bmac(wk, xi - x[colx<D16>(col, idx, row, n) * M + c], acc);
       }
   }
 }
@@ -143,6 +148,226 @@ __global__ __launch_bounds__(kThreads) void bk_rows(const int32_t* __restrict__ 
     y[row * M + c] = bi - acc;
   else
     y[row * M + c] = xi + omega * (bi - acc) / d;
+}
+
+// ----------------------------------------------------------------- vectorised row kernels
+// With at least 16 bytes of columns per row (M >= 4 FP32 or M >= 2 FP64 columns), a thread
+// takes 16 bytes of consecutive columns of its row: one 16-byte load per vector and per
+// neighbour in place of four or two, and a wavefront covers four or two times as many rows,
+// so each row's index and weight loads serve more columns.  The arithmetic of every column is
+// that of bk_rows (explicit fused multiply-adds in entry order), so the results are the same.
+template <typename T>
+constexpr int kVW = 16 / static_cast<int>(sizeof(T));
+
+template <typename T, int VW>
+struct alignas(sizeof(T) * VW) VecT {
+  T v[VW];
+};
+
+template <typename T, bool D16, int M, int N, typename WT>
+__device__ __forceinline__ void brow_v_n(const void* __restrict__ col, const WT* __restrict__ w,
+                                         const T* __restrict__ x, int beg, int lane, int row,
+                                         int c0, int n, const VecT<T, kVW<T>>& xi,
+                                         T (&acc)[kVW<T>], T& d) {
+  constexpr int VW = kVW<T>;
+  int cj[N];
+  T wk[N];
+  VecT<T, VW> xj[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    cj[k] = colx<D16>(col, idx, row, n);
+    wk[k] = static_cast<T>(w[idx]);
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    xj[k] = *reinterpret_cast<const VecT<T, VW>*>(x + cj[k] * M + c0);
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    d += wk[k];
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = bmac(wk[k], xi.v[e] - xj[k].v[e], acc[e]);
+  }
+}
+
+// bk_rows over 16-byte column vectors (M >= kVW<T>)
+template <typename T, int MODE, bool D16, int M, typename WT>
+__global__ __launch_bounds__(kThreads) void bk_rows_v(const int32_t* __restrict__ sptr,
+                                                      const void* __restrict__ col,
+                                                      const WT* __restrict__ w,
+                                                      const T* __restrict__ x,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ y, int32_t n, T omega,
+                                                      const BatchFlag* __restrict__ flag) {
+  constexpr int VW = kVW<T>, TPR = M / VW, RB = kThreads / TPR;
+  static_assert(M >= VW && M % VW == 0, "at least one full vector per row");
+  using V = VecT<T, VW>;
+  if (flag && flag->all_done) return;
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * VW;
+  const int row = xcd_blk() * RB + static_cast<int>(threadIdx.x) / TPR;
+  if (row >= n) return;
+  const V xi = *reinterpret_cast<const V*>(x + row * M + c0);
+  V bi;
+  if (MODE != 0) bi = *reinterpret_cast<const V*>(b + row * M + c0);
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = sptr[s];
+  const int width = sptr[s + 1] - beg;
+  const int lane = row & 63;
+  T acc[VW];
+#pragma unroll
+  for (int e = 0; e < VW; ++e) acc[e] = T(0);
+  T d = T(0);
+  switch (width) {
+    case 0: break;
+#define BK_ROWV(K)                                                                            \
+  case K:                                                                                     \
+    brow_v_n<T, D16, M, K>(col, w, x, beg, lane, row, c0, n, xi, acc, d);                     \
+    break;
+    BK_ROWV(1) BK_ROWV(2) BK_ROWV(3) BK_ROWV(4) BK_ROWV(5) BK_ROWV(6) BK_ROWV(7) BK_ROWV(8)
+#undef BK_ROWV
+    default:
+      for (int k = 0; k < width; ++k) {
+        const int idx = (beg + k) * kSlice + lane;
+        const T wk = static_cast<T>(w[idx]);
+        const V xj = *reinterpret_cast<const V*>(x + colx<D16>(col, idx, row, n) * M + c0);
+        d += wk;
+#pragma unroll
+        for (int e = 0; e < VW; ++e) acc[e] = bmac(wk, xi.v[e] - xj.v[e], acc[e]);
+      }
+  }
+  V out;
+#pragma unroll
+  for (int e = 0; e < VW; ++e) {
+    if (MODE == 0)
+      out.v[e] = acc[e];
+    else if (MODE == 1)
+      out.v[e] = bi.v[e] - acc[e];
+    else
+      out.v[e] = xi.v[e] + omega * (bi.v[e] - acc[e]) / d;
+  }
+  *reinterpret_cast<V*>(y + row * M + c0) = out;
+}
+
+// bk_jacobi_zero over 16-byte column vectors
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_jacobi_zero_v(const T* __restrict__ idiag,
+                                                             const T* __restrict__ b,
+                                                             T* __restrict__ y, int32_t n, T omega,
+                                                             const BatchFlag* __restrict__ flag) {
+  constexpr int VW = kVW<T>, TPR = M / VW, RB = kThreads / TPR;
+  using V = VecT<T, VW>;
+  if (flag && flag->all_done) return;
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * VW;
+  const int row = xcd_blk() * RB + static_cast<int>(threadIdx.x) / TPR;
+  if (row >= n) return;
+  const V bi = *reinterpret_cast<const V*>(b + row * M + c0);
+  const T di = idiag[row];
+  V out;
+  {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) out.v[e] = omega * bi.v[e] * di;
+  }
+  *reinterpret_cast<V*>(y + row * M + c0) = out;
+}
+
+// restriction over column vectors: rc = rf[kept] + 1/2 (sum of the midpoint entries)
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_restrict_v(const int32_t* __restrict__ self,
+                                                          const int32_t* __restrict__ sptr,
+                                                          const int32_t* __restrict__ col,
+                                                          const T* __restrict__ rf,
+                                                          T* __restrict__ rc, int32_t nc,
+                                                          const BatchFlag* __restrict__ flag) {
+  constexpr int VW = kVW<T>, TPR = M / VW, RB = kThreads / TPR;
+  using V = VecT<T, VW>;
+  if (flag && flag->all_done) return;
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * VW;
+  const int row = xcd_blk() * RB + static_cast<int>(threadIdx.x) / TPR;
+  if (row >= nc) return;
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = sptr[s], width = sptr[s + 1] - beg;
+  const int lane = row & 63;
+  const V rs = *reinterpret_cast<const V*>(rf + self[row] * M + c0);
+  T acc[VW];
+#pragma unroll
+  for (int e = 0; e < VW; ++e) acc[e] = T(0);
+  for (int k = 0; k < width; ++k) {
+    const V v = *reinterpret_cast<const V*>(rf + col[(beg + k) * kSlice + lane] * M + c0);
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] += v.v[e];
+  }
+  V out;
+#pragma unroll
+  for (int e = 0; e < VW; ++e) out.v[e] = rs.v[e] + T(0.5) * acc[e];
+  *reinterpret_cast<V*>(rc + row * M + c0) = out;
+}
+
+// interpolation over column vectors: xf += 1/2 (ec[pa] + ec[pb])
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_prolong_v(const int32_t* __restrict__ pa,
+                                                         const int32_t* __restrict__ pb,
+                                                         const T* __restrict__ ec,
+                                                         T* __restrict__ xf, int32_t nf,
+                                                         const BatchFlag* __restrict__ flag) {
+  constexpr int VW = kVW<T>, TPR = M / VW, RB = kThreads / TPR;
+  using V = VecT<T, VW>;
+  if (flag && flag->all_done) return;
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * VW;
+  const int row = xcd_blk() * RB + static_cast<int>(threadIdx.x) / TPR;
+  if (row >= nf) return;
+  const V ea = *reinterpret_cast<const V*>(ec + pa[row] * M + c0);
+  const V eb = *reinterpret_cast<const V*>(ec + pb[row] * M + c0);
+  V x = *reinterpret_cast<const V*>(xf + row * M + c0);
+#pragma unroll
+  for (int e = 0; e < VW; ++e) x.v[e] += T(0.5) * (ea.v[e] + eb.v[e]);
+  *reinterpret_cast<V*>(xf + row * M + c0) = x;
+}
+
+// bk_prolong_sweep over column vectors
+template <typename T, bool D16, int M, typename WT>
+__global__ __launch_bounds__(kThreads) void bk_prolong_sweep_v(
+    const int32_t* __restrict__ sptr, const void* __restrict__ col, const WT* __restrict__ w,
+    const int32_t* __restrict__ pa, const int32_t* __restrict__ pb, const T* __restrict__ ec,
+    const T* __restrict__ x, const T* __restrict__ b, T* __restrict__ y, int32_t n, T omega,
+    const BatchFlag* __restrict__ flag) {
+  constexpr int VW = kVW<T>, TPR = M / VW, RB = kThreads / TPR;
+  using V = VecT<T, VW>;
+  if (flag && flag->all_done) return;
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * VW;
+  const int row = xcd_blk() * RB + static_cast<int>(threadIdx.x) / TPR;
+  if (row >= n) return;
+  // x0 = x + M(f)^T e_c at one row (the zero slot's parents are the coarse zero slot)
+  auto x0 = [&](int j) {
+    const V xv = *reinterpret_cast<const V*>(x + j * M + c0);
+    const V ea = *reinterpret_cast<const V*>(ec + pa[j] * M + c0);
+    const V eb = *reinterpret_cast<const V*>(ec + pb[j] * M + c0);
+    V r;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) r.v[e] = xv.v[e] + T(0.5) * (ea.v[e] + eb.v[e]);
+    return r;
+  };
+  const V xi0 = x0(row);
+  const V bi = *reinterpret_cast<const V*>(b + row * M + c0);
+  const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+  const int beg = sptr[s], width = sptr[s + 1] - beg;
+  const int lane = row & 63;
+  T acc[VW];
+#pragma unroll
+  for (int e = 0; e < VW; ++e) acc[e] = T(0);
+  T d = T(0);
+  for (int k = 0; k < width; ++k) {
+    const int idx = (beg + k) * kSlice + lane;
+    const V xj = x0(colx<D16>(col, idx, row, n));
+    const T wk = static_cast<T>(w[idx]);
+    d += wk;
+#pragma unroll
+    for (int e = 0; e < VW; ++e) acc[e] = bmac(wk, xi0.v[e] - xj.v[e], acc[e]);
+  }
+  V out;
+#pragma unroll
+  for (int e = 0; e < VW; ++e) out.v[e] = xi0.v[e] + omega * (bi.v[e] - acc[e]) / d;
+  *reinterpret_cast<V*>(y + row * M + c0) = out;
 }
 
 template <typename T, int M>
@@ -212,7 +437,7 @@ __global__ __launch_bounds__(kThreads) void bk_prolong_sweep(
     const T xj = x[j * M + c] + T(0.5) * (ec[pa[j] * M + c] + ec[pb[j] * M + c]);
     const T wk = static_cast<T>(w[idx]);
     d += wk;
-    acc += wk * (xi0 - xj);
+    acc = bmac(wk, xi0 - xj, acc);
   }
   y[row * M + c] = xi0 + omega * (b[row * M + c] - acc) / d;
 }
@@ -398,7 +623,7 @@ __global__ __launch_bounds__(kThreads) void bk_zdot(int32_t n, const BatchCol* _
   double v = 0.0;
   for (int t = t0; t < t1; ++t) {
     const int i = t * rb + threadIdx.x / M;
-    if (i < n) v += zval<T>(z, i * M + c, cc, sub_mean) * q[i * M + c];
+    if (i < n) v = bmac(zval<T>(z, i * M + c, cc, sub_mean), q[i * M + c], v);
   }
   block_cols<M>(v, 0.0, part, nullptr, blk);
 }
@@ -414,7 +639,7 @@ __global__ __launch_bounds__(kThreads) void bk_pupd(int32_t n, const BatchCol* _
   const BatchCol& cc = col[c];
   if (cc.done) return;
   const int k = row * M + c;
-  p[k] = zval<T>(z, k, cc, sub_mean) + cc.beta * p[k];
+  p[k] = bmac(cc.beta, p[k], zval<T>(z, k, cc, sub_mean));
 }
 
 template <bool D16, int M, typename WT>
@@ -438,11 +663,195 @@ __global__ __launch_bounds__(kThreads) void bk_spmv_dot2(const int32_t* __restri
       double acc, d;
       brow<double, D16, M>(sptr, colv, w, p, row, c, n, pi, acc, d);
       q[k] = acc;
-      v0 += pi * acc;
-      v1 += pi * r[k];
+      v0 = bmac(pi, acc, v0);
+      v1 = bmac(pi, r[k], v1);
     }
   }
   block_cols<M>(v0, v1, part0, part1, blk);
+}
+
+// ----------------------------------------------------------------- Krylov part, vectorised
+// Two FP64 columns per thread (M >= 2): tiles of 2 kThreads / M rows; per-column block sums in
+// a fixed order (row slots of the workgroup in increasing order).
+constexpr int kKV = 2;
+using D2 = VecT<double, kKV>;
+
+#define BK_TILES_V(M, n)                                                \
+  constexpr int TPR = (M) / kKV, RBV = kThreads / TPR;                  \
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * kKV;           \
+  const int slot = static_cast<int>(threadIdx.x) / TPR;                 \
+  const int blk = blockIdx.x;                                           \
+  int t0, t1;                                                           \
+  tiles_of(((n) + RBV - 1) / RBV, blk, t0, t1);
+
+template <int M>
+__device__ __forceinline__ void block_cols_v(const double (&v0)[kKV], const double (&v1)[kKV],
+                                             double* part0, double* part1, int blk) {
+  constexpr int TPR = M / kKV, RBV = kThreads / TPR;
+  __shared__ double s0[kThreads * kKV], s1[kThreads * kKV];
+#pragma unroll
+  for (int e = 0; e < kKV; ++e) {
+    s0[threadIdx.x * kKV + e] = v0[e];
+    if (part1) s1[threadIdx.x * kKV + e] = v1[e];
+  }
+  __syncthreads();
+  if (static_cast<int>(threadIdx.x) < M) {
+    const int c = threadIdx.x, tc = c / kKV, e = c % kKV;
+    double a = 0.0, b = 0.0;
+    for (int j = 0; j < RBV; ++j) {
+      a += s0[(j * TPR + tc) * kKV + e];
+      if (part1) b += s1[(j * TPR + tc) * kKV + e];
+    }
+    part0[blk * M + c] = a;
+    if (part1) part1[blk * M + c] = b;
+  }
+}
+
+// z.q per column (z widened and, when projecting, minus the column mean)
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_zdot_v(int32_t n, const BatchCol* __restrict__ col,
+                                                      const T* __restrict__ z,
+                                                      const double* __restrict__ q,
+                                                      double* __restrict__ part, int sub_mean,
+                                                      const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_TILES_V(M, n)
+  const BatchCol ca = col[c0], cb = col[c0 + 1];
+  double v[kKV] = {0.0, 0.0}, none[kKV] = {0.0, 0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * RBV + slot;
+    if (i < n) {
+      const int k = i * M + c0;
+      const D2 qv = *reinterpret_cast<const D2*>(q + k);
+      v[0] = bmac(zval<T>(z, k, ca, sub_mean), qv.v[0], v[0]);
+      v[1] = bmac(zval<T>(z, k + 1, cb, sub_mean), qv.v[1], v[1]);
+    }
+  }
+  block_cols_v<M>(v, none, part, nullptr, blk);
+}
+
+// p = z + beta p per live column
+template <typename T, int M>
+__global__ __launch_bounds__(kThreads) void bk_pupd_v(int32_t n, const BatchCol* __restrict__ col,
+                                                      const T* __restrict__ z,
+                                                      double* __restrict__ p, int sub_mean,
+                                                      const BatchFlag* __restrict__ flag) {
+  constexpr int TPR = M / kKV, RBV = kThreads / TPR;
+  if (flag->all_done) return;
+  const int c0 = (static_cast<int>(threadIdx.x) % TPR) * kKV;
+  const int row = xcd_blk() * RBV + static_cast<int>(threadIdx.x) / TPR;
+  if (row >= n) return;
+  const BatchCol& ca = col[c0];
+  const BatchCol& cb = col[c0 + 1];
+  if (ca.done && cb.done) return;
+  const int k = row * M + c0;
+  D2 pv = *reinterpret_cast<const D2*>(p + k);
+  if (!ca.done) pv.v[0] = bmac(ca.beta, pv.v[0], zval<T>(z, k, ca, sub_mean));
+  if (!cb.done) pv.v[1] = bmac(cb.beta, pv.v[1], zval<T>(z, k + 1, cb, sub_mean));
+  *reinterpret_cast<D2*>(p + k) = pv;
+}
+
+// q = A p per column, with the partial sums of p.q and p.r
+template <bool D16, int M, typename WT>
+__global__ __launch_bounds__(kThreads) void bk_spmv_dot2_v(const int32_t* __restrict__ sptr,
+                                                           const void* __restrict__ colv,
+                                                           const WT* __restrict__ w,
+                                                           const double* __restrict__ p,
+                                                           double* __restrict__ q,
+                                                           const double* __restrict__ r,
+                                                           double* __restrict__ part0,
+                                                           double* __restrict__ part1, int32_t n,
+                                                           const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_TILES_V(M, n)
+  double v0[kKV] = {0.0, 0.0}, v1[kKV] = {0.0, 0.0};
+  for (int t = t0; t < t1; ++t) {
+    const int row = t * RBV + slot;
+    if (row < n) {
+      const int k = row * M + c0;
+      const D2 pi = *reinterpret_cast<const D2*>(p + k);
+      const D2 ri = *reinterpret_cast<const D2*>(r + k);
+      const int s = __builtin_amdgcn_readfirstlane(row >> 6);
+      const int beg = sptr[s], width = sptr[s + 1] - beg;
+      const int lane = row & 63;
+      double acc[kKV] = {0.0, 0.0}, d = 0.0;
+      switch (width) {
+        case 0: break;
+#define BK_SPMVV(K)                                                                           \
+  case K:                                                                                     \
+    brow_v_n<double, D16, M, K>(colv, w, p, beg, lane, row, c0, n, pi, acc, d);               \
+    break;
+        BK_SPMVV(1) BK_SPMVV(2) BK_SPMVV(3) BK_SPMVV(4) BK_SPMVV(5) BK_SPMVV(6) BK_SPMVV(7)
+        BK_SPMVV(8)
+#undef BK_SPMVV
+        default:
+          for (int kk = 0; kk < width; ++kk) {
+            const int idx = (beg + kk) * kSlice + lane;
+            const double wk = static_cast<double>(w[idx]);
+            const D2 pj = *reinterpret_cast<const D2*>(p + colx<D16>(colv, idx, row, n) * M + c0);
+            d += wk;
+            acc[0] = bmac(wk, pi.v[0] - pj.v[0], acc[0]);
+            acc[1] = bmac(wk, pi.v[1] - pj.v[1], acc[1]);
+          }
+      }
+      D2 qv;
+      qv.v[0] = acc[0];
+      qv.v[1] = acc[1];
+      *reinterpret_cast<D2*>(q + k) = qv;
+#pragma unroll
+      for (int e = 0; e < kKV; ++e) {
+        v0[e] = bmac(pi.v[e], acc[e], v0[e]);
+        v1[e] = bmac(pi.v[e], ri.v[e], v1[e]);
+      }
+    }
+  }
+  block_cols_v<M>(v0, v1, part0, part1, blk);
+}
+
+// x += alpha p, r -= alpha q (live columns), the FP32 copy of r, and the partial sums of r.r
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_update_xr_v(int32_t n, const BatchCol* __restrict__ col,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q,
+                                                           double* __restrict__ x,
+                                                           double* __restrict__ r,
+                                                           float* __restrict__ r32,
+                                                           double* __restrict__ part,
+                                                           const BatchFlag* __restrict__ flag) {
+  if (flag->all_done) return;
+  BK_TILES_V(M, n)
+  const BatchCol ca = col[c0], cb = col[c0 + 1];
+  const bool la = !ca.done, lb = !cb.done;
+  double v[kKV] = {0.0, 0.0}, none[kKV] = {0.0, 0.0};
+  if (la || lb) {
+    for (int t = t0; t < t1; ++t) {
+      const int i = t * RBV + slot;
+      if (i < n) {
+        const int k = i * M + c0;
+        const D2 pv = *reinterpret_cast<const D2*>(p + k);
+        const D2 qv = *reinterpret_cast<const D2*>(q + k);
+        D2 xv = *reinterpret_cast<const D2*>(x + k);
+        D2 rv = *reinterpret_cast<const D2*>(r + k);
+        if (la) {
+          xv.v[0] = bmac(ca.alpha, pv.v[0], xv.v[0]);
+          rv.v[0] = bmac(-ca.alpha, qv.v[0], rv.v[0]);
+          v[0] = bmac(rv.v[0], rv.v[0], v[0]);
+        }
+        if (lb) {
+          xv.v[1] = bmac(cb.alpha, pv.v[1], xv.v[1]);
+          rv.v[1] = bmac(-cb.alpha, qv.v[1], rv.v[1]);
+          v[1] = bmac(rv.v[1], rv.v[1], v[1]);
+        }
+        *reinterpret_cast<D2*>(x + k) = xv;
+        *reinterpret_cast<D2*>(r + k) = rv;
+        if (r32) {
+          if (la) r32[k] = static_cast<float>(rv.v[0] * ca.scale);
+          if (lb) r32[k + 1] = static_cast<float>(rv.v[1] * cb.scale);
+        }
+      }
+    }
+  }
+  block_cols_v<M>(v, none, part, nullptr, blk);
 }
 
 template <int M>
@@ -463,10 +872,10 @@ __global__ __launch_bounds__(kThreads) void bk_update_xr(int32_t n, const BatchC
       const int i = t * rb + threadIdx.x / M;
       if (i < n) {
         const int k = i * M + c;
-        x[k] = x[k] + cc.alpha * p[k];
-        const double ri = r[k] - cc.alpha * q[k];
+        x[k] = bmac(cc.alpha, p[k], x[k]);
+        const double ri = bmac(-cc.alpha, q[k], r[k]);
         r[k] = ri;
-        v += ri * ri;
+        v = bmac(ri, ri, v);
         if (r32) r32[k] = static_cast<float>(ri * cc.scale);
       }
     }
@@ -780,8 +1189,12 @@ void zdot(int M, int32_t n, const BatchCol* col, const T* z, const double* q, do
           int sub_mean, const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    hipLaunchKernelGGL((bk_zdot<T, MM>), dim3(nb), dim3(kThreads), 0, s, n, col, z, q, part,
-                       sub_mean, flag);
+    if constexpr (MM >= kKV)
+      hipLaunchKernelGGL((bk_zdot_v<T, MM>), dim3(nb), dim3(kThreads), 0, s, n, col, z, q, part,
+                         sub_mean, flag);
+    else
+      hipLaunchKernelGGL((bk_zdot<T, MM>), dim3(nb), dim3(kThreads), 0, s, n, col, z, q, part,
+                         sub_mean, flag);
   });
 }
 
@@ -790,13 +1203,36 @@ void pupd(int M, int32_t n, const BatchCol* col, const T* z, double* p, int sub_
           const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    hipLaunchKernelGGL((bk_pupd<T, MM>), dim3(row_blocks(n, MM)), dim3(kThreads), 0, s, n, col, z,
-                       p, sub_mean, flag);
+    if constexpr (MM >= kKV) {
+      constexpr int RBV = kThreads / (MM / kKV);
+      hipLaunchKernelGGL((bk_pupd_v<T, MM>), dim3(unsigned((int64_t(n) + RBV - 1) / RBV)),
+                         dim3(kThreads), 0, s, n, col, z, p, sub_mean, flag);
+    } else {
+      hipLaunchKernelGGL((bk_pupd<T, MM>), dim3(row_blocks(n, MM)), dim3(kThreads), 0, s, n, col,
+                         z, p, sub_mean, flag);
+    }
   });
 }
 
 void spmv_dot2(int M, const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, int nb, const BatchFlag* flag, hipStream_t s) {
+  if (M >= kKV) {
+    with_m(M, [&](auto mc) {
+      constexpr int MM = decltype(mc)::value;
+      if constexpr (MM >= kKV) {
+        with_wts<double>(L, [&](auto w) {
+          using WT = pointee<decltype(w)>;
+          if (L.op.col16)
+            hipLaunchKernelGGL((bk_spmv_dot2_v<true, MM, WT>), dim3(nb), dim3(kThreads), 0, s,
+                               L.op.sptr, colp(L), w, p, q, r, part0, part1, L.n, flag);
+          else
+            hipLaunchKernelGGL((bk_spmv_dot2_v<false, MM, WT>), dim3(nb), dim3(kThreads), 0, s,
+                               L.op.sptr, colp(L), w, p, q, r, part0, part1, L.n, flag);
+        });
+      }
+    });
+    return;
+  }
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
     with_wts<double>(L, [&](auto w) {
@@ -815,8 +1251,12 @@ void update_xr(int M, int32_t n, const BatchCol* col, const double* p, const dou
                double* r, float* r32, double* part, int nb, const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    hipLaunchKernelGGL(bk_update_xr<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, p, q, x, r, r32,
-                       part, flag);
+    if constexpr (MM >= kKV)
+      hipLaunchKernelGGL(bk_update_xr_v<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, p, q, x, r,
+                         r32, part, flag);
+    else
+      hipLaunchKernelGGL(bk_update_xr<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, p, q, x, r,
+                         r32, part, flag);
   });
 }
 
@@ -839,6 +1279,36 @@ void residual_norm(int M, const Level& L, const double* x, const double* b, doub
 template <typename T>
 void rows(int mode, int M, const Level& L, const T* x, const T* b, T* y, double omega,
           const BatchFlag* flag, hipStream_t s) {
+  if (M >= kVW<T>) {
+    with_m(M, [&](auto mc) {
+      constexpr int MM = decltype(mc)::value;
+      if constexpr (MM >= kVW<T>) {
+        constexpr int RB = kThreads / (MM / kVW<T>);
+        const dim3 g(unsigned((int64_t(L.n) + RB - 1) / RB));
+        const T om = static_cast<T>(omega);
+        const bool d16 = L.op.col16 != nullptr;
+        with_wts<T>(L, [&](auto w) {
+          using WT = pointee<decltype(w)>;
+#define BK_ROWSV_LAUNCH(MODE)                                                                     \
+  if (d16)                                                                                        \
+    hipLaunchKernelGGL((bk_rows_v<T, MODE, true, MM, WT>), g, dim3(kThreads), 0, s, L.op.sptr,     \
+                       colp(L), w, x, b, y, L.n, om, flag);                                       \
+  else                                                                                            \
+    hipLaunchKernelGGL((bk_rows_v<T, MODE, false, MM, WT>), g, dim3(kThreads), 0, s, L.op.sptr,    \
+                       colp(L), w, x, b, y, L.n, om, flag);
+          if (mode == 0) {
+            BK_ROWSV_LAUNCH(0)
+          } else if (mode == 1) {
+            BK_ROWSV_LAUNCH(1)
+          } else {
+            BK_ROWSV_LAUNCH(2)
+          }
+#undef BK_ROWSV_LAUNCH
+        });
+      }
+    });
+    return;
+  }
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
     const dim3 g(row_blocks(L.n, MM));
@@ -868,6 +1338,18 @@ void rows(int mode, int M, const Level& L, const T* x, const T* b, T* y, double 
 template <typename T>
 void jacobi_zero(int M, const Level& L, const T* b, T* y, double omega, const BatchFlag* flag,
                  hipStream_t s) {
+  if (M >= kVW<T>) {
+    with_m(M, [&](auto mc) {
+      constexpr int MM = decltype(mc)::value;
+      if constexpr (MM >= kVW<T>) {
+        constexpr int RB = kThreads / (MM / kVW<T>);
+        hipLaunchKernelGGL((bk_jacobi_zero_v<T, MM>), dim3(unsigned((int64_t(L.n) + RB - 1) / RB)),
+                           dim3(kThreads), 0, s, idiag_of<T>(L), b, y, L.n,
+                           static_cast<T>(omega), flag);
+      }
+    });
+    return;
+  }
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
     hipLaunchKernelGGL((bk_jacobi_zero<T, MM>), dim3(row_blocks(L.n, MM)), dim3(kThreads), 0, s,
@@ -880,8 +1362,15 @@ void restrict_(int M, const Level& Lf, const Level& Lc, const T* rf, T* rc, cons
                hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    hipLaunchKernelGGL((bk_restrict<T, MM>), dim3(row_blocks(Lc.n, MM)), dim3(kThreads), 0, s,
-                       Lf.tr.r_self, Lf.tr.r_sptr, Lf.tr.r_col, rf, rc, Lc.n, flag);
+    if constexpr (MM >= kVW<T>) {
+      constexpr int RB = kThreads / (MM / kVW<T>);
+      hipLaunchKernelGGL((bk_restrict_v<T, MM>), dim3(unsigned((int64_t(Lc.n) + RB - 1) / RB)),
+                         dim3(kThreads), 0, s, Lf.tr.r_self, Lf.tr.r_sptr, Lf.tr.r_col, rf, rc,
+                         Lc.n, flag);
+    } else {
+      hipLaunchKernelGGL((bk_restrict<T, MM>), dim3(row_blocks(Lc.n, MM)), dim3(kThreads), 0, s,
+                         Lf.tr.r_self, Lf.tr.r_sptr, Lf.tr.r_col, rf, rc, Lc.n, flag);
+    }
   });
 }
 
@@ -891,8 +1380,14 @@ void prolong(int M, const Level& Lf, const Level& Lc, const T* ec, T* xf, const 
   (void)Lc;
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
-    hipLaunchKernelGGL((bk_prolong<T, MM>), dim3(row_blocks(Lf.n, MM)), dim3(kThreads), 0, s,
-                       Lf.tr.pa, Lf.tr.pb, ec, xf, Lf.n, flag);
+    if constexpr (MM >= kVW<T>) {
+      constexpr int RB = kThreads / (MM / kVW<T>);
+      hipLaunchKernelGGL((bk_prolong_v<T, MM>), dim3(unsigned((int64_t(Lf.n) + RB - 1) / RB)),
+                         dim3(kThreads), 0, s, Lf.tr.pa, Lf.tr.pb, ec, xf, Lf.n, flag);
+    } else {
+      hipLaunchKernelGGL((bk_prolong<T, MM>), dim3(row_blocks(Lf.n, MM)), dim3(kThreads), 0, s,
+                         Lf.tr.pa, Lf.tr.pb, ec, xf, Lf.n, flag);
+    }
   });
 }
 
@@ -901,6 +1396,22 @@ void prolong_sweep(int M, const Level& Lf, const T* ec, const T* x, const T* b, 
                    double omega, const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
+    if constexpr (MM >= kVW<T>) {
+      constexpr int RB = kThreads / (MM / kVW<T>);
+      const dim3 gv(unsigned((int64_t(Lf.n) + RB - 1) / RB));
+      with_wts<T>(Lf, [&](auto w) {
+        using WT = pointee<decltype(w)>;
+        if (Lf.op.col16)
+          hipLaunchKernelGGL((bk_prolong_sweep_v<T, true, MM, WT>), gv, dim3(kThreads), 0, s,
+                             Lf.op.sptr, colp(Lf), w, Lf.tr.pa, Lf.tr.pb, ec, x, b, y, Lf.n,
+                             static_cast<T>(omega), flag);
+        else
+          hipLaunchKernelGGL((bk_prolong_sweep_v<T, false, MM, WT>), gv, dim3(kThreads), 0, s,
+                             Lf.op.sptr, colp(Lf), w, Lf.tr.pa, Lf.tr.pb, ec, x, b, y, Lf.n,
+                             static_cast<T>(omega), flag);
+      });
+      return;
+    }
     const dim3 g(row_blocks(Lf.n, MM));
     with_wts<T>(Lf, [&](auto w) {
       using WT = pointee<decltype(w)>;

@@ -355,6 +355,9 @@ template <typename T> void tile_up(const Level& L, const T* ec, const T* x, cons
 template <typename T> bool coarse_cycle_general_ok(const Hierarchy& H, int top, bool gs);
 // one cycle of shape `kind` on levels top..0 in one launch, from zero or (x_init) from x, in place
 template <typename T> void coarse_cycle_general(const Hierarchy& H, int top, const T* b, T* x, bool x_init, double omega, int nu1, int nu2, int kind, bool gs, const int* done, hipStream_t s);
+// the same (weighted Jacobi) for ncols right-hand sides stored row-blocked, entry (i, c) at
+// i ncols + c: one workgroup per column; requires coarse_cycle_general_ok(H, top, false)
+template <typename T> void coarse_cycle_columns(const Hierarchy& H, int top, const T* b, T* x, bool x_init, double omega, int nu1, int nu2, int kind, int ncols, const int* done, hipStream_t s);
 template <typename T> void copy(const T* src, T* dst, int32_t n, const int* done, hipStream_t s);
 template <typename T> void fill(T* p, int64_t n, T v, hipStream_t s);
 template <typename T> void gather(const int32_t* perm, int32_t n, const T* src, T* dst, hipStream_t s);

@@ -1457,9 +1457,13 @@ template <typename T, int K, int NL, int RPT, bool GEN>
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
     const CoarseLevel<T>* __restrict__ lv, const double* __restrict__ ainv, int32_t n0,
     int32_t inv_off, const T* __restrict__ b_in, T* __restrict__ x_io, int x_init, T omega,
-    int nu1, int nu2, int kind, int gs, const int* __restrict__ done) {
+    int nu1, int nu2, int kind, int gs, const int* __restrict__ done, int stride) {
   constexpr int RW = 8;
   if (done && *done) return;
+  // several right-hand sides stored row-blocked (entry (i, c) at i stride + c): workgroup c
+  // runs column c
+  b_in += blockIdx.x;
+  x_io += blockIdx.x;
   const bool use_gs = GEN && gs != 0, use_x = GEN && x_init != 0;
   extern __shared__ double smem_d[];
   T* sm = reinterpret_cast<T*>(smem_d);
@@ -1509,8 +1513,8 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
   {
     const int n = lv[NL].n;
     for (int i = t; i < n; i += nt) {
-      sm[lv[NL].lds + 2 * (n + 1) + i] = b_in[i];
-      if (use_x) sm[lv[NL].lds + i] = x_io[i];
+      sm[lv[NL].lds + 2 * (n + 1) + i] = b_in[i * stride];
+      if (use_x) sm[lv[NL].lds + i] = x_io[i * stride];
     }
   }
   __syncthreads();
@@ -1664,7 +1668,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
     solve0();
     levels_up<1, NL>([&](auto Lc) { up(Lc); });
     const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
-    for (int i = t; i < lv[NL].n; i += nt) x_io[i] = xs[i];
+    for (int i = t; i < lv[NL].n; i += nt) x_io[i * stride] = xs[i];
     return;
   }
   // the recursion as a loop: per level a 2-bit stage (0 enter, 1 after the first coarse
@@ -1705,7 +1709,7 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_cycle_reg(
     ++level;
   }
   const T* xs = sm + lv[NL].lds + ((in_t >> NL & 1u) ? (lv[NL].n + 1) : 0);
-  for (int i = t; i < lv[NL].n; i += nt) x_io[i] = xs[i];
+  for (int i = t; i < lv[NL].n; i += nt) x_io[i * stride] = xs[i];
 }
 
 // dst = src (a no-op once `done` is set, like the kernels that produced src)
@@ -2894,40 +2898,41 @@ void prepare_coarse(const Hierarchy& H) {
 template <typename T, int K, int NL, int RPT, bool GEN>
 static void launch_coarse_cycle_reg(const Hierarchy& H, const T* b, T* x, bool x_init,
                                     double omega, int nu1, int nu2, int kind, bool gs,
-                                    const int* done, hipStream_t s) {
+                                    const int* done, int ncols, hipStream_t s) {
   const size_t bytes = coarse_lds_bytes<T>(H);
   const size_t int_off = coarse_int_offset<T>(H);
   const size_t inv_off = int_off - size_t(H.n0) * H.n0 * sizeof(double);
-  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL, RPT, GEN>), dim3(1), dim3(kCoarseThreads),
+  hipLaunchKernelGGL((k_coarse_cycle_reg<T, K, NL, RPT, GEN>), dim3(ncols), dim3(kCoarseThreads),
                      bytes, s, coarse_levels<T>(H), H.coarse_inv, H.n0, int32_t(inv_off), b, x,
-                     x_init ? 1 : 0, static_cast<T>(omega), nu1, nu2, kind, gs ? 1 : 0, done);
+                     x_init ? 1 : 0, static_cast<T>(omega), nu1, nu2, kind, gs ? 1 : 0, done,
+                     ncols);
 }
 template <typename T, int K, int RPT, bool GEN>
 static void coarse_cycle_reg(const Hierarchy& H, int top, const T* b, T* x, bool x_init,
                              double omega, int nu1, int nu2, int kind, bool gs, const int* done,
-                             hipStream_t s) {
+                             int ncols, hipStream_t s) {
   switch (top) {
-    case 1: launch_coarse_cycle_reg<T, K, 1, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
-    case 2: launch_coarse_cycle_reg<T, K, 2, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
-    case 3: launch_coarse_cycle_reg<T, K, 3, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
-    default: launch_coarse_cycle_reg<T, K, 4, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, s); break;
+    case 1: launch_coarse_cycle_reg<T, K, 1, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s); break;
+    case 2: launch_coarse_cycle_reg<T, K, 2, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s); break;
+    case 3: launch_coarse_cycle_reg<T, K, 3, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s); break;
+    default: launch_coarse_cycle_reg<T, K, 4, RPT, GEN>(H, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s); break;
   }
 }
 template <typename T, bool GEN>
 static void coarse_cycle_regs(const Hierarchy& H, int top, const T* b, T* x, bool x_init,
                               double omega, int nu1, int nu2, int kind, bool gs, const int* done,
-                              hipStream_t s) {
+                              hipStream_t s, int ncols = 1) {
   const bool one = H.lv[top]->n <= kCoarseThreads;
   if (H.coarse_width <= 4) {
     if (one)
-      coarse_cycle_reg<T, 4, 1, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+      coarse_cycle_reg<T, 4, 1, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s);
     else
-      coarse_cycle_reg<T, 4, 2, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+      coarse_cycle_reg<T, 4, 2, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s);
   } else {
     if (one)
-      coarse_cycle_reg<T, 8, 1, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+      coarse_cycle_reg<T, 8, 1, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s);
     else
-      coarse_cycle_reg<T, 8, 2, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+      coarse_cycle_reg<T, 8, 2, GEN>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, ncols, s);
   }
 }
 
@@ -2951,6 +2956,19 @@ void coarse_cycle_general(const Hierarchy& H, int top, const T* b, T* x, bool x_
                           double omega, int nu1, int nu2, int kind, bool gs, const int* done,
                           hipStream_t s) {
   coarse_cycle_regs<T, true>(H, top, b, x, x_init, omega, nu1, nu2, kind, gs, done, s);
+}
+
+template <typename T>
+void coarse_cycle_columns(const Hierarchy& H, int top, const T* b, T* x, bool x_init,
+                          double omega, int nu1, int nu2, int kind, int ncols, const int* done,
+                          hipStream_t s) {
+  if (!coarse_cycle_general_ok<T>(H, top, false))
+    throw std::logic_error("coarse_cycle_columns: levels do not fit the fused bottom");
+  if (!x_init && kind == MG_CYCLE_V)
+    coarse_cycle_regs<T, false>(H, top, b, x, false, omega, nu1, nu2, MG_CYCLE_V, false, done, s,
+                                ncols);
+  else
+    coarse_cycle_regs<T, true>(H, top, b, x, x_init, omega, nu1, nu2, kind, false, done, s, ncols);
 }
 
 template <typename T>
@@ -3181,6 +3199,8 @@ void sum_abs64(int32_t n, const double* v, double* part0, double* part1, hipStre
   template void coarse_cycle<T>(const Hierarchy&, int, const T*, T*, double, int, int, const int*, \
                                 hipStream_t);                                                  \
   template bool coarse_cycle_general_ok<T>(const Hierarchy&, int, bool);                         \
+  template void coarse_cycle_columns<T>(const Hierarchy&, int, const T*, T*, bool, double, int,    \
+                                        int, int, int, const int*, hipStream_t);                 \
   template void tile_down<T>(const Level&, const T*, T*, T*, double, int, const int*,         \
                              hipStream_t);                                                      \
   template void tile_up<T>(const Level&, const T*, const T*, const T*, T*, double, int,       \

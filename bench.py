@@ -55,6 +55,8 @@ def parse():
                    help="skip the FP64 MG-PCG timing on the level-7 icosphere")
     p.add_argument("--no-large", action="store_true",
                    help="skip the sweep rates on the 4097 x 4097 grid (working set > MALL)")
+    p.add_argument("--batch-tuning", default=None,
+                   help="with --only batch: max_cols,pad_groups,streams instead of the tuner")
     p.add_argument("--cpu-baseline-worker", type=int, default=0, help=argparse.SUPPRESS)
     return p.parse_args()
 
@@ -500,7 +502,7 @@ def large_sweeps(mg, W, torch, reps=20):
     return out
 
 
-def batch_bench(mg, W, torch, np, steps):
+def batch_bench(mg, W, torch, np, steps, fixed=None):
     """The 256-instance mix (icospheres of levels 4..7, squares of 33..513 vertices a side,
     seeded types), FP32-preconditioned FCG to 1e-10 for every instance, solved as one batch
     after the tuner has picked the grouping; aggregate unknowns per second."""
@@ -522,9 +524,14 @@ def batch_bench(mg, W, torch, np, steps):
     t_build = time.perf_counter() - t0
     xs = [torch.zeros_like(b) for b in bs]
     o = mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F32, rtol=1e-10)
-    bt = mg.mg_batch_create(hs, o)
     t0 = time.perf_counter()
-    chosen, tune_ms = mg.mg_batch_autotune(bt, bs, xs, reps=1)
+    if fixed:
+        # a given grouping (no tuner runs: for a kernel trace of the solves alone)
+        bt = mg.mg_batch_create(hs, o, mg.mg_batch_tuning(*fixed, 0))
+        chosen, _ = mg.mg_batch_info(bt)
+    else:
+        bt = mg.mg_batch_create(hs, o)
+        chosen, tune_ms = mg.mg_batch_autotune(bt, bs, xs, reps=1)
     t_tune = time.perf_counter() - t0
     _, ngroups = mg.mg_batch_info(bt)
     mg.mg_batch_solve(bt, bs, xs)
@@ -599,7 +606,9 @@ def main():
         elif a.only == "cubic":
             rec = cubic_bench(mg, W, torch, np, max(3, a.steps // 2))
         else:
-            rec = batch_bench(mg, W, torch, np, max(3, a.steps // 2))
+            fixed = (tuple(int(v) for v in a.batch_tuning.split(",")) if a.batch_tuning
+                     else None)
+            rec = batch_bench(mg, W, torch, np, max(3, a.steps // 2), fixed)
         print(json.dumps({"only": a.only, **rec}))
         return
     t0 = time.perf_counter()

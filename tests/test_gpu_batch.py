@@ -6,6 +6,8 @@
   1e-10 under the oracle's operator and agrees with the exact solve to 1e-8.
 * Different groupings (column widths 1..64, padded or exact groups, 1 or 4 streams) give the
   same solutions to 1e-12 and the same iteration counts.
+* W- and F-cycles (FP64) match the oracle's FCG with the same cycle: iteration counts and
+  1e-12.
 * The tuner returns a valid tuning, and a batch created from its cache file uses it.
 """
 import os
@@ -88,6 +90,24 @@ def test_batch_fp64_cycle_matches_oracle_fcg(mix):
         assert e <= 1e-12, (i, e)
         assert res[i].status == mg.MG_OK and res[i].rel_residual <= 1e-10
     print(f"[batch] FP64 cycle: {len(mix.kind)} instances match the oracle FCG")
+    mg.mg_batch_free(bt)
+
+
+@pytest.mark.parametrize("shape", ["W", "F"])
+def test_batch_cycle_shapes_match_oracle_fcg(mix, shape):
+    # W- and F-cycles: below the tiled levels the register-resident bottom runs once per column
+    # (stride-M access), the second coarse cycle of each visit starting from the first's result
+    kind = {"W": mg.MG_CYCLE_W, "F": mg.MG_CYCLE_F}[shape]
+    o = mg.mg_opts_default(outer=mg.MG_OUTER_FCG, precision=mg.MG_F64, cycle=kind)
+    bt = mg.mg_batch_create(mix.hs, o)
+    bs, xs = mix.tensors()
+    res = mg.mg_batch_solve(bt, bs, xs)
+    for i, k in enumerate(mix.kind):
+        xo, ko, _ = omg.mg_fcg(mix.o[k], mix.b[i], cycle=shape)
+        e = rel(host(xs[i]), xo)
+        assert res[i].iterations == ko, (i, res[i].iterations, ko)
+        assert e <= 1e-12, (i, e)
+    print(f"[batch] FP64 {shape}-cycle: {len(mix.kind)} instances match the oracle FCG")
     mg.mg_batch_free(bt)
 
 

@@ -117,6 +117,37 @@ def kernel_bytes(info, dtype_bytes, kind):
     return nnz * (ib + wb) + n * nvec * dtype_bytes
 
 
+def transfer_bytes(fine, coarse, dtype_bytes, kind):
+    """Algorithmic bytes of one per-step transfer launch between level `fine` and its coarse
+    level, each array read or written once: the restriction reads per coarse row the kept
+    vertex's id and its midpoint list (16-bit offsets or 32-bit ids, padded to the uniform
+    width), each fine residual entry once, and writes each coarse entry once; the interpolation
+    reads per fine row its two parents (one packed 32-bit word, or two 32-bit ids; plus a 32-bit
+    base per 64 rows when packed) and x, writes x, and reads each coarse entry once."""
+    nf, nc = fine["n_unknowns"], coarse["n_unknowns"]
+    if kind == "restrict":
+        ib = 2 if fine["restrict_offsets16"] else 4
+        return nc * (4 + fine["restrict_width"] * ib + dtype_bytes) + nf * dtype_bytes
+    if kind != "prolong":
+        raise ValueError(kind)
+    packed = fine["interp_packed16"]
+    return (nf * ((4 if packed else 8) + 2 * dtype_bytes) + nc * dtype_bytes
+            + (4 * ((nf + 63) // 64) if packed else 0))
+
+
+def transfer_rates(mg, H, level, reps):
+    """FP32 per-step restriction and interpolation of `level`, timed back to back."""
+    fine = mg.mg_hierarchy_info(H.h, level)
+    coarse = mg.mg_hierarchy_info(H.h, level - 1)
+    out = {}
+    for name, kern in (("restrict_fp32", mg.KERNEL_RESTRICT), ("prolong_fp32", mg.KERNEL_PROLONG)):
+        ms = mg.mg_time_kernel(H.h, kern, level, mg.MG_F32, reps)
+        by = transfer_bytes(fine, coarse, 4, name.split("_")[0])
+        out[name] = {"ms_per_launch": ms, "bytes_per_launch": by,
+                     "GB/s": by / (ms * 1e-3) / 1e9, "frac": by / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    return out
+
+
 def sweep_kernel_name(info):
     """The FP32 finest-level sweep's instantiation: over row patterns, or one or two rows per
     thread with int16 or int32 columns and binary16 or FP32 weights."""
@@ -494,6 +525,7 @@ def large_sweeps(mg, W, torch, reps=20):
                                "row_patterns": info["row_patterns"],
                                "weight_bytes": info["weight_bytes32" if nb == 4 else "weight_bytes64"]}
     rates("")
+    out.update(transfer_rates(mg, L, L.top, reps))
     g = torch.tensor(W.normal(L.nv(), 5), device="cuda:0")
     mg.mg_smooth(L.h, L.top, 20, 0.8, torch.zeros_like(g), g)
     mg.mg_hierarchy_set_log_coeff(L.h, g)
@@ -700,7 +732,9 @@ def main():
         print(f"[bench] 4097^2 finest sweeps: FP32 {large['fp32']['GB/s']:.0f} GB/s, FP64 "
               f"{large['fp64']['GB/s']:.0f} GB/s; general k: FP32 "
               f"{large['general_k_fp32']['GB/s']:.0f} GB/s, FP64 "
-              f"{large['general_k_fp64']['GB/s']:.0f} GB/s", file=sys.stderr, flush=True)
+              f"{large['general_k_fp64']['GB/s']:.0f} GB/s; transfers: restriction "
+              f"{large['restrict_fp32']['GB/s']:.0f} GB/s, interpolation "
+              f"{large['prolong_fp32']['GB/s']:.0f} GB/s", file=sys.stderr, flush=True)
 
     ms_step = 1e3 * total_m / a.steps
     value = unknowns / (total_m / a.steps)
@@ -721,7 +755,12 @@ def main():
     achieved = gbs(by_j32, ms_j32)
     print(f"[bench] probe: {n_probe} finest-level FP32 sweeps in {a.probe_steps} eager solves, "
           f"{1e3 * ms_j32:.2f} us each, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
-    others = {}
+    # the finest transfers back to back (the 2049^2 working sets fit in the MALL)
+    others = {"transfers_back_to_back": transfer_rates(mg, H, top, a.kernel_reps)}
+    tr = others["transfers_back_to_back"]
+    print(f"[bench] finest transfers back to back: restriction {tr['restrict_fp32']['GB/s']:.0f}"
+          f" GB/s, interpolation {tr['prolong_fp32']['GB/s']:.0f} GB/s", file=sys.stderr,
+          flush=True)
     if a.isolated:
         by_j64 = kernel_bytes(info, 8, "jacobi")
         by_a64 = kernel_bytes(info, 8, "spmv")

@@ -146,6 +146,9 @@ typedef struct {
                             offsets has at most 256 of them; 0: they read the SELL arrays.
                             Skipped when a DECMG_NO_ROW_PATTERNS environment variable is set
                             when the weights are built */
+  int32_t restrict_width;  /* entries (midpoints) of every list of the binary restriction onto
+                              level-1 when all its slices have one width, else -1 (also on the
+                              base level and weighted levels) */
 } mg_level_info;
 mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info* out);
 

@@ -61,7 +61,7 @@ class mg_level_info(ctypes.Structure):
                 ("weight_bytes32", ctypes.c_int32), ("weight_bytes64", ctypes.c_int32),
                 ("uniform_width", ctypes.c_int32), ("rows_per_thread", ctypes.c_int32),
                 ("interp_packed16", ctypes.c_int32), ("restrict_offsets16", ctypes.c_int32),
-                ("row_patterns", ctypes.c_int32)]
+                ("row_patterns", ctypes.c_int32), ("restrict_width", ctypes.c_int32)]
 
 
 class mg_opts(ctypes.Structure):

@@ -186,7 +186,7 @@ void sync_check(hipStream_t s) {
 extern "C" {
 
 const char* mg_last_error(void) { return g_err.c_str(); }
-int32_t mg_abi_version(void) { return 3; }
+int32_t mg_abi_version(void) { return 4; }
 
 mg_status dec_mesh_from_arrays(int64_t nv, const double* xyz, int64_t nt, const int32_t* tri,
                                dec_mesh** out) {
@@ -326,6 +326,7 @@ mg_status mg_hierarchy_info(const mg_hierarchy* h, int32_t level, mg_level_info*
   out->index_bytes = L.op.col16 ? 2 : 4;
   out->scheme = L.mesh.scheme;
   out->row_patterns = L.op.npat;
+  out->restrict_width = (level >= 1 && !L.tr.weighted) ? L.tr.r_uw : -1;
   out->fused_tiles = L.tiles.ntiles;
   out->fused_tile_rows = int32_t(L.tiles.rows_total);
   out->weight_bytes32 = L.op.w_exact16 ? 2 : 4;

@@ -18,7 +18,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert set(names) == set(mg._PROTOS), set(names) ^ set(mg._PROTOS)
-    assert L.mg_abi_version() == 3
+    assert L.mg_abi_version() == 4
 
 
 def test_opts_default():
@@ -35,9 +35,10 @@ def test_struct_layouts_match_the_header(tmp_path):
     src = tmp_path / "layout.cpp"
     src.write_text(
         '#include <cstddef>\n#include <cstdio>\n#include "decmg.h"\n'
-        "int main() { std::printf(\"%zu %zu %zu %zu %zu\\n\", sizeof(mg_opts),\n"
+        "int main() { std::printf(\"%zu %zu %zu %zu %zu %zu %zu\\n\", sizeof(mg_opts),\n"
         "  offsetof(mg_opts, stall_checks), sizeof(mg_result), offsetof(mg_result, history_len),\n"
-        "  offsetof(mg_result, fp64_fallback)); }\n")
+        "  offsetof(mg_result, fp64_fallback), sizeof(mg_level_info),\n"
+        "  offsetof(mg_level_info, restrict_width)); }\n")
     exe = tmp_path / "layout"
     inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
     subprocess.run([cxx, "-std=c++17", f"-I{inc}", str(src), "-o", str(exe)], check=True)
@@ -45,7 +46,8 @@ def test_struct_layouts_match_the_header(tmp_path):
                                           check=True).stdout.split()]
     assert got == [ctypes.sizeof(mg.mg_opts), mg.mg_opts.stall_checks.offset,
                    ctypes.sizeof(mg.mg_result), mg.mg_result.history_len.offset,
-                   mg.mg_result.fp64_fallback.offset]
+                   mg.mg_result.fp64_fallback.offset, ctypes.sizeof(mg.mg_level_info),
+                   mg.mg_level_info.restrict_width.offset]
 
 
 def test_debug_flags_validated():

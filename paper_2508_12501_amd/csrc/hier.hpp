@@ -225,7 +225,8 @@ struct DevScalars {
   double true_rnorm;   // ||b - A x|| recomputed at exit
   int32_t done, iters, status, max_iter;
   double* hist;        // relative residual of the loop after each iteration (device), or null
-  int32_t hist_cap, pad_;
+  int32_t hist_cap;
+  int32_t pbuf;        // direction buffer (0 first, 1 second) of the pending step x += alpha p
 };
 
 // Finest-level data of the porous-convection step and of the solve gradients (built on first
@@ -416,10 +417,12 @@ int red_blocks(int32_t n);   // grid (= number of partials) of the streaming red
 int pupd_spmv_partials(const Level& L);
 void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
-                    const double* r, double* part0, double* part1, const int* done,
+                    const double* r, double* x, double* part0, double* part1, const int* done,
                     hipStream_t s);
-void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
-               double* r, float* r32, double* part0, const int* done, hipStream_t s);
+void update_r(int32_t n, const DevScalars* sc, const double* q, double* r, float* r32,
+              double* part0, const int* done, hipStream_t s);
+void apply_pending(int32_t n, const DevScalars* sc, const double* p0, const double* p1, double* x,
+                   hipStream_t s);
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s);
 void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s);

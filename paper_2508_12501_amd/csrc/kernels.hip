@@ -1811,22 +1811,28 @@ __device__ __forceinline__ void row_pnew_n(const void* __restrict__ col, const W
 // The direction update of (flexible) CG folded into its operator product: p = z + beta p_old
 // is formed at the row and again at each neighbour, q = A p, and the block partials of p.q and
 // p.r.  p goes to a second buffer (neighbours still read p_old) and is never read back here,
-// which saves the separate update pass and one write-then-read of p.
+// which saves the separate update pass and one write-then-read of p.  The previous
+// iteration's solution step x += alpha p_old is taken here too, where p_old is read anyway
+// (alpha still holds that iteration's step length; it is 0 when no step is pending).
 template <typename ZT, bool D16, typename WT>
 __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
     const int32_t* __restrict__ sptr, int32_t uw, const void* __restrict__ col,
     const WT* __restrict__ w, const DevScalars* __restrict__ sc, const ZT* __restrict__ z,
     int sub_mean, const double* __restrict__ po, double* __restrict__ pn,
-    double* __restrict__ q, const double* __restrict__ r, double* __restrict__ part0,
-    double* __restrict__ part1, int32_t n, const int* __restrict__ done) {
+    double* __restrict__ q, const double* __restrict__ r, double* __restrict__ x,
+    double* __restrict__ part0, double* __restrict__ part1, int32_t n,
+    const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
   const int row = blk * kBlock + threadIdx.x;
   double v0 = 0.0, v1 = 0.0;
   if (row < n) {
     const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
-    const double pi = mac(beta, po[row], z_val(z[row], s, m, sub_mean != 0));
+    const double ax = sc->alpha;
+    const double pold = po[row], xi = x[row];
+    const double pi = mac(beta, pold, z_val(z[row], s, m, sub_mean != 0));
     const double ri = r[row];
+    x[row] = mac(ax, pold, xi);
     int beg, width;
     slice_bounds(sptr, uw, row, beg, width);
     const int lane = row & 63;
@@ -1870,17 +1876,18 @@ __device__ __forceinline__ void pupd_spmv_dot2_2_body(
     const uint8_t* __restrict__ pat, int npat, const DevScalars* __restrict__ sc,
     const ZT* __restrict__ z, int sub_mean, const double* __restrict__ po,
     double* __restrict__ pn, double* __restrict__ q, const double* __restrict__ r,
-    double* __restrict__ part0, double* __restrict__ part1, int32_t n,
+    double* __restrict__ x, double* __restrict__ part0, double* __restrict__ part1, int32_t n,
     const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
   const int r0 = blk * (2 * kBlock) + threadIdx.x;
   const bool live = r0 < n;
   const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
+  const double ax = sc->alpha;
   const bool sm = sub_mean != 0;
   int r1 = 0, e0 = 0, e1 = 0;
   ZT z0 = ZT(0), z1 = ZT(0);
-  double o0 = 0.0, o1 = 0.0, q0r = 0.0, q1r = 0.0;
+  double o0 = 0.0, o1 = 0.0, q0r = 0.0, q1r = 0.0, x0 = 0.0, x1 = 0.0;
   if (live) {
     r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
     e0 = row_first<PAT>(pat, r0, uw);
@@ -1891,6 +1898,8 @@ __device__ __forceinline__ void pupd_spmv_dot2_2_body(
     z1 = z[r1];
     q0r = r[r0];
     q1r = r[r1];
+    x0 = x[r0];
+    x1 = x[r1];
   }
   if constexpr (PAT) {   // the row loads above are in flight meanwhile
     const int16_t* so;
@@ -1909,11 +1918,13 @@ __device__ __forceinline__ void pupd_spmv_dot2_2_body(
                            d0, a1, d1);
     pn[r0] = p0;
     q[r0] = a0;
+    x[r0] = mac(ax, o0, x0);
     v0 = p0 * a0;
     v1 = p0 * q0r;
     if (r1 != r0) {
       pn[r1] = p1;
       q[r1] = a1;
+      x[r1] = mac(ax, o1, x1);
       v0 += p1 * a1;
       v1 += p1 * q1r;
     }
@@ -1929,10 +1940,10 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2(
     int32_t uw, const void* __restrict__ col, const WT* __restrict__ w,
     const DevScalars* __restrict__ sc, const ZT* __restrict__ z, int sub_mean,
     const double* __restrict__ po, double* __restrict__ pn, double* __restrict__ q,
-    const double* __restrict__ r, double* __restrict__ part0, double* __restrict__ part1,
-    int32_t n, const int* __restrict__ done) {
+    const double* __restrict__ r, double* __restrict__ x, double* __restrict__ part0,
+    double* __restrict__ part1, int32_t n, const int* __restrict__ done) {
   pupd_spmv_dot2_2_body<ZT, D16, WT, false>(uw, col, w, nullptr, 0, sc, z, sub_mean, po, pn, q,
-                                            r, part0, part1, n, done);
+                                            r, x, part0, part1, n, done);
 }
 // over row patterns (see k_rows2p)
 template <typename ZT>
@@ -1941,20 +1952,20 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2p(
     const uint8_t* __restrict__ pat, int npat, const DevScalars* __restrict__ sc,
     const ZT* __restrict__ z, int sub_mean, const double* __restrict__ po,
     double* __restrict__ pn, double* __restrict__ q, const double* __restrict__ r,
-    double* __restrict__ part0, double* __restrict__ part1, int32_t n,
+    double* __restrict__ x, double* __restrict__ part0, double* __restrict__ part1, int32_t n,
     const int* __restrict__ done) {
   pupd_spmv_dot2_2_body<ZT, true, double, true>(uw, off, w, pat, npat, sc, z, sub_mean, po, pn,
-                                                q, r, part0, part1, n, done);
+                                                q, r, x, part0, part1, n, done);
 }
 
-__global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalars* __restrict__ sc,
-                                                      const double* __restrict__ p,
-                                                      const double* __restrict__ q,
-                                                      double* __restrict__ x,
-                                                      double* __restrict__ r,
-                                                      float* __restrict__ r32,
-                                                      double* __restrict__ part0,
-                                                      const int* __restrict__ done) {
+// r -= alpha q, its FP32 copy for the next cycle and the block partials of r.r (x takes the
+// step in the next direction update, or in k_apply_pending when the loop ends first)
+__global__ __launch_bounds__(kBlock) void k_update_r(int32_t n, const DevScalars* __restrict__ sc,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ r,
+                                                     float* __restrict__ r32,
+                                                     double* __restrict__ part0,
+                                                     const int* __restrict__ done) {
   if (*done) return;
   const int blk = xcd_block();
   int t0, t1;
@@ -1964,12 +1975,10 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
   int t = t0;
   // four tiles' loads in flight before any of them is used (same order of summation)
   for (; t + 4 <= t1; t += 4) {
-    double xv[4], pv[4], rv[4], qv[4];
+    double rv[4], qv[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int i = min((t + u) * kBlock + static_cast<int>(threadIdx.x), n - 1);
-      xv[u] = x[i];
-      pv[u] = p[i];
       rv[u] = r[i];
       qv[u] = q[i];
     }
@@ -1977,7 +1986,6 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
     for (int u = 0; u < 4; ++u) {
       const int i = (t + u) * kBlock + threadIdx.x;
       if (i < n) {
-        x[i] = xv[u] + a * pv[u];
         const double ri = rv[u] - a * qv[u];
         r[i] = ri;
         v += ri * ri;
@@ -1988,7 +1996,6 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
   for (; t < t1; ++t) {
     const int i = t * kBlock + threadIdx.x;
     if (i < n) {
-      x[i] = x[i] + a * p[i];
       const double ri = r[i] - a * q[i];
       r[i] = ri;
       v += ri * ri;
@@ -1997,6 +2004,22 @@ __global__ __launch_bounds__(kBlock) void k_update_xr(int32_t n, const DevScalar
   }
   v = block_sum1(v);
   if (threadIdx.x == 0) part0[blk] = v;
+}
+
+// The solution step still pending when the loop ends: x += alpha p with p the direction
+// buffer the last direction update wrote (sc->pbuf).  alpha = 0 means none is pending (set so
+// by the start, by a breakdown of the step length, and by the end-of-solve finalisation once
+// the step is taken), which also keeps a direction left non-finite by a breakdown out of x.
+__global__ __launch_bounds__(kBlock) void k_apply_pending(int32_t n,
+                                                          const DevScalars* __restrict__ sc,
+                                                          const double* __restrict__ p0,
+                                                          const double* __restrict__ p1,
+                                                          double* __restrict__ x) {
+  const double a = sc->alpha;
+  if (a == 0.0) return;
+  const double* __restrict__ p = sc->pbuf ? p1 : p0;
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i < n) x[i] = mac(a, p[i], x[i]);
 }
 
 template <bool D16, typename WT = double>
@@ -2394,13 +2417,17 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       }
       break;
     }
+    // extra: the direction buffer (0 or 1) that holds this iteration's p, which the pending
+    // solution step x += alpha p reads; on a breakdown no step is pending (alpha = 0)
     case k::FIN_ALPHA_CG:
       sc->pq = a;
       if (!(a > 0.0) || !isfinite(a)) {
         sc->status = isfinite(a) ? MG_EBREAKDOWN : MG_ENONFINITE;
         sc->done = 1;
+        sc->alpha = 0.0;
       } else {
         sc->alpha = rho / a;
+        sc->pbuf = extra != 0.0 ? 1 : 0;
       }
       break;
     case k::FIN_ALPHA_FCG:
@@ -2408,8 +2435,10 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
         sc->status = (isfinite(a) && isfinite(b)) ? MG_EBREAKDOWN : MG_ENONFINITE;
         sc->done = 1;
+        sc->alpha = 0.0;
       } else {
         sc->alpha = b / a;
+        sc->pbuf = extra != 0.0 ? 1 : 0;
       }
       break;
     case k::FIN_CHECK: {
@@ -2461,7 +2490,9 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       }
       break;
     case k::FIN_RNORM:
+      // ends the exit work, which took the pending solution step first
       sc->true_rnorm = sqrt(a);
+      sc->alpha = 0.0;
       break;
   }
 }
@@ -3032,18 +3063,18 @@ int pupd_spmv_partials(const Level& L) {
 }
 void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
-                    const double* r, double* part0, double* part1, const int* done,
+                    const double* r, double* x, double* part0, double* part1, const int* done,
                     hipStream_t s) {
   if (row_patterns(L)) {
     if (z32)
       hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<float>), dim3(grid2_for(L.n)), dim3(kBlock),
                          pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat,
-                         L.op.npat, sc, z32, sub_mean_flag, p_old, p_new, q, r, part0, part1,
+                         L.op.npat, sc, z32, sub_mean_flag, p_old, p_new, q, r, x, part0, part1,
                          L.n, done);
     else
       hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<double>), dim3(grid2_for(L.n)), dim3(kBlock),
                          pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat,
-                         L.op.npat, sc, z64, sub_mean_flag, p_old, p_new, q, r, part0, part1,
+                         L.op.npat, sc, z64, sub_mean_flag, p_old, p_new, q, r, x, part0, part1,
                          L.n, done);
     return;
   }
@@ -3055,21 +3086,21 @@ void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, cons
         if (L.op.col16)
           hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, true, WT>), dim3(grid2_for(L.n)),
                              dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col16), w,
-                             sc, zp, sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+                             sc, zp, sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
         else
           hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, false, WT>), dim3(grid2_for(L.n)),
                              dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col), w,
-                             sc, zp, sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+                             sc, zp, sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
         return;
       }
       if (L.op.col16)
         hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0,
                            s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, sc, zp,
-                           sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+                           sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
       else
         hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, false, WT>), dim3(grid_for(L.n)), dim3(kBlock),
                            0, s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, sc, zp,
-                           sub_mean_flag, p_old, p_new, q, r, part0, part1, L.n, done);
+                           sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
     };
     if (z32)
       go(z32);
@@ -3077,10 +3108,14 @@ void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, cons
       go(z64);
   });
 }
-void update_xr(int32_t n, const DevScalars* sc, const double* p, const double* q, double* x,
-               double* r, float* r32, double* part0, const int* done, hipStream_t s) {
-  hipLaunchKernelGGL(k_update_xr, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, p, q, x, r, r32,
-                     part0, done);
+void update_r(int32_t n, const DevScalars* sc, const double* q, double* r, float* r32,
+              double* part0, const int* done, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_r, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, q, r, r32, part0,
+                     done);
+}
+void apply_pending(int32_t n, const DevScalars* sc, const double* p0, const double* p1, double* x,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_pending, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, p0, p1, x);
 }
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s) {

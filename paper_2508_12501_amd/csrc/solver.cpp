@@ -306,11 +306,13 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   // singular systems; an FP64 z has it subtracted already unless the sums were fused)
   const double* p_old = parity ? H.sp2 : H.sp;
   double* p_new = parity ? H.sp : H.sp2;
+  // the previous iteration's step x += alpha p_old is taken inside the direction update; this
+  // iteration's is left pending (alpha, and the buffer of p_new) for the next one or the exit
   k::pupd_spmv_dot2(F, H.scal, z32, z32 ? nullptr : z, z32 ? (natural ? 1 : 0) : (fused_mean ? 1 : 0),
-                    p_old, p_new, H.sq, H.sr, P0, P1, done, s);
+                    p_old, p_new, H.sq, H.sr, H.sx, P0, P1, done, s);
   k::finalize(o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG,
-              k::pupd_spmv_partials(F), P0, P1, H.scal, 0.0, 0, s);
-  k::update_xr(n, H.scal, p_new, H.sq, H.sx, H.sr, r32, P0, done, s);
+              k::pupd_spmv_partials(F), P0, P1, H.scal, p_new == H.sp2 ? 1.0 : 0.0, 0, s);
+  k::update_r(n, H.scal, H.sq, H.sr, r32, P0, done, s);
   fin(H, k::FIN_CHECK, n, false, s);
 }
 
@@ -394,13 +396,18 @@ void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_comp
   }
 }
 
-// Final projection, true residual, scatter to the caller's numbering (kernels only).  Without
-// the projection (Dirichlet systems) it only reads x, so it can be enqueued after every batch
-// of iterations and simply runs again after more of them; on singular systems it projects x
-// in place, which would change the rounding of later iterations, so it runs once at the end.
+// Pending solution step, final projection, true residual, scatter to the caller's numbering
+// (kernels only).  Without the projection (Dirichlet systems) it changes x only by the step
+// the next iteration would take in the same expression, so it can be enqueued after every
+// batch of iterations and simply runs again after more of them; on singular systems it
+// projects x in place, which would change the rounding of later iterations, so it runs once at
+// the end.
 void enqueue_finish(Hierarchy& H, const double* b_nat, double* x_nat, hipStream_t s) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
+  // the solution step of the last CG/FCG iteration (a no-op when none is pending; FIN_RNORM
+  // below clears it, so running the finish again takes it only once)
+  k::apply_pending(n, H.scal, H.sp, H.sp2, H.sx, s);
   if (H.bc == MG_BC_NATURAL) {
     k::sum64(n, H.sx, H.part, nullptr, s);
     fin(H, k::FIN_MEAN, n, false, s, false, true);

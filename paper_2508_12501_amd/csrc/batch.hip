@@ -22,7 +22,7 @@ namespace decmg {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kFin = 1024;
+constexpr int kFin = 256;    // threads of the per-column finaliser
 constexpr int kMaxRed = 1024;   // cap on workgroups (partials per column) of a reduction
 
 __device__ __forceinline__ int xcd_blk() {
@@ -46,7 +46,8 @@ __device__ __forceinline__ int colx(const void* __restrict__ col, int idx, int r
   return static_cast<const int32_t*>(col)[idx];
 }
 
-// Per-column block reduction of up to two values; threads t < M write part[blk * M + t].
+// Per-column block reduction of up to two values; threads t < M write part[t * nb + blk]
+// (nb = gridDim.x: each column's partials are contiguous, for the per-column finaliser).
 template <int M>
 __device__ __forceinline__ void block_cols(double v0, double v1, double* part0, double* part1,
                                            int blk) {
@@ -60,8 +61,8 @@ __device__ __forceinline__ void block_cols(double v0, double v1, double* part0, 
       a += s0[j * M + threadIdx.x];
       if (part1) b += s1[j * M + threadIdx.x];
     }
-    part0[blk * M + threadIdx.x] = a;
-    if (part1) part1[blk * M + threadIdx.x] = b;
+    part0[threadIdx.x * gridDim.x + blk] = a;
+    if (part1) part1[threadIdx.x * gridDim.x + blk] = b;
   }
 }
 
@@ -517,7 +518,7 @@ __global__ __launch_bounds__(kThreads) void bk_nat_sumsq(int M, int ncols, int32
   if (threadIdx.x == 0) {
     double a = 0.0;
     for (int j = 0; j < kThreads; ++j) a += s[j];
-    part[blockIdx.x * M + c] = a;
+    part[c * gridDim.x + blockIdx.x] = a;
   }
 }
 
@@ -702,8 +703,8 @@ __device__ __forceinline__ void block_cols_v(const double (&v0)[kKV], const doub
       a += s0[(j * TPR + tc) * kKV + e];
       if (part1) b += s1[(j * TPR + tc) * kKV + e];
     }
-    part0[blk * M + c] = a;
-    if (part1) part1[blk * M + c] = b;
+    part0[c * gridDim.x + blk] = a;
+    if (part1) part1[c * gridDim.x + blk] = b;
   }
 }
 
@@ -921,122 +922,124 @@ __global__ void bk_init(BatchCol* __restrict__ col, BatchFlag* __restrict__ flag
     z.done = c < ncols ? 0 : 1;
     col[c] = z;
   }
-  if (c == 0) flag->all_done = ncols > 0 ? 0 : 1;
+  if (c == 0) {
+    flag->all_done = ncols > 0 ? 0 : 1;
+    flag->n_done = M - ncols;
+  }
 }
 
-// One workgroup: per column, sum the nb partials of part0 (and part1), then apply `op`.
+// One workgroup per column c: sum its nb partials part0[c nb ..] (and part1's) in a fixed
+// order, then apply `op` to the column.  A column that becomes finished adds itself to
+// flag->n_done; the workgroup that completes the count sets flag->all_done, which the later
+// launches of the group test (a workgroup of this launch that misses it only finds its column
+// finished).
 __global__ __launch_bounds__(kFin) void bk_finalize(int op, int M, int nb,
                                                     const double* __restrict__ part0,
                                                     const double* __restrict__ part1,
                                                     BatchCol* __restrict__ col,
                                                     BatchFlag* __restrict__ flag, int force) {
   if (!force && flag->all_done) return;
-  const int J = kFin / M;
-  const int c = threadIdx.x % M, j = threadIdx.x / M;
+  const int c = blockIdx.x;
+  const double* __restrict__ p0 = part0 + static_cast<size_t>(c) * nb;
+  const double* __restrict__ p1 = part1 ? part1 + static_cast<size_t>(c) * nb : nullptr;
   double a = 0.0, b = 0.0;
-  // thread (c, j) sums blocks j, j + J, j + 2J, ... in that order; the loads go out eight at a
-  // time so that their latencies overlap
-  for (int base = j; base < nb; base += 8 * J) {
-    double va[8], vb[8];
+  // thread t sums partials t, t + kFin, ... in that order, four loads in flight at a time
+  for (int base = threadIdx.x; base < nb; base += 4 * kFin) {
+    double va[4], vb[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int blk = base + q * J;
-      const int bc = blk < nb ? blk : nb - 1;
-      va[q] = part0[bc * M + c];
-      vb[q] = part1 ? part1[bc * M + c] : 0.0;
-      if (blk >= nb) {
+    for (int q = 0; q < 4; ++q) {
+      const int i = base + q * kFin;
+      const int ic = i < nb ? i : nb - 1;
+      va[q] = p0[ic];
+      vb[q] = p1 ? p1[ic] : 0.0;
+      if (i >= nb) {
         va[q] = 0.0;
         vb[q] = 0.0;
       }
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 4; ++q) {
       a += va[q];
       b += vb[q];
     }
   }
   __shared__ double sa[kFin], sb[kFin];
-  __shared__ int sdone[kBatchMaxCols];
   sa[threadIdx.x] = a;
   sb[threadIdx.x] = b;
-  __syncthreads();
-  if (j == 0) {
-    a = 0.0;
-    b = 0.0;
-    for (int q = 0; q < J; ++q) {
-      a += sa[q * M + c];
-      b += sb[q * M + c];
+  for (int h = kFin / 2; h > 0; h >>= 1) {
+    __syncthreads();
+    if (static_cast<int>(threadIdx.x) < h) {
+      sa[threadIdx.x] += sa[threadIdx.x + h];
+      sb[threadIdx.x] += sb[threadIdx.x + h];
     }
-    BatchCol& cc = col[c];
-    const bool live = force || !cc.done;
-    if (live) {
-      switch (op) {
-        case bk::FIN_BNORM: {
-          const double bn = sqrt(a);
-          cc.bnorm = bn;
-          cc.rnorm = bn;
-          if (!isfinite(bn)) {
-            cc.status = MG_ENONFINITE;
-            cc.done = 1;
-          } else if (bn == 0.0) {
-            cc.status = MG_OK;
-            cc.done = 1;
-          } else {
-            int e;
-            frexp(bn / sqrt(cc.n_unknowns), &e);
-            cc.scale = ldexp(1.0, -e);
-            cc.inv_scale = ldexp(1.0, e);
-          }
-          break;
+  }
+  if (threadIdx.x != 0) return;
+  a = sa[0];
+  b = sb[0];
+  BatchCol& cc = col[c];
+  const int was_done = cc.done;
+  const bool live = force || !was_done;
+  if (live) {
+    switch (op) {
+      case bk::FIN_BNORM: {
+        const double bn = sqrt(a);
+        cc.bnorm = bn;
+        cc.rnorm = bn;
+        if (!isfinite(bn)) {
+          cc.status = MG_ENONFINITE;
+          cc.done = 1;
+        } else if (bn == 0.0) {
+          cc.status = MG_OK;
+          cc.done = 1;
+        } else {
+          int e;
+          frexp(bn / sqrt(cc.n_unknowns), &e);
+          cc.scale = ldexp(1.0, -e);
+          cc.inv_scale = ldexp(1.0, e);
         }
-        case bk::FIN_ALPHA_FCG:
-          cc.pq = a;
-          if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
-            cc.status = (isfinite(a) && isfinite(b)) ? MG_EBREAKDOWN : MG_ENONFINITE;
-            cc.done = 1;
-          } else {
-            cc.alpha = b / a;
-          }
-          break;
-        case bk::FIN_CHECK: {
-          const double rn = sqrt(a);
-          cc.rnorm = rn;
-          cc.iters += 1;
-          if (!isfinite(rn)) {
-            cc.status = MG_ENONFINITE;
-            cc.done = 1;
-          } else if (rn <= cc.rtol * cc.bnorm) {
-            cc.status = MG_OK;
-            cc.done = 1;
-          } else if (cc.iters >= cc.max_iter) {
-            cc.status = MG_ENOCONV;
-            cc.done = 1;
-          }
-          break;
-        }
-        case bk::FIN_BETA_FCG:
-          cc.beta = -a / cc.pq;
-          if (!isfinite(cc.beta)) {
-            cc.status = MG_ENONFINITE;
-            cc.done = 1;
-          }
-          break;
-        case bk::FIN_MEAN:
-          cc.mean = a / cc.n_unknowns;
-          break;
-        case bk::FIN_RNORM:
-          cc.true_rnorm = sqrt(a);
-          break;
+        break;
       }
+      case bk::FIN_ALPHA_FCG:
+        cc.pq = a;
+        if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
+          cc.status = (isfinite(a) && isfinite(b)) ? MG_EBREAKDOWN : MG_ENONFINITE;
+          cc.done = 1;
+        } else {
+          cc.alpha = b / a;
+        }
+        break;
+      case bk::FIN_CHECK: {
+        const double rn = sqrt(a);
+        cc.rnorm = rn;
+        cc.iters += 1;
+        if (!isfinite(rn)) {
+          cc.status = MG_ENONFINITE;
+          cc.done = 1;
+        } else if (rn <= cc.rtol * cc.bnorm) {
+          cc.status = MG_OK;
+          cc.done = 1;
+        } else if (cc.iters >= cc.max_iter) {
+          cc.status = MG_ENOCONV;
+          cc.done = 1;
+        }
+        break;
+      }
+      case bk::FIN_BETA_FCG:
+        cc.beta = -a / cc.pq;
+        if (!isfinite(cc.beta)) {
+          cc.status = MG_ENONFINITE;
+          cc.done = 1;
+        }
+        break;
+      case bk::FIN_MEAN:
+        cc.mean = a / cc.n_unknowns;
+        break;
+      case bk::FIN_RNORM:
+        cc.true_rnorm = sqrt(a);
+        break;
     }
-    sdone[c] = cc.done;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int all = 1;
-    for (int q = 0; q < M; ++q) all &= (sdone[q] != 0);
-    flag->all_done = all;
-  }
+  if (!was_done && cc.done && atomicAdd(&flag->n_done, 1) == M - 1) flag->all_done = 1;
 }
 
 __global__ void bk_fill(uint32_t* __restrict__ p, size_t n) {
@@ -1112,7 +1115,7 @@ void init_cols(BatchCol* col, BatchFlag* flag, int M, int ncols, double rtol, in
 
 void finalize(int op, int M, int nb, const double* part0, const double* part1, BatchCol* col,
               BatchFlag* flag, int force, hipStream_t s) {
-  hipLaunchKernelGGL(bk_finalize, dim3(1), dim3(kFin), 0, s, op, M, nb, part0, part1, col, flag,
+  hipLaunchKernelGGL(bk_finalize, dim3(M), dim3(kFin), 0, s, op, M, nb, part0, part1, col, flag,
                      force);
 }
 

@@ -27,8 +27,9 @@ struct BatchCol {
 };
 
 struct BatchFlag {
-  int32_t all_done;
-  int32_t pad[63];
+  int32_t all_done;   // every column finished: the group's launches return at once
+  int32_t n_done;     // finished columns (padding included)
+  int32_t pad[62];
 };
 
 template <typename T>

@@ -142,7 +142,7 @@ void enqueue_iter(const mg_opts& o, BatchGroup& G, hipStream_t s) {
     }
     bk::zdot<float>(M, n, G.col, z, G.Q, P0, nb, natural, fl, s);
     bk::finalize(bk::FIN_BETA_FCG, M, nb, P0, nullptr, G.col, fl, 0, s);
-    bk::pupd<float>(M, n, G.col, z, G.P, natural, fl, s);
+    bk::pupd<float>(M, n, G.col, z, G.P, G.X, natural, fl, s);
   } else {
     double* z = cycle_b<double>(o, G, top, G.R, nullptr, o.cycle, s);
     if (natural) {
@@ -151,11 +151,11 @@ void enqueue_iter(const mg_opts& o, BatchGroup& G, hipStream_t s) {
     }
     bk::zdot<double>(M, n, G.col, z, G.Q, P0, nb, natural, fl, s);
     bk::finalize(bk::FIN_BETA_FCG, M, nb, P0, nullptr, G.col, fl, 0, s);
-    bk::pupd<double>(M, n, G.col, z, G.P, natural, fl, s);
+    bk::pupd<double>(M, n, G.col, z, G.P, G.X, natural, fl, s);
   }
   bk::spmv_dot2(M, F, G.P, G.Q, G.R, P0, P1, nb, fl, s);
   bk::finalize(bk::FIN_ALPHA_FCG, M, nb, P0, P1, G.col, fl, 0, s);
-  bk::update_xr(M, n, G.col, G.P, G.Q, G.X, G.R, r32, P0, nb, fl, s);
+  bk::update_r(M, n, G.col, G.Q, G.R, r32, P0, nb, fl, s);
   bk::finalize(bk::FIN_CHECK, M, nb, P0, nullptr, G.col, fl, 0, s);
 }
 
@@ -190,6 +190,7 @@ void enqueue_finish(BatchGroup& G, hipStream_t s) {
   const int32_t n = F.n;
   const int M = G.M;
   const int nb = bk::red_blocks(n, M);
+  bk::apply_pending(M, n, G.col, G.P, G.X, s);   // each column's last solution step
   if (H.bc == MG_BC_NATURAL) {
     bk::colsum(M, n, G.X, G.part, nb, nullptr, s);
     bk::finalize(bk::FIN_MEAN, M, nb, G.part, nullptr, G.col, G.flag, 1, s);

@@ -632,7 +632,7 @@ __global__ __launch_bounds__(kThreads) void bk_zdot(int32_t n, const BatchCol* _
 template <typename T, int M>
 __global__ __launch_bounds__(kThreads) void bk_pupd(int32_t n, const BatchCol* __restrict__ col,
                                                     const T* __restrict__ z, double* __restrict__ p,
-                                                    int sub_mean,
+                                                    double* __restrict__ x, int sub_mean,
                                                     const BatchFlag* __restrict__ flag) {
   if (flag->all_done) return;
   BK_ROWCOL(M)
@@ -640,7 +640,9 @@ __global__ __launch_bounds__(kThreads) void bk_pupd(int32_t n, const BatchCol* _
   const BatchCol& cc = col[c];
   if (cc.done) return;
   const int k = row * M + c;
-  p[k] = bmac(cc.beta, p[k], zval<T>(z, k, cc, sub_mean));
+  const double po = p[k];
+  x[k] = bmac(cc.alpha, po, x[k]);
+  p[k] = bmac(cc.beta, po, zval<T>(z, k, cc, sub_mean));
 }
 
 template <bool D16, int M, typename WT>
@@ -735,7 +737,8 @@ __global__ __launch_bounds__(kThreads) void bk_zdot_v(int32_t n, const BatchCol*
 template <typename T, int M>
 __global__ __launch_bounds__(kThreads) void bk_pupd_v(int32_t n, const BatchCol* __restrict__ col,
                                                       const T* __restrict__ z,
-                                                      double* __restrict__ p, int sub_mean,
+                                                      double* __restrict__ p,
+                                                      double* __restrict__ x, int sub_mean,
                                                       const BatchFlag* __restrict__ flag) {
   constexpr int TPR = M / kKV, RBV = kThreads / TPR;
   if (flag->all_done) return;
@@ -747,8 +750,16 @@ __global__ __launch_bounds__(kThreads) void bk_pupd_v(int32_t n, const BatchCol*
   if (ca.done && cb.done) return;
   const int k = row * M + c0;
   D2 pv = *reinterpret_cast<const D2*>(p + k);
-  if (!ca.done) pv.v[0] = bmac(ca.beta, pv.v[0], zval<T>(z, k, ca, sub_mean));
-  if (!cb.done) pv.v[1] = bmac(cb.beta, pv.v[1], zval<T>(z, k + 1, cb, sub_mean));
+  D2 xv = *reinterpret_cast<const D2*>(x + k);
+  if (!ca.done) {
+    xv.v[0] = bmac(ca.alpha, pv.v[0], xv.v[0]);
+    pv.v[0] = bmac(ca.beta, pv.v[0], zval<T>(z, k, ca, sub_mean));
+  }
+  if (!cb.done) {
+    xv.v[1] = bmac(cb.alpha, pv.v[1], xv.v[1]);
+    pv.v[1] = bmac(cb.beta, pv.v[1], zval<T>(z, k + 1, cb, sub_mean));
+  }
+  *reinterpret_cast<D2*>(x + k) = xv;
   *reinterpret_cast<D2*>(p + k) = pv;
 }
 
@@ -811,14 +822,12 @@ __global__ __launch_bounds__(kThreads) void bk_spmv_dot2_v(const int32_t* __rest
 
 // x += alpha p, r -= alpha q (live columns), the FP32 copy of r, and the partial sums of r.r
 template <int M>
-__global__ __launch_bounds__(kThreads) void bk_update_xr_v(int32_t n, const BatchCol* __restrict__ col,
-                                                           const double* __restrict__ p,
-                                                           const double* __restrict__ q,
-                                                           double* __restrict__ x,
-                                                           double* __restrict__ r,
-                                                           float* __restrict__ r32,
-                                                           double* __restrict__ part,
-                                                           const BatchFlag* __restrict__ flag) {
+__global__ __launch_bounds__(kThreads) void bk_update_r_v(int32_t n, const BatchCol* __restrict__ col,
+                                                          const double* __restrict__ q,
+                                                          double* __restrict__ r,
+                                                          float* __restrict__ r32,
+                                                          double* __restrict__ part,
+                                                          const BatchFlag* __restrict__ flag) {
   if (flag->all_done) return;
   BK_TILES_V(M, n)
   const BatchCol ca = col[c0], cb = col[c0 + 1];
@@ -829,21 +838,16 @@ __global__ __launch_bounds__(kThreads) void bk_update_xr_v(int32_t n, const Batc
       const int i = t * RBV + slot;
       if (i < n) {
         const int k = i * M + c0;
-        const D2 pv = *reinterpret_cast<const D2*>(p + k);
         const D2 qv = *reinterpret_cast<const D2*>(q + k);
-        D2 xv = *reinterpret_cast<const D2*>(x + k);
         D2 rv = *reinterpret_cast<const D2*>(r + k);
         if (la) {
-          xv.v[0] = bmac(ca.alpha, pv.v[0], xv.v[0]);
           rv.v[0] = bmac(-ca.alpha, qv.v[0], rv.v[0]);
           v[0] = bmac(rv.v[0], rv.v[0], v[0]);
         }
         if (lb) {
-          xv.v[1] = bmac(cb.alpha, pv.v[1], xv.v[1]);
           rv.v[1] = bmac(-cb.alpha, qv.v[1], rv.v[1]);
           v[1] = bmac(rv.v[1], rv.v[1], v[1]);
         }
-        *reinterpret_cast<D2*>(x + k) = xv;
         *reinterpret_cast<D2*>(r + k) = rv;
         if (r32) {
           if (la) r32[k] = static_cast<float>(rv.v[0] * ca.scale);
@@ -856,14 +860,12 @@ __global__ __launch_bounds__(kThreads) void bk_update_xr_v(int32_t n, const Batc
 }
 
 template <int M>
-__global__ __launch_bounds__(kThreads) void bk_update_xr(int32_t n, const BatchCol* __restrict__ col,
-                                                         const double* __restrict__ p,
-                                                         const double* __restrict__ q,
-                                                         double* __restrict__ x,
-                                                         double* __restrict__ r,
-                                                         float* __restrict__ r32,
-                                                         double* __restrict__ part,
-                                                         const BatchFlag* __restrict__ flag) {
+__global__ __launch_bounds__(kThreads) void bk_update_r(int32_t n, const BatchCol* __restrict__ col,
+                                                        const double* __restrict__ q,
+                                                        double* __restrict__ r,
+                                                        float* __restrict__ r32,
+                                                        double* __restrict__ part,
+                                                        const BatchFlag* __restrict__ flag) {
   if (flag->all_done) return;
   BK_TILES(M, n)
   const BatchCol cc = col[c];
@@ -873,7 +875,6 @@ __global__ __launch_bounds__(kThreads) void bk_update_xr(int32_t n, const BatchC
       const int i = t * rb + threadIdx.x / M;
       if (i < n) {
         const int k = i * M + c;
-        x[k] = bmac(cc.alpha, p[k], x[k]);
         const double ri = bmac(-cc.alpha, q[k], r[k]);
         r[k] = ri;
         v = bmac(ri, ri, v);
@@ -905,6 +906,23 @@ __global__ __launch_bounds__(kThreads) void bk_residual_norm(const int32_t* __re
     }
   }
   block_cols<M>(v, 0.0, part, nullptr, blk);
+}
+
+// The solution step each column still has pending when the loop ends: x += alpha p.  The
+// direction update takes the previous iteration's step (it reads p_old anyway), so after a
+// column's last iteration its step is left for this kernel; alpha = 0 marks none pending
+// (the start, a breakdown of the step length, and FIN_RNORM after this kernel).
+template <int M>
+__global__ __launch_bounds__(kThreads) void bk_apply_pending(int32_t n,
+                                                             const BatchCol* __restrict__ col,
+                                                             const double* __restrict__ p,
+                                                             double* __restrict__ x) {
+  BK_ROWCOL(M)
+  if (row >= n) return;
+  const double a = col[c].alpha;
+  if (a == 0.0) return;
+  const int k = row * M + c;
+  x[k] = bmac(a, p[k], x[k]);
 }
 
 __global__ void bk_init(BatchCol* __restrict__ col, BatchFlag* __restrict__ flag, int M, int ncols,
@@ -1004,6 +1022,7 @@ __global__ __launch_bounds__(kFin) void bk_finalize(int op, int M, int nb,
         if (!(a > 0.0) || !isfinite(a) || !isfinite(b)) {
           cc.status = (isfinite(a) && isfinite(b)) ? MG_EBREAKDOWN : MG_ENONFINITE;
           cc.done = 1;
+          cc.alpha = 0.0;
         } else {
           cc.alpha = b / a;
         }
@@ -1035,7 +1054,9 @@ __global__ __launch_bounds__(kFin) void bk_finalize(int op, int M, int nb,
         cc.mean = a / cc.n_unknowns;
         break;
       case bk::FIN_RNORM:
+        // the exit work took the pending step first
         cc.true_rnorm = sqrt(a);
+        cc.alpha = 0.0;
         break;
     }
   }
@@ -1202,17 +1223,17 @@ void zdot(int M, int32_t n, const BatchCol* col, const T* z, const double* q, do
 }
 
 template <typename T>
-void pupd(int M, int32_t n, const BatchCol* col, const T* z, double* p, int sub_mean,
+void pupd(int M, int32_t n, const BatchCol* col, const T* z, double* p, double* x, int sub_mean,
           const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
     if constexpr (MM >= kKV) {
       constexpr int RBV = kThreads / (MM / kKV);
       hipLaunchKernelGGL((bk_pupd_v<T, MM>), dim3(unsigned((int64_t(n) + RBV - 1) / RBV)),
-                         dim3(kThreads), 0, s, n, col, z, p, sub_mean, flag);
+                         dim3(kThreads), 0, s, n, col, z, p, x, sub_mean, flag);
     } else {
       hipLaunchKernelGGL((bk_pupd<T, MM>), dim3(row_blocks(n, MM)), dim3(kThreads), 0, s, n, col,
-                         z, p, sub_mean, flag);
+                         z, p, x, sub_mean, flag);
     }
   });
 }
@@ -1250,16 +1271,26 @@ void spmv_dot2(int M, const Level& L, const double* p, double* q, const double* 
   });
 }
 
-void update_xr(int M, int32_t n, const BatchCol* col, const double* p, const double* q, double* x,
-               double* r, float* r32, double* part, int nb, const BatchFlag* flag, hipStream_t s) {
+void update_r(int M, int32_t n, const BatchCol* col, const double* q, double* r, float* r32,
+              double* part, int nb, const BatchFlag* flag, hipStream_t s) {
   with_m(M, [&](auto mc) {
     constexpr int MM = decltype(mc)::value;
     if constexpr (MM >= kKV)
-      hipLaunchKernelGGL(bk_update_xr_v<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, p, q, x, r,
-                         r32, part, flag);
+      hipLaunchKernelGGL(bk_update_r_v<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, q, r, r32,
+                         part, flag);
     else
-      hipLaunchKernelGGL(bk_update_xr<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, p, q, x, r,
-                         r32, part, flag);
+      hipLaunchKernelGGL(bk_update_r<MM>, dim3(nb), dim3(kThreads), 0, s, n, col, q, r, r32, part,
+                         flag);
+  });
+}
+
+void apply_pending(int M, int32_t n, const BatchCol* col, const double* p, double* x,
+                   hipStream_t s) {
+  if (n == 0) return;
+  with_m(M, [&](auto mc) {
+    constexpr int MM = decltype(mc)::value;
+    hipLaunchKernelGGL(bk_apply_pending<MM>, dim3(row_blocks(n, MM)), dim3(kThreads), 0, s, n, col,
+                       p, x);
   });
 }
 
@@ -1449,9 +1480,9 @@ template void zdot<float>(int, int32_t, const BatchCol*, const float*, const dou
                           int, const BatchFlag*, hipStream_t);
 template void zdot<double>(int, int32_t, const BatchCol*, const double*, const double*, double*,
                            int, int, const BatchFlag*, hipStream_t);
-template void pupd<float>(int, int32_t, const BatchCol*, const float*, double*, int,
+template void pupd<float>(int, int32_t, const BatchCol*, const float*, double*, double*, int,
                           const BatchFlag*, hipStream_t);
-template void pupd<double>(int, int32_t, const BatchCol*, const double*, double*, int,
+template void pupd<double>(int, int32_t, const BatchCol*, const double*, double*, double*, int,
                            const BatchFlag*, hipStream_t);
 template void rows<float>(int, int, const Level&, const float*, const float*, float*, double,
                           const BatchFlag*, hipStream_t);

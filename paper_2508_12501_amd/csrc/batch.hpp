@@ -116,13 +116,18 @@ void start(int M, int32_t n, const BatchCol* col, const double* Bv, double* X, d
 template <typename T>
 void zdot(int M, int32_t n, const BatchCol* col, const T* z, const double* q, double* part, int nb,
           int sub_mean, const BatchFlag* flag, hipStream_t s);
+// p = z + beta p, and the previous iteration's step x += alpha p_old (per live column)
 template <typename T>
-void pupd(int M, int32_t n, const BatchCol* col, const T* z, double* p, int sub_mean,
+void pupd(int M, int32_t n, const BatchCol* col, const T* z, double* p, double* x, int sub_mean,
           const BatchFlag* flag, hipStream_t s);
 void spmv_dot2(int M, const Level& L, const double* p, double* q, const double* r, double* part0,
                double* part1, int nb, const BatchFlag* flag, hipStream_t s);
-void update_xr(int M, int32_t n, const BatchCol* col, const double* p, const double* q, double* x,
-               double* r, float* r32, double* part, int nb, const BatchFlag* flag, hipStream_t s);
+// r -= alpha q, its FP32 copy (r32 nullable) and the partials of r.r (per live column)
+void update_r(int M, int32_t n, const BatchCol* col, const double* q, double* r, float* r32,
+              double* part, int nb, const BatchFlag* flag, hipStream_t s);
+// x += alpha p for every column whose last step is still pending (alpha != 0)
+void apply_pending(int M, int32_t n, const BatchCol* col, const double* p, double* x,
+                   hipStream_t s);
 void residual_norm(int M, const Level& L, const double* x, const double* b, double* part, int nb,
                    hipStream_t s);
 template <typename T>

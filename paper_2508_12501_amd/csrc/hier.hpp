@@ -227,6 +227,8 @@ struct DevScalars {
   double* hist;        // relative residual of the loop after each iteration (device), or null
   int32_t hist_cap;
   int32_t pbuf;        // direction buffer (0 first, 1 second) of the pending step x += alpha p
+  int32_t check_pending;   // a residual update whose convergence check has not run yet
+  int32_t pad_;
 };
 
 // Finest-level data of the porous-convection step and of the solve gradients (built on first
@@ -423,6 +425,13 @@ void update_r(int32_t n, const DevScalars* sc, const double* q, double* r, float
               double* part0, const int* done, hipStream_t s);
 void apply_pending(int32_t n, const DevScalars* sc, const double* p0, const double* p1, double* x,
                    hipStream_t s);
+// jacobi_two on a row-pattern level with one more workgroup that takes the Krylov loop's
+// pending convergence check from the nbp (<= 8192) partials of its residual update (the bits
+// of a FIN_CHECK finalisation; a no-op when no check is pending)
+bool jacobi_two_chk_ok(const Level& L);
+template <typename T>
+void jacobi_two_chk(const Level& L, const T* b, T* xo, double omega, const int* done,
+                    DevScalars* sc, const double* part, int32_t nbp, hipStream_t s);
 void residual_norm(const Level& L, const double* x, const double* b, double* r, float* r32,
                    const DevScalars* sc, double* part0, const int* done, hipStream_t s);
 void sum64(int32_t n, const double* v, double* part0, const int* done, hipStream_t s);

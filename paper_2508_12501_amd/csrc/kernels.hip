@@ -22,11 +22,11 @@
 namespace decmg {
 namespace {
 
-__device__ __forceinline__ int xcd_block() {
-  const int b = blockIdx.x, g = gridDim.x;
+__device__ __forceinline__ int xcd_block_of(int b, int g) {
   const int x = b & 7, i = b >> 3, q = g >> 3, r = g & 7;
   return x * q + (x < r ? x : r) + i;
 }
+__device__ __forceinline__ int xcd_block() { return xcd_block_of(blockIdx.x, gridDim.x); }
 
 // Reduction kernels run a capped grid; logical block b walks a contiguous range of 256-row
 // tiles so the number of partial sums stays small.
@@ -469,9 +469,9 @@ __device__ __forceinline__ void jacobi_two2_body(int32_t uw, const void* __restr
                                                  const T* __restrict__ idiag,
                                                  const T* __restrict__ b, T* __restrict__ y,
                                                  int32_t n, T omega,
-                                                 const int* __restrict__ done) {
+                                                 const int* __restrict__ done, int blk) {
   DECMG_DONE_LOAD(n)
-  const int r0 = xcd_block() * (2 * kBlock) + threadIdx.x;
+  const int r0 = blk * (2 * kBlock) + threadIdx.x;
   const bool live = r0 < n;
   int r1 = 0, e0 = 0, e1 = 0;
   T b0 = T(0), b1 = T(0), i0 = T(1), i1 = T(1);
@@ -507,7 +507,8 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two2(int32_t uw, const void* 
                                                         const T* __restrict__ b,
                                                         T* __restrict__ y, int32_t n, T omega,
                                                         const int* __restrict__ done) {
-  jacobi_two2_body<T, D16, WT, false>(uw, col, w, nullptr, 0, idiag, b, y, n, omega, done);
+  jacobi_two2_body<T, D16, WT, false>(uw, col, w, nullptr, 0, idiag, b, y, n, omega, done,
+                                      xcd_block());
 }
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_jacobi_two2p(int32_t uw,
@@ -519,8 +520,10 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two2p(int32_t uw,
                                                          const T* __restrict__ b,
                                                          T* __restrict__ y, int32_t n, T omega,
                                                          const int* __restrict__ done) {
-  jacobi_two2_body<T, true, T, true>(uw, off, w, pat, npat, idiag, b, y, n, omega, done);
+  jacobi_two2_body<T, true, T, true>(uw, off, w, pat, npat, idiag, b, y, n, omega, done,
+                                     xcd_block());
 }
+
 
 // First smoothing sweep from x = 0: x = omega b (1/D).
 template <typename T>
@@ -2318,6 +2321,86 @@ __global__ void k_init_scalars(DevScalars* __restrict__ sc, double rtol, int32_t
 
 constexpr int kFinThreads = 1024;
 
+// The convergence check of the Krylov loop from sum(r_i^2) = a: the loop residual, the
+// iteration count, the history entry, and the end of the loop on convergence, a non-finite
+// residual or the iteration limit.  Clears the pending-check mark.
+__device__ __forceinline__ void fin_check_apply(DevScalars* __restrict__ sc, double a, int iters,
+                                                int max_iter, double rtol, double bnorm,
+                                                double* hist, int hist_cap) {
+  const double rn = sqrt(a);
+  sc->check_pending = 0;
+  sc->rnorm = rn;
+  sc->iters = iters + 1;
+  if (hist && iters < hist_cap) hist[iters] = rn / bnorm;
+  if (!isfinite(rn)) {
+    sc->status = MG_ENONFINITE;
+    sc->done = 1;
+  } else if (rn <= rtol * bnorm) {
+    sc->status = MG_OK;
+    sc->done = 1;
+  } else if (iters + 1 >= max_iter) {
+    sc->status = MG_ENOCONV;
+    sc->done = 1;
+  }
+}
+
+// The pending convergence check taken by one 256-thread workgroup of another kernel: the sum
+// of the nb <= 8 kFinThreads partials in exactly k_finalize's order (its thread v adds
+// part[v], part[v + 1024], ... and pads with zeros to eight terms; each 64-thread wave sums
+// with the same butterfly; thread 0 adds the sixteen wave sums in order), so the check gives
+// the same bits as a separate FIN_CHECK launch.  Thread t stands for k_finalize's threads
+// t + 256 j, j = 0..3.
+__device__ void fin_check_block(DevScalars* __restrict__ sc, const double* __restrict__ part,
+                                int32_t nb) {
+  const int done0 = sc->done, pending = sc->check_pending;
+  const double rtol = sc->rtol, bnorm = sc->bnorm;
+  const int iters = sc->iters, max_iter = sc->max_iter;
+  double* const hist = sc->hist;
+  const int hist_cap = sc->hist_cap;
+  if (done0 || !pending) return;
+  const int t = threadIdx.x;
+  __shared__ double sw[kFinThreads / 64];
+  // one stand-in thread at a time keeps the register need of the host kernel low; this
+  // workgroup runs beside the sweeps, so its four round trips are not on their path
+#pragma unroll 1
+  for (int j = 0; j < 4; ++j) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = t + 256 * j + q * kFinThreads;
+      v[q] = i < nb ? part[i] : 0.0;
+    }
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a += v[q];
+    a = wave_sum(a);
+    if ((t & 63) == 0) sw[(t >> 6) + 4 * j] = a;
+  }
+  __syncthreads();
+  if (t != 0) return;
+  double a = 0.0;
+  for (int i = 0; i < kFinThreads / 64; ++i) a += sw[i];
+  fin_check_apply(sc, a, iters, max_iter, rtol, bnorm, hist, hist_cap);
+}
+
+// k_jacobi_two2p with one extra workgroup (block 0) that takes the Krylov loop's pending
+// convergence check, which the sweeps do not wait for: it runs beside them instead of as a
+// launch of its own between the residual update and the cycle
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_jacobi_two2p_chk(
+    int32_t uw, const int16_t* __restrict__ off, const T* __restrict__ w,
+    const uint8_t* __restrict__ pat, int npat, const T* __restrict__ idiag,
+    const T* __restrict__ b, T* __restrict__ y, int32_t n, T omega,
+    const int* __restrict__ done, DevScalars* __restrict__ sc,
+    const double* __restrict__ part, int32_t nbp) {
+  if (blockIdx.x == 0) {
+    fin_check_block(sc, part, nbp);
+    return;
+  }
+  jacobi_two2_body<T, true, T, true>(uw, off, w, pat, npat, idiag, b, y, n, omega, done,
+                                     xcd_block_of(blockIdx.x - 1, gridDim.x - 1));
+}
+
 // Per-thread part of the finaliser's fixed-order sum: thread t adds part[t + k * kFinThreads]
 // for k = 0, 1, ... in that order, B loads of each array in flight at a time.
 template <int B>
@@ -2362,7 +2445,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
   const double nun = sc->n_unknowns;
   const int iters = sc->iters, max_iter = sc->max_iter;
   double* const hist = sc->hist;
-  const int hist_cap = sc->hist_cap;
+  const int hist_cap = sc->hist_cap, pending = sc->check_pending;
   // thread t sums part[t], part[t + 1024], ... in that order; loads go out in batches of 8, or
   // of 16 when there are more than 8 per thread (the one-partial-per-256-rows kernels on the
   // finest level), so that a single round trip fetches them all
@@ -2428,6 +2511,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       } else {
         sc->alpha = rho / a;
         sc->pbuf = extra != 0.0 ? 1 : 0;
+        sc->check_pending = 1;
       }
       break;
     case k::FIN_ALPHA_FCG:
@@ -2439,25 +2523,15 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(int op, int32_t nb,
       } else {
         sc->alpha = b / a;
         sc->pbuf = extra != 0.0 ? 1 : 0;
+        sc->check_pending = 1;
       }
       break;
-    case k::FIN_CHECK: {
-      const double rn = sqrt(a);
-      sc->rnorm = rn;
-      sc->iters = iters + 1;
-      if (hist && iters < hist_cap) hist[iters] = rn / bnorm;
-      if (!isfinite(rn)) {
-        sc->status = MG_ENONFINITE;
-        sc->done = 1;
-      } else if (rn <= rtol * bnorm) {
-        sc->status = MG_OK;
-        sc->done = 1;
-      } else if (iters + 1 >= max_iter) {
-        sc->status = MG_ENOCONV;
-        sc->done = 1;
-      }
+    case k::FIN_CHECK:
+      // extra != 0: only when a residual update is waiting for its check (the end of a batch
+      // of iterations whose checks run inside the next iteration's first kernel)
+      if (extra != 0.0 && !pending) break;
+      fin_check_apply(sc, a, iters, max_iter, rtol, bnorm, hist, hist_cap);
       break;
-    }
     case k::FIN_BETA_CG:
       if (!(a > 0.0) || !isfinite(a)) {
         sc->status = isfinite(a) ? MG_EBREAKDOWN : MG_ENONFINITE;
@@ -2677,6 +2751,17 @@ void jacobi_two(const Level& L, const T* b, T* xo, double omega, const int* done
                          L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, diagonal<T>(L), b, xo,
                          L.n, static_cast<T>(omega), done);
   });
+}
+bool jacobi_two_chk_ok(const Level& L) { return L.n > 0 && row_patterns(L); }
+template <typename T>
+void jacobi_two_chk(const Level& L, const T* b, T* xo, double omega, const int* done,
+                    DevScalars* sc, const double* part, int32_t nbp, hipStream_t s) {
+  if (!jacobi_two_chk_ok(L)) throw std::logic_error("jacobi_two_chk: level without row patterns");
+  if (nbp < 1 || nbp > 8 * kFinThreads) throw std::logic_error("jacobi_two_chk: partial count");
+  hipLaunchKernelGGL((k_jacobi_two2p_chk<T>), dim3(grid2_for(L.n) + 1), dim3(kBlock),
+                     pattern_lds<T>(L), s, L.op.uw, L.op.poff, pattern_weights<T>(L), L.op.pat,
+                     L.op.npat, diagonal<T>(L), b, xo, L.n, static_cast<T>(omega), done, sc, part,
+                     nbp);
 }
 template <typename T>
 void jacobi_zero(const Level& L, const T* b, T* xo, double omega, const int* done, hipStream_t s) {
@@ -3202,6 +3287,7 @@ __global__ void k_restart_scalars(DevScalars* __restrict__ sc) {
   sc->status = MG_OK;
   sc->rho = 1.0;
   sc->pq = 1.0;
+  sc->check_pending = 0;
 }
 
 void restart_scalars(DevScalars* sc, hipStream_t s) {
@@ -3218,6 +3304,8 @@ void sum_abs64(int32_t n, const double* v, double* part0, double* part1, hipStre
   template void jacobi<T>(const Level&, const T*, const T*, T*, double, const int*, hipStream_t); \
   template void jacobi_zero<T>(const Level&, const T*, T*, double, const int*, hipStream_t);    \
   template void jacobi_two<T>(const Level&, const T*, T*, double, const int*, hipStream_t);     \
+  template void jacobi_two_chk<T>(const Level&, const T*, T*, double, const int*, DevScalars*,   \
+                                  const double*, int32_t, hipStream_t);                          \
   template void jacobi_timed<T>(const Level&, const T*, const T*, T*, double, const int*,        \
                                 hipStream_t, hipEvent_t, hipEvent_t);                           \
   template void restrict_<T>(const Level&, const Level&, const T*, T*, const int*, hipStream_t); \

@@ -48,7 +48,7 @@ static void sweep(Hierarchy& H, int l, const T* x, const T* b, T* xo, double ome
 
 template <typename T>
 static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, int kind,
-                  const int* done, hipStream_t s);
+                  const int* done, hipStream_t s, bool chk = false);
 
 // The coarse-grid correction of level l for a cycle of shape `kind`: level l-1 solved by one
 // cycle of the same shape from zero (V), two (W), or an F-cycle then a V-cycle (F).
@@ -121,12 +121,19 @@ static T* cg_cycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o,
 
 // One cycle of shape `kind` on level l (MG_CYCLE_V/W/F): the coarse-grid correction is one
 // cycle of the same shape from zero (V), two (W, the second from the first's result), or an
-// F-cycle followed by a V-cycle (F).  Returns the buffer holding the result.
+// F-cycle followed by a V-cycle (F).  Returns the buffer holding the result.  chk: the
+// opening two sweeps from zero also take the Krylov loop's pending convergence check (only
+// where check_fused_ok says the cycle opens with them).
 template <typename T>
 static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, int kind,
-                  const int* done, hipStream_t s) {
+                  const int* done, hipStream_t s, bool chk) {
   Level& L = *H.lv[l];
   LevelVecs<T>& V = vecs<T>(L);
+  if (chk && (l == 0 || x_init || o.smoother != MG_SMOOTH_JACOBI || o.nu1 < 2 ||
+              (o.fuse_levels && L.tiles.ntiles > 0) || !k::jacobi_two_chk_ok(L) ||
+              (kind == MG_CYCLE_V && l <= coarse_top<T>(H)) ||
+              k::coarse_cycle_general_ok<T>(H, l, false)))
+    throw std::logic_error("mgcycle: this cycle does not open with the two sweeps from zero");
   if (l == 0) {
     k::coarse<T>(H, b, V.x, done, s);
     return V.x;
@@ -179,7 +186,10 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
     cur = V.x;
     oth = V.t;
     if (pre >= 2) {
-      k::jacobi_two<T>(L, b, cur, o.omega, done, s);
+      if (chk)
+        k::jacobi_two_chk<T>(L, b, cur, o.omega, done, H.scal, H.part, k::red_blocks(L.n), s);
+      else
+        k::jacobi_two<T>(L, b, cur, o.omega, done, s);
       pre -= 2;
     } else if (pre == 1) {
       k::jacobi_zero<T>(L, b, cur, o.omega, done, s);
@@ -223,14 +233,31 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
 
 template <typename T>
 T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const int* done,
-          hipStream_t s) {
-  return mgcycle<T>(H, l, b, x_init, o, o.cycle, done, s);
+          hipStream_t s, bool chk) {
+  return mgcycle<T>(H, l, b, x_init, o, o.cycle, done, s, chk);
 }
 
 template double* vcycle<double>(Hierarchy&, int, const double*, double*, const mg_opts&,
-                                const int*, hipStream_t);
+                                const int*, hipStream_t, bool);
 template float* vcycle<float>(Hierarchy&, int, const float*, float*, const mg_opts&, const int*,
-                              hipStream_t);
+                              hipStream_t, bool);
+
+// Whether a CG/FCG iteration's cycle opens on the finest level with the two Jacobi sweeps from
+// zero of a row-pattern level, which then take the previous iteration's convergence check in
+// one more workgroup (the fused levels switched on, Jacobi smoothing with nu1 >= 2, a finest
+// level with a coarse level below it that is neither tiled nor inside a one-launch bottom).
+bool check_fused_ok(const Hierarchy& H, const mg_opts& o) {
+  const int top = int(H.lv.size()) - 1;
+  if (o.outer == MG_OUTER_IR || !o.fuse_levels) return false;
+  if (top < 1 || o.smoother != MG_SMOOTH_JACOBI || o.nu1 < 2) return false;
+  const Level& L = *H.lv[top];
+  if (L.tiles.ntiles > 0 || !k::jacobi_two_chk_ok(L)) return false;
+  if (o.precision == MG_F32)
+    return !((o.cycle == MG_CYCLE_V && top <= coarse_top<float>(H)) ||
+             k::coarse_cycle_general_ok<float>(H, top, false));
+  return !((o.cycle == MG_CYCLE_V && top <= coarse_top<double>(H)) ||
+           k::coarse_cycle_general_ok<double>(H, top, false));
+}
 
 namespace {
 
@@ -253,6 +280,8 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   double* P0 = H.part;
   double* P1 = H.part + H.part_cap;
   const double* other = (o.outer == MG_OUTER_FCG) ? H.sq : H.sr;
+  // the previous iteration's convergence check rides with the cycle's first kernel
+  const bool chk = check_fused_ok(H, o);
   double* z;
   float* z32 = nullptr;
   double* P2 = H.part + 2 * H.part_cap;
@@ -261,7 +290,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   // sum o) and subtract the mean inside the p update; IR projects z before using it.
   const bool fused_mean = natural && o.outer != MG_OUTER_IR;
   if (o.precision == MG_F32) {
-    z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s);
+    z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s, chk);
     if (H.debug_flags & MG_DEBUG_ZERO_PRECOND32) k::fill<float>(z32, n, 0.0f, s);
     if (fused_mean) {
       k::zsum_dot32(n, H.scal, z32, other, P0, P1, P2, done, s);
@@ -279,7 +308,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
     }
     z = H.sz;
   } else {
-    z = vcycle<double>(H, top, H.sr, nullptr, o, done, s);
+    z = vcycle<double>(H, top, H.sr, nullptr, o, done, s, chk);
     if (fused_mean) {
       k::zsum_dot64(n, H.scal, z, other, P0, P1, P2, done, s);
     } else {
@@ -313,7 +342,9 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   k::finalize(o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG,
               k::pupd_spmv_partials(F), P0, P1, H.scal, p_new == H.sp2 ? 1.0 : 0.0, 0, s);
   k::update_r(n, H.scal, H.sq, H.sr, r32, P0, done, s);
-  fin(H, k::FIN_CHECK, n, false, s);
+  // with chk the check waits for the next iteration's first kernel, or for the end of the
+  // batch (run_pcg's tail)
+  if (!chk) fin(H, k::FIN_CHECK, n, false, s);
 }
 
 // One stand-alone V-cycle iteration (mg_solve): x <- V(b, x); r = b - A x; check.
@@ -556,6 +587,9 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     H.p_parity ^= 1;
   };
   auto tail = [&]() {
+    // the last iteration's convergence check when it was left to a next iteration (a no-op
+    // otherwise), before the host reads the flag and before the finish reuses the partials
+    k::finalize(k::FIN_CHECK, k::red_blocks(n), H.part, nullptr, H.scal, 1.0, 0, s);
     if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
   };
   // the loop from iteration `launched` on; stagnation ends it only while the FP32 cycle runs

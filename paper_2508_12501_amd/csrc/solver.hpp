@@ -9,10 +9,14 @@ LevelVecs<T>& vecs(Level& L);
 
 // One V(nu1, nu2) cycle on level l for A_l x = b.  x_init == nullptr means x = 0 (the first
 // pre-sweep then reads only b and the diagonal); otherwise x_init is the initial guess and
-// one of its buffers.  Returns the buffer that holds the result.
+// one of its buffers.  Returns the buffer that holds the result.  chk: the finest level's
+// opening sweeps also take the Krylov loop's pending convergence check.
 template <typename T>
 T* vcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, const int* done,
-          hipStream_t s);
+          hipStream_t s, bool chk = false);
+// Whether a CG/FCG iteration with these options leaves its convergence check to the first
+// kernel of the next iteration's cycle (see jacobi_two_chk).
+bool check_fused_ok(const Hierarchy& H, const mg_opts& o);
 
 Hierarchy* build_hierarchy(const Mesh& base, const mg_hier_opts& o);
 // Levels over given meshes whose interpolation rows are already set (set_interp_from_geomap).

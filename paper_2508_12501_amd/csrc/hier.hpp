@@ -429,6 +429,21 @@ void apply_pending(int32_t n, const DevScalars* sc, const double* p0, const doub
 // pending convergence check from the nbp (<= 8192) partials of its residual update (the bits
 // of a FIN_CHECK finalisation; a no-op when no check is pending)
 bool jacobi_two_chk_ok(const Level& L);
+// The exit work's ||b - A x||^2 as true_residual_partials(L) block partials (r_scratch: n
+// doubles, used only on levels without row patterns).
+bool true_residual_fast(const Level& L);
+int true_residual_partials(const Level& L);
+void true_residual(const Level& L, const double* x, const double* b, double* r_scratch,
+                   double* part0, hipStream_t s);
+// Dirichlet exit in one launch: pending step into x, x scattered through perm into x_nat, and
+// x_nat[bnd[j]] = b_nat[bnd[j]] for the nbnd boundary vertices.
+void finish_scatter(int32_t n, const DevScalars* sc, const double* p0, const double* p1,
+                    double* x, const int32_t* perm, double* x_nat, const int32_t* bnd,
+                    int32_t nbnd, const double* b_nat, hipStream_t s);
+// init_krylov with b gathered from the caller's numbering (b[i] = b_nat[perm[i]]) on the way.
+void init_krylov_gather(int32_t n, const DevScalars* sc, const int32_t* perm, const double* b_nat,
+                        double* b, double* r, double* x, double* p, double* q, float* r32,
+                        hipStream_t s);
 template <typename T>
 void jacobi_two_chk(const Level& L, const T* b, T* xo, double omega, const int* done,
                     DevScalars* sc, const double* part, int32_t nbp, hipStream_t s);

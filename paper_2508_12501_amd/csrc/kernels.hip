@@ -2053,6 +2053,118 @@ __global__ __launch_bounds__(kBlock) void k_residual_norm(const int32_t* __restr
   if (threadIdx.x == 0) part0[blk] = v;
 }
 
+// ||b - A x||^2 block partials with two rows per thread (one partial per 2 kBlock rows; over
+// row patterns or the uniform-width SELL arrays, which hold the same entries in the same
+// order, so both give the same bits), r itself not stored: the true residual of the exit work.
+template <bool D16, typename WT, bool PAT>
+__device__ __forceinline__ void true_residual2_body(int32_t uw, const void* __restrict__ col,
+                                                    const WT* __restrict__ w,
+                                                    const uint8_t* __restrict__ pat, int npat,
+                                                    const double* __restrict__ x,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ part0, int32_t n) {
+  const int blk = xcd_block();
+  const int r0 = blk * (2 * kBlock) + threadIdx.x;
+  const bool live = r0 < n;
+  int r1 = 0, e0 = 0, e1 = 0;
+  double x0 = 0.0, x1 = 0.0, b0 = 0.0, b1 = 0.0;
+  if (live) {
+    r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
+    e0 = row_first<PAT>(pat, r0, uw);
+    e1 = row_first<PAT>(pat, r1, uw);
+    x0 = x[r0];
+    x1 = x[r1];
+    b0 = b[r0];
+    b1 = b[r1];
+  }
+  if constexpr (PAT) {   // the row loads above are in flight meanwhile
+    const int16_t* so;
+    const WT* sw;
+    stage_patterns(static_cast<const int16_t*>(col), w, npat * uw, so, sw);
+    col = so;
+    w = sw;
+  }
+  double v = 0.0;
+  if (live) {
+    double a0, d0, a1, d1;
+    row2<double, D16, PAT>(col, w, e0, e1, r0, r1, uw, n, x0, x1, [&](int j) { return x[j]; },
+                           a0, d0, a1, d1);
+    const double q0 = b0 - a0;
+    v = q0 * q0;
+    if (r1 != r0) {
+      const double q1 = b1 - a1;
+      v = mac(q1, q1, v);
+    }
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+__global__ __launch_bounds__(kBlock) void k_true_residual2p(int32_t uw,
+                                                            const int16_t* __restrict__ off,
+                                                            const double* __restrict__ w,
+                                                            const uint8_t* __restrict__ pat,
+                                                            int npat,
+                                                            const double* __restrict__ x,
+                                                            const double* __restrict__ b,
+                                                            double* __restrict__ part0,
+                                                            int32_t n) {
+  true_residual2_body<true, double, true>(uw, off, w, pat, npat, x, b, part0, n);
+}
+template <bool D16, typename WT>
+__global__ __launch_bounds__(kBlock) void k_true_residual2(int32_t uw,
+                                                           const void* __restrict__ col,
+                                                           const WT* __restrict__ w,
+                                                           const double* __restrict__ x,
+                                                           const double* __restrict__ b,
+                                                           double* __restrict__ part0,
+                                                           int32_t n) {
+  true_residual2_body<D16, WT, false>(uw, col, w, nullptr, 0, x, b, part0, n);
+}
+
+// The exit of a Dirichlet solve in one pass: the pending solution step x += alpha p (alpha = 0:
+// none), x scattered to the caller's numbering, and (blocks past the interior rows) the
+// boundary vertices' values copied from b.
+__global__ __launch_bounds__(kBlock) void k_finish_scatter(
+    int32_t n, const DevScalars* __restrict__ sc, const double* __restrict__ p0,
+    const double* __restrict__ p1, double* __restrict__ x, const int32_t* __restrict__ perm,
+    double* __restrict__ x_nat, const int32_t* __restrict__ bnd, int32_t nbnd,
+    const double* __restrict__ b_nat) {
+  const int nbi = (n + kBlock - 1) / kBlock;
+  if (static_cast<int>(blockIdx.x) >= nbi) {
+    const int j = (blockIdx.x - nbi) * kBlock + threadIdx.x;
+    if (j < nbnd) x_nat[bnd[j]] = b_nat[bnd[j]];
+    return;
+  }
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double a = sc->alpha;
+  const double* __restrict__ p = sc->pbuf ? p1 : p0;
+  double xi = x[i];
+  if (a != 0.0) {
+    xi = mac(a, p[i], xi);
+    x[i] = xi;
+  }
+  x_nat[perm[i]] = xi;
+}
+
+// The start of a solve from x = 0 on a Dirichlet system: b gathered from the caller's
+// numbering into the internal right-hand side, r = b, x = p = q = 0, and the scaled FP32 copy of r.
+__global__ __launch_bounds__(kBlock) void k_init_krylov_gather(
+    int32_t n, const DevScalars* __restrict__ sc, const int32_t* __restrict__ perm,
+    const double* __restrict__ b_nat, double* __restrict__ b, double* __restrict__ r,
+    double* __restrict__ x, double* __restrict__ p, double* __restrict__ q,
+    float* __restrict__ r32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double v = b_nat[perm[i]];
+  b[i] = v;
+  r[i] = v;
+  x[i] = 0.0;
+  p[i] = 0.0;
+  q[i] = 0.0;
+  if (r32) r32[i] = static_cast<float>(v * sc->scale);
+}
+
 // part0 = z.o, part1 = sum z, part2 = sum o per block (z widened by 1/scale when ZT is float):
 // the sums from which the mean projection of z and the projected dot follow in one pass.
 template <typename ZT>
@@ -3257,6 +3369,47 @@ void dot(int32_t n, const double* a, const double* b, double* part0, const int* 
 }
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, v);
+}
+bool true_residual_fast(const Level& L) { return L.n > 0 && two_rows(L); }
+int true_residual_partials(const Level& L) {
+  return true_residual_fast(L) ? static_cast<int>(grid2_for(L.n)) : blocks_for(L.n);
+}
+void true_residual(const Level& L, const double* x, const double* b, double* r_scratch,
+                   double* part0, hipStream_t s) {
+  if (L.n == 0) return;
+  if (!true_residual_fast(L)) {
+    residual_norm(L, x, b, r_scratch, nullptr, nullptr, part0, nullptr, s);
+    return;
+  }
+  if (row_patterns(L)) {
+    hipLaunchKernelGGL(k_true_residual2p, dim3(grid2_for(L.n)), dim3(kBlock), pattern_lds<double>(L),
+                       s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat, L.op.npat, x, b, part0, L.n);
+    return;
+  }
+  with_weights<double>(L, [&](auto w) {
+    using WT = pointee_t<decltype(w)>;
+    if (L.op.col16)
+      hipLaunchKernelGGL((k_true_residual2<true, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.uw, static_cast<const void*>(L.op.col16), w, x, b, part0, L.n);
+    else
+      hipLaunchKernelGGL((k_true_residual2<false, WT>), dim3(grid2_for(L.n)), dim3(kBlock), 0, s,
+                         L.op.uw, static_cast<const void*>(L.op.col), w, x, b, part0, L.n);
+  });
+}
+void finish_scatter(int32_t n, const DevScalars* sc, const double* p0, const double* p1,
+                    double* x, const int32_t* perm, double* x_nat, const int32_t* bnd,
+                    int32_t nbnd, const double* b_nat, hipStream_t s) {
+  const unsigned g = grid_for(n) + grid_for(nbnd);
+  if (g == 0) return;
+  hipLaunchKernelGGL(k_finish_scatter, dim3(g), dim3(kBlock), 0, s, n, sc, p0, p1, x, perm, x_nat,
+                     bnd, nbnd, b_nat);
+}
+void init_krylov_gather(int32_t n, const DevScalars* sc, const int32_t* perm, const double* b_nat,
+                        double* b, double* r, double* x, double* p, double* q, float* r32,
+                        hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_init_krylov_gather, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, perm,
+                     b_nat, b, r, x, p, q, r32);
 }
 void init_krylov(int32_t n, const DevScalars* sc, const double* b, double* r, double* x,
                  double* p, double* q, float* r32, hipStream_t s) {

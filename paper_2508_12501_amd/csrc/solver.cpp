@@ -403,10 +403,12 @@ void read_scalars(Hierarchy& H, hipStream_t s) {
 // With b_nat == nullptr the internal right-hand side is already in H.sb.  check_compat: a
 // natural-boundary b whose sum exceeds rounding (|sum b| > kCompatTol sum |b|) ends the solve
 // with MG_EINCOMPAT.
-void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_compat = false) {
+void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_compat = false,
+               bool defer_gather = false) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
-  if (b_nat) k::gather<double>(F.perm, n, b_nat, H.sb, s);
+  // defer_gather (Dirichlet systems only): the caller gathers b into H.sb itself
+  if (b_nat && !(defer_gather && H.bc != MG_BC_NATURAL)) k::gather<double>(F.perm, n, b_nat, H.sb, s);
   if (H.bc == MG_BC_NATURAL) {
     if (check_compat) {
       k::sum_abs64(n, H.sb, H.part, H.part + H.part_cap, s);
@@ -437,16 +439,22 @@ void enqueue_finish(Hierarchy& H, const double* b_nat, double* x_nat, hipStream_
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   // the solution step of the last CG/FCG iteration (a no-op when none is pending; FIN_RNORM
-  // below clears it, so running the finish again takes it only once)
-  k::apply_pending(n, H.scal, H.sp, H.sp2, H.sx, s);
+  // below clears it, so running the finish again takes it only once), with the scatter to the
+  // caller's numbering in the same pass on Dirichlet systems
+  const bool scatter_now = x_nat && H.bc != MG_BC_NATURAL;
+  if (scatter_now)
+    k::finish_scatter(n, H.scal, H.sp, H.sp2, H.sx, F.perm, x_nat, F.bnd_ids,
+                      b_nat ? int32_t(F.bnd_h.size()) : 0, b_nat, s);
+  else
+    k::apply_pending(n, H.scal, H.sp, H.sp2, H.sx, s);
   if (H.bc == MG_BC_NATURAL) {
     k::sum64(n, H.sx, H.part, nullptr, s);
     fin(H, k::FIN_MEAN, n, false, s, false, true);
     k::sub_mean(n, H.scal, H.sx, s);
   }
-  k::residual_norm(F, H.sx, H.sb, H.sz, nullptr, H.scal, H.part, nullptr, s);
-  fin(H, k::FIN_RNORM, n, false, s, true, true);
-  if (x_nat) {
+  k::true_residual(F, H.sx, H.sb, H.sz, H.part, s);
+  k::finalize(k::FIN_RNORM, k::true_residual_partials(F), H.part, nullptr, H.scal, 0.0, 1, s);
+  if (x_nat && !scatter_now) {
     k::scatter<double>(F.perm, n, H.sx, x_nat, s);
     k::bnd_copy<double>(F.bnd_ids, int32_t(F.bnd_h.size()), b_nat, x_nat, s);
   }
@@ -559,7 +567,9 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   init_scalars(H, o, s);
-  setup_rhs(H, b_nat, s, check_compat);
+  // a Dirichlet solve from x = 0 gathers b inside the Krylov start below
+  const bool gather_in_init = b_nat && H.bc != MG_BC_NATURAL;
+  setup_rhs(H, b_nat, s, check_compat, gather_in_init);
   H.p_parity = 0;
   mg_opts cur = o;   // the FP64 fallback switches the cycle's precision
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
@@ -568,6 +578,8 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::fill<double>(H.sq, n, 0.0, s);
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
     if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
+  } else if (gather_in_init) {
+    k::init_krylov_gather(n, H.scal, F.perm, b_nat, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   } else {
     k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }

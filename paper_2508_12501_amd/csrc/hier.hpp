@@ -437,9 +437,15 @@ void true_residual(const Level& L, const double* x, const double* b, double* r_s
                    double* part0, hipStream_t s);
 // Dirichlet exit in one launch: pending step into x, x scattered through perm into x_nat, and
 // x_nat[bnd[j]] = b_nat[bnd[j]] for the nbnd boundary vertices.
-void finish_scatter(int32_t n, const DevScalars* sc, const double* p0, const double* p1,
-                    double* x, const int32_t* perm, double* x_nat, const int32_t* bnd,
-                    int32_t nbnd, const double* b_nat, hipStream_t s);
+// part (nullable): also the loop's pending convergence check from its nbp partials, as a
+// conditional FIN_CHECK would take it.
+void finish_scatter(int32_t n, DevScalars* sc, const double* p0, const double* p1, double* x,
+                    const int32_t* perm, double* x_nat, const int32_t* bnd, int32_t nbnd,
+                    const double* b_nat, const double* part, int32_t nbp, hipStream_t s);
+// dot() whose partials kernel also writes the solver's starting scalars (init_scalars).
+void dot_init(int32_t n, const double* a, const double* b, double* part0, DevScalars* sc,
+              double rtol, int32_t max_iter, double n_unknowns, double* hist, int32_t hist_cap,
+              hipStream_t s);
 // init_krylov with b gathered from the caller's numbering (b[i] = b_nat[perm[i]]) on the way.
 void init_krylov_gather(int32_t n, const DevScalars* sc, const int32_t* perm, const double* b_nat,
                         double* b, double* r, double* x, double* p, double* q, float* r32,

@@ -2121,21 +2121,31 @@ __global__ __launch_bounds__(kBlock) void k_true_residual2(int32_t uw,
   true_residual2_body<D16, WT, false>(uw, col, w, nullptr, 0, x, b, part0, n);
 }
 
+__device__ void fin_check_block(DevScalars* __restrict__ sc, const double* __restrict__ part,
+                                int32_t nb);
+
 // The exit of a Dirichlet solve in one pass: the pending solution step x += alpha p (alpha = 0:
 // none), x scattered to the caller's numbering, and (blocks past the interior rows) the
 // boundary vertices' values copied from b.
 __global__ __launch_bounds__(kBlock) void k_finish_scatter(
-    int32_t n, const DevScalars* __restrict__ sc, const double* __restrict__ p0,
+    int32_t n, DevScalars* __restrict__ sc, const double* __restrict__ p0,
     const double* __restrict__ p1, double* __restrict__ x, const int32_t* __restrict__ perm,
     double* __restrict__ x_nat, const int32_t* __restrict__ bnd, int32_t nbnd,
-    const double* __restrict__ b_nat) {
+    const double* __restrict__ b_nat, const double* __restrict__ part, int32_t nbp) {
+  // block 0: the loop's pending convergence check (fin_check_block), which reads neither
+  // alpha nor the direction the others use
+  if (blockIdx.x == 0) {
+    if (part) fin_check_block(sc, part, nbp);
+    return;
+  }
+  const int b = blockIdx.x - 1;
   const int nbi = (n + kBlock - 1) / kBlock;
-  if (static_cast<int>(blockIdx.x) >= nbi) {
-    const int j = (blockIdx.x - nbi) * kBlock + threadIdx.x;
+  if (b >= nbi) {
+    const int j = (b - nbi) * kBlock + threadIdx.x;
     if (j < nbnd) x_nat[bnd[j]] = b_nat[bnd[j]];
     return;
   }
-  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const int i = b * kBlock + threadIdx.x;
   if (i >= n) return;
   const double a = sc->alpha;
   const double* __restrict__ p = sc->pbuf ? p1 : p0;
@@ -2383,6 +2393,40 @@ __global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double* __restr
   if (threadIdx.x == 0) part0[blk] = v;
 }
 
+// k_dot whose first thread also writes the solver's starting scalars (k_init_scalars), for
+// the start of a solve: the finalisation after it reads both
+__global__ __launch_bounds__(kBlock) void k_dot_init(int32_t n, const double* __restrict__ a,
+                                                     const double* __restrict__ b,
+                                                     double* __restrict__ part0,
+                                                     DevScalars* __restrict__ sc, double rtol,
+                                                     int32_t max_iter, double n_unknowns,
+                                                     double* hist, int32_t hist_cap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    DevScalars z = {};
+    z.hist = hist;
+    z.hist_cap = hist_cap;
+    z.rho = 1.0;
+    z.pq = 1.0;
+    z.beta = -0.0;
+    z.scale = 1.0;
+    z.inv_scale = 1.0;
+    z.rtol = rtol;
+    z.max_iter = max_iter;
+    z.n_unknowns = n_unknowns;
+    *sc = z;
+  }
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  double v = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) v += a[i] * b[i];
+  }
+  v = block_sum1(v);
+  if (threadIdx.x == 0) part0[blk] = v;
+}
+
 __global__ void k_sub_mean(int32_t n, const DevScalars* __restrict__ sc, double* __restrict__ v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) v[i] = v[i] - sc->mean;
@@ -2423,6 +2467,9 @@ __global__ void k_init_scalars(DevScalars* __restrict__ sc, double rtol, int32_t
   z.hist_cap = hist_cap;
   z.rho = 1.0;
   z.pq = 1.0;
+  // what FCG's first beta = -(z.q)/pq is with q = 0 and pq = 1, for a first iteration that
+  // skips that dot
+  z.beta = -0.0;
   z.scale = 1.0;
   z.inv_scale = 1.0;
   z.rtol = rtol;
@@ -3367,6 +3414,12 @@ void dot(int32_t n, const double* a, const double* b, double* part0, const int* 
          hipStream_t s) {
   hipLaunchKernelGGL(k_dot, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, a, b, part0, done);
 }
+void dot_init(int32_t n, const double* a, const double* b, double* part0, DevScalars* sc,
+              double rtol, int32_t max_iter, double n_unknowns, double* hist, int32_t hist_cap,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_init, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, a, b, part0, sc, rtol,
+                     max_iter, n_unknowns, hist, hist_cap);
+}
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, v);
 }
@@ -3396,13 +3449,14 @@ void true_residual(const Level& L, const double* x, const double* b, double* r_s
                          L.op.uw, static_cast<const void*>(L.op.col), w, x, b, part0, L.n);
   });
 }
-void finish_scatter(int32_t n, const DevScalars* sc, const double* p0, const double* p1,
-                    double* x, const int32_t* perm, double* x_nat, const int32_t* bnd,
-                    int32_t nbnd, const double* b_nat, hipStream_t s) {
-  const unsigned g = grid_for(n) + grid_for(nbnd);
-  if (g == 0) return;
+void finish_scatter(int32_t n, DevScalars* sc, const double* p0, const double* p1, double* x,
+                    const int32_t* perm, double* x_nat, const int32_t* bnd, int32_t nbnd,
+                    const double* b_nat, const double* part, int32_t nbp, hipStream_t s) {
+  if (part && (nbp < 1 || nbp > 8 * kFinThreads))
+    throw std::logic_error("finish_scatter: partial count");
+  const unsigned g = 1 + grid_for(n) + grid_for(nbnd);
   hipLaunchKernelGGL(k_finish_scatter, dim3(g), dim3(kBlock), 0, s, n, sc, p0, p1, x, perm, x_nat,
-                     bnd, nbnd, b_nat);
+                     bnd, nbnd, b_nat, part, nbp);
 }
 void init_krylov_gather(int32_t n, const DevScalars* sc, const int32_t* perm, const double* b_nat,
                         double* b, double* r, double* x, double* p, double* q, float* r32,
@@ -3440,6 +3494,7 @@ __global__ void k_restart_scalars(DevScalars* __restrict__ sc) {
   sc->status = MG_OK;
   sc->rho = 1.0;
   sc->pq = 1.0;
+  sc->beta = -0.0;
   sc->check_pending = 0;
 }
 

@@ -271,7 +271,11 @@ void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, bool tiles = 
 
 // One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).  `parity` selects
 // which direction buffer holds p on entry; the iteration leaves the new p in the other one.
-void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s) {
+// first: the iteration right after a start from p = q = 0 of an FCG loop on a Dirichlet
+// system, whose beta = -(z.q)/pq is -0 (set by the start): the dot and its finalisation are
+// left out.
+void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s,
+                       bool first = false) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   const int top = int(H.lv.size()) - 1;
@@ -289,6 +293,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   // mean.  CG and FCG take the mean and the projected dot from one pass over z (sum z, z.o,
   // sum o) and subtract the mean inside the p update; IR projects z before using it.
   const bool fused_mean = natural && o.outer != MG_OUTER_IR;
+  const bool skip_beta = first && o.outer == MG_OUTER_FCG && !natural;
   if (o.precision == MG_F32) {
     z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s, chk);
     if (H.debug_flags & MG_DEBUG_ZERO_PRECOND32) k::fill<float>(z32, n, 0.0f, s);
@@ -301,7 +306,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
       }
       if (o.outer == MG_OUTER_IR) {
         k::zconv_dot(n, H.scal, z32, H.sz, other, P0, natural ? 1 : 0, done, s);
-      } else {
+      } else if (!skip_beta) {
         // z stays in FP32: the dot and the p update widen it on the fly
         k::zdot32(n, H.scal, z32, other, P0, 0, done, s);
       }
@@ -316,7 +321,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
         k::sum64(n, z, P0, done, s);
         fin(H, k::FIN_MEAN, n, false, s);
       }
-      k::zsub_dot(n, H.scal, z, other, P0, natural ? 1 : 0, done, s);
+      if (!skip_beta) k::zsub_dot(n, H.scal, z, other, P0, natural ? 1 : 0, done, s);
     }
   }
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
@@ -329,7 +334,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   if (fused_mean)
     k::finalize(o.outer == MG_OUTER_CG ? k::FIN_MEAN_BETA_CG : k::FIN_MEAN_BETA_FCG,
                 k::red_blocks(n), P0, P1, H.scal, 0.0, 0, s, P2);
-  else
+  else if (!skip_beta)
     fin(H, o.outer == MG_OUTER_CG ? k::FIN_BETA_CG : k::FIN_BETA_FCG, n, false, s);
   // p = z + beta p formed inside the operator product (z32 carries the mean subtraction on
   // singular systems; an FP64 z has it subtracted already unless the sums were fused)
@@ -365,7 +370,8 @@ std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
                          o.cycle + 4 * o.smoother + 16 * (o.fuse_levels ? 1 : 0), o.omega);
 }
 
-// kind 0 and 2: a Krylov iteration with p in the first or the second buffer; 1: a cycle
+// kind 0 and 2: a Krylov iteration with p in the first or the second buffer; 1: a cycle;
+// 3: the first FCG iteration after a start from p = q = 0 (p in the first buffer)
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
   auto key = graph_key(o, kind);
   auto it = H.graphs.find(key);
@@ -374,10 +380,10 @@ hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
   check_hip(hipStreamBeginCapture(H.capture_stream, hipStreamCaptureModeThreadLocal),
             "hipStreamBeginCapture");
   H.capturing = true;
-  if (kind != 1)
-    enqueue_iteration(H, o, kind == 2 ? 1 : 0, H.capture_stream);
-  else
+  if (kind == 1)
     enqueue_cycle(H, o, H.capture_stream);
+  else
+    enqueue_iteration(H, o, kind == 2 ? 1 : 0, H.capture_stream, kind == 3);
   H.capturing = false;
   check_hip(hipStreamEndCapture(H.capture_stream, &g), "hipStreamEndCapture");
   hipGraphExec_t ex = nullptr;
@@ -404,7 +410,7 @@ void read_scalars(Hierarchy& H, hipStream_t s) {
 // natural-boundary b whose sum exceeds rounding (|sum b| > kCompatTol sum |b|) ends the solve
 // with MG_EINCOMPAT.
 void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_compat = false,
-               bool defer_gather = false) {
+               bool defer_gather = false, const mg_opts* init = nullptr) {
   Level& F = *H.lv.back();
   const int32_t n = F.n;
   // defer_gather (Dirichlet systems only): the caller gathers b into H.sb itself
@@ -421,7 +427,12 @@ void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_comp
     k::dot(n, H.sb, H.sb, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, n, false, s);
   } else if (b_nat) {
-    k::dot(F.nv, b_nat, b_nat, H.part, nullptr, s);
+    // init: the dot's first thread also writes the starting scalars (no init_scalars launch)
+    if (init)
+      k::dot_init(F.nv, b_nat, b_nat, H.part, H.scal, init->rtol, init->max_iter, double(n),
+                  H.hist, H.hist_cap, s);
+    else
+      k::dot(F.nv, b_nat, b_nat, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, F.nv, false, s);
   } else {
     k::dot(n, H.sb, H.sb, H.part, nullptr, s);
@@ -442,9 +453,9 @@ void enqueue_finish(Hierarchy& H, const double* b_nat, double* x_nat, hipStream_
   // below clears it, so running the finish again takes it only once), with the scatter to the
   // caller's numbering in the same pass on Dirichlet systems
   const bool scatter_now = x_nat && H.bc != MG_BC_NATURAL;
-  if (scatter_now)
+  if (scatter_now)   // with the loop's pending convergence check (a no-op when none is)
     k::finish_scatter(n, H.scal, H.sp, H.sp2, H.sx, F.perm, x_nat, F.bnd_ids,
-                      b_nat ? int32_t(F.bnd_h.size()) : 0, b_nat, s);
+                      b_nat ? int32_t(F.bnd_h.size()) : 0, b_nat, H.part, k::red_blocks(n), s);
   else
     k::apply_pending(n, H.scal, H.sp, H.sp2, H.sx, s);
   if (H.bc == MG_BC_NATURAL) {
@@ -566,10 +577,11 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   HostTimer T;
   Level& F = *H.lv.back();
   const int32_t n = F.n;
-  init_scalars(H, o, s);
-  // a Dirichlet solve from x = 0 gathers b inside the Krylov start below
+  // a Dirichlet solve from the caller's b gathers b inside the Krylov start below and writes
+  // the starting scalars with the norm of b
   const bool gather_in_init = b_nat && H.bc != MG_BC_NATURAL;
-  setup_rhs(H, b_nat, s, check_compat, gather_in_init);
+  if (!gather_in_init) init_scalars(H, o, s);
+  setup_rhs(H, b_nat, s, check_compat, gather_in_init, gather_in_init ? &o : nullptr);
   H.p_parity = 0;
   mg_opts cur = o;   // the FP64 fallback switches the cycle's precision
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
@@ -584,15 +596,26 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }
   T.mark("setup");
-  hipGraphExec_t g[2] = {nullptr, nullptr};
+  hipGraphExec_t g[2] = {nullptr, nullptr}, gfirst = nullptr;
+  // FCG on a Dirichlet system: the first iteration after a start from p = q = 0 has no dot
+  // for beta (first_graph)
+  auto first_ok = [&]() { return cur.outer == MG_OUTER_FCG && H.bc != MG_BC_NATURAL; };
   auto load_graphs = [&]() {
     g[0] = cur.use_graph ? iteration_graph(H, cur, 0) : nullptr;
     g[1] = cur.use_graph ? iteration_graph(H, cur, 2) : nullptr;
+    gfirst = (cur.use_graph && first_ok()) ? iteration_graph(H, cur, 3) : nullptr;
   };
   load_graphs();
   T.mark("graph");
+  bool fresh = true;   // p = q = 0 and beta = -0: the next iteration is a first one
   auto step = [&]() {
-    if (g[H.p_parity])
+    const bool first = fresh && first_ok() && H.p_parity == 0;
+    fresh = false;
+    if (first && gfirst)
+      check_hip(hipGraphLaunch(gfirst, s), "hipGraphLaunch");
+    else if (first)
+      enqueue_iteration(H, cur, 0, s, true);
+    else if (g[H.p_parity])
       check_hip(hipGraphLaunch(g[H.p_parity], s), "hipGraphLaunch");
     else
       enqueue_iteration(H, cur, H.p_parity, s);
@@ -600,8 +623,10 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   };
   auto tail = [&]() {
     // the last iteration's convergence check when it was left to a next iteration (a no-op
-    // otherwise), before the host reads the flag and before the finish reuses the partials
-    k::finalize(k::FIN_CHECK, k::red_blocks(n), H.part, nullptr, H.scal, 1.0, 0, s);
+    // otherwise), before the host reads the flag and before the finish reuses the partials;
+    // a Dirichlet finish with the caller's x takes it in its first launch
+    if (H.bc == MG_BC_NATURAL || !x_nat)
+      k::finalize(k::FIN_CHECK, k::red_blocks(n), H.part, nullptr, H.scal, 1.0, 0, s);
     if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
   };
   // the loop from iteration `launched` on; stagnation ends it only while the FP32 cycle runs
@@ -624,6 +649,7 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::fill<double>(H.sq, n, 0.0, s);
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
     if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
+    fresh = true;
   };
   bool stalled = run(0);
   for (;;) {

@@ -417,10 +417,12 @@ int red_blocks(int32_t n);   // grid (= number of partials) of the streaming red
 // p_new = z + beta p_old (z from z32 / scale or from z64, minus the mean when asked), q = A p_new,
 // with the block partials of p_new.q (part0) and p_new.r (part1): pupd_spmv_partials(L) of each
 int pupd_spmv_partials(const Level& L);
+// first: the first iteration after a start from p_old = 0 with no step pending (p = z; p_old
+// and x are not read, x is not written)
 void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
                     const double* r, double* x, double* part0, double* part1, const int* done,
-                    hipStream_t s);
+                    hipStream_t s, bool first = false);
 void update_r(int32_t n, const DevScalars* sc, const double* q, double* r, float* r32,
               double* part0, const int* done, hipStream_t s);
 void apply_pending(int32_t n, const DevScalars* sc, const double* p0, const double* p1, double* x,
@@ -447,6 +449,7 @@ void dot_init(int32_t n, const double* a, const double* b, double* part0, DevSca
               double rtol, int32_t max_iter, double n_unknowns, double* hist, int32_t hist_cap,
               hipStream_t s);
 // init_krylov with b gathered from the caller's numbering (b[i] = b_nat[perm[i]]) on the way.
+// p, q nullable: left as they are (a first iteration that reads neither follows).
 void init_krylov_gather(int32_t n, const DevScalars* sc, const int32_t* perm, const double* b_nat,
                         double* b, double* r, double* x, double* p, double* q, float* r32,
                         hipStream_t s);

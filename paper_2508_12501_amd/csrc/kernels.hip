@@ -1789,7 +1789,7 @@ __device__ __forceinline__ double z_val(ZT zraw, double s, double m, bool sub_me
   return zj;
 }
 
-template <typename ZT, bool D16, int N, typename WT>
+template <typename ZT, bool D16, int N, bool FIRST, typename WT>
 __device__ __forceinline__ void row_pnew_n(const void* __restrict__ col, const WT* __restrict__ w,
                                            const ZT* __restrict__ z, const double* __restrict__ po,
                                            int beg, int lane, int row, int n, double s, double m,
@@ -1802,11 +1802,12 @@ __device__ __forceinline__ void row_pnew_n(const void* __restrict__ col, const W
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     zj[k] = z[cj[k]];
-    pj[k] = po[cj[k]];
+    pj[k] = FIRST ? 0.0 : po[cj[k]];
   }
 #pragma unroll
   for (int k = 0; k < N; ++k) {
-    const double xj = mac(beta, pj[k], z_val(zj[k], s, m, sub_mean));
+    const double zv = z_val(zj[k], s, m, sub_mean);
+    const double xj = FIRST ? zv : mac(beta, pj[k], zv);
     acc = mac(wk[k], pi - xj, acc);
   }
 }
@@ -1817,7 +1818,9 @@ __device__ __forceinline__ void row_pnew_n(const void* __restrict__ col, const W
 // which saves the separate update pass and one write-then-read of p.  The previous
 // iteration's solution step x += alpha p_old is taken here too, where p_old is read anyway
 // (alpha still holds that iteration's step length; it is 0 when no step is pending).
-template <typename ZT, bool D16, typename WT>
+// FIRST: the first iteration after a start from p_old = 0 with no solution step pending,
+// where p = z exactly (beta p_old = -0 adds nothing): p_old and x are not read.
+template <typename ZT, bool D16, typename WT, bool FIRST = false>
 __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
     const int32_t* __restrict__ sptr, int32_t uw, const void* __restrict__ col,
     const WT* __restrict__ w, const DevScalars* __restrict__ sc, const ZT* __restrict__ z,
@@ -1831,11 +1834,16 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
   double v0 = 0.0, v1 = 0.0;
   if (row < n) {
     const double s = sc->inv_scale, m = sub_mean ? sc->mean : 0.0, beta = sc->beta;
-    const double ax = sc->alpha;
-    const double pold = po[row], xi = x[row];
-    const double pi = mac(beta, pold, z_val(z[row], s, m, sub_mean != 0));
+    double pi;
+    if constexpr (FIRST) {
+      pi = z_val(z[row], s, m, sub_mean != 0);
+    } else {
+      const double ax = sc->alpha;
+      const double pold = po[row], xi = x[row];
+      pi = mac(beta, pold, z_val(z[row], s, m, sub_mean != 0));
+      x[row] = mac(ax, pold, xi);
+    }
     const double ri = r[row];
-    x[row] = mac(ax, pold, xi);
     int beg, width;
     slice_bounds(sptr, uw, row, beg, width);
     const int lane = row & 63;
@@ -1844,8 +1852,8 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
       case 0: break;
 #define DECMG_PN(K)                                                                          \
   case K:                                                                                    \
-    row_pnew_n<ZT, D16, K>(col, w, z, po, beg, lane, row, n, s, m, sub_mean != 0, beta, pi,  \
-                           acc);                                                             \
+    row_pnew_n<ZT, D16, K, FIRST>(col, w, z, po, beg, lane, row, n, s, m, sub_mean != 0, beta, \
+                                  pi, acc);                                                  \
     break;
       DECMG_PN(1) DECMG_PN(2) DECMG_PN(3) DECMG_PN(4) DECMG_PN(5) DECMG_PN(6) DECMG_PN(7)
       DECMG_PN(8)
@@ -1855,7 +1863,8 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
           int j;
           double wk;
           entry_at<double, D16>(col, w, (beg + k) * kSlice + lane, row, n, j, wk);
-          const double xj = mac(beta, po[j], z_val(z[j], s, m, sub_mean != 0));
+          const double zj = z_val(z[j], s, m, sub_mean != 0);
+          const double xj = FIRST ? zj : mac(beta, po[j], zj);
           acc = mac(wk, pi - xj, acc);
         }
     }
@@ -1873,7 +1882,7 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2(
 
 // k_pupd_spmv_dot2 with two rows per thread (uniform widths 1..8 only): one partial per
 // 2 kBlock rows
-template <typename ZT, bool D16, typename WT, bool PAT>
+template <typename ZT, bool D16, typename WT, bool PAT, bool FIRST = false>
 __device__ __forceinline__ void pupd_spmv_dot2_2_body(
     int32_t uw, const void* __restrict__ col, const WT* __restrict__ w,
     const uint8_t* __restrict__ pat, int npat, const DevScalars* __restrict__ sc,
@@ -1895,14 +1904,16 @@ __device__ __forceinline__ void pupd_spmv_dot2_2_body(
     r1 = (r0 + kBlock < n) ? r0 + kBlock : r0;
     e0 = row_first<PAT>(pat, r0, uw);
     e1 = row_first<PAT>(pat, r1, uw);
-    o0 = po[r0];
-    o1 = po[r1];
+    if constexpr (!FIRST) {
+      o0 = po[r0];
+      o1 = po[r1];
+      x0 = x[r0];
+      x1 = x[r1];
+    }
     z0 = z[r0];
     z1 = z[r1];
     q0r = r[r0];
     q1r = r[r1];
-    x0 = x[r0];
-    x1 = x[r1];
   }
   if constexpr (PAT) {   // the row loads above are in flight meanwhile
     const int16_t* so;
@@ -1913,21 +1924,24 @@ __device__ __forceinline__ void pupd_spmv_dot2_2_body(
   }
   double v0 = 0.0, v1 = 0.0;
   if (live) {
-    const double p0 = mac(beta, o0, z_val(z0, s, m, sm));
-    const double p1 = mac(beta, o1, z_val(z1, s, m, sm));
+    const double p0 = FIRST ? z_val(z0, s, m, sm) : mac(beta, o0, z_val(z0, s, m, sm));
+    const double p1 = FIRST ? z_val(z1, s, m, sm) : mac(beta, o1, z_val(z1, s, m, sm));
     double a0, d0, a1, d1;
     row2<double, D16, PAT>(col, w, e0, e1, r0, r1, uw, n, p0, p1,
-                           [&](int j) { return mac(beta, po[j], z_val(z[j], s, m, sm)); }, a0,
-                           d0, a1, d1);
+                           [&](int j) {
+                             if constexpr (FIRST) return z_val(z[j], s, m, sm);
+                             else return mac(beta, po[j], z_val(z[j], s, m, sm));
+                           },
+                           a0, d0, a1, d1);
     pn[r0] = p0;
     q[r0] = a0;
-    x[r0] = mac(ax, o0, x0);
+    if constexpr (!FIRST) x[r0] = mac(ax, o0, x0);
     v0 = p0 * a0;
     v1 = p0 * q0r;
     if (r1 != r0) {
       pn[r1] = p1;
       q[r1] = a1;
-      x[r1] = mac(ax, o1, x1);
+      if constexpr (!FIRST) x[r1] = mac(ax, o1, x1);
       v0 += p1 * a1;
       v1 += p1 * q1r;
     }
@@ -1938,18 +1952,18 @@ __device__ __forceinline__ void pupd_spmv_dot2_2_body(
     part1[blk] = v1;
   }
 }
-template <typename ZT, bool D16, typename WT>
+template <typename ZT, bool D16, typename WT, bool FIRST = false>
 __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2(
     int32_t uw, const void* __restrict__ col, const WT* __restrict__ w,
     const DevScalars* __restrict__ sc, const ZT* __restrict__ z, int sub_mean,
     const double* __restrict__ po, double* __restrict__ pn, double* __restrict__ q,
     const double* __restrict__ r, double* __restrict__ x, double* __restrict__ part0,
     double* __restrict__ part1, int32_t n, const int* __restrict__ done) {
-  pupd_spmv_dot2_2_body<ZT, D16, WT, false>(uw, col, w, nullptr, 0, sc, z, sub_mean, po, pn, q,
-                                            r, x, part0, part1, n, done);
+  pupd_spmv_dot2_2_body<ZT, D16, WT, false, FIRST>(uw, col, w, nullptr, 0, sc, z, sub_mean, po,
+                                                   pn, q, r, x, part0, part1, n, done);
 }
 // over row patterns (see k_rows2p)
-template <typename ZT>
+template <typename ZT, bool FIRST = false>
 __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2p(
     int32_t uw, const int16_t* __restrict__ off, const double* __restrict__ w,
     const uint8_t* __restrict__ pat, int npat, const DevScalars* __restrict__ sc,
@@ -1957,8 +1971,8 @@ __global__ __launch_bounds__(kBlock) void k_pupd_spmv_dot2_2p(
     double* __restrict__ pn, double* __restrict__ q, const double* __restrict__ r,
     double* __restrict__ x, double* __restrict__ part0, double* __restrict__ part1, int32_t n,
     const int* __restrict__ done) {
-  pupd_spmv_dot2_2_body<ZT, true, double, true>(uw, off, w, pat, npat, sc, z, sub_mean, po, pn,
-                                                q, r, x, part0, part1, n, done);
+  pupd_spmv_dot2_2_body<ZT, true, double, true, FIRST>(uw, off, w, pat, npat, sc, z, sub_mean, po,
+                                                       pn, q, r, x, part0, part1, n, done);
 }
 
 // r -= alpha q, its FP32 copy for the next cycle and the block partials of r.r (x takes the
@@ -2158,7 +2172,8 @@ __global__ __launch_bounds__(kBlock) void k_finish_scatter(
 }
 
 // The start of a solve from x = 0 on a Dirichlet system: b gathered from the caller's
-// numbering into the internal right-hand side, r = b, x = p = q = 0, and the scaled FP32 copy of r.
+// numbering into the internal right-hand side, r = b, x = 0, p = q = 0 (unless p, q are null:
+// a first FCG iteration that reads neither), and the scaled FP32 copy of r.
 __global__ __launch_bounds__(kBlock) void k_init_krylov_gather(
     int32_t n, const DevScalars* __restrict__ sc, const int32_t* __restrict__ perm,
     const double* __restrict__ b_nat, double* __restrict__ b, double* __restrict__ r,
@@ -2170,8 +2185,8 @@ __global__ __launch_bounds__(kBlock) void k_init_krylov_gather(
   b[i] = v;
   r[i] = v;
   x[i] = 0.0;
-  p[i] = 0.0;
-  q[i] = 0.0;
+  if (p) p[i] = 0.0;
+  if (q) q[i] = 0.0;
   if (r32) r32[i] = static_cast<float>(v * sc->scale);
 }
 
@@ -3308,49 +3323,60 @@ int pupd_spmv_partials(const Level& L) {
 void pupd_spmv_dot2(const Level& L, const DevScalars* sc, const float* z32, const double* z64,
                     int sub_mean_flag, const double* p_old, double* p_new, double* q,
                     const double* r, double* x, double* part0, double* part1, const int* done,
-                    hipStream_t s) {
-  if (row_patterns(L)) {
-    if (z32)
-      hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<float>), dim3(grid2_for(L.n)), dim3(kBlock),
-                         pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat,
-                         L.op.npat, sc, z32, sub_mean_flag, p_old, p_new, q, r, x, part0, part1,
-                         L.n, done);
-    else
-      hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<double>), dim3(grid2_for(L.n)), dim3(kBlock),
-                         pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64, L.op.pat,
-                         L.op.npat, sc, z64, sub_mean_flag, p_old, p_new, q, r, x, part0, part1,
-                         L.n, done);
-    return;
-  }
-  with_weights<double>(L, [&](auto w) {
-    using WT = pointee_t<decltype(w)>;
-    auto go = [&](auto zp) {
-      using ZT = pointee_t<decltype(zp)>;
-      if (two_rows(L)) {
-        if (L.op.col16)
-          hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, true, WT>), dim3(grid2_for(L.n)),
-                             dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col16), w,
-                             sc, zp, sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
-        else
-          hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, false, WT>), dim3(grid2_for(L.n)),
-                             dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col), w,
-                             sc, zp, sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
-        return;
-      }
-      if (L.op.col16)
-        hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, true, WT>), dim3(grid_for(L.n)), dim3(kBlock), 0,
-                           s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col16), w, sc, zp,
-                           sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
+                    hipStream_t s, bool first) {
+  auto launch = [&](auto fc) {
+    constexpr bool FIRST = decltype(fc)::value;
+    if (row_patterns(L)) {
+      if (z32)
+        hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<float, FIRST>), dim3(grid2_for(L.n)),
+                           dim3(kBlock), pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64,
+                           L.op.pat, L.op.npat, sc, z32, sub_mean_flag, p_old, p_new, q, r, x,
+                           part0, part1, L.n, done);
       else
-        hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, false, WT>), dim3(grid_for(L.n)), dim3(kBlock),
-                           0, s, L.op.sptr, L.op.uw, static_cast<const void*>(L.op.col), w, sc, zp,
-                           sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n, done);
-    };
-    if (z32)
-      go(z32);
-    else
-      go(z64);
-  });
+        hipLaunchKernelGGL((k_pupd_spmv_dot2_2p<double, FIRST>), dim3(grid2_for(L.n)),
+                           dim3(kBlock), pattern_lds<double>(L), s, L.op.uw, L.op.poff, L.op.pw64,
+                           L.op.pat, L.op.npat, sc, z64, sub_mean_flag, p_old, p_new, q, r, x,
+                           part0, part1, L.n, done);
+      return;
+    }
+    with_weights<double>(L, [&](auto w) {
+      using WT = pointee_t<decltype(w)>;
+      auto go = [&](auto zp) {
+        using ZT = pointee_t<decltype(zp)>;
+        if (two_rows(L)) {
+          if (L.op.col16)
+            hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, true, WT, FIRST>), dim3(grid2_for(L.n)),
+                               dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col16),
+                               w, sc, zp, sub_mean_flag, p_old, p_new, q, r, x, part0, part1,
+                               L.n, done);
+          else
+            hipLaunchKernelGGL((k_pupd_spmv_dot2_2<ZT, false, WT, FIRST>), dim3(grid2_for(L.n)),
+                               dim3(kBlock), 0, s, L.op.uw, static_cast<const void*>(L.op.col), w,
+                               sc, zp, sub_mean_flag, p_old, p_new, q, r, x, part0, part1, L.n,
+                               done);
+          return;
+        }
+        if (L.op.col16)
+          hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, true, WT, FIRST>), dim3(grid_for(L.n)),
+                             dim3(kBlock), 0, s, L.op.sptr, L.op.uw,
+                             static_cast<const void*>(L.op.col16), w, sc, zp, sub_mean_flag, p_old,
+                             p_new, q, r, x, part0, part1, L.n, done);
+        else
+          hipLaunchKernelGGL((k_pupd_spmv_dot2<ZT, false, WT, FIRST>), dim3(grid_for(L.n)),
+                             dim3(kBlock), 0, s, L.op.sptr, L.op.uw,
+                             static_cast<const void*>(L.op.col), w, sc, zp, sub_mean_flag, p_old,
+                             p_new, q, r, x, part0, part1, L.n, done);
+      };
+      if (z32)
+        go(z32);
+      else
+        go(z64);
+    });
+  };
+  if (first)
+    launch(std::true_type{});
+  else
+    launch(std::false_type{});
 }
 void update_r(int32_t n, const DevScalars* sc, const double* q, double* r, float* r32,
               double* part0, const int* done, hipStream_t s) {

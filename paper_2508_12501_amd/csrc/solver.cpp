@@ -271,9 +271,10 @@ void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, bool tiles = 
 
 // One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).  `parity` selects
 // which direction buffer holds p on entry; the iteration leaves the new p in the other one.
-// first: the iteration right after a start from p = q = 0 of an FCG loop on a Dirichlet
-// system, whose beta = -(z.q)/pq is -0 (set by the start): the dot and its finalisation are
-// left out.
+// first: the iteration right after a start from p = q = 0 (x = 0, no step pending) of an FCG
+// loop on a Dirichlet system, whose beta = -(z.q)/pq is -0 (set by the start): the dot and
+// its finalisation are left out, and the direction update takes p = z without reading p_old
+// or x (so the start need not clear p and q).
 void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s,
                        bool first = false) {
   Level& F = *H.lv.back();
@@ -343,7 +344,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   // the previous iteration's step x += alpha p_old is taken inside the direction update; this
   // iteration's is left pending (alpha, and the buffer of p_new) for the next one or the exit
   k::pupd_spmv_dot2(F, H.scal, z32, z32 ? nullptr : z, z32 ? (natural ? 1 : 0) : (fused_mean ? 1 : 0),
-                    p_old, p_new, H.sq, H.sr, H.sx, P0, P1, done, s);
+                    p_old, p_new, H.sq, H.sr, H.sx, P0, P1, done, s, skip_beta);
   k::finalize(o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG,
               k::pupd_spmv_partials(F), P0, P1, H.scal, p_new == H.sp2 ? 1.0 : 0.0, 0, s);
   k::update_r(n, H.scal, H.sq, H.sr, r32, P0, done, s);
@@ -591,7 +592,10 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
     if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
   } else if (gather_in_init) {
-    k::init_krylov_gather(n, H.scal, F.perm, b_nat, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
+    // an FCG loop's first iteration reads neither p nor q
+    const bool keep_pq = o.outer == MG_OUTER_FCG;
+    k::init_krylov_gather(n, H.scal, F.perm, b_nat, H.sb, H.sr, H.sx, keep_pq ? nullptr : H.sp,
+                          keep_pq ? nullptr : H.sq, r32, s);
   } else {
     k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }

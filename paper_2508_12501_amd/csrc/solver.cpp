@@ -372,19 +372,28 @@ std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
 }
 
 // kind 0 and 2: a Krylov iteration with p in the first or the second buffer; 1: a cycle;
-// 3: the first FCG iteration after a start from p = q = 0 (p in the first buffer)
-hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind) {
-  auto key = graph_key(o, kind);
+// 3: the first FCG iteration after a start from p = q = 0 (p in the first buffer).  m > 1
+// (Krylov kinds): m iterations in one graph, the later ones alternating the buffers (and not
+// first ones): one launch, and one gap between launches, for m iterations.
+hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind, int m = 1) {
+  int lg = 0;
+  while ((1 << lg) < m) ++lg;
+  if (m < 1 || (1 << lg) != m || lg > 3 || (kind == 1 && m != 1))
+    throw std::logic_error("iteration_graph: iterations per graph");
+  auto key = graph_key(o, kind + 4 * lg);
   auto it = H.graphs.find(key);
   if (it != H.graphs.end()) return it->second;
   hipGraph_t g = nullptr;
   check_hip(hipStreamBeginCapture(H.capture_stream, hipStreamCaptureModeThreadLocal),
             "hipStreamBeginCapture");
   H.capturing = true;
-  if (kind == 1)
+  if (kind == 1) {
     enqueue_cycle(H, o, H.capture_stream);
-  else
-    enqueue_iteration(H, o, kind == 2 ? 1 : 0, H.capture_stream, kind == 3);
+  } else {
+    int parity = kind == 2 ? 1 : 0;
+    for (int i = 0; i < m; ++i, parity ^= 1)
+      enqueue_iteration(H, o, parity, H.capture_stream, kind == 3 && i == 0);
+  }
   H.capturing = false;
   check_hip(hipStreamEndCapture(H.capture_stream, &g), "hipStreamEndCapture");
   hipGraphExec_t ex = nullptr;
@@ -540,7 +549,7 @@ bool iterate(Hierarchy& H, const mg_opts& o, int kind, hipStream_t s, F enqueue,
   bool stalled = false;
   while (launched < o.max_iter) {
     batch = std::min(batch, o.max_iter - launched);
-    for (int j = 0; j < batch; ++j) enqueue();
+    enqueue(batch);
     launched += batch;
     tail();
     if (T) T->mark("enqueue");
@@ -600,30 +609,37 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }
   T.mark("setup");
-  hipGraphExec_t g[2] = {nullptr, nullptr}, gfirst = nullptr;
   // FCG on a Dirichlet system: the first iteration after a start from p = q = 0 has no dot
-  // for beta (first_graph)
+  // for beta (enqueue_iteration's `first`)
   auto first_ok = [&]() { return cur.outer == MG_OUTER_FCG && H.bc != MG_BC_NATURAL; };
   auto load_graphs = [&]() {
-    g[0] = cur.use_graph ? iteration_graph(H, cur, 0) : nullptr;
-    g[1] = cur.use_graph ? iteration_graph(H, cur, 2) : nullptr;
-    gfirst = (cur.use_graph && first_ok()) ? iteration_graph(H, cur, 3) : nullptr;
+    // the graphs of the usual first batch (the rest are captured when first used)
+    if (!cur.use_graph) return;
+    iteration_graph(H, cur, 0);
+    iteration_graph(H, cur, 2);
+    if (first_ok()) iteration_graph(H, cur, 3);
   };
   load_graphs();
   T.mark("graph");
   bool fresh = true;   // p = q = 0 and beta = -0: the next iteration is a first one
-  auto step = [&]() {
-    const bool first = fresh && first_ok() && H.p_parity == 0;
-    fresh = false;
-    if (first && gfirst)
-      check_hip(hipGraphLaunch(gfirst, s), "hipGraphLaunch");
-    else if (first)
-      enqueue_iteration(H, cur, 0, s, true);
-    else if (g[H.p_parity])
-      check_hip(hipGraphLaunch(g[H.p_parity], s), "hipGraphLaunch");
-    else
-      enqueue_iteration(H, cur, H.p_parity, s);
-    H.p_parity ^= 1;
+  // `count` iterations as graphs of 8, 4, 2 and 1 iterations (the binary digits of count)
+  auto step = [&](int count) {
+    while (count > 0) {
+      const int m = count >= 8 ? 8 : count >= 4 ? 4 : count >= 2 ? 2 : 1;
+      const bool first = fresh && first_ok() && H.p_parity == 0;
+      fresh = false;
+      if (cur.use_graph) {
+        check_hip(hipGraphLaunch(iteration_graph(H, cur, first ? 3 : (H.p_parity ? 2 : 0), m), s),
+                  "hipGraphLaunch");
+        if (m & 1) H.p_parity ^= 1;
+      } else {
+        for (int i = 0; i < m; ++i) {
+          enqueue_iteration(H, cur, H.p_parity, s, first && i == 0);
+          H.p_parity ^= 1;
+        }
+      }
+      count -= m;
+    }
   };
   auto tail = [&]() {
     // the last iteration's convergence check when it was left to a next iteration (a no-op
@@ -706,11 +722,13 @@ int run_mg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, m
   setup_rhs(H, b_nat, s, o.compat_check != 0);
   k::fill<double>(H.sx, F.n, 0.0, s);
   hipGraphExec_t g = o.use_graph ? iteration_graph(H, o, 1) : nullptr;
-  iterate(H, o, 1, s, [&]() {
-    if (g)
-      check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
-    else
-      enqueue_cycle(H, o, s);
+  iterate(H, o, 1, s, [&](int count) {
+    for (int j = 0; j < count; ++j) {
+      if (g)
+        check_hip(hipGraphLaunch(g, s), "hipGraphLaunch");
+      else
+        enqueue_cycle(H, o, s);
+    }
   }, [&]() {
     if (H.bc != MG_BC_NATURAL) enqueue_finish(H, b_nat, x_nat, s);
   });

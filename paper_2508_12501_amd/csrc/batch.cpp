@@ -202,10 +202,10 @@ void enqueue_finish(BatchGroup& G, hipStream_t s) {
                   s);
 }
 
-hipGraphExec_t capture(const mg_opts& o, BatchGroup& G, hipStream_t cs) {
+hipGraphExec_t capture(const mg_opts& o, BatchGroup& G, hipStream_t cs, int m = 1) {
   hipGraph_t g = nullptr;
   check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-  enqueue_iter(o, G, cs);
+  for (int i = 0; i < m; ++i) enqueue_iter(o, G, cs);
   check_hip(hipStreamEndCapture(cs, &g), "hipStreamEndCapture");
   hipGraphExec_t ex = nullptr;
   const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -218,7 +218,11 @@ hipGraphExec_t capture(const mg_opts& o, BatchGroup& G, hipStream_t cs) {
 
 void batch_release_groups(Batch& B) {
   for (BatchGroup& G : B.groups) {
-    if (G.graph) (void)hipGraphExecDestroy(G.graph);
+    for (hipGraphExec_t& ge : G.graph)
+      if (ge) {
+        (void)hipGraphExecDestroy(ge);
+        ge = nullptr;
+      }
     for (auto& v : G.v32)
       for (void* p : {(void*)v.x, (void*)v.t, (void*)v.r, (void*)v.b}) dfree(p);
     for (auto& v : G.v64)
@@ -342,7 +346,7 @@ void batch_setup(Batch& B) {
             "hipHostMalloc");
   if (B.opts.use_graph)
     for (BatchGroup& G : B.groups) {
-      G.graph = capture(B.opts, G, B.capture_stream);
+      G.graph[0] = capture(B.opts, G, B.capture_stream);
       G.graph_epoch = G.H->weight_epoch;
     }
 }
@@ -353,11 +357,14 @@ int batch_solve(Batch& B, const double* const* b, double* const* x, mg_result* r
   // a hierarchy whose coefficient changed the form of its weights since a group's graph was
   // captured: capture that group's iteration again
   for (BatchGroup& G : B.groups)
-    if (G.graph && G.graph_epoch != G.H->weight_epoch) {
+    if (G.graph[0] && G.graph_epoch != G.H->weight_epoch) {
       check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-      (void)hipGraphExecDestroy(G.graph);
-      G.graph = nullptr;
-      G.graph = capture(o, G, B.capture_stream);
+      for (hipGraphExec_t& ge : G.graph)
+        if (ge) {
+          (void)hipGraphExecDestroy(ge);
+          ge = nullptr;
+        }
+      G.graph[0] = capture(o, G, B.capture_stream);
       G.graph_epoch = G.H->weight_epoch;
     }
   check_hip(hipEventRecord(B.ev_start, s), "hipEventRecord");
@@ -389,11 +396,16 @@ int batch_solve(Batch& B, const double* const* b, double* const* x, mg_result* r
       BatchGroup& G = B.groups[g];
       hipStream_t st = B.streams[G.stream_slot];
       const int reps = first && G.last_iters > 0 ? G.last_iters : std::max(1, o.check_every);
-      for (int k = 0; k < reps; ++k) {
-        if (G.graph)
-          check_hip(hipGraphLaunch(G.graph, st), "hipGraphLaunch");
-        else
-          enqueue_iter(o, G, st);
+      if (G.graph[0]) {
+        // reps iterations as graphs of 8, 4, 2 and 1 iterations: one launch gap per graph
+        for (int left = reps; left > 0;) {
+          const int lg = left >= 8 ? 3 : left >= 4 ? 2 : left >= 2 ? 1 : 0;
+          if (!G.graph[lg]) G.graph[lg] = capture(o, G, B.capture_stream, 1 << lg);
+          check_hip(hipGraphLaunch(G.graph[lg], st), "hipGraphLaunch");
+          left -= 1 << lg;
+        }
+      } else {
+        for (int k = 0; k < reps; ++k) enqueue_iter(o, G, st);
       }
       check_hip(hipMemcpyAsync(B.col_host + g * kBatchMaxCols, G.col, G.M * sizeof(BatchCol),
                                hipMemcpyDeviceToHost, st),

@@ -52,8 +52,10 @@ struct BatchGroup {
   BatchFlag* flag = nullptr;
   const double** bptr = nullptr;   // device table of M input pointers
   double** xptr = nullptr;         // device table of M output pointers
-  hipGraphExec_t graph = nullptr;
-  int64_t graph_epoch = -1;        // H->weight_epoch when the graph was captured
+  // graphs of 1, 2, 4 and 8 iterations (graph[k]: 2^k), captured when first used; a batch of
+  // iterations launches the binary digits of its count
+  hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t graph_epoch = -1;        // H->weight_epoch when the graphs were captured
   int last_iters = 0;
 };
 

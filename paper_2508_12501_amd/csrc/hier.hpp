@@ -351,7 +351,10 @@ template <typename T> void coarse(const Hierarchy& H, const T* b, T* x, const in
 template <typename T> void coarse_cycle(const Hierarchy& H, int top, const T* b, T* x, double omega, int nu1, int nu2, const int* done, hipStream_t s);
 // Fused down leg of a tiled level from x = 0: nu1 (<= 2) Jacobi sweeps into x, and the
 // restriction of the residual into bc (the coarse right-hand side)
-template <typename T> void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done, hipStream_t s);
+// chk_part non-null: one more workgroup takes the Krylov loop's pending convergence check from
+// its chk_nb (<= 8192) partials, as jacobi_two_chk does
+template <typename T> void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done, hipStream_t s,
+                                     DevScalars* chk_sc = nullptr, const double* chk_part = nullptr, int32_t chk_nb = 0);
 // Fused up leg of a tiled level: xo = nu2 (1 or 2) Jacobi sweeps of x + M(f)^T ec
 template <typename T> void tile_up(const Level& L, const T* ec, const T* x, const T* b, T* xo, double omega, int nu2, const int* done, hipStream_t s);
 // whether levels top..0 fit the one-workgroup register-resident cycle of any shape and smoother

@@ -739,6 +739,10 @@ __device__ __forceinline__ void tile_row(int g, int i, int cap, const int32_t* _
   }
 }
 
+template <int NT>
+__device__ void fin_check_block(DevScalars* __restrict__ sc, const double* __restrict__ part,
+                                int32_t nb);
+
 template <typename T, typename WT, int KT, int TB, int Q, int CQ, bool WTR>
 __global__ __launch_bounds__(TB) void k_tile_down(
     const int32_t* __restrict__ meta, const int32_t* __restrict__ trow,
@@ -747,12 +751,20 @@ __global__ __launch_bounds__(TB) void k_tile_down(
     int32_t ccap, int32_t uw, const WT* __restrict__ w, const T* __restrict__ idiag,
     const T* __restrict__ b, T* __restrict__ x, T* __restrict__ bc, T omega, int nu1,
     const int32_t* __restrict__ tcent, int32_t rws, const T* __restrict__ rw,
-    const int* __restrict__ done) {
+    const int* __restrict__ done, DevScalars* __restrict__ chk_sc,
+    const double* __restrict__ chk_part, int32_t chk_nb) {
+  // with chk_part: block 0 takes the Krylov loop's pending convergence check, the others the
+  // tiles
+  if (chk_part && blockIdx.x == 0) {
+    fin_check_block<TB>(chk_sc, chk_part, chk_nb);
+    return;
+  }
   extern __shared__ double tile_smem[];
   T* s1 = reinterpret_cast<T*>(tile_smem);
   T* s2 = s1 + (cap + 1);
   const int dn = done ? *done : 0;
-  const int tb = xcd_block(), t = threadIdx.x;
+  const int tb = chk_part ? xcd_block_of(blockIdx.x - 1, gridDim.x - 1) : xcd_block();
+  const int t = threadIdx.x;
   const int32_t* m = meta + 8 * tb;
   const int nF = m[0], n0 = m[1], n1 = m[2], n2 = m[3], ncb = m[4];
   const int nq = (cap + TB - 1) / TB;
@@ -2135,6 +2147,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual2(int32_t uw,
   true_residual2_body<D16, WT, false>(uw, col, w, nullptr, 0, x, b, part0, n);
 }
 
+template <int NT>
 __device__ void fin_check_block(DevScalars* __restrict__ sc, const double* __restrict__ part,
                                 int32_t nb);
 
@@ -2149,7 +2162,7 @@ __global__ __launch_bounds__(kBlock) void k_finish_scatter(
   // block 0: the loop's pending convergence check (fin_check_block), which reads neither
   // alpha nor the direction the others use
   if (blockIdx.x == 0) {
-    if (part) fin_check_block(sc, part, nbp);
+    if (part) fin_check_block<kBlock>(sc, part, nbp);
     return;
   }
   const int b = blockIdx.x - 1;
@@ -2518,12 +2531,13 @@ __device__ __forceinline__ void fin_check_apply(DevScalars* __restrict__ sc, dou
   }
 }
 
-// The pending convergence check taken by one 256-thread workgroup of another kernel: the sum
-// of the nb <= 8 kFinThreads partials in exactly k_finalize's order (its thread v adds
-// part[v], part[v + 1024], ... and pads with zeros to eight terms; each 64-thread wave sums
-// with the same butterfly; thread 0 adds the sixteen wave sums in order), so the check gives
-// the same bits as a separate FIN_CHECK launch.  Thread t stands for k_finalize's threads
-// t + 256 j, j = 0..3.
+// The pending convergence check taken by one workgroup (NT = 256 or 512 threads) of another
+// kernel: the sum of the nb <= 8 kFinThreads partials in exactly k_finalize's order (its
+// thread v adds part[v], part[v + 1024], ... and pads with zeros to eight terms; each 64-thread
+// wave sums with the same butterfly; thread 0 adds the sixteen wave sums in order), so the
+// check gives the same bits as a separate FIN_CHECK launch.  Thread t stands for k_finalize's
+// threads t + NT j, j < 1024 / NT.
+template <int NT = 256>
 __device__ void fin_check_block(DevScalars* __restrict__ sc, const double* __restrict__ part,
                                 int32_t nb) {
   const int done0 = sc->done, pending = sc->check_pending;
@@ -2535,20 +2549,21 @@ __device__ void fin_check_block(DevScalars* __restrict__ sc, const double* __res
   const int t = threadIdx.x;
   __shared__ double sw[kFinThreads / 64];
   // one stand-in thread at a time keeps the register need of the host kernel low; this
-  // workgroup runs beside the sweeps, so its four round trips are not on their path
+  // workgroup runs beside the others, so its round trips are not on their path
+  static_assert(NT == 256 || NT == 512, "fin_check_block: 256 or 512 threads");
 #pragma unroll 1
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kFinThreads / NT; ++j) {
     double v[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int i = t + 256 * j + q * kFinThreads;
+      const int i = t + NT * j + q * kFinThreads;
       v[q] = i < nb ? part[i] : 0.0;
     }
     double a = 0.0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) a += v[q];
     a = wave_sum(a);
-    if ((t & 63) == 0) sw[(t >> 6) + 4 * j] = a;
+    if ((t & 63) == 0) sw[(t >> 6) + (NT / 64) * j] = a;
   }
   __syncthreads();
   if (t != 0) return;
@@ -2568,7 +2583,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_two2p_chk(
     const int* __restrict__ done, DevScalars* __restrict__ sc,
     const double* __restrict__ part, int32_t nbp) {
   if (blockIdx.x == 0) {
-    fin_check_block(sc, part, nbp);
+    fin_check_block<kBlock>(sc, part, nbp);
     return;
   }
   jacobi_two2_body<T, true, T, true>(uw, off, w, pat, npat, idiag, b, y, n, omega, done,
@@ -3016,17 +3031,20 @@ static const T* interp_weights(const Level& L) {
 
 template <typename T>
 void tile_down(const Level& L, const T* b, T* x, T* bc, double omega, int nu1, const int* done,
-               hipStream_t s) {
+               hipStream_t s, DevScalars* chk_sc, const double* chk_part, int32_t chk_nb) {
   const DevTiles& D = L.tiles;
   if (D.ntiles == 0) throw std::logic_error("tile_down on a level without tiles");
+  if (chk_part && (!chk_sc || chk_nb < 1 || chk_nb > 8 * kFinThreads))
+    throw std::logic_error("tile_down: convergence check arguments");
   const size_t lds = tile_lds<T>(D);
   with_weights<T>(L, [&](auto w) {
     using WT = pointee_t<decltype(w)>;
     const T* rw = transfer_weights<T>(L);
     auto go = [&](auto kern, int tbk) {
-      hipLaunchKernelGGL(kern, dim3(D.ntiles), dim3(tbk), lds, s, D.meta, D.row, D.ent, D.col,
-                         D.crow, D.cst, D.cap, D.ccap, L.op.uw, w, diagonal<T>(L), b, x, bc,
-                         static_cast<T>(omega), nu1, D.cent, D.rws, rw, done);
+      hipLaunchKernelGGL(kern, dim3(D.ntiles + (chk_part ? 1 : 0)), dim3(tbk), lds, s, D.meta,
+                         D.row, D.ent, D.col, D.crow, D.cst, D.cap, D.ccap, L.op.uw, w,
+                         diagonal<T>(L), b, x, bc, static_cast<T>(omega), nu1, D.cent, D.rws, rw,
+                         done, chk_sc, chk_part, chk_nb);
     };
     const bool one = D.cap <= kTileThreads;
     if (L.tr.weighted) {
@@ -3559,7 +3577,7 @@ void sum_abs64(int32_t n, const double* v, double* part0, double* part1, hipStre
   template void coarse_cycle_columns<T>(const Hierarchy&, int, const T*, T*, bool, double, int,    \
                                         int, int, int, const int*, hipStream_t);                 \
   template void tile_down<T>(const Level&, const T*, T*, T*, double, int, const int*,         \
-                             hipStream_t);                                                      \
+                             hipStream_t, DevScalars*, const double*, int32_t);                 \
   template void tile_up<T>(const Level&, const T*, const T*, const T*, T*, double, int,       \
                            const int*, hipStream_t);                                           \
   template void coarse_cycle_general<T>(const Hierarchy&, int, const T*, T*, bool, double, int,  \

@@ -129,11 +129,12 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
                   const int* done, hipStream_t s, bool chk) {
   Level& L = *H.lv[l];
   LevelVecs<T>& V = vecs<T>(L);
-  if (chk && (l == 0 || x_init || o.smoother != MG_SMOOTH_JACOBI || o.nu1 < 2 ||
-              (o.fuse_levels && L.tiles.ntiles > 0) || !k::jacobi_two_chk_ok(L) ||
+  if (chk && (l == 0 || x_init || o.smoother != MG_SMOOTH_JACOBI ||
+              ((o.fuse_levels && L.tiles.ntiles > 0) ? o.nu1 > 2
+                                                     : (o.nu1 < 2 || !k::jacobi_two_chk_ok(L))) ||
               (kind == MG_CYCLE_V && l <= coarse_top<T>(H)) ||
               k::coarse_cycle_general_ok<T>(H, l, false)))
-    throw std::logic_error("mgcycle: this cycle does not open with the two sweeps from zero");
+    throw std::logic_error("mgcycle: this cycle does not open with a kernel that takes the check");
   if (l == 0) {
     k::coarse<T>(H, b, V.x, done, s);
     return V.x;
@@ -179,7 +180,11 @@ static T* mgcycle(Hierarchy& H, int l, const T* b, T* x_init, const mg_opts& o, 
   if (!x_init && tiled && pre <= 2) {
     cur = V.x;
     oth = V.t;
-    k::tile_down<T>(L, b, cur, vecs<T>(C).b, o.omega, pre, done, s);
+    if (chk)
+      k::tile_down<T>(L, b, cur, vecs<T>(C).b, o.omega, pre, done, s, H.scal, H.part,
+                      k::red_blocks(L.n));
+    else
+      k::tile_down<T>(L, b, cur, vecs<T>(C).b, o.omega, pre, done, s);
     pre = 0;
     restricted = true;
   } else if (!x_init) {
@@ -242,16 +247,17 @@ template double* vcycle<double>(Hierarchy&, int, const double*, double*, const m
 template float* vcycle<float>(Hierarchy&, int, const float*, float*, const mg_opts&, const int*,
                               hipStream_t, bool);
 
-// Whether a CG/FCG iteration's cycle opens on the finest level with the two Jacobi sweeps from
-// zero of a row-pattern level, which then take the previous iteration's convergence check in
-// one more workgroup (the fused levels switched on, Jacobi smoothing with nu1 >= 2, a finest
-// level with a coarse level below it that is neither tiled nor inside a one-launch bottom).
+// Whether a CG/FCG iteration's cycle opens on the finest level with a kernel that takes the
+// previous iteration's convergence check in one more workgroup: the fused levels switched on,
+// Jacobi smoothing, a finest level with a coarse level below it outside the one-launch
+// bottom, and either the tiled down leg (nu1 <= 2) or the two sweeps from zero of a
+// row-pattern level (nu1 >= 2).
 bool check_fused_ok(const Hierarchy& H, const mg_opts& o) {
   const int top = int(H.lv.size()) - 1;
   if (o.outer == MG_OUTER_IR || !o.fuse_levels) return false;
-  if (top < 1 || o.smoother != MG_SMOOTH_JACOBI || o.nu1 < 2) return false;
+  if (top < 1 || o.smoother != MG_SMOOTH_JACOBI) return false;
   const Level& L = *H.lv[top];
-  if (L.tiles.ntiles > 0 || !k::jacobi_two_chk_ok(L)) return false;
+  if (L.tiles.ntiles > 0 ? o.nu1 > 2 : (o.nu1 < 2 || !k::jacobi_two_chk_ok(L))) return false;
   if (o.precision == MG_F32)
     return !((o.cycle == MG_CYCLE_V && top <= coarse_top<float>(H)) ||
              k::coarse_cycle_general_ok<float>(H, top, false));

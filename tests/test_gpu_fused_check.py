@@ -7,7 +7,10 @@ in the separate finaliser's order, so both must give the same bits: solution, it
 count, status, loop and true residuals, residual history.  Cases: FCG and CG, FP32 and FP64
 cycles, V- and W-cycles, graph replay and eager launches, host checks after every iteration,
 an iteration limit that ends the loop, and the FP64 fallback after a forced breakdown, on a
-1025 x 1025 grid (finest level 1,046,529 rows, untiled, 9 row patterns)."""
+1025 x 1025 grid (finest level 1,046,529 rows, untiled, 9 row patterns).  On finest levels cut
+into workgroup tiles the check rides with the tiled down leg instead: FCG and CG, FP32 and
+FP64 cycles, on a 129 x 129 grid (Dirichlet) and the level-6 icosphere (natural boundary,
+mean-projected), each against fuse_levels = 0 (no tiles, separate check)."""
 import numpy as np
 import pytest
 
@@ -103,3 +106,29 @@ def test_fallback_after_breakdown(grid):
     assert fused[0].iterations == ref[0].iterations
     assert np.array_equal(fused[1], ref[1])
     same(fused, plain)
+
+
+TILED = [("square", mg.MG_OUTER_FCG, mg.MG_F32), ("square", mg.MG_OUTER_CG, mg.MG_F64),
+         ("square", mg.MG_OUTER_FCG, mg.MG_F64), ("sphere", mg.MG_OUTER_FCG, mg.MG_F32),
+         ("sphere", mg.MG_OUTER_CG, mg.MG_F64)]
+
+
+@pytest.mark.parametrize("kind,outer,precision", TILED)
+def test_fused_check_in_tiled_down_leg(kind, outer, precision):
+    print(f"[fused-check] tiled {kind} outer={outer} precision={precision}", flush=True)
+    g = mg.Hierarchy("square", 5, base_cells=4) if kind == "square" else mg.Hierarchy("sphere", 6)
+    try:
+        assert g.info[g.top]["fused_tiles"] > 0, g.info[g.top]
+        rng = np.random.default_rng(24)
+        bh = rng.standard_normal(g.nv())
+        if kind == "sphere":
+            bh -= bh.mean()
+        b = torch.as_tensor(bh, dtype=torch.float64, device=DEV)
+        fused = solve(g, b, fuse_levels=1, outer=outer, precision=precision)
+        plain = solve(g, b, fuse_levels=0, outer=outer, precision=precision)
+        print(f"  iterations {fused[0].iterations}", flush=True)
+        assert fused[0].status == mg.MG_OK and fused[0].rel_residual <= 1e-10
+        same(fused, plain)
+        same(fused, solve(g, b, fuse_levels=1, outer=outer, precision=precision, use_graph=0))
+    finally:
+        g.close()

@@ -176,11 +176,6 @@ void op_prolong(decmg::Hierarchy& H, int level, const void* ec, void* xf, hipStr
   k::scatter<T>(F.perm, F.n, vecs<T>(F).x, static_cast<T*>(xf), s);
 }
 
-void sync_check(hipStream_t s) {
-  decmg::check_hip(hipGetLastError(), "kernel launch");
-  decmg::check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-}
-
 }  // namespace
 
 extern "C" {
@@ -373,6 +368,7 @@ mg_status mg_hierarchy_export_interp(const mg_hierarchy* h, int32_t level, int32
   return MG_OK;
 }
 
+extern "C++" {  // helpers with C++ types, internal to this file
 namespace {
 // The finest level's vertex coefficient (host copy of a device array of nv values), checked.
 mg_status set_vertex_field(decmg::Hierarchy& H, std::vector<double> kv) {
@@ -399,6 +395,7 @@ std::vector<double> to_host(const double* d, size_t n, void* stream) {
   return h;
 }
 }  // namespace
+}  // extern "C++"
 
 mg_status mg_hierarchy_set_vertex_coeff(mg_hierarchy* h, const double* k_vertex, void* stream) {
   API_BEGIN
@@ -643,6 +640,7 @@ mg_status mg_pcg_adjoint(mg_hierarchy* h, const mg_opts* o, const double* u_fine
   return MG_OK;
 }
 
+extern "C++" {  // helpers with C++ types, internal to this file
 namespace {
 mg_status check_porous(const mg_hierarchy* h, const porous_params* p, bool need_dt = true) {
   if (!h || !h->h) return fail(MG_EINVAL, "null hierarchy");
@@ -659,6 +657,7 @@ mg_status check_porous(const mg_hierarchy* h, const porous_params* p, bool need_
 }
 decmg::PorousParams porous_of(const porous_params* p) { return decmg::porous_params_of(*p); }
 }  // namespace
+}  // extern "C++"
 
 mg_status porous_step(mg_hierarchy* h, const porous_params* prm, const double* T, double* T_out,
                       double* p, mg_result* res, void* stream) {
@@ -686,6 +685,7 @@ mg_status porous_rhs(mg_hierarchy* h, const porous_params* prm, const double* T,
   return MG_OK;
 }
 
+extern "C++" {  // helpers with C++ types, internal to this file
 namespace {
 mg_status check_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
                           int32_t n_save, const double* t_save, double* T_save, double* T_end) {
@@ -708,6 +708,7 @@ mg_status check_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double
   return MG_OK;
 }
 }  // namespace
+}  // extern "C++"
 
 mg_status porous_integrate(mg_hierarchy* h, const porous_rk_opts* o, const double* T0,
                            int32_t n_save, const double* t_save, double* T_save, double* T_end,
@@ -755,6 +756,7 @@ mg_status porous_step_adjoint(mg_hierarchy* h, const porous_params* prm, const d
   return MG_OK;
 }
 
+extern "C++" {  // helpers with C++ types, internal to this file
 namespace {
 mg_status check_tuning(const mg_batch_tuning* t) {
   const int mc = t->max_cols;
@@ -772,6 +774,7 @@ mg_status check_ptrs(const mg_batch* bt, const double* const* b, double* const* 
   return MG_OK;
 }
 }  // namespace
+}  // extern "C++"
 
 mg_status mg_batch_create(mg_hierarchy* const* h, int32_t n, const mg_opts* o,
                           const mg_batch_tuning* tune, const char* tune_cache, mg_batch** out) {

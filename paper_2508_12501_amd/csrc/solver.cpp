@@ -277,10 +277,10 @@ void fin(Hierarchy& H, int op, int32_t n, bool two, hipStream_t s, bool tiles = 
 
 // One outer iteration of mg_pcg, enqueued on s (eagerly or under capture).  `parity` selects
 // which direction buffer holds p on entry; the iteration leaves the new p in the other one.
-// first: the iteration right after a start from p = q = 0 (x = 0, no step pending) of an FCG
-// loop on a Dirichlet system, whose beta = -(z.q)/pq is -0 (set by the start): the dot and
-// its finalisation are left out, and the direction update takes p = z without reading p_old
-// or x (so the start need not clear p and q).
+// first: the iteration right after a start from p = q = 0 (x = 0, no step pending) of a CG or
+// FCG loop on a Dirichlet system: the direction update takes p = z without reading p_old or x
+// (so the start need not clear p and q), and FCG, whose beta = -(z.q)/pq is -0 there (set by
+// the start), also leaves out that dot and its finalisation.
 void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s,
                        bool first = false) {
   Level& F = *H.lv.back();
@@ -300,7 +300,8 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   // mean.  CG and FCG take the mean and the projected dot from one pass over z (sum z, z.o,
   // sum o) and subtract the mean inside the p update; IR projects z before using it.
   const bool fused_mean = natural && o.outer != MG_OUTER_IR;
-  const bool skip_beta = first && o.outer == MG_OUTER_FCG && !natural;
+  const bool first_pupd = first && o.outer != MG_OUTER_IR && !natural;
+  const bool skip_beta = first_pupd && o.outer == MG_OUTER_FCG;
   if (o.precision == MG_F32) {
     z32 = vcycle<float>(H, top, F.v32.b, nullptr, o, done, s, chk);
     if (H.debug_flags & MG_DEBUG_ZERO_PRECOND32) k::fill<float>(z32, n, 0.0f, s);
@@ -350,7 +351,7 @@ void enqueue_iteration(Hierarchy& H, const mg_opts& o, int parity, hipStream_t s
   // the previous iteration's step x += alpha p_old is taken inside the direction update; this
   // iteration's is left pending (alpha, and the buffer of p_new) for the next one or the exit
   k::pupd_spmv_dot2(F, H.scal, z32, z32 ? nullptr : z, z32 ? (natural ? 1 : 0) : (fused_mean ? 1 : 0),
-                    p_old, p_new, H.sq, H.sr, H.sx, P0, P1, done, s, skip_beta);
+                    p_old, p_new, H.sq, H.sr, H.sx, P0, P1, done, s, first_pupd);
   k::finalize(o.outer == MG_OUTER_CG ? k::FIN_ALPHA_CG : k::FIN_ALPHA_FCG,
               k::pupd_spmv_partials(F), P0, P1, H.scal, p_new == H.sp2 ? 1.0 : 0.0, 0, s);
   k::update_r(n, H.scal, H.sq, H.sr, r32, P0, done, s);
@@ -378,7 +379,7 @@ std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
 }
 
 // kind 0 and 2: a Krylov iteration with p in the first or the second buffer; 1: a cycle;
-// 3: the first FCG iteration after a start from p = q = 0 (p in the first buffer).  m > 1
+// 3: the first CG/FCG iteration after a start from p = q = 0 (p in the first buffer).  m > 1
 // (Krylov kinds): m iterations in one graph, the later ones alternating the buffers (and not
 // first ones): one launch, and one gap between launches, for m iterations.
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind, int m = 1) {
@@ -607,17 +608,17 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
     if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
   } else if (gather_in_init) {
-    // an FCG loop's first iteration reads neither p nor q
-    const bool keep_pq = o.outer == MG_OUTER_FCG;
+    // a CG or FCG loop's first iteration reads neither p nor q
+    const bool keep_pq = o.outer != MG_OUTER_IR;
     k::init_krylov_gather(n, H.scal, F.perm, b_nat, H.sb, H.sr, H.sx, keep_pq ? nullptr : H.sp,
                           keep_pq ? nullptr : H.sq, r32, s);
   } else {
     k::init_krylov(n, H.scal, H.sb, H.sr, H.sx, H.sp, H.sq, r32, s);
   }
   T.mark("setup");
-  // FCG on a Dirichlet system: the first iteration after a start from p = q = 0 has no dot
-  // for beta (enqueue_iteration's `first`)
-  auto first_ok = [&]() { return cur.outer == MG_OUTER_FCG && H.bc != MG_BC_NATURAL; };
+  // CG and FCG on a Dirichlet system: the first iteration after a start from p = q = 0 forms
+  // p = z directly (enqueue_iteration's `first`)
+  auto first_ok = [&]() { return cur.outer != MG_OUTER_IR && H.bc != MG_BC_NATURAL; };
   auto load_graphs = [&]() {
     // the graphs of the usual first batch (the rest are captured when first used)
     if (!cur.use_graph) return;

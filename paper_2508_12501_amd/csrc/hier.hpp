@@ -447,6 +447,18 @@ void true_residual(const Level& L, const double* x, const double* b, double* r_s
 void finish_scatter(int32_t n, DevScalars* sc, const double* p0, const double* p1, double* x,
                     const int32_t* perm, double* x_nat, const int32_t* bnd, int32_t nbnd,
                     const double* b_nat, const double* part, int32_t nbp, hipStream_t s);
+// sum64 whose partials kernel also writes the solver's starting scalars (init_scalars).
+void sum64_init(int32_t n, const double* v, double* part0, DevScalars* sc, double rtol,
+                int32_t max_iter, double n_unknowns, double* hist, int32_t hist_cap,
+                hipStream_t s);
+// sub_mean then dot(v, v) in one pass (same bits).
+void sub_mean_dot(int32_t n, const DevScalars* sc, double* v, double* part0, hipStream_t s);
+// apply_pending then sum64(x) in one pass (same bits).
+void apply_pending_sum(int32_t n, const DevScalars* sc, const double* p0, const double* p1,
+                       double* x, double* part0, hipStream_t s);
+// p = q = 0 and the scaled FP32 copy of r (r32 nullable), after a warm start's residual.
+void warm_aux(int32_t n, const DevScalars* sc, const double* r, float* r32, double* p, double* q,
+              hipStream_t s);
 // dot() whose partials kernel also writes the solver's starting scalars (init_scalars).
 void dot_init(int32_t n, const double* a, const double* b, double* part0, DevScalars* sc,
               double rtol, int32_t max_iter, double n_unknowns, double* hist, int32_t hist_cap,

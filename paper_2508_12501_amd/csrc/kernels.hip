@@ -2421,6 +2421,111 @@ __global__ __launch_bounds__(kBlock) void k_dot(int32_t n, const double* __restr
   if (threadIdx.x == 0) part0[blk] = v;
 }
 
+// The solver's starting scalars (as k_init_scalars writes them)
+__device__ __forceinline__ void write_start_scalars(DevScalars* __restrict__ sc, double rtol,
+                                                    int32_t max_iter, double n_unknowns,
+                                                    double* hist, int32_t hist_cap) {
+  DevScalars z = {};
+  z.hist = hist;
+  z.hist_cap = hist_cap;
+  z.rho = 1.0;
+  z.pq = 1.0;
+  z.beta = -0.0;
+  z.scale = 1.0;
+  z.inv_scale = 1.0;
+  z.rtol = rtol;
+  z.max_iter = max_iter;
+  z.n_unknowns = n_unknowns;
+  *sc = z;
+}
+
+// k_sum64 (block partials of sum v) whose first thread also writes the starting scalars, for
+// the start of a solve on a singular system
+__global__ __launch_bounds__(kBlock) void k_sum64_init(int32_t n, const double* __restrict__ v,
+                                                       double* __restrict__ part0,
+                                                       DevScalars* __restrict__ sc, double rtol,
+                                                       int32_t max_iter, double n_unknowns,
+                                                       double* hist, int32_t hist_cap) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    write_start_scalars(sc, rtol, max_iter, n_unknowns, hist, hist_cap);
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) a += v[i];
+  }
+  a = block_sum1(a);
+  if (threadIdx.x == 0) part0[blk] = a;
+}
+
+// v -= mean and the block partials of v.v in one pass (k_sub_mean then k_dot, the same values
+// and order of summation)
+__global__ __launch_bounds__(kBlock) void k_sub_mean_dot(int32_t n,
+                                                         const DevScalars* __restrict__ sc,
+                                                         double* __restrict__ v,
+                                                         double* __restrict__ part0) {
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double m = sc->mean;
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      const double vi = v[i] - m;
+      v[i] = vi;
+      a += vi * vi;
+    }
+  }
+  a = block_sum1(a);
+  if (threadIdx.x == 0) part0[blk] = a;
+}
+
+// The pending solution step x += alpha p (none when alpha = 0) and the block partials of
+// sum x in one pass (k_apply_pending then k_sum64), for the exit of a singular system's solve
+__global__ __launch_bounds__(kBlock) void k_apply_pending_sum(int32_t n,
+                                                              const DevScalars* __restrict__ sc,
+                                                              const double* __restrict__ p0,
+                                                              const double* __restrict__ p1,
+                                                              double* __restrict__ x,
+                                                              double* __restrict__ part0) {
+  const int blk = xcd_block();
+  int t0, t1;
+  tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
+  const double al = sc->alpha;
+  const double* __restrict__ p = sc->pbuf ? p1 : p0;
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    const int i = t * kBlock + threadIdx.x;
+    if (i < n) {
+      double xi = x[i];
+      if (al != 0.0) {
+        xi = mac(al, p[i], xi);
+        x[i] = xi;
+      }
+      a += xi;
+    }
+  }
+  a = block_sum1(a);
+  if (threadIdx.x == 0) part0[blk] = a;
+}
+
+// A warm start's remaining set-up after r = b - A x: p = q = 0 and the scaled FP32 copy of r
+// (r32 nullable)
+__global__ __launch_bounds__(kBlock) void k_warm_aux(int32_t n, const DevScalars* __restrict__ sc,
+                                                     const double* __restrict__ r,
+                                                     float* __restrict__ r32,
+                                                     double* __restrict__ p,
+                                                     double* __restrict__ q) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  p[i] = 0.0;
+  q[i] = 0.0;
+  if (r32) r32[i] = static_cast<float>(r[i] * sc->scale);
+}
+
 // k_dot whose first thread also writes the solver's starting scalars (k_init_scalars), for
 // the start of a solve: the finalisation after it reads both
 __global__ __launch_bounds__(kBlock) void k_dot_init(int32_t n, const double* __restrict__ a,
@@ -2429,20 +2534,8 @@ __global__ __launch_bounds__(kBlock) void k_dot_init(int32_t n, const double* __
                                                      DevScalars* __restrict__ sc, double rtol,
                                                      int32_t max_iter, double n_unknowns,
                                                      double* hist, int32_t hist_cap) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    DevScalars z = {};
-    z.hist = hist;
-    z.hist_cap = hist_cap;
-    z.rho = 1.0;
-    z.pq = 1.0;
-    z.beta = -0.0;
-    z.scale = 1.0;
-    z.inv_scale = 1.0;
-    z.rtol = rtol;
-    z.max_iter = max_iter;
-    z.n_unknowns = n_unknowns;
-    *sc = z;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    write_start_scalars(sc, rtol, max_iter, n_unknowns, hist, hist_cap);
   const int blk = xcd_block();
   int t0, t1;
   tile_range((n + kBlock - 1) / kBlock, blk, t0, t1);
@@ -3463,6 +3556,25 @@ void dot_init(int32_t n, const double* a, const double* b, double* part0, DevSca
               hipStream_t s) {
   hipLaunchKernelGGL(k_dot_init, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, a, b, part0, sc, rtol,
                      max_iter, n_unknowns, hist, hist_cap);
+}
+void sum64_init(int32_t n, const double* v, double* part0, DevScalars* sc, double rtol,
+                int32_t max_iter, double n_unknowns, double* hist, int32_t hist_cap,
+                hipStream_t s) {
+  hipLaunchKernelGGL(k_sum64_init, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, v, part0, sc, rtol,
+                     max_iter, n_unknowns, hist, hist_cap);
+}
+void sub_mean_dot(int32_t n, const DevScalars* sc, double* v, double* part0, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_mean_dot, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, v, part0);
+}
+void apply_pending_sum(int32_t n, const DevScalars* sc, const double* p0, const double* p1,
+                       double* x, double* part0, hipStream_t s) {
+  hipLaunchKernelGGL(k_apply_pending_sum, dim3(red_blocks(n)), dim3(kBlock), 0, s, n, sc, p0, p1,
+                     x, part0);
+}
+void warm_aux(int32_t n, const DevScalars* sc, const double* r, float* r32, double* p, double* q,
+              hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_warm_aux, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, r, r32, p, q);
 }
 void sub_mean(int32_t n, const DevScalars* sc, double* v, hipStream_t s) {
   hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(n)), dim3(kBlock), 0, s, n, sc, v);

@@ -434,14 +434,19 @@ void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_comp
   if (b_nat && !(defer_gather && H.bc != MG_BC_NATURAL)) k::gather<double>(F.perm, n, b_nat, H.sb, s);
   if (H.bc == MG_BC_NATURAL) {
     if (check_compat) {
+      if (init) init_scalars(H, *init, s);
       k::sum_abs64(n, H.sb, H.part, H.part + H.part_cap, s);
       fin(H, k::FIN_MEAN_COMPAT, n, true, s);
     } else {
-      k::sum64(n, H.sb, H.part, nullptr, s);
+      // init: the sum's first thread also writes the starting scalars
+      if (init)
+        k::sum64_init(n, H.sb, H.part, H.scal, init->rtol, init->max_iter, double(n), H.hist,
+                      H.hist_cap, s);
+      else
+        k::sum64(n, H.sb, H.part, nullptr, s);
       fin(H, k::FIN_MEAN, n, false, s);
     }
-    k::sub_mean(n, H.scal, H.sb, s);
-    k::dot(n, H.sb, H.sb, H.part, nullptr, s);
+    k::sub_mean_dot(n, H.scal, H.sb, H.part, s);
     fin(H, k::FIN_BNORM, n, false, s);
   } else if (b_nat) {
     // init: the dot's first thread also writes the starting scalars (no init_scalars launch)
@@ -452,7 +457,11 @@ void setup_rhs(Hierarchy& H, const double* b_nat, hipStream_t s, bool check_comp
       k::dot(F.nv, b_nat, b_nat, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, F.nv, false, s);
   } else {
-    k::dot(n, H.sb, H.sb, H.part, nullptr, s);
+    if (init)
+      k::dot_init(n, H.sb, H.sb, H.part, H.scal, init->rtol, init->max_iter, double(n), H.hist,
+                  H.hist_cap, s);
+    else
+      k::dot(n, H.sb, H.sb, H.part, nullptr, s);
     fin(H, k::FIN_BNORM, n, false, s);
   }
 }
@@ -473,10 +482,10 @@ void enqueue_finish(Hierarchy& H, const double* b_nat, double* x_nat, hipStream_
   if (scatter_now)   // with the loop's pending convergence check (a no-op when none is)
     k::finish_scatter(n, H.scal, H.sp, H.sp2, H.sx, F.perm, x_nat, F.bnd_ids,
                       b_nat ? int32_t(F.bnd_h.size()) : 0, b_nat, H.part, k::red_blocks(n), s);
-  else
+  else if (H.bc != MG_BC_NATURAL)
     k::apply_pending(n, H.scal, H.sp, H.sp2, H.sx, s);
   if (H.bc == MG_BC_NATURAL) {
-    k::sum64(n, H.sx, H.part, nullptr, s);
+    k::apply_pending_sum(n, H.scal, H.sp, H.sp2, H.sx, H.part, s);
     fin(H, k::FIN_MEAN, n, false, s, false, true);
     k::sub_mean(n, H.scal, H.sx, s);
   }
@@ -594,19 +603,16 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   HostTimer T;
   Level& F = *H.lv.back();
   const int32_t n = F.n;
-  // a Dirichlet solve from the caller's b gathers b inside the Krylov start below and writes
-  // the starting scalars with the norm of b
+  // the first reduction over b also writes the starting scalars; a Dirichlet solve from the
+  // caller's b gathers b inside the Krylov start below
   const bool gather_in_init = b_nat && H.bc != MG_BC_NATURAL;
-  if (!gather_in_init) init_scalars(H, o, s);
-  setup_rhs(H, b_nat, s, check_compat, gather_in_init, gather_in_init ? &o : nullptr);
+  setup_rhs(H, b_nat, s, check_compat, gather_in_init, &o);
   H.p_parity = 0;
   mg_opts cur = o;   // the FP64 fallback switches the cycle's precision
   float* r32 = (o.precision == MG_F32) ? F.v32.b : nullptr;
   if (warm_start && !b_nat) {
-    k::fill<double>(H.sp, n, 0.0, s);
-    k::fill<double>(H.sq, n, 0.0, s);
     k::residual<double>(F, H.sx, H.sb, H.sr, nullptr, s);
-    if (r32) k::to_f32(n, H.scal, H.sr, r32, nullptr, s);
+    k::warm_aux(n, H.scal, H.sr, r32, H.sp, H.sq, s);
   } else if (gather_in_init) {
     // a CG or FCG loop's first iteration reads neither p nor q
     const bool keep_pq = o.outer != MG_OUTER_IR;

@@ -380,14 +380,14 @@ std::tuple<int, int, int, int, double> graph_key(const mg_opts& o, int kind) {
 
 // kind 0 and 2: a Krylov iteration with p in the first or the second buffer; 1: a cycle;
 // 3: the first CG/FCG iteration after a start from p = q = 0 (p in the first buffer).  m > 1
-// (Krylov kinds): m iterations in one graph, the later ones alternating the buffers (and not
-// first ones): one launch, and one gap between launches, for m iterations.
+// (Krylov kinds, m <= kMaxGraphIters): m iterations in one graph, the later ones alternating
+// the buffers (and not first ones): one launch, and one gap between launches, for m
+// iterations.
+constexpr int kMaxGraphIters = 16;
 hipGraphExec_t iteration_graph(Hierarchy& H, const mg_opts& o, int kind, int m = 1) {
-  int lg = 0;
-  while ((1 << lg) < m) ++lg;
-  if (m < 1 || (1 << lg) != m || lg > 3 || (kind == 1 && m != 1))
+  if (m < 1 || m > kMaxGraphIters || (kind == 1 && m != 1))
     throw std::logic_error("iteration_graph: iterations per graph");
-  auto key = graph_key(o, kind + 4 * lg);
+  auto key = graph_key(o, kind + 4 * (m - 1));
   auto it = H.graphs.find(key);
   if (it != H.graphs.end()) return it->second;
   hipGraph_t g = nullptr;
@@ -635,10 +635,11 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   load_graphs();
   T.mark("graph");
   bool fresh = true;   // p = q = 0 and beta = -0: the next iteration is a first one
-  // `count` iterations as graphs of 8, 4, 2 and 1 iterations (the binary digits of count)
+  // `count` iterations as graphs of up to kMaxGraphIters iterations each (a batch is usually
+  // the iteration count of the previous solve, so few graph sizes are ever captured)
   auto step = [&](int count) {
     while (count > 0) {
-      const int m = count >= 8 ? 8 : count >= 4 ? 4 : count >= 2 ? 2 : 1;
+      const int m = std::min(count, kMaxGraphIters);
       const bool first = fresh && first_ok() && H.p_parity == 0;
       fresh = false;
       if (cur.use_graph) {

@@ -1,11 +1,10 @@
-"""Batches of CG/FCG iterations are launched as replayed graphs of 8, 4, 2 and 1 iterations
-(the binary digits of the batch size), the first iteration after a start from p = q = 0 as a
-graph of its own kind.  Whatever the decomposition, a solve must equal the same solve with
-eager launches (use_graph = 0) bit for bit: solution, iteration count, status, residuals and
-residual history.  The batch sizes are set with check_every on fresh hierarchies (the first
-batch of a hierarchy's first solve has check_every iterations), so that sizes 1, 2, 3, 5, 7,
-8 and 13 exercise every mix of graph sizes, on a Dirichlet grid (FCG, CG) and on a sphere
-(natural boundary)."""
+"""Batches of CG/FCG iterations are launched as replayed graphs of several iterations each
+(up to 16), the first iteration after a start from p = q = 0 in a graph of its own kind.
+Whatever the graph sizes, a solve must equal the same solve with eager launches
+(use_graph = 0) bit for bit: solution, iteration count, status, residuals and residual
+history.  The batch sizes are set with check_every on fresh hierarchies (the first batch of a
+hierarchy's first solve has check_every iterations): sizes 1, 2, 3, 5, 7, 8 and 13, on a
+Dirichlet grid (FCG, CG) and on a sphere (natural boundary)."""
 import numpy as np
 import pytest
 

@@ -625,14 +625,7 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
   // CG and FCG on a Dirichlet system: the first iteration after a start from p = q = 0 forms
   // p = z directly (enqueue_iteration's `first`)
   auto first_ok = [&]() { return cur.outer != MG_OUTER_IR && H.bc != MG_BC_NATURAL; };
-  auto load_graphs = [&]() {
-    // the graphs of the usual first batch (the rest are captured when first used)
-    if (!cur.use_graph) return;
-    iteration_graph(H, cur, 0);
-    iteration_graph(H, cur, 2);
-    if (first_ok()) iteration_graph(H, cur, 3);
-  };
-  load_graphs();
+  // the iteration graphs are captured when a batch of their size and kind first needs them
   T.mark("graph");
   bool fresh = true;   // p = q = 0 and beta = -0: the next iteration is a first one
   // `count` iterations as graphs of up to kMaxGraphIters iterations each (a batch is usually
@@ -701,7 +694,6 @@ int run_pcg(Hierarchy& H, const mg_opts& o, const double* b_nat, double* x_nat, 
       fell_back = true;
       cur.precision = MG_F64;
       r32 = nullptr;
-      load_graphs();
       const int done_iters = h.iters;
       restart();
       stalled = run(done_iters);
